@@ -1,0 +1,205 @@
+"""Seeded synthetic inputs for the FGA workloads.
+
+This module only draws and lays out input data: velocity-model node values,
+initial displacement fields on a quadrature grid, phase-space mesh
+descriptors, receiver positions and request streams.  It holds none of the
+method's arithmetic (no FBI projection, no ray or amplitude equations, no
+Gaussian summation) and is the only code shared by the CPU oracle tests and
+the GPU path.
+
+Conventions
+-----------
+* A uniform axis-aligned point set ("mesh") is described by ``(n, lo, h)``
+  per axis: points ``lo[d] + i*h[d]`` for ``i = 0..n[d]-1``.  Cell-centred
+  meshes of a box ``[a, b]`` use ``lo = a + h/2``.
+* 3-D arrays are stored ``[z][y][x]`` (x fastest); vector fields are
+  ``[component][z][y][x]``.
+* Every random draw uses ``numpy.random.default_rng(1000*config + purpose)``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SQRT3 = math.sqrt(3.0)
+
+
+def rng(config: int, purpose: int) -> np.random.Generator:
+    """Seeded generator for input ``purpose`` of workload ``config``."""
+    return np.random.default_rng(1000 * config + purpose)
+
+
+@dataclass
+class Mesh3:
+    """Uniform point set ``lo + i*h`` on each axis (i = 0..n-1)."""
+    n: tuple
+    lo: tuple
+    h: tuple
+
+    @property
+    def count(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    @property
+    def cell_volume(self) -> float:
+        return float(self.h[0] * self.h[1] * self.h[2])
+
+    def axis(self, d: int) -> np.ndarray:
+        return self.lo[d] + self.h[d] * np.arange(self.n[d], dtype=np.float64)
+
+    def points(self) -> np.ndarray:
+        """All points, shape (count, 3), x index fastest."""
+        z, y, x = np.meshgrid(self.axis(2), self.axis(1), self.axis(0), indexing="ij")
+        return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+
+def cell_centred(n: int, a: float, b: float) -> Mesh3:
+    """n^3 cell-centred points on the cube [a, b]^3."""
+    h = (b - a) / n
+    return Mesh3((n, n, n), (a + 0.5 * h,) * 3, (h,) * 3)
+
+
+def box_mesh(n: int, centre, half_width: float) -> Mesh3:
+    """n^3 cell-centred points on the box centre +- half_width (per axis)."""
+    h = 2.0 * half_width / n
+    lo = tuple(float(c) - half_width + 0.5 * h for c in centre)
+    return Mesh3((n, n, n), lo, (h,) * 3)
+
+
+def packet_momentum_spread(eps: float, width: float) -> float:
+    """Standard deviation, per axis, of |FBI transform| of a Gaussian-enveloped
+    plane wave of envelope std ``width`` in the momentum variable p.  Used
+    only to place the p-mesh (the paper leaves mesh placement to the user)."""
+    return eps * math.sqrt(1.0 / width ** 2 + 1.0 / eps)
+
+
+def p_mesh_around(k0, eps: float, width: float, n: int, nsig: float = 3.0) -> Mesh3:
+    """Cell-centred p-mesh spanning k0 +- nsig*sigma_p per axis."""
+    sp = packet_momentum_spread(eps, width)
+    return box_mesh(n, k0, nsig * sp)
+
+
+def unit_vector(g: np.random.Generator) -> np.ndarray:
+    v = g.standard_normal(3)
+    return v / np.linalg.norm(v)
+
+
+def gaussian_plane_wave(ymesh: Mesh3, eps: float, centre, width: float, k0, d) -> np.ndarray:
+    """f(y) = exp(-|y-centre|^2/(2 width^2)) * d * exp(i k0.y/eps) on ymesh.
+
+    Returns complex128 array [3][z][y][x]."""
+    x = ymesh.axis(0)[None, None, :]
+    y = ymesh.axis(1)[None, :, None]
+    z = ymesh.axis(2)[:, None, None]
+    r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2
+    phase = (k0[0] * x + k0[1] * y + k0[2] * z) / eps
+    s = np.exp(-r2 / (2.0 * width ** 2)) * np.exp(1j * phase)
+    d = np.asarray(d, dtype=np.complex128)
+    return np.ascontiguousarray(d[:, None, None, None] * s[None])
+
+
+def gaussian_random_field(n: int, corr_len: float, std: float, clip: float,
+                          g: np.random.Generator) -> np.ndarray:
+    """Periodic Gaussian random field on the n^3 node grid of [0,1)^3.
+
+    White noise filtered in Fourier space so that the covariance is
+    proportional to exp(-r^2/(2 corr_len^2)); rescaled to the given standard
+    deviation and clipped to [-clip, clip].  Array order [z][y][x]."""
+    noise = g.standard_normal((n, n, n))
+    xi = 2.0 * math.pi * np.fft.fftfreq(n, d=1.0 / n)
+    kz, ky, kx = np.meshgrid(xi, xi, xi, indexing="ij")
+    filt = np.exp(-(corr_len ** 2) * (kx ** 2 + ky ** 2 + kz ** 2) / 4.0)
+    f = np.real(np.fft.ifftn(np.fft.fftn(noise) * filt))
+    f = f - f.mean()
+    f = f * (std / f.std())
+    return np.clip(f, -clip, clip)
+
+
+def node_grid(n: int) -> Mesh3:
+    """n^3 node grid of the periodic unit cube: nodes i/n."""
+    return Mesh3((n, n, n), (0.0, 0.0, 0.0), (1.0 / n,) * 3)
+
+
+def uniform_points(count: int, g: np.random.Generator, lo=0.0, hi=1.0) -> np.ndarray:
+    return lo + (hi - lo) * g.random((count, 3))
+
+
+# ---------------------------------------------------------------------------
+# Workload descriptions.  Each is a plain dictionary of sizes and seeds; the
+# arrays are produced on demand by ``make_workload``.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    eps: float
+    cp0: float
+    cs0: float
+    qmesh: Mesh3
+    pmesh: Mesh3
+    ymesh: Mesh3
+    f: np.ndarray                  # complex128 [3][z][y][x] initial displacement
+    dt: float
+    nsteps: int
+    out_grid: Mesh3 | None
+    receivers: np.ndarray | None   # (n_r, 3)
+    medium_nodes: np.ndarray | None = None   # c_p node values [z][y][x] (grid media)
+    medium_grid: Mesh3 | None = None
+    cs_ratio: float = 1.0 / SQRT3
+    branches: tuple = (0, 1, 2)    # P, SH, SV
+    tau: float = 25.0
+    cull_abs: float = 0.0          # |psi| threshold below which a beam is not created
+    extra: dict = field(default_factory=dict)
+
+
+def homogeneous_packet(name="c1", eps=1.0 / 32, nq=8, np_=4, ny=64, nsteps=100,
+                       dt=0.005, nout=32, config=1, tau=25.0) -> Workload:
+    """Plain FGA in a homogeneous medium (cp = sqrt(3), cs = 1): a Gaussian
+    plane-wave packet of width 0.1 centred at (0.5,0.5,0.5) travelling along
+    x, one-way data, q nq^3 on [0,1]^3, p np^3 around k0 = (1,0,0)."""
+    width, centre, k0 = 0.1, (0.5, 0.5, 0.5), (1.0, 0.0, 0.0)
+    d = unit_vector(rng(config, 1))
+    ymesh = cell_centred(ny, 0.0, 1.0)
+    return Workload(
+        name=name, eps=eps, cp0=SQRT3, cs0=1.0,
+        qmesh=cell_centred(nq, 0.0, 1.0),
+        pmesh=p_mesh_around(k0, eps, width, np_),
+        ymesh=ymesh,
+        f=gaussian_plane_wave(ymesh, eps, centre, width, k0, d),
+        dt=dt, nsteps=nsteps,
+        out_grid=cell_centred(nout, 0.0, 1.0) if nout else None,
+        receivers=None, tau=tau,
+        extra={"width": width, "centre": centre, "k0": k0, "d": d},
+    )
+
+
+def smooth_medium_packet(name="c2", eps=1.0 / 128, nq=32, np_=8, ny=128, nmed=128,
+                         nsteps=1000, dt=1e-3, nout=128, nrec=256, config=2,
+                         tau=25.0, cull_rel=1e-10) -> Workload:
+    """Smooth heterogeneous medium cp = sqrt(3)(1 + 0.2 g), cs = cp/sqrt(3),
+    g a periodic Gaussian random field (correlation length 0.2, std 1/3,
+    clipped to |g| <= 1) on an nmed^3 node grid; Gaussian plane-wave packet
+    initial data; receivers uniform in [0,1]^3."""
+    width, centre, k0 = 0.1, (0.5, 0.5, 0.5), (1.0, 0.0, 0.0)
+    gfield = gaussian_random_field(nmed, 0.2, 1.0 / 3.0, 1.0, rng(config, 1))
+    cp_nodes = SQRT3 * (1.0 + 0.2 * gfield)
+    d = unit_vector(rng(config, 3))
+    ymesh = cell_centred(ny, 0.0, 1.0)
+    rec = uniform_points(nrec, rng(config, 2)) if nrec else None
+    # Peak |psi| of this data is bounded by the y-integral of |f|, which is at
+    # most (2 pi width^2)^{3/2}; beams below cull_rel times that are not made.
+    peak = (2.0 * math.pi * width ** 2) ** 1.5
+    return Workload(
+        name=name, eps=eps, cp0=SQRT3, cs0=1.0,
+        qmesh=cell_centred(nq, 0.0, 1.0),
+        pmesh=p_mesh_around(k0, eps, width, np_),
+        ymesh=ymesh,
+        f=gaussian_plane_wave(ymesh, eps, centre, width, k0, d),
+        dt=dt, nsteps=nsteps,
+        out_grid=cell_centred(nout, 0.0, 1.0) if nout else None,
+        receivers=rec, medium_nodes=cp_nodes, medium_grid=node_grid(nmed),
+        tau=tau, cull_abs=cull_rel * peak,
+        extra={"width": width, "centre": centre, "k0": k0, "d": d},
+    )

@@ -1,0 +1,283 @@
+"""CPU oracle for the FGA hot path -- TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 implementation (C99 + OpenMP in ``fga_oracle.c``, driven from
+here through ctypes) of the frozen Gaussian approximation of the 3-D elastic
+wave equation: FBI decomposition (eq:psi, eq:alpha^k), RK4 of the ray,
+variational and amplitude ODEs (eq:char_plus/minus, eq:DzDt, eq:amp_P/SV/SH),
+the interface map (eq:p:int, eq:Yilmaz, eq:Inter_DzQDzP) and the windowed
+Gaussian summation (eq:FGA).  Only the tests, the smoke check and the
+CPU-baseline leg of the benchmark use it; the GPU library never does, and it
+shares no code with the GPU library.
+
+Beams are numpy structured arrays (``BEAM_DTYPE``) mirroring ``om_beam``.
+Beam numbering ("lineage") follows the canonical enumeration
+    lineage = ((branch*2 + dir)*Np + ip)*Nq + iq,
+branch 0/1/2 = P/SH/SV, dir 0/1 = "+"/"-", ip and iq the row-major mesh
+indices with x fastest.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fga_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+BEAM_DTYPE = np.dtype([
+    ("Q", "f8", 3), ("P", "f8", 3),
+    ("ZQ", "c16", (3, 3)), ("ZP", "c16", (3, 3)),
+    ("a", "c16", 2), ("S", "f8"), ("w", "c16"), ("e", "f8", 3),
+    ("branch", "i4"), ("sigma", "i4"), ("layer", "i4"), ("gen", "i4"), ("alive", "i4"),
+    ("lineage", "i8"),
+], align=True)
+
+
+class Medium(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int), ("geometry", C.c_int),
+        ("cp", C.c_double), ("cs", C.c_double), ("rho", C.c_double),
+        ("n", C.c_int * 3), ("lo", C.c_double * 3), ("h", C.c_double * 3),
+        ("tab", C.POINTER(C.c_double)), ("cs_ratio", C.c_double), ("two_fields", C.c_int),
+        ("x0", C.c_double * 3), ("amp", C.c_double), ("s", C.c_double), ("g", C.c_double * 3),
+        ("nlayer", C.c_int), ("bound", C.c_double * 8),
+        ("cpl", C.c_double * 8), ("csl", C.c_double * 8), ("rhol", C.c_double * 8),
+    ]
+
+
+HOMOGENEOUS, GRID, BUMP, LINEAR, LAYERED = 0, 1, 2, 3, 4
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB_PATH)
+        vp = C.c_void_p
+        L.om_beam_size.restype = C.c_size_t
+        L.om_sum_points.restype = C.c_int64
+        L.om_sum_points.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_double, C.c_double, vp]
+        L.om_evolve.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_int]
+        L.om_fbi_many.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, C.c_double, vp]
+        L.om_make_beams.restype = C.c_int
+        L.om_make_beams.argtypes = [vp, vp, vp, vp, C.c_int, C.c_double, C.c_double, C.c_double,
+                                    C.c_int, C.c_double, C.c_int64, C.c_int64, vp]
+        L.om_grid_fields.argtypes = [vp, vp, vp, vp]
+        L.om_speed_many.argtypes = [vp, C.c_int, vp, C.c_int64, vp]
+        L.om_rhs_beam.argtypes = [vp, vp, vp]
+        L.om_amplitude_vectors.argtypes = [vp, C.c_int64, vp]
+        L.om_reframe_many.argtypes = [vp, C.c_int64]
+        L.om_rk4_step.argtypes = [vp, vp, C.c_double]
+        L.om_medium_size.restype = C.c_size_t
+        if L.om_medium_size() != C.sizeof(Medium):
+            raise RuntimeError("oracle medium layout mismatch")
+        if L.om_beam_size() != BEAM_DTYPE.itemsize:
+            raise RuntimeError("oracle beam layout mismatch: C %d vs numpy %d"
+                               % (L.om_beam_size(), BEAM_DTYPE.itemsize))
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# media
+# ---------------------------------------------------------------------------
+
+class OracleMedium:
+    """Owns an ``om_medium`` plus any derived node tables."""
+
+    def __init__(self, m: Medium, keep=()):
+        self.m = m
+        self._keep = list(keep)
+
+    @property
+    def ref(self):
+        return C.byref(self.m)
+
+
+def homogeneous(cp: float, cs: float, rho: float = 1.0) -> OracleMedium:
+    m = Medium()
+    m.kind, m.cp, m.cs, m.rho = HOMOGENEOUS, cp, cs, rho
+    return OracleMedium(m)
+
+
+def bump(cp: float, cs: float, x0, amp: float, s: float) -> OracleMedium:
+    m = Medium()
+    m.kind, m.cp, m.cs = BUMP, cp, cs
+    m.x0[:] = list(x0)
+    m.amp, m.s = amp, s
+    return OracleMedium(m)
+
+
+def linear(cp: float, cs: float, g) -> OracleMedium:
+    m = Medium()
+    m.kind, m.cp, m.cs = LINEAR, cp, cs
+    m.g[:] = list(g)
+    return OracleMedium(m)
+
+
+def grid(cp_nodes: np.ndarray, mesh, cs_ratio: float = None, cs_nodes: np.ndarray = None) -> OracleMedium:
+    """Periodic node-grid medium; nodes mesh.lo + i*mesh.h, arrays [z][y][x]."""
+    lib_ = lib()
+    n = np.array(mesh.n, dtype=np.int32)
+    h = np.array(mesh.h, dtype=np.float64)
+    fields = [np.ascontiguousarray(cp_nodes, dtype=np.float64)]
+    if cs_nodes is not None:
+        fields.append(np.ascontiguousarray(cs_nodes, dtype=np.float64))
+    tab = np.empty((len(fields),) + tuple(int(v) for v in mesh.n[::-1]) + (10,), dtype=np.float64)
+    for i, f in enumerate(fields):
+        lib_.om_grid_fields(_p(f), _p(n), _p(h), _p(tab[i]))
+    m = Medium()
+    m.kind = GRID
+    m.n[:] = [int(v) for v in mesh.n]
+    m.lo[:] = [float(v) for v in mesh.lo]
+    m.h[:] = [float(v) for v in mesh.h]
+    m.tab = tab.ctypes.data_as(C.POINTER(C.c_double))
+    m.two_fields = 1 if cs_nodes is not None else 0
+    m.cs_ratio = 0.0 if cs_ratio is None else cs_ratio
+    return OracleMedium(m, keep=[tab, n, h])
+
+
+def layered(geometry: int, bounds, cp, cs, rho) -> OracleMedium:
+    m = Medium()
+    m.kind, m.geometry = LAYERED, geometry
+    m.nlayer = len(cp)
+    m.bound[:len(bounds)] = list(bounds)
+    m.cpl[:len(cp)] = list(cp)
+    m.csl[:len(cs)] = list(cs)
+    m.rhol[:len(rho)] = list(rho)
+    m.cp, m.cs, m.rho = cp[0], cs[0], rho[0]
+    return OracleMedium(m)
+
+
+def speed(med: OracleMedium, sp: int, x: np.ndarray):
+    """c, grad c, Hessian of wave type sp at points x (n,3)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    out = np.empty((x.shape[0], 13))
+    lib().om_speed_many(med.ref, sp, _p(x), x.shape[0], _p(out))
+    return out[:, 0], out[:, 1:4], out[:, 4:].reshape(-1, 3, 3)
+
+
+# ---------------------------------------------------------------------------
+# decomposition
+# ---------------------------------------------------------------------------
+
+def fbi(f: np.ndarray, ymesh, q: np.ndarray, p: np.ndarray, eps: float) -> np.ndarray:
+    """FBI transform (eq:psi integrand without alpha's prefactor) of the
+    vector field f [3][z][y][x] at the (q, p) pairs (n,3), by quadrature on
+    ymesh.  Returns complex (n,3)."""
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+    p = np.ascontiguousarray(p, dtype=np.float64).reshape(-1, 3)
+    f = np.ascontiguousarray(f, dtype=np.complex128)
+    yn = np.array(ymesh.n, dtype=np.int32)
+    ylo = np.array(ymesh.lo, dtype=np.float64)
+    yh = np.array(ymesh.h, dtype=np.float64)
+    out = np.empty((q.shape[0], 3), dtype=np.complex128)
+    lib().om_fbi_many(_p(f), _p(yn), _p(ylo), _p(yh), _p(q), _p(p), q.shape[0], eps, _p(out))
+    return out
+
+
+def make_beams(qmesh, pmesh, Ft: np.ndarray, eps: float, iq: np.ndarray, ip: np.ndarray,
+               one_way: bool = True, Gt: np.ndarray = None, branch_mask: int = 7,
+               cull_abs: float = 0.0) -> np.ndarray:
+    """Beams of the mesh points (qmesh[iq], pmesh[ip]) from their FBI values
+    Ft (n,3) (and Gt (n,2,3) = FBI[g/c_P], FBI[g/c_S] when g != 0).
+    Returned sorted by lineage."""
+    lib_ = lib()
+    qs = qmesh.points()[iq]
+    ps = pmesh.points()[ip]
+    nq, npm = qmesh.count, pmesh.count
+    dq, dp = qmesh.cell_volume, pmesh.cell_volume
+    out = np.zeros(6 * len(iq), dtype=BEAM_DTYPE)
+    tmp = np.zeros(6, dtype=BEAM_DTYPE)
+    k = 0
+    for i in range(len(iq)):
+        q = np.ascontiguousarray(qs[i])
+        p = np.ascontiguousarray(ps[i])
+        F = np.ascontiguousarray(Ft[i], dtype=np.complex128)
+        G = None if Gt is None else np.ascontiguousarray(Gt[i], dtype=np.complex128)
+        nb = lib_.om_make_beams(_p(q), _p(p), _p(F), None if G is None else _p(G),
+                                1 if one_way else 0, eps, dq, dp, branch_mask, cull_abs,
+                                int(ip[i]) * nq + int(iq[i]), nq * npm, _p(tmp))
+        out[k:k + nb] = tmp[:nb]
+        k += nb
+    out = out[:k]
+    return out[np.argsort(out["lineage"], kind="stable")]
+
+
+def decompose(work, one_way: bool = True, iq=None, ip=None, branch_mask: int = 7) -> np.ndarray:
+    """Step 1 of the method (Sec. 2.2 algorithm): FBI weights and initial
+    beams for all mesh points, or for the listed (iq, ip) pairs."""
+    if iq is None:
+        iq_all, ip_all = np.meshgrid(np.arange(work.qmesh.count), np.arange(work.pmesh.count), indexing="xy")
+        iq, ip = iq_all.ravel(), ip_all.ravel()
+    iq = np.asarray(iq, dtype=np.int64)
+    ip = np.asarray(ip, dtype=np.int64)
+    Ft = fbi(work.f, work.ymesh, work.qmesh.points()[iq], work.pmesh.points()[ip], work.eps)
+    return make_beams(work.qmesh, work.pmesh, Ft, work.eps, iq, ip, one_way=one_way,
+                      branch_mask=branch_mask, cull_abs=work.cull_abs)
+
+
+# ---------------------------------------------------------------------------
+# evolution and reconstruction
+# ---------------------------------------------------------------------------
+
+def evolve(med: OracleMedium, beams: np.ndarray, dt: float, nsteps: int) -> None:
+    """Advance beams in place by nsteps classic RK4 steps."""
+    assert beams.dtype == BEAM_DTYPE and beams.flags.c_contiguous
+    lib().om_evolve(med.ref, _p(beams), beams.shape[0], dt, nsteps)
+
+
+def rhs(med: OracleMedium, beam: np.ndarray) -> np.ndarray:
+    """Time derivative of one beam's state (fields Q, P, ZQ, ZP, a, S)."""
+    b = np.ascontiguousarray(beam.reshape(1))
+    d = np.zeros(1, dtype=BEAM_DTYPE)
+    lib().om_rhs_beam(med.ref, _p(b), _p(d))
+    return d[0]
+
+
+def amplitude_vectors(beams: np.ndarray) -> np.ndarray:
+    """Physical amplitude vectors A (n,3) complex."""
+    b = np.ascontiguousarray(beams)
+    A = np.empty((b.shape[0], 3), dtype=np.complex128)
+    lib().om_amplitude_vectors(_p(b), b.shape[0], _p(A))
+    return A
+
+
+def reframe(beams: np.ndarray) -> None:
+    lib().om_reframe_many(_p(beams), beams.shape[0])
+
+
+def sum_points(beams: np.ndarray, x: np.ndarray, eps: float, tau: float):
+    """Windowed Gaussian summation (eq:FGA) at points x (n,3).
+    Returns (u (n,3) complex, number of in-window beam-point terms)."""
+    b = np.ascontiguousarray(beams)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    out = np.empty((x.shape[0], 3), dtype=np.complex128)
+    cnt = lib().om_sum_points(_p(b), b.shape[0], _p(x), x.shape[0], eps, tau, _p(out))
+    return out, int(cnt)
+
+
+def medium_for(work) -> OracleMedium:
+    if work.medium_nodes is None:
+        return homogeneous(work.cp0, work.cs0)
+    return grid(work.medium_nodes, work.medium_grid, cs_ratio=work.cs_ratio)

@@ -1,0 +1,642 @@
+/*
+ * fga_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU implementation of the frozen Gaussian approximation
+ * (FGA) for the 3-D isotropic elastic wave equation (Hateley, Chai, Tong, Yang,
+ * "Frozen Gaussian Approximation for 3-D Elastic Wave Equation and Seismic
+ * Tomography").  It exists so that tests can check the GPU library against an
+ * independent, obviously-correct computation.  Only the tests, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it; the product path never
+ * does.  It shares no source with the GPU library.
+ *
+ * What it computes (paper section / equation for each step):
+ *   - wave speeds c_P, c_S and their first/second derivatives   (Sec. 2, eq:ps_speed)
+ *   - FBI weights psi of the initial data                        (Sec. 2.1, eq:psi, eq:alpha^k)
+ *   - ray ODEs for "+" and "-" propagation                       (Sec. 2.2, eq:char_plus, eq:char_minus)
+ *   - variational ODEs for dzQ, dzP                              (App. A, eq:DzDt)
+ *   - P amplitude and coupled SV/SH amplitudes                   (Sec. 2.2, eq:amp_P, eq:amp_SV, eq:amp_SH)
+ *   - classic fixed-step RK4                                     (Sec. 2.3)
+ *   - Gaussian summation of the beams                            (Sec. 2.1, eq:FGA)
+ *   - flat / spherical interface map: Snell, Zoeppritz, F and W  (Sec. 3.1, eq:p:int, eq:Yilmaz, eq:Inter_DzQDzP)
+ *
+ * Readings where the paper is silent or garbled are noted at each use.
+ * Parity status: every function here is pinned by a CPU test against closed
+ * forms, invariants or brute force, except the point-source weights, whose
+ * parity is unpinned beyond their closed-form derivative check.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------ */
+/* Media                                                                     */
+/* ------------------------------------------------------------------------ */
+
+enum {
+  OM_HOMOGENEOUS = 0,  /* constant c_P, c_S                                        */
+  OM_GRID = 1,         /* periodic node grid of c_P (and c_S or a fixed ratio)      */
+  OM_BUMP = 2,         /* c_b(x) = c0_b (1 + amp exp(-|x-x0|^2/(2 s^2)))            */
+  OM_LINEAR = 3,       /* c_b(x) = c0_b (1 + g.x)                                   */
+  OM_LAYERED = 4       /* flat layers in z or spherical shells, constant per layer */
+};
+
+#define OM_MAXL 8
+
+typedef struct {
+  int kind;
+  int geometry;          /* layered media: 0 = flat interfaces z = zi, 1 = spheres |x| = ri */
+  double cp, cs, rho;    /* homogeneous values, and c0 of the analytic media             */
+  /* grid media: nodes lo + i*h, i = 0..n-1, periodic with period n*h                  */
+  int n[3];
+  double lo[3], h[3];
+  const double *tab;     /* derived fields, [speed 0/1][node][10], built by om_grid_fields */
+  double cs_ratio;       /* c_S = cs_ratio * c_P when only one node field is given          */
+  int two_fields;        /* 1: tab holds independent c_P and c_S fields                     */
+  /* analytic media                                                                         */
+  double x0[3], amp, s, g[3];
+  /* layered media: layer i occupies level in (bound[i], bound[i-1]) for geometry 1        */
+  /* (radii, descending; layer 0 outermost) or z in (bound[i-1], bound[i]) for geometry 0  */
+  int nlayer;
+  double bound[OM_MAXL];
+  double cpl[OM_MAXL], csl[OM_MAXL], rhol[OM_MAXL];
+} om_medium;
+
+/* Derived fields of one scalar node field: c, dc/dx, dc/dy, dc/dz,
+ * d2c/dx2, d2c/dy2, d2c/dz2, d2c/dxdy, d2c/dxdz, d2c/dydz, from second-order
+ * central differences on the periodic grid (the paper gives no discretisation
+ * of a gridded medium; this is the reading used throughout).  Node arrays are
+ * stored [z][y][x]. */
+void om_grid_fields(const double *c, const int n[3], const double h[3], double *out)
+{
+  const int nx = n[0], ny = n[1], nz = n[2];
+#define C(i, j, k) c[((size_t)(((k) + nz) % nz) * ny + (((j) + ny) % ny)) * nx + (((i) + nx) % nx)]
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double *o = out + 10 * ((size_t)(k * ny + j) * nx + i);
+        double c0 = C(i, j, k);
+        o[0] = c0;
+        o[1] = (C(i + 1, j, k) - C(i - 1, j, k)) / (2.0 * h[0]);
+        o[2] = (C(i, j + 1, k) - C(i, j - 1, k)) / (2.0 * h[1]);
+        o[3] = (C(i, j, k + 1) - C(i, j, k - 1)) / (2.0 * h[2]);
+        o[4] = (C(i + 1, j, k) - 2.0 * c0 + C(i - 1, j, k)) / (h[0] * h[0]);
+        o[5] = (C(i, j + 1, k) - 2.0 * c0 + C(i, j - 1, k)) / (h[1] * h[1]);
+        o[6] = (C(i, j, k + 1) - 2.0 * c0 + C(i, j, k - 1)) / (h[2] * h[2]);
+        o[7] = (C(i + 1, j + 1, k) - C(i + 1, j - 1, k) - C(i - 1, j + 1, k) + C(i - 1, j - 1, k)) /
+               (4.0 * h[0] * h[1]);
+        o[8] = (C(i + 1, j, k + 1) - C(i + 1, j, k - 1) - C(i - 1, j, k + 1) + C(i - 1, j, k - 1)) /
+               (4.0 * h[0] * h[2]);
+        o[9] = (C(i, j + 1, k + 1) - C(i, j + 1, k - 1) - C(i, j - 1, k + 1) + C(i, j - 1, k - 1)) /
+               (4.0 * h[1] * h[2]);
+      }
+#undef C
+}
+
+/* Layer index of point x in a layered medium. */
+int om_layer_of(const om_medium *m, const double x[3])
+{
+  if (m->kind != OM_LAYERED) return 0;
+  if (m->geometry == 1) {
+    double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    int L = 0;
+    while (L < m->nlayer - 1 && r < m->bound[L]) ++L;
+    return L;
+  }
+  int L = 0;
+  while (L < m->nlayer - 1 && x[2] > m->bound[L]) ++L;
+  return L;
+}
+
+/* Speed of wave type sp (0 = P, 1 = S) at x in layer `layer`, with gradient
+ * and Hessian (H[i][j] = d2c/dx_i dx_j). */
+void om_speed(const om_medium *m, int sp, int layer, const double x[3],
+              double *c, double gc[3], double H[3][3])
+{
+  memset(gc, 0, 3 * sizeof(double));
+  memset(H, 0, 9 * sizeof(double));
+  switch (m->kind) {
+  case OM_HOMOGENEOUS:
+    *c = sp == 0 ? m->cp : m->cs;
+    return;
+  case OM_LAYERED:
+    *c = sp == 0 ? m->cpl[layer] : m->csl[layer];
+    return;
+  case OM_BUMP: {
+    double c0 = sp == 0 ? m->cp : m->cs;
+    double d[3] = {x[0] - m->x0[0], x[1] - m->x0[1], x[2] - m->x0[2]};
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double s2 = m->s * m->s;
+    double E = m->amp * exp(-r2 / (2.0 * s2));
+    *c = c0 * (1.0 + E);
+    for (int i = 0; i < 3; ++i) gc[i] = -c0 * E * d[i] / s2;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        H[i][j] = c0 * E * (d[i] * d[j] / (s2 * s2) - (i == j ? 1.0 / s2 : 0.0));
+    return;
+  }
+  case OM_LINEAR: {
+    double c0 = sp == 0 ? m->cp : m->cs;
+    *c = c0 * (1.0 + m->g[0] * x[0] + m->g[1] * x[1] + m->g[2] * x[2]);
+    for (int i = 0; i < 3; ++i) gc[i] = c0 * m->g[i];
+    return;
+  }
+  case OM_GRID: {
+    /* trilinear interpolation of the ten derived node fields */
+    const int nx = m->n[0], ny = m->n[1], nz = m->n[2];
+    int i0[3];
+    double t[3];
+    for (int d = 0; d < 3; ++d) {
+      double u = (x[d] - m->lo[d]) / m->h[d];
+      double fl = floor(u);
+      t[d] = u - fl;
+      long long ii = (long long)fl % m->n[d];
+      if (ii < 0) ii += m->n[d];
+      i0[d] = (int)ii;
+    }
+    const double *tab = m->tab;
+    double scale = 1.0;
+    if (sp == 1) {
+      if (m->two_fields) tab += (size_t)10 * nx * ny * nz;
+      else scale = m->cs_ratio;
+    }
+    double v[10] = {0};
+    for (int corner = 0; corner < 8; ++corner) {
+      int dx = corner & 1, dy = (corner >> 1) & 1, dz = (corner >> 2) & 1;
+      int ix = (i0[0] + dx) % nx, iy = (i0[1] + dy) % ny, iz = (i0[2] + dz) % nz;
+      double wgt = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) * (dz ? t[2] : 1.0 - t[2]);
+      const double *o = tab + 10 * ((size_t)(iz * ny + iy) * nx + ix);
+      for (int f = 0; f < 10; ++f) v[f] += wgt * o[f];
+    }
+    for (int f = 0; f < 10; ++f) v[f] *= scale;
+    *c = v[0];
+    gc[0] = v[1]; gc[1] = v[2]; gc[2] = v[3];
+    H[0][0] = v[4]; H[1][1] = v[5]; H[2][2] = v[6];
+    H[0][1] = H[1][0] = v[7];
+    H[0][2] = H[2][0] = v[8];
+    H[1][2] = H[2][1] = v[9];
+    return;
+  }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Beams                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* One frozen Gaussian packet.  ZQ[m][j] = d Q_j / d z_m, ZP likewise, with
+ * d/dz = d/dq - i d/dp (eq:op_zZ_app).  P beams carry a[0] = a_P; S beams
+ * carry (a[0], a[1]) = (a_SV, a_SH) in the frame
+ *   N_SH = (e x P)/|e x P|,  N_SV = (P/|P|) x N_SH
+ * built from the reference axis e (the paper only requires two unit vectors
+ * orthogonal to P; this frame is the reading used here).  w folds the weight
+ * psi, the cell volumes and the (k/2 pi)^{9/2} normalisation of eq:FGA. */
+typedef struct {
+  double Q[3], P[3];
+  cplx ZQ[3][3], ZP[3][3];
+  cplx a[2];
+  double S;
+  cplx w;
+  double e[3];
+  int32_t branch;   /* 0 = P, 1 = SH, 2 = SV */
+  int32_t sigma;    /* +1 or -1: the "+" or "-" propagation direction */
+  int32_t layer;
+  int32_t gen;
+  int32_t alive;
+  int64_t lineage;
+} om_beam;
+
+size_t om_beam_size(void) { return sizeof(om_beam); }
+
+typedef struct {
+  double Q[3], P[3];
+  cplx ZQ[3][3], ZP[3][3];
+  cplx a[2];
+  double S;
+} om_state;
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double a[3], const double b[3], double o[3])
+{
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* SH / SV polarisation directions for momentum P and reference axis e. */
+void om_s_frame(const double P[3], const double e[3], double nsh[3], double nsv[3])
+{
+  double ex[3], ph[3];
+  cross3(e, P, ex);
+  double n = sqrt(dot3(ex, ex));
+  for (int i = 0; i < 3; ++i) nsh[i] = ex[i] / n;
+  double np = sqrt(dot3(P, P));
+  for (int i = 0; i < 3; ++i) ph[i] = P[i] / np;
+  cross3(ph, nsh, nsv);
+}
+
+/* Reference axis for a new S beam: e_z, unless P is within 20 degrees of it,
+ * then e_x. */
+void om_initial_axis(const double P[3], double e[3])
+{
+  double np = sqrt(dot3(P, P));
+  e[0] = e[1] = e[2] = 0.0;
+  if (fabs(P[2]) / np > cos(20.0 * M_PI / 180.0)) e[0] = 1.0;
+  else e[2] = 1.0;
+}
+
+/* Solve Z X = B for complex 3x3 matrices by Gaussian elimination with
+ * partial pivoting. */
+static void csolve3(cplx Z[3][3], cplx B[3][3], cplx X[3][3])
+{
+  cplx A[3][3], R[3][3];
+  memcpy(A, Z, sizeof(A));
+  memcpy(R, B, sizeof(R));
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 3; ++r)
+      if (cabs(A[r][col]) > cabs(A[piv][col])) piv = r;
+    if (piv != col) {
+      for (int j = 0; j < 3; ++j) {
+        cplx t = A[col][j]; A[col][j] = A[piv][j]; A[piv][j] = t;
+        t = R[col][j]; R[col][j] = R[piv][j]; R[piv][j] = t;
+      }
+    }
+    for (int r = col + 1; r < 3; ++r) {
+      cplx f = A[r][col] / A[col][col];
+      for (int j = 0; j < 3; ++j) { A[r][j] -= f * A[col][j]; R[r][j] -= f * R[col][j]; }
+    }
+  }
+  for (int col = 2; col >= 0; --col)
+    for (int j = 0; j < 3; ++j) {
+      cplx s = R[col][j];
+      for (int k = col + 1; k < 3; ++k) s -= A[col][k] * X[k][j];
+      X[col][j] = s / A[col][col];
+    }
+}
+
+/* Right-hand side of the FGA ODE system for one beam (Sec. 2.2):
+ *   dQ/dt = sigma c P/|P|,  dP/dt = -sigma |P| grad c            (eq:char_plus / eq:char_minus)
+ *   d(dzQ)/dt, d(dzP)/dt from eq:DzDt, times sigma for the "-" flow
+ *   da_P/dt = a_P (sigma grad c . P/|P| + tr(Z^{-1} dZ/dt)/2)      (eq:amp_P)
+ *   da_SV/dt = s a_SV - a_SH (dN_SH/dt . N_SV)                     (eq:amp_SV)
+ *   da_SH/dt = s a_SH + a_SV (dN_SH/dt . N_SV)                     (eq:amp_SH)
+ *   dS/dt = P . dQ/dt - H, H = sigma c |P|
+ * The action S is not in the paper's ansatz; since H is homogeneous of degree
+ * one in P it stays zero up to rounding, and is carried so that the phase
+ * factor exp(i k S) is explicit. */
+void om_rhs(const om_medium *m, const om_beam *b, const om_state *y, om_state *dy)
+{
+  const int sp = b->branch == 0 ? 0 : 1;
+  const double sg = (double)b->sigma;
+  double c, gc[3], H[3][3];
+  om_speed(m, sp, b->layer, y->Q, &c, gc, H);
+  const double *P = y->P;
+  const double np = sqrt(dot3(P, P));
+
+  for (int j = 0; j < 3; ++j) {
+    dy->Q[j] = sg * c * P[j] / np;
+    dy->P[j] = -sg * gc[j] * np;
+  }
+  /* eq:DzDt:  d(dzQ)/dt = dzQ (grad c (x) P)/|P| + c dzP (I/|P| - P (x) P/|P|^3)
+   *           d(dzP)/dt = -|P| dzQ Hess(c) - dzP (P (x) grad c)/|P|           */
+  for (int mm = 0; mm < 3; ++mm)
+    for (int j = 0; j < 3; ++j) {
+      cplx zq = 0, zp = 0;
+      for (int l = 0; l < 3; ++l) {
+        double Mq = gc[l] * P[j] / np;
+        double Mp = (l == j ? 1.0 / np : 0.0) - P[l] * P[j] / (np * np * np);
+        zq += y->ZQ[mm][l] * Mq + c * y->ZP[mm][l] * Mp;
+        zp += -np * y->ZQ[mm][l] * H[l][j] - y->ZP[mm][l] * P[l] * gc[j] / np;
+      }
+      dy->ZQ[mm][j] = sg * zq;
+      dy->ZP[mm][j] = sg * zp;
+    }
+  /* tr(Z^{-1} dZ/dt), Z = dzQ + i dzP */
+  cplx Z[3][3], dZ[3][3], X[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      Z[i][j] = y->ZQ[i][j] + I * y->ZP[i][j];
+      dZ[i][j] = dy->ZQ[i][j] + I * dy->ZP[i][j];
+    }
+  csolve3(Z, dZ, X);
+  cplx tr = X[0][0] + X[1][1] + X[2][2];
+  cplx s = sg * dot3(gc, P) / np + 0.5 * tr;
+  if (b->branch == 0) {
+    dy->a[0] = s * y->a[0];
+    dy->a[1] = 0;
+  } else {
+    /* omega = dN_SH/dt . N_SV, with N_SH = (e x P)/|e x P| differentiated
+     * along dP/dt (e is fixed during a step). */
+    double ex[3], exd[3], nsh[3], nsv[3];
+    cross3(b->e, P, ex);
+    cross3(b->e, dy->P, exd);
+    double n2 = dot3(ex, ex), n = sqrt(n2);
+    double proj = dot3(ex, exd);
+    double dnsh[3];
+    for (int i = 0; i < 3; ++i) dnsh[i] = exd[i] / n - ex[i] * proj / (n2 * n);
+    om_s_frame(P, b->e, nsh, nsv);
+    double om = dot3(dnsh, nsv);
+    dy->a[0] = s * y->a[0] - om * y->a[1];
+    dy->a[1] = s * y->a[1] + om * y->a[0];
+  }
+  dy->S = dot3(P, dy->Q) - sg * c * np;
+}
+
+static void st_from_beam(const om_beam *b, om_state *y)
+{
+  memcpy(y->Q, b->Q, sizeof(y->Q));
+  memcpy(y->P, b->P, sizeof(y->P));
+  memcpy(y->ZQ, b->ZQ, sizeof(y->ZQ));
+  memcpy(y->ZP, b->ZP, sizeof(y->ZP));
+  y->a[0] = b->a[0]; y->a[1] = b->a[1];
+  y->S = b->S;
+}
+
+static void st_to_beam(const om_state *y, om_beam *b)
+{
+  memcpy(b->Q, y->Q, sizeof(y->Q));
+  memcpy(b->P, y->P, sizeof(y->P));
+  memcpy(b->ZQ, y->ZQ, sizeof(y->ZQ));
+  memcpy(b->ZP, y->ZP, sizeof(y->ZP));
+  b->a[0] = y->a[0]; b->a[1] = y->a[1];
+  b->S = y->S;
+}
+
+/* out = y + h*k, field by field */
+static void st_axpy(om_state *out, const om_state *y, double h, const om_state *k)
+{
+  for (int i = 0; i < 3; ++i) { out->Q[i] = y->Q[i] + h * k->Q[i]; out->P[i] = y->P[i] + h * k->P[i]; }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      out->ZQ[i][j] = y->ZQ[i][j] + h * k->ZQ[i][j];
+      out->ZP[i][j] = y->ZP[i][j] + h * k->ZP[i][j];
+    }
+  out->a[0] = y->a[0] + h * k->a[0];
+  out->a[1] = y->a[1] + h * k->a[1];
+  out->S = y->S + h * k->S;
+}
+
+/* Classic fourth-order Runge-Kutta step of size dt (Sec. 2.3: fixed-step
+ * RK4): y' = y + dt/6 (k1 + 2 k2 + 2 k3 + k4). */
+void om_rk4_step(const om_medium *m, om_beam *b, double dt)
+{
+  om_state y, k1, k2, k3, k4, t;
+  st_from_beam(b, &y);
+  om_rhs(m, b, &y, &k1);
+  st_axpy(&t, &y, 0.5 * dt, &k1);
+  om_rhs(m, b, &t, &k2);
+  st_axpy(&t, &y, 0.5 * dt, &k2);
+  om_rhs(m, b, &t, &k3);
+  st_axpy(&t, &y, dt, &k3);
+  om_rhs(m, b, &t, &k4);
+  om_state out;
+  for (int i = 0; i < 3; ++i) {
+    out.Q[i] = y.Q[i] + dt / 6.0 * (k1.Q[i] + 2.0 * k2.Q[i] + 2.0 * k3.Q[i] + k4.Q[i]);
+    out.P[i] = y.P[i] + dt / 6.0 * (k1.P[i] + 2.0 * k2.P[i] + 2.0 * k3.P[i] + k4.P[i]);
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      out.ZQ[i][j] = y.ZQ[i][j] + dt / 6.0 * (k1.ZQ[i][j] + 2.0 * k2.ZQ[i][j] + 2.0 * k3.ZQ[i][j] + k4.ZQ[i][j]);
+      out.ZP[i][j] = y.ZP[i][j] + dt / 6.0 * (k1.ZP[i][j] + 2.0 * k2.ZP[i][j] + 2.0 * k3.ZP[i][j] + k4.ZP[i][j]);
+    }
+  for (int i = 0; i < 2; ++i)
+    out.a[i] = y.a[i] + dt / 6.0 * (k1.a[i] + 2.0 * k2.a[i] + 2.0 * k3.a[i] + k4.a[i]);
+  out.S = y.S + dt / 6.0 * (k1.S + 2.0 * k2.S + 2.0 * k3.S + k4.S);
+  st_to_beam(&out, b);
+}
+
+/* After a step: if an S beam's momentum has come within 10 degrees of its
+ * reference axis, switch to the other axis (e_z <-> e_x) and re-express the
+ * physical polarisation a_SV N_SV + a_SH N_SH in the new frame. */
+void om_reframe(om_beam *b)
+{
+  if (b->branch == 0) return;
+  double np = sqrt(dot3(b->P, b->P));
+  if (fabs(dot3(b->P, b->e)) / np <= cos(10.0 * M_PI / 180.0)) return;
+  double nsh[3], nsv[3], e2[3] = {0, 0, 0};
+  om_s_frame(b->P, b->e, nsh, nsv);
+  cplx A[3];
+  for (int i = 0; i < 3; ++i) A[i] = b->a[0] * nsv[i] + b->a[1] * nsh[i];
+  if (b->e[2] != 0.0 && b->e[0] == 0.0 && b->e[1] == 0.0) e2[0] = 1.0;
+  else e2[2] = 1.0;
+  memcpy(b->e, e2, sizeof(e2));
+  om_s_frame(b->P, b->e, nsh, nsv);
+  b->a[0] = A[0] * nsv[0] + A[1] * nsv[1] + A[2] * nsv[2];
+  b->a[1] = A[0] * nsh[0] + A[1] * nsh[1] + A[2] * nsh[2];
+}
+
+/* Advance n beams by nsteps RK4 steps of size dt (no interfaces). */
+void om_evolve(const om_medium *m, om_beam *beams, int64_t n, double dt, int nsteps)
+{
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    if (!beams[i].alive) continue;
+    for (int s = 0; s < nsteps; ++s) {
+      om_rk4_step(m, &beams[i], dt);
+      om_reframe(&beams[i]);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial decomposition (Sec. 2.1, eq:psi, eq:alpha^k)                      */
+/* ------------------------------------------------------------------------ */
+
+/* FBI transform of one vector field sampled on the uniform quadrature mesh
+ * (ylo + i*yh, x index fastest, array [3][z][y][x]):
+ *   Ft_c(q, p) = sum_y yh^3 f_c(y) exp(-i p.(y-q)/eps - |y-q|^2/(2 eps)).
+ * The kernel is the product of its three one-dimensional factors, which are
+ * tabulated first. */
+void om_fbi(const cplx *f, const int yn[3], const double ylo[3], const double yh[3],
+            const double q[3], const double p[3], double eps, cplx out[3])
+{
+  cplx *K[3];
+  for (int d = 0; d < 3; ++d) {
+    K[d] = (cplx *)malloc(sizeof(cplx) * yn[d]);
+    for (int i = 0; i < yn[d]; ++i) {
+      double u = ylo[d] + i * yh[d] - q[d];
+      K[d][i] = cexp(-I * p[d] * u / eps - u * u / (2.0 * eps));
+    }
+  }
+  const size_t plane = (size_t)yn[0] * yn[1] * yn[2];
+  cplx acc[3] = {0, 0, 0};
+  for (int iz = 0; iz < yn[2]; ++iz)
+    for (int iy = 0; iy < yn[1]; ++iy) {
+      cplx kyz = K[2][iz] * K[1][iy];
+      for (int ix = 0; ix < yn[0]; ++ix) {
+        cplx kk = kyz * K[0][ix];
+        size_t o = ((size_t)iz * yn[1] + iy) * yn[0] + ix;
+        for (int c = 0; c < 3; ++c) acc[c] += f[c * plane + o] * kk;
+      }
+    }
+  double vol = yh[0] * yh[1] * yh[2];
+  for (int c = 0; c < 3; ++c) out[c] = acc[c] * vol;
+  for (int d = 0; d < 3; ++d) free(K[d]);
+}
+
+/* Unit polarisation of branch b at momentum p with reference axis e. */
+static void om_polarisation(int branch, const double p[3], const double e[3], double nh[3])
+{
+  if (branch == 0) {
+    double np = sqrt(dot3(p, p));
+    for (int i = 0; i < 3; ++i) nh[i] = p[i] / np;
+  } else {
+    double nsh[3], nsv[3];
+    om_s_frame(p, e, nsh, nsv);
+    for (int i = 0; i < 3; ++i) nh[i] = branch == 1 ? nsh[i] : nsv[i];
+  }
+}
+
+/* Build the beams of one (q, p) mesh point from the FBI transforms Ft = FBI[f]
+ * and Gt[b] = FBI[g / c_b] (Gt may be NULL when g = 0).
+ *   alpha_{+-} = (1/2)(f +- i g/(k c |p|)) . n_b          (eq:alpha^k read with
+ * prefactor 1/(2 k c |p|): with a(0) = 2^{3/2} this is the normalisation under
+ * which the summation formula returns f at t = 0; the printed |p|^3 does not)
+ *   psi_{b,+-} = (1/2) Ft.n_b +- (i eps/(2|p|)) Gt_b.n_b
+ * In one-way mode only "+" beams are made and psi_{b,+} = Ft.n_b, i.e. the
+ * data is taken to be the "+"-going part of f.
+ *   w = psi * dq * dp * (2 pi eps)^{-9/2}                   (eq:FGA)
+ * Returns the number of beams written (<= 6). */
+int om_make_beams(const double q[3], const double p[3], const cplx Ft[3], const cplx *Gt,
+                  int one_way, double eps, double dq, double dp, int branch_mask,
+                  double cull_abs, int64_t lineage_base, int64_t lineage_stride, om_beam *out)
+{
+  int nb = 0;
+  const double np = sqrt(dot3(p, p));
+  const double norm = dq * dp * pow(2.0 * M_PI * eps, -4.5);
+  for (int br = 0; br < 3; ++br) {
+    if (!(branch_mask & (1 << br))) continue;
+    for (int si = 0; si < (one_way ? 1 : 2); ++si) {
+      int sg = si == 0 ? 1 : -1;
+      double e[3], nh[3];
+      om_initial_axis(p, e);
+      om_polarisation(br, p, e, nh);
+      cplx fn = Ft[0] * nh[0] + Ft[1] * nh[1] + Ft[2] * nh[2];
+      cplx psi;
+      if (one_way) psi = fn;
+      else {
+        psi = 0.5 * fn;
+        if (Gt) {
+          const cplx *G = Gt + 3 * (br == 0 ? 0 : 1);
+          cplx gn = G[0] * nh[0] + G[1] * nh[1] + G[2] * nh[2];
+          psi += sg * I * eps / (2.0 * np) * gn;
+        }
+      }
+      int64_t lin = lineage_base + (int64_t)(br * 2 + si) * lineage_stride;
+      if (cabs(psi) < cull_abs) continue;
+      om_beam *b = &out[nb++];
+      memset(b, 0, sizeof(*b));
+      memcpy(b->Q, q, 3 * sizeof(double));
+      memcpy(b->P, p, 3 * sizeof(double));
+      for (int i = 0; i < 3; ++i) { b->ZQ[i][i] = 1.0; b->ZP[i][i] = -I; }
+      const double a0 = pow(2.0, 1.5);
+      if (br == 0) { b->a[0] = a0; b->a[1] = 0; }
+      else if (br == 1) { b->a[0] = 0; b->a[1] = a0; }
+      else { b->a[0] = a0; b->a[1] = 0; }
+      b->S = 0.0;
+      b->w = psi * norm;
+      memcpy(b->e, e, sizeof(e));
+      b->branch = br;
+      b->sigma = sg;
+      b->layer = 0;
+      b->gen = 0;
+      b->alive = 1;
+      b->lineage = lin;
+    }
+  }
+  return nb;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reconstruction (Sec. 2.1, eq:FGA)                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Physical amplitude vector A = a_P P/|P| (P beams) or
+ * a_SV N_SV + a_SH N_SH (S beams). */
+void om_amplitude_vector(const om_beam *b, cplx A[3])
+{
+  if (b->branch == 0) {
+    double np = sqrt(dot3(b->P, b->P));
+    for (int i = 0; i < 3; ++i) A[i] = b->a[0] * b->P[i] / np;
+  } else {
+    double nsh[3], nsv[3];
+    om_s_frame(b->P, b->e, nsh, nsv);
+    for (int i = 0; i < 3; ++i) A[i] = b->a[0] * nsv[i] + b->a[1] * nsh[i];
+  }
+}
+
+/* u(x) = sum_b w_b exp(i S_b/eps) A_b exp(i P_b.(x-Q_b)/eps - |x-Q_b|^2/(2 eps))
+ * over the beams whose box window max_d |x_d - Q_d| <= sqrt(2 tau eps)
+ * contains x; beams summed in array order.  out is [npt][3] complex.
+ * Returns the number of (beam, point) terms evaluated. */
+int64_t om_sum_points(const om_beam *beams, int64_t nb, const double *x, int64_t npt,
+                      double eps, double tau, cplx *out)
+{
+  const double R = sqrt(2.0 * tau * eps);
+  int64_t count = 0;
+#pragma omp parallel for schedule(static) reduction(+ : count)
+  for (int64_t ip = 0; ip < npt; ++ip) {
+    const double *xp = x + 3 * ip;
+    cplx u[3] = {0, 0, 0};
+    for (int64_t ib = 0; ib < nb; ++ib) {
+      const om_beam *b = &beams[ib];
+      if (!b->alive) continue;
+      double d[3] = {xp[0] - b->Q[0], xp[1] - b->Q[1], xp[2] - b->Q[2]};
+      if (fabs(d[0]) > R || fabs(d[1]) > R || fabs(d[2]) > R) continue;
+      ++count;
+      cplx A[3];
+      om_amplitude_vector(b, A);
+      cplx g = b->w * cexp(I * b->S / eps) *
+               cexp(I * dot3(b->P, d) / eps - dot3(d, d) / (2.0 * eps));
+      for (int c = 0; c < 3; ++c) u[c] += g * A[c];
+    }
+    for (int c = 0; c < 3; ++c) out[3 * ip + c] = u[c];
+  }
+  return count;
+}
+
+/* Batched helpers for the Python wrapper. */
+void om_fbi_many(const cplx *f, const int yn[3], const double ylo[3], const double yh[3],
+                 const double *q, const double *p, int64_t n, double eps, cplx *out)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t i = 0; i < n; ++i) om_fbi(f, yn, ylo, yh, q + 3 * i, p + 3 * i, eps, out + 3 * i);
+}
+
+/* rhs of one beam at its stored state, for tests of the ODE itself */
+void om_rhs_beam(const om_medium *m, const om_beam *b, om_beam *d)
+{
+  om_state y, dy;
+  st_from_beam(b, &y);
+  om_rhs(m, b, &y, &dy);
+  *d = *b;
+  st_to_beam(&dy, d);
+}
+
+void om_speed_many(const om_medium *m, int sp, const double *x, int64_t n, double *out /* [n][13] */)
+{
+  for (int64_t i = 0; i < n; ++i) {
+    double c, gc[3], H[3][3];
+    om_speed(m, sp, om_layer_of(m, x + 3 * i), x + 3 * i, &c, gc, H);
+    double *o = out + 13 * i;
+    o[0] = c;
+    for (int k = 0; k < 3; ++k) o[1 + k] = gc[k];
+    for (int k = 0; k < 9; ++k) o[4 + k] = H[k / 3][k % 3];
+  }
+}
+
+void om_amplitude_vectors(const om_beam *b, int64_t n, cplx *A)
+{
+  for (int64_t i = 0; i < n; ++i) om_amplitude_vector(&b[i], A + 3 * i);
+}
+
+void om_reframe_many(om_beam *b, int64_t n)
+{
+  for (int64_t i = 0; i < n; ++i) om_reframe(&b[i]);
+}
+
+size_t om_medium_size(void) { return sizeof(om_medium); }
