@@ -1,0 +1,227 @@
+#!/usr/bin/env python
+"""Benchmark of the FGA hot path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input:
+  decompose (FBI weights of the initial packet on the 32^3 q x 8^3 p mesh,
+  3 branches) -> evolve (1,000 FP64 RK4 steps of every beam in the smooth
+  random medium, with 3-component seismograms at 256 receivers after every
+  step) -> reconstruct (wavefield at T = 1 on the 128^3 grid, FP64 tile GEMMs
+  on the matrix cores).
+Inputs (medium table, initial data, receivers) are resident in HBM before the
+timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload smooth|homogeneous] [--scale S]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP64 operations per unit of algorithmic work (derivation in the design doc):
+#   one RK4 beam-step (4 right-hand sides + the update), per medium kind,
+#   one receiver/point term (window test excluded), one grid term.
+FLOP_BEAM_STEP = {"homogeneous": 3390, "grid": 4186}
+FLOP_POINT_EVAL = 101     # 41 arithmetic + exp (21) + sincos (39), counted from the gfx950 code
+FLOP_GRID_EVAL = 24       # 3 complex multiply-adds
+PEAK_FP64 = 78.6e12       # FP64 vector and FP64 matrix peak, MI355X
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous"])
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="fraction of the q mesh per axis and of the time steps (quick runs only)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-beams", type=int, default=48, help="(q,p) pairs in the oracle sample")
+    return ap.parse_args()
+
+
+def make_workload(name: str, scale: float):
+    import fga_inputs as fi
+    if name == "smooth":
+        nq = max(2, int(round(32 * scale)))
+        nsteps = max(4, int(round(1000 * scale)))
+        w = fi.smooth_medium_packet(nq=nq, nsteps=nsteps, dt=1.0 / nsteps)
+        label = "smooth random medium cp=sqrt3(1+0.2g), eps=1/128, q %d^3 x p 8^3 x 3 branches, " \
+                "%d RK4 steps to T=1, 256 receivers x %d samples, 128^3 grid at T=1, FP64" % (nq, nsteps, nsteps)
+    else:
+        w = fi.homogeneous_packet()
+        label = "homogeneous cp=sqrt3 cs=1, eps=1/32, q 8^3 x p 4^3 x 3 branches, 100 RK4 steps to T=0.5, " \
+                "32^3 grid, FP64"
+    return w, label
+
+
+def gpu_run(w, args):
+    import torch
+    import paper_1810_06760_amd as fga
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    med = fga.medium_for(w)
+    mesh = fga.mesh_for(w)
+    f = fga._complex_dev(w.f)
+    rec = fga._dev(w.receivers, torch.float64) if w.receivers is not None else None
+    nq = w.qmesh.count * w.pmesh.count * 3
+    beams = fga.BeamSet(nq)
+    ws_dec = fga._workspace(fga.workspace_bytes("decompose", mesh=mesh))
+    state = {"ws_ev": None, "ws_grid": None, "seis": None, "grid": None}
+
+    def step():
+        fga.fga_decompose(med, mesh, f, beams=beams, ws=ws_dec)
+        if state["ws_ev"] is None:
+            state["ws_ev"] = fga._workspace(fga.workspace_bytes(
+                "evolve", beams=beams, nsteps=w.nsteps, n_receivers=0 if rec is None else rec.shape[0],
+                eps=w.eps, tau=w.tau))
+        seis, st = fga.fga_evolve(med, beams, w.dt, w.nsteps, receivers=rec, eps=w.eps, tau=w.tau,
+                                  seis=state["seis"], ws=state["ws_ev"])
+        state["seis"] = seis
+        ev_grid = 0
+        if w.out_grid is not None:
+            if state["ws_grid"] is None:
+                state["ws_grid"] = fga._workspace(fga.workspace_bytes("grid", beams=beams, mesh=w.out_grid,
+                                                                      eps=w.eps, tau=w.tau))
+            state["grid"], ev_grid = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid, out=state["grid"],
+                                                              ws=state["ws_grid"])
+        return beams.count, st, ev_grid
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fga.fga_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = {"beams": 0, "beam_steps": 0, "ev_rec": 0, "ev_grid": 0}
+    for _ in range(args.steps):
+        nb, st, evg = step()
+        tot["beams"] += nb
+        tot["beam_steps"] += st["beam_steps"]
+        tot["ev_rec"] += st["evals"]
+        tot["ev_grid"] += evg
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {fga.KERNEL_NAMES[k]: fga.fga_profile_read(k) for k in fga.KERNEL_NAMES}
+    fga.fga_profile_enable(False)
+    return t1 - t0, tot, prof
+
+
+def roofline(tot, prof, medium_kind):
+    """Dominant kernel: algorithmic FLOPs per launch / mean launch time."""
+    work = {
+        "integrate": tot["beam_steps"] * FLOP_BEAM_STEP[medium_kind],
+        "sum_points": tot["ev_rec"] * FLOP_POINT_EVAL,
+        "grid_tile": tot["ev_grid"] * FLOP_GRID_EVAL,
+    }
+    name = max(work, key=lambda k: prof.get(k, (0, 0.0))[1])
+    launches, ms = prof[name]
+    if launches == 0 or ms <= 0:
+        return None, name
+    achieved = work[name] / launches / (ms / launches * 1e-3)
+    bound = "mfma" if name == "grid_tile" else "alu"
+    return {"bound": bound, "kernel": name, "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+            "launches": launches, "avg_launch_ms": ms / launches}, name
+
+
+def cpu_baseline(w, tot_per_step, npairs, args):
+    """The oracle on a bounded sample of the same workload, scaled to the
+    whole step by the per-unit rates of its stages."""
+    import oracle as om
+    g = np.random.default_rng(4242)
+    nqp = w.qmesh.count * w.pmesh.count
+    pick = g.choice(nqp, size=min(args.cpu_beams, nqp), replace=False)
+    iq, ip = pick % w.qmesh.count, pick // w.qmesh.count
+    med = om.medium_for(w)
+    t = time.perf_counter()
+    F = om.fbi(w.f, w.ymesh, w.qmesh.points()[iq], w.pmesh.points()[ip], w.eps)
+    t_fbi = (time.perf_counter() - t) / len(pick)
+    beams = om.make_beams(w.qmesh, w.pmesh, F, w.eps, iq, ip, cull_abs=0.0)
+    nsteps = min(w.nsteps, 200)
+    t_ev = t_rec = 0.0
+    n_rec = 0
+    for s in range(nsteps):
+        t = time.perf_counter()
+        om.evolve(med, beams, w.dt, 1)
+        t_ev += time.perf_counter() - t
+        if w.receivers is not None:
+            t = time.perf_counter()
+            _, c = om.sum_points(beams, w.receivers, w.eps, w.tau)
+            t_rec += time.perf_counter() - t
+            n_rec += len(beams) * len(w.receivers)
+    rate_step = t_ev / (nsteps * len(beams))
+    rate_rec = t_rec / n_rec if n_rec else 0.0
+    t_grid = 0.0
+    if w.out_grid is not None:
+        pts = w.out_grid.points()
+        sel = g.choice(len(pts), size=min(4096, len(pts)), replace=False)
+        t = time.perf_counter()
+        om.sum_points(beams, pts[sel], w.eps, w.tau)
+        t_grid = (time.perf_counter() - t) / (len(sel) * len(beams))
+    # whole-step CPU time: FBI per (q,p) pair, per beam-step, per (beam, receiver, sample)
+    # pair tested, per (beam, grid point) pair tested
+    full = (t_fbi * npairs + rate_step * tot_per_step["beam_steps"]
+            + rate_rec * tot_per_step["beams"] * (len(w.receivers) if w.receivers is not None else 0) * w.nsteps
+            + t_grid * tot_per_step["beams"] * (w.out_grid.count if w.out_grid is not None else 0))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": tot_per_step["beam_steps"] / full, "unit": "beam-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "%d random (q,p) pairs (%d beams): FBI, %d RK4 steps with 256-receiver sums per step, "
+                      "4096 random grid points; stage rates scaled to the full step (FBI per pair, per "
+                      "beam-step, per beam-receiver pair, per beam-grid point pair)"
+                      % (len(pick), len(beams), nsteps),
+            "seconds_per_step_extrapolated": full}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d (WORLD_SIZE %d) is not supported"
+              % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+    w, label = make_workload(args.workload, args.scale)
+    elapsed, tot, prof = gpu_run(w, args)
+    K = args.steps
+    per = {k: v / K for k, v in tot.items()}
+    value = tot["beam_steps"] / elapsed
+    kind = "grid" if w.medium_nodes is not None else "homogeneous"
+    roof, dom = roofline(tot, prof, kind)
+    line = {
+        "metric": "beam-steps/s + beam-point evals/s; served solves/s, p50/p99 at rel-L2<=1e-3",
+        "value": value,
+        "unit": "beam-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": label, "beams": int(per["beams"]), "global_batch": int(per["beams"]),
+                   "parallelism": "single GPU"},
+        "beam_point_evals_per_s": (tot["ev_rec"] + tot["ev_grid"]) / elapsed,
+        "receiver_evals_per_step": int(per["ev_rec"]),
+        "grid_evals_per_step": int(per["ev_grid"]),
+        "kernel_ms_per_step": {k: v[1] / K for k, v in prof.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, per, w.qmesh.count * w.pmesh.count, args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,283 @@
+/*
+ * fga.h -- C ABI of the MI355X (gfx950) frozen Gaussian approximation library.
+ *
+ * The library computes the frozen Gaussian approximation (FGA) of the 3-D
+ * isotropic elastic wave equation of Hateley, Chai, Tong and Yang, "Frozen
+ * Gaussian Approximation for 3-D Elastic Wave Equation and Seismic Tomography"
+ * (Sec. 2, eq:ewe with F = 0 and initial data eq:ini).  Its three calls follow
+ * the three steps of the method (Sec. 2.2, the algorithm and Fig. 1):
+ *   fga_decompose          Step 1: FBI projection of the initial data onto
+ *                          P/SH/SV Gaussian packets ("beams")          (eq:psi, eq:alpha^k)
+ *   fga_evolve             Step 2: RK4 of each beam's ray, Jacobians, amplitudes
+ *                          and action; optional seismogram sampling    (eq:char_plus/minus, eq:DzDt,
+ *                                                                      eq:amp_P/SV/SH)
+ *   fga_reconstruct_points Step 3: Gaussian summation at points        (eq:FGA)
+ *   fga_reconstruct_grid   Step 3 on a uniform grid                    (eq:FGA)
+ *
+ * Conventions (all calls):
+ *  - Every pointer marked "device" must be device memory of the current HIP
+ *    device; the library never frees caller memory and keeps no pointer after
+ *    a call returns.  Work is enqueued on `stream` (a hipStream_t, NULL = the
+ *    default stream); a call returns once its work is enqueued unless noted.
+ *  - Complex numbers are interleaved (re, im) doubles.  3-D arrays are
+ *    [z][y][x] with x fastest; vector fields are [component][z][y][x].
+ *  - A uniform mesh is given per axis by (n, lo, h): points lo + i*h.
+ *  - k = 1/eps is the paper's large wave number.
+ *  - Calls return FGA_OK or an error code; fga_last_error() then describes
+ *    the failure (thread-local).  On error, outputs are unspecified, caller
+ *    buffers stay valid and the beam set is unchanged unless noted.
+ *  - No call allocates device memory except where a workspace query says 0
+ *    and the caller passes none; every workspace-taking call states its size
+ *    through the matching *_workspace_bytes query.
+ */
+#ifndef FGA_H
+#define FGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FGA_OK = 0,
+  FGA_EINVAL = 1,       /* invalid argument (shape, size, pointer, option)         */
+  FGA_ENOMEM = 2,       /* workspace too small                                      */
+  FGA_EDEVICE = 3,      /* a HIP runtime call failed                                */
+  FGA_ENUMERIC = 4,     /* non-finite values detected                               */
+  FGA_ECAPACITY = 5,    /* beam capacity exceeded (children would not fit)          */
+  FGA_EUNSUPPORTED = 6  /* option combination not implemented                       */
+} fga_status;
+
+/* Message describing the last failing call on this host thread. */
+const char *fga_last_error(void);
+/* Library version string. */
+const char *fga_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Beam state                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Beams are held as structure-of-arrays planes in caller device memory.
+ * f64 holds FGA_NF64 planes of `capacity` doubles; plane p of beam i is
+ * f64[p*capacity + i].  i32 holds FGA_NI32 int32 planes likewise, lineage
+ * one int64 per slot.  Live beams occupy slots [0, count).
+ *
+ * Meaning of the double planes (paper notation, eq:FGA and Sec. 2.2):
+ *   Q[3], P[3]         packet centre and propagation vector
+ *   ZQ_RE[9], ZQ_IM[9] dzQ, element (m, j) = d Q_j / d z_m at index 3m+j,
+ *                      with d/dz = d/dq - i d/dp (eq:op_zZ_app)
+ *   ZP_RE[9], ZP_IM[9] dzP, same layout
+ *   A0, A1 (re, im)    amplitudes: P beams a_P, 0; S beams a_SV, a_SH
+ *   S                  action (stays ~0: H is homogeneous of degree 1 in P)
+ *   W (re, im)         psi * dq * dp * (k/2pi)^{9/2}, the beam's fixed weight
+ *   E[3]               reference axis of the S polarisation frame
+ *                      N_SH = (E x P)/|E x P|, N_SV = (P/|P|) x N_SH
+ * int32 planes: BRANCH (0 P, 1 SH, 2 SV), SIGMA (+1 "+" flow, -1 "-" flow),
+ *   LAYER (layered media), GEN (interface generation), FLAGS (bit 0 alive,
+ *   bit 1 quarantined: non-finite state).
+ * lineage: canonical number ((branch*2 + dir)*Np + ip)*Nq + iq of the mesh
+ *   point the beam (or its ancestor) came from; children get
+ *   parent*4 + child index + FGA_LINEAGE_CHILD_BASE... (see fga_evolve). */
+enum {
+  FGA_Q = 0, FGA_P = 3,
+  FGA_ZQ_RE = 6, FGA_ZQ_IM = 15, FGA_ZP_RE = 24, FGA_ZP_IM = 33,
+  FGA_A0_RE = 42, FGA_A0_IM = 43, FGA_A1_RE = 44, FGA_A1_IM = 45,
+  FGA_S = 46, FGA_W_RE = 47, FGA_W_IM = 48, FGA_E = 49,
+  FGA_NF64 = 52
+};
+enum { FGA_BRANCH = 0, FGA_SIGMA = 1, FGA_LAYER = 2, FGA_GEN = 3, FGA_FLAGS = 4, FGA_NI32 = 5 };
+enum { FGA_FLAG_ALIVE = 1, FGA_FLAG_QUARANTINED = 2 };
+
+typedef struct {
+  int64_t capacity;   /* slots per plane                                         */
+  int64_t count;      /* live beams occupy [0, count); updated by the calls      */
+  double *f64;        /* device, FGA_NF64 * capacity doubles                     */
+  int32_t *i32;       /* device, FGA_NI32 * capacity int32                       */
+  int64_t *lineage;   /* device, capacity int64                                  */
+} fga_beams;
+
+/* ------------------------------------------------------------------------ */
+/* Media (Sec. 2, eq:ps_speed; Sec. 3.1 for layers)                          */
+/* ------------------------------------------------------------------------ */
+
+typedef enum {
+  FGA_MEDIUM_HOMOGENEOUS = 0,  /* constant c_P, c_S                                   */
+  FGA_MEDIUM_GRID = 1,         /* periodic node grid, trilinear interpolation of c and
+                                  of its central-difference gradient and Hessian      */
+  FGA_MEDIUM_LAYERED = 2       /* constant speeds per layer: flat layers in z or
+                                  concentric spherical shells                          */
+} fga_medium_kind;
+
+#define FGA_MAX_LAYERS 8
+#define FGA_GRID_NODE_DOUBLES 16  /* doubles per node per speed field in a grid table */
+
+typedef struct {
+  int kind;                /* fga_medium_kind                                          */
+  double cp, cs, rho;      /* homogeneous speeds and density                           */
+  /* FGA_MEDIUM_GRID: nodes lo + i*h (i = 0..n-1), periodic with period n*h.          */
+  int n[3];
+  double lo[3], h[3];
+  const double *table;     /* device, built by fga_medium_grid_build                    */
+  int two_fields;          /* 1: table holds a c_P field then a c_S field;
+                              0: one c_P field and c_S = cs_ratio * c_P                */
+  double cs_ratio;
+  /* FGA_MEDIUM_LAYERED: geometry 0: layer i is z in (bound[i-1], bound[i]) (layer 0
+     below bound[0]); geometry 1: layer i is |x| in (bound[i], bound[i-1]) (layer 0
+     outermost, radii descending).                                                     */
+  int geometry;
+  int nlayer;
+  double bound[FGA_MAX_LAYERS];
+  double cpl[FGA_MAX_LAYERS], csl[FGA_MAX_LAYERS], rhol[FGA_MAX_LAYERS];
+} fga_medium;
+
+/* Bytes of the derived-field table of a grid medium with n[0]*n[1]*n[2] nodes. */
+size_t fga_medium_grid_table_bytes(const int n[3], int two_fields);
+
+/* Builds the per-node fields c, grad c (3), Hessian (xx, yy, zz, xy, xz, yz)
+ * of each node field by second-order periodic central differences (the paper
+ * gives no discretisation of gridded media; this is the reading the library
+ * uses).  cp_nodes, cs_nodes (NULL unless two_fields): device, [z][y][x].
+ * table: device, fga_medium_grid_table_bytes(n, two_fields) bytes.
+ * Errors: FGA_EINVAL for n < 3 or non-positive h or NULL pointers. */
+fga_status fga_medium_grid_build(const int n[3], const double h[3], const double *cp_nodes,
+                                 const double *cs_nodes, double *table, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Step 1: decomposition (Sec. 2.1 eq:psi, eq:alpha^k; Sec. 2.2 Step 1)      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  double eps;              /* 1/k                                                     */
+  int nq[3]; double qlo[3], qh[3];   /* q mesh (Gaussian centres)                      */
+  int np[3]; double plo[3], ph[3];   /* p mesh (propagation vectors); |p| > 0          */
+  int ny[3]; double ylo[3], yh[3];   /* quadrature mesh on which f (and g) are given    */
+  int branch_mask;         /* bit b set: make branch b (0 P, 1 SH, 2 SV)               */
+  int one_way;             /* 1: only "+" beams, psi = FBI[f].n (f is taken as the
+                              "+"-going part); 0: "+" and "-" beams per eq:alpha^k     */
+  double cull_abs;         /* beams with |psi| < cull_abs are not created             */
+} fga_mesh;
+
+/* Workspace bytes fga_decompose needs for this mesh (with_g: g != NULL). */
+size_t fga_decompose_workspace_bytes(const fga_mesh *mesh, int with_g);
+/* Number of candidate beams (upper bound of the beams made). */
+int64_t fga_decompose_candidates(const fga_mesh *mesh);
+
+/* psi_{b,+-}(q,p) = (1/2) FBI[f](q,p).n_b +- (i eps/(2|p|)) FBI[g/c_b](q,p).n_b,
+ * FBI[h](q,p) = sum_y yh^3 h(y) exp(-i p.(y-q)/eps - |y-q|^2/(2 eps)),
+ * (eq:psi with eq:alpha^k read with prefactor 1/(2kc|p|), the normalisation
+ * under which eq:FGA returns f at t = 0), then w = psi dq dp (2 pi eps)^{-9/2},
+ * Q = q, P = p, dzQ = I, dzP = -iI, a = 2^{3/2} on the beam's own polarisation,
+ * S = 0.  One-way mode: psi_{b,+} = FBI[f].n_b.  Beams are written in lineage
+ * order (stable), replacing the previous contents; beams->count is set (this
+ * call synchronises `stream` to read it back).
+ * f, g: device, complex [3][ny2][ny1][ny0]; g may be NULL (g = 0).
+ * Errors: FGA_EINVAL (mesh sizes, |p| = 0 on the mesh, NULL f),
+ *         FGA_ENOMEM (workspace), FGA_ECAPACITY (more beams than capacity). */
+fga_status fga_decompose(const fga_medium *med, const fga_mesh *mesh, const double *f,
+                         const double *g, fga_beams *beams, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Step 2: evolution (Sec. 2.2, eq:char_plus, eq:char_minus, eq:DzDt,        */
+/* eq:amp_P, eq:amp_SV, eq:amp_SH; Sec. 2.3 fixed-step RK4)                  */
+/* ------------------------------------------------------------------------ */
+
+typedef enum { FGA_FP64 = 0, FGA_FP32 = 1, FGA_BF16X3 = 2, FGA_FP16X3 = 3 } fga_precision;
+
+typedef struct {
+  int64_t n;               /* receivers                                                */
+  const double *xyz;       /* device, [n][3] Cartesian positions                       */
+  int stride;              /* a sample after every `stride` steps (>= 1)               */
+  double eps, tau;         /* summation: 1/k and window exp(-tau) (half-width
+                              sqrt(2 tau eps) per axis)                                */
+  int precision;           /* fga_precision of the receiver sums                       */
+} fga_receivers;
+
+typedef struct {
+  int chunk;               /* RK4 steps per integrator launch (0: library default)     */
+  double cutoff_abs;       /* drop beams with |w| max(|a0|,|a1|) < cutoff_abs (0: off)  */
+  int compact;             /* 1: compact the beam set after culling (stable order)     */
+  int64_t batch;           /* beams per receiver batch (0: library default)            */
+} fga_evolve_opts;
+
+typedef struct {
+  int64_t beam_steps;      /* RK4 steps taken by live beams                            */
+  int64_t evals;           /* in-window (beam, receiver, sample) terms summed          */
+  int64_t culled;          /* beams dropped by the cutoff                              */
+  int64_t quarantined;     /* beams dropped for non-finite state                       */
+} fga_evolve_stats;
+
+size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_evolve_opts *opts,
+                                  const fga_receivers *rec);
+
+/* Advances every live beam by nsteps classic RK4 steps of size dt, in place.
+ * After each step an S beam whose P has come within 10 degrees of its frame
+ * axis switches axis (e_z <-> e_x) and re-expresses (a_SV, a_SH) so that the
+ * physical polarisation is unchanged.  If rec != NULL, after every
+ * rec->stride-th step the beams are summed at the receivers (eq:FGA with the
+ * box window) into seis: device, complex [rec->n][nsteps/rec->stride][3]
+ * (overwritten).  stats (host, may be NULL) receives counters; this call
+ * synchronises `stream` when stats != NULL or culling is on.
+ * Errors: FGA_EINVAL, FGA_ENOMEM (workspace), FGA_EDEVICE. */
+fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int nsteps,
+                      const fga_evolve_opts *opts, const fga_receivers *rec, double *seis,
+                      void *workspace, size_t workspace_bytes, void *stream,
+                      fga_evolve_stats *stats);
+
+/* ------------------------------------------------------------------------ */
+/* Step 3: reconstruction (Sec. 2.1 eq:FGA; Sec. 3 spherical coordinates)    */
+/* ------------------------------------------------------------------------ */
+
+/* u(x) = sum_b w_b exp(i S_b/eps) A_b exp(i P_b.(x-Q_b)/eps - |x-Q_b|^2/(2 eps))
+ * over the beams with max_d |x_d - Q_d| <= sqrt(2 tau eps), A_b = a_P P/|P| or
+ * a_SV N_SV + a_SH N_SH.  xyz: device [n][3]; out: device complex [n][3]
+ * (overwritten).  evals (host, may be NULL): number of in-window terms; the
+ * call synchronises `stream` when evals != NULL. */
+size_t fga_reconstruct_points_workspace_bytes(const fga_beams *beams, int64_t n);
+fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau, int64_t n,
+                                  const double *xyz, int precision, double *out,
+                                  void *workspace, size_t workspace_bytes, void *stream,
+                                  int64_t *evals);
+
+/* The same sum on the grid points lo + i*h (i < n per axis), using the
+ * separability of the window and the phase: each 16^3 tile is a complex
+ * Khatri-Rao x factor product on the matrix cores.  out: device complex
+ * [3][n2][n1][n0] (overwritten).  precision: FGA_FP64 (FP64 matrix cores),
+ * FGA_FP32, FGA_BF16X3 or FGA_FP16X3 (split hi+lo factors, FP32 accumulation;
+ * phases reduced modulo 2 pi in FP64 before the cast).  evals (host, may be
+ * NULL): algorithmic in-window (beam, point) terms. */
+size_t fga_reconstruct_grid_workspace_bytes(const fga_beams *beams, const int n[3], double eps,
+                                            double tau, const double h[3]);
+fga_status fga_reconstruct_grid(const fga_beams *beams, double eps, double tau, const int n[3],
+                                const double lo[3], const double h[3], int precision, double *out,
+                                void *workspace, size_t workspace_bytes, void *stream,
+                                int64_t *evals);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Kernels whose launches can be timed. */
+typedef enum {
+  FGA_K_INTEGRATE = 0,   /* RK4 integrator                                   */
+  FGA_K_SUM_POINTS = 1,  /* receiver / point summation                       */
+  FGA_K_GRID_TILE = 2,   /* grid tile GEMMs on the matrix cores              */
+  FGA_K_FBI_GEMM = 3,    /* FBI mode products of the decomposition           */
+  FGA_K_COUNT = 4
+} fga_kernel_id;
+
+/* While enabled (on != 0), every launch of the kernels above is bracketed by
+ * a pair of hipEvents recorded on the launch's own stream.  Enabling or
+ * disabling discards what was recorded.  Process-wide; not thread-safe. */
+fga_status fga_profile_enable(int on);
+/* Waits for the recorded events of kernel `k` and returns the number of
+ * launches and their summed duration in milliseconds (GPU clock); reset != 0
+ * clears the record afterwards.  Errors: FGA_EINVAL for an unknown kernel. */
+fga_status fga_profile_read(int k, int64_t *launches, double *total_ms, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FGA_H */

@@ -1,0 +1,487 @@
+// C ABI of the gfx950 FGA library: argument validation, workspace layout and
+// the host-side sequencing of the kernels.  See include/fga.h.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device_common.h"
+
+namespace fga {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...)
+{
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+fga_status fail(fga_status st, const char *fmt, ...)
+{
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+int64_t decompose_candidates(const fga_mesh *m);
+
+// ------------------------------------------------------------ kernel timing --
+namespace {
+struct ProfRec {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+bool g_prof_on = false;
+ProfRec g_prof[FGA_K_COUNT];
+
+void prof_clear()
+{
+  for (auto &r : g_prof) {
+    for (auto &p : r.ev) {
+      hipEventDestroy(p.first);
+      hipEventDestroy(p.second);
+    }
+    r.ev.clear();
+  }
+}
+}  // namespace
+
+ProfScope::ProfScope(int kernel, hipStream_t s) : k(kernel), st(s)
+{
+  if (g_prof_on && hipEventCreate(&a) == hipSuccess) {
+    if (hipEventRecord(a, st) != hipSuccess) {
+      hipEventDestroy(a);
+      a = nullptr;
+    }
+  } else {
+    a = nullptr;
+  }
+}
+
+ProfScope::~ProfScope()
+{
+  if (!a) return;
+  hipEvent_t b;
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return;
+  }
+  hipEventRecord(b, st);
+  g_prof[k].ev.emplace_back(a, b);
+}
+
+fga_status make_dev_medium(const fga_medium *m, DevMedium *o)
+{
+  if (!m) return fail(FGA_EINVAL, "medium is NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->kind = m->kind;
+  switch (m->kind) {
+  case FGA_MEDIUM_HOMOGENEOUS:
+    if (!(m->cp > 0) || !(m->cs > 0)) return fail(FGA_EINVAL, "homogeneous medium needs cp > 0 and cs > 0");
+    o->cp = m->cp;
+    o->cs = m->cs;
+    return FGA_OK;
+  case FGA_MEDIUM_GRID:
+    if (!m->table) return fail(FGA_EINVAL, "grid medium table is NULL");
+    for (int d = 0; d < 3; ++d) {
+      if (m->n[d] < 3) return fail(FGA_EINVAL, "grid medium needs n >= 3 per axis");
+      if (!(m->h[d] > 0)) return fail(FGA_EINVAL, "grid medium needs h > 0");
+      o->n[d] = m->n[d];
+      o->lo[d] = m->lo[d];
+      o->ih[d] = 1.0 / m->h[d];
+    }
+    o->table = m->table;
+    o->two_fields = m->two_fields ? 1 : 0;
+    o->cs_ratio = m->cs_ratio;
+    o->field_stride = (int64_t)FGA_GRID_NODE_DOUBLES * m->n[0] * m->n[1] * m->n[2];
+    if (!o->two_fields && !(m->cs_ratio > 0)) return fail(FGA_EINVAL, "grid medium needs cs_ratio > 0");
+    return FGA_OK;
+  case FGA_MEDIUM_LAYERED:
+    if (m->nlayer < 1 || m->nlayer > FGA_MAX_LAYERS) return fail(FGA_EINVAL, "layered medium needs 1..8 layers");
+    if (m->geometry != 0 && m->geometry != 1) return fail(FGA_EINVAL, "layered geometry must be 0 or 1");
+    o->geometry = m->geometry;
+    o->nlayer = m->nlayer;
+    for (int l = 0; l < FGA_MAX_LAYERS; ++l) {
+      o->bound[l] = m->bound[l];
+      o->cpl[l] = m->cpl[l];
+      o->csl[l] = m->csl[l];
+    }
+    for (int l = 0; l < m->nlayer; ++l)
+      if (!(m->cpl[l] > 0) || !(m->csl[l] > 0)) return fail(FGA_EINVAL, "layer %d has non-positive speed", l);
+    return FGA_OK;
+  default:
+    return fail(FGA_EINVAL, "unknown medium kind %d", m->kind);
+  }
+}
+
+static fga_status check_beams(const fga_beams *b)
+{
+  if (!b) return fail(FGA_EINVAL, "beams is NULL");
+  if (b->capacity < 0 || b->count < 0 || b->count > b->capacity) return fail(FGA_EINVAL, "beam count/capacity invalid");
+  if (b->capacity > 0 && (!b->f64 || !b->i32 || !b->lineage)) return fail(FGA_EINVAL, "beam planes are NULL");
+  return FGA_OK;
+}
+
+static fga_status check_mesh(const fga_mesh *m)
+{
+  if (!m) return fail(FGA_EINVAL, "mesh is NULL");
+  if (!(m->eps > 0)) return fail(FGA_EINVAL, "eps must be > 0");
+  for (int d = 0; d < 3; ++d) {
+    if (m->nq[d] < 1 || m->np[d] < 1 || m->ny[d] < 1) return fail(FGA_EINVAL, "mesh sizes must be >= 1");
+    if (!(m->qh[d] > 0) || !(m->ph[d] > 0) || !(m->yh[d] > 0)) return fail(FGA_EINVAL, "mesh spacings must be > 0");
+  }
+  if (m->branch_mask < 1 || m->branch_mask > 7) return fail(FGA_EINVAL, "branch_mask must be in 1..7");
+  // |p| must not vanish on the p mesh: p_d = lo + i h is zero only if lo/h is a non-positive integer > -n
+  bool zero = true;
+  for (int d = 0; d < 3; ++d) {
+    const double u = -m->plo[d] / m->ph[d];
+    zero = zero && u >= 0 && u <= m->np[d] - 1 && std::fabs(u - std::round(u)) < 1e-12;
+  }
+  if (zero) return fail(FGA_EINVAL, "the p mesh contains p = 0");
+  const double ncand = 6.0 * m->nq[0] * m->nq[1] * m->nq[2] * (double)m->np[0] * m->np[1] * m->np[2];
+  if (ncand > 4.0e9) return fail(FGA_EUNSUPPORTED, "more than 4e9 candidate beams");
+  return FGA_OK;
+}
+
+}  // namespace fga
+
+using namespace fga;
+
+extern "C" {
+
+const char *fga_last_error(void) { return g_err.c_str(); }
+
+fga_status fga_profile_enable(int on)
+{
+  prof_clear();
+  g_prof_on = on != 0;
+  return FGA_OK;
+}
+
+fga_status fga_profile_read(int k, int64_t *launches, double *total_ms, int reset)
+{
+  if (k < 0 || k >= FGA_K_COUNT) return fail(FGA_EINVAL, "unknown kernel id %d", k);
+  double tot = 0.0;
+  for (auto &p : g_prof[k].ev) {
+    FGA_HIP(hipEventSynchronize(p.second));
+    float ms = 0.0f;
+    FGA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)g_prof[k].ev.size();
+  if (total_ms) *total_ms = tot;
+  if (reset) {
+    for (auto &p : g_prof[k].ev) {
+      hipEventDestroy(p.first);
+      hipEventDestroy(p.second);
+    }
+    g_prof[k].ev.clear();
+  }
+  return FGA_OK;
+}
+const char *fga_version(void) { return "fga-gfx950 0.1"; }
+
+size_t fga_medium_grid_table_bytes(const int n[3], int two_fields)
+{
+  if (!n || n[0] < 1 || n[1] < 1 || n[2] < 1) return 0;
+  return sizeof(double) * FGA_GRID_NODE_DOUBLES * (size_t)n[0] * n[1] * n[2] * (two_fields ? 2 : 1);
+}
+
+fga_status fga_medium_grid_build(const int n[3], const double h[3], const double *cp_nodes, const double *cs_nodes,
+                                 double *table, void *stream)
+{
+  if (!n || !h || !cp_nodes || !table) return fail(FGA_EINVAL, "NULL argument");
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 3) return fail(FGA_EINVAL, "grid needs n >= 3 per axis");
+    if (!(h[d] > 0)) return fail(FGA_EINVAL, "grid needs h > 0");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  FGA_HIP(launch_grid_build(n, h, cp_nodes, table, st));
+  if (cs_nodes)
+    FGA_HIP(launch_grid_build(n, h, cs_nodes, table + (size_t)FGA_GRID_NODE_DOUBLES * n[0] * n[1] * n[2], st));
+  return FGA_OK;
+}
+
+int64_t fga_decompose_candidates(const fga_mesh *mesh)
+{
+  if (check_mesh(mesh) != FGA_OK) return -1;
+  return decompose_candidates(mesh);
+}
+
+size_t fga_decompose_workspace_bytes(const fga_mesh *mesh, int with_g)
+{
+  if (check_mesh(mesh) != FGA_OK) return 0;
+  Arena ar(nullptr, 0);
+  size_t need = 0;
+  DevMedium dm{};
+  fga_beams b{};
+  double dummy;
+  decompose_impl(dm, mesh, &dummy, with_g ? &dummy : nullptr, &b, ar, nullptr, true, &need);
+  return need;
+}
+
+fga_status fga_decompose(const fga_medium *med, const fga_mesh *mesh, const double *f, const double *g,
+                         fga_beams *beams, void *workspace, size_t workspace_bytes, void *stream)
+{
+  fga_status s;
+  DevMedium dm;
+  if ((s = make_dev_medium(med, &dm)) != FGA_OK) return s;
+  if ((s = check_mesh(mesh)) != FGA_OK) return s;
+  if ((s = check_beams(beams)) != FGA_OK) return s;
+  if (!f) return fail(FGA_EINVAL, "f is NULL");
+  Arena ar(workspace, workspace_bytes);
+  size_t need = 0;
+  return decompose_impl(dm, mesh, f, g, beams, ar, (hipStream_t)stream, false, &need);
+}
+
+// ------------------------------------------------------------------ evolve --
+
+namespace {
+
+struct EvolvePlan {
+  int chunk;
+  int64_t batch;
+  int nsamp;        // total samples
+  int bpb;          // beams per receiver workgroup
+};
+
+EvolvePlan evolve_plan(const fga_beams *b, int nsteps, const fga_evolve_opts *o, const fga_receivers *r)
+{
+  EvolvePlan p;
+  p.chunk = (o && o->chunk > 0) ? o->chunk : (r ? 16 : 50);
+  if (p.chunk > nsteps) p.chunk = nsteps > 0 ? nsteps : 1;
+  p.batch = (o && o->batch > 0) ? o->batch : ((int64_t)1 << 22);
+  if (p.batch > b->count) p.batch = b->count > 0 ? b->count : 1;
+  p.nsamp = r ? nsteps / r->stride : 0;
+  p.bpb = 4096;
+  return p;
+}
+
+fga_status evolve_layout(const fga_beams *b, const EvolvePlan &p, const fga_receivers *r, Arena &ar,
+                         unsigned long long **ctr, double **emit, double **partial)
+{
+  *ctr = ar.take<unsigned long long>(4);
+  *emit = nullptr;
+  *partial = nullptr;
+  if (r) {
+    const int m = (p.chunk + r->stride - 1) / r->stride + 1;
+    *emit = ar.take<double>((size_t)m * 12 * p.batch);
+    const int64_t nblk = (p.batch + p.bpb - 1) / p.bpb;
+    *partial = ar.take<double>((size_t)nblk * m * r->n * 6);
+  }
+  return FGA_OK;
+}
+
+}  // namespace
+
+size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_evolve_opts *opts,
+                                  const fga_receivers *rec)
+{
+  if (check_beams(beams) != FGA_OK || nsteps < 0) return 0;
+  if (rec && rec->stride < 1) return 0;
+  const EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
+  Arena ar(nullptr, 0);
+  unsigned long long *c;
+  double *e, *pa;
+  evolve_layout(beams, p, rec, ar, &c, &e, &pa);
+  size_t need = ar.used;
+  if (opts && opts->compact) {
+    Arena a2(nullptr, 0);
+    size_t n2 = 0;
+    fga_beams bb = *beams;
+    compact_beams(&bb, a2, nullptr, true, &n2);
+    need = need > n2 ? need : n2;
+  }
+  return need;
+}
+
+fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int nsteps, const fga_evolve_opts *opts,
+                      const fga_receivers *rec, double *seis, void *workspace, size_t workspace_bytes, void *stream,
+                      fga_evolve_stats *stats)
+{
+  fga_status s;
+  DevMedium dm;
+  if ((s = make_dev_medium(med, &dm)) != FGA_OK) return s;
+  if ((s = check_beams(beams)) != FGA_OK) return s;
+  if (nsteps < 0) return fail(FGA_EINVAL, "nsteps < 0");
+  if (!(dt > 0) && nsteps > 0) return fail(FGA_EINVAL, "dt must be > 0");
+  if (rec) {
+    if (rec->stride < 1) return fail(FGA_EINVAL, "receiver stride must be >= 1");
+    if (rec->n < 0 || (rec->n > 0 && !rec->xyz)) return fail(FGA_EINVAL, "receiver positions invalid");
+    if (!(rec->eps > 0) || !(rec->tau > 0)) return fail(FGA_EINVAL, "receiver eps and tau must be > 0");
+    if (rec->precision != FGA_FP64) return fail(FGA_EUNSUPPORTED, "receiver precision %d not built", rec->precision);
+    if (!seis && rec->n > 0 && nsteps / rec->stride > 0) return fail(FGA_EINVAL, "seis is NULL");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
+  Arena ar(workspace, workspace_bytes);
+  unsigned long long *ctr;
+  double *emit, *partial;
+  evolve_layout(beams, p, rec, ar, &ctr, &emit, &partial);
+  if (!ctr || (rec && (!emit || !partial)))
+    return fail(FGA_ENOMEM, "evolve workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
+  FGA_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), st));
+
+  const double cutoff = opts ? opts->cutoff_abs : 0.0;
+  const int64_t n = beams->count;
+  for (int s0 = 0; s0 < nsteps; s0 += p.chunk) {
+    const int m = s0 + p.chunk <= nsteps ? p.chunk : nsteps - s0;
+    const bool last = s0 + m >= nsteps;
+    int ns = 0, sfirst = 0;
+    if (rec) {
+      sfirst = s0 / rec->stride;
+      ns = (s0 + m) / rec->stride - sfirst;
+    }
+    for (int64_t b0 = 0; b0 < n; b0 += (rec && ns > 0) ? p.batch : n) {
+      const int64_t b1 = (rec && ns > 0) ? (b0 + p.batch < n ? b0 + p.batch : n) : n;
+      IntegrateArgs a{};
+      a.f64 = beams->f64;
+      a.i32 = beams->i32;
+      a.cap = beams->capacity;
+      a.beg = b0;
+      a.end = b1;
+      a.dt = dt;
+      a.nsteps = m;
+      a.step0 = s0;
+      a.stride = (rec && ns > 0) ? rec->stride : 0;
+      a.emit = emit;
+      a.eps_emit = rec ? rec->eps : 1.0;
+      a.cutoff_abs = last ? cutoff : 0.0;
+      a.counters = ctr;
+      FGA_HIP(launch_integrate(dm, a, st));
+      if (rec && ns > 0 && rec->n > 0) {
+        PointsArgs pa{};
+        pa.emit = emit;
+        pa.nb = b1 - b0;
+        pa.m = ns;
+        pa.xyz = rec->xyz;
+        pa.n = rec->n;
+        pa.eps = rec->eps;
+        pa.tau = rec->tau;
+        pa.partial = partial;
+        pa.beams_per_block = p.bpb;
+        pa.evals = ctr + 3;
+        int nblk = 0;
+        FGA_HIP(launch_sum_points(pa, &nblk, st));
+        FGA_HIP(launch_reduce_points(partial, nblk, ns, rec->n, seis, p.nsamp, sfirst, b0 > 0 ? 1 : 0, st));
+      }
+    }
+    if (n == 0 && rec && ns > 0 && rec->n > 0)
+      FGA_HIP(launch_reduce_points(partial, 0, ns, rec->n, seis, p.nsamp, sfirst, 0, st));
+  }
+  if (opts && opts->compact && cutoff > 0 && nsteps > 0) {
+    Arena a2(workspace, workspace_bytes);
+    size_t need = 0;
+    if ((s = compact_beams(beams, a2, st, false, &need)) != FGA_OK) return s;
+  }
+  if (stats || (cutoff > 0 && nsteps > 0)) {
+    unsigned long long h[4] = {0, 0, 0, 0};
+    FGA_HIP(hipMemcpyAsync(h, ctr, sizeof h, hipMemcpyDeviceToHost, st));
+    FGA_HIP(hipStreamSynchronize(st));
+    if (stats) {
+      stats->beam_steps = (int64_t)h[0];
+      stats->culled = (int64_t)h[1];
+      stats->quarantined = (int64_t)h[2];
+      stats->evals = (int64_t)h[3];
+    }
+  }
+  return FGA_OK;
+}
+
+// ----------------------------------------------------------- reconstruct --
+
+size_t fga_reconstruct_points_workspace_bytes(const fga_beams *beams, int64_t n)
+{
+  if (check_beams(beams) != FGA_OK || n < 0) return 0;
+  const int64_t batch = beams->count < ((int64_t)1 << 22) ? (beams->count > 0 ? beams->count : 1) : ((int64_t)1 << 22);
+  Arena ar(nullptr, 0);
+  ar.take<unsigned long long>(1);
+  ar.take<double>((size_t)12 * batch);
+  ar.take<double>((size_t)((batch + 4095) / 4096) * n * 6);
+  return ar.used;
+}
+
+fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau, int64_t n, const double *xyz,
+                                  int precision, double *out, void *workspace, size_t workspace_bytes, void *stream,
+                                  int64_t *evals)
+{
+  fga_status s;
+  if ((s = check_beams(beams)) != FGA_OK) return s;
+  if (n < 0 || (n > 0 && (!xyz || !out))) return fail(FGA_EINVAL, "points invalid");
+  if (!(eps > 0) || !(tau > 0)) return fail(FGA_EINVAL, "eps and tau must be > 0");
+  if (precision != FGA_FP64) return fail(FGA_EUNSUPPORTED, "point precision %d not built", precision);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nb = beams->count;
+  const int64_t batch = nb < ((int64_t)1 << 22) ? (nb > 0 ? nb : 1) : ((int64_t)1 << 22);
+  Arena ar(workspace, workspace_bytes);
+  unsigned long long *ctr = ar.take<unsigned long long>(1);
+  double *emit = ar.take<double>((size_t)12 * batch);
+  double *partial = ar.take<double>((size_t)((batch + 4095) / 4096) * n * 6);
+  if (!ctr || !emit || !partial)
+    return fail(FGA_ENOMEM, "reconstruct workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
+  FGA_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long), st));
+  if (nb == 0) FGA_HIP(launch_reduce_points(partial, 0, 1, n, out, 1, 0, 0, st));
+  for (int64_t b0 = 0; b0 < nb; b0 += batch) {
+    const int64_t b1 = b0 + batch < nb ? b0 + batch : nb;
+    FGA_HIP(launch_emit(beams->f64, beams->i32, beams->capacity, b0, b1, eps, emit, st));
+    PointsArgs pa{};
+    pa.emit = emit;
+    pa.nb = b1 - b0;
+    pa.m = 1;
+    pa.xyz = xyz;
+    pa.n = n;
+    pa.eps = eps;
+    pa.tau = tau;
+    pa.partial = partial;
+    pa.beams_per_block = 4096;
+    pa.evals = ctr;
+    int nblk = 0;
+    FGA_HIP(launch_sum_points(pa, &nblk, st));
+    FGA_HIP(launch_reduce_points(partial, nblk, 1, n, out, 1, 0, b0 > 0 ? 1 : 0, st));
+  }
+  if (evals) {
+    unsigned long long h = 0;
+    FGA_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, st));
+    FGA_HIP(hipStreamSynchronize(st));
+    *evals = (int64_t)h;
+  }
+  return FGA_OK;
+}
+
+size_t fga_reconstruct_grid_workspace_bytes(const fga_beams *beams, const int n[3], double eps, double tau,
+                                            const double h[3])
+{
+  if (check_beams(beams) != FGA_OK || !n || !h) return 0;
+  const double lo[3] = {0, 0, 0};
+  Arena ar(nullptr, 0);
+  size_t need = 0;
+  grid_sum_impl(beams, eps, tau, n, lo, h, FGA_FP64, nullptr, ar, nullptr, true, &need, nullptr);
+  return need;
+}
+
+fga_status fga_reconstruct_grid(const fga_beams *beams, double eps, double tau, const int n[3], const double lo[3],
+                                const double h[3], int precision, double *out, void *workspace,
+                                size_t workspace_bytes, void *stream, int64_t *evals)
+{
+  fga_status s;
+  if ((s = check_beams(beams)) != FGA_OK) return s;
+  if (!n || !lo || !h || !out) return fail(FGA_EINVAL, "NULL grid argument");
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 1) return fail(FGA_EINVAL, "grid sizes must be >= 1");
+    if (!(h[d] > 0)) return fail(FGA_EINVAL, "grid spacing must be > 0");
+  }
+  if (!(eps > 0) || !(tau > 0)) return fail(FGA_EINVAL, "eps and tau must be > 0");
+  Arena ar(workspace, workspace_bytes);
+  size_t need = 0;
+  return grid_sum_impl(beams, eps, tau, n, lo, h, precision, out, ar, (hipStream_t)stream, false, &need, evals);
+}
+
+}  // extern "C"

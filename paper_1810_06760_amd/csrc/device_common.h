@@ -1,0 +1,108 @@
+// Device-side helpers shared by the gfx950 kernels: medium evaluation and
+// polarisation frames.
+#pragma once
+
+#include "fga_internal.h"
+
+namespace fga {
+
+// Medium kinds a kernel is specialised for.
+enum { MK_HOMOG = 0, MK_GRID = 1, MK_LAYERED = 2 };
+
+// Speed of wave type sp (0 = P, 1 = S) at x: c, gradient g and Hessian H
+// (xx, yy, zz, xy, xz, yz).  Grid media interpolate the ten precomputed node
+// fields trilinearly (periodic); each node is one 128-byte record.
+template <int MK>
+__device__ __forceinline__ void medium_eval(const DevMedium &m, int sp, int layer, const double *x,
+                                            double &c, double g[3], double H[6])
+{
+  if constexpr (MK == MK_HOMOG) {
+    c = sp == 0 ? m.cp : m.cs;
+    g[0] = g[1] = g[2] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) H[i] = 0.0;
+  } else if constexpr (MK == MK_LAYERED) {
+    c = sp == 0 ? m.cpl[layer] : m.csl[layer];
+    g[0] = g[1] = g[2] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) H[i] = 0.0;
+  } else {
+    const double *tab = m.table;
+    double scale = 1.0;
+    if (sp) {
+      if (m.two_fields) tab += m.field_stride;
+      else scale = m.cs_ratio;
+    }
+    int i0[3], i1[3];
+    double t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double u = (x[d] - m.lo[d]) * m.ih[d];
+      double fl = floor(u);
+      t[d] = u - fl;
+      int ii = (int)fl % m.n[d];
+      if (ii < 0) ii += m.n[d];
+      i0[d] = ii;
+      i1[d] = ii + 1 == m.n[d] ? 0 : ii + 1;
+    }
+    double v[10];
+#pragma unroll
+    for (int f = 0; f < 10; ++f) v[f] = 0.0;
+#pragma unroll 2
+    for (int corner = 0; corner < 8; ++corner) {
+      const int ix = (corner & 1) ? i1[0] : i0[0];
+      const int iy = (corner & 2) ? i1[1] : i0[1];
+      const int iz = (corner & 4) ? i1[2] : i0[2];
+      const double w = ((corner & 1) ? t[0] : 1.0 - t[0]) * ((corner & 2) ? t[1] : 1.0 - t[1]) *
+                       ((corner & 4) ? t[2] : 1.0 - t[2]);
+      const double2 *p = reinterpret_cast<const double2 *>(
+          tab + (size_t)FGA_GRID_NODE_DOUBLES * (((size_t)iz * m.n[1] + iy) * m.n[0] + ix));
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const double2 a = p[k];
+        v[2 * k] += w * a.x;
+        v[2 * k + 1] += w * a.y;
+      }
+    }
+    c = scale * v[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] = scale * v[1 + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) H[k] = scale * v[4 + k];
+  }
+}
+
+// SH/SV frame: N_SH = (e x P)/|e x P|, N_SV = (P/|P|) x N_SH.
+__device__ __forceinline__ void s_frame(const double P[3], const double e[3], double nsh[3], double nsv[3])
+{
+  double x0 = e[1] * P[2] - e[2] * P[1];
+  double x1 = e[2] * P[0] - e[0] * P[2];
+  double x2 = e[0] * P[1] - e[1] * P[0];
+  double in = 1.0 / sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+  nsh[0] = x0 * in; nsh[1] = x1 * in; nsh[2] = x2 * in;
+  double ip = 1.0 / sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+  double p0 = P[0] * ip, p1 = P[1] * ip, p2 = P[2] * ip;
+  nsv[0] = p1 * nsh[2] - p2 * nsh[1];
+  nsv[1] = p2 * nsh[0] - p0 * nsh[2];
+  nsv[2] = p0 * nsh[1] - p1 * nsh[0];
+}
+
+// Rank of this lane among the lanes of its 256-thread block with keep = true,
+// and the block total.  Uses wavefront ballots; must be called by all threads.
+__device__ __forceinline__ int block_rank(bool keep, int *total)
+{
+  __shared__ int wsum[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(keep);
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int r = __popcll(m & lt);
+  if (lane == 0) wsum[w] = __popcll(m);
+  __syncthreads();
+  int off = 0;
+  for (int k = 0; k < w; ++k) off += wsum[k];
+  *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  __syncthreads();
+  return off + r;
+}
+
+}  // namespace fga

@@ -1,0 +1,146 @@
+// Internal declarations of the gfx950 FGA library (host launchers, device
+// helpers, error reporting).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "fga.h"
+
+namespace fga {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const char *fmt, ...);
+fga_status fail(fga_status st, const char *fmt, ...);
+
+#define FGA_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::fga::fail(FGA_EDEVICE, "%s failed: %s (%s:%d)", #call,                  \
+                         hipGetErrorString(e_), __FILE__, __LINE__);                   \
+  } while (0)
+
+#define FGA_LAUNCH_CHECK()                                                             \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                 \
+    if (e_ != hipSuccess)                                                              \
+      return ::fga::fail(FGA_EDEVICE, "kernel launch failed: %s (%s:%d)",              \
+                         hipGetErrorString(e_), __FILE__, __LINE__);                   \
+  } while (0)
+
+// --------------------------------------------------------------- timing --
+// Records a start event on construction and a stop event on destruction
+// (around one kernel launch) when profiling is enabled.
+struct ProfScope {
+  int k;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(int kernel, hipStream_t s);
+  ~ProfScope();
+};
+
+// ------------------------------------------------------------- workspace --
+// Bump allocator over a caller workspace; every sub-buffer is 256-byte aligned.
+struct Arena {
+  char *base = nullptr;
+  size_t size = 0, used = 0;
+  Arena(void *b, size_t s) : base(static_cast<char *>(b)), size(s) {}
+  template <class T> T *take(size_t n) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + n * sizeof(T);
+    if (base == nullptr || used > size) return nullptr;
+    return reinterpret_cast<T *>(base + off);
+  }
+  static size_t need(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+};
+
+// ----------------------------------------------------------- media (GPU) --
+// Device view of a medium; passed by value to kernels.
+struct DevMedium {
+  int kind;
+  double cp, cs;
+  // grid
+  const double *table;
+  int n[3];
+  double lo[3], ih[3];
+  int64_t field_stride;   // doubles between the c_P and c_S tables
+  int two_fields;
+  double cs_ratio;
+  // layered
+  int geometry, nlayer;
+  double bound[FGA_MAX_LAYERS];
+  double cpl[FGA_MAX_LAYERS], csl[FGA_MAX_LAYERS];
+};
+
+fga_status make_dev_medium(const fga_medium *m, DevMedium *out);
+
+// -------------------------------------------------------------- launchers --
+hipError_t launch_grid_build(const int n[3], const double h[3], const double *c, double *table,
+                             hipStream_t st);
+
+struct IntegrateArgs {
+  double *f64;
+  int32_t *i32;
+  int64_t cap;
+  int64_t beg, end;          // beams [beg, end)
+  double dt;
+  int nsteps;
+  int step0;                 // global index of the first step of this launch
+  int stride;                // emit after steps with (step+1) % stride == 0 (0: never)
+  double *emit;              // [n_emit][12][end-beg]
+  double eps_emit;
+  double cutoff_abs;
+  unsigned long long *counters;  // [0] beam-steps, [1] culled, [2] quarantined
+};
+hipError_t launch_integrate(const DevMedium &m, const IntegrateArgs &a, hipStream_t st);
+
+struct PointsArgs {
+  const double *emit;        // [m][12][nb] records
+  int64_t nb;                // beams in the batch
+  int m;                     // samples in the batch
+  const double *xyz;         // [n][3]
+  int64_t n;
+  double eps, tau;
+  double *partial;           // [nblk][m][n][6]
+  int beams_per_block;
+  unsigned long long *evals;
+};
+hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st);
+// seis[r][s0 + s][c] (+)= sum_blk partial[blk][s][r][c]
+hipError_t launch_reduce_points(const double *partial, int nblk, int m, int64_t n, double *out,
+                                int64_t out_samples, int s0, int accumulate, hipStream_t st);
+
+// beams -> emission records (current state, one sample)
+hipError_t launch_emit(const double *f64, const int32_t *i32, int64_t cap, int64_t beg, int64_t end,
+                       double eps, double *emit, hipStream_t st);
+
+// decomposition
+struct DecompArgs {
+  const fga_mesh *mesh;
+  const double *Ft;          // complex [3][nz*npz][ny*npy][nx*npx] (see k_decompose)
+  const double *Gt;          // NULL or complex [2][3][...] (FBI[g/c_P], FBI[g/c_S])
+  double *f64;
+  int32_t *i32;
+  int64_t *lineage;
+  int64_t cap;
+};
+fga_status decompose_impl(const DevMedium &dm, const fga_mesh *mesh, const double *f, const double *g,
+                          fga_beams *beams, Arena &ar, hipStream_t st, bool size_only, size_t *need);
+
+// exclusive scan of n int64 values (one workgroup); total = sum
+hipError_t launch_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st);
+
+// stable compaction of the beam set by FLAGS & ALIVE
+fga_status compact_beams(fga_beams *b, Arena &ar, hipStream_t st, bool size_only, size_t *need);
+
+// grid summation
+fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n[3], const double lo[3],
+                         const double h[3], int precision, double *out, Arena &ar, hipStream_t st,
+                         bool size_only, size_t *need, int64_t *evals);
+
+}  // namespace fga

@@ -1,0 +1,431 @@
+// Step 3 on a uniform grid (eq:FGA) as tile GEMMs on the matrix cores.
+//
+// With the box window, each beam's term factorises over the axes:
+//   u_c(x_i, y_j, z_l) = sum_b W_bc Ex_b(i) Ey_b(j) Ez_b(l),
+//   E_d(i) = exp(i P_d (x_i - Q_d)/eps - (x_i - Q_d)^2/(2 eps)) on |x_i - Q_d| <= R, else 0,
+//   W_bc = w_b exp(i S_b/eps) A_bc.
+// For a 16^3 tile this is the complex product U[(j,i),(c,l)] =
+// sum_b (Ey (.) Ex)[(j,i),b] (W_c Ez)[b,(c,l)] -- a Khatri-Rao row block times
+// a factor block, M = 256, N = 48, K = beams near the tile.  It runs as a real
+// GEMM [Re X | Im X] [[Re V, Im V], [-Im V, Re V]] on v_mfma_f64_16x16x4_f64.
+//
+// Beams are binned by the tile-sized cell of Q (radix sort of cell keys); a
+// tile's candidates are the (2r+1)^2 contiguous runs of cells within reach of
+// it.  Each tile's candidate list is split into segments, one workgroup per
+// segment, whose partial tiles are then reduced in a fixed order.
+#include <hipcub/hipcub.hpp>
+
+#include "device_common.h"
+
+namespace fga {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int T = 16;       // tile edge (points)
+constexpr int NB = 16;      // beams per LDS batch
+constexpr int MAXR = 1024;  // max candidate runs per tile: (2 reach + 1)^2
+
+struct GridGeom {
+  int n[3], nt[3], nc[3], reach[3];
+  double lo[3], h[3];
+  double R, eps;
+};
+
+__device__ __forceinline__ double axis_coord(const GridGeom &g, int d, int i)
+{
+  return __dadd_rn(g.lo[d], __dmul_rn(g.h[d], (double)i));
+}
+
+// Number of grid indices i in [0, n) with |lo + i h - q| <= R.
+__device__ int64_t axis_count(const GridGeom &g, int d, double q)
+{
+  int lo_i = (int)ceil((q - g.R - g.lo[d]) / g.h[d]);
+  int hi_i = (int)floor((q + g.R - g.lo[d]) / g.h[d]);
+  lo_i = lo_i < 0 ? 0 : lo_i;
+  hi_i = hi_i > g.n[d] - 1 ? g.n[d] - 1 : hi_i;
+  while (lo_i > 0 && fabs(axis_coord(g, d, lo_i - 1) - q) <= g.R) --lo_i;
+  while (lo_i <= hi_i && fabs(axis_coord(g, d, lo_i) - q) > g.R) ++lo_i;
+  while (hi_i < g.n[d] - 1 && fabs(axis_coord(g, d, hi_i + 1) - q) <= g.R) ++hi_i;
+  while (hi_i >= lo_i && fabs(axis_coord(g, d, hi_i) - q) > g.R) --hi_i;
+  return hi_i >= lo_i ? (int64_t)(hi_i - lo_i + 1) : 0;
+}
+
+__global__ __launch_bounds__(256) void k_bin_keys(const double *__restrict__ F, const int32_t *__restrict__ I,
+                                                  int64_t cap, int64_t n, GridGeom g, int32_t *__restrict__ keys,
+                                                  int32_t *__restrict__ vals, unsigned long long *__restrict__ evals)
+{
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long ev = 0;
+  if (i < n) {
+    int32_t key = 0x7fffffff;
+    if (I[FGA_FLAGS * cap + i] & FGA_FLAG_ALIVE) {
+      bool in = true;
+      int c[3];
+      int64_t cnt = 1;
+      for (int d = 0; d < 3; ++d) {
+        const double q = F[(FGA_Q + d) * cap + i];
+        const double u = floor((q - g.lo[d]) / (T * g.h[d]));
+        in = in && u >= -(double)g.reach[d] && u < (double)(g.nt[d] + g.reach[d]);
+        c[d] = in ? (int)u + g.reach[d] : 0;
+        cnt *= axis_count(g, d, q);
+      }
+      if (in) key = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+      ev = (unsigned long long)cnt;
+    }
+    keys[i] = key;
+    vals[i] = (int32_t)i;
+  }
+  for (int off = 32; off > 0; off >>= 1) ev += __shfl_down(ev, off);
+  if ((threadIdx.x & 63) == 0 && ev && evals) atomicAdd(evals, ev);
+}
+
+// start[c] = first sorted position with key >= c, for c in [0, ncells].
+__global__ __launch_bounds__(256) void k_cell_start(const int32_t *__restrict__ keys, int64_t n, int32_t ncells,
+                                                    int64_t *__restrict__ start)
+{
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c > ncells) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  start[c] = lo;
+}
+
+// Candidate runs of tile t: for each (cz, cy) within reach, the cells
+// cx in [tx, tx + 2 reach] of the shifted cell grid.
+__device__ __forceinline__ void tile_run(const GridGeom &g, const int64_t *start, int tx, int ty, int tz, int r,
+                                         int64_t &b, int64_t &len)
+{
+  const int wy = 2 * g.reach[1] + 1;
+  const int cz = tz + r / wy, cy = ty + r % wy;
+  const int64_t row = ((int64_t)cz * g.nc[1] + cy) * g.nc[0];
+  b = start[row + tx];
+  len = start[row + tx + 2 * g.reach[0] + 1] - b;
+}
+
+__global__ __launch_bounds__(256) void k_tile_counts(GridGeom g, const int64_t *__restrict__ start,
+                                                     int64_t *__restrict__ counts)
+{
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int ntile = g.nt[0] * g.nt[1] * g.nt[2];
+  if (t >= ntile) return;
+  const int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
+  const int nr = (2 * g.reach[1] + 1) * (2 * g.reach[2] + 1);
+  int64_t s = 0;
+  for (int r = 0; r < nr; ++r) {
+    int64_t b, len;
+    tile_run(g, start, tx, ty, tz, r, b, len);
+    s += len;
+  }
+  counts[t] = s;
+}
+
+struct Item {
+  int32_t tile;
+  int32_t pad;
+  int64_t k0, k1;
+};
+
+__device__ __forceinline__ void cmul(double ar, double ai, double br, double bi, double &cr, double &ci)
+{
+  cr = ar * br - ai * bi;
+  ci = ar * bi + ai * br;
+}
+
+__global__ __launch_bounds__(256) void k_grid_tile_f64(GridGeom g, const int64_t *__restrict__ start,
+                                                       const int32_t *__restrict__ order, const Item *__restrict__ items,
+                                                       const double *__restrict__ F, const int32_t *__restrict__ I,
+                                                       int64_t cap, double *__restrict__ partial)
+{
+  __shared__ int64_t run_b[MAXR], run_pre[MAXR + 1];
+  __shared__ double2 Ex[NB][T], Ey[NB][T], Ez[NB][T], V[NB][3][T];
+  __shared__ double bQ[NB][3], bP[NB][3];
+  __shared__ double2 bW[NB][3];
+
+  const Item it = items[blockIdx.x];
+  const int t = it.tile;
+  const int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
+  const int nr = (2 * g.reach[1] + 1) * (2 * g.reach[2] + 1);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+
+  // prefix of run lengths (serial by one thread: nr <= MAXR)
+  if (tid == 0) {
+    int64_t s = 0;
+    for (int r = 0; r < nr; ++r) {
+      int64_t b, len;
+      tile_run(g, start, tx, ty, tz, r, b, len);
+      run_b[r] = b;
+      run_pre[r] = s;
+      s += len;
+    }
+    run_pre[nr] = s;
+  }
+  __syncthreads();
+
+  d4 acc[4][6];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const double ieps = 1.0 / g.eps, hieps = 0.5 / g.eps;
+  for (int64_t kb = it.k0; kb < it.k1; kb += NB) {
+    // 1. beam data of this batch
+    if (tid < NB) {
+      const int64_t k = kb + tid;
+      int64_t bi = -1;
+      if (k < it.k1) {
+        int lo = 0, hi = nr - 1;  // last run with run_pre <= k
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (run_pre[mid] <= k) lo = mid;
+          else hi = mid - 1;
+        }
+        bi = order[run_b[lo] + (k - run_pre[lo])];
+      }
+      if (bi >= 0) {
+        double P[3], e[3];
+        for (int d = 0; d < 3; ++d) {
+          bQ[tid][d] = F[(FGA_Q + d) * cap + bi];
+          P[d] = F[(FGA_P + d) * cap + bi];
+          bP[tid][d] = P[d];
+          e[d] = F[(FGA_E + d) * cap + bi];
+        }
+        const double a0r = F[FGA_A0_RE * cap + bi], a0i = F[FGA_A0_IM * cap + bi];
+        const double a1r = F[FGA_A1_RE * cap + bi], a1i = F[FGA_A1_IM * cap + bi];
+        double Ar[3], Ai[3];
+        if (I[FGA_BRANCH * cap + bi] == 0) {
+          const double ip = 1.0 / sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+          for (int c = 0; c < 3; ++c) { Ar[c] = a0r * P[c] * ip; Ai[c] = a0i * P[c] * ip; }
+        } else {
+          double nsh[3], nsv[3];
+          s_frame(P, e, nsh, nsv);
+          for (int c = 0; c < 3; ++c) {
+            Ar[c] = a0r * nsv[c] + a1r * nsh[c];
+            Ai[c] = a0i * nsv[c] + a1i * nsh[c];
+          }
+        }
+        double sn, cs;
+        sincos(F[FGA_S * cap + bi] * ieps, &sn, &cs);
+        double wr, wi;
+        cmul(F[FGA_W_RE * cap + bi], F[FGA_W_IM * cap + bi], cs, sn, wr, wi);
+        for (int c = 0; c < 3; ++c) {
+          double r_, i_;
+          cmul(wr, wi, Ar[c], Ai[c], r_, i_);
+          bW[tid][c] = make_double2(r_, i_);
+        }
+      } else {
+        for (int d = 0; d < 3; ++d) { bQ[tid][d] = 1.0e300; bP[tid][d] = 0.0; bW[tid][d] = make_double2(0.0, 0.0); }
+      }
+    }
+    __syncthreads();
+    // 2. one-dimensional factors, masked by the window
+    for (int e = tid; e < NB * 3 * T; e += 256) {
+      const int jb = e / (3 * T), d = (e / T) % 3, ii = e % T;
+      const int tt = d == 0 ? tx : (d == 1 ? ty : tz);
+      const double x = axis_coord(g, d, T * tt + ii);
+      const double u = x - bQ[jb][d];
+      double2 E = make_double2(0.0, 0.0);
+      if (fabs(u) <= g.R) {
+        double sn, cs;
+        sincos(bP[jb][d] * u * ieps, &sn, &cs);
+        const double m = exp(-u * u * hieps);
+        E = make_double2(m * cs, m * sn);
+      }
+      if (d == 0) Ex[jb][ii] = E;
+      else if (d == 1) Ey[jb][ii] = E;
+      else Ez[jb][ii] = E;
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * 3 * T; e += 256) {
+      const int jb = e / (3 * T), c = (e / T) % 3, l = e % T;
+      double r_, i_;
+      cmul(bW[jb][c].x, bW[jb][c].y, Ez[jb][l].x, Ez[jb][l].y, r_, i_);
+      V[jb][c][l] = make_double2(r_, i_);
+    }
+    __syncthreads();
+    // 3. K loop on the matrix cores: K step of 4 = 2 beams x (re, im)
+    const int li = lane & 15, kk = lane >> 4, part = kk & 1;
+#pragma unroll 2
+    for (int ks = 0; ks < NB / 2; ++ks) {
+      const int jb = 2 * ks + (kk >> 1);
+      const double2 xv = Ex[jb][li];
+      double a[4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const double2 yv = Ey[jb][4 * w + rb];
+        double xr, xi;
+        cmul(xv.x, xv.y, yv.x, yv.y, xr, xi);
+        a[rb] = part ? xi : xr;
+      }
+      double b[6];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double2 v = V[jb][c][li];
+        b[c] = part ? -v.y : v.x;      // columns of Re U
+        b[3 + c] = part ? v.x : v.y;   // columns of Im U
+      }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 6; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // 4. partial tile [c][l][j][i] complex.  Result register r of lane holds
+  // D[lane/16 + 4r][lane % 16] (row: x index i; column: z index l).
+  double *P = partial + (int64_t)blockIdx.x * (3 * T * T * T * 2);
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int j = 4 * w + rb;
+#pragma unroll
+    for (int cb = 0; cb < 6; ++cb) {
+      const int u = cb / 3, c = cb % 3;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = (lane >> 4) + 4 * r, l = lane & 15;
+        P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = acc[rb][cb][r];
+      }
+    }
+  }
+}
+
+// out[c][z][y][x] = sum of the tile's partials (fixed item order); points
+// outside the grid of a ragged tile are skipped.
+__global__ __launch_bounds__(256) void k_grid_reduce(GridGeom g, const int32_t *__restrict__ first,
+                                                     const int32_t *__restrict__ nitems,
+                                                     const double *__restrict__ partial, double *__restrict__ out)
+{
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t plane = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  if (id >= 3 * plane) return;
+  const int c = (int)(id / plane);
+  const int64_t p = id % plane;
+  const int x = (int)(p % g.n[0]), y = (int)((p / g.n[0]) % g.n[1]), z = (int)(p / ((int64_t)g.n[0] * g.n[1]));
+  const int t = ((z / T) * g.nt[1] + (y / T)) * g.nt[0] + (x / T);
+  const int i = x % T, j = y % T, l = z % T;
+  double re = 0.0, im = 0.0;
+  const int f = first[t];
+  for (int k = 0; k < nitems[t]; ++k) {
+    const double *P = partial + (int64_t)(f + k) * (3 * T * T * T * 2) + ((((int64_t)c * T + l) * T + j) * T + i) * 2;
+    re += P[0];
+    im += P[1];
+  }
+  out[2 * id] = re;
+  out[2 * id + 1] = im;
+}
+
+GridGeom make_geom(const int n[3], const double lo[3], const double h[3], double eps, double tau)
+{
+  GridGeom g{};
+  g.R = sqrt(2.0 * tau * eps);
+  g.eps = eps;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = n[d];
+    g.lo[d] = lo[d];
+    g.h[d] = h[d];
+    g.nt[d] = (n[d] + T - 1) / T;
+    g.reach[d] = (int)floor(g.R / (T * h[d])) + 1;
+    g.nc[d] = g.nt[d] + 2 * g.reach[d];
+  }
+  return g;
+}
+
+}  // namespace
+
+fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n[3], const double lo[3],
+                         const double h[3], int precision, double *out, Arena &ar, hipStream_t st, bool size_only,
+                         size_t *need, int64_t *evals_out)
+{
+  if (precision != FGA_FP64) return fail(FGA_EUNSUPPORTED, "grid summation precision %d not built yet", precision);
+  const GridGeom g = make_geom(n, lo, h, eps, tau);
+  if ((2 * g.reach[1] + 1) * (2 * g.reach[2] + 1) > MAXR)
+    return fail(FGA_EUNSUPPORTED, "window reach %d x %d tiles exceeds the supported %d runs per tile", g.reach[1],
+                g.reach[2], MAXR);
+  const int64_t nb = b->count;
+  const int ntile = g.nt[0] * g.nt[1] * g.nt[2];
+  const int64_t ncells = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+  if (ncells >= 0x7fffffff) return fail(FGA_EUNSUPPORTED, "too many cells");
+  const int max_items = 1024 + ntile;
+
+  int32_t *keys = ar.take<int32_t>(nb + 1), *keys2 = ar.take<int32_t>(nb + 1);
+  int32_t *vals = ar.take<int32_t>(nb + 1), *vals2 = ar.take<int32_t>(nb + 1);
+  int64_t *start = ar.take<int64_t>(ncells + 1);
+  int64_t *tcount = ar.take<int64_t>(ntile);
+  Item *items = ar.take<Item>(max_items);
+  int32_t *first = ar.take<int32_t>(ntile), *nitems = ar.take<int32_t>(ntile);
+  unsigned long long *ev = ar.take<unsigned long long>(1);
+  double *partial = ar.take<double>((size_t)max_items * 3 * T * T * T * 2);
+  size_t sort_bytes = 0;
+  int end_bit = 1;
+  while (end_bit < 31 && (1LL << end_bit) <= ncells) ++end_bit;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, keys, keys2, vals, vals2, (int)nb, 0, 31, st) !=
+      hipSuccess)
+    return fail(FGA_EDEVICE, "radix sort size query failed");
+  void *sort_tmp = ar.take<char>(sort_bytes);
+  if (size_only) {
+    *need = ar.used;
+    return FGA_OK;
+  }
+  if (!keys || !keys2 || !vals || !vals2 || !start || !tcount || !items || !first || !nitems || !ev || !partial ||
+      !sort_tmp)
+    return fail(FGA_ENOMEM, "grid summation workspace too small (%zu bytes given)", ar.size);
+  if (nb > 0x7fffffff) return fail(FGA_EUNSUPPORTED, "more than 2^31 beams in one grid summation");
+
+  FGA_HIP(hipMemsetAsync(ev, 0, sizeof(unsigned long long), st));
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_bin_keys, (unsigned)((nb + 255) / 256), 256, 0, st, b->f64, b->i32, b->capacity, nb, g,
+                       keys, vals, ev);
+    FGA_LAUNCH_CHECK();
+    FGA_HIP(hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, keys, keys2, vals, vals2, (int)nb, 0, 31, st));
+  }
+  hipLaunchKernelGGL(k_cell_start, (unsigned)((ncells + 1 + 255) / 256), 256, 0, st, keys2, nb, (int32_t)ncells,
+                     start);
+  FGA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_tile_counts, (unsigned)((ntile + 255) / 256), 256, 0, st, g, start, tcount);
+  FGA_LAUNCH_CHECK();
+  std::vector<int64_t> hc(ntile);
+  FGA_HIP(hipMemcpyAsync(hc.data(), tcount, ntile * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  unsigned long long hev = 0;
+  FGA_HIP(hipMemcpyAsync(&hev, ev, sizeof(hev), hipMemcpyDeviceToHost, st));
+  FGA_HIP(hipStreamSynchronize(st));
+  if (evals_out) *evals_out = (int64_t)hev;
+
+  int64_t total = 0;
+  for (int t = 0; t < ntile; ++t) total += hc[t];
+  int64_t seg = (total + 1023) / 1024;
+  if (seg < 64) seg = 64;
+  seg = (seg + NB - 1) / NB * NB;
+  std::vector<Item> hi;
+  std::vector<int32_t> hf(ntile), hn(ntile);
+  for (int t = 0; t < ntile; ++t) {
+    hf[t] = (int32_t)hi.size();
+    for (int64_t k = 0; k < hc[t]; k += seg) hi.push_back(Item{t, 0, k, k + seg < hc[t] ? k + seg : hc[t]});
+    hn[t] = (int32_t)hi.size() - hf[t];
+  }
+  if ((int)hi.size() > max_items) return fail(FGA_EDEVICE, "internal: %zu work items > %d", hi.size(), max_items);
+  if (!hi.empty()) {
+    FGA_HIP(hipMemcpyAsync(items, hi.data(), hi.size() * sizeof(Item), hipMemcpyHostToDevice, st));
+  }
+  FGA_HIP(hipMemcpyAsync(first, hf.data(), ntile * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  FGA_HIP(hipMemcpyAsync(nitems, hn.data(), ntile * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  if (!hi.empty()) {
+    ProfScope prof(FGA_K_GRID_TILE, st);
+    hipLaunchKernelGGL(k_grid_tile_f64, (unsigned)hi.size(), 256, 0, st, g, start, vals2, items, b->f64, b->i32,
+                       b->capacity, partial);
+    FGA_LAUNCH_CHECK();
+  }
+  const int64_t plane = (int64_t)n[0] * n[1] * n[2];
+  hipLaunchKernelGGL(k_grid_reduce, (unsigned)((3 * plane + 255) / 256), 256, 0, st, g, first, nitems, partial, out);
+  FGA_LAUNCH_CHECK();
+  // the host vectors above must outlive the copies that read them
+  FGA_HIP(hipStreamSynchronize(st));
+  return FGA_OK;
+}
+
+}  // namespace fga

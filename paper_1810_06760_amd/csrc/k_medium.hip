@@ -1,0 +1,45 @@
+// Grid media: per-node derived fields (c, grad c, Hessian) by second-order
+// periodic central differences, one 128-byte record per node so that a
+// trilinear gather touches one cache line per corner.
+#include "device_common.h"
+
+namespace fga {
+namespace {
+
+__global__ __launch_bounds__(256) void k_grid_build(const double *__restrict__ c, int nx, int ny, int nz,
+                                                    double hx, double hy, double hz, double *__restrict__ tab)
+{
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)nx * ny * nz;
+  if (id >= total) return;
+  const int i = (int)(id % nx), j = (int)((id / nx) % ny), k = (int)(id / ((int64_t)nx * ny));
+  auto at = [&](int a, int b, int d) -> double {
+    a = (a + nx) % nx; b = (b + ny) % ny; d = (d + nz) % nz;
+    return c[((int64_t)d * ny + b) * nx + a];
+  };
+  const double c0 = at(i, j, k);
+  double *o = tab + (int64_t)FGA_GRID_NODE_DOUBLES * id;
+  o[0] = c0;
+  o[1] = (at(i + 1, j, k) - at(i - 1, j, k)) / (2.0 * hx);
+  o[2] = (at(i, j + 1, k) - at(i, j - 1, k)) / (2.0 * hy);
+  o[3] = (at(i, j, k + 1) - at(i, j, k - 1)) / (2.0 * hz);
+  o[4] = (at(i + 1, j, k) - 2.0 * c0 + at(i - 1, j, k)) / (hx * hx);
+  o[5] = (at(i, j + 1, k) - 2.0 * c0 + at(i, j - 1, k)) / (hy * hy);
+  o[6] = (at(i, j, k + 1) - 2.0 * c0 + at(i, j, k - 1)) / (hz * hz);
+  o[7] = (at(i + 1, j + 1, k) - at(i + 1, j - 1, k) - at(i - 1, j + 1, k) + at(i - 1, j - 1, k)) / (4.0 * hx * hy);
+  o[8] = (at(i + 1, j, k + 1) - at(i + 1, j, k - 1) - at(i - 1, j, k + 1) + at(i - 1, j, k - 1)) / (4.0 * hx * hz);
+  o[9] = (at(i, j + 1, k + 1) - at(i, j + 1, k - 1) - at(i, j - 1, k + 1) + at(i, j - 1, k - 1)) / (4.0 * hy * hz);
+  for (int f = 10; f < FGA_GRID_NODE_DOUBLES; ++f) o[f] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_grid_build(const int n[3], const double h[3], const double *c, double *table, hipStream_t st)
+{
+  const int64_t total = (int64_t)n[0] * n[1] * n[2];
+  hipLaunchKernelGGL(k_grid_build, (unsigned)((total + 255) / 256), 256, 0, st, c, n[0], n[1], n[2], h[0], h[1],
+                     h[2], table);
+  return hipGetLastError();
+}
+
+}  // namespace fga

@@ -1,0 +1,244 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Bar (FP64 path): relative L2 <= 1e-10 for every floating-point output, exact
+equality for integer outputs (beam lineage sets, in-window term counts).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import fga_inputs as fi
+import oracle as om
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def fga():
+    import paper_1810_06760_amd as m
+    m.lib()
+    return m
+
+
+def rel_l2(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = np.linalg.norm(b.ravel())
+    return np.linalg.norm((a - b).ravel()) / (den if den > 0 else 1.0)
+
+
+def oracle_to_dict(ob):
+    return {"Q": ob["Q"], "P": ob["P"], "ZQ": ob["ZQ"], "ZP": ob["ZP"], "a": ob["a"], "S": ob["S"], "w": ob["w"],
+            "e": ob["e"], "branch": ob["branch"], "sigma": ob["sigma"], "layer": ob["layer"], "gen": ob["gen"],
+            "flags": ob["alive"], "lineage": ob["lineage"]}
+
+
+def phys_amp_gpu(d):
+    """physical amplitude vectors of exported GPU beams"""
+    n = len(d["Q"])
+    A = np.zeros((n, 3), dtype=np.complex128)
+    for i in range(n):
+        P = d["P"][i]
+        if d["branch"][i] == 0:
+            A[i] = d["a"][i, 0] * P / np.linalg.norm(P)
+        else:
+            e = d["e"][i]
+            nsh = np.cross(e, P); nsh /= np.linalg.norm(nsh)
+            nsv = np.cross(P / np.linalg.norm(P), nsh)
+            A[i] = d["a"][i, 0] * nsv + d["a"][i, 1] * nsh
+    return A
+
+
+def compare_states(g, ob, tol=RTOL):
+    assert np.array_equal(g["lineage"], ob["lineage"])
+    for k in ("Q", "P", "ZQ", "ZP", "S"):
+        err = rel_l2(g[k], ob[k]) if k != "S" else np.max(np.abs(g[k] - ob[k]))
+        assert err <= (tol if k != "S" else 1e-12), (k, err)
+    err = rel_l2(phys_amp_gpu(g), om.amplitude_vectors(ob))
+    assert err <= tol, ("A", err)
+
+
+def small_c1(nq=4, np_=2, ny=16):
+    return fi.homogeneous_packet(nq=nq, np_=np_, ny=ny, nout=0)
+
+
+def small_c2(nq=4, np_=2, ny=16, nmed=32):
+    return fi.smooth_medium_packet(nq=nq, np_=np_, ny=ny, nmed=nmed, nout=0, nrec=8)
+
+
+@pytest.mark.parametrize("case", ["homogeneous", "grid"])
+def test_evolve_parity(case):
+    m = fga()
+    w = small_c1() if case == "homogeneous" else small_c2()
+    say("evolve parity", case)
+    ob = om.decompose(w)
+    med_o = om.medium_for(w)
+    med_g = m.medium_for(w)
+    bs = m.BeamSet(len(ob) + 5)
+    bs.load(oracle_to_dict(ob))
+    nsteps, dt = (100, 0.005) if case == "homogeneous" else (150, 2e-3)
+    m.fga_evolve(med_g, bs, dt, nsteps, chunk=37)
+    om.evolve(med_o, ob, dt, nsteps)
+    compare_states(bs.export(), ob)
+
+
+def test_s_frame_switch_parity():
+    """S beams whose momentum swings through the frame axis switch frames
+    identically on both sides (bump-free check with a steep grid medium)."""
+    m = fga()
+    say("s frame switch")
+    n = 16
+    mesh = fi.node_grid(n)
+    ax = mesh.axis(0)
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    cp = 1.7 * (1.0 + 0.25 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Z))
+    med_o = om.grid(cp, mesh, cs_ratio=0.6)
+    med_g = m.Medium.grid(cp, mesh, cs_ratio=0.6)
+    g = np.random.default_rng(11)
+    nb = 64
+    ob = np.zeros(nb, dtype=om.BEAM_DTYPE)
+    ob["Q"] = g.random((nb, 3))
+    d = g.standard_normal((nb, 3))
+    d[:, 2] += 3.0
+    ob["P"] = d / np.linalg.norm(d, axis=1)[:, None] * 1.3
+    for i in range(3):
+        ob["ZQ"][:, i, i] = 1.0
+        ob["ZP"][:, i, i] = -1j
+    ob["a"][:, 0] = 2 ** 1.5
+    ob["a"][:, 1] = 0.3j
+    ob["w"] = 1.0
+    ob["e"][:, 0] = 1.0    # x axis, far from P (mostly along z)
+    ob["branch"] = 2
+    ob["sigma"] = np.where(np.arange(nb) % 2 == 0, 1, -1)
+    ob["alive"] = 1
+    ob["lineage"] = np.arange(nb)
+    om.reframe(ob)
+    bs = m.BeamSet(nb)
+    bs.load(oracle_to_dict(ob))
+    m.fga_evolve(med_g, bs, 4e-3, 200)
+    om.evolve(med_o, ob, 4e-3, 200)
+    gexp = bs.export()
+    assert np.array_equal(gexp["e"], ob["e"])
+    compare_states(gexp, ob)
+
+
+def test_decompose_parity():
+    """Step 1 on the full homogeneous packet mesh (8^3 q x 4^3 p x 3 branches)."""
+    m = fga()
+    say("decompose parity")
+    w = fi.homogeneous_packet(ny=32, nout=0)
+    ob = om.decompose(w)
+    bs = m.fga_decompose(m.medium_for(w), m.mesh_for(w), w.f)
+    g = bs.export()
+    assert bs.count == len(ob) == 3 * 8 ** 3 * 4 ** 3
+    assert np.array_equal(g["lineage"], ob["lineage"])
+    assert np.array_equal(g["branch"], ob["branch"])
+    assert rel_l2(g["w"], ob["w"]) <= RTOL
+    assert np.array_equal(g["Q"], ob["Q"]) and np.array_equal(g["P"], ob["P"])
+    assert np.array_equal(g["e"], ob["e"])
+    compare_states(g, ob)
+
+
+def test_decompose_cull_parity():
+    """Culling by |psi| makes the same beam set on both sides (beams within
+    1e-9 relative of the threshold are not counted either way)."""
+    m = fga()
+    say("decompose cull parity")
+    w = fi.homogeneous_packet(ny=32, nout=0)
+    ob_all = om.decompose(w)
+    psi_abs = np.abs(ob_all["w"])
+    thr = np.quantile(psi_abs, 0.6)
+    norm = w.qmesh.cell_volume * w.pmesh.cell_volume * (2 * math.pi * w.eps) ** -4.5
+    w.cull_abs = thr / norm
+    bs = m.fga_decompose(m.medium_for(w), m.mesh_for(w), w.f)
+    g = bs.export()
+    keep_o = set(ob_all["lineage"][psi_abs >= thr].tolist())
+    amb = set(ob_all["lineage"][np.abs(psi_abs - thr) <= 1e-9 * thr].tolist())
+    keep_g = set(g["lineage"].tolist())
+    assert keep_o - amb <= keep_g and keep_g - amb <= keep_o
+    assert np.all(np.diff(g["lineage"]) > 0)
+
+
+def evolved_beams(w, nsteps, dt):
+    ob = om.decompose(w)
+    om.evolve(om.medium_for(w), ob, dt, nsteps)
+    return ob
+
+
+def test_points_parity():
+    m = fga()
+    say("points parity")
+    w = small_c1(nq=5, np_=3, ny=16)
+    ob = evolved_beams(w, 40, 0.005)
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    x = fi.uniform_points(300, np.random.default_rng(2), -0.2, 1.2)
+    for tau in (25.0, 4.0):
+        uo, co = om.sum_points(ob, x, w.eps, tau)
+        ug, cg = m.fga_reconstruct_points(bs, w.eps, tau, x)
+        assert cg == co
+        assert rel_l2(m.to_complex(ug), uo) <= RTOL
+
+
+@pytest.mark.parametrize("n,tau", [(20, 25.0), (37, 6.0)])
+def test_grid_parity(n, tau):
+    """Step 3 on a grid with ragged tiles: the tile GEMMs on the matrix cores
+    against the oracle's direct windowed sum at every grid point."""
+    m = fga()
+    say("grid parity", n, tau)
+    w = small_c1(nq=5, np_=3, ny=16)
+    ob = evolved_beams(w, 30, 0.005)
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    grid = fi.cell_centred(n, -0.1, 1.1)
+    ug, cg = m.fga_reconstruct_grid(bs, w.eps, tau, grid)
+    uo, co = om.sum_points(ob, grid.points(), w.eps, tau)
+    assert cg == co
+    ug = m.to_complex(ug).reshape(3, -1).T
+    assert rel_l2(ug, uo) <= RTOL
+
+
+def test_seismogram_parity():
+    """Receivers sampled after every step during the evolution."""
+    m = fga()
+    say("seismogram parity")
+    w = small_c2(nq=4, np_=2, ny=16)
+    ob = om.decompose(w)
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    rec = w.receivers
+    nsteps, dt, tau = 24, 2e-3, 25.0
+    seis, st = m.fga_evolve(m.medium_for(w), bs, dt, nsteps, receivers=rec, eps=w.eps, tau=tau, stride=2, chunk=5,
+                            batch=97)
+    med_o = om.medium_for(w)
+    ref = np.zeros((len(rec), nsteps // 2, 3), dtype=np.complex128)
+    cnt = 0
+    for s in range(nsteps // 2):
+        om.evolve(med_o, ob, dt, 2)
+        u, c = om.sum_points(ob, rec, w.eps, tau)
+        ref[:, s, :] = u
+        cnt += c
+    assert st["evals"] == cnt
+    assert st["beam_steps"] == nsteps * len(ob)
+    assert rel_l2(m.to_complex(seis), ref) <= RTOL
+
+
+def test_empty_beam_set():
+    m = fga()
+    say("empty beams")
+    bs = m.BeamSet(4)
+    x = np.array([[0.5, 0.5, 0.5]])
+    u, c = m.fga_reconstruct_points(bs, 1 / 32, 25.0, x)
+    assert c == 0 and np.all(m.to_complex(u) == 0)
+    g, c = m.fga_reconstruct_grid(bs, 1 / 32, 25.0, fi.cell_centred(5, 0, 1))
+    assert c == 0 and np.all(m.to_complex(g) == 0)
+    seis, st = m.fga_evolve(m.Medium.homogeneous(1.7, 1.0), bs, 0.01, 3, receivers=x, eps=1 / 32)
+    assert np.all(m.to_complex(seis) == 0) and st["beam_steps"] == 0
