@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "device_common.h"
@@ -120,6 +121,50 @@ fga_status make_dev_medium(const fga_medium *m, DevMedium *o)
   default:
     return fail(FGA_EINVAL, "unknown medium kind %d", m->kind);
   }
+}
+
+fga_status sort_points(const double *xyz, int64_t n, double *xyz_sorted, int32_t *perm, hipStream_t st)
+{
+  std::vector<double> h((size_t)3 * n);
+  FGA_HIP(hipMemcpyAsync(h.data(), xyz, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  FGA_HIP(hipStreamSynchronize(st));
+  double lo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, hi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) {
+      const double v = h[3 * i + d];
+      if (!std::isfinite(v)) return fail(FGA_EINVAL, "point %lld is not finite", (long long)i);
+      lo[d] = v < lo[d] ? v : lo[d];
+      hi[d] = v > hi[d] ? v : hi[d];
+    }
+  // 10-bit Morton key of each point within the points' bounding box
+  std::vector<std::pair<uint32_t, int32_t>> key((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t k = 0;
+    uint32_t c[3];
+    for (int d = 0; d < 3; ++d) {
+      const double span = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0;
+      double u = (h[3 * i + d] - lo[d]) / span * 1023.0;
+      c[d] = (uint32_t)(u < 0 ? 0 : (u > 1023 ? 1023 : u));
+    }
+    for (int b = 9; b >= 0; --b)
+      for (int d = 2; d >= 0; --d) k = (k << 1) | ((c[d] >> b) & 1u);
+    key[(size_t)i] = {k, (int32_t)i};
+  }
+  std::stable_sort(key.begin(), key.end(),
+                   [](const std::pair<uint32_t, int32_t> &a, const std::pair<uint32_t, int32_t> &b) {
+                     return a.first < b.first;
+                   });
+  std::vector<double> hs((size_t)3 * n);
+  std::vector<int32_t> hp((size_t)n);
+  for (int64_t k = 0; k < n; ++k) {
+    const int32_t i = key[(size_t)k].second;
+    hp[(size_t)k] = i;
+    for (int d = 0; d < 3; ++d) hs[3 * k + d] = h[3 * (size_t)i + d];
+  }
+  FGA_HIP(hipMemcpyAsync(xyz_sorted, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  FGA_HIP(hipMemcpyAsync(perm, hp.data(), hp.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  FGA_HIP(hipStreamSynchronize(st));
+  return FGA_OK;
 }
 
 static fga_status check_beams(const fga_beams *b)
@@ -265,19 +310,25 @@ EvolvePlan evolve_plan(const fga_beams *b, int nsteps, const fga_evolve_opts *o,
   return p;
 }
 
-fga_status evolve_layout(const fga_beams *b, const EvolvePlan &p, const fga_receivers *r, Arena &ar,
-                         unsigned long long **ctr, double **emit, double **partial)
+struct EvolveBufs {
+  unsigned long long *ctr = nullptr;
+  double *emit = nullptr, *partial = nullptr, *xs = nullptr;
+  int32_t *perm = nullptr;
+};
+
+EvolveBufs evolve_layout(const EvolvePlan &p, const fga_receivers *r, Arena &ar)
 {
-  *ctr = ar.take<unsigned long long>(4);
-  *emit = nullptr;
-  *partial = nullptr;
+  EvolveBufs b;
+  b.ctr = ar.take<unsigned long long>(4);
   if (r) {
     const int m = (p.chunk + r->stride - 1) / r->stride + 1;
-    *emit = ar.take<double>((size_t)m * 12 * p.batch);
+    b.emit = ar.take<double>((size_t)m * 12 * p.batch);
     const int64_t nblk = (p.batch + p.bpb - 1) / p.bpb;
-    *partial = ar.take<double>((size_t)nblk * m * r->n * 6);
+    b.partial = ar.take<double>((size_t)nblk * m * r->n * 6);
+    b.xs = ar.take<double>((size_t)3 * r->n + 1);
+    b.perm = ar.take<int32_t>((size_t)r->n + 1);
   }
-  return FGA_OK;
+  return b;
 }
 
 }  // namespace
@@ -289,9 +340,7 @@ size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_
   if (rec && rec->stride < 1) return 0;
   const EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
   Arena ar(nullptr, 0);
-  unsigned long long *c;
-  double *e, *pa;
-  evolve_layout(beams, p, rec, ar, &c, &e, &pa);
+  evolve_layout(p, rec, ar);
   size_t need = ar.used;
   if (opts && opts->compact) {
     Arena a2(nullptr, 0);
@@ -323,12 +372,13 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
   hipStream_t st = (hipStream_t)stream;
   const EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
   Arena ar(workspace, workspace_bytes);
-  unsigned long long *ctr;
-  double *emit, *partial;
-  evolve_layout(beams, p, rec, ar, &ctr, &emit, &partial);
-  if (!ctr || (rec && (!emit || !partial)))
+  const EvolveBufs wb = evolve_layout(p, rec, ar);
+  unsigned long long *ctr = wb.ctr;
+  double *emit = wb.emit, *partial = wb.partial;
+  if (!ctr || (rec && (!emit || !partial || !wb.xs || !wb.perm)))
     return fail(FGA_ENOMEM, "evolve workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
   FGA_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), st));
+  if (rec && rec->n > 0 && (s = sort_points(rec->xyz, rec->n, wb.xs, wb.perm, st)) != FGA_OK) return s;
 
   const double cutoff = opts ? opts->cutoff_abs : 0.0;
   const int64_t n = beams->count;
@@ -362,7 +412,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
         pa.emit = emit;
         pa.nb = b1 - b0;
         pa.m = ns;
-        pa.xyz = rec->xyz;
+        pa.xyz = wb.xs;
         pa.n = rec->n;
         pa.eps = rec->eps;
         pa.tau = rec->tau;
@@ -371,11 +421,12 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
         pa.evals = ctr + 3;
         int nblk = 0;
         FGA_HIP(launch_sum_points(pa, &nblk, st));
-        FGA_HIP(launch_reduce_points(partial, nblk, ns, rec->n, seis, p.nsamp, sfirst, b0 > 0 ? 1 : 0, st));
+        FGA_HIP(launch_reduce_points(partial, nblk, ns, rec->n, wb.perm, seis, p.nsamp, sfirst, b0 > 0 ? 1 : 0,
+                                     st));
       }
     }
     if (n == 0 && rec && ns > 0 && rec->n > 0)
-      FGA_HIP(launch_reduce_points(partial, 0, ns, rec->n, seis, p.nsamp, sfirst, 0, st));
+      FGA_HIP(launch_reduce_points(partial, 0, ns, rec->n, wb.perm, seis, p.nsamp, sfirst, 0, st));
   }
   if (opts && opts->compact && cutoff > 0 && nsteps > 0) {
     Arena a2(workspace, workspace_bytes);
@@ -406,6 +457,8 @@ size_t fga_reconstruct_points_workspace_bytes(const fga_beams *beams, int64_t n)
   ar.take<unsigned long long>(1);
   ar.take<double>((size_t)12 * batch);
   ar.take<double>((size_t)((batch + 4095) / 4096) * n * 6);
+  ar.take<double>((size_t)3 * n + 1);
+  ar.take<int32_t>((size_t)n + 1);
   return ar.used;
 }
 
@@ -425,10 +478,14 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
   unsigned long long *ctr = ar.take<unsigned long long>(1);
   double *emit = ar.take<double>((size_t)12 * batch);
   double *partial = ar.take<double>((size_t)((batch + 4095) / 4096) * n * 6);
-  if (!ctr || !emit || !partial)
+  double *xs = ar.take<double>((size_t)3 * n + 1);
+  int32_t *perm = ar.take<int32_t>((size_t)n + 1);
+  if (!ctr || !emit || !partial || !xs || !perm)
     return fail(FGA_ENOMEM, "reconstruct workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
+  if (n > 0x7fffffff) return fail(FGA_EUNSUPPORTED, "more than 2^31 points");
   FGA_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long), st));
-  if (nb == 0) FGA_HIP(launch_reduce_points(partial, 0, 1, n, out, 1, 0, 0, st));
+  if (n > 0 && (s = sort_points(xyz, n, xs, perm, st)) != FGA_OK) return s;
+  if (nb == 0) FGA_HIP(launch_reduce_points(partial, 0, 1, n, nullptr, out, 1, 0, 0, st));
   for (int64_t b0 = 0; b0 < nb; b0 += batch) {
     const int64_t b1 = b0 + batch < nb ? b0 + batch : nb;
     FGA_HIP(launch_emit(beams->f64, beams->i32, beams->capacity, b0, b1, eps, emit, st));
@@ -436,7 +493,7 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
     pa.emit = emit;
     pa.nb = b1 - b0;
     pa.m = 1;
-    pa.xyz = xyz;
+    pa.xyz = xs;
     pa.n = n;
     pa.eps = eps;
     pa.tau = tau;
@@ -445,7 +502,7 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
     pa.evals = ctr;
     int nblk = 0;
     FGA_HIP(launch_sum_points(pa, &nblk, st));
-    FGA_HIP(launch_reduce_points(partial, nblk, 1, n, out, 1, 0, b0 > 0 ? 1 : 0, st));
+    FGA_HIP(launch_reduce_points(partial, nblk, 1, n, perm, out, 1, 0, b0 > 0 ? 1 : 0, st));
   }
   if (evals) {
     unsigned long long h = 0;

@@ -111,9 +111,12 @@ struct PointsArgs {
   unsigned long long *evals;
 };
 hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st);
-// seis[r][s0 + s][c] (+)= sum_blk partial[blk][s][r][c]
-hipError_t launch_reduce_points(const double *partial, int nblk, int m, int64_t n, double *out,
-                                int64_t out_samples, int s0, int accumulate, hipStream_t st);
+// seis[perm[r]][s0 + s][c] (+)= sum_blk partial[blk][s][r][c]   (perm NULL: identity)
+hipError_t launch_reduce_points(const double *partial, int nblk, int m, int64_t n, const int32_t *perm,
+                                double *out, int64_t out_samples, int s0, int accumulate, hipStream_t st);
+// Copies n points (device [n][3]) into xyz_sorted in Morton order of their
+// positions and sets perm[k] = original index of sorted point k.  Synchronises st.
+fga_status sort_points(const double *xyz, int64_t n, double *xyz_sorted, int32_t *perm, hipStream_t st);
 
 // beams -> emission records (current state, one sample)
 hipError_t launch_emit(const double *f64, const int32_t *i32, int64_t cap, int64_t beg, int64_t end,

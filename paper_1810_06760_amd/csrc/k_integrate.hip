@@ -175,7 +175,10 @@ __device__ __forceinline__ void emit_record(double *__restrict__ out, int64_t nb
   sincos(y[IS] * ieps, &sn, &cs);
   const double Wr = wr * cs - wi * sn, Wi = wr * sn + wi * cs;
 #pragma unroll
-  for (int f = 0; f < 6; ++f) out[f * nb + j] = y[f];
+  for (int f = 0; f < 3; ++f) {
+    out[f * nb + j] = y[IQ + f];
+    out[(3 + f) * nb + j] = y[IP + f] * ieps;  // P/eps: the phase is (P/eps).(x - Q)
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     out[(6 + 2 * c) * nb + j] = Wr * A[2 * c] - Wi * A[2 * c + 1];
@@ -185,8 +188,9 @@ __device__ __forceinline__ void emit_record(double *__restrict__ out, int64_t nb
 
 __device__ __forceinline__ void emit_dead(double *__restrict__ out, int64_t nb, int64_t j)
 {
+  // dead beams sit at -1e300 (idle point lanes use +1e300), never in any window
 #pragma unroll
-  for (int f = 0; f < 3; ++f) out[f * nb + j] = 1.0e300;
+  for (int f = 0; f < 3; ++f) out[f * nb + j] = -1.0e300;
 #pragma unroll
   for (int f = 3; f < 12; ++f) out[f * nb + j] = 0.0;
 }

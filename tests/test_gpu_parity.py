@@ -188,6 +188,25 @@ def test_points_parity():
         assert rel_l2(m.to_complex(ug), uo) <= RTOL
 
 
+@pytest.mark.parametrize("npts", [1, 17, 65])
+def test_points_ragged_and_dead(npts):
+    """Ragged point groups, a ragged last beam tile and dead beams: the
+    in-window count is exact and idle lanes never add a term."""
+    m = fga()
+    say("points ragged", npts)
+    w = small_c1(nq=5, np_=3, ny=16)
+    ob = evolved_beams(w, 10, 0.005)
+    ob = ob[:4096 + 64 * 3 + 7].copy()
+    ob["alive"][::7] = 0
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    x = fi.uniform_points(npts, np.random.default_rng(npts), 0.0, 1.0)
+    uo, co = om.sum_points(ob, x, w.eps, 25.0)
+    ug, cg = m.fga_reconstruct_points(bs, w.eps, 25.0, x)
+    assert cg == co
+    assert rel_l2(m.to_complex(ug), uo) <= RTOL
+
+
 @pytest.mark.parametrize("n,tau", [(20, 25.0), (37, 6.0)])
 def test_grid_parity(n, tau):
     """Step 3 on a grid with ragged tiles: the tile GEMMs on the matrix cores
