@@ -200,6 +200,8 @@ typedef struct {
   double cutoff_abs;       /* drop beams with |w| max(|a0|,|a1|) < cutoff_abs (0: off)  */
   int compact;             /* 1: compact the beam set after culling (stable order)     */
   int64_t batch;           /* beams per receiver batch (0: library default)            */
+  int resort;              /* steps between spatial re-orderings of the beam set
+                              (0: library default 64; < 0: never reorder)              */
 } fga_evolve_opts;
 
 typedef struct {
@@ -213,6 +215,11 @@ size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_
                                   const fga_receivers *rec);
 
 /* Advances every live beam by nsteps classic RK4 steps of size dt, in place.
+ * Unless opts->resort < 0, the beam set is first put in Morton order of the
+ * beam centres Q, and again every `resort` steps: beams that share medium
+ * cells then run in the same wavefronts.  Each reordering drops dead beams
+ * (count shrinks); beams keep their lineage numbers, so results are matched
+ * by lineage, not by slot.
  * After each step an S beam whose P has come within 10 degrees of its frame
  * axis switches axis (e_z <-> e_x) and re-expresses (a_SV, a_SH) so that the
  * physical polarisation is unchanged.  If rec != NULL, after every

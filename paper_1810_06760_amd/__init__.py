@@ -76,7 +76,8 @@ class ReceiversC(C.Structure):
 
 
 class EvolveOptsC(C.Structure):
-    _fields_ = [("chunk", C.c_int), ("cutoff_abs", C.c_double), ("compact", C.c_int), ("batch", C.c_int64)]
+    _fields_ = [("chunk", C.c_int), ("cutoff_abs", C.c_double), ("compact", C.c_int), ("batch", C.c_int64),
+                ("resort", C.c_int)]
 
 
 class EvolveStatsC(C.Structure):
@@ -337,12 +338,13 @@ def fga_decompose(medium: Medium, mesh: MeshC, f, g=None, beams: BeamSet = None,
 
 def fga_evolve(medium: Medium, beams: BeamSet, dt: float, nsteps: int, receivers=None, eps: float = None,
                tau: float = 25.0, stride: int = 1, chunk: int = 0, cutoff_abs: float = 0.0, compact: bool = False,
-               batch: int = 0, precision: int = FGA_FP64, seis=None, ws=None):
+               batch: int = 0, precision: int = FGA_FP64, seis=None, ws=None, resort: int = 0):
     """Step 2.  Returns (seis or None, stats dict).  receivers: (n,3) array;
-    seis is complex [n][nsteps/stride][3] as a float64 tensor [n, ns, 3, 2]."""
+    seis is complex [n][nsteps/stride][3] as a float64 tensor [n, ns, 3, 2].
+    resort: steps between spatial reorderings (0 default, < 0 never)."""
     torch = _torch()
     L = lib()
-    opts = EvolveOptsC(chunk, cutoff_abs, 1 if compact else 0, batch)
+    opts = EvolveOptsC(chunk, cutoff_abs, 1 if compact else 0, batch, resort)
     rec = None
     xyz = None
     if receivers is not None:
@@ -402,7 +404,7 @@ def workspace_bytes(kind: str, **kw) -> int:
         return L.fga_decompose_workspace_bytes(C.byref(kw["mesh"]), 1 if kw.get("with_g") else 0)
     if kind == "evolve":
         opts = EvolveOptsC(kw.get("chunk", 0), kw.get("cutoff_abs", 0.0), 1 if kw.get("compact") else 0,
-                           kw.get("batch", 0))
+                           kw.get("batch", 0), kw.get("resort", 0))
         rec = None
         if kw.get("n_receivers"):
             rec = ReceiversC(kw["n_receivers"], 0, kw.get("stride", 1), kw["eps"], kw.get("tau", 25.0),

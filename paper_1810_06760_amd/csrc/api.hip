@@ -296,6 +296,7 @@ struct EvolvePlan {
   int64_t batch;
   int nsamp;        // total samples
   int bpb;          // beams per receiver workgroup
+  int resort;       // steps between spatial reorderings (0: never)
 };
 
 EvolvePlan evolve_plan(const fga_beams *b, int nsteps, const fga_evolve_opts *o, const fga_receivers *r)
@@ -306,7 +307,9 @@ EvolvePlan evolve_plan(const fga_beams *b, int nsteps, const fga_evolve_opts *o,
   p.batch = (o && o->batch > 0) ? o->batch : ((int64_t)1 << 22);
   if (p.batch > b->count) p.batch = b->count > 0 ? b->count : 1;
   p.nsamp = r ? nsteps / r->stride : 0;
-  p.bpb = 4096;
+  p.bpb = kPointsBeamsPerBlock;
+  p.resort = (o && o->resort < 0) ? 0 : ((o && o->resort > 0) ? o->resort : 64);
+  if (p.resort > 0 && p.resort < p.chunk) p.resort = p.chunk;
   return p;
 }
 
@@ -341,6 +344,11 @@ size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_
   const EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
   Arena ar(nullptr, 0);
   evolve_layout(p, rec, ar);
+  if (p.resort > 0) {
+    size_t ns = 0;
+    fga_beams bb = *beams;
+    sort_beams_spatial(&bb, ar, nullptr, true, &ns);
+  }
   size_t need = ar.used;
   if (opts && opts->compact) {
     Arena a2(nullptr, 0);
@@ -377,12 +385,20 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
   double *emit = wb.emit, *partial = wb.partial;
   if (!ctr || (rec && (!emit || !partial || !wb.xs || !wb.perm)))
     return fail(FGA_ENOMEM, "evolve workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
+  const size_t sort_base = ar.used;
   FGA_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), st));
   if (rec && rec->n > 0 && (s = sort_points(rec->xyz, rec->n, wb.xs, wb.perm, st)) != FGA_OK) return s;
 
   const double cutoff = opts ? opts->cutoff_abs : 0.0;
-  const int64_t n = beams->count;
+  int last_sort = -1;
   for (int s0 = 0; s0 < nsteps; s0 += p.chunk) {
+    if (p.resort > 0 && (last_sort < 0 || s0 - last_sort >= p.resort)) {
+      Arena sa(static_cast<char *>(workspace) + sort_base, workspace_bytes - sort_base);
+      size_t need = 0;
+      if ((s = sort_beams_spatial(beams, sa, st, false, &need)) != FGA_OK) return s;
+      last_sort = s0;
+    }
+    const int64_t n = beams->count;
     const int m = s0 + p.chunk <= nsteps ? p.chunk : nsteps - s0;
     const bool last = s0 + m >= nsteps;
     int ns = 0, sfirst = 0;
@@ -456,7 +472,7 @@ size_t fga_reconstruct_points_workspace_bytes(const fga_beams *beams, int64_t n)
   Arena ar(nullptr, 0);
   ar.take<unsigned long long>(1);
   ar.take<double>((size_t)12 * batch);
-  ar.take<double>((size_t)((batch + 4095) / 4096) * n * 6);
+  ar.take<double>((size_t)((batch + kPointsBeamsPerBlock - 1) / kPointsBeamsPerBlock) * n * 6);
   ar.take<double>((size_t)3 * n + 1);
   ar.take<int32_t>((size_t)n + 1);
   return ar.used;
@@ -477,7 +493,7 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
   Arena ar(workspace, workspace_bytes);
   unsigned long long *ctr = ar.take<unsigned long long>(1);
   double *emit = ar.take<double>((size_t)12 * batch);
-  double *partial = ar.take<double>((size_t)((batch + 4095) / 4096) * n * 6);
+  double *partial = ar.take<double>((size_t)((batch + kPointsBeamsPerBlock - 1) / kPointsBeamsPerBlock) * n * 6);
   double *xs = ar.take<double>((size_t)3 * n + 1);
   int32_t *perm = ar.take<int32_t>((size_t)n + 1);
   if (!ctr || !emit || !partial || !xs || !perm)
@@ -498,7 +514,7 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
     pa.eps = eps;
     pa.tau = tau;
     pa.partial = partial;
-    pa.beams_per_block = 4096;
+    pa.beams_per_block = kPointsBeamsPerBlock;
     pa.evals = ctr;
     int nblk = 0;
     FGA_HIP(launch_sum_points(pa, &nblk, st));

@@ -111,6 +111,7 @@ struct PointsArgs {
   unsigned long long *evals;
 };
 hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st);
+constexpr int kPointsBeamsPerBlock = 8192;  // beams walked by one point-sum workgroup
 // seis[perm[r]][s0 + s][c] (+)= sum_blk partial[blk][s][r][c]   (perm NULL: identity)
 hipError_t launch_reduce_points(const double *partial, int nblk, int m, int64_t n, const int32_t *perm,
                                 double *out, int64_t out_samples, int s0, int accumulate, hipStream_t st);
@@ -137,6 +138,9 @@ fga_status decompose_impl(const DevMedium &dm, const fga_mesh *mesh, const doubl
 
 // exclusive scan of n int64 values (one workgroup); total = sum
 hipError_t launch_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st);
+
+// Morton-order the beam set by Q (dead beams dropped; count updated; synchronises st)
+fga_status sort_beams_spatial(fga_beams *b, Arena &ar, hipStream_t st, bool size_only, size_t *need);
 
 // stable compaction of the beam set by FLAGS & ALIVE
 fga_status compact_beams(fga_beams *b, Arena &ar, hipStream_t st, bool size_only, size_t *need);

@@ -16,6 +16,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "device_common.h"
+#include "fastmath.h"
 
 namespace fga {
 namespace {
@@ -136,33 +137,145 @@ __device__ __forceinline__ void cmul(double ar, double ai, double br, double bi,
   ci = ar * bi + ai * br;
 }
 
-__global__ __launch_bounds__(256) void k_grid_tile_f64(GridGeom g, const int64_t *__restrict__ start,
-                                                       const int32_t *__restrict__ order, const Item *__restrict__ items,
-                                                       const double *__restrict__ F, const int32_t *__restrict__ I,
-                                                       int64_t cap, double *__restrict__ partial)
+// Compact per-beam record in cell order: Q (3), P/eps (3), W = w e^{iS/eps} A (3 complex).
+__global__ __launch_bounds__(256) void k_grid_records(const double *__restrict__ F, const int32_t *__restrict__ I,
+                                                      int64_t cap, const int32_t *__restrict__ keys,
+                                                      const int32_t *__restrict__ order, int64_t n, double ieps,
+                                                      double *__restrict__ rec)
 {
-  __shared__ int64_t run_b[MAXR], run_pre[MAXR + 1];
-  __shared__ double2 Ex[NB][T], Ey[NB][T], Ez[NB][T], V[NB][3][T];
-  __shared__ double bQ[NB][3], bP[NB][3];
-  __shared__ double2 bW[NB][3];
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n || keys[s] == 0x7fffffff) return;
+  const int64_t bi = order[s];
+  double P[3], e[3];
+  double *o = rec + s * 12;
+  for (int d = 0; d < 3; ++d) {
+    o[d] = F[(FGA_Q + d) * cap + bi];
+    P[d] = F[(FGA_P + d) * cap + bi];
+    o[3 + d] = P[d] * ieps;
+    e[d] = F[(FGA_E + d) * cap + bi];
+  }
+  const double a0r = F[FGA_A0_RE * cap + bi], a0i = F[FGA_A0_IM * cap + bi];
+  const double a1r = F[FGA_A1_RE * cap + bi], a1i = F[FGA_A1_IM * cap + bi];
+  double Ar[3], Ai[3];
+  if (I[FGA_BRANCH * cap + bi] == 0) {
+    const double ip = 1.0 / sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+    for (int c = 0; c < 3; ++c) { Ar[c] = a0r * P[c] * ip; Ai[c] = a0i * P[c] * ip; }
+  } else {
+    double nsh[3], nsv[3];
+    s_frame(P, e, nsh, nsv);
+    for (int c = 0; c < 3; ++c) {
+      Ar[c] = a0r * nsv[c] + a1r * nsh[c];
+      Ai[c] = a0i * nsv[c] + a1i * nsh[c];
+    }
+  }
+  double sn, cs;
+  sincos(F[FGA_S * cap + bi] * ieps, &sn, &cs);
+  double wr, wi;
+  cmul(F[FGA_W_RE * cap + bi], F[FGA_W_IM * cap + bi], cs, sn, wr, wi);
+  for (int c = 0; c < 3; ++c) cmul(wr, wi, Ar[c], Ai[c], o[6 + 2 * c], o[7 + 2 * c]);
+}
 
+struct TileSmem {
+  int64_t run_b[MAXR], run_pre[MAXR + 1];
+  int32_t list[256 + NB];
+  int listn;
+  double brec[NB][12];
+  double2 Ex[NB][T], Ey[NB][T], Ez[NB][T], V[NB][3][T];
+  TrigTables tab;
+};
+
+// One batch of `cnt` (<= NB) accepted beams, listed by sorted position in
+// sm.list[0..cnt): build the window-masked 1-D factors and W Ez, then the
+// K = 2 cnt (re, im) slice of the tile GEMM on the matrix cores.
+__device__ __forceinline__ void grid_batch(const GridGeom &g, const double *__restrict__ rec, TileSmem &sm, int cnt,
+                                           const int tc[3], d4 acc[4][6])
+{
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const double hieps = 0.5 / g.eps;
+  for (int e = tid; e < NB * 12; e += 256) {
+    const int jb = e / 12, f = e % 12;
+    sm.brec[jb][f] = jb < cnt ? rec[(int64_t)sm.list[jb] * 12 + f] : (f < 3 ? -1.0e300 : 0.0);
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * 3 * T; e += 256) {
+    const int jb = e / (3 * T), d = (e / T) % 3, ii = e % T;
+    const double x = axis_coord(g, d, T * tc[d] + ii);
+    const double u = x - sm.brec[jb][d];
+    double2 E = make_double2(0.0, 0.0);
+    if (fabs(u) <= g.R) cexp_neg(sm.tab, u * u * hieps, sm.brec[jb][3 + d] * u, E.x, E.y);
+    if (d == 0) sm.Ex[jb][ii] = E;
+    else if (d == 1) sm.Ey[jb][ii] = E;
+    else sm.Ez[jb][ii] = E;
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * 3 * T; e += 256) {
+    const int jb = e / (3 * T), c = (e / T) % 3, l = e % T;
+    double r_, i_;
+    cmul(sm.brec[jb][6 + 2 * c], sm.brec[jb][7 + 2 * c], sm.Ez[jb][l].x, sm.Ez[jb][l].y, r_, i_);
+    sm.V[jb][c][l] = make_double2(r_, i_);
+  }
+  __syncthreads();
+  const int li = lane & 15, kk = lane >> 4, part = kk & 1;
+  const int nks = (cnt + 1) / 2;
+#pragma unroll 2
+  for (int ks = 0; ks < nks; ++ks) {
+    const int jb = 2 * ks + (kk >> 1);
+    const double2 xv = sm.Ex[jb][li];
+    double a[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const double2 yv = sm.Ey[jb][4 * w + rb];
+      double xr, xi;
+      cmul(xv.x, xv.y, yv.x, yv.y, xr, xi);
+      a[rb] = part ? xi : xr;
+    }
+    double b[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double2 v = sm.V[jb][c][li];
+      b[c] = part ? -v.y : v.x;     // columns of Re U
+      b[3 + c] = part ? v.x : v.y;  // columns of Im U
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_grid_tile_f64(GridGeom g, const int64_t *__restrict__ start,
+                                                       const Item *__restrict__ items, const double *__restrict__ rec,
+                                                       double *__restrict__ partial,
+                                                       unsigned long long *__restrict__ executed)
+{
+  __shared__ TileSmem sm;
+  fill_tables(sm.tab);
   const Item it = items[blockIdx.x];
   const int t = it.tile;
-  const int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
+  const int tc[3] = {t % g.nt[0], (t / g.nt[0]) % g.nt[1], t / (g.nt[0] * g.nt[1])};
   const int nr = (2 * g.reach[1] + 1) * (2 * g.reach[2] + 1);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-
-  // prefix of run lengths (serial by one thread: nr <= MAXR)
+  // point box of the tile (ragged tiles end at the grid edge)
+  double plo[3], phi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int i1 = T * tc[d] + T - 1 < g.n[d] - 1 ? T * tc[d] + T - 1 : g.n[d] - 1;
+    plo[d] = axis_coord(g, d, T * tc[d]);
+    phi[d] = axis_coord(g, d, i1);
+  }
   if (tid == 0) {
     int64_t s = 0;
     for (int r = 0; r < nr; ++r) {
       int64_t b, len;
-      tile_run(g, start, tx, ty, tz, r, b, len);
-      run_b[r] = b;
-      run_pre[r] = s;
+      tile_run(g, start, tc[0], tc[1], tc[2], r, b, len);
+      sm.run_b[r] = b;
+      sm.run_pre[r] = s;
       s += len;
     }
-    run_pre[nr] = s;
+    sm.run_pre[nr] = s;
+    sm.listn = 0;
   }
   __syncthreads();
 
@@ -172,112 +285,50 @@ __global__ __launch_bounds__(256) void k_grid_tile_f64(GridGeom g, const int64_t
 #pragma unroll
     for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const double ieps = 1.0 / g.eps, hieps = 0.5 / g.eps;
-  for (int64_t kb = it.k0; kb < it.k1; kb += NB) {
-    // 1. beam data of this batch
-    if (tid < NB) {
-      const int64_t k = kb + tid;
-      int64_t bi = -1;
-      if (k < it.k1) {
-        int lo = 0, hi = nr - 1;  // last run with run_pre <= k
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (run_pre[mid] <= k) lo = mid;
-          else hi = mid - 1;
-        }
-        bi = order[run_b[lo] + (k - run_pre[lo])];
+  unsigned long long nexec = 0;
+  for (int64_t c0 = it.k0; c0 < it.k1; c0 += 256) {
+    // candidates -> beams whose window box meets the tile's point box
+    const int64_t k = c0 + tid;
+    bool ok = false;
+    int32_t s = -1;
+    if (k < it.k1) {
+      int lo = 0, hi = nr - 1;  // last run with run_pre <= k
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sm.run_pre[mid] <= k) lo = mid;
+        else hi = mid - 1;
       }
-      if (bi >= 0) {
-        double P[3], e[3];
-        for (int d = 0; d < 3; ++d) {
-          bQ[tid][d] = F[(FGA_Q + d) * cap + bi];
-          P[d] = F[(FGA_P + d) * cap + bi];
-          bP[tid][d] = P[d];
-          e[d] = F[(FGA_E + d) * cap + bi];
-        }
-        const double a0r = F[FGA_A0_RE * cap + bi], a0i = F[FGA_A0_IM * cap + bi];
-        const double a1r = F[FGA_A1_RE * cap + bi], a1i = F[FGA_A1_IM * cap + bi];
-        double Ar[3], Ai[3];
-        if (I[FGA_BRANCH * cap + bi] == 0) {
-          const double ip = 1.0 / sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
-          for (int c = 0; c < 3; ++c) { Ar[c] = a0r * P[c] * ip; Ai[c] = a0i * P[c] * ip; }
-        } else {
-          double nsh[3], nsv[3];
-          s_frame(P, e, nsh, nsv);
-          for (int c = 0; c < 3; ++c) {
-            Ar[c] = a0r * nsv[c] + a1r * nsh[c];
-            Ai[c] = a0i * nsv[c] + a1i * nsh[c];
-          }
-        }
-        double sn, cs;
-        sincos(F[FGA_S * cap + bi] * ieps, &sn, &cs);
-        double wr, wi;
-        cmul(F[FGA_W_RE * cap + bi], F[FGA_W_IM * cap + bi], cs, sn, wr, wi);
-        for (int c = 0; c < 3; ++c) {
-          double r_, i_;
-          cmul(wr, wi, Ar[c], Ai[c], r_, i_);
-          bW[tid][c] = make_double2(r_, i_);
-        }
-      } else {
-        for (int d = 0; d < 3; ++d) { bQ[tid][d] = 1.0e300; bP[tid][d] = 0.0; bW[tid][d] = make_double2(0.0, 0.0); }
-      }
+      s = (int32_t)(sm.run_b[lo] + (k - sm.run_pre[lo]));
+      const double *q = rec + (int64_t)s * 12;
+      ok = q[0] + g.R >= plo[0] && q[0] - g.R <= phi[0] && q[1] + g.R >= plo[1] && q[1] - g.R <= phi[1] &&
+           q[2] + g.R >= plo[2] && q[2] - g.R <= phi[2];
     }
+    int tot;
+    const int rk = block_rank(ok, &tot);
+    const int base = sm.listn;
+    if (ok) sm.list[base + rk] = s;
     __syncthreads();
-    // 2. one-dimensional factors, masked by the window
-    for (int e = tid; e < NB * 3 * T; e += 256) {
-      const int jb = e / (3 * T), d = (e / T) % 3, ii = e % T;
-      const int tt = d == 0 ? tx : (d == 1 ? ty : tz);
-      const double x = axis_coord(g, d, T * tt + ii);
-      const double u = x - bQ[jb][d];
-      double2 E = make_double2(0.0, 0.0);
-      if (fabs(u) <= g.R) {
-        double sn, cs;
-        sincos(bP[jb][d] * u * ieps, &sn, &cs);
-        const double m = exp(-u * u * hieps);
-        E = make_double2(m * cs, m * sn);
-      }
-      if (d == 0) Ex[jb][ii] = E;
-      else if (d == 1) Ey[jb][ii] = E;
-      else Ez[jb][ii] = E;
+    if (tid == 0) sm.listn = base + tot;
+    __syncthreads();
+    int ln = base + tot;
+    while (ln >= NB) {
+      grid_batch(g, rec, sm, NB, tc, acc);
+      nexec += NB;
+      const int32_t v = tid + NB < ln ? sm.list[tid + NB] : 0;
+      __syncthreads();
+      if (tid + NB < ln) sm.list[tid] = v;
+      ln -= NB;
+      if (tid == 0) sm.listn = ln;
+      __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < NB * 3 * T; e += 256) {
-      const int jb = e / (3 * T), c = (e / T) % 3, l = e % T;
-      double r_, i_;
-      cmul(bW[jb][c].x, bW[jb][c].y, Ez[jb][l].x, Ez[jb][l].y, r_, i_);
-      V[jb][c][l] = make_double2(r_, i_);
-    }
-    __syncthreads();
-    // 3. K loop on the matrix cores: K step of 4 = 2 beams x (re, im)
-    const int li = lane & 15, kk = lane >> 4, part = kk & 1;
-#pragma unroll 2
-    for (int ks = 0; ks < NB / 2; ++ks) {
-      const int jb = 2 * ks + (kk >> 1);
-      const double2 xv = Ex[jb][li];
-      double a[4];
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        const double2 yv = Ey[jb][4 * w + rb];
-        double xr, xi;
-        cmul(xv.x, xv.y, yv.x, yv.y, xr, xi);
-        a[rb] = part ? xi : xr;
-      }
-      double b[6];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double2 v = V[jb][c][li];
-        b[c] = part ? -v.y : v.x;      // columns of Re U
-        b[3 + c] = part ? v.x : v.y;   // columns of Im U
-      }
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 6; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
-    }
-    __syncthreads();
   }
-  // 4. partial tile [c][l][j][i] complex.  Result register r of lane holds
+  if (sm.listn > 0) {
+    const int cnt = sm.listn;
+    grid_batch(g, rec, sm, cnt, tc, acc);
+    nexec += cnt;
+  }
+  if (tid == 0 && executed && nexec) atomicAdd(executed, nexec);
+  // partial tile [c][l][j][i] complex.  Result register r of lane holds
   // D[lane/16 + 4r][lane % 16] (row: x index i; column: z index l).
   double *P = partial + (int64_t)blockIdx.x * (3 * T * T * T * 2);
 #pragma unroll
@@ -359,11 +410,10 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
   int64_t *tcount = ar.take<int64_t>(ntile);
   Item *items = ar.take<Item>(max_items);
   int32_t *first = ar.take<int32_t>(ntile), *nitems = ar.take<int32_t>(ntile);
-  unsigned long long *ev = ar.take<unsigned long long>(1);
+  unsigned long long *ev = ar.take<unsigned long long>(2);
   double *partial = ar.take<double>((size_t)max_items * 3 * T * T * T * 2);
+  double *rec = ar.take<double>((size_t)12 * (nb + 1));
   size_t sort_bytes = 0;
-  int end_bit = 1;
-  while (end_bit < 31 && (1LL << end_bit) <= ncells) ++end_bit;
   if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, keys, keys2, vals, vals2, (int)nb, 0, 31, st) !=
       hipSuccess)
     return fail(FGA_EDEVICE, "radix sort size query failed");
@@ -373,16 +423,19 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
     return FGA_OK;
   }
   if (!keys || !keys2 || !vals || !vals2 || !start || !tcount || !items || !first || !nitems || !ev || !partial ||
-      !sort_tmp)
+      !sort_tmp || !rec)
     return fail(FGA_ENOMEM, "grid summation workspace too small (%zu bytes given)", ar.size);
   if (nb > 0x7fffffff) return fail(FGA_EUNSUPPORTED, "more than 2^31 beams in one grid summation");
 
-  FGA_HIP(hipMemsetAsync(ev, 0, sizeof(unsigned long long), st));
+  FGA_HIP(hipMemsetAsync(ev, 0, 2 * sizeof(unsigned long long), st));
   if (nb > 0) {
     hipLaunchKernelGGL(k_bin_keys, (unsigned)((nb + 255) / 256), 256, 0, st, b->f64, b->i32, b->capacity, nb, g,
                        keys, vals, ev);
     FGA_LAUNCH_CHECK();
     FGA_HIP(hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, keys, keys2, vals, vals2, (int)nb, 0, 31, st));
+    hipLaunchKernelGGL(k_grid_records, (unsigned)((nb + 255) / 256), 256, 0, st, b->f64, b->i32, b->capacity, keys2,
+                       vals2, nb, 1.0 / eps, rec);
+    FGA_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_cell_start, (unsigned)((ncells + 1 + 255) / 256), 256, 0, st, keys2, nb, (int32_t)ncells,
                      start);
@@ -416,8 +469,7 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
   FGA_HIP(hipMemcpyAsync(nitems, hn.data(), ntile * sizeof(int32_t), hipMemcpyHostToDevice, st));
   if (!hi.empty()) {
     ProfScope prof(FGA_K_GRID_TILE, st);
-    hipLaunchKernelGGL(k_grid_tile_f64, (unsigned)hi.size(), 256, 0, st, g, start, vals2, items, b->f64, b->i32,
-                       b->capacity, partial);
+    hipLaunchKernelGGL(k_grid_tile_f64, (unsigned)hi.size(), 256, 0, st, g, start, items, rec, partial, ev + 1);
     FGA_LAUNCH_CHECK();
   }
   const int64_t plane = (int64_t)n[0] * n[1] * n[2];

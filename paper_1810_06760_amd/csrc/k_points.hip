@@ -1,118 +1,124 @@
 // Step 3 at scattered points (eq:FGA): receivers and seismograms.
 //
-// Layout.  Points are pre-sorted along a Morton curve and split into groups
-// of 16; a wavefront owns one group, its lanes being (point ri = lane % 16,
-// beam slot bs = lane / 16).  The workgroup (4 groups, 64 points) walks a
-// range of beams in tiles of 64 emission records (Q, P/eps, B = w e^{iS/eps} A)
-// staged in LDS; lane (ri, bs) evaluates beams bs, bs + 4, ... of each tile
-// against its point.  Beams of a tile are spatially close and so are the 16
-// points of a group, so the window test is nearly uniform across a
-// wavefront, and a tile whose bounding box is farther than the window from
-// the group's box is skipped as a whole.  Each point's sum is reduced over
-// its four beam slots with lane shuffles and written once per workgroup and
-// sample; workgroup partials are reduced afterwards in a fixed order, so the
-// sums are bitwise reproducible and need no atomics.
+// Beam-major layout.  A wavefront owns RW points and walks a range of beams
+// 64 at a time, one beam per lane, each lane holding its beam's emission
+// record (Q, P/eps, B = w e^{iS/eps} A) in registers and RW complex 3-vector
+// sums.  The beam set is kept in Morton order of Q, so the 64 beams of a
+// lane group are close together and the window test against one point is
+// (nearly) the same on every lane: evaluation is divergence-free and a point
+// whose window misses all 64 beams costs one test.  After the beam range the
+// sums are reduced over the lanes in a fixed order and written once per
+// wavefront and sample; per-workgroup partials are then reduced in a fixed
+// order, so the sums are bitwise reproducible and need no atomics.
 #include "device_common.h"
 #include "fastmath.h"
 
 namespace fga {
 namespace {
 
-constexpr int TILE = 64;   // beam records per LDS stage
-constexpr int GROUP = 16;  // points per wavefront
+constexpr int RW = 8;  // points per wavefront
 
 __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a)
 {
-  __shared__ double rec[12][TILE];
-  __shared__ double tbox[6];
   __shared__ TrigTables tab;
   fill_tables(tab);
+  __syncthreads();
 
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ri = lane & (GROUP - 1), bs = lane / GROUP;
-  const int64_t r = (int64_t)blockIdx.y * 64 + w * GROUP + ri;
-  const bool rv = r < a.n;
-  double x0 = 1.0e300, x1 = 1.0e300, x2 = 1.0e300;
-  if (rv) {
-    x0 = a.xyz[3 * r];
-    x1 = a.xyz[3 * r + 1];
-    x2 = a.xyz[3 * r + 2];
-  }
-  // bounding box of the group's points (lanes of a wavefront share the group)
-  double gb[6] = {rv ? x0 : 1e300, rv ? x1 : 1e300, rv ? x2 : 1e300,
-                  rv ? x0 : -1e300, rv ? x1 : -1e300, rv ? x2 : -1e300};
-  for (int off = 32; off > 0; off >>= 1) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: points live in SGPRs
+  // blockIdx.x: point group (fastest, so workgroups sharing a beam range run
+  // together and re-read its records from L2); blockIdx.y: beam range
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * RW;
+  double xr[RW][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      gb[d] = fmin(gb[d], __shfl_xor(gb[d], off));
-      gb[3 + d] = fmax(gb[3 + d], __shfl_xor(gb[3 + d], off));
-    }
-  }
+  for (int k = 0; k < RW; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xr[k][d] = r0 + k < a.n ? a.xyz[3 * (r0 + k) + d] : 1.0e300;
   const double R = sqrt(2.0 * a.tau * a.eps);
   const double hieps = 0.5 / a.eps;
-  const int64_t b0 = (int64_t)blockIdx.x * a.beams_per_block;
+  const int64_t b0 = (int64_t)blockIdx.y * a.beams_per_block;
   const int64_t b1 = b0 + a.beams_per_block < a.nb ? b0 + a.beams_per_block : a.nb;
   unsigned long long cnt = 0;
-  __syncthreads();  // tables
   for (int s = 0; s < a.m; ++s) {
     const double *E = a.emit + (int64_t)s * 12 * a.nb;
-    double u[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t t0 = b0; t0 < b1; t0 += TILE) {
-      for (int k = threadIdx.x; k < 12 * TILE; k += 256) {
-        const int f = k / TILE, jj = k % TILE;
-        // padding beams sit at -1e300, points of idle lanes at +1e300: never in window
-        rec[f][jj] = t0 + jj < b1 ? E[f * a.nb + t0 + jj] : (f < 3 ? -1.0e300 : 0.0);
+    double u[RW][6];
+#pragma unroll
+    for (int k = 0; k < RW; ++k)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) u[k][c] = 0.0;
+    // records of the lane's beam, software-pipelined one tile ahead so the
+    // global loads overlap the previous tile's arithmetic
+    double nq[3], npe[3], nB[6];
+    auto fetch = [&](int64_t t0) {
+      const int64_t j = t0 + lane;
+      const bool v = j < b1;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        nq[d] = v ? E[d * a.nb + j] : -1.0e300;
+        npe[d] = v ? E[(3 + d) * a.nb + j] : 0.0;
       }
-      if (w == 0) {
-        // tile bounding box of the beam centres
-        const bool bv = t0 + lane < b1;
-        double q[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) q[d] = bv ? E[d * a.nb + t0 + lane] : 0.0;
-        double tb[6] = {bv ? q[0] : 1e300, bv ? q[1] : 1e300, bv ? q[2] : 1e300,
-                        bv ? q[0] : -1e300, bv ? q[1] : -1e300, bv ? q[2] : -1e300};
-        for (int off = 32; off > 0; off >>= 1) {
+      for (int c = 0; c < 6; ++c) nB[c] = v ? E[(6 + c) * a.nb + j] : 0.0;
+    };
+    fetch(b0);
+    for (int64_t t0 = b0; t0 < b1; t0 += 64) {
+      double q[3], pe[3], B[6];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            tb[d] = fmin(tb[d], __shfl_xor(tb[d], off));
-            tb[3 + d] = fmax(tb[3 + d], __shfl_xor(tb[3 + d], off));
-          }
+      for (int d = 0; d < 3; ++d) { q[d] = nq[d]; pe[d] = npe[d]; }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) B[c] = nB[c];
+      if (t0 + 64 < b1) fetch(t0 + 64);
+      // points two at a time: two independent exponential chains per lane;
+      // a pair no lane's window reaches is skipped by the whole wavefront,
+      // and a lane outside one window contributes an exact zero
+#pragma unroll
+      for (int k = 0; k < RW; k += 2) {
+        double dd[2][3];
+        bool in[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) dd[h][d] = xr[k + h][d] - q[d];
+          in[h] = !(fmax(fabs(dd[h][0]), fmax(fabs(dd[h][1]), fabs(dd[h][2]))) > R);
         }
-        if (lane < 6) tbox[lane] = tb[lane];
-      }
-      __syncthreads();
-      const bool near = tbox[0] - R <= gb[3] && gb[0] <= tbox[3] + R && tbox[1] - R <= gb[4] &&
-                        gb[1] <= tbox[4] + R && tbox[2] - R <= gb[5] && gb[2] <= tbox[5] + R;
-      if (near) {
-#pragma unroll 2
-        for (int jb = bs; jb < TILE; jb += 64 / GROUP) {
-          const double d0 = x0 - rec[0][jb], d1 = x1 - rec[1][jb], d2 = x2 - rec[2][jb];
-          if (fmax(fabs(d0), fmax(fabs(d1), fabs(d2))) > R) continue;
-          ++cnt;
-          const double g = (d0 * d0 + d1 * d1 + d2 * d2) * hieps;
-          const double ph = rec[3][jb] * d0 + rec[4][jb] * d1 + rec[5][jb] * d2;
-          double er, ei;
-          cexp_neg(tab, g, ph, er, ei);
+        if (!__any(in[0] || in[1])) continue;
+        double er[2], ei[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          cnt += in[h] ? 1 : 0;
+          const double g = in[h] ? (dd[h][0] * dd[h][0] + dd[h][1] * dd[h][1] + dd[h][2] * dd[h][2]) * hieps : 0.0;
+          const double ph = in[h] ? pe[0] * dd[h][0] + pe[1] * dd[h][1] + pe[2] * dd[h][2] : 0.0;
+          cexp_neg(tab, g, ph, er[h], ei[h]);
+          er[h] = in[h] ? er[h] : 0.0;
+          ei[h] = in[h] ? ei[h] : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double br = rec[6 + 2 * c][jb], bi = rec[7 + 2 * c][jb];
-            u[2 * c] = fma(er, br, fma(-ei, bi, u[2 * c]));
-            u[2 * c + 1] = fma(er, bi, fma(ei, br, u[2 * c + 1]));
+            u[k + h][2 * c] = fma(er[h], B[2 * c], fma(-ei[h], B[2 * c + 1], u[k + h][2 * c]));
+            u[k + h][2 * c + 1] = fma(er[h], B[2 * c + 1], fma(ei[h], B[2 * c], u[k + h][2 * c + 1]));
           }
-        }
       }
-      __syncthreads();
     }
-    // sum the four beam slots of each point (fixed order: slot 0+1, 2+3, then both)
+    // lane reduction in a fixed butterfly order; every lane ends with the total
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      u[c] += __shfl_xor(u[c], 16);
-      u[c] += __shfl_xor(u[c], 32);
-    }
-    if (rv && bs == 0) {
-      double *o = a.partial + (((int64_t)blockIdx.x * a.m + s) * a.n + r) * 6;
+    for (int k = 0; k < RW; ++k)
 #pragma unroll
-      for (int c = 0; c < 6; ++c) o[c] = u[c];
+      for (int c = 0; c < 6; ++c) {
+        double v = u[k][c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        u[k][c] = v;
+      }
+    if (lane < RW * 6) {
+      const int k = lane / 6, c = lane % 6;
+      double v = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < RW; ++kk)
+#pragma unroll
+        for (int cc = 0; cc < 6; ++cc)
+          if (kk == k && cc == c) v = u[kk][cc];
+      if (r0 + k < a.n) a.partial[(((int64_t)blockIdx.y * a.m + s) * a.n + r0 + k) * 6 + c] = v;
     }
   }
   if (a.evals) {
@@ -146,7 +152,7 @@ hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st)
   const int64_t nblk = (a.nb + a.beams_per_block - 1) / a.beams_per_block;
   *nblk_out = (int)nblk;
   if (a.nb == 0 || a.n == 0 || a.m == 0) return hipSuccess;
-  dim3 grid((unsigned)nblk, (unsigned)((a.n + 63) / 64));
+  dim3 grid((unsigned)((a.n + 4 * RW - 1) / (4 * RW)), (unsigned)nblk);
   ProfScope prof(FGA_K_SUM_POINTS, st);
   hipLaunchKernelGGL(k_sum_points, grid, 256, 0, st, a);
   return hipGetLastError();
