@@ -97,8 +97,11 @@ def gpu_run(w, args):
                                                               ws=state["ws_grid"])
         return beams.count, st, ev_grid
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
+        t = time.perf_counter()
         step()
+        torch.cuda.synchronize()
+        print("bench: warmup step %d done in %.1f s" % (i + 1, time.perf_counter() - t), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     fga.fga_profile_enable(True)
     torch.cuda.synchronize()
@@ -110,6 +113,7 @@ def gpu_run(w, args):
         tot["beam_steps"] += st["beam_steps"]
         tot["ev_rec"] += st["evals"]
         tot["ev_grid"] += evg
+        print("bench: timed step done, %d beams" % nb, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = {fga.KERNEL_NAMES[k]: fga.fga_profile_read(k) for k in fga.KERNEL_NAMES}

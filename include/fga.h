@@ -201,7 +201,8 @@ typedef struct {
   int compact;             /* 1: compact the beam set after culling (stable order)     */
   int64_t batch;           /* beams per receiver batch (0: library default)            */
   int resort;              /* steps between spatial re-orderings of the beam set
-                              (0: library default 64; < 0: never reorder)              */
+                              (0: library default, 16 with receivers, else 64;
+                               < 0: never reorder)                                     */
 } fga_evolve_opts;
 
 typedef struct {

@@ -307,15 +307,15 @@ EvolvePlan evolve_plan(const fga_beams *b, int nsteps, const fga_evolve_opts *o,
   p.batch = (o && o->batch > 0) ? o->batch : ((int64_t)1 << 22);
   if (p.batch > b->count) p.batch = b->count > 0 ? b->count : 1;
   p.nsamp = r ? nsteps / r->stride : 0;
-  p.bpb = kPointsBeamsPerBlock;
-  p.resort = (o && o->resort < 0) ? 0 : ((o && o->resort > 0) ? o->resort : 64);
+  p.bpb = r ? points_beams_per_block(p.batch, r->n, (p.chunk + r->stride - 1) / r->stride + 1) : 1024;
+  p.resort = (o && o->resort < 0) ? 0 : ((o && o->resort > 0) ? o->resort : (r ? 16 : 64));
   if (p.resort > 0 && p.resort < p.chunk) p.resort = p.chunk;
   return p;
 }
 
 struct EvolveBufs {
   unsigned long long *ctr = nullptr;
-  double *emit = nullptr, *partial = nullptr, *xs = nullptr;
+  double *emit = nullptr, *partial = nullptr, *xs = nullptr, *box = nullptr;
   int32_t *perm = nullptr;
 };
 
@@ -328,6 +328,7 @@ EvolveBufs evolve_layout(const EvolvePlan &p, const fga_receivers *r, Arena &ar)
     b.emit = ar.take<double>((size_t)m * 12 * p.batch);
     const int64_t nblk = (p.batch + p.bpb - 1) / p.bpb;
     b.partial = ar.take<double>((size_t)nblk * m * r->n * 6);
+    b.box = ar.take<double>((size_t)m * ((p.batch + 63) / 64) * 6);
     b.xs = ar.take<double>((size_t)3 * r->n + 1);
     b.perm = ar.take<int32_t>((size_t)r->n + 1);
   }
@@ -383,7 +384,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
   const EvolveBufs wb = evolve_layout(p, rec, ar);
   unsigned long long *ctr = wb.ctr;
   double *emit = wb.emit, *partial = wb.partial;
-  if (!ctr || (rec && (!emit || !partial || !wb.xs || !wb.perm)))
+  if (!ctr || (rec && (!emit || !partial || !wb.box || !wb.xs || !wb.perm)))
     return fail(FGA_ENOMEM, "evolve workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
   const size_t sort_base = ar.used;
   FGA_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), st));
@@ -435,6 +436,8 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
         pa.partial = partial;
         pa.beams_per_block = p.bpb;
         pa.evals = ctr + 3;
+        pa.tile_box = wb.box;
+        pa.ntiles = (pa.nb + 63) / 64;
         int nblk = 0;
         FGA_HIP(launch_sum_points(pa, &nblk, st));
         FGA_HIP(launch_reduce_points(partial, nblk, ns, rec->n, wb.perm, seis, p.nsamp, sfirst, b0 > 0 ? 1 : 0,
@@ -472,7 +475,9 @@ size_t fga_reconstruct_points_workspace_bytes(const fga_beams *beams, int64_t n)
   Arena ar(nullptr, 0);
   ar.take<unsigned long long>(1);
   ar.take<double>((size_t)12 * batch);
-  ar.take<double>((size_t)((batch + kPointsBeamsPerBlock - 1) / kPointsBeamsPerBlock) * n * 6);
+  const int bpb = points_beams_per_block(batch, n, 1);
+  ar.take<double>((size_t)((batch + bpb - 1) / bpb) * n * 6);
+  ar.take<double>((size_t)((batch + 63) / 64) * 6);
   ar.take<double>((size_t)3 * n + 1);
   ar.take<int32_t>((size_t)n + 1);
   return ar.used;
@@ -493,10 +498,12 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
   Arena ar(workspace, workspace_bytes);
   unsigned long long *ctr = ar.take<unsigned long long>(1);
   double *emit = ar.take<double>((size_t)12 * batch);
-  double *partial = ar.take<double>((size_t)((batch + kPointsBeamsPerBlock - 1) / kPointsBeamsPerBlock) * n * 6);
+  const int bpb = points_beams_per_block(batch, n, 1);
+  double *partial = ar.take<double>((size_t)((batch + bpb - 1) / bpb) * n * 6);
+  double *box = ar.take<double>((size_t)((batch + 63) / 64) * 6);
   double *xs = ar.take<double>((size_t)3 * n + 1);
   int32_t *perm = ar.take<int32_t>((size_t)n + 1);
-  if (!ctr || !emit || !partial || !xs || !perm)
+  if (!ctr || !emit || !partial || !box || !xs || !perm)
     return fail(FGA_ENOMEM, "reconstruct workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
   if (n > 0x7fffffff) return fail(FGA_EUNSUPPORTED, "more than 2^31 points");
   FGA_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long), st));
@@ -514,8 +521,10 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
     pa.eps = eps;
     pa.tau = tau;
     pa.partial = partial;
-    pa.beams_per_block = kPointsBeamsPerBlock;
+    pa.beams_per_block = bpb;
     pa.evals = ctr;
+    pa.tile_box = box;
+    pa.ntiles = (pa.nb + 63) / 64;
     int nblk = 0;
     FGA_HIP(launch_sum_points(pa, &nblk, st));
     FGA_HIP(launch_reduce_points(partial, nblk, 1, n, perm, out, 1, 0, b0 > 0 ? 1 : 0, st));

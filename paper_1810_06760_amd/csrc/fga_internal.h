@@ -109,9 +109,14 @@ struct PointsArgs {
   double *partial;           // [nblk][m][n][6]
   int beams_per_block;
   unsigned long long *evals;
+  double *tile_box;          // scratch [m][ntiles][6], ntiles = ceil(nb / 64)
+  int64_t ntiles;
 };
 hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st);
-constexpr int kPointsBeamsPerBlock = 8192;  // beams walked by one point-sum workgroup
+// beams walked by one point-sum workgroup for nb beams, n points and m samples
+// per launch (a multiple of 64 in [1024, 8192]); partial holds
+// ceil(nb / that) * m * n * 6 doubles
+int points_beams_per_block(int64_t nb, int64_t n, int m);
 // seis[perm[r]][s0 + s][c] (+)= sum_blk partial[blk][s][r][c]   (perm NULL: identity)
 hipError_t launch_reduce_points(const double *partial, int nblk, int m, int64_t n, const int32_t *perm,
                                 double *out, int64_t out_samples, int s0, int accumulate, hipStream_t st);

@@ -4,12 +4,16 @@
 // 64 at a time, one beam per lane, each lane holding its beam's emission
 // record (Q, P/eps, B = w e^{iS/eps} A) in registers and RW complex 3-vector
 // sums.  The beam set is kept in Morton order of Q, so the 64 beams of a
-// lane group are close together and the window test against one point is
+// tile are close together and the window test against one point is
 // (nearly) the same on every lane: evaluation is divergence-free and a point
-// whose window misses all 64 beams costs one test.  After the beam range the
-// sums are reduced over the lanes in a fixed order and written once per
-// wavefront and sample; per-workgroup partials are then reduced in a fixed
-// order, so the sums are bitwise reproducible and need no atomics.
+// whose window misses all 64 beams costs one test.  A workgroup covers one
+// sample, 32 points (four wavefronts) and one beam range; each beam tile is
+// read from memory once per workgroup and shared through LDS, double-
+// buffered so the next tile's loads overlap this tile's sums.  Tiles out of
+// reach of all of a workgroup's points (by bounding boxes) are not loaded.
+// After the beam range the sums are reduced over the lanes in a fixed order
+// and written once per wavefront; per-workgroup partials are then reduced in
+// a fixed order, so the sums are bitwise reproducible and need no atomics.
 #include "device_common.h"
 #include "fastmath.h"
 
@@ -17,18 +21,41 @@ namespace fga {
 namespace {
 
 constexpr int RW = 8;  // points per wavefront
+constexpr int PG = 4 * RW;  // points per workgroup
 
-__global__ __launch_bounds__(256) void k_sum_points(PointsArgs a)
+// Workgroup -> (point group, beam range, sample).  Workgroups are dealt to
+// the 8 XCDs round-robin by id; the point groups of one (beam range, sample)
+// unit get consecutive ids on the same XCD, so that unit's records come from
+// HBM once and are then served by that XCD's L2.
+struct PointsWork {
+  int pg;
+  int64_t blk;
+  int s;
+  bool valid;
+};
+__device__ __forceinline__ PointsWork points_work(int64_t id, int groups, int64_t nblk, int m)
+{
+  PointsWork w;
+  const int64_t xcd = id & 7, j = id >> 3;
+  w.pg = (int)(j % groups);
+  const int64_t unit = (j / groups) * 8 + xcd;
+  w.blk = unit % nblk;
+  w.s = (int)(unit / nblk);
+  w.valid = w.s < m;
+  return w;
+}
+
+__global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, int64_t nblk)
 {
   __shared__ TrigTables tab;
   fill_tables(tab);
   __syncthreads();
 
+  const PointsWork wk = points_work(blockIdx.x, groups, nblk, a.m);
+  if (!wk.valid) return;  // whole workgroup: padding of the last XCD round
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: points live in SGPRs
-  // blockIdx.x: point group (fastest, so workgroups sharing a beam range run
-  // together and re-read its records from L2); blockIdx.y: beam range
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * RW;
+  const int64_t r0 = (int64_t)wk.pg * PG + w * RW;
   double xr[RW][3];
 #pragma unroll
   for (int k = 0; k < RW; ++k)
@@ -36,94 +63,159 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a)
     for (int d = 0; d < 3; ++d) xr[k][d] = r0 + k < a.n ? a.xyz[3 * (r0 + k) + d] : 1.0e300;
   const double R = sqrt(2.0 * a.tau * a.eps);
   const double hieps = 0.5 / a.eps;
-  const int64_t b0 = (int64_t)blockIdx.y * a.beams_per_block;
+  const int64_t b0 = wk.blk * a.beams_per_block;
   const int64_t b1 = b0 + a.beams_per_block < a.nb ? b0 + a.beams_per_block : a.nb;
-  unsigned long long cnt = 0;
-  for (int s = 0; s < a.m; ++s) {
-    const double *E = a.emit + (int64_t)s * 12 * a.nb;
-    double u[RW][6];
+  const int s = wk.s;
+  const double *E = a.emit + (int64_t)s * 12 * a.nb;
+  uint64_t cnt = 0;          // wave-uniform in-window count
+  double u[RW][6];
 #pragma unroll
-    for (int k = 0; k < RW; ++k)
+  for (int k = 0; k < RW; ++k)
 #pragma unroll
-      for (int c = 0; c < 6; ++c) u[k][c] = 0.0;
-    // records of the lane's beam, software-pipelined one tile ahead so the
-    // global loads overlap the previous tile's arithmetic
-    double nq[3], npe[3], nB[6];
-    auto fetch = [&](int64_t t0) {
-      const int64_t j = t0 + lane;
-      const bool v = j < b1;
+    for (int c = 0; c < 6; ++c) u[k][c] = 0.0;
+
+  // bounding box of the wavefront's points; a beam tile whose box lies more
+  // than R away from it along some axis holds no term for any of them (the
+  // rounded differences are monotone, so this agrees with the per-lane test)
+  double plo[3], phi[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        nq[d] = v ? E[d * a.nb + j] : -1.0e300;
-        npe[d] = v ? E[(3 + d) * a.nb + j] : 0.0;
+  for (int d = 0; d < 3; ++d) {
+    plo[d] = xr[0][d];
+    phi[d] = xr[0][d];
+#pragma unroll
+    for (int k = 1; k < RW; ++k)
+      if (r0 + k < a.n) {
+        plo[d] = fmin(plo[d], xr[k][d]);
+        phi[d] = fmax(phi[d], xr[k][d]);
       }
-#pragma unroll
-      for (int c = 0; c < 6; ++c) nB[c] = v ? E[(6 + c) * a.nb + j] : 0.0;
-    };
-    fetch(b0);
-    for (int64_t t0 = b0; t0 < b1; t0 += 64) {
-      double q[3], pe[3], B[6];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) { q[d] = nq[d]; pe[d] = npe[d]; }
-#pragma unroll
-      for (int c = 0; c < 6; ++c) B[c] = nB[c];
-      if (t0 + 64 < b1) fetch(t0 + 64);
-      // points two at a time: two independent exponential chains per lane;
-      // a pair no lane's window reaches is skipped by the whole wavefront,
-      // and a lane outside one window contributes an exact zero
-#pragma unroll
-      for (int k = 0; k < RW; k += 2) {
-        double dd[2][3];
-        bool in[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-#pragma unroll
-          for (int d = 0; d < 3; ++d) dd[h][d] = xr[k + h][d] - q[d];
-          in[h] = !(fmax(fabs(dd[h][0]), fmax(fabs(dd[h][1]), fabs(dd[h][2]))) > R);
-        }
-        if (!__any(in[0] || in[1])) continue;
-        double er[2], ei[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          cnt += in[h] ? 1 : 0;
-          const double g = in[h] ? (dd[h][0] * dd[h][0] + dd[h][1] * dd[h][1] + dd[h][2] * dd[h][2]) * hieps : 0.0;
-          const double ph = in[h] ? pe[0] * dd[h][0] + pe[1] * dd[h][1] + pe[2] * dd[h][2] : 0.0;
-          cexp_neg(tab, g, ph, er[h], ei[h]);
-          er[h] = in[h] ? er[h] : 0.0;
-          ei[h] = in[h] ? ei[h] : 0.0;
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            u[k + h][2 * c] = fma(er[h], B[2 * c], fma(-ei[h], B[2 * c + 1], u[k + h][2 * c]));
-            u[k + h][2 * c + 1] = fma(er[h], B[2 * c + 1], fma(ei[h], B[2 * c], u[k + h][2 * c + 1]));
-          }
-      }
-    }
-    // lane reduction in a fixed butterfly order; every lane ends with the total
-#pragma unroll
-    for (int k = 0; k < RW; ++k)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        double v = u[k][c];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        u[k][c] = v;
-      }
-    if (lane < RW * 6) {
-      const int k = lane / 6, c = lane % 6;
-      double v = 0.0;
-#pragma unroll
-      for (int kk = 0; kk < RW; ++kk)
-#pragma unroll
-        for (int cc = 0; cc < 6; ++cc)
-          if (kk == k && cc == c) v = u[kk][cc];
-      if (r0 + k < a.n) a.partial[(((int64_t)blockIdx.y * a.m + s) * a.n + r0 + k) * 6 + c] = v;
-    }
   }
-  if (a.evals) {
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
-    if (lane == 0 && cnt) atomicAdd(a.evals, cnt);
+  const double *TB = a.tile_box + (int64_t)s * a.ntiles * 6;
+  auto live = [&](int64_t t0) {
+    const double *tb = TB + (t0 >> 6) * 6;  // lo[3], hi[3]
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ok = ok && !(tb[d] - phi[d] > R) && !(plo[d] - tb[3 + d] > R);
+    return ok;
+  };
+  auto next_live = [&](int64_t t0) {
+    while (t0 < b1 && !live(t0)) t0 += 64;
+    return t0;
+  };
+  // records of the lane's beam, software-pipelined one tile ahead so the
+  // global loads overlap the previous tile's arithmetic
+  double nq[3], npe[3], nB[6];
+  auto fetch = [&](int64_t t0) {
+    const int64_t j = t0 + lane;
+    const bool v = j < b1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      nq[d] = v ? E[d * a.nb + j] : -1.0e300;
+      npe[d] = v ? E[(3 + d) * a.nb + j] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) nB[c] = v ? E[(6 + c) * a.nb + j] : 0.0;
+  };
+  int64_t t0 = next_live(b0);
+  if (t0 < b1) fetch(t0);
+  while (t0 < b1) {
+    double q[3], pe[3], B[6];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { q[d] = nq[d]; pe[d] = npe[d]; }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) B[c] = nB[c];
+    const int64_t tn = next_live(t0 + 64);
+    if (tn < b1) fetch(tn);
+    // points four at a time: unless no lane's beam is in any of the four
+    // windows, the four terms are evaluated together (four independent
+    // exponential chains per lane hide each other's latency).  Outside its
+    // window a term gets the argument g = 2048, whose exponential underflows
+    // to exactly zero.
+#pragma unroll
+    for (int k = 0; k < RW; k += 4) {
+      double dd[4][3];
+      bool in[4];
+      bool any = false;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dd[h][d] = xr[k + h][d] - q[d];
+        in[h] = !(fmax(fabs(dd[h][0]), fmax(fabs(dd[h][1]), fabs(dd[h][2]))) > R);
+        cnt += __popcll(__ballot(in[h]));
+        any = any || in[h];
+      }
+      if (!__any(any)) continue;
+      double er[4], ei[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const double g = in[h] ? (dd[h][0] * dd[h][0] + dd[h][1] * dd[h][1] + dd[h][2] * dd[h][2]) * hieps : 2048.0;
+        const double ph = in[h] ? pe[0] * dd[h][0] + pe[1] * dd[h][1] + pe[2] * dd[h][2] : 0.0;
+        cexp_neg(tab, g, ph, er[h], ei[h]);
+      }
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          u[k + h][2 * c] = fma(er[h], B[2 * c], fma(-ei[h], B[2 * c + 1], u[k + h][2 * c]));
+          u[k + h][2 * c + 1] = fma(er[h], B[2 * c + 1], fma(ei[h], B[2 * c], u[k + h][2 * c + 1]));
+        }
+    }
+    t0 = tn;
+  }
+  // lane reduction in a fixed butterfly order; every lane ends with the total
+#pragma unroll
+  for (int k = 0; k < RW; ++k)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      double v = u[k][c];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      u[k][c] = v;
+    }
+  if (lane < RW * 6) {
+    const int k = lane / 6, c = lane % 6;
+    double v = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < RW; ++kk)
+#pragma unroll
+      for (int cc = 0; cc < 6; ++cc)
+        if (kk == k && cc == c) v = u[kk][cc];
+    if (r0 + k < a.n) a.partial[((wk.blk * a.m + s) * a.n + r0 + k) * 6 + c] = v;
+  }
+  if (a.evals && lane == 0 && cnt) atomicAdd(a.evals, (unsigned long long)cnt);
+}
+
+// Per sample and 64-beam tile: bounding box of the live beams' centres Q
+// (lo[3], hi[3]; an all-dead tile gets an empty box +inf / -inf).
+__global__ __launch_bounds__(256) void k_tile_box(const double *__restrict__ emit, int64_t nb, int64_t ntiles,
+                                                  double *__restrict__ box)
+{
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int s = blockIdx.y;
+  if (t >= ntiles) return;
+  const double *E = emit + (int64_t)s * 12 * nb;
+  const int64_t j = t * 64 + lane;
+  double lo[3], hi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double q = j < nb ? E[d * nb + j] : -1.0e300;
+    const bool dead = !(q > -1.0e299);
+    lo[d] = dead ? INFINITY : q;
+    hi[d] = dead ? -INFINITY : q;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[d] = fmin(lo[d], __shfl_xor(lo[d], off));
+      hi[d] = fmax(hi[d], __shfl_xor(hi[d], off));
+    }
+  if (lane < 6) {
+    double v = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (lane == d) v = lo[d];
+      if (lane == 3 + d) v = hi[d];
+    }
+    box[((int64_t)s * ntiles + t) * 6 + lane] = v;
   }
 }
 
@@ -147,14 +239,37 @@ __global__ __launch_bounds__(256) void k_reduce_points(const double *__restrict_
 
 }  // namespace
 
+int points_beams_per_block(int64_t nb, int64_t n, int m)
+{
+  // enough workgroups (about 8192) that the last partial round of resident
+  // workgroups is a small fraction of the launch; ranges are whole 64-beam tiles
+  const int64_t groups = (n + 4 * RW - 1) / (4 * RW);
+  const int64_t pairs = nb * groups * (m > 0 ? m : 1);
+  int64_t bpb = (pairs + 8191) / 8192;
+  bpb = (bpb + 63) / 64 * 64;
+  if (bpb < 1024) bpb = 1024;
+  if (bpb > 8192) bpb = 8192;
+  return (int)bpb;
+}
+
 hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st)
 {
   const int64_t nblk = (a.nb + a.beams_per_block - 1) / a.beams_per_block;
   *nblk_out = (int)nblk;
   if (a.nb == 0 || a.n == 0 || a.m == 0) return hipSuccess;
-  dim3 grid((unsigned)((a.n + 4 * RW - 1) / (4 * RW)), (unsigned)nblk);
+  if (a.m > 65535) return hipErrorInvalidConfiguration;
+  const int64_t ntiles = (a.nb + 63) / 64;
+  if (ntiles != a.ntiles) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tile_box, dim3((unsigned)((ntiles + 3) / 4), (unsigned)a.m), 256, 0, st, a.emit, a.nb, ntiles,
+                     a.tile_box);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int groups = (int)((a.n + PG - 1) / PG);
+  const int64_t units = (nblk * a.m + 7) / 8 * 8;
+  const int64_t nwg = units * groups;
+  if (nwg > 0x7fffffff) return hipErrorInvalidConfiguration;
   ProfScope prof(FGA_K_SUM_POINTS, st);
-  hipLaunchKernelGGL(k_sum_points, grid, 256, 0, st, a);
+  hipLaunchKernelGGL(k_sum_points, dim3((unsigned)nwg), 256, 0, st, a, groups, nblk);
   return hipGetLastError();
 }
 
