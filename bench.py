@@ -33,6 +33,8 @@ FLOP_BEAM_STEP = {"homogeneous": 3390, "grid": 4186}
 FLOP_POINT_EVAL = 101     # 41 arithmetic + exp (21) + sincos (39), counted from the gfx950 code
 FLOP_GRID_EVAL = 24       # 3 complex multiply-adds
 PEAK_FP64 = 78.6e12       # FP64 vector and FP64 matrix peak, MI355X
+# grid summation variants: (library code, dense MFMA peak of the operand type)
+GRID_PREC = {"fp64": (0, 78.6e12), "fp32": (1, 157.3e12), "bf16x3": (2, 2.5e15), "fp16x3": (3, 2.5e15)}
 HBM_PEAK = 8.0e12
 
 
@@ -46,6 +48,8 @@ def parse():
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-beams", type=int, default=48, help="(q,p) pairs in the oracle sample")
+    ap.add_argument("--grid-precision", default="fp64", choices=list(GRID_PREC),
+                    help="grid summation variant (mixed variants also report their error against FP64)")
     return ap.parse_args()
 
 
@@ -93,8 +97,9 @@ def gpu_run(w, args):
             if state["ws_grid"] is None:
                 state["ws_grid"] = fga._workspace(fga.workspace_bytes("grid", beams=beams, mesh=w.out_grid,
                                                                       eps=w.eps, tau=w.tau))
-            state["grid"], ev_grid = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid, out=state["grid"],
-                                                              ws=state["ws_grid"])
+            state["grid"], ev_grid = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid,
+                                                              precision=GRID_PREC[args.grid_precision][0],
+                                                              out=state["grid"], ws=state["ws_grid"])
         return beams.count, st, ev_grid
 
     for i in range(args.warmup):
@@ -118,10 +123,15 @@ def gpu_run(w, args):
     t1 = time.perf_counter()
     prof = {fga.KERNEL_NAMES[k]: fga.fga_profile_read(k) for k in fga.KERNEL_NAMES}
     fga.fga_profile_enable(False)
+    if args.grid_precision != "fp64" and w.out_grid is not None:
+        # error of the mixed variant against the FP64 path (itself at oracle parity), same final beams
+        ref, _ = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid, precision=0, ws=state["ws_grid"])
+        tot["grid_rel_l2_vs_fp64"] = float(torch.linalg.vector_norm(state["grid"] - ref) /
+                                           torch.linalg.vector_norm(ref))
     return t1 - t0, tot, prof
 
 
-def roofline(tot, prof, medium_kind):
+def roofline(tot, prof, medium_kind, grid_peak=PEAK_FP64):
     """Dominant kernel: algorithmic FLOPs per launch / mean launch time."""
     work = {
         "integrate": tot["beam_steps"] * FLOP_BEAM_STEP[medium_kind],
@@ -134,8 +144,9 @@ def roofline(tot, prof, medium_kind):
         return None, name
     achieved = work[name] / launches / (ms / launches * 1e-3)
     bound = "mfma" if name == "grid_tile" else "alu"
-    return {"bound": bound, "kernel": name, "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+    peak = grid_peak if name == "grid_tile" else PEAK_FP64
+    return {"bound": bound, "kernel": name, "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
             "launches": launches, "avg_launch_ms": ms / launches}, name
 
 
@@ -197,10 +208,10 @@ def main():
     w, label = make_workload(args.workload, args.scale)
     elapsed, tot, prof = gpu_run(w, args)
     K = args.steps
-    per = {k: v / K for k, v in tot.items()}
+    per = {k: v / K for k, v in tot.items() if k != "grid_rel_l2_vs_fp64"}
     value = tot["beam_steps"] / elapsed
     kind = "grid" if w.medium_nodes is not None else "homogeneous"
-    roof, dom = roofline(tot, prof, kind)
+    roof, dom = roofline(tot, prof, kind, GRID_PREC[args.grid_precision][1])
     line = {
         "metric": "beam-steps/s + beam-point evals/s; served solves/s, p50/p99 at rel-L2<=1e-3",
         "value": value,
@@ -222,6 +233,9 @@ def main():
         "kernel_ms_per_step": {k: v[1] / K for k, v in prof.items()},
         "roofline": roof,
     }
+    if args.grid_precision != "fp64":
+        line["grid_precision"] = args.grid_precision
+        line["grid_rel_l2_vs_fp64"] = tot.get("grid_rel_l2_vs_fp64")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, per, w.qmesh.count * w.pmesh.count, args)
     print(json.dumps(line), flush=True)

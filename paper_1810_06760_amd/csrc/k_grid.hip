@@ -9,11 +9,20 @@
 // a factor block, M = 256, N = 48, K = beams near the tile.  It runs as a real
 // GEMM [Re X | Im X] [[Re V, Im V], [-Im V, Re V]] on v_mfma_f64_16x16x4_f64.
 //
+// Mixed precision: the 1-D factors take their phases reduced modulo 2 pi
+// and their Gaussian exponents in FP64, then the exponential and sine/cosine
+// in FP32; W is scaled by 1 / max_b |W_b|.  The product runs with FP32
+// accumulation on v_mfma_f32_16x16x4_f32 (FGA_FP32), or with each operand
+// split into hi + lo halves, hi = round(x), lo = round(x - hi), and the three
+// products hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_{bf16,f16}
+// (FGA_BF16X3, FGA_FP16X3).
+//
 // Beams are binned by the tile-sized cell of Q (radix sort of cell keys); a
 // tile's candidates are the (2r+1)^2 contiguous runs of cells within reach of
 // it.  Each tile's candidate list is split into segments, one workgroup per
 // segment, whose partial tiles are then reduced in a fixed order.
 #include <hipcub/hipcub.hpp>
+#include <type_traits>
 
 #include "device_common.h"
 #include "fastmath.h"
@@ -141,7 +150,7 @@ __device__ __forceinline__ void cmul(double ar, double ai, double br, double bi,
 __global__ __launch_bounds__(256) void k_grid_records(const double *__restrict__ F, const int32_t *__restrict__ I,
                                                       int64_t cap, const int32_t *__restrict__ keys,
                                                       const int32_t *__restrict__ order, int64_t n, double ieps,
-                                                      double *__restrict__ rec)
+                                                      double *__restrict__ rec, unsigned long long *__restrict__ wmax)
 {
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (s >= n || keys[s] == 0x7fffffff) return;
@@ -172,14 +181,23 @@ __global__ __launch_bounds__(256) void k_grid_records(const double *__restrict__
   sincos(F[FGA_S * cap + bi] * ieps, &sn, &cs);
   double wr, wi;
   cmul(F[FGA_W_RE * cap + bi], F[FGA_W_IM * cap + bi], cs, sn, wr, wi);
-  for (int c = 0; c < 3; ++c) cmul(wr, wi, Ar[c], Ai[c], o[6 + 2 * c], o[7 + 2 * c]);
+  double m = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    cmul(wr, wi, Ar[c], Ai[c], o[6 + 2 * c], o[7 + 2 * c]);
+    m = fmax(m, fmax(fabs(o[6 + 2 * c]), fabs(o[7 + 2 * c])));
+  }
+  // non-negative doubles order like their bit patterns
+  if (wmax && m > 0.0 && m < INFINITY) atomicMax(wmax, (unsigned long long)__double_as_longlong(m));
 }
 
-struct TileSmem {
+struct ListSmem {
   int64_t run_b[MAXR], run_pre[MAXR + 1];
   int32_t list[256 + NB];
   int listn;
   double brec[NB][12];
+};
+
+struct TileSmem : ListSmem {
   double2 Ex[NB][T], Ey[NB][T], Ez[NB][T], V[NB][3][T];
   TrigTables tab;
 };
@@ -245,13 +263,229 @@ __device__ __forceinline__ void grid_batch(const GridGeom &g, const double *__re
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_grid_tile_f64(GridGeom g, const int64_t *__restrict__ start,
-                                                       const Item *__restrict__ items, const double *__restrict__ rec,
-                                                       double *__restrict__ partial,
-                                                       unsigned long long *__restrict__ executed)
+struct PolicyF64 {
+  typedef TileSmem Smem;
+  typedef d4 Acc[4][6];
+  static __device__ void init(Smem &sm) { fill_tables(sm.tab); }
+  static __device__ void zero(Acc &acc)
+  {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  static __device__ void batch(const GridGeom &g, const double *rec, Smem &sm, int cnt, const int tc[3], Acc &acc,
+                               double)
+  {
+    grid_batch(g, rec, sm, cnt, tc, acc);
+  }
+  // result register r of lane holds D[lane/16 + 4r][lane % 16] (row: x index i; column: z index l)
+  static __device__ void store(const Acc &acc, double *P, double)
+  {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int j = 4 * w + rb;
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) {
+        const int u = cb / 3, c = cb % 3;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = (lane >> 4) + 4 * r, l = lane & 15;
+          P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = acc[rb][cb][r];
+        }
+      }
+    }
+  }
+};
+
+// ------------------------------------------------------ mixed precision --
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+constexpr double INV_2PI = 0.15915494309189535;
+constexpr double LOG2E = 1.4426950408889634;
+
+struct MxSmem : ListSmem {
+  float2 Ex[NB][T], Ey[NB][T], V[NB][3][T];
+};
+
+// Window-masked 1-D factors in FP32 from FP64 arguments: the Gaussian
+// exponent and the phase (in revolutions, reduced to [-1/2, 1/2]) are formed
+// in FP64; exp2 and sin/cos of 2 pi r run on the FP32 transcendental unit.
+// V = (W / wmax) Ez.
+__device__ __forceinline__ void mx_factors(const GridGeom &g, const double *__restrict__ rec, MxSmem &sm, int cnt,
+                                           const int tc[3], double iws)
 {
-  __shared__ TileSmem sm;
-  fill_tables(sm.tab);
+  const int tid = threadIdx.x;
+  const double hieps = 0.5 / g.eps;
+  for (int e = tid; e < NB * 12; e += 256) {
+    const int jb = e / 12, f = e % 12;
+    sm.brec[jb][f] = jb < cnt ? rec[(int64_t)sm.list[jb] * 12 + f] : (f < 3 ? -1.0e300 : 0.0);
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * 3 * T; e += 256) {
+    const int jb = e / (3 * T), d = (e / T) % 3, ii = e % T;
+    const double x = axis_coord(g, d, T * tc[d] + ii);
+    const double u = x - sm.brec[jb][d];
+    // balance a small |W| between the two operands by an exact power of two
+    // (Ex scaled by 2^kb, V by 2^-kb, |W| / wmax ~ 2^(2 kb)), so that neither
+    // leaves the normal range of a 16-bit type sooner than it must
+    double wm = 0.0;
+#pragma unroll
+    for (int f = 6; f < 12; ++f) wm = fmax(wm, fabs(sm.brec[jb][f]));
+    wm *= iws;
+    const int kb = wm > 0.0 ? ilogb(wm) / 2 : 0;
+    float2 E = make_float2(0.0f, 0.0f);
+    if (fabs(u) <= g.R) {
+      const double rev = sm.brec[jb][3 + d] * u * INV_2PI;
+      const float r = (float)(rev - rint(rev));
+      const float amp = __builtin_amdgcn_exp2f((float)(-(u * u * hieps) * LOG2E));
+      E = make_float2(amp * __builtin_amdgcn_cosf(r), amp * __builtin_amdgcn_sinf(r));
+    }
+    if (d == 0) sm.Ex[jb][ii] = make_float2(ldexpf(E.x, kb), ldexpf(E.y, kb));
+    else if (d == 1) sm.Ey[jb][ii] = E;
+    else
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float wr = (float)ldexp(sm.brec[jb][6 + 2 * c] * iws, -kb);
+        const float wi = (float)ldexp(sm.brec[jb][7 + 2 * c] * iws, -kb);
+        sm.V[jb][c][ii] = make_float2(wr * E.x - wi * E.y, wr * E.y + wi * E.x);
+      }
+  }
+  __syncthreads();
+}
+
+template <int PREC> struct PolicyMx {
+  typedef MxSmem Smem;
+  typedef f4 Acc[4][6];
+  static __device__ void init(Smem &) {}
+  static __device__ void zero(Acc &acc)
+  {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  template <class V8, class S> static __device__ void split(const float (&x)[8], V8 &hi, V8 &lo)
+  {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const S h = (S)x[i];
+      hi[i] = h;
+      lo[i] = (S)(x[i] - (float)h);
+    }
+  }
+  static __device__ void batch(const GridGeom &g, const double *rec, Smem &sm, int cnt, const int tc[3], Acc &acc,
+                               double iws)
+  {
+    mx_factors(g, rec, sm, cnt, tc, iws);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, kq = lane >> 4;
+    if constexpr (PREC == FGA_FP32) {
+      // K = 4 per instruction: 2 beams x (re, im); lane holds A[i = li][k = kq], B[k = kq][l = li]
+      const int part = kq & 1;
+      const int nks = (cnt + 1) / 2;
+      for (int ks = 0; ks < nks; ++ks) {
+        const int jb = 2 * ks + (kq >> 1);
+        const float2 xv = sm.Ex[jb][li];
+        float a[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          const float2 yv = sm.Ey[jb][4 * w + rb];
+          a[rb] = part ? xv.x * yv.y + xv.y * yv.x : xv.x * yv.x - xv.y * yv.y;
+        }
+        float b[6];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float2 v = sm.V[jb][c][li];
+          b[c] = part ? -v.y : v.x;
+          b[3 + c] = part ? v.x : v.y;
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 6; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+      }
+    } else {
+      // K = 32 per instruction: the 16 beams of the batch x (re, im); lane
+      // holds A[i = li][k = 8 kq + t] and B[k = 8 kq + t][l = li], t < 8,
+      // k = 2 beam + part
+      typedef typename std::conditional<PREC == FGA_BF16X3, bf8, h8>::type V8;
+      typedef typename std::conditional<PREC == FGA_BF16X3, __bf16, _Float16>::type S;
+      V8 ahi[4], alo[4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        float x[8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int jb = 4 * kq + t;
+          const float2 xv = sm.Ex[jb][li], yv = sm.Ey[jb][4 * w + rb];
+          x[2 * t] = xv.x * yv.x - xv.y * yv.y;
+          x[2 * t + 1] = xv.x * yv.y + xv.y * yv.x;
+        }
+        split<V8, S>(x, ahi[rb], alo[rb]);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) {
+        const int c = cb % 3;
+        float x[8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float2 v = sm.V[4 * kq + t][c][li];
+          x[2 * t] = cb < 3 ? v.x : v.y;       // part 0 (Re X rows)
+          x[2 * t + 1] = cb < 3 ? -v.y : v.x;  // part 1 (Im X rows)
+        }
+        V8 bhi, blo;
+        split<V8, S>(x, bhi, blo);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          if constexpr (PREC == FGA_BF16X3) {
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
+          } else {
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // result register r of lane holds D[4 (lane/16) + r][lane % 16]; scaled back by wmax
+  static __device__ void store(const Acc &acc, double *P, double ws)
+  {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int j = 4 * w + rb;
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) {
+        const int u = cb / 3, c = cb % 3;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * (lane >> 4) + r, l = lane & 15;
+          P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = (double)acc[rb][cb][r] * ws;
+        }
+      }
+    }
+  }
+};
+
+template <class Pol>
+__global__ __launch_bounds__(256) void k_grid_tile(GridGeom g, const int64_t *__restrict__ start,
+                                                   const Item *__restrict__ items, const double *__restrict__ rec,
+                                                   double *__restrict__ partial, unsigned long long *__restrict__ executed,
+                                                   const unsigned long long *__restrict__ wmax)
+{
+  __shared__ typename Pol::Smem sm;
+  Pol::init(sm);
+  const double ws = wmax ? __longlong_as_double((long long)*wmax) : 1.0;
+  const double iws = ws > 0.0 ? 1.0 / ws : 0.0;
   const Item it = items[blockIdx.x];
   const int t = it.tile;
   const int tc[3] = {t % g.nt[0], (t / g.nt[0]) % g.nt[1], t / (g.nt[0] * g.nt[1])};
@@ -279,11 +513,8 @@ __global__ __launch_bounds__(256) void k_grid_tile_f64(GridGeom g, const int64_t
   }
   __syncthreads();
 
-  d4 acc[4][6];
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+  typename Pol::Acc acc;
+  Pol::zero(acc);
 
   unsigned long long nexec = 0;
   for (int64_t c0 = it.k0; c0 < it.k1; c0 += 256) {
@@ -312,7 +543,7 @@ __global__ __launch_bounds__(256) void k_grid_tile_f64(GridGeom g, const int64_t
     __syncthreads();
     int ln = base + tot;
     while (ln >= NB) {
-      grid_batch(g, rec, sm, NB, tc, acc);
+      Pol::batch(g, rec, sm, NB, tc, acc, iws);
       nexec += NB;
       const int32_t v = tid + NB < ln ? sm.list[tid + NB] : 0;
       __syncthreads();
@@ -324,26 +555,12 @@ __global__ __launch_bounds__(256) void k_grid_tile_f64(GridGeom g, const int64_t
   }
   if (sm.listn > 0) {
     const int cnt = sm.listn;
-    grid_batch(g, rec, sm, cnt, tc, acc);
+    Pol::batch(g, rec, sm, cnt, tc, acc, iws);
     nexec += cnt;
   }
   if (tid == 0 && executed && nexec) atomicAdd(executed, nexec);
-  // partial tile [c][l][j][i] complex.  Result register r of lane holds
-  // D[lane/16 + 4r][lane % 16] (row: x index i; column: z index l).
-  double *P = partial + (int64_t)blockIdx.x * (3 * T * T * T * 2);
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb) {
-    const int j = 4 * w + rb;
-#pragma unroll
-    for (int cb = 0; cb < 6; ++cb) {
-      const int u = cb / 3, c = cb % 3;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = (lane >> 4) + 4 * r, l = lane & 15;
-        P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = acc[rb][cb][r];
-      }
-    }
-  }
+  // partial tile [c][l][j][i] complex
+  Pol::store(acc, partial + (int64_t)blockIdx.x * (3 * T * T * T * 2), ws);
 }
 
 // out[c][z][y][x] = sum of the tile's partials (fixed item order); points
@@ -393,7 +610,8 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
                          const double h[3], int precision, double *out, Arena &ar, hipStream_t st, bool size_only,
                          size_t *need, int64_t *evals_out)
 {
-  if (precision != FGA_FP64) return fail(FGA_EUNSUPPORTED, "grid summation precision %d not built yet", precision);
+  if (precision != FGA_FP64 && precision != FGA_FP32 && precision != FGA_BF16X3 && precision != FGA_FP16X3)
+    return fail(FGA_EINVAL, "unknown grid summation precision %d", precision);
   const GridGeom g = make_geom(n, lo, h, eps, tau);
   if ((2 * g.reach[1] + 1) * (2 * g.reach[2] + 1) > MAXR)
     return fail(FGA_EUNSUPPORTED, "window reach %d x %d tiles exceeds the supported %d runs per tile", g.reach[1],
@@ -410,7 +628,7 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
   int64_t *tcount = ar.take<int64_t>(ntile);
   Item *items = ar.take<Item>(max_items);
   int32_t *first = ar.take<int32_t>(ntile), *nitems = ar.take<int32_t>(ntile);
-  unsigned long long *ev = ar.take<unsigned long long>(2);
+  unsigned long long *ev = ar.take<unsigned long long>(3);  // evals, executed, max |W| bits
   double *partial = ar.take<double>((size_t)max_items * 3 * T * T * T * 2);
   double *rec = ar.take<double>((size_t)12 * (nb + 1));
   size_t sort_bytes = 0;
@@ -427,14 +645,14 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
     return fail(FGA_ENOMEM, "grid summation workspace too small (%zu bytes given)", ar.size);
   if (nb > 0x7fffffff) return fail(FGA_EUNSUPPORTED, "more than 2^31 beams in one grid summation");
 
-  FGA_HIP(hipMemsetAsync(ev, 0, 2 * sizeof(unsigned long long), st));
+  FGA_HIP(hipMemsetAsync(ev, 0, 3 * sizeof(unsigned long long), st));
   if (nb > 0) {
     hipLaunchKernelGGL(k_bin_keys, (unsigned)((nb + 255) / 256), 256, 0, st, b->f64, b->i32, b->capacity, nb, g,
                        keys, vals, ev);
     FGA_LAUNCH_CHECK();
     FGA_HIP(hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, keys, keys2, vals, vals2, (int)nb, 0, 31, st));
     hipLaunchKernelGGL(k_grid_records, (unsigned)((nb + 255) / 256), 256, 0, st, b->f64, b->i32, b->capacity, keys2,
-                       vals2, nb, 1.0 / eps, rec);
+                       vals2, nb, 1.0 / eps, rec, precision == FGA_FP64 ? nullptr : ev + 2);
     FGA_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_cell_start, (unsigned)((ncells + 1 + 255) / 256), 256, 0, st, keys2, nb, (int32_t)ncells,
@@ -469,7 +687,24 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
   FGA_HIP(hipMemcpyAsync(nitems, hn.data(), ntile * sizeof(int32_t), hipMemcpyHostToDevice, st));
   if (!hi.empty()) {
     ProfScope prof(FGA_K_GRID_TILE, st);
-    hipLaunchKernelGGL(k_grid_tile_f64, (unsigned)hi.size(), 256, 0, st, g, start, items, rec, partial, ev + 1);
+    const unsigned nwg = (unsigned)hi.size();
+    switch (precision) {
+      case FGA_FP64:
+        hipLaunchKernelGGL(k_grid_tile<PolicyF64>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1, nullptr);
+        break;
+      case FGA_FP32:
+        hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_FP32>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
+                           ev + 2);
+        break;
+      case FGA_BF16X3:
+        hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_BF16X3>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
+                           ev + 2);
+        break;
+      default:
+        hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_FP16X3>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
+                           ev + 2);
+        break;
+    }
     FGA_LAUNCH_CHECK();
   }
   const int64_t plane = (int64_t)n[0] * n[1] * n[2];

@@ -250,6 +250,29 @@ def test_grid_parity(n, tau):
     assert rel_l2(ug, uo) <= RTOL
 
 
+@pytest.mark.parametrize("prec", ["FGA_FP32", "FGA_BF16X3", "FGA_FP16X3"])
+def test_grid_mixed_precision(prec):
+    """Mixed-precision tile GEMMs (FP32 factors from FP64-reduced arguments,
+    FP32 accumulation; hi+lo split operands for BF16/FP16) against the
+    oracle's FP64 direct sum: relative L2 <= 1e-3, exact in-window count."""
+    m = fga()
+    say("grid mixed", prec)
+    w = small_c1(nq=5, np_=3, ny=16)
+    ob = evolved_beams(w, 30, 0.005)
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    grid = fi.cell_centred(37, -0.1, 1.1)
+    tau = 16.0
+    ug, cg = m.fga_reconstruct_grid(bs, w.eps, tau, grid, precision=getattr(m, prec))
+    uo, co = om.sum_points(ob, grid.points(), w.eps, tau)
+    assert cg == co
+    err = rel_l2(m.to_complex(ug).reshape(3, -1).T, uo)
+    say("  rel L2", err)
+    assert err <= 1e-3
+    if prec != "FGA_FP16X3":
+        assert err <= 1e-4   # FP32 factors and 16-bit hi+lo splits carry ~1e-5
+
+
 def test_seismogram_parity():
     """Receivers sampled after every step during the evolution."""
     m = fga()
