@@ -84,6 +84,15 @@ def lib():
         L.om_amplitude_vectors.argtypes = [vp, C.c_int64, vp]
         L.om_reframe_many.argtypes = [vp, C.c_int64]
         L.om_rk4_step.argtypes = [vp, vp, C.c_double]
+        L.om_evolve_layered.restype = C.c_int64
+        L.om_evolve_layered.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_double,
+                                        vp]
+        L.om_interface_modes.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, vp, vp, vp]
+        L.om_interface_jacobians.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, vp, vp]
+        L.om_child_lineage.restype = C.c_int64
+        L.om_child_lineage.argtypes = [C.c_int64, C.c_int, C.c_int]
+        L.om_layer_exit.restype = C.c_int
+        L.om_layer_exit.argtypes = [vp, C.c_int, vp, vp, vp]
         L.om_medium_size.restype = C.c_size_t
         if L.om_medium_size() != C.sizeof(Medium):
             raise RuntimeError("oracle medium layout mismatch")
@@ -245,6 +254,53 @@ def evolve(med: OracleMedium, beams: np.ndarray, dt: float, nsteps: int) -> None
     """Advance beams in place by nsteps classic RK4 steps."""
     assert beams.dtype == BEAM_DTYPE and beams.flags.c_contiguous
     lib().om_evolve(med.ref, _p(beams), beams.shape[0], dt, nsteps)
+
+
+def evolve_layered(med: OracleMedium, beams: np.ndarray, dt: float, nsteps: int, gmax: int = 3,
+                   child_cut: float = 1e-3, capacity: int = None):
+    """Advance beams by nsteps RK4 steps in a layered medium, splitting beams
+    at interfaces.  Returns (beam array holding parents and children; retired
+    beams have alive = 0, number of beams retired at the generation cap)."""
+    n = beams.shape[0]
+    cap = capacity if capacity is not None else max(16, 8 * n)
+    buf = np.zeros(cap, dtype=BEAM_DTYPE)
+    buf[:n] = beams
+    ncap = C.c_int64(0)
+    m = lib().om_evolve_layered(med.ref, _p(buf), n, cap, dt, nsteps, gmax, child_cut, C.byref(ncap))
+    if m < 0:
+        raise RuntimeError("beam capacity %d exceeded" % cap)
+    return buf[:m].copy(), int(ncap.value)
+
+
+# interface mode record, as filled by om_interface_modes
+MODE_DTYPE = np.dtype([("exists", np.int32), ("sp", np.int32), ("side", np.int32), ("P", np.float64, 3),
+                       ("A", np.complex128, 3)], align=True)
+
+
+def interface_modes(med: OracleMedium, layer: int, new_layer: int, normal, sp_in: int, P, A):
+    """Snell / elastic boundary problem at one interface point: returns the
+    4 outgoing modes (P reflected, S reflected, P transmitted, S transmitted)."""
+    out = np.zeros(4, dtype=MODE_DTYPE)
+    n = np.ascontiguousarray(normal, dtype=np.float64)
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    lib().om_interface_modes(med.ref, layer, new_layer, _p(n), sp_in, _p(P), _p(A), _p(out))
+    return out
+
+
+def interface_jacobians(normal, Pin, Pout, c_in, c_out, ZQ, ZP, grad_in=(0, 0, 0), grad_out=(0, 0, 0)):
+    """Map (dzQ, dzP) across an interface to one outgoing mode."""
+    ZQ = np.array(ZQ, dtype=np.complex128, order="C")
+    ZP = np.array(ZP, dtype=np.complex128, order="C")
+    args = [np.ascontiguousarray(v, dtype=np.float64) for v in (normal, Pin, Pout)]
+    g = [np.ascontiguousarray(v, dtype=np.float64) for v in (grad_in, grad_out)]
+    lib().om_interface_jacobians(_p(args[0]), _p(args[1]), _p(args[2]), c_in, c_out, _p(g[0]), _p(g[1]),
+                                 _p(ZQ), _p(ZP))
+    return ZQ, ZP
+
+
+def child_lineage(parent: int, gen: int, k: int) -> int:
+    return int(lib().om_child_lineage(parent, gen, k))
 
 
 def rhs(med: OracleMedium, beam: np.ndarray) -> np.ndarray:

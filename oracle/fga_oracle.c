@@ -599,6 +599,357 @@ int64_t om_sum_points(const om_beam *beams, int64_t nb, const double *x, int64_t
   return count;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Interfaces (Sec. 3.1, eq:p:int, eq:Yilmaz, eq:Inter_DzQDzP)               */
+/* ------------------------------------------------------------------------ */
+
+/* If Q lies outside layer L, report the interface crossed and the layer on
+ * its far side; returns 0 when Q is inside L (points on an interface count
+ * as inside).  Flat media: interface i is z = bound[i] between layer i
+ * (below) and i+1 (above).  Spherical media: interface i is |x| = bound[i]
+ * between layer i (outside) and i+1 (inside). */
+int om_layer_exit(const om_medium *m, int L, const double Q[3], int *iface, int *newL)
+{
+  if (m->kind != OM_LAYERED) return 0;
+  const double v = m->geometry == 1 ? sqrt(dot3(Q, Q)) : Q[2];
+  const int nl = m->nlayer;
+  if (m->geometry == 1) {
+    if (L < nl - 1 && v < m->bound[L]) { *iface = L; *newL = L + 1; return 1; }
+    if (L > 0 && v > m->bound[L - 1]) { *iface = L - 1; *newL = L - 1; return 1; }
+  } else {
+    if (L < nl - 1 && v > m->bound[L]) { *iface = L; *newL = L + 1; return 1; }
+    if (L > 0 && v < m->bound[L - 1]) { *iface = L - 1; *newL = L - 1; return 1; }
+  }
+  return 0;
+}
+
+/* Fraction theta in [0, 1] of the straight segment Q0 -> Q1 at which it meets
+ * interface `iface` (layers are homogeneous, so a ray inside one is a
+ * straight line and an RK4 step moves Q along it exactly). */
+double om_crossing_fraction(const om_medium *m, int iface, const double Q0[3], const double Q1[3])
+{
+  const double r = m->bound[iface];
+  double th;
+  if (m->geometry == 1) {
+    /* |Q0 + th D| = r: a th^2 + 2 b th + c = 0; the root where the segment
+       first meets the sphere */
+    double D[3] = {Q1[0] - Q0[0], Q1[1] - Q0[1], Q1[2] - Q0[2]};
+    const double a = dot3(D, D), b = dot3(Q0, D), c = dot3(Q0, Q0) - r * r;
+    double disc = b * b - a * c;
+    if (disc < 0.0) disc = 0.0;
+    const double sq = sqrt(disc);
+    /* c > 0: Q0 outside, entering; c <= 0: Q0 inside, leaving */
+    th = c > 0.0 ? (-b - sq) / a : (-b + sq) / a;
+  } else {
+    th = (r - Q0[2]) / (Q1[2] - Q0[2]);
+  }
+  return th < 0.0 ? 0.0 : (th > 1.0 ? 1.0 : th);
+}
+
+/* Complex linear solve A x = b (n <= 4) by Gaussian elimination with partial
+ * pivoting; A and b are overwritten. */
+static void csolve_n(int n, cplx A[4][4], cplx b[4], cplx x[4])
+{
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (cabs(A[r][col]) > cabs(A[piv][col])) piv = r;
+    if (piv != col) {
+      for (int j = 0; j < n; ++j) { cplx t = A[col][j]; A[col][j] = A[piv][j]; A[piv][j] = t; }
+      cplx t = b[col]; b[col] = b[piv]; b[piv] = t;
+    }
+    for (int r = col + 1; r < n; ++r) {
+      cplx f = A[r][col] / A[col][col];
+      for (int j = col; j < n; ++j) A[r][j] -= f * A[col][j];
+      b[r] -= f * b[col];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    cplx s = b[r];
+    for (int j = r + 1; j < n; ++j) s -= A[r][j] * x[j];
+    x[r] = s / A[r][r];
+  }
+}
+
+/* One outgoing plane-wave mode at the interface. */
+typedef struct {
+  int exists;     /* propagating (not evanescent)                          */
+  int sp;         /* 0 = P, 1 = S                                          */
+  int side;       /* 0 = reflected (incident layer), 1 = transmitted       */
+  double P[3];    /* momentum (global frame)                               */
+  cplx A[3];      /* displacement amplitude vector (global frame)          */
+} om_mode;
+
+/* Snell's law and the elastic transmission/reflection problem for a plane
+ * wave with momentum Pin and complex displacement amplitude vector Ain
+ * (polarised along Pin for sp_in = 0, orthogonal to it for sp_in = 1)
+ * arriving from layer L at an interface with unit normal n (pointing into
+ * the transmission layer newL).
+ *   Snell (eq:p:int): every outgoing mode keeps the tangential momentum and
+ *   the frequency H = c_in |Pin|, so |P_out| = H / c_out; transmitted modes
+ *   keep the sign of the normal component, reflected modes flip it.  A mode
+ *   whose normal component would be imaginary is evanescent: it enters the
+ *   boundary problem with the decaying imaginary normal component but is not
+ *   returned as a beam (the paper is silent on post-critical incidence).
+ *   Amplitudes: the paper's printed Zoeppritz system (eq:Yilmaz) is for
+ *   potentials and has a misprint in its last right-hand-side entry; here
+ *   the same physics is solved directly for displacements: continuity of the
+ *   displacement u and of the traction sigma.n across the interface, with
+ *   sigma_ij = lambda div(u) delta_ij + mu (d_i u_j + d_j u_i), lambda =
+ *   rho (c_P^2 - 2 c_S^2), mu = rho c_S^2, for plane waves u = A d exp(i k.x/eps)
+ *   with k = P (the common factor i/eps drops out).  P modes are polarised
+ *   along k/|k|, in-plane S modes along e2 x k/|k| and SH modes along e2,
+ *   in the local frame e3 = n, e1 = tangential momentum direction,
+ *   e2 = e3 x e1.
+ * out[0..3] = (P reflected, S reflected, P transmitted, S transmitted). */
+void om_interface_modes(const om_medium *m, int L, int newL, const double n[3], int sp_in, const double Pin[3],
+                        const cplx Ain[3], om_mode out[4])
+{
+  const double c_in = sp_in == 0 ? m->cpl[L] : m->csl[L];
+  const double H = c_in * sqrt(dot3(Pin, Pin));
+  const double pn = dot3(Pin, n);
+  double pt[3] = {Pin[0] - pn * n[0], Pin[1] - pn * n[1], Pin[2] - pn * n[2]};
+  const double p1 = sqrt(dot3(pt, pt));
+  double e1[3], e2[3];
+  if (p1 > 1e-12 * sqrt(dot3(Pin, Pin))) {
+    for (int i = 0; i < 3; ++i) e1[i] = pt[i] / p1;
+  } else {
+    /* normal incidence: any tangent direction (the problem is symmetric) */
+    double t[3] = {1.0, 0.0, 0.0};
+    if (fabs(n[0]) > 0.9) { t[0] = 0.0; t[1] = 1.0; }
+    const double tn = dot3(t, n);
+    for (int i = 0; i < 3; ++i) t[i] -= tn * n[i];
+    const double nt = sqrt(dot3(t, t));
+    for (int i = 0; i < 3; ++i) e1[i] = t[i] / nt;
+  }
+  cross3(n, e1, e2);
+  const double sgn = pn >= 0.0 ? 1.0 : -1.0;
+  /* media of the two sides */
+  const double rho[2] = {m->rhol[L], m->rhol[newL]};
+  const double cP[2] = {m->cpl[L], m->cpl[newL]}, cS[2] = {m->csl[L], m->csl[newL]};
+  double lam[2], mu[2];
+  for (int s = 0; s < 2; ++s) {
+    mu[s] = rho[s] * cS[s] * cS[s];
+    lam[s] = rho[s] * (cP[s] * cP[s] - 2.0 * cS[s] * cS[s]);
+  }
+  /* local (k1, k3) and polarisations (d1, d2, d3) of the four outgoing modes
+     and of the incident one */
+  cplx k3[5], d1[5], d3[5];
+  double kk[5];
+  int side[5], exists[5];
+  const double p1l = p1 > 1e-12 * sqrt(dot3(Pin, Pin)) ? p1 : 0.0;
+  for (int mo = 0; mo < 4; ++mo) {
+    const int sp = mo & 1, sd = mo >> 1;
+    const double c = sp == 0 ? cP[sd] : cS[sd];
+    const double kabs = H / c;
+    const double rad = kabs * kabs - p1l * p1l;
+    const double dir = sd == 1 ? sgn : -sgn;  /* transmitted keep the sign */
+    kk[mo] = kabs;
+    side[mo] = sd;
+    if (rad >= 0.0) {
+      k3[mo] = dir * sqrt(rad);
+      exists[mo] = 1;
+    } else {
+      /* decays away from the interface on its own side (x3 > 0 transmitted) */
+      k3[mo] = (sd == 1 ? 1.0 : -1.0) * I * sqrt(-rad);
+      exists[mo] = 0;
+    }
+  }
+  kk[4] = H / c_in;
+  k3[4] = pn;
+  side[4] = 0;
+  exists[4] = 1;
+  for (int mo = 0; mo < 5; ++mo) {
+    const int sp = mo == 4 ? sp_in : (mo & 1);
+    const cplx h1 = p1l / kk[mo], h3 = k3[mo] / kk[mo]; /* k / |k| */
+    if (sp == 0) { d1[mo] = h1; d3[mo] = h3; }
+    else { d1[mo] = h3; d3[mo] = -h1; } /* e2 x khat */
+  }
+  /* incident amplitude in the local frame: along khat (P) or split into the
+     in-plane and SH parts (S) */
+  const cplx A1 = Ain[0] * e1[0] + Ain[1] * e1[1] + Ain[2] * e1[2];
+  const cplx A2 = Ain[0] * e2[0] + Ain[1] * e2[1] + Ain[2] * e2[2];
+  const cplx A3 = Ain[0] * n[0] + Ain[1] * n[1] + Ain[2] * n[2];
+  const cplx a_inplane = A1 * d1[4] + A3 * d3[4];
+  const cplx a_sh = sp_in == 0 ? 0.0 : A2;
+  /* P-SV system: rows u1, u3, t1, t3; columns R_P, R_S, T_P, T_S */
+  cplx M[4][4], b[4], x[4];
+  for (int mo = 0; mo < 5; ++mo) {
+    const int sd = side[mo];
+    const cplx k1 = p1l;
+    const cplx kd = k1 * d1[mo] + k3[mo] * d3[mo];
+    const cplx col[4] = {d1[mo], d3[mo], mu[sd] * (k1 * d3[mo] + k3[mo] * d1[mo]),
+                         lam[sd] * kd + 2.0 * mu[sd] * k3[mo] * d3[mo]};
+    for (int r = 0; r < 4; ++r) {
+      if (mo == 4) b[r] = -a_inplane * col[r];
+      else M[r][mo] = sd == 0 ? col[r] : -col[r];
+    }
+  }
+  csolve_n(4, M, b, x);
+  /* SH system: rows u2, t2; columns R_SH, T_SH (polarisation e2 for all) */
+  cplx y[2] = {0.0, 0.0};
+  if (sp_in == 1) {
+    cplx Ms[4][4], bs[4], xs[4];
+    Ms[0][0] = 1.0;
+    Ms[0][1] = -1.0;
+    Ms[1][0] = mu[0] * k3[1];
+    Ms[1][1] = -mu[1] * k3[3];
+    bs[0] = -a_sh;
+    bs[1] = -a_sh * mu[0] * k3[4];
+    csolve_n(2, Ms, bs, xs);
+    y[0] = xs[0];
+    y[1] = xs[1];
+  }
+  for (int mo = 0; mo < 4; ++mo) {
+    om_mode *o = &out[mo];
+    o->sp = mo & 1;
+    o->side = side[mo];
+    o->exists = exists[mo];
+    const double k3r = creal(k3[mo]);
+    for (int i = 0; i < 3; ++i) o->P[i] = p1l * e1[i] + k3r * n[i];
+    const cplx ain = x[mo];
+    const cplx ash = o->sp == 1 ? y[mo >> 1] : 0.0;
+    for (int i = 0; i < 3; ++i) o->A[i] = ain * (d1[mo] * e1[i] + d3[mo] * n[i]) + ash * e2[i];
+  }
+}
+
+/* Lineage number of child k (0..3: P reflected, S reflected, P transmitted,
+ * S transmitted) of a beam: generation in the top bits, then the parent's
+ * path shifted by two bits. */
+int64_t om_child_lineage(int64_t parent, int gen_parent, int k)
+{
+  const int64_t path = parent & ((INT64_C(1) << 58) - 1);
+  return ((int64_t)(gen_parent + 1) << 58) | (path << 2) | k;
+}
+
+/* Map of the state of a beam at an interface point to one outgoing mode
+ * (eq:Inter_DzQDzP): with n the unit normal, p_n = Pin.n, p_n' = Pout.n and
+ * kappa = (c_out / c_in)^2,
+ *   dzQ' = dzQ F,  F = I + n (x) v,  v = (kappa - 1) p_t / p_n + (kappa p_n'/p_n - 1) n
+ *   dzP' = dzP W - |Pout| / (c_out p_n') (dzQ' grad c_out - dzQ grad c_in) (x) n,
+ *   W = F^{-T} = I - v (x) n / (kappa p_n' / p_n)
+ * (the printed 3x3 F written in any frame whose third axis is n; rows of dzQ
+ * are the z-derivatives, columns the spatial components). */
+void om_interface_jacobians(const double n[3], const double Pin[3], const double Pout[3], double c_in, double c_out,
+                            const double gin[3], const double gout[3], cplx ZQ[3][3], cplx ZP[3][3])
+{
+  const double pn = dot3(Pin, n), pno = dot3(Pout, n);
+  const double kap = (c_out / c_in) * (c_out / c_in);
+  double v[3];
+  for (int i = 0; i < 3; ++i) v[i] = (kap - 1.0) * (Pin[i] - pn * n[i]) / pn + (kap * pno / pn - 1.0) * n[i];
+  const double den = kap * pno / pn;
+  cplx ZQo[3][3], ZPo[3][3];
+  for (int mrow = 0; mrow < 3; ++mrow) {
+    cplx qn = 0.0, pv = 0.0;
+    for (int i = 0; i < 3; ++i) { qn += ZQ[mrow][i] * n[i]; pv += ZP[mrow][i] * v[i]; }
+    for (int j = 0; j < 3; ++j) {
+      ZQo[mrow][j] = ZQ[mrow][j] + qn * v[j];
+      ZPo[mrow][j] = ZP[mrow][j] - pv / den * n[j];
+    }
+  }
+  const double f = sqrt(dot3(Pout, Pout)) / (c_out * pno);
+  for (int mrow = 0; mrow < 3; ++mrow) {
+    cplx g = 0.0;
+    for (int i = 0; i < 3; ++i) g += ZQo[mrow][i] * gout[i] - ZQ[mrow][i] * gin[i];
+    for (int j = 0; j < 3; ++j) ZPo[mrow][j] -= f * g * n[j];
+  }
+  memcpy(ZQ, ZQo, sizeof(ZQo));
+  memcpy(ZP, ZPo, sizeof(ZPo));
+}
+
+/* Advance n beams (array capacity cap) by nsteps RK4 steps in a layered
+ * medium with interfaces.  After each step a beam whose centre has left its
+ * layer is split: it is moved back to the start of the step and advanced by
+ * theta dt to the crossing (theta from the straight ray), Q is put exactly on
+ * the interface, and each propagating outgoing mode whose amplitude is at
+ * least child_cut times the incident one becomes a child beam (lineage from
+ * om_child_lineage, generation + 1, the parent's weight, sigma and action),
+ * which then takes the remaining (1 - theta) dt in its own layer.  The parent
+ * is retired.  A beam already at generation gmax is retired at an interface
+ * without children.  Children are appended in parent order; beams appended
+ * during a step are not stepped again in it.  Returns the new beam count, or
+ * -1 if the capacity would be exceeded (then the beam set is partly
+ * updated).  *capped receives the number of beams retired at the cap. */
+int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t cap, double dt, int nsteps,
+                          int gmax, double child_cut, int64_t *capped)
+{
+  int64_t ncap = 0;
+  for (int s = 0; s < nsteps; ++s) {
+    const int64_t n0 = n;
+    for (int64_t i = 0; i < n0; ++i) {
+      om_beam *b = &beams[i];
+      if (!b->alive) continue;
+      om_beam y0 = *b;
+      om_rk4_step(m, b, dt);
+      int iface, newL;
+      if (!om_layer_exit(m, y0.layer, b->Q, &iface, &newL)) {
+        om_reframe(b);
+        continue;
+      }
+      const double th = om_crossing_fraction(m, iface, y0.Q, b->Q);
+      om_beam x = y0;
+      om_rk4_step(m, &x, th * dt);
+      /* exactly onto the interface */
+      double nrm[3] = {0.0, 0.0, 0.0};
+      if (m->geometry == 1) {
+        const double r = sqrt(dot3(x.Q, x.Q));
+        for (int k = 0; k < 3; ++k) x.Q[k] *= m->bound[iface] / r;
+        for (int k = 0; k < 3; ++k) nrm[k] = (newL > y0.layer ? -1.0 : 1.0) * x.Q[k] / m->bound[iface];
+      } else {
+        x.Q[2] = m->bound[iface];
+        nrm[2] = newL > y0.layer ? 1.0 : -1.0;
+      }
+      b->alive = 0;
+      if (x.gen >= gmax) {
+        ++ncap;
+        continue;
+      }
+      const int sp_in = x.branch == 0 ? 0 : 1;
+      cplx Ain[3];
+      om_amplitude_vector(&x, Ain);
+      const double ain = sqrt(creal(Ain[0] * conj(Ain[0]) + Ain[1] * conj(Ain[1]) + Ain[2] * conj(Ain[2])));
+      om_mode md[4];
+      om_interface_modes(m, y0.layer, newL, nrm, sp_in, x.P, Ain, md);
+      const double c_in = sp_in == 0 ? m->cpl[y0.layer] : m->csl[y0.layer];
+      for (int k = 0; k < 4; ++k) {
+        if (!md[k].exists) continue;
+        const double am = sqrt(creal(md[k].A[0] * conj(md[k].A[0]) + md[k].A[1] * conj(md[k].A[1]) +
+                                     md[k].A[2] * conj(md[k].A[2])));
+        if (!(am >= child_cut * ain)) continue;
+        if (n >= cap) return -1;
+        om_beam c = x;
+        const int lay = md[k].side == 1 ? newL : y0.layer;
+        const double c_out = md[k].sp == 0 ? m->cpl[lay] : m->csl[lay];
+        double gz[3] = {0.0, 0.0, 0.0};
+        memcpy(c.P, md[k].P, sizeof c.P);
+        om_interface_jacobians(nrm, x.P, c.P, c_in, c_out, gz, gz, c.ZQ, c.ZP);
+        c.layer = lay;
+        c.branch = md[k].sp == 0 ? 0 : 2;
+        c.gen = x.gen + 1;
+        c.lineage = om_child_lineage(x.lineage, x.gen, k);
+        c.alive = 1;
+        om_initial_axis(c.P, c.e);
+        if (md[k].sp == 0) {
+          const double np = sqrt(dot3(c.P, c.P));
+          c.a[0] = (md[k].A[0] * c.P[0] + md[k].A[1] * c.P[1] + md[k].A[2] * c.P[2]) / np;
+          c.a[1] = 0.0;
+        } else {
+          double nsh[3], nsv[3];
+          om_s_frame(c.P, c.e, nsh, nsv);
+          c.a[0] = md[k].A[0] * nsv[0] + md[k].A[1] * nsv[1] + md[k].A[2] * nsv[2];
+          c.a[1] = md[k].A[0] * nsh[0] + md[k].A[1] * nsh[1] + md[k].A[2] * nsh[2];
+        }
+        om_rk4_step(m, &c, (1.0 - th) * dt);
+        om_reframe(&c);
+        beams[n++] = c;
+        b = &beams[i];
+      }
+    }
+  }
+  if (capped) *capped = ncap;
+  return n;
+}
+
 /* Batched helpers for the Python wrapper. */
 void om_fbi_many(const cplx *f, const int yn[3], const double ylo[3], const double yh[3],
                  const double *q, const double *p, int64_t n, double eps, cplx *out)
