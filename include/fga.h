@@ -74,12 +74,16 @@ const char *fga_version(void);
  *   W (re, im)         psi * dq * dp * (k/2pi)^{9/2}, the beam's fixed weight
  *   E[3]               reference axis of the S polarisation frame
  *                      N_SH = (E x P)/|E x P|, N_SV = (P/|P|) x N_SH
- * int32 planes: BRANCH (0 P, 1 SH, 2 SV), SIGMA (+1 "+" flow, -1 "-" flow),
- *   LAYER (layered media), GEN (interface generation), FLAGS (bit 0 alive,
- *   bit 1 quarantined: non-finite state).
+ * int32 planes: BRANCH (0 P, 1 SH, 2 SV; beams made at interfaces are 0 or
+ *   2), SIGMA (+1 "+" flow, -1 "-" flow), LAYER (layered media), GEN
+ *   (interface generation), FLAGS (bit 0 alive, bit 1 quarantined: non-finite
+ *   state, bit 2 internal: crossed an interface during the current step).
  * lineage: canonical number ((branch*2 + dir)*Np + ip)*Nq + iq of the mesh
- *   point the beam (or its ancestor) came from; children get
- *   parent*4 + child index + FGA_LINEAGE_CHILD_BASE... (see fga_evolve). */
+ *   point a generation-0 beam came from.  A beam of generation g made at an
+ *   interface as mode k (0 P reflected, 1 S reflected, 2 P transmitted,
+ *   3 S transmitted) of its parent gets
+ *   (g << 58) | ((parent & (2^58 - 1)) << 2) | k
+ *   (FGA_LINEAGE_CHILD), so lineages stay unique and name the path. */
 enum {
   FGA_Q = 0, FGA_P = 3,
   FGA_ZQ_RE = 6, FGA_ZQ_IM = 15, FGA_ZP_RE = 24, FGA_ZP_IM = 33,
@@ -88,7 +92,9 @@ enum {
   FGA_NF64 = 52
 };
 enum { FGA_BRANCH = 0, FGA_SIGMA = 1, FGA_LAYER = 2, FGA_GEN = 3, FGA_FLAGS = 4, FGA_NI32 = 5 };
-enum { FGA_FLAG_ALIVE = 1, FGA_FLAG_QUARANTINED = 2 };
+enum { FGA_FLAG_ALIVE = 1, FGA_FLAG_QUARANTINED = 2, FGA_FLAG_CROSS = 4 };
+#define FGA_LINEAGE_CHILD(parent, gen_parent, k)                                   \
+  ((((int64_t)(gen_parent) + 1) << 58) | (((int64_t)(parent) & ((INT64_C(1) << 58) - 1)) << 2) | (int64_t)(k))
 
 typedef struct {
   int64_t capacity;   /* slots per plane                                         */
@@ -203,6 +209,9 @@ typedef struct {
   int resort;              /* steps between spatial re-orderings of the beam set
                               (0: library default, 16 with receivers, else 64;
                                < 0: never reorder)                                     */
+  int gen_max;             /* layered media: interface generation cap (0: default 3)   */
+  double child_cut;        /* layered media: children with |A_child| < child_cut |A_in|
+                              are not made (0: default 1e-3; < 0: keep all)            */
 } fga_evolve_opts;
 
 typedef struct {
@@ -210,6 +219,9 @@ typedef struct {
   int64_t evals;           /* in-window (beam, receiver, sample) terms summed          */
   int64_t culled;          /* beams dropped by the cutoff                              */
   int64_t quarantined;     /* beams dropped for non-finite state                       */
+  int64_t crossings;       /* interface hits (layered media)                           */
+  int64_t spawned;         /* beams made at interfaces                                 */
+  int64_t capped;          /* beams retired at an interface at the generation cap      */
 } fga_evolve_stats;
 
 size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_evolve_opts *opts,
@@ -228,7 +240,24 @@ size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_
  * box window) into seis: device, complex [rec->n][nsteps/rec->stride][3]
  * (overwritten).  stats (host, may be NULL) receives counters; this call
  * synchronises `stream` when stats != NULL or culling is on.
- * Errors: FGA_EINVAL, FGA_ENOMEM (workspace), FGA_EDEVICE. */
+ * Layered media (Sec. 3.1): the layer is beam state and the speeds are
+ * constant inside a layer, so a ray is straight between interfaces.  After
+ * each step a beam whose centre has left its layer is taken back to the
+ * start of the step, advanced to the crossing point (theta dt, from the
+ * straight ray) and put exactly on the interface; every outgoing mode that
+ * propagates (eq:p:int: tangential momentum and c|P| kept) and whose
+ * displacement amplitude from the elastic boundary problem (continuity of
+ * displacement and traction, the physics of eq:Yilmaz) is at least
+ * opts->child_cut times the incident one becomes a child with the parent's
+ * weight, sigma and action, generation + 1, (dzQ, dzP) mapped by
+ * eq:Inter_DzQDzP in the local tangent-normal frame, and the remaining
+ * (1 - theta) dt in its own layer.  The first child takes the parent's slot,
+ * the others are appended after `count` in a deterministic order; a parent at
+ * the generation cap, or with no child, is retired.  The call then
+ * synchronises `stream` after every step and steps one at a time.  If the
+ * children would not fit in `capacity` the call stops with FGA_ECAPACITY
+ * (nothing is dropped silently; the beam set is then partly advanced).
+ * Errors: FGA_EINVAL, FGA_ENOMEM (workspace), FGA_ECAPACITY, FGA_EDEVICE. */
 fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int nsteps,
                       const fga_evolve_opts *opts, const fga_receivers *rec, double *seis,
                       void *workspace, size_t workspace_bytes, void *stream,

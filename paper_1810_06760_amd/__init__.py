@@ -77,12 +77,12 @@ class ReceiversC(C.Structure):
 
 class EvolveOptsC(C.Structure):
     _fields_ = [("chunk", C.c_int), ("cutoff_abs", C.c_double), ("compact", C.c_int), ("batch", C.c_int64),
-                ("resort", C.c_int)]
+                ("resort", C.c_int), ("gen_max", C.c_int), ("child_cut", C.c_double)]
 
 
 class EvolveStatsC(C.Structure):
     _fields_ = [("beam_steps", C.c_int64), ("evals", C.c_int64), ("culled", C.c_int64),
-                ("quarantined", C.c_int64)]
+                ("quarantined", C.c_int64), ("crossings", C.c_int64), ("spawned", C.c_int64), ("capped", C.c_int64)]
 
 
 def lib():
@@ -92,6 +92,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libfga.so is not built (run python -m paper_1810_06760_amd.build); "
                                "there is no CPU fallback")
+        # torch first: the library then binds to the HIP runtime torch has loaded,
+        # so device memory and streams from torch are valid in it
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i64, sz, st = C.c_void_p, C.c_int64, C.c_size_t, C.c_int
         L.fga_last_error.restype = C.c_char_p
@@ -338,13 +341,16 @@ def fga_decompose(medium: Medium, mesh: MeshC, f, g=None, beams: BeamSet = None,
 
 def fga_evolve(medium: Medium, beams: BeamSet, dt: float, nsteps: int, receivers=None, eps: float = None,
                tau: float = 25.0, stride: int = 1, chunk: int = 0, cutoff_abs: float = 0.0, compact: bool = False,
-               batch: int = 0, precision: int = FGA_FP64, seis=None, ws=None, resort: int = 0):
+               batch: int = 0, precision: int = FGA_FP64, seis=None, ws=None, resort: int = 0, gen_max: int = 0,
+               child_cut: float = 0.0):
     """Step 2.  Returns (seis or None, stats dict).  receivers: (n,3) array;
     seis is complex [n][nsteps/stride][3] as a float64 tensor [n, ns, 3, 2].
-    resort: steps between spatial reorderings (0 default, < 0 never)."""
+    resort: steps between spatial reorderings (0 default, < 0 never).
+    gen_max, child_cut: interface generation cap and child amplitude cut of
+    layered media (0: library defaults 3 and 1e-3; child_cut < 0 keeps all)."""
     torch = _torch()
     L = lib()
-    opts = EvolveOptsC(chunk, cutoff_abs, 1 if compact else 0, batch, resort)
+    opts = EvolveOptsC(chunk, cutoff_abs, 1 if compact else 0, batch, resort, gen_max, child_cut)
     rec = None
     xyz = None
     if receivers is not None:
@@ -360,7 +366,8 @@ def fga_evolve(medium: Medium, beams: BeamSet, dt: float, nsteps: int, receivers
                         C.byref(rec) if rec is not None else None, _ptr(seis), _ptr(ws), ws.numel(), _stream(),
                         C.byref(stats)))
     return seis, {"beam_steps": stats.beam_steps, "evals": stats.evals, "culled": stats.culled,
-                  "quarantined": stats.quarantined}
+                  "quarantined": stats.quarantined, "crossings": stats.crossings, "spawned": stats.spawned,
+                  "capped": stats.capped}
 
 
 def fga_reconstruct_points(beams: BeamSet, eps: float, tau: float, xyz, precision: int = FGA_FP64, out=None,
@@ -404,7 +411,7 @@ def workspace_bytes(kind: str, **kw) -> int:
         return L.fga_decompose_workspace_bytes(C.byref(kw["mesh"]), 1 if kw.get("with_g") else 0)
     if kind == "evolve":
         opts = EvolveOptsC(kw.get("chunk", 0), kw.get("cutoff_abs", 0.0), 1 if kw.get("compact") else 0,
-                           kw.get("batch", 0), kw.get("resort", 0))
+                           kw.get("batch", 0), kw.get("resort", 0), kw.get("gen_max", 0), kw.get("child_cut", 0.0))
         rec = None
         if kw.get("n_receivers"):
             rec = ReceiversC(kw["n_receivers"], 0, kw.get("stride", 1), kw["eps"], kw.get("tau", 25.0),

@@ -114,9 +114,14 @@ fga_status make_dev_medium(const fga_medium *m, DevMedium *o)
       o->bound[l] = m->bound[l];
       o->cpl[l] = m->cpl[l];
       o->csl[l] = m->csl[l];
+      o->rhol[l] = m->rhol[l];
     }
     for (int l = 0; l < m->nlayer; ++l)
-      if (!(m->cpl[l] > 0) || !(m->csl[l] > 0)) return fail(FGA_EINVAL, "layer %d has non-positive speed", l);
+      if (!(m->cpl[l] > 0) || !(m->csl[l] > 0) || !(m->rhol[l] > 0))
+        return fail(FGA_EINVAL, "layer %d has non-positive speed or density", l);
+    for (int l = 0; l + 1 < m->nlayer - 1; ++l)
+      if (m->geometry == 0 ? !(m->bound[l] < m->bound[l + 1]) : !(m->bound[l] > m->bound[l + 1] && m->bound[l + 1] > 0))
+        return fail(FGA_EINVAL, "layer bounds must be increasing (flat) or decreasing and positive (spherical)");
     return FGA_OK;
   default:
     return fail(FGA_EINVAL, "unknown medium kind %d", m->kind);
@@ -305,7 +310,7 @@ EvolvePlan evolve_plan(const fga_beams *b, int nsteps, const fga_evolve_opts *o,
   p.chunk = (o && o->chunk > 0) ? o->chunk : (r ? 16 : 50);
   if (p.chunk > nsteps) p.chunk = nsteps > 0 ? nsteps : 1;
   p.batch = (o && o->batch > 0) ? o->batch : ((int64_t)1 << 22);
-  if (p.batch > b->count) p.batch = b->count > 0 ? b->count : 1;
+  if (p.batch > b->capacity) p.batch = b->capacity > 0 ? b->capacity : 1;
   p.nsamp = r ? nsteps / r->stride : 0;
   p.bpb = r ? points_beams_per_block(p.batch, r->n, (p.chunk + r->stride - 1) / r->stride + 1) : 1024;
   p.resort = (o && o->resort < 0) ? 0 : ((o && o->resort > 0) ? o->resort : (r ? 16 : 64));
@@ -317,12 +322,17 @@ struct EvolveBufs {
   unsigned long long *ctr = nullptr;
   double *emit = nullptr, *partial = nullptr, *xs = nullptr, *box = nullptr;
   int32_t *perm = nullptr;
+  int64_t *blk_extra = nullptr, *blk_off = nullptr, *total = nullptr;  // interface step
 };
 
-EvolveBufs evolve_layout(const EvolvePlan &p, const fga_receivers *r, Arena &ar)
+EvolveBufs evolve_layout(const EvolvePlan &p, const fga_receivers *r, int64_t cap, Arena &ar)
 {
   EvolveBufs b;
-  b.ctr = ar.take<unsigned long long>(4);
+  b.ctr = ar.take<unsigned long long>(8);
+  const int64_t nblk_all = (cap + 255) / 256 + 1;
+  b.blk_extra = ar.take<int64_t>(nblk_all);
+  b.blk_off = ar.take<int64_t>(nblk_all);
+  b.total = ar.take<int64_t>(1);
   if (r) {
     const int m = (p.chunk + r->stride - 1) / r->stride + 1;
     b.emit = ar.take<double>((size_t)m * 12 * p.batch);
@@ -344,10 +354,12 @@ size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_
   if (rec && rec->stride < 1) return 0;
   const EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
   Arena ar(nullptr, 0);
-  evolve_layout(p, rec, ar);
+  evolve_layout(p, rec, beams->capacity, ar);
+  // sized for a full beam set: interface splitting can grow it up to capacity
   if (p.resort > 0) {
     size_t ns = 0;
     fga_beams bb = *beams;
+    bb.count = bb.capacity;
     sort_beams_spatial(&bb, ar, nullptr, true, &ns);
   }
   size_t need = ar.used;
@@ -355,6 +367,7 @@ size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_
     Arena a2(nullptr, 0);
     size_t n2 = 0;
     fga_beams bb = *beams;
+    bb.count = bb.capacity;
     compact_beams(&bb, a2, nullptr, true, &n2);
     need = need > n2 ? need : n2;
   }
@@ -381,18 +394,96 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
   hipStream_t st = (hipStream_t)stream;
   const EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
   Arena ar(workspace, workspace_bytes);
-  const EvolveBufs wb = evolve_layout(p, rec, ar);
+  const EvolveBufs wb = evolve_layout(p, rec, beams->capacity, ar);
   unsigned long long *ctr = wb.ctr;
   double *emit = wb.emit, *partial = wb.partial;
-  if (!ctr || (rec && (!emit || !partial || !wb.box || !wb.xs || !wb.perm)))
+  if (!ctr || !wb.blk_extra || !wb.blk_off || !wb.total ||
+      (rec && (!emit || !partial || !wb.box || !wb.xs || !wb.perm)))
     return fail(FGA_ENOMEM, "evolve workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
   const size_t sort_base = ar.used;
-  FGA_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), st));
+  FGA_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), st));
   if (rec && rec->n > 0 && (s = sort_points(rec->xyz, rec->n, wb.xs, wb.perm, st)) != FGA_OK) return s;
 
   const double cutoff = opts ? opts->cutoff_abs : 0.0;
   int last_sort = -1;
-  for (int s0 = 0; s0 < nsteps; s0 += p.chunk) {
+  if (dm.kind == FGA_MEDIUM_LAYERED) {
+    // one step at a time: integrator, interface split, then the sample
+    const int gen_max = (opts && opts->gen_max > 0) ? opts->gen_max : 3;
+    const double child_cut = (opts && opts->child_cut != 0.0) ? (opts->child_cut < 0.0 ? 0.0 : opts->child_cut) : 1e-3;
+    for (int s0 = 0; s0 < nsteps; ++s0) {
+      if (p.resort > 0 && (last_sort < 0 || s0 - last_sort >= p.resort)) {
+        Arena sa(static_cast<char *>(workspace) + sort_base, workspace_bytes - sort_base);
+        size_t need = 0;
+        if ((s = sort_beams_spatial(beams, sa, st, false, &need)) != FGA_OK) return s;
+        last_sort = s0;
+      }
+      const int64_t n = beams->count;
+      IntegrateArgs a{};
+      a.f64 = beams->f64;
+      a.i32 = beams->i32;
+      a.cap = beams->capacity;
+      a.beg = 0;
+      a.end = n;
+      a.dt = dt;
+      a.nsteps = 1;
+      a.step0 = s0;
+      a.stride = 0;
+      a.eps_emit = 1.0;
+      a.cutoff_abs = s0 + 1 >= nsteps ? cutoff : 0.0;
+      a.counters = ctr;
+      FGA_HIP(launch_integrate(dm, a, st));
+      InterfaceArgs ia{};
+      ia.f64 = beams->f64;
+      ia.i32 = beams->i32;
+      ia.lineage = beams->lineage;
+      ia.cap = beams->capacity;
+      ia.n = n;
+      ia.dt = dt;
+      ia.gen_max = gen_max;
+      ia.child_cut = child_cut;
+      ia.blk_extra = wb.blk_extra;
+      ia.blk_off = wb.blk_off;
+      ia.counters = ctr + 4;
+      if (n > 0) {
+        FGA_HIP(launch_interface(dm, ia, 0, st));
+        FGA_HIP(launch_scan(wb.blk_extra, wb.blk_off, (n + 255) / 256, wb.total, st));
+        int64_t extra = 0;
+        FGA_HIP(hipMemcpyAsync(&extra, wb.total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        FGA_HIP(hipStreamSynchronize(st));
+        if (n + extra > beams->capacity)
+          return fail(FGA_ECAPACITY, "step %d: %lld beams after interface splitting exceed the capacity %lld", s0,
+                      (long long)(n + extra), (long long)beams->capacity);
+        FGA_HIP(launch_interface(dm, ia, 1, st));
+        beams->count = n + extra;
+      }
+      if (rec && (s0 + 1) % rec->stride == 0 && rec->n > 0) {
+        const int sample = (s0 + 1) / rec->stride - 1;
+        const int64_t nb = beams->count;
+        if (nb == 0) FGA_HIP(launch_reduce_points(partial, 0, 1, rec->n, wb.perm, seis, p.nsamp, sample, 0, st));
+        for (int64_t b0 = 0; b0 < nb; b0 += p.batch) {
+          const int64_t b1 = b0 + p.batch < nb ? b0 + p.batch : nb;
+          FGA_HIP(launch_emit(beams->f64, beams->i32, beams->capacity, b0, b1, rec->eps, emit, st));
+          PointsArgs pa{};
+          pa.emit = emit;
+          pa.nb = b1 - b0;
+          pa.m = 1;
+          pa.xyz = wb.xs;
+          pa.n = rec->n;
+          pa.eps = rec->eps;
+          pa.tau = rec->tau;
+          pa.partial = partial;
+          pa.beams_per_block = p.bpb;
+          pa.evals = ctr + 3;
+          pa.tile_box = wb.box;
+          pa.ntiles = (pa.nb + 63) / 64;
+          int nblk = 0;
+          FGA_HIP(launch_sum_points(pa, &nblk, st));
+          FGA_HIP(launch_reduce_points(partial, nblk, 1, rec->n, wb.perm, seis, p.nsamp, sample, b0 > 0 ? 1 : 0, st));
+        }
+      }
+    }
+  }
+  for (int s0 = 0; s0 < (dm.kind == FGA_MEDIUM_LAYERED ? 0 : nsteps); s0 += p.chunk) {
     if (p.resort > 0 && (last_sort < 0 || s0 - last_sort >= p.resort)) {
       Arena sa(static_cast<char *>(workspace) + sort_base, workspace_bytes - sort_base);
       size_t need = 0;
@@ -453,7 +544,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
     if ((s = compact_beams(beams, a2, st, false, &need)) != FGA_OK) return s;
   }
   if (stats || (cutoff > 0 && nsteps > 0)) {
-    unsigned long long h[4] = {0, 0, 0, 0};
+    unsigned long long h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     FGA_HIP(hipMemcpyAsync(h, ctr, sizeof h, hipMemcpyDeviceToHost, st));
     FGA_HIP(hipStreamSynchronize(st));
     if (stats) {
@@ -461,6 +552,9 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
       stats->culled = (int64_t)h[1];
       stats->quarantined = (int64_t)h[2];
       stats->evals = (int64_t)h[3];
+      stats->crossings = (int64_t)h[4];
+      stats->spawned = (int64_t)h[5];
+      stats->capped = (int64_t)h[6];
     }
   }
   return FGA_OK;

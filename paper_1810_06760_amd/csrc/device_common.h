@@ -9,6 +9,24 @@ namespace fga {
 // Medium kinds a kernel is specialised for.
 enum { MK_HOMOG = 0, MK_GRID = 1, MK_LAYERED = 2 };
 
+// Layered media: if Q lies outside layer L, the interface crossed and the
+// layer beyond it (points on an interface count as inside).  Flat: interface
+// i is z = bound[i] between layer i (below) and i+1; spherical: |x| = bound[i]
+// between layer i (outside) and i+1 (inside).
+__device__ __forceinline__ bool layer_exit(const DevMedium &m, int L, const double Q[3], int &iface, int &newL)
+{
+  const int nl = m.nlayer;
+  if (m.geometry == 1) {
+    const double r = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
+    if (L < nl - 1 && r < m.bound[L]) { iface = L; newL = L + 1; return true; }
+    if (L > 0 && r > m.bound[L - 1]) { iface = L - 1; newL = L - 1; return true; }
+  } else {
+    if (L < nl - 1 && Q[2] > m.bound[L]) { iface = L; newL = L + 1; return true; }
+    if (L > 0 && Q[2] < m.bound[L - 1]) { iface = L - 1; newL = L - 1; return true; }
+  }
+  return false;
+}
+
 // Speed of wave type sp (0 = P, 1 = S) at x: c, gradient g and Hessian H
 // (xx, yy, zz, xy, xz, yz).  Grid media interpolate the ten precomputed node
 // fields trilinearly (periodic); each node is one 128-byte record.

@@ -74,7 +74,7 @@ struct DevMedium {
   // layered
   int geometry, nlayer;
   double bound[FGA_MAX_LAYERS];
-  double cpl[FGA_MAX_LAYERS], csl[FGA_MAX_LAYERS];
+  double cpl[FGA_MAX_LAYERS], csl[FGA_MAX_LAYERS], rhol[FGA_MAX_LAYERS];
 };
 
 fga_status make_dev_medium(const fga_medium *m, DevMedium *out);
@@ -140,6 +140,28 @@ struct DecompArgs {
 };
 fga_status decompose_impl(const DevMedium &dm, const fga_mesh *mesh, const double *f, const double *g,
                           fga_beams *beams, Arena &ar, hipStream_t st, bool size_only, size_t *need);
+
+// Interface step of a layered medium after one integrator step: beams that
+// left their layer during the step (flag FGA_FLAG_CROSS, state still at the
+// start of the step) are split into children (Snell, elastic boundary
+// problem, Jacobian map) which finish the step in their own layers.
+struct InterfaceArgs {
+  double *f64;
+  int32_t *i32;
+  int64_t *lineage;
+  int64_t cap;
+  int64_t n;                 // beams in the set before the step
+  double dt;
+  int gen_max;
+  double child_cut;
+  int64_t *blk_extra;        // [ceil(n / 256)] extra slots per workgroup (pass 1 output)
+  int64_t *blk_off;          // [ceil(n / 256)] exclusive scan of blk_extra (pass 2 input)
+  unsigned long long *counters;  // [0] crossings, [1] children, [2] retired at the generation cap
+};
+// pass 1 (write = 0): per-workgroup counts of extra slots; pass 2 (write = 1):
+// children written (first child in the parent's slot, the others appended at
+// n + blk_off + rank)
+hipError_t launch_interface(const DevMedium &m, const InterfaceArgs &a, int write, hipStream_t st);
 
 // exclusive scan of n int64 values (one workgroup); total = sum
 hipError_t launch_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st);

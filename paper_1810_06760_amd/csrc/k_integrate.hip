@@ -4,149 +4,15 @@
 // planes (coalesced), advances it by `nsteps` classic RK4 steps held entirely
 // in registers, optionally writes an emission record (Q, P, w e^{iS/eps} A)
 // after every sample step for the receiver summation, and stores the state
-// back.  The right-hand side is, for sigma = +1 / -1 (Sec. 2.2):
-//   dQ/dt = sigma c P/|P|,  dP/dt = -sigma |P| grad c         (eq:char_plus, eq:char_minus)
-//   d(dzQ)/dt = sigma [dzQ (grad c (x) P)/|P| + c dzP (I - P (x) P/|P|^2)/|P|]
-//   d(dzP)/dt = sigma [-|P| dzQ Hess c - dzP (P (x) grad c)/|P|]   (eq:DzDt)
-//   da_P/dt = a_P (sigma grad c . P/|P| + tr(Z^{-1} dZ/dt)/2)       (eq:amp_P)
-//   d(a_SV, a_SH)/dt = s (a_SV, a_SH) + omega (-a_SH, a_SV),
-//     omega = dN_SH/dt . N_SV = sigma (P.e) e.(grad c x P)/|e x P|^2  (eq:amp_SV, eq:amp_SH)
-//   dS/dt = P . dQ/dt - sigma c |P|
-// tr(Z^{-1} dZ/dt) is formed as (sum_ij cof(Z)_ij dZ_ij) / det Z, so no
-// matrix inverse is built.
-#include "device_common.h"
+// back (the right-hand side and the RK4 step are in rk4.h).  In layered media
+// a beam whose centre leaves its layer during a step keeps its stored state
+// and is flagged for the interface step.
+#include "rk4.h"
 
 namespace fga {
 namespace {
 
-constexpr int NS = 47;
-enum { IQ = 0, IP = 3, IZQR = 6, IZQI = 15, IZPR = 24, IZPI = 33, IA = 42, IS = 46 };
-constexpr double COS10 = 0.98480775301220805936;  // cos(10 degrees)
-
-// One RK4 stage: k = f(yt); acc += wacc*k; yt <- y + cnext*k in place.  The
-// derivative is folded in as soon as each group of components is complete,
-// row by row for dzQ/dzP, so the live state stays at y, acc and yt.
-template <int MK>
-__device__ __forceinline__ void stage(const DevMedium &med, int sp, int layer, double sg, bool isS,
-                                      const double e[3], const double *__restrict__ y, double *__restrict__ yt,
-                                      double *__restrict__ acc, double wacc, double cnext)
-{
-  double c, g[3], H6[6];
-  medium_eval<MK>(med, sp, layer, yt + IQ, c, g, H6);
-  const double H[3][3] = {{H6[0], H6[3], H6[4]}, {H6[3], H6[1], H6[5]}, {H6[4], H6[5], H6[2]}};
-  const double P0 = yt[IP], P1 = yt[IP + 1], P2 = yt[IP + 2];
-  const double np = sqrt(P0 * P0 + P1 * P1 + P2 * P2);
-  const double inp = 1.0 / np;
-  const double ph[3] = {P0 * inp, P1 * inp, P2 * inp};
-  const double sc = sg * c;
-  const double ci = sc * inp;
-
-  // cofactors of Z = dzQ + i dzP and det Z (cyclic index form carries the sign)
-  double Cr[9], Ci[9];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-      const int a = 3 * i1 + j1, b = 3 * i2 + j2, cc = 3 * i1 + j2, d = 3 * i2 + j1;
-      const double ar = yt[IZQR + a] - yt[IZPI + a], ai = yt[IZQI + a] + yt[IZPR + a];
-      const double br = yt[IZQR + b] - yt[IZPI + b], bi = yt[IZQI + b] + yt[IZPR + b];
-      const double cr = yt[IZQR + cc] - yt[IZPI + cc], cim = yt[IZQI + cc] + yt[IZPR + cc];
-      const double dr = yt[IZQR + d] - yt[IZPI + d], di = yt[IZQI + d] + yt[IZPR + d];
-      Cr[3 * i + j] = (ar * br - ai * bi) - (cr * dr - cim * di);
-      Ci[3 * i + j] = (ar * bi + ai * br) - (cr * di + cim * dr);
-    }
-  }
-  double detr = 0.0, deti = 0.0;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const double zr = yt[IZQR + j] - yt[IZPI + j], zi = yt[IZQI + j] + yt[IZPR + j];
-    detr += zr * Cr[j] - zi * Ci[j];
-    deti += zr * Ci[j] + zi * Cr[j];
-  }
-
-  double Tr = 0.0, Ti = 0.0;
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    const double ur = yt[IZQR + 3 * m] * g[0] + yt[IZQR + 3 * m + 1] * g[1] + yt[IZQR + 3 * m + 2] * g[2];
-    const double ui = yt[IZQI + 3 * m] * g[0] + yt[IZQI + 3 * m + 1] * g[1] + yt[IZQI + 3 * m + 2] * g[2];
-    const double vr = yt[IZPR + 3 * m] * ph[0] + yt[IZPR + 3 * m + 1] * ph[1] + yt[IZPR + 3 * m + 2] * ph[2];
-    const double vi = yt[IZPI + 3 * m] * ph[0] + yt[IZPI + 3 * m + 1] * ph[1] + yt[IZPI + 3 * m + 2] * ph[2];
-    double kq_r[3], kq_i[3], kp_r[3], kp_i[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int o = 3 * m + j;
-      kq_r[j] = sg * ur * ph[j] + ci * (yt[IZPR + o] - vr * ph[j]);
-      kq_i[j] = sg * ui * ph[j] + ci * (yt[IZPI + o] - vi * ph[j]);
-      const double hr = yt[IZQR + 3 * m] * H[0][j] + yt[IZQR + 3 * m + 1] * H[1][j] + yt[IZQR + 3 * m + 2] * H[2][j];
-      const double hi = yt[IZQI + 3 * m] * H[0][j] + yt[IZQI + 3 * m + 1] * H[1][j] + yt[IZQI + 3 * m + 2] * H[2][j];
-      kp_r[j] = -sg * (np * hr + vr * g[j]);
-      kp_i[j] = -sg * (np * hi + vi * g[j]);
-      // dZ = d(dzQ) + i d(dzP); T += cof(Z) : dZ
-      const double dr = kq_r[j] - kp_i[j], di = kq_i[j] + kp_r[j];
-      Tr += Cr[o] * dr - Ci[o] * di;
-      Ti += Cr[o] * di + Ci[o] * dr;
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int o = 3 * m + j;
-      const double kk[4] = {kq_r[j], kq_i[j], kp_r[j], kp_i[j]};
-      const int base[4] = {IZQR, IZQI, IZPR, IZPI};
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int f = base[t] + o;
-        acc[f] += wacc * kk[t];
-        yt[f] = y[f] + cnext * kk[t];
-      }
-    }
-  }
-  const double idd = 1.0 / (detr * detr + deti * deti);
-  const double trr = (Tr * detr + Ti * deti) * idd;
-  const double tri = (Ti * detr - Tr * deti) * idd;
-  const double sr = sg * (g[0] * ph[0] + g[1] * ph[1] + g[2] * ph[2]) + 0.5 * trr;
-  const double si = 0.5 * tri;
-  double ka[4];
-  {
-    const double a0r = yt[IA], a0i = yt[IA + 1], a1r = yt[IA + 2], a1i = yt[IA + 3];
-    if (!isS) {
-      ka[0] = sr * a0r - si * a0i;
-      ka[1] = sr * a0i + si * a0r;
-      ka[2] = 0.0;
-      ka[3] = 0.0;
-    } else {
-      const double gx0 = g[1] * P2 - g[2] * P1, gx1 = g[2] * P0 - g[0] * P2, gx2 = g[0] * P1 - g[1] * P0;
-      const double egp = e[0] * gx0 + e[1] * gx1 + e[2] * gx2;
-      const double pe = P0 * e[0] + P1 * e[1] + P2 * e[2];
-      const double x0 = e[1] * P2 - e[2] * P1, x1 = e[2] * P0 - e[0] * P2, x2 = e[0] * P1 - e[1] * P0;
-      const double om = sg * pe * egp / (x0 * x0 + x1 * x1 + x2 * x2);
-      ka[0] = sr * a0r - si * a0i - om * a1r;
-      ka[1] = sr * a0i + si * a0r - om * a1i;
-      ka[2] = sr * a1r - si * a1i + om * a0r;
-      ka[3] = sr * a1i + si * a1r + om * a0i;
-    }
-  }
-  double kr[7];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    kr[j] = sc * ph[j];
-    kr[3 + j] = -sg * np * g[j];
-  }
-  kr[6] = P0 * kr[0] + P1 * kr[1] + P2 * kr[2] - sc * np;
-  const int fr[7] = {IQ, IQ + 1, IQ + 2, IP, IP + 1, IP + 2, IS};
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int f = IA + t;
-    acc[f] += wacc * ka[t];
-    yt[f] = y[f] + cnext * ka[t];
-  }
-#pragma unroll
-  for (int t = 0; t < 7; ++t) {
-    const int f = fr[t];
-    acc[f] += wacc * kr[t];
-    yt[f] = y[f] + cnext * kr[t];
-  }
-}
+using namespace rk;
 
 // Emission record of the current state: Q (3), P (3), B = w e^{iS/eps} A (3 complex).
 __device__ __forceinline__ void emit_record(double *__restrict__ out, int64_t nb, int64_t j,
@@ -224,51 +90,31 @@ __global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs 
       for (int f = 0; f < NS; ++f) y[f] = F[f * cap + i];
       double e[3] = {F[(FGA_E + 0) * cap + i], F[(FGA_E + 1) * cap + i], F[(FGA_E + 2) * cap + i]};
       const double wr = F[FGA_W_RE * cap + i], wi = F[FGA_W_IM * cap + i];
-      const double dt = a.dt, h2 = 0.5 * a.dt, h6 = a.dt / 6.0;
+      const double dt = a.dt;
       const double ieps = 1.0 / a.eps_emit;
+      bool crossed = false;
       for (int s = 0; s < a.nsteps; ++s) {
-        // classic RK4, y' = y + dt/6 (k1 + 2 k2 + 2 k3 + k4); the four stages run
-        // as a loop so that only y, acc and the stage input stay live
-        double acc[NS], yt[NS];
-#pragma unroll
-        for (int f = 0; f < NS; ++f) { yt[f] = y[f]; acc[f] = 0.0; }
-#pragma nounroll
-        for (int st = 0; st < 4; ++st) {
-          const double wacc = (st == 0 || st == 3) ? 1.0 : 2.0;
-          const double cnext = st == 2 ? dt : (st == 3 ? 0.0 : h2);
-          stage<MK>(med, sp, layer, sg, isS, e, y, yt, acc, wacc, cnext);
-        }
-#pragma unroll
-        for (int f = 0; f < NS; ++f) y[f] += h6 * acc[f];
-        if (isS) {
-          // switch the frame axis when P comes within 10 degrees of it
-          const double np = sqrt(y[IP] * y[IP] + y[IP + 1] * y[IP + 1] + y[IP + 2] * y[IP + 2]);
-          const double pe = y[IP] * e[0] + y[IP + 1] * e[1] + y[IP + 2] * e[2];
-          if (fabs(pe) / np > COS10) {
-            double nsh[3], nsv[3];
-            s_frame(y + IP, e, nsh, nsv);
-            double Ar[3], Ai[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              Ar[c] = y[IA] * nsv[c] + y[IA + 2] * nsh[c];
-              Ai[c] = y[IA + 1] * nsv[c] + y[IA + 3] * nsh[c];
-            }
-            const bool was_z = e[2] != 0.0 && e[0] == 0.0 && e[1] == 0.0;
-            e[0] = was_z ? 1.0 : 0.0;
-            e[1] = 0.0;
-            e[2] = was_z ? 0.0 : 1.0;
-            s_frame(y + IP, e, nsh, nsv);
-            y[IA] = Ar[0] * nsv[0] + Ar[1] * nsv[1] + Ar[2] * nsv[2];
-            y[IA + 1] = Ai[0] * nsv[0] + Ai[1] * nsv[1] + Ai[2] * nsv[2];
-            y[IA + 2] = Ar[0] * nsh[0] + Ar[1] * nsh[1] + Ar[2] * nsh[2];
-            y[IA + 3] = Ai[0] * nsh[0] + Ai[1] * nsh[1] + Ai[2] * nsh[2];
+        rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt);
+        if constexpr (MK == MK_LAYERED) {
+          // left the layer: the interface step redoes this step from the
+          // stored state, which is therefore not overwritten
+          int iface, newL;
+          if (layer_exit(med, layer, y + IQ, iface, newL)) {
+            crossed = true;
+            break;
           }
         }
+        if (isS) reframe_s(y, e);
         if (a.stride && (a.step0 + s + 1) % a.stride == 0)
           emit_record(a.emit + (int64_t)((a.step0 + s + 1) / a.stride - 1 - first_emit) * 12 * nb, nb, j,
                       y, e, wr, wi, isS, ieps);
       }
       steps_done = (unsigned long long)a.nsteps;
+      if (crossed) {
+        a.i32[FGA_FLAGS * cap + i] = flags | FGA_FLAG_CROSS;
+        goto done;
+      }
+      {
       bool finite = true;
 #pragma unroll
       for (int f = 0; f < NS; ++f) finite = finite && isfinite(y[f]);
@@ -289,8 +135,10 @@ __global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs 
 #pragma unroll
       for (int d = 0; d < 3; ++d) F[(FGA_E + d) * cap + i] = e[d];
       a.i32[FGA_FLAGS * cap + i] = flags;
+      }
     }
   }
+done:
   // wavefront-level reduction of the counters, one atomic per wavefront
   for (int off = 32; off > 0; off >>= 1) {
     steps_done += __shfl_down(steps_done, off);

@@ -1,0 +1,463 @@
+// Interface step of layered media (Sec. 3.1: eq:p:int, eq:Yilmaz,
+// eq:Inter_DzQDzP), run after every integrator step.
+//
+// The integrator leaves a beam that left its layer during the step at the
+// start of the step, flagged FGA_FLAG_CROSS.  Here each such beam redoes the
+// step to find where it left (speeds are constant inside a layer, so the ray
+// is the straight segment Q0 -> Q1 and the crossing fraction theta is found
+// exactly on it), advances theta dt, is put exactly on the interface, and
+// is split into the outgoing plane-wave modes:
+//   - Snell: every mode keeps the tangential momentum and the frequency
+//     H = c_in |P|; transmitted modes keep the sign of the normal momentum,
+//     reflected ones flip it; a mode with imaginary normal momentum is
+//     evanescent and is not made (it stays in the boundary problem).
+//   - Amplitudes: continuity of displacement and of traction sigma.n across
+//     the interface for u = A d exp(i P.x/eps), with sigma_ij = lambda div u
+//     delta_ij + mu (d_i u_j + d_j u_i).  In the local frame (e3 = normal
+//     into the far layer, e1 = tangential momentum direction, e2 = e3 x e1)
+//     the in-plane (P, SV) part is a 4x4 complex system for (R_P, R_S, T_P,
+//     T_S) and the SH part a 2x2 one; P modes are polarised along k/|k|,
+//     in-plane S modes along e2 x k/|k|, SH modes along e2.
+//   - Jacobians: dzQ' = dzQ F, dzP' = dzP F^{-T} - (gradient terms, zero in
+//     homogeneous layers), with F = I + n (x) v in any frame with third axis
+//     n, v = (kappa - 1) p_t / p_n + (kappa p_n' / p_n - 1) n,
+//     kappa = (c_out / c_in)^2.
+// Children with |A_child| >= child_cut |A_in| are made (generation + 1,
+// lineage FGA_LINEAGE_CHILD) and take the remaining (1 - theta) dt in their
+// own layer.  The first child reuses the parent's slot; the others go after
+// the current count, at offsets from a two-pass count / exclusive scan over
+// workgroups, so slot assignment is deterministic.
+#include "rk4.h"
+
+namespace fga {
+namespace {
+
+using namespace rk;
+
+struct cx {
+  double r, i;
+};
+__device__ __forceinline__ cx mk(double r, double i = 0.0) { return cx{r, i}; }
+__device__ __forceinline__ cx operator+(cx a, cx b) { return cx{a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cx operator-(cx a, cx b) { return cx{a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ cx operator-(cx a) { return cx{-a.r, -a.i}; }
+__device__ __forceinline__ cx operator*(cx a, cx b) { return cx{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cx operator*(double s, cx a) { return cx{s * a.r, s * a.i}; }
+__device__ __forceinline__ cx operator/(cx a, cx b)
+{
+  const double d = b.r * b.r + b.i * b.i;
+  return cx{(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+__device__ __forceinline__ double cabs2(cx a) { return a.r * a.r + a.i * a.i; }
+
+__device__ __forceinline__ double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// A x = b for n <= 4 by Gaussian elimination with partial pivoting (by modulus).
+__device__ void solve_small(int n, cx A[4][4], cx b[4], cx x[4])
+{
+  for (int c = 0; c < n; ++c) {
+    int pv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (cabs2(A[r][c]) > cabs2(A[pv][c])) pv = r;
+    if (pv != c) {
+      for (int j = 0; j < n; ++j) {
+        const cx t = A[c][j];
+        A[c][j] = A[pv][j];
+        A[pv][j] = t;
+      }
+      const cx t = b[c];
+      b[c] = b[pv];
+      b[pv] = t;
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const cx f = A[r][c] / A[c][c];
+      for (int j = c; j < n; ++j) A[r][j] = A[r][j] - f * A[c][j];
+      b[r] = b[r] - f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    cx s = b[r];
+    for (int j = r + 1; j < n; ++j) s = s - A[r][j] * x[j];
+    x[r] = s / A[r][r];
+  }
+}
+
+// Crossing fraction of the straight segment Q0 -> Q1 with interface `iface`.
+__device__ double crossing(const DevMedium &m, int iface, const double *Q0, const double *Q1)
+{
+  const double r = m.bound[iface];
+  double th;
+  if (m.geometry == 1) {
+    const double D[3] = {Q1[0] - Q0[0], Q1[1] - Q0[1], Q1[2] - Q0[2]};
+    const double a = dot3(D, D), b = dot3(Q0, D), c = dot3(Q0, Q0) - r * r;
+    const double disc = fmax(b * b - a * c, 0.0);
+    th = c > 0.0 ? (-b - sqrt(disc)) / a : (-b + sqrt(disc)) / a;  // first contact with the sphere
+  } else {
+    th = (r - Q0[2]) / (Q1[2] - Q0[2]);
+  }
+  return fmin(fmax(th, 0.0), 1.0);
+}
+
+struct Modes {
+  bool exists[4];
+  int sp[4], side[4];
+  double P[4][3];
+  cx A[4][3];
+};
+
+// Outgoing modes (0 P reflected, 1 S reflected, 2 P transmitted,
+// 3 S transmitted) for the plane wave (Pin, Ain) of type sp_in hitting the
+// interface from layer L into layer L2 across unit normal n.
+__device__ void outgoing_modes(const DevMedium &m, int L, int L2, const double n[3], int sp_in, const double Pin[3],
+                               const cx Ain[3], Modes &o)
+{
+  const double pabs = sqrt(dot3(Pin, Pin));
+  const double c_in = sp_in == 0 ? m.cpl[L] : m.csl[L];
+  const double H = c_in * pabs;
+  const double pn = dot3(Pin, n);
+  double e1[3], e2[3], t[3];
+  for (int d = 0; d < 3; ++d) t[d] = Pin[d] - pn * n[d];
+  double p1 = sqrt(dot3(t, t));
+  if (p1 > 1e-12 * pabs) {
+    for (int d = 0; d < 3; ++d) e1[d] = t[d] / p1;
+  } else {
+    // normal incidence: any tangent (the problem is then symmetric about n)
+    p1 = 0.0;
+    double u[3] = {1.0, 0.0, 0.0};
+    if (fabs(n[0]) > 0.9) { u[0] = 0.0; u[1] = 1.0; }
+    const double un = dot3(u, n);
+    for (int d = 0; d < 3; ++d) u[d] -= un * n[d];
+    const double nu = sqrt(dot3(u, u));
+    for (int d = 0; d < 3; ++d) e1[d] = u[d] / nu;
+  }
+  e2[0] = n[1] * e1[2] - n[2] * e1[1];
+  e2[1] = n[2] * e1[0] - n[0] * e1[2];
+  e2[2] = n[0] * e1[1] - n[1] * e1[0];
+  const double dirn = pn >= 0.0 ? 1.0 : -1.0;
+  const int lay[2] = {L, L2};
+  double lam[2], mu[2];
+  for (int s = 0; s < 2; ++s) {
+    const double rho = m.rhol[lay[s]], a = m.cpl[lay[s]], b = m.csl[lay[s]];
+    mu[s] = rho * b * b;
+    lam[s] = rho * (a * a - 2.0 * b * b);
+  }
+  // normal momentum k3 and in-plane polarisation (d1, d3) per wave:
+  // 0..3 the outgoing modes, 4 the incident wave
+  cx k3[5], d1[5], d3[5];
+  int sd[5];
+  for (int w = 0; w < 5; ++w) {
+    int spw, s;
+    double kabs;
+    if (w < 4) {
+      spw = w & 1;
+      s = w >> 1;
+      kabs = H / (spw == 0 ? m.cpl[lay[s]] : m.csl[lay[s]]);
+      const double rad = kabs * kabs - p1 * p1;
+      if (rad >= 0.0) {
+        k3[w] = mk((s == 1 ? dirn : -dirn) * sqrt(rad));
+        o.exists[w] = true;
+      } else {
+        k3[w] = mk(0.0, (s == 1 ? 1.0 : -1.0) * sqrt(-rad));  // decays away from the interface
+        o.exists[w] = false;
+      }
+      o.sp[w] = spw;
+      o.side[w] = s;
+    } else {
+      spw = sp_in;
+      s = 0;
+      kabs = H / c_in;
+      k3[w] = mk(pn);
+    }
+    sd[w] = s;
+    const cx h1 = mk(p1 / kabs), h3 = (1.0 / kabs) * k3[w];
+    if (spw == 0) {
+      d1[w] = h1;
+      d3[w] = h3;
+    } else {
+      d1[w] = h3;
+      d3[w] = -h1;
+    }
+  }
+  // incident amplitude: in-plane part along (d1, d3) of the incident wave, SH part along e2
+  cx A1 = mk(0.0), A2 = mk(0.0), A3 = mk(0.0);
+  for (int d = 0; d < 3; ++d) {
+    A1 = A1 + e1[d] * Ain[d];
+    A2 = A2 + e2[d] * Ain[d];
+    A3 = A3 + n[d] * Ain[d];
+  }
+  const cx ain = A1 * d1[4] + A3 * d3[4];
+  // P-SV: rows u1, u3, t1, t3; incident and reflected on side 0 = transmitted on side 1
+  cx M[4][4], rhs[4], x[4];
+  for (int w = 0; w < 5; ++w) {
+    const int s = sd[w];
+    const cx k1 = mk(p1);
+    const cx col[4] = {d1[w], d3[w], mu[s] * (k1 * d3[w] + k3[w] * d1[w]),
+                       lam[s] * (k1 * d1[w] + k3[w] * d3[w]) + (2.0 * mu[s]) * (k3[w] * d3[w])};
+    for (int r = 0; r < 4; ++r) {
+      if (w == 4) rhs[r] = -(ain * col[r]);
+      else M[r][w] = s == 0 ? col[r] : -col[r];
+    }
+  }
+  solve_small(4, M, rhs, x);
+  // SH: rows u2, t2 (polarisation e2 for every SH wave)
+  cx y[2] = {mk(0.0), mk(0.0)};
+  if (sp_in == 1) {
+    cx S[4][4], bs[4], xs[4];
+    S[0][0] = mk(1.0);
+    S[0][1] = mk(-1.0);
+    S[1][0] = mu[0] * k3[1];
+    S[1][1] = -(mu[1] * k3[3]);
+    bs[0] = -A2;
+    bs[1] = -(mu[0] * (k3[4] * A2));
+    solve_small(2, S, bs, xs);
+    y[0] = xs[0];
+    y[1] = xs[1];
+  }
+  for (int w = 0; w < 4; ++w) {
+    for (int d = 0; d < 3; ++d) o.P[w][d] = p1 * e1[d] + k3[w].r * n[d];
+    const cx sh = o.sp[w] == 1 ? y[w >> 1] : mk(0.0);
+    for (int d = 0; d < 3; ++d) o.A[w][d] = x[w] * (e1[d] * d1[w] + n[d] * d3[w]) + e2[d] * sh;
+  }
+}
+
+// dzQ, dzP (planes of y) mapped to an outgoing mode with momentum Pout and
+// speed ratio c_out / c_in across normal n (homogeneous layers: no gradient terms).
+__device__ void map_jacobians(double *y, const double n[3], const double Pin[3], const double Pout[3], double c_in,
+                              double c_out)
+{
+  const double pn = dot3(Pin, n), pno = dot3(Pout, n);
+  const double kap = (c_out / c_in) * (c_out / c_in);
+  double v[3];
+  for (int d = 0; d < 3; ++d) v[d] = (kap - 1.0) * (Pin[d] - pn * n[d]) / pn + (kap * pno / pn - 1.0) * n[d];
+  const double den = kap * pno / pn;
+  for (int r = 0; r < 3; ++r) {
+    // row r of dzQ gains (row . n) v; row r of dzP loses (row . v) / den n
+    double qnr = 0.0, qni = 0.0, pvr = 0.0, pvi = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      qnr += y[IZQR + 3 * r + d] * n[d];
+      qni += y[IZQI + 3 * r + d] * n[d];
+      pvr += y[IZPR + 3 * r + d] * v[d];
+      pvi += y[IZPI + 3 * r + d] * v[d];
+    }
+    for (int d = 0; d < 3; ++d) {
+      y[IZQR + 3 * r + d] += qnr * v[d];
+      y[IZQI + 3 * r + d] += qni * v[d];
+      y[IZPR + 3 * r + d] -= pvr / den * n[d];
+      y[IZPI + 3 * r + d] -= pvi / den * n[d];
+    }
+  }
+}
+
+__device__ __forceinline__ void initial_axis(const double P[3], double e[3])
+{
+  const double np = sqrt(dot3(P, P));
+  const bool nearz = fabs(P[2]) / np > 0.93969262078590838405;  // cos(20 degrees)
+  e[0] = nearz ? 1.0 : 0.0;
+  e[1] = 0.0;
+  e[2] = nearz ? 0.0 : 1.0;
+}
+
+// Per crossing beam: the crossing point state (in y), the modes, and which
+// of them become children.
+struct Crossing {
+  double th;
+  int newL;
+  double n[3];
+  Modes md;
+  bool keep[4];
+  int nkeep;
+  bool capped;
+};
+
+__device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, double *y, double e[3], Crossing &c)
+{
+  const int64_t cap = a.cap;
+  const int br = a.i32[FGA_BRANCH * cap + i];
+  const int sp = br == 0 ? 0 : 1;
+  const double sg = (double)a.i32[FGA_SIGMA * cap + i];
+  const int L = a.i32[FGA_LAYER * cap + i];
+  const int gen = a.i32[FGA_GEN * cap + i];
+  for (int f = 0; f < NS; ++f) y[f] = a.f64[f * cap + i];
+  for (int d = 0; d < 3; ++d) e[d] = a.f64[(FGA_E + d) * cap + i];
+  double y1[NS];
+  for (int f = 0; f < NS; ++f) y1[f] = y[f];
+  rk4_step<MK_LAYERED>(m, sp, L, sg, sp == 1, e, y1, a.dt);
+  int iface = 0, newL = L;
+  c.nkeep = 0;
+  c.capped = false;
+  for (int k = 0; k < 4; ++k) c.keep[k] = false;
+  if (!layer_exit(m, L, y1 + IQ, iface, newL)) {
+    // not reached when the integrator flagged the beam: treat as an ordinary step
+    c.th = -1.0;
+    for (int f = 0; f < NS; ++f) y[f] = y1[f];
+    return;
+  }
+  c.newL = newL;
+  c.th = crossing(m, iface, y + IQ, y1 + IQ);
+  rk4_step<MK_LAYERED>(m, sp, L, sg, sp == 1, e, y, c.th * a.dt);
+  const double rb = m.bound[iface];
+  if (m.geometry == 1) {
+    const double r = sqrt(dot3(y + IQ, y + IQ));
+    for (int d = 0; d < 3; ++d) y[IQ + d] *= rb / r;
+    for (int d = 0; d < 3; ++d) c.n[d] = (newL > L ? -1.0 : 1.0) * y[IQ + d] / rb;
+  } else {
+    y[IQ + 2] = rb;
+    c.n[0] = c.n[1] = 0.0;
+    c.n[2] = newL > L ? 1.0 : -1.0;
+  }
+  if (gen >= a.gen_max) {
+    c.capped = true;
+    return;
+  }
+  // incident displacement amplitude vector
+  cx Ain[3];
+  if (sp == 0) {
+    const double ip = 1.0 / sqrt(dot3(y + IP, y + IP));
+    for (int d = 0; d < 3; ++d) Ain[d] = mk(y[IA] * y[IP + d] * ip, y[IA + 1] * y[IP + d] * ip);
+  } else {
+    double nsh[3], nsv[3];
+    s_frame(y + IP, e, nsh, nsv);
+    for (int d = 0; d < 3; ++d)
+      Ain[d] = mk(y[IA] * nsv[d] + y[IA + 2] * nsh[d], y[IA + 1] * nsv[d] + y[IA + 3] * nsh[d]);
+  }
+  const double ain = sqrt(cabs2(Ain[0]) + cabs2(Ain[1]) + cabs2(Ain[2]));
+  outgoing_modes(m, L, newL, c.n, sp, y + IP, Ain, c.md);
+  for (int k = 0; k < 4; ++k) {
+    const double am = sqrt(cabs2(c.md.A[k][0]) + cabs2(c.md.A[k][1]) + cabs2(c.md.A[k][2]));
+    c.keep[k] = c.md.exists[k] && am >= a.child_cut * ain;
+    c.nkeep += c.keep[k] ? 1 : 0;
+  }
+}
+
+// exclusive prefix sum over the workgroup of v (small non-negative ints); total in *tot
+__device__ int block_exscan(int v, int *tot)
+{
+  __shared__ int ws[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) ws[w] = incl;
+  __syncthreads();
+  int base = 0, all = 0;
+  for (int k = 0; k < 4; ++k) {
+    if (k < w) base += ws[k];
+    all += ws[k];
+  }
+  __syncthreads();
+  *tot = all;
+  return base + incl - v;
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_interface(DevMedium m, InterfaceArgs a)
+{
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool mine = i < a.n && (a.i32[FGA_FLAGS * a.cap + i] & FGA_FLAG_CROSS);
+  if (!__syncthreads_or(mine)) {
+    if (!WRITE && threadIdx.x == 0) a.blk_extra[blockIdx.x] = 0;
+    return;
+  }
+  double y[NS], e[3];
+  Crossing c;
+  c.nkeep = 0;
+  c.th = -1.0;
+  c.capped = false;
+  if (mine) analyse(m, a, i, y, e, c);
+  const int extra = (mine && c.th >= 0.0 && c.nkeep > 1) ? c.nkeep - 1 : 0;
+  int tot;
+  const int off = block_exscan(extra, &tot);
+  if (!WRITE) {
+    if (threadIdx.x == 0) a.blk_extra[blockIdx.x] = tot;
+    return;
+  }
+  if (!mine) return;
+  const int64_t cap = a.cap;
+  const int L = a.i32[FGA_LAYER * cap + i];
+  const int br = a.i32[FGA_BRANCH * cap + i];
+  const int sp_in = br == 0 ? 0 : 1;
+  const int sigma = a.i32[FGA_SIGMA * cap + i];
+  const int gen = a.i32[FGA_GEN * cap + i];
+  const int flags = a.i32[FGA_FLAGS * cap + i] & ~FGA_FLAG_CROSS;
+  const int64_t lin = a.lineage[i];
+  const double wr = a.f64[FGA_W_RE * cap + i], wi = a.f64[FGA_W_IM * cap + i];
+  if (c.th < 0.0) {
+    // no crossing found after all: the ordinary step result
+    if (sp_in == 1) reframe_s(y, e);
+    for (int f = 0; f < NS; ++f) a.f64[f * cap + i] = y[f];
+    for (int d = 0; d < 3; ++d) a.f64[(FGA_E + d) * cap + i] = e[d];
+    a.i32[FGA_FLAGS * cap + i] = flags;
+    return;
+  }
+  unsigned long long nchild = 0;
+  if (c.nkeep == 0) a.i32[FGA_FLAGS * cap + i] = 0;  // retired (generation cap or no child)
+  const double c_in = sp_in == 0 ? m.cpl[L] : m.csl[L];
+  int j = 0;
+  for (int k = 0; k < 4; ++k) {
+    if (!c.keep[k]) continue;
+    const int64_t slot = j == 0 ? i : a.n + a.blk_off[blockIdx.x] + off + (j - 1);
+    ++j;
+    const int layc = c.md.side[k] == 1 ? c.newL : L;
+    const int spc = c.md.sp[k];
+    const double c_out = spc == 0 ? m.cpl[layc] : m.csl[layc];
+    double z[NS], ec[3];
+    for (int f = 0; f < NS; ++f) z[f] = y[f];
+    for (int d = 0; d < 3; ++d) z[IP + d] = c.md.P[k][d];
+    map_jacobians(z, c.n, y + IP, z + IP, c_in, c_out);
+    initial_axis(z + IP, ec);
+    if (spc == 0) {
+      const double ip = 1.0 / sqrt(dot3(z + IP, z + IP));
+      cx ap = mk(0.0);
+      for (int d = 0; d < 3; ++d) ap = ap + (z[IP + d] * ip) * c.md.A[k][d];
+      z[IA] = ap.r;
+      z[IA + 1] = ap.i;
+      z[IA + 2] = 0.0;
+      z[IA + 3] = 0.0;
+    } else {
+      double nsh[3], nsv[3];
+      s_frame(z + IP, ec, nsh, nsv);
+      cx asv = mk(0.0), ash = mk(0.0);
+      for (int d = 0; d < 3; ++d) {
+        asv = asv + nsv[d] * c.md.A[k][d];
+        ash = ash + nsh[d] * c.md.A[k][d];
+      }
+      z[IA] = asv.r;
+      z[IA + 1] = asv.i;
+      z[IA + 2] = ash.r;
+      z[IA + 3] = ash.i;
+    }
+    rk4_step<MK_LAYERED>(m, spc, layc, (double)sigma, spc == 1, ec, z, (1.0 - c.th) * a.dt);
+    if (spc == 1) reframe_s(z, ec);
+    for (int f = 0; f < NS; ++f) a.f64[f * cap + slot] = z[f];
+    for (int d = 0; d < 3; ++d) a.f64[(FGA_E + d) * cap + slot] = ec[d];
+    a.f64[FGA_W_RE * cap + slot] = wr;
+    a.f64[FGA_W_IM * cap + slot] = wi;
+    a.i32[FGA_BRANCH * cap + slot] = spc == 0 ? 0 : 2;
+    a.i32[FGA_SIGMA * cap + slot] = sigma;
+    a.i32[FGA_LAYER * cap + slot] = layc;
+    a.i32[FGA_GEN * cap + slot] = gen + 1;
+    a.i32[FGA_FLAGS * cap + slot] = FGA_FLAG_ALIVE;
+    a.lineage[slot] = FGA_LINEAGE_CHILD(lin, gen, k);
+    ++nchild;
+  }
+  if (a.counters) {
+    atomicAdd(a.counters + 0, 1ull);
+    if (nchild) atomicAdd(a.counters + 1, nchild);
+    if (c.capped) atomicAdd(a.counters + 2, 1ull);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_interface(const DevMedium &m, const InterfaceArgs &a, int write, hipStream_t st)
+{
+  if (a.n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((a.n + 255) / 256);
+  if (write) hipLaunchKernelGGL(k_interface<true>, blocks, 256, 0, st, m, a);
+  else hipLaunchKernelGGL(k_interface<false>, blocks, 256, 0, st, m, a);
+  return hipGetLastError();
+}
+
+}  // namespace fga

@@ -309,3 +309,101 @@ def test_empty_beam_set():
     assert c == 0 and np.all(m.to_complex(g) == 0)
     seis, st = m.fga_evolve(m.Medium.homogeneous(1.7, 1.0), bs, 0.01, 3, receivers=x, eps=1 / 32)
     assert np.all(m.to_complex(seis) == 0) and st["beam_steps"] == 0
+
+
+# ---------------------------------------------------------------------------
+# layered media: interface splitting (Sec. 3.1)
+# ---------------------------------------------------------------------------
+
+LAYERED = {
+    "flat": (0, [0.42, 0.58], [1.7, 2.2, 1.9], [1.0, 1.3, 1.1], [1.0, 1.35, 1.2]),
+    "sphere": (1, [0.95, 0.8], [1.7, 2.1, 2.4], [1.0, 1.2, 1.4], [1.0, 1.25, 1.5]),
+}
+
+
+def initial_layers(ob, geometry, bounds):
+    """Layer index of each beam centre (interfaces: flat z = b_i, layer i
+    below; spheres |x| = b_i, layer i outside)."""
+    if geometry == 0:
+        v = ob["Q"][:, 2]
+        return np.array([sum(1 for b in bounds if z > b) for z in v], dtype=np.int32)
+    r = np.linalg.norm(ob["Q"], axis=1)
+    return np.array([sum(1 for b in bounds if x < b) for x in r], dtype=np.int32)
+
+
+def layered_case(name, nq=4, np_=2):
+    geo, bounds, cp, cs, rho = LAYERED[name]
+    w = small_c1(nq=nq, np_=np_, ny=16)
+    ob = om.decompose(w)
+    ob["layer"] = initial_layers(ob, geo, bounds)
+    return w, ob, om.layered(geo, bounds, cp, cs, rho), fga().Medium.layered(geo, bounds, cp, cs, rho)
+
+
+def alive_by_lineage(d):
+    keep = (d["flags"] & 1) == 1 if "flags" in d else d["alive"] == 1
+    return {k: v[keep] for k, v in d.items()}
+
+
+@pytest.mark.parametrize("name", ["flat", "sphere"])
+def test_interface_parity(name):
+    """Beams crossing flat or spherical interfaces split into the same
+    children (lineage, generation, layer, branch) with the same states."""
+    m = fga()
+    say("interface parity", name)
+    w, ob, med_o, med_g = layered_case(name)
+    nsteps, dt = 60, 0.005
+    out, ncap = om.evolve_layered(med_o, ob, dt, nsteps, gmax=3, child_cut=1e-3)
+    ref = alive_by_lineage(oracle_to_dict(out))
+    ref = {k: v[np.argsort(ref["lineage"], kind="stable")] for k, v in ref.items()}
+    assert (ref["gen"] > 0).sum() > 50, "test geometry should produce children"
+    bs = m.BeamSet(len(out) + 256)
+    bs.load(oracle_to_dict(ob))
+    _, st = m.fga_evolve(med_g, bs, dt, nsteps)
+    g = alive_by_lineage(bs.export())
+    g = by_lineage(g)
+    assert np.array_equal(g["lineage"], ref["lineage"])
+    for k in ("gen", "layer", "branch", "sigma"):
+        assert np.array_equal(g[k], ref[k]), k
+    assert st["capped"] == ncap
+    assert st["spawned"] == int((out["gen"] > 0).sum())
+    for k in ("Q", "P", "ZQ", "ZP"):
+        assert rel_l2(g[k], ref[k]) <= RTOL, k
+    keep = out["alive"] == 1
+    A_ref = om.amplitude_vectors(out[keep][np.argsort(out["lineage"][keep], kind="stable")])
+    assert rel_l2(phys_amp_gpu(g), A_ref) <= RTOL
+
+
+def test_interface_seismogram_parity():
+    """Receiver sums during a layered run, children included."""
+    m = fga()
+    say("interface seismograms")
+    w, ob, med_o, med_g = layered_case("flat")
+    rec = fi.uniform_points(9, np.random.default_rng(9), 0.2, 0.8)
+    nsteps, dt, tau, stride = 30, 0.005, 25.0, 3
+    bs = m.BeamSet(4 * len(ob))
+    bs.load(oracle_to_dict(ob))
+    seis, st = m.fga_evolve(med_g, bs, dt, nsteps, receivers=rec, eps=w.eps, tau=tau, stride=stride)
+    ref = np.zeros((len(rec), nsteps // stride, 3), dtype=np.complex128)
+    cnt = 0
+    cur = ob.copy()
+    for s in range(nsteps // stride):
+        cur, _ = om.evolve_layered(med_o, cur, dt, stride, gmax=3, child_cut=1e-3)
+        cur = cur[cur["alive"] == 1].copy()
+        u, c = om.sum_points(cur, rec, w.eps, tau)
+        ref[:, s, :] = u
+        cnt += c
+    assert st["spawned"] > 0
+    assert st["evals"] == cnt
+    assert rel_l2(m.to_complex(seis), ref) <= RTOL
+
+
+def test_interface_capacity_error():
+    """Children that do not fit the beam capacity stop the call with
+    FGA_ECAPACITY instead of being dropped."""
+    m = fga()
+    say("interface capacity")
+    w, ob, med_o, med_g = layered_case("flat")
+    bs = m.BeamSet(len(ob) + 3)
+    bs.load(oracle_to_dict(ob))
+    with pytest.raises(RuntimeError, match="capacity"):
+        m.fga_evolve(med_g, bs, 0.005, 60)
