@@ -293,6 +293,67 @@ fga_status fga_reconstruct_grid(const fga_beams *beams, double eps, double tau, 
                                 int64_t *evals);
 
 /* ------------------------------------------------------------------------ */
+/* Serving: forward solves for many sources on one GPU (tomography sweeps)   */
+/* ------------------------------------------------------------------------ */
+
+/* One forward solve: decompose the initial data, evolve with receivers and
+ * return the seismograms (Steps 1-3 of Sec. 2 for one source). */
+typedef struct {
+  fga_medium medium;        /* by value; a grid table it points to is device memory,
+                               built (and its build finished) before submit, that
+                               the caller keeps valid until the request completes   */
+  fga_mesh mesh;            /* decomposition mesh (eps = mesh.eps)                   */
+  const double *f;          /* host, complex [3][ny2][ny1][ny0] initial displacement
+                               ("+"-going with mesh.one_way); copied by submit      */
+  int64_t n_receivers;
+  const double *receivers;  /* host, [n_receivers][3]; copied by submit               */
+  double tau;               /* window parameter of the receiver sums                 */
+  double dt;
+  int nsteps;
+  int stride;               /* a sample after every stride-th step                   */
+  double *seis_out;         /* host, complex [n_receivers][nsteps/stride][3]; written
+                               before the completion is reported; caller-owned       */
+} fga_request;
+
+typedef struct {
+  uint64_t id;              /* as returned by fga_server_submit                      */
+  int status;               /* fga_status of the solve                               */
+  double t_submit, t_start, t_done;  /* seconds on the server's monotonic clock     */
+  size_t footprint;         /* device bytes the request held                         */
+  int64_t beams, beam_steps, evals;
+} fga_completion;
+
+typedef struct fga_server fga_server;
+
+/* Device bytes one request holds while it runs (beams, workspaces, inputs,
+ * seismograms); admission compares this with the budget. */
+size_t fga_server_footprint(const fga_request *r);
+
+/* A request server on the current device.  Requests are admitted in
+ * arrival order, skipping ahead to the first queued one that fits, whenever
+ * a slot is free (at most max_active at once) and the device bytes held by
+ * running requests plus the new one's footprint stay within hbm_budget.
+ * Each slot runs its request on its own stream from its own host thread,
+ * so admitted requests overlap on the device; a request's result does not
+ * depend on what runs beside it (each solve is deterministic).
+ * Errors: FGA_EINVAL (max_active < 1), FGA_EDEVICE. */
+fga_status fga_server_create(size_t hbm_budget, int max_active, fga_server **out);
+/* Queues a request (non-blocking; f and receivers are copied).  Errors:
+ * FGA_EINVAL (invalid request), FGA_ECAPACITY (footprint above the budget:
+ * it could never run). */
+fga_status fga_server_submit(fga_server *s, const fga_request *r, uint64_t *id);
+/* Moves up to max finished requests into out (completion order) and sets
+ * *n; waits up to wait_ms milliseconds for the first one when none is ready
+ * (0: do not wait). */
+fga_status fga_server_poll(fga_server *s, fga_completion *out, int max, int *n, int wait_ms);
+/* Current queue length, running requests and device bytes they hold, and the
+ * largest number of requests that have run at once. */
+fga_status fga_server_status(fga_server *s, int *queued, int *running, size_t *held, int *peak_running);
+/* Waits for every queued and running request, then frees the server;
+ * completions not yet polled are discarded. */
+fga_status fga_server_destroy(fga_server *s);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing                                                             */
 /* ------------------------------------------------------------------------ */
 

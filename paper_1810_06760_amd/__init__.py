@@ -38,7 +38,8 @@ EXPORTED = ["fga_last_error", "fga_version", "fga_medium_grid_table_bytes", "fga
             "fga_decompose_workspace_bytes", "fga_decompose_candidates", "fga_decompose",
             "fga_evolve_workspace_bytes", "fga_evolve", "fga_reconstruct_points_workspace_bytes",
             "fga_reconstruct_points", "fga_reconstruct_grid_workspace_bytes", "fga_reconstruct_grid",
-            "fga_profile_enable", "fga_profile_read"]
+            "fga_profile_enable", "fga_profile_read", "fga_server_footprint", "fga_server_create",
+            "fga_server_submit", "fga_server_poll", "fga_server_status", "fga_server_destroy"]
 FGA_K_INTEGRATE, FGA_K_SUM_POINTS, FGA_K_GRID_TILE, FGA_K_FBI_GEMM = 0, 1, 2, 3
 KERNEL_NAMES = {0: "integrate", 1: "sum_points", 2: "grid_tile", 3: "fbi_gemm"}
 
@@ -85,6 +86,18 @@ class EvolveStatsC(C.Structure):
                 ("quarantined", C.c_int64), ("crossings", C.c_int64), ("spawned", C.c_int64), ("capped", C.c_int64)]
 
 
+class RequestC(C.Structure):
+    _fields_ = [("medium", MediumC), ("mesh", MeshC), ("f", C.c_void_p), ("n_receivers", C.c_int64),
+                ("receivers", C.c_void_p), ("tau", C.c_double), ("dt", C.c_double), ("nsteps", C.c_int),
+                ("stride", C.c_int), ("seis_out", C.c_void_p)]
+
+
+class CompletionC(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double), ("footprint", C.c_size_t), ("beams", C.c_int64), ("beam_steps", C.c_int64),
+                ("evals", C.c_int64)]
+
+
 def lib():
     """Load libfga.so; raises if it has not been built."""
     global _lib
@@ -125,6 +138,18 @@ def lib():
         L.fga_profile_enable.argtypes = [C.c_int]
         L.fga_profile_read.restype = st
         L.fga_profile_read.argtypes = [C.c_int, vp, vp, C.c_int]
+        L.fga_server_footprint.restype = sz
+        L.fga_server_footprint.argtypes = [vp]
+        L.fga_server_create.restype = st
+        L.fga_server_create.argtypes = [sz, C.c_int, vp]
+        L.fga_server_submit.restype = st
+        L.fga_server_submit.argtypes = [vp, vp, vp]
+        L.fga_server_poll.restype = st
+        L.fga_server_poll.argtypes = [vp, vp, C.c_int, vp, C.c_int]
+        L.fga_server_status.restype = st
+        L.fga_server_status.argtypes = [vp, vp, vp, vp, vp]
+        L.fga_server_destroy.restype = st
+        L.fga_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -271,6 +296,8 @@ class Medium:
         nbytes = lib().fga_medium_grid_table_bytes(n, 1 if cs is not None else 0)
         table = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
         fga_medium_grid_build(n, h, cp, cs, table)
+        # complete before any other stream (a server slot) reads the table
+        torch.cuda.synchronize()
         m = MediumC()
         m.kind = FGA_MEDIUM_GRID
         m.n[:] = list(n)
@@ -442,3 +469,70 @@ def to_complex(t) -> np.ndarray:
     """float64 tensor with a trailing (re, im) axis -> complex numpy array."""
     a = t.detach().cpu().numpy()
     return a[..., 0] + 1j * a[..., 1]
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+def make_request(medium: Medium, mesh, f, receivers, tau: float, dt: float, nsteps: int, stride: int = 1):
+    """A forward-solve request: host initial data f (complex [3, nz, ny, nx])
+    and receivers (n, 3).  Returns (RequestC, seismogram array it fills:
+    complex [n, nsteps // stride, 3]); both must stay alive until completion."""
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.complex128))
+    x = np.ascontiguousarray(np.asarray(receivers, dtype=np.float64).reshape(-1, 3))
+    seis = np.zeros((x.shape[0], nsteps // stride, 3), dtype=np.complex128)
+    r = RequestC()
+    r.medium = medium.c
+    r.mesh = mesh
+    r.f = f.ctypes.data
+    r.n_receivers = x.shape[0]
+    r.receivers = x.ctypes.data
+    r.tau, r.dt, r.nsteps, r.stride = tau, dt, nsteps, stride
+    r.seis_out = seis.ctypes.data
+    return r, seis, (f, x, medium)
+
+
+class Server:
+    """fga_server: admits queued forward solves by device footprint into at
+    most max_active concurrent slots, each on its own stream."""
+
+    def __init__(self, hbm_budget: int, max_active: int):
+        _torch()
+        self._s = C.c_void_p()
+        _check(lib().fga_server_create(int(hbm_budget), int(max_active), C.byref(self._s)))
+        self._keep = {}
+
+    @staticmethod
+    def footprint(req: RequestC) -> int:
+        return int(lib().fga_server_footprint(C.byref(req)))
+
+    def submit(self, req: RequestC, keep=()) -> int:
+        i = C.c_uint64(0)
+        _check(lib().fga_server_submit(self._s, C.byref(req), C.byref(i)))
+        self._keep[i.value] = (req, keep)
+        return i.value
+
+    def poll(self, max_n: int = 64, wait_ms: int = 0):
+        out = (CompletionC * max_n)()
+        n = C.c_int(0)
+        _check(lib().fga_server_poll(self._s, out, max_n, C.byref(n), int(wait_ms)))
+        res = []
+        for k in range(n.value):
+            c = out[k]
+            self._keep.pop(c.id, None)
+            res.append({"id": c.id, "status": c.status, "t_submit": c.t_submit, "t_start": c.t_start,
+                        "t_done": c.t_done, "footprint": c.footprint, "beams": c.beams,
+                        "beam_steps": c.beam_steps, "evals": c.evals})
+        return res
+
+    def status(self):
+        q, r, pk = C.c_int(0), C.c_int(0), C.c_int(0)
+        h = C.c_size_t(0)
+        _check(lib().fga_server_status(self._s, C.byref(q), C.byref(r), C.byref(h), C.byref(pk)))
+        return {"queued": q.value, "running": r.value, "held": h.value, "peak_running": pk.value}
+
+    def close(self):
+        if self._s:
+            _check(lib().fga_server_destroy(self._s))
+            self._s = C.c_void_p()
