@@ -48,6 +48,13 @@ def parse():
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-beams", type=int, default=48, help="(q,p) pairs in the oracle sample")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving run instead: a seeded sweep of forward-solve requests over 4 resident models, "
+                         "saturated and at Poisson arrivals; prints solves/s with p50/p99 latency")
+    ap.add_argument("--requests", type=int, default=48, help="requests per serving phase")
+    ap.add_argument("--slots", type=int, default=4, help="concurrent request slots of the server")
+    ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="server device-memory budget")
+    ap.add_argument("--load", type=float, default=0.8, help="Poisson arrival rate as a fraction of saturated")
     ap.add_argument("--grid-precision", default="fp64", choices=list(GRID_PREC),
                     help="grid summation variant (mixed variants also report their error against FP64)")
     return ap.parse_args()
@@ -198,6 +205,103 @@ def cpu_baseline(w, tot_per_step, npairs, args):
             "seconds_per_step_extrapolated": full}
 
 
+def serve(args):
+    """Serving sweep: 4 resident smooth models (128^3), requests from the
+    seeded sweep generator; phase 1 submits all requests at once (saturated
+    throughput), phase 2 submits them at Poisson arrivals with rate
+    load x saturated throughput and reports latency percentiles."""
+    import torch
+    import fga_inputs as fi
+    import paper_1810_06760_amd as fga
+    torch.cuda.set_device(0)
+    models = [fga.Medium.grid(fi.sweep_model(j), fi.node_grid(128), cs_ratio=1.0 / math.sqrt(3.0)) for j in range(4)]
+    reqs = [fi.sweep_request(i) for i in range(args.requests)]
+
+    def request(rq):
+        mesh = fga.make_mesh(rq["eps"], rq["qmesh"], rq["pmesh"], rq["ymesh"], cull_abs=rq["cull_abs"])
+        return fga.make_request(models[rq["model"]], mesh, rq["f"], rq["receivers"], rq["tau"], rq["dt"],
+                                rq["nsteps"], 1)
+
+    budget = int(args.hbm_budget_gb * 2 ** 30)
+    # warm-up: one solve (module load, first allocations)
+    srv = fga.Server(budget, 1)
+    r, sz, keep = request(reqs[0])
+    srv.submit(r, keep=(keep, sz))
+    assert srv.poll(1, wait_ms=600000)[0]["status"] == 0
+    srv.close()
+
+    def phase(arrivals):
+        srv = fga.Server(budget, args.slots)
+        held = []
+        done = []
+        t0 = time.perf_counter()
+        try:
+            for k, rq in enumerate(reqs):
+                wait = arrivals[k] - (time.perf_counter() - t0)
+                if wait > 0:
+                    done += srv.poll(64, wait_ms=int(wait * 1000))
+                    rest = arrivals[k] - (time.perf_counter() - t0)
+                    if rest > 0:
+                        time.sleep(rest)
+                r, sz, keep = request(rq)
+                srv.submit(r, keep=(keep, sz))
+                held.append((r, sz, keep))
+            while len(done) < len(reqs):
+                got = srv.poll(64, wait_ms=600000)
+                if not got:
+                    raise RuntimeError("serving made no progress")
+                done += got
+                print("bench: %d of %d solves done" % (len(done), len(reqs)), file=sys.stderr, flush=True)
+            st = srv.status()
+        finally:
+            srv.close()
+        bad = [c for c in done if c["status"] != 0]
+        if bad:
+            raise RuntimeError("failed solves: %s" % bad[:3])
+        lat = np.array([c["t_done"] - c["t_submit"] for c in done])
+        span = max(c["t_done"] for c in done) - min(c["t_submit"] for c in done)
+        return {"solves_per_s": len(done) / span, "p50_s": float(np.percentile(lat, 50)),
+                "p99_s": float(np.percentile(lat, 99)), "makespan_s": span, "peak_running": st["peak_running"],
+                "beam_steps": int(sum(c["beam_steps"] for c in done)), "evals": int(sum(c["evals"] for c in done)),
+                "beams": [int(c["beams"]) for c in done]}
+
+    sat = phase([0.0] * len(reqs))
+    print("bench: saturated phase %.1f s, %.3f solves/s" % (sat["makespan_s"], sat["solves_per_s"]),
+          file=sys.stderr, flush=True)
+    rate = args.load * sat["solves_per_s"]
+    gen = np.random.default_rng(5999)
+    arrivals = np.cumsum(gen.exponential(1.0 / rate, len(reqs)))
+    arrivals -= arrivals[0]
+    poi = phase(list(arrivals))
+    beams = np.array(sat["beams"])
+    line = {
+        "metric": "served solves/s, p50/p99 latency",
+        "value": poi["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 1,
+        "ms_per_step": 1e3 / poi["solves_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "tomography sweep: %d requests over 4 resident 128^3 smooth random models, Gaussian "
+                               "packet sources at random centres/directions, eps in {1/32, 1/64, 1/128}, "
+                               "128..1024 receivers x 250 samples, 250 RK4 steps, FP64; Poisson arrivals at "
+                               "%.2f x saturated rate" % (len(reqs), args.load),
+                   "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb, "parallelism": "single GPU"},
+        "p50_s": poi["p50_s"], "p99_s": poi["p99_s"], "arrival_rate": rate,
+        "saturated": {k: sat[k] for k in ("solves_per_s", "p50_s", "p99_s", "makespan_s", "peak_running")},
+        "poisson_peak_running": poi["peak_running"],
+        "beams_per_request": {"min": int(beams.min()), "median": int(np.median(beams)), "max": int(beams.max())},
+        "beam_steps_per_s_saturated": sat["beam_steps"] / sat["makespan_s"],
+        "evals_per_s_saturated": sat["evals"] / sat["makespan_s"],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -205,6 +309,9 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus %d (WORLD_SIZE %d) is not supported"
               % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve(args)
+        return
     w, label = make_workload(args.workload, args.scale)
     elapsed, tot, prof = gpu_run(w, args)
     K = args.steps
