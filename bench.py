@@ -30,12 +30,18 @@ sys.path.insert(0, ROOT)
 #   one RK4 beam-step (4 right-hand sides + the update), per medium kind,
 #   one receiver/point term (window test excluded), one grid term.
 FLOP_BEAM_STEP = {"homogeneous": 3390, "grid": 4186}
-FLOP_POINT_EVAL = 101     # 41 arithmetic + exp (21) + sincos (39), counted from the gfx950 code
+FLOP_POINT_EVAL = 87      # FP64 flops per in-window receiver term (window test, exponent, phase, table
+                          # exp and sincos, 12 accumulating FMAs), FMA = 2, counted in the gfx950 code
 FLOP_GRID_EVAL = 24       # 3 complex multiply-adds
 PEAK_FP64 = 78.6e12       # FP64 vector and FP64 matrix peak, MI355X
 # grid summation variants: (library code, dense MFMA peak of the operand type)
 GRID_PREC = {"fp64": (0, 78.6e12), "fp32": (1, 157.3e12), "bf16x3": (2, 2.5e15), "fp16x3": (3, 2.5e15)}
 HBM_PEAK = 8.0e12
+# HBM bytes per launch of a kernel on the default workload (smooth, scale 1), from rocprofv3
+# FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy calibration; valid only while the kernel's
+# source is unchanged (sha256 prefix), else reported as null
+TRAFFIC = {"sum_points": {"source": "paper_1810_06760_amd/csrc/k_points.hip", "sha256": "961585de920b9c6c",
+                          "bytes_per_launch": 7.67545e9}}
 
 
 def parse():
@@ -47,6 +53,7 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0,
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--segments", type=int, default=4, help="evolution calls per step (progress between them)")
     ap.add_argument("--cpu-beams", type=int, default=48, help="(q,p) pairs in the oracle sample")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead: a seeded sweep of forward-solve requests over 4 resident models, "
@@ -55,6 +62,9 @@ def parse():
     ap.add_argument("--slots", type=int, default=4, help="concurrent request slots of the server")
     ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="server device-memory budget")
     ap.add_argument("--load", type=float, default=0.8, help="Poisson arrival rate as a fraction of saturated")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers (the known-size kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--grid-precision", default="fp64", choices=list(GRID_PREC),
                     help="grid summation variant (mixed variants also report their error against FP64)")
     return ap.parse_args()
@@ -90,15 +100,28 @@ def gpu_run(w, args):
     ws_dec = fga._workspace(fga.workspace_bytes("decompose", mesh=mesh))
     state = {"ws_ev": None, "ws_grid": None, "seis": None, "grid": None}
 
+    nseg = max(1, min(args.segments, w.nsteps))
+    seg = -(-w.nsteps // nseg)
+
     def step():
         fga.fga_decompose(med, mesh, f, beams=beams, ws=ws_dec)
         if state["ws_ev"] is None:
             state["ws_ev"] = fga._workspace(fga.workspace_bytes(
-                "evolve", beams=beams, nsteps=w.nsteps, n_receivers=0 if rec is None else rec.shape[0],
+                "evolve", beams=beams, nsteps=seg, n_receivers=0 if rec is None else rec.shape[0],
                 eps=w.eps, tau=w.tau))
-        seis, st = fga.fga_evolve(med, beams, w.dt, w.nsteps, receivers=rec, eps=w.eps, tau=w.tau,
-                                  seis=state["seis"], ws=state["ws_ev"])
-        state["seis"] = seis
+            if rec is not None:
+                state["seis"] = torch.empty((rec.shape[0], w.nsteps, 3, 2), dtype=torch.float64, device=dev)
+        # the evolution in a few calls of `seg` steps (progress lines between)
+        st = {"beam_steps": 0, "evals": 0}
+        for s0 in range(0, w.nsteps, seg):
+            n = min(seg, w.nsteps - s0)
+            part, st_k = fga.fga_evolve(med, beams, w.dt, n, receivers=rec, eps=w.eps, tau=w.tau,
+                                        ws=state["ws_ev"])
+            if rec is not None:
+                state["seis"][:, s0:s0 + n].copy_(part)
+            st["beam_steps"] += st_k["beam_steps"]
+            st["evals"] += st_k["evals"]
+            print("bench: steps %d..%d done" % (s0, s0 + n), file=sys.stderr, flush=True)
         ev_grid = 0
         if w.out_grid is not None:
             if state["ws_grid"] is None:
@@ -138,7 +161,19 @@ def gpu_run(w, args):
     return t1 - t0, tot, prof
 
 
-def roofline(tot, prof, medium_kind, grid_peak=PEAK_FP64):
+def traffic_for(name, default_workload):
+    """Measured HBM bytes per launch, if taken on this workload and this kernel source."""
+    import hashlib
+    t = TRAFFIC.get(name)
+    if t is None or not default_workload:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest()[:16] != t["sha256"]:
+            return None
+    return t["bytes_per_launch"]
+
+
+def roofline(tot, prof, medium_kind, grid_peak=PEAK_FP64, default_workload=False):
     """Dominant kernel: algorithmic FLOPs per launch / mean launch time."""
     work = {
         "integrate": tot["beam_steps"] * FLOP_BEAM_STEP[medium_kind],
@@ -153,7 +188,7 @@ def roofline(tot, prof, medium_kind, grid_peak=PEAK_FP64):
     bound = "mfma" if name == "grid_tile" else "alu"
     peak = grid_peak if name == "grid_tile" else PEAK_FP64
     return {"bound": bound, "kernel": name, "achieved": achieved / 1e12, "peak": peak / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic_for(name, default_workload),
             "launches": launches, "avg_launch_ms": ms / launches}, name
 
 
@@ -312,13 +347,22 @@ def main():
     if args.serve:
         serve(args)
         return
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(args.copy_calibration // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 8}), flush=True)
+        return
     w, label = make_workload(args.workload, args.scale)
     elapsed, tot, prof = gpu_run(w, args)
     K = args.steps
     per = {k: v / K for k, v in tot.items() if k != "grid_rel_l2_vs_fp64"}
     value = tot["beam_steps"] / elapsed
     kind = "grid" if w.medium_nodes is not None else "homogeneous"
-    roof, dom = roofline(tot, prof, kind, GRID_PREC[args.grid_precision][1])
+    roof, dom = roofline(tot, prof, kind, GRID_PREC[args.grid_precision][1],
+                         default_workload=(args.workload == "smooth" and args.scale == 1.0))
     line = {
         "metric": "beam-steps/s + beam-point evals/s; served solves/s, p50/p99 at rel-L2<=1e-3",
         "value": value,
