@@ -198,7 +198,9 @@ typedef struct {
   int stride;              /* a sample after every `stride` steps (>= 1)               */
   double eps, tau;         /* summation: 1/k and window exp(-tau) (half-width
                               sqrt(2 tau eps) per axis)                                */
-  int precision;           /* fga_precision of the receiver sums                       */
+  int precision;           /* FGA_FP64: FP64 sums; FGA_FP32 (mixed): the Gaussian
+                              exponent and the phase reduced modulo 2 pi in FP64, then
+                              exp / sin / cos in FP32, sums in FP64                    */
 } fga_receivers;
 
 typedef struct {
@@ -270,8 +272,9 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
 /* u(x) = sum_b w_b exp(i S_b/eps) A_b exp(i P_b.(x-Q_b)/eps - |x-Q_b|^2/(2 eps))
  * over the beams with max_d |x_d - Q_d| <= sqrt(2 tau eps), A_b = a_P P/|P| or
  * a_SV N_SV + a_SH N_SH.  xyz: device [n][3]; out: device complex [n][3]
- * (overwritten).  evals (host, may be NULL): number of in-window terms; the
- * call synchronises `stream` when evals != NULL. */
+ * (overwritten).  precision: FGA_FP64 or FGA_FP32 (as in fga_receivers);
+ * others give FGA_EUNSUPPORTED.  evals (host, may be NULL): number of
+ * in-window terms; the call synchronises `stream` when evals != NULL. */
 size_t fga_reconstruct_points_workspace_bytes(const fga_beams *beams, int64_t n);
 fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau, int64_t n,
                                   const double *xyz, int precision, double *out,
@@ -313,6 +316,7 @@ typedef struct {
   int stride;               /* a sample after every stride-th step                   */
   double *seis_out;         /* host, complex [n_receivers][nsteps/stride][3]; written
                                before the completion is reported; caller-owned       */
+  int precision;            /* receiver sums: FGA_FP64 or FGA_FP32 (mixed)            */
 } fga_request;
 
 typedef struct {

@@ -89,7 +89,7 @@ class EvolveStatsC(C.Structure):
 class RequestC(C.Structure):
     _fields_ = [("medium", MediumC), ("mesh", MeshC), ("f", C.c_void_p), ("n_receivers", C.c_int64),
                 ("receivers", C.c_void_p), ("tau", C.c_double), ("dt", C.c_double), ("nsteps", C.c_int),
-                ("stride", C.c_int), ("seis_out", C.c_void_p)]
+                ("stride", C.c_int), ("seis_out", C.c_void_p), ("precision", C.c_int)]
 
 
 class CompletionC(C.Structure):
@@ -475,7 +475,8 @@ def to_complex(t) -> np.ndarray:
 # serving
 # ---------------------------------------------------------------------------
 
-def make_request(medium: Medium, mesh, f, receivers, tau: float, dt: float, nsteps: int, stride: int = 1):
+def make_request(medium: Medium, mesh, f, receivers, tau: float, dt: float, nsteps: int, stride: int = 1,
+                 precision: int = FGA_FP64):
     """A forward-solve request: host initial data f (complex [3, nz, ny, nx])
     and receivers (n, 3).  Returns (RequestC, seismogram array it fills:
     complex [n, nsteps // stride, 3]); both must stay alive until completion."""
@@ -490,6 +491,7 @@ def make_request(medium: Medium, mesh, f, receivers, tau: float, dt: float, nste
     r.receivers = x.ctypes.data
     r.tau, r.dt, r.nsteps, r.stride = tau, dt, nsteps, stride
     r.seis_out = seis.ctypes.data
+    r.precision = precision
     return r, seis, (f, x, medium)
 
 

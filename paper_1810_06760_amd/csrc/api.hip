@@ -388,7 +388,8 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
     if (rec->stride < 1) return fail(FGA_EINVAL, "receiver stride must be >= 1");
     if (rec->n < 0 || (rec->n > 0 && !rec->xyz)) return fail(FGA_EINVAL, "receiver positions invalid");
     if (!(rec->eps > 0) || !(rec->tau > 0)) return fail(FGA_EINVAL, "receiver eps and tau must be > 0");
-    if (rec->precision != FGA_FP64) return fail(FGA_EUNSUPPORTED, "receiver precision %d not built", rec->precision);
+    if (rec->precision != FGA_FP64 && rec->precision != FGA_FP32)
+      return fail(FGA_EUNSUPPORTED, "receiver precision %d not built (FGA_FP64, FGA_FP32)", rec->precision);
     if (!seis && rec->n > 0 && nsteps / rec->stride > 0) return fail(FGA_EINVAL, "seis is NULL");
   }
   hipStream_t st = (hipStream_t)stream;
@@ -476,6 +477,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
           pa.evals = ctr + 3;
           pa.tile_box = wb.box;
           pa.ntiles = (pa.nb + 63) / 64;
+          pa.precision = rec->precision;
           int nblk = 0;
           FGA_HIP(launch_sum_points(pa, &nblk, st));
           FGA_HIP(launch_reduce_points(partial, nblk, 1, rec->n, wb.perm, seis, p.nsamp, sample, b0 > 0 ? 1 : 0, st));
@@ -529,6 +531,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
         pa.evals = ctr + 3;
         pa.tile_box = wb.box;
         pa.ntiles = (pa.nb + 63) / 64;
+        pa.precision = rec->precision;
         int nblk = 0;
         FGA_HIP(launch_sum_points(pa, &nblk, st));
         FGA_HIP(launch_reduce_points(partial, nblk, ns, rec->n, wb.perm, seis, p.nsamp, sfirst, b0 > 0 ? 1 : 0,
@@ -585,7 +588,8 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
   if ((s = check_beams(beams)) != FGA_OK) return s;
   if (n < 0 || (n > 0 && (!xyz || !out))) return fail(FGA_EINVAL, "points invalid");
   if (!(eps > 0) || !(tau > 0)) return fail(FGA_EINVAL, "eps and tau must be > 0");
-  if (precision != FGA_FP64) return fail(FGA_EUNSUPPORTED, "point precision %d not built", precision);
+  if (precision != FGA_FP64 && precision != FGA_FP32)
+    return fail(FGA_EUNSUPPORTED, "point precision %d not built (FGA_FP64, FGA_FP32)", precision);
   hipStream_t st = (hipStream_t)stream;
   const int64_t nb = beams->count;
   const int64_t batch = nb < ((int64_t)1 << 22) ? (nb > 0 ? nb : 1) : ((int64_t)1 << 22);
@@ -619,6 +623,7 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
     pa.evals = ctr;
     pa.tile_box = box;
     pa.ntiles = (pa.nb + 63) / 64;
+    pa.precision = precision;
     int nblk = 0;
     FGA_HIP(launch_sum_points(pa, &nblk, st));
     FGA_HIP(launch_reduce_points(partial, nblk, 1, n, perm, out, 1, 0, b0 > 0 ? 1 : 0, st));

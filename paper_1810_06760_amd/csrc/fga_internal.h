@@ -111,6 +111,7 @@ struct PointsArgs {
   unsigned long long *evals;
   double *tile_box;          // scratch [m][ntiles][6], ntiles = ceil(nb / 64)
   int64_t ntiles;
+  int precision;             // FGA_FP64, or FGA_FP32: FP32 exp/sin/cos of FP64-reduced arguments
 };
 hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st);
 // beams walked by one point-sum workgroup for nb beams, n points and m samples

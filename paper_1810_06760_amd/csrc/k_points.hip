@@ -45,6 +45,13 @@ __device__ __forceinline__ PointsWork points_work(int64_t id, int groups, int64_
   return w;
 }
 
+constexpr double INV_2PI = 0.15915494309189535;
+constexpr double LOG2E = 1.4426950408889634;
+
+// MIXED: the exponent and the phase (in revolutions, reduced to [-1/2, 1/2])
+// are formed in FP64, then exp2 / sin / cos run on the FP32 transcendental
+// unit; sums stay FP64.  Otherwise the FP64 table-driven exponential.
+template <bool MIXED>
 __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, int64_t nblk)
 {
   __shared__ TrigTables tab;
@@ -149,7 +156,15 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
       for (int h = 0; h < 4; ++h) {
         const double g = in[h] ? (dd[h][0] * dd[h][0] + dd[h][1] * dd[h][1] + dd[h][2] * dd[h][2]) * hieps : 2048.0;
         const double ph = in[h] ? pe[0] * dd[h][0] + pe[1] * dd[h][1] + pe[2] * dd[h][2] : 0.0;
-        cexp_neg(tab, g, ph, er[h], ei[h]);
+        if constexpr (MIXED) {
+          const double rev = ph * INV_2PI;
+          const float r = (float)(rev - rint(rev));
+          const float amp = in[h] ? __builtin_amdgcn_exp2f((float)(-g * LOG2E)) : 0.0f;
+          er[h] = (double)(amp * __builtin_amdgcn_cosf(r));
+          ei[h] = (double)(amp * __builtin_amdgcn_sinf(r));
+        } else {
+          cexp_neg(tab, g, ph, er[h], ei[h]);
+        }
       }
 #pragma unroll
       for (int h = 0; h < 4; ++h)
@@ -269,7 +284,8 @@ hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st)
   const int64_t nwg = units * groups;
   if (nwg > 0x7fffffff) return hipErrorInvalidConfiguration;
   ProfScope prof(FGA_K_SUM_POINTS, st);
-  hipLaunchKernelGGL(k_sum_points, dim3((unsigned)nwg), 256, 0, st, a, groups, nblk);
+  if (a.precision == FGA_FP32) hipLaunchKernelGGL(k_sum_points<true>, dim3((unsigned)nwg), 256, 0, st, a, groups, nblk);
+  else hipLaunchKernelGGL(k_sum_points<false>, dim3((unsigned)nwg), 256, 0, st, a, groups, nblk);
   return hipGetLastError();
 }
 

@@ -21,8 +21,6 @@
 
 namespace {
 
-constexpr size_t kBeamBytes = FGA_NF64 * sizeof(double) + FGA_NI32 * sizeof(int32_t) + sizeof(int64_t);
-
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Sizes {
@@ -33,6 +31,7 @@ struct Sizes {
 bool request_sizes(const fga_request *r, Sizes *z)
 {
   if (!r || r->nsteps < 0 || r->stride < 1 || r->n_receivers < 0) return false;
+  if (r->precision != FGA_FP64 && r->precision != FGA_FP32) return false;
   const int64_t cand = fga_decompose_candidates(&r->mesh);
   if (cand <= 0) return false;
   // layered media grow the beam set at interfaces
@@ -56,7 +55,7 @@ bool request_sizes(const fga_request *r, Sizes *z)
   rc.stride = r->stride;
   rc.eps = r->mesh.eps;
   rc.tau = r->tau;
-  rc.precision = FGA_FP64;
+  rc.precision = r->precision;
   const size_t wd = fga_decompose_workspace_bytes(&r->mesh, 0);
   const size_t we = fga_evolve_workspace_bytes(&b, r->nsteps, nullptr, r->n_receivers > 0 ? &rc : nullptr);
   z->ws = align256(wd > we ? wd : we);
@@ -144,7 +143,7 @@ fga_completion fga_server::run(Job &j, hipStream_t st)
     rc.stride = r.stride;
     rc.eps = r.mesh.eps;
     rc.tau = r.tau;
-    rc.precision = FGA_FP64;
+    rc.precision = r.precision;
     fga_evolve_stats es{};
     if ((s = fga_evolve(&r.medium, &b, r.dt, r.nsteps, nullptr, r.n_receivers > 0 ? &rc : nullptr, sd, ws, j.sz.ws,
                         st, &es)) != FGA_OK)

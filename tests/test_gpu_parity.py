@@ -195,6 +195,24 @@ def test_points_parity():
         assert rel_l2(m.to_complex(ug), uo) <= RTOL
 
 
+def test_points_mixed_precision():
+    """Receiver sums in mixed mode (FP64 arguments, FP32 exp/sin/cos, FP64
+    sums) against the oracle: relative L2 <= 1e-3, exact in-window count."""
+    m = fga()
+    say("points mixed")
+    w = small_c1(nq=5, np_=3, ny=16)
+    ob = evolved_beams(w, 40, 0.005)
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    x = fi.uniform_points(300, np.random.default_rng(2), -0.2, 1.2)
+    uo, co = om.sum_points(ob, x, w.eps, 16.0)
+    ug, cg = m.fga_reconstruct_points(bs, w.eps, 16.0, x, precision=m.FGA_FP32)
+    assert cg == co
+    err = rel_l2(m.to_complex(ug), uo)
+    say("  rel L2", err)
+    assert err <= 1e-3
+
+
 def test_points_tile_skip():
     """Points spread far beyond the beams with a narrow window: most beam
     tiles lie outside every point group's reach and are skipped whole; the
@@ -296,6 +314,25 @@ def test_seismogram_parity():
     assert st["evals"] == cnt
     assert st["beam_steps"] == nsteps * len(ob)
     assert rel_l2(m.to_complex(seis), ref) <= RTOL
+
+
+def test_seismogram_mixed_precision():
+    m = fga()
+    say("seismogram mixed")
+    w = small_c2(nq=4, np_=2, ny=16)
+    ob = om.decompose(w)
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    rec = w.receivers
+    nsteps, dt, tau = 24, 2e-3, 16.0
+    seis, st = m.fga_evolve(m.medium_for(w), bs, dt, nsteps, receivers=rec, eps=w.eps, tau=tau, stride=3,
+                            precision=m.FGA_FP32)
+    med_o = om.medium_for(w)
+    ref = np.zeros((len(rec), nsteps // 3, 3), dtype=np.complex128)
+    for s in range(nsteps // 3):
+        om.evolve(med_o, ob, dt, 3)
+        ref[:, s, :] = om.sum_points(ob, rec, w.eps, tau)[0]
+    assert rel_l2(m.to_complex(seis), ref) <= 1e-3
 
 
 def test_empty_beam_set():

@@ -104,6 +104,31 @@ def test_server_matches_direct_calls():
 
 
 @pytest.mark.gpu
+def test_mixed_precision_requests():
+    """Served solves in mixed mode stay within 1e-3 of the FP64 ones."""
+    m = fga()
+    say("serving mixed")
+    reqs, keep = build_requests(m)
+    srv = m.Server(1 << 34, 2)
+    outs = {}
+    try:
+        for i, r in enumerate(reqs[:3]):
+            for prec in (m.FGA_FP64, m.FGA_FP32):
+                rq, s, k = m.make_request(*r, precision=prec)
+                outs[srv.submit(rq, keep=(k, s))] = (i, prec, s)
+        got = []
+        while len(got) < 6:
+            got += srv.poll(8, wait_ms=20000)
+    finally:
+        srv.close()
+    assert all(c["status"] == 0 for c in got)
+    res = {(i, p): s for i, p, s in outs.values()}
+    for i in range(3):
+        a, b = res[(i, m.FGA_FP32)], res[(i, m.FGA_FP64)]
+        assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b)
+
+
+@pytest.mark.gpu
 def test_budget_limits_concurrency():
     """With a budget that fits one request at a time, solves run one by one
     even with several free slots; a request above the budget is refused."""
