@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--slots", type=int, default=4, help="concurrent request slots of the server")
     ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="server device-memory budget")
     ap.add_argument("--load", type=float, default=0.8, help="Poisson arrival rate as a fraction of saturated")
+    ap.add_argument("--serve-precision", default="fp64", choices=["fp64", "mixed"],
+                    help="receiver sums of the served solves (mixed: FP32 exp/sin/cos of FP64-reduced arguments; "
+                         "the run then also reports its error against FP64 solves of the first 8 requests)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (the known-size kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -252,10 +255,12 @@ def serve(args):
     models = [fga.Medium.grid(fi.sweep_model(j), fi.node_grid(128), cs_ratio=1.0 / math.sqrt(3.0)) for j in range(4)]
     reqs = [fi.sweep_request(i) for i in range(args.requests)]
 
-    def request(rq):
+    prec = fga.FGA_FP32 if args.serve_precision == "mixed" else fga.FGA_FP64
+
+    def request(rq, precision=None):
         mesh = fga.make_mesh(rq["eps"], rq["qmesh"], rq["pmesh"], rq["ymesh"], cull_abs=rq["cull_abs"])
         return fga.make_request(models[rq["model"]], mesh, rq["f"], rq["receivers"], rq["tau"], rq["dt"],
-                                rq["nsteps"], 1)
+                                rq["nsteps"], 1, precision=prec if precision is None else precision)
 
     budget = int(args.hbm_budget_gb * 2 ** 30)
     # warm-up: one solve (module load, first allocations)
@@ -293,9 +298,12 @@ def serve(args):
         bad = [c for c in done if c["status"] != 0]
         if bad:
             raise RuntimeError("failed solves: %s" % bad[:3])
+        seis_by_req = {}
+        for k, (r, sz, keep) in enumerate(held):
+            seis_by_req[k] = sz
         lat = np.array([c["t_done"] - c["t_submit"] for c in done])
         span = max(c["t_done"] for c in done) - min(c["t_submit"] for c in done)
-        return {"solves_per_s": len(done) / span, "p50_s": float(np.percentile(lat, 50)),
+        return {"seis": seis_by_req, "solves_per_s": len(done) / span, "p50_s": float(np.percentile(lat, 50)),
                 "p99_s": float(np.percentile(lat, 99)), "makespan_s": span, "peak_running": st["peak_running"],
                 "beam_steps": int(sum(c["beam_steps"] for c in done)), "evals": int(sum(c["evals"] for c in done)),
                 "beams": [int(c["beams"]) for c in done]}
@@ -309,6 +317,21 @@ def serve(args):
     arrivals -= arrivals[0]
     poi = phase(list(arrivals))
     beams = np.array(sat["beams"])
+    err = None
+    if prec != fga.FGA_FP64:
+        # the same first 8 requests in FP64, one slot
+        srv = fga.Server(budget, args.slots)
+        ref = {}
+        try:
+            for k in range(min(8, len(reqs))):
+                r, sz, keep = request(reqs[k], fga.FGA_FP64)
+                ref[srv.submit(r, keep=(keep, sz))] = (k, sz)
+            got = []
+            while len(got) < len(ref):
+                got += srv.poll(16, wait_ms=600000)
+        finally:
+            srv.close()
+        err = max(float(np.linalg.norm(sat["seis"][k] - sz) / np.linalg.norm(sz)) for k, sz in ref.values())
     line = {
         "metric": "served solves/s, p50/p99 latency",
         "value": poi["solves_per_s"],
@@ -320,12 +343,14 @@ def serve(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == fga.FGA_FP64 else "f64+f32",
         "data": "synthetic",
         "config": {"workload": "tomography sweep: %d requests over 4 resident 128^3 smooth random models, Gaussian "
                                "packet sources at random centres/directions, eps in {1/32, 1/64, 1/128}, "
-                               "128..1024 receivers x 250 samples, 250 RK4 steps, FP64; Poisson arrivals at "
-                               "%.2f x saturated rate" % (len(reqs), args.load),
+                               "128..1024 receivers x 250 samples, 250 FP64 RK4 steps, %s receiver sums; "
+                               "Poisson arrivals at %.2f x saturated rate"
+                               % (len(reqs), "FP64" if prec == fga.FGA_FP64 else "mixed (FP32 exp/sin/cos)",
+                                  args.load),
                    "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb, "parallelism": "single GPU"},
         "p50_s": poi["p50_s"], "p99_s": poi["p99_s"], "arrival_rate": rate,
         "saturated": {k: sat[k] for k in ("solves_per_s", "p50_s", "p99_s", "makespan_s", "peak_running")},
@@ -334,6 +359,8 @@ def serve(args):
         "beam_steps_per_s_saturated": sat["beam_steps"] / sat["makespan_s"],
         "evals_per_s_saturated": sat["evals"] / sat["makespan_s"],
     }
+    if err is not None:
+        line["max_rel_l2_vs_fp64_first8"] = err
     print(json.dumps(line), flush=True)
 
 
