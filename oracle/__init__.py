@@ -64,6 +64,13 @@ class Medium(C.Structure):
 HOMOGENEOUS, GRID, BUMP, LINEAR, LAYERED = 0, 1, 2, 3, 4
 
 
+class PointSource(C.Structure):
+    _fields_ = [("eps", C.c_double), ("x0", C.c_double * 3), ("M", C.c_double * 6), ("rho0", C.c_double),
+                ("nq", C.c_int), ("qhalf", C.c_double), ("ndir", C.c_int), ("nshell", C.c_int),
+                ("shell_lo", C.c_double), ("shell_hi", C.c_double), ("ricker", C.c_int), ("branch_mask", C.c_int),
+                ("cull_abs", C.c_double)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -93,6 +100,15 @@ def lib():
         L.om_child_lineage.argtypes = [C.c_int64, C.c_int, C.c_int]
         L.om_layer_exit.restype = C.c_int
         L.om_layer_exit.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.om_point_source_beams.restype = C.c_int64
+        L.om_point_source_beams.argtypes = [vp, vp, vp]
+        L.om_point_source_size.restype = C.c_size_t
+        L.om_fibonacci_dirs.argtypes = [C.c_int, vp]
+        L.om_gauss_legendre.argtypes = [C.c_int, C.c_double, C.c_double, vp, vp]
+        L.om_ricker.restype = C.c_double
+        L.om_ricker.argtypes = [C.c_double, C.c_double]
+        if L.om_point_source_size() != C.sizeof(PointSource):
+            raise RuntimeError("oracle point-source layout mismatch")
         L.om_medium_size.restype = C.c_size_t
         if L.om_medium_size() != C.sizeof(Medium):
             raise RuntimeError("oracle medium layout mismatch")
@@ -297,6 +313,52 @@ def interface_jacobians(normal, Pin, Pout, c_in, c_out, ZQ, ZP, grad_in=(0, 0, 0
     lib().om_interface_jacobians(_p(args[0]), _p(args[1]), _p(args[2]), c_in, c_out, _p(g[0]), _p(g[1]),
                                  _p(ZQ), _p(ZP))
     return ZQ, ZP
+
+
+def point_source(eps, x0, M, nq, qhalf=None, ndir=64, nshell=4, shell_lo=0.2, shell_hi=2.5, ricker=True,
+                 rho0=0.0, branch_mask=7, cull_abs=0.0) -> PointSource:
+    """Parameters of a point moment-tensor source (M = xx, yy, zz, xy, xz, yz)."""
+    src = PointSource()
+    src.eps = eps
+    src.x0[:] = list(x0)
+    src.M[:] = list(M)
+    src.rho0 = rho0
+    src.nq = nq
+    src.qhalf = 4.0 * eps ** 0.5 if qhalf is None else qhalf
+    src.ndir, src.nshell = ndir, nshell
+    src.shell_lo, src.shell_hi = shell_lo, shell_hi
+    src.ricker = 1 if ricker else 0
+    src.branch_mask = branch_mask
+    src.cull_abs = cull_abs
+    return src
+
+
+def point_source_candidates(src: PointSource) -> int:
+    return src.nq ** 3 * src.ndir * src.nshell * bin(src.branch_mask & 7).count("1") * 2
+
+
+def point_source_beams(med: OracleMedium, src: PointSource) -> np.ndarray:
+    """Beams of a point moment-tensor source (closed-form weights), lineage order."""
+    out = np.zeros(point_source_candidates(src), dtype=BEAM_DTYPE)
+    n = lib().om_point_source_beams(med.ref, C.byref(src), _p(out))
+    return out[:n].copy()
+
+
+def fibonacci_dirs(n: int) -> np.ndarray:
+    d = np.zeros((n, 3))
+    lib().om_fibonacci_dirs(n, _p(d))
+    return d
+
+
+def gauss_legendre(n: int, a: float, b: float):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    lib().om_gauss_legendre(n, a, b, _p(x), _p(w))
+    return x, w
+
+
+def ricker(w: float, w0: float) -> float:
+    return lib().om_ricker(w, w0)
 
 
 def child_lineage(parent: int, gen: int, k: int) -> int:

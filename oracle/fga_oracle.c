@@ -600,6 +600,170 @@ int64_t om_sum_points(const om_beam *beams, int64_t nb, const double *x, int64_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* Point moment-tensor source (initial data for Step 1, closed form)         */
+/* ------------------------------------------------------------------------ */
+
+/* The paper's seismic examples use point sources whose decomposition it
+ * defers to another paper; the reading used here: an impulsive moment-tensor
+ * source is the initial velocity g = -(1/rho0) M grad delta(x - x0), u(0) = 0.
+ * Then FBI[g/c_b](q,p) = (1/rho0) M . grad_y [K(y)/c_b(y)] at y = x0
+ * (integration by parts), K(y) = exp(-i p.(y-q)/eps - |y-q|^2/(2 eps)), and
+ * with f = 0 the weights are psi_{b,+-} = +-(i eps/(2|p|)) FBI[g/c_b].n_b.
+ * A Ricker source wavelet multiplies each beam, whose frequency is
+ * c_b |p| / eps, by R(w) = (w/w0)^2 exp(1 - (w/w0)^2), w0 = c_P(x0)/eps.
+ * Meshes: q on nq^3 cell-centred points of the cube x0 +- qhalf; p on
+ * Fibonacci directions times Gauss-Legendre |p| shells on
+ * [shell_lo, shell_hi] * c_P(x0)/c_b(x0), measure |p|^2 w_shell 4 pi / ndir. */
+typedef struct {
+  double eps;
+  double x0[3];
+  double M[6];           /* xx, yy, zz, xy, xz, yz                       */
+  double rho0;
+  int nq;
+  double qhalf;
+  int ndir, nshell;
+  double shell_lo, shell_hi;
+  int ricker;
+  int branch_mask;
+  double cull_abs;
+} om_point_source;
+
+/* Unit vectors on the golden spiral: z_i = 1 - (2i+1)/n, azimuth i pi (3 - sqrt 5). */
+void om_fibonacci_dirs(int n, double *d)
+{
+  const double ga = M_PI * (3.0 - sqrt(5.0));
+  for (int i = 0; i < n; ++i) {
+    const double z = 1.0 - (2.0 * i + 1.0) / n;
+    const double r = sqrt(fmax(0.0, 1.0 - z * z));
+    d[3 * i] = r * cos(ga * i);
+    d[3 * i + 1] = r * sin(ga * i);
+    d[3 * i + 2] = z;
+  }
+}
+
+/* Gauss-Legendre nodes and weights on [a, b]: Newton iteration on P_n from
+ * the Chebyshev-like guesses cos(pi (i + 3/4)/(n + 1/2)). */
+void om_gauss_legendre(int n, double a, double b, double *x, double *w)
+{
+  for (int i = 0; i < n; ++i) {
+    double t = cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = t; p0 = 1.0; }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      const double dt = p1 / dp;
+      t -= dt;
+      if (fabs(dt) < 1e-16) break;
+    }
+    /* recompute the derivative at the converged node */
+    double p0 = 1.0, p1 = t;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (n == 1) { p1 = t; p0 = 1.0; }
+    dp = n * (t * p1 - p0) / (t * t - 1.0);
+    x[i] = 0.5 * (a + b) + 0.5 * (b - a) * t;
+    w[i] = (b - a) / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+double om_ricker(double w, double w0)
+{
+  const double r = (w / w0) * (w / w0);
+  return r * exp(1.0 - r);
+}
+
+/* The beams of a point source, in lineage order
+ * ((branch*2 + dir) * Np + ip) * Nq + iq with ip = shell * ndir + direction;
+ * returns the number written (out must hold the candidate count). */
+int64_t om_point_source_beams(const om_medium *m, const om_point_source *src, om_beam *out)
+{
+  const int L0 = om_layer_of(m, src->x0);
+  double cP, gP[3], HP[3][3];
+  om_speed(m, 0, L0, src->x0, &cP, gP, HP);
+  const double rho0 = src->rho0 > 0.0 ? src->rho0
+                      : (m->kind == OM_LAYERED ? m->rhol[L0] : (m->rho > 0.0 ? m->rho : 1.0));
+  const int nq = src->nq, Nq = nq * nq * nq, Np = src->ndir * src->nshell;
+  const double hq = 2.0 * src->qhalf / nq, dq = hq * hq * hq;
+  double *dirs = malloc(sizeof(double) * 3 * src->ndir);
+  double *xs = malloc(sizeof(double) * src->nshell), *ws = malloc(sizeof(double) * src->nshell);
+  om_fibonacci_dirs(src->ndir, dirs);
+  const double eps = src->eps, norm = pow(2.0 * M_PI * eps, -4.5);
+  int64_t nb = 0;
+  for (int br = 0; br < 3; ++br) {
+    if (!(src->branch_mask & (1 << br))) continue;
+    const int sp = br == 0 ? 0 : 1;
+    double cb, gb[3], Hb[3][3];
+    om_speed(m, sp, L0, src->x0, &cb, gb, Hb);
+    om_gauss_legendre(src->nshell, src->shell_lo * cP / cb, src->shell_hi * cP / cb, xs, ws);
+    for (int si = 0; si < 2; ++si) {
+      const int sg = si == 0 ? 1 : -1;
+      for (int ip = 0; ip < Np; ++ip) {
+        const int sh = ip / src->ndir, dj = ip % src->ndir;
+        double p[3];
+        for (int k = 0; k < 3; ++k) p[k] = xs[sh] * dirs[3 * dj + k];
+        const double np = xs[sh];
+        const double dp = np * np * ws[sh] * 4.0 * M_PI / src->ndir;
+        double e[3], nh[3];
+        om_initial_axis(p, e);
+        om_polarisation(br, p, e, nh);
+        const double rk = src->ricker ? om_ricker(cb * np / eps, cP / eps) : 1.0;
+        for (int iq = 0; iq < Nq; ++iq) {
+          const int ix = iq % nq, iy = (iq / nq) % nq, iz = iq / (nq * nq);
+          double q[3] = {src->x0[0] - src->qhalf + (ix + 0.5) * hq, src->x0[1] - src->qhalf + (iy + 0.5) * hq,
+                         src->x0[2] - src->qhalf + (iz + 0.5) * hq};
+          double d[3] = {src->x0[0] - q[0], src->x0[1] - q[1], src->x0[2] - q[2]};
+          const cplx K = cexp(-I * dot3(p, d) / eps - dot3(d, d) / (2.0 * eps));
+          cplx gradKc[3];
+          for (int j = 0; j < 3; ++j)
+            gradKc[j] = K * (-I * p[j] / eps - d[j] / eps) / cb - K * gb[j] / (cb * cb);
+          const double Mm[3][3] = {{src->M[0], src->M[3], src->M[4]},
+                                   {src->M[3], src->M[1], src->M[5]},
+                                   {src->M[4], src->M[5], src->M[2]}};
+          cplx G[3];
+          for (int i = 0; i < 3; ++i) {
+            G[i] = 0.0;
+            for (int j = 0; j < 3; ++j) G[i] += Mm[i][j] * gradKc[j];
+            G[i] /= rho0;
+          }
+          const cplx gn = G[0] * nh[0] + G[1] * nh[1] + G[2] * nh[2];
+          const cplx psi = sg * I * eps / (2.0 * np) * gn * rk;
+          if (cabs(psi) < src->cull_abs) continue;
+          om_beam *b = &out[nb++];
+          memset(b, 0, sizeof(*b));
+          memcpy(b->Q, q, sizeof(q));
+          memcpy(b->P, p, sizeof(p));
+          for (int i = 0; i < 3; ++i) { b->ZQ[i][i] = 1.0; b->ZP[i][i] = -I; }
+          const double a0 = pow(2.0, 1.5);
+          if (br == 1) { b->a[0] = 0; b->a[1] = a0; }
+          else { b->a[0] = a0; b->a[1] = 0; }
+          b->w = psi * dq * dp * norm;
+          memcpy(b->e, e, sizeof(e));
+          b->branch = br;
+          b->sigma = sg;
+          b->layer = om_layer_of(m, q);
+          b->alive = 1;
+          b->lineage = ((int64_t)(br * 2 + si) * Np + ip) * Nq + iq;
+        }
+      }
+    }
+  }
+  free(dirs);
+  free(xs);
+  free(ws);
+  return nb;
+}
+
+size_t om_point_source_size(void) { return sizeof(om_point_source); }
+
+/* ------------------------------------------------------------------------ */
 /* Interfaces (Sec. 3.1, eq:p:int, eq:Yilmaz, eq:Inter_DzQDzP)               */
 /* ------------------------------------------------------------------------ */
 
