@@ -185,6 +185,43 @@ fga_status fga_decompose(const fga_medium *med, const fga_mesh *mesh, const doub
                          const double *g, fga_beams *beams, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/* Point moment-tensor source (the seismic examples of Sec. 3.2 and Sec. 4
+ * use point sources whose decomposition the paper takes from elsewhere; the
+ * reading used here): u(0) = 0, u_t(0) = g = -(1/rho0) M grad delta(x - x0),
+ * whose FBI is closed-form, FBI[g/c_b](q,p) = (1/rho0) M . grad_y[K(y)/c_b(y)]
+ * at y = x0 with K the FBI kernel; psi_{b,+-} = +-(i eps/(2|p|))
+ * FBI[g/c_b].n_b (eq:psi, eq:alpha^k with f = 0).  Both directions and the
+ * branches of branch_mask are made.  With ricker != 0 each beam's weight is
+ * multiplied by R(w) = (w/w0)^2 exp(1 - (w/w0)^2) at its frequency
+ * w = c_b(x0)|p|/eps, w0 = c_P(x0)/eps (zero-phase Ricker wavelet).
+ * q mesh: nq^3 cell-centred points of the cube x0 +- qhalf.  p mesh per
+ * branch: ndir Fibonacci directions (z_j = 1 - (2j+1)/ndir, azimuth
+ * j pi (3 - sqrt 5)) times nshell Gauss-Legendre |p| shells on
+ * [shell_lo, shell_hi] * c_P(x0)/c_b(x0); the p-cell measure is
+ * |p|^2 w_shell 4 pi / ndir.  Lineage ((branch*2 + dir)*Np + ip)*Nq + iq with
+ * ip = shell*ndir + j, iq = (iz*nq + iy)*nq + ix. */
+typedef struct {
+  double eps;
+  double x0[3];
+  double M[6];              /* symmetric moment tensor: xx, yy, zz, xy, xz, yz      */
+  double rho0;              /* density at x0 (<= 0: the medium's)                    */
+  int nq;
+  double qhalf;
+  int ndir, nshell;         /* 1 <= nshell <= 64                                     */
+  double shell_lo, shell_hi;
+  int ricker;
+  int branch_mask;
+  double cull_abs;          /* beams with |psi| < cull_abs are not made              */
+} fga_point_source;
+
+int64_t fga_point_source_candidates(const fga_point_source *src);
+size_t fga_decompose_point_source_workspace_bytes(const fga_point_source *src);
+/* Writes the kept beams in lineage order and sets beams->count (synchronises
+ * `stream`).  Errors: FGA_EINVAL, FGA_ENOMEM (workspace), FGA_ECAPACITY. */
+fga_status fga_decompose_point_source(const fga_medium *med, const fga_point_source *src,
+                                      fga_beams *beams, void *workspace, size_t workspace_bytes,
+                                      void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Step 2: evolution (Sec. 2.2, eq:char_plus, eq:char_minus, eq:DzDt,        */
 /* eq:amp_P, eq:amp_SV, eq:amp_SH; Sec. 2.3 fixed-step RK4)                  */

@@ -18,11 +18,11 @@
  *   - classic fixed-step RK4                                     (Sec. 2.3)
  *   - Gaussian summation of the beams                            (Sec. 2.1, eq:FGA)
  *   - flat / spherical interface map: Snell, Zoeppritz, F and W  (Sec. 3.1, eq:p:int, eq:Yilmaz, eq:Inter_DzQDzP)
+ *   - point moment-tensor source weights (closed-form FBI)      (Sec. 2.1 eq:psi with f = 0)
  *
  * Readings where the paper is silent or garbled are noted at each use.
  * Parity status: every function here is pinned by a CPU test against closed
- * forms, invariants or brute force, except the point-source weights, whose
- * parity is unpinned beyond their closed-form derivative check.
+ * forms, invariants, brute force, finite differences or quadrature.
  */
 #include <complex.h>
 #include <math.h>

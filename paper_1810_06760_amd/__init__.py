@@ -39,7 +39,9 @@ EXPORTED = ["fga_last_error", "fga_version", "fga_medium_grid_table_bytes", "fga
             "fga_evolve_workspace_bytes", "fga_evolve", "fga_reconstruct_points_workspace_bytes",
             "fga_reconstruct_points", "fga_reconstruct_grid_workspace_bytes", "fga_reconstruct_grid",
             "fga_profile_enable", "fga_profile_read", "fga_server_footprint", "fga_server_create",
-            "fga_server_submit", "fga_server_poll", "fga_server_status", "fga_server_destroy"]
+            "fga_server_submit", "fga_server_poll", "fga_server_status", "fga_server_destroy",
+            "fga_point_source_candidates", "fga_decompose_point_source_workspace_bytes",
+            "fga_decompose_point_source"]
 FGA_K_INTEGRATE, FGA_K_SUM_POINTS, FGA_K_GRID_TILE, FGA_K_FBI_GEMM = 0, 1, 2, 3
 KERNEL_NAMES = {0: "integrate", 1: "sum_points", 2: "grid_tile", 3: "fbi_gemm"}
 
@@ -84,6 +86,13 @@ class EvolveOptsC(C.Structure):
 class EvolveStatsC(C.Structure):
     _fields_ = [("beam_steps", C.c_int64), ("evals", C.c_int64), ("culled", C.c_int64),
                 ("quarantined", C.c_int64), ("crossings", C.c_int64), ("spawned", C.c_int64), ("capped", C.c_int64)]
+
+
+class PointSourceC(C.Structure):
+    _fields_ = [("eps", C.c_double), ("x0", C.c_double * 3), ("M", C.c_double * 6), ("rho0", C.c_double),
+                ("nq", C.c_int), ("qhalf", C.c_double), ("ndir", C.c_int), ("nshell", C.c_int),
+                ("shell_lo", C.c_double), ("shell_hi", C.c_double), ("ricker", C.c_int), ("branch_mask", C.c_int),
+                ("cull_abs", C.c_double)]
 
 
 class RequestC(C.Structure):
@@ -138,6 +147,12 @@ def lib():
         L.fga_profile_enable.argtypes = [C.c_int]
         L.fga_profile_read.restype = st
         L.fga_profile_read.argtypes = [C.c_int, vp, vp, C.c_int]
+        L.fga_point_source_candidates.restype = i64
+        L.fga_point_source_candidates.argtypes = [vp]
+        L.fga_decompose_point_source_workspace_bytes.restype = sz
+        L.fga_decompose_point_source_workspace_bytes.argtypes = [vp]
+        L.fga_decompose_point_source.restype = st
+        L.fga_decompose_point_source.argtypes = [vp, vp, vp, vp, sz, vp]
         L.fga_server_footprint.restype = sz
         L.fga_server_footprint.argtypes = [vp]
         L.fga_server_create.restype = st
@@ -363,6 +378,35 @@ def fga_decompose(medium: Medium, mesh: MeshC, f, g=None, beams: BeamSet = None,
     ws = _workspace(L.fga_decompose_workspace_bytes(C.byref(mesh), 1 if g is not None else 0), ws)
     _check(L.fga_decompose(C.byref(medium.c), C.byref(mesh), _ptr(fd), _ptr(gd), C.byref(beams.c),
                            _ptr(ws), ws.numel(), _stream()))
+    return beams
+
+
+def point_source(eps, x0, M, nq, qhalf=None, ndir=64, nshell=4, shell_lo=0.2, shell_hi=2.5, ricker=True,
+                 rho0=0.0, branch_mask=7, cull_abs=0.0) -> PointSourceC:
+    """Point moment-tensor source parameters (M = xx, yy, zz, xy, xz, yz)."""
+    s = PointSourceC()
+    s.eps = eps
+    s.x0[:] = [float(v) for v in x0]
+    s.M[:] = [float(v) for v in M]
+    s.rho0 = rho0
+    s.nq = nq
+    s.qhalf = 4.0 * eps ** 0.5 if qhalf is None else qhalf
+    s.ndir, s.nshell = ndir, nshell
+    s.shell_lo, s.shell_hi = shell_lo, shell_hi
+    s.ricker = 1 if ricker else 0
+    s.branch_mask = branch_mask
+    s.cull_abs = cull_abs
+    return s
+
+
+def fga_decompose_point_source(medium: Medium, src: PointSourceC, beams: BeamSet = None, ws=None) -> BeamSet:
+    """Step 1 for a point moment-tensor source (closed-form weights)."""
+    L = lib()
+    if beams is None:
+        beams = BeamSet(int(L.fga_point_source_candidates(C.byref(src))))
+    ws = _workspace(L.fga_decompose_point_source_workspace_bytes(C.byref(src)), ws)
+    _check(L.fga_decompose_point_source(C.byref(medium.c), C.byref(src), C.byref(beams.c), _ptr(ws), ws.numel(),
+                                        _stream()))
     return beams
 
 

@@ -16,7 +16,7 @@ OBJ = os.path.join(ROOT, "_build", "fga")
 LIB = os.path.join(HERE, "libfga.so")
 
 SOURCES = ["api.hip", "k_integrate.hip", "k_medium.hip", "k_decompose.hip", "k_points.hip", "k_grid.hip",
-           "k_compact.hip", "k_sort.hip", "k_interface.hip", "server.hip"]
+           "k_compact.hip", "k_sort.hip", "k_interface.hip", "server.hip", "k_source.hip"]
 
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of all device code

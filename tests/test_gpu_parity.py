@@ -444,3 +444,87 @@ def test_interface_capacity_error():
     bs.load(oracle_to_dict(ob))
     with pytest.raises(RuntimeError, match="capacity"):
         m.fga_evolve(med_g, bs, 0.005, 60)
+
+
+# ---------------------------------------------------------------------------
+# point moment-tensor source
+# ---------------------------------------------------------------------------
+
+SRC_M = [1.0, 0.5, -0.3, 0.2, 0.1, -0.4]
+
+
+@pytest.mark.parametrize("medium", ["homogeneous", "grid", "layered"])
+def test_point_source_parity(medium):
+    """Closed-form point-source beams: same lineage set after the cull, same
+    states and weights (Ricker-weighted, both directions, 3 branches)."""
+    m = fga()
+    say("point source", medium)
+    eps = 1.0 / 32
+    if medium == "homogeneous":
+        mo, mg = om.homogeneous(math.sqrt(3), 1.0, 1.2), m.Medium.homogeneous(math.sqrt(3), 1.0)
+        x0, rho0 = [0.5, 0.45, 0.55], 1.2
+    elif medium == "grid":
+        w = small_c2(nmed=16)
+        mo, mg = om.medium_for(w), m.medium_for(w)
+        x0, rho0 = [0.43, 0.52, 0.61], 1.0
+    else:
+        geo, bounds, cp, cs, rho = LAYERED["sphere"]
+        mo, mg = om.layered(geo, bounds, cp, cs, rho), m.Medium.layered(geo, bounds, cp, cs, rho)
+        x0, rho0 = [0.3, 0.4, 0.75], 0.0
+    kw = dict(nq=5, ndir=40, nshell=3, ricker=True, rho0=rho0)
+    ob = om.point_source_beams(mo, om.point_source(eps, x0, SRC_M, **kw))
+    bs = m.fga_decompose_point_source(mg, m.point_source(eps, x0, SRC_M, **kw))
+    g = bs.export()
+    assert np.array_equal(g["lineage"], ob["lineage"])
+    for k in ("branch", "sigma", "layer"):
+        assert np.array_equal(g[k], ob[k]), k
+    assert rel_l2(g["Q"], ob["Q"]) <= 1e-14
+    assert rel_l2(g["P"], ob["P"]) <= 1e-14
+    assert rel_l2(g["w"], ob["w"]) <= RTOL
+    assert np.array_equal(g["e"], ob["e"])
+
+
+def source_psi_abs(b, eps, nq, qhalf, ndir, nshell, cP, cS, lo=0.2, hi=2.5):
+    """|psi| of point-source beams in a homogeneous medium: |w| / (dq dp (2 pi eps)^{-9/2})."""
+    dq = (2 * qhalf / nq) ** 3
+    Nq, Np = nq ** 3, ndir * nshell
+    out = np.empty(len(b))
+    for k, (lin, br) in enumerate(zip(b["lineage"], b["branch"])):
+        cb = cP if br == 0 else cS
+        xs, ws = om.gauss_legendre(nshell, lo * cP / cb, hi * cP / cb)
+        sh = ((lin // Nq) % Np) // ndir
+        dp = xs[sh] ** 2 * ws[sh] * 4 * math.pi / ndir
+        out[k] = abs(b["w"][k]) / (dq * dp * (2 * math.pi * eps) ** -4.5)
+    return out
+
+
+def test_point_source_cull_and_evolve():
+    """With a cull threshold on |psi| the kept sets agree (outside a 1e-9
+    band), and the source's beams evolve and sum at receivers like the
+    oracle's."""
+    m = fga()
+    say("point source cull + seismograms")
+    eps = 1.0 / 32
+    mo, mg = om.homogeneous(math.sqrt(3), 1.0, 1.0), m.Medium.homogeneous(math.sqrt(3), 1.0)
+    x0 = [0.5, 0.5, 0.5]
+    kw = dict(nq=4, ndir=24, nshell=3, qhalf=4 * eps ** 0.5)
+    full = om.point_source_beams(mo, om.point_source(eps, x0, SRC_M, **kw))
+    psi = source_psi_abs(full, eps, 4, kw["qhalf"], 24, 3, math.sqrt(3), 1.0)
+    thr = float(np.quantile(psi, 0.5))
+    ob = om.point_source_beams(mo, om.point_source(eps, x0, SRC_M, cull_abs=thr, **kw))
+    bs = m.fga_decompose_point_source(mg, m.point_source(eps, x0, SRC_M, cull_abs=thr, **kw))
+    g = bs.export()
+    amb = set(full["lineage"][np.abs(psi - thr) <= 1e-9 * thr].tolist())
+    so, sg = set(ob["lineage"].tolist()), set(g["lineage"].tolist())
+    assert so - amb <= sg and sg - amb <= so
+    assert 0.3 * len(full) < len(so) < 0.7 * len(full)
+    ob = ob[np.isin(ob["lineage"], g["lineage"])]
+    rec = fi.uniform_points(6, np.random.default_rng(3), 0.3, 0.7)
+    nsteps, dt, tau = 20, 0.005, 25.0
+    seis, st = m.fga_evolve(mg, bs, dt, nsteps, receivers=rec, eps=eps, tau=tau, stride=5)
+    ref = np.zeros((len(rec), nsteps // 5, 3), dtype=np.complex128)
+    cur = ob.copy()
+    for s in range(nsteps // 5):
+        om.evolve(mo, cur, dt, 5)
+        ref[:, s, :] = om.sum_points(cur, rec, eps, tau)[0]
+    assert rel_l2(m.to_complex(seis), ref) <= RTOL
