@@ -258,9 +258,9 @@ def serve(args):
     prec = fga.FGA_FP32 if args.serve_precision == "mixed" else fga.FGA_FP64
 
     def request(rq, precision=None):
-        mesh = fga.make_mesh(rq["eps"], rq["qmesh"], rq["pmesh"], rq["ymesh"], cull_abs=rq["cull_abs"])
-        return fga.make_request(models[rq["model"]], mesh, rq["f"], rq["receivers"], rq["tau"], rq["dt"],
-                                rq["nsteps"], 1, precision=prec if precision is None else precision)
+        src = fga.point_source(rq["eps"], rq["x0"], rq["M"], nq=rq["nq"], ndir=rq["ndir"], nshell=rq["nshell"])
+        return fga.make_request(models[rq["model"]], None, None, rq["receivers"], rq["tau"], rq["dt"],
+                                rq["nsteps"], 1, precision=prec if precision is None else precision, source=src)
 
     budget = int(args.hbm_budget_gb * 2 ** 30)
     # warm-up: one solve (module load, first allocations)
@@ -345,8 +345,8 @@ def serve(args):
         "vs_baseline": None,
         "dtype": "f64" if prec == fga.FGA_FP64 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "tomography sweep: %d requests over 4 resident 128^3 smooth random models, Gaussian "
-                               "packet sources at random centres/directions, eps in {1/32, 1/64, 1/128}, "
+        "config": {"workload": "tomography sweep: %d requests over 4 resident 128^3 smooth random models, point "
+                               "moment-tensor sources (Ricker) at random positions, eps in {1/32, 1/64, 1/128}, "
                                "128..1024 receivers x 250 samples, 250 FP64 RK4 steps, %s receiver sums; "
                                "Poisson arrivals at %.2f x saturated rate"
                                % (len(reqs), "FP64" if prec == fga.FGA_FP64 else "mixed (FP32 exp/sin/cos)",

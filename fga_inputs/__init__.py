@@ -209,8 +209,8 @@ def smooth_medium_packet(name="c2", eps=1.0 / 128, nq=32, np_=8, ny=128, nmed=12
 # tomography-style request sweep (serving)
 # ---------------------------------------------------------------------------
 
-# eps -> (q points per axis, p points per axis, quadrature points per axis)
-SWEEP_MESHES = {1.0 / 32: (8, 4, 48), 1.0 / 64: (12, 4, 64), 1.0 / 128: (16, 6, 96)}
+# eps -> (q points per axis, Fibonacci directions, |p| shells) of a point-source request
+SWEEP_MESHES = {1.0 / 32: (5, 64, 3), 1.0 / 64: (6, 120, 4), 1.0 / 128: (8, 200, 4)}
 
 
 def sweep_model(j: int, nmed: int = 128) -> np.ndarray:
@@ -220,25 +220,29 @@ def sweep_model(j: int, nmed: int = 128) -> np.ndarray:
     return SQRT3 * (1.0 + 0.2 * g)
 
 
+def moment_tensor(g: np.random.Generator) -> list:
+    """Symmetric moment tensor with N(0,1) entries, Frobenius-normalised;
+    returned as (xx, yy, zz, xy, xz, yz)."""
+    a = g.standard_normal((3, 3))
+    m = 0.5 * (a + a.T)
+    m /= np.linalg.norm(m)
+    return [m[0, 0], m[1, 1], m[2, 2], m[0, 1], m[0, 2], m[1, 2]]
+
+
 def sweep_request(i: int, nmodels: int = 4, nsteps: int = 250, dt: float = 2e-3, tau: float = 25.0) -> dict:
-    """Request i of the sweep: model index, a Gaussian plane-wave packet
-    source (width 0.1) at a random centre in [0.25, 0.75]^3 with a random
-    direction and polarisation, eps from SWEEP_MESHES, 128..1024 receivers
-    uniform in [0,1]^3; one-way data, all three branches."""
+    """Request i of the sweep: model index, a point moment-tensor source at
+    a uniform position in [0.25, 0.75]^3 with a random moment tensor and a
+    Ricker wavelet, eps from SWEEP_MESHES, 128..1024 receivers uniform in
+    [0,1]^3."""
     g = rng(5, 100 + i)
     model = int(g.integers(0, nmodels))
-    centre = g.uniform(0.25, 0.75, 3)
-    k0 = unit_vector(g)
-    d = unit_vector(g)
+    x0 = g.uniform(0.25, 0.75, 3)
+    M = moment_tensor(g)
     eps = list(SWEEP_MESHES)[int(g.integers(0, len(SWEEP_MESHES)))]
-    nq, np_, ny = SWEEP_MESHES[eps]
+    nq, ndir, nshell = SWEEP_MESHES[eps]
     nrec = int(g.integers(128, 1025))
-    ymesh = cell_centred(ny, 0.0, 1.0)
-    width = 0.1
     return {
         "model": model, "eps": eps, "nsteps": nsteps, "dt": dt, "tau": tau,
-        "qmesh": cell_centred(nq, 0.0, 1.0), "pmesh": p_mesh_around(k0, eps, width, np_), "ymesh": ymesh,
-        "f": gaussian_plane_wave(ymesh, eps, centre, width, k0, d),
+        "x0": x0, "M": M, "nq": nq, "ndir": ndir, "nshell": nshell,
         "receivers": uniform_points(nrec, g),
-        "cull_abs": 1e-10 * (2.0 * math.pi * width ** 2) ** 1.5,
     }

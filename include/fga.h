@@ -354,6 +354,8 @@ typedef struct {
   double *seis_out;         /* host, complex [n_receivers][nsteps/stride][3]; written
                                before the completion is reported; caller-owned       */
   int precision;            /* receiver sums: FGA_FP64 or FGA_FP32 (mixed)            */
+  int point_source;         /* 1: the initial data is `source` (mesh and f unused)    */
+  fga_point_source source;
 } fga_request;
 
 typedef struct {

@@ -98,7 +98,8 @@ class PointSourceC(C.Structure):
 class RequestC(C.Structure):
     _fields_ = [("medium", MediumC), ("mesh", MeshC), ("f", C.c_void_p), ("n_receivers", C.c_int64),
                 ("receivers", C.c_void_p), ("tau", C.c_double), ("dt", C.c_double), ("nsteps", C.c_int),
-                ("stride", C.c_int), ("seis_out", C.c_void_p), ("precision", C.c_int)]
+                ("stride", C.c_int), ("seis_out", C.c_void_p), ("precision", C.c_int), ("point_source", C.c_int),
+                ("source", PointSourceC)]
 
 
 class CompletionC(C.Structure):
@@ -520,22 +521,26 @@ def to_complex(t) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def make_request(medium: Medium, mesh, f, receivers, tau: float, dt: float, nsteps: int, stride: int = 1,
-                 precision: int = FGA_FP64):
+                 precision: int = FGA_FP64, source: "PointSourceC" = None):
     """A forward-solve request: host initial data f (complex [3, nz, ny, nx])
     and receivers (n, 3).  Returns (RequestC, seismogram array it fills:
     complex [n, nsteps // stride, 3]); both must stay alive until completion."""
-    f = np.ascontiguousarray(np.asarray(f, dtype=np.complex128))
+    f = np.ascontiguousarray(np.asarray(f if f is not None else np.zeros(1), dtype=np.complex128))
     x = np.ascontiguousarray(np.asarray(receivers, dtype=np.float64).reshape(-1, 3))
     seis = np.zeros((x.shape[0], nsteps // stride, 3), dtype=np.complex128)
     r = RequestC()
     r.medium = medium.c
-    r.mesh = mesh
+    if mesh is not None:
+        r.mesh = mesh
     r.f = f.ctypes.data
     r.n_receivers = x.shape[0]
     r.receivers = x.ctypes.data
     r.tau, r.dt, r.nsteps, r.stride = tau, dt, nsteps, stride
     r.seis_out = seis.ctypes.data
     r.precision = precision
+    if source is not None:
+        r.point_source = 1
+        r.source = source
     return r, seis, (f, x, medium)
 
 

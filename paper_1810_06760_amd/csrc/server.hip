@@ -32,12 +32,12 @@ bool request_sizes(const fga_request *r, Sizes *z)
 {
   if (!r || r->nsteps < 0 || r->stride < 1 || r->n_receivers < 0) return false;
   if (r->precision != FGA_FP64 && r->precision != FGA_FP32) return false;
-  const int64_t cand = fga_decompose_candidates(&r->mesh);
+  const int64_t cand = r->point_source ? fga_point_source_candidates(&r->source) : fga_decompose_candidates(&r->mesh);
   if (cand <= 0) return false;
   // layered media grow the beam set at interfaces
   z->capacity = r->medium.kind == FGA_MEDIUM_LAYERED ? 4 * cand : cand;
   z->ns = r->nsteps / r->stride;
-  const int64_t ny = (int64_t)r->mesh.ny[0] * r->mesh.ny[1] * r->mesh.ny[2];
+  const int64_t ny = r->point_source ? 1 : (int64_t)r->mesh.ny[0] * r->mesh.ny[1] * r->mesh.ny[2];
   z->beams = align256((size_t)z->capacity * FGA_NF64 * sizeof(double)) +
              align256((size_t)z->capacity * FGA_NI32 * sizeof(int32_t)) + align256((size_t)z->capacity * sizeof(int64_t));
   z->f = align256((size_t)ny * 3 * 2 * sizeof(double));
@@ -53,10 +53,11 @@ bool request_sizes(const fga_request *r, Sizes *z)
   rc.n = r->n_receivers;
   rc.xyz = reinterpret_cast<const double *>(256);
   rc.stride = r->stride;
-  rc.eps = r->mesh.eps;
+  rc.eps = r->point_source ? r->source.eps : r->mesh.eps;
   rc.tau = r->tau;
   rc.precision = r->precision;
-  const size_t wd = fga_decompose_workspace_bytes(&r->mesh, 0);
+  const size_t wd = r->point_source ? fga_decompose_point_source_workspace_bytes(&r->source)
+                                    : fga_decompose_workspace_bytes(&r->mesh, 0);
   const size_t we = fga_evolve_workspace_bytes(&b, r->nsteps, nullptr, r->n_receivers > 0 ? &rc : nullptr);
   z->ws = align256(wd > we ? wd : we);
   z->total = z->beams + z->f + z->rec + z->seis + z->ws;
@@ -129,19 +130,22 @@ fga_completion fga_server::run(Job &j, hipStream_t st)
   p += j.sz.seis;
   void *ws = p;
   do {
-    if (hipMemcpyAsync(fd, j.f.data(), j.f.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+    if ((!r.point_source &&
+         hipMemcpyAsync(fd, j.f.data(), j.f.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess) ||
         (r.n_receivers > 0 &&
          hipMemcpyAsync(xd, j.rec.data(), j.rec.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)) {
       s = FGA_EDEVICE;
       break;
     }
-    if ((s = fga_decompose(&r.medium, &r.mesh, fd, nullptr, &b, ws, j.sz.ws, st)) != FGA_OK) break;
+    s = r.point_source ? fga_decompose_point_source(&r.medium, &r.source, &b, ws, j.sz.ws, st)
+                       : fga_decompose(&r.medium, &r.mesh, fd, nullptr, &b, ws, j.sz.ws, st);
+    if (s != FGA_OK) break;
     c.beams = b.count;
     fga_receivers rc{};
     rc.n = r.n_receivers;
     rc.xyz = xd;
     rc.stride = r.stride;
-    rc.eps = r.mesh.eps;
+    rc.eps = r.point_source ? r.source.eps : r.mesh.eps;
     rc.tau = r.tau;
     rc.precision = r.precision;
     fga_evolve_stats es{};
@@ -238,14 +242,16 @@ fga_status fga_server_submit(fga_server *s, const fga_request *r, uint64_t *id)
   if (!s || !r) return fga::fail(FGA_EINVAL, "server or request is NULL");
   Sizes z;
   if (!request_sizes(r, &z)) return fga::fail(FGA_EINVAL, "invalid request (mesh, steps, stride or receivers)");
-  if (!r->f || (r->n_receivers > 0 && (!r->receivers || (z.ns > 0 && !r->seis_out))))
+  if ((!r->point_source && !r->f) || (r->n_receivers > 0 && (!r->receivers || (z.ns > 0 && !r->seis_out))))
     return fga::fail(FGA_EINVAL, "request has a NULL f, receivers or seis_out");
   if (z.total > s->budget)
     return fga::fail(FGA_ECAPACITY, "request needs %zu device bytes, above the server budget %zu", z.total, s->budget);
   Job j;
   j.req = *r;
-  const int64_t ny = (int64_t)r->mesh.ny[0] * r->mesh.ny[1] * r->mesh.ny[2];
-  j.f.assign(r->f, r->f + ny * 6);
+  if (!r->point_source) {
+    const int64_t ny = (int64_t)r->mesh.ny[0] * r->mesh.ny[1] * r->mesh.ny[2];
+    j.f.assign(r->f, r->f + ny * 6);
+  }
   if (r->n_receivers > 0) j.rec.assign(r->receivers, r->receivers + r->n_receivers * 3);
   j.sz = z;
   {

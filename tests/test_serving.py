@@ -43,6 +43,17 @@ def build_requests(m):
     return reqs, (grid_med, homog_med)
 
 
+def point_source_requests(m, meds):
+    """Two point-source requests (sweep generator, shrunk meshes)."""
+    out = []
+    for i in range(2):
+        rq = fi.sweep_request(i, nsteps=20)
+        src = m.point_source(1.0 / 32, rq["x0"], rq["M"], nq=4, ndir=24, nshell=2)
+        out.append(dict(medium=meds[i], receivers=rq["receivers"][:9], tau=25.0, dt=2e-3, nsteps=20, stride=2,
+                        source=src))
+    return out
+
+
 def run_server(m, reqs, budget, slots):
     srv = m.Server(budget, slots)
     seis = {}
@@ -126,6 +137,31 @@ def test_mixed_precision_requests():
     for i in range(3):
         a, b = res[(i, m.FGA_FP32)], res[(i, m.FGA_FP64)]
         assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b)
+
+
+@pytest.mark.gpu
+def test_point_source_requests_match_direct_calls():
+    m = fga()
+    say("serving point sources")
+    reqs, meds = build_requests(m)
+    srv = m.Server(1 << 34, 2)
+    outs = {}
+    try:
+        for k, r in enumerate(point_source_requests(m, meds)):
+            rq, s, keep = m.make_request(r["medium"], None, None, r["receivers"], r["tau"], r["dt"], r["nsteps"],
+                                         r["stride"], source=r["source"])
+            outs[srv.submit(rq, keep=(keep, s, r))] = (k, s, r)
+        got = []
+        while len(got) < 2:
+            got += srv.poll(4, wait_ms=20000)
+    finally:
+        srv.close()
+    assert all(c["status"] == 0 for c in got)
+    for k, s, r in outs.values():
+        bs = m.fga_decompose_point_source(r["medium"], r["source"])
+        seis, _ = m.fga_evolve(r["medium"], bs, r["dt"], r["nsteps"], receivers=r["receivers"], eps=1.0 / 32,
+                               tau=r["tau"], stride=r["stride"])
+        assert np.array_equal(s, m.to_complex(seis))
 
 
 @pytest.mark.gpu
