@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 # FP64 operations per unit of algorithmic work (derivation in the design doc):
 #   one RK4 beam-step (4 right-hand sides + the update), per medium kind,
 #   one receiver/point term (window test excluded), one grid term.
-FLOP_BEAM_STEP = {"homogeneous": 3390, "grid": 4186}
+FLOP_BEAM_STEP = {"homogeneous": 3390, "grid": 4186, "layered": 3390}
 FLOP_POINT_EVAL = 87      # FP64 flops per in-window receiver term (window test, exponent, phase, table
                           # exp and sincos, 12 accumulating FMAs), FMA = 2, counted in the gfx950 code
 FLOP_GRID_EVAL = 24       # 3 complex multiply-adds
@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous"])
+    ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered"])
     ap.add_argument("--scale", type=float, default=1.0,
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -243,6 +243,81 @@ def cpu_baseline(w, tot_per_step, npairs, args):
             "seconds_per_step_extrapolated": full}
 
 
+def layered(args):
+    """Layered spherical Earth-like model (4 shells) with a point moment-tensor
+    source (Ricker, eps = 1/256): decompose, then 2000 RK4 steps with
+    interface splitting (generation cap 3) and 512 surface receivers sampled
+    every step.  --scale shrinks the direction count and the step count."""
+    import torch
+    import fga_inputs as fi
+    import paper_1810_06760_amd as fga
+    torch.cuda.set_device(0)
+    sc = args.scale
+    e = fi.layered_earth(ndir=max(16, int(round(1600 * sc))), nsteps=max(8, int(round(2000 * sc))))
+    med = fga.Medium.layered(1, e["bounds"], e["cp"], e["cs"], e["rho"])
+    src = fga.point_source(e["eps"], e["x0"], e["M"], nq=e["nq"], ndir=e["ndir"], nshell=e["nshell"])
+    ncand = int(fga.lib().fga_point_source_candidates(fga.C.byref(src)))
+    beams = fga.BeamSet(12 * ncand)   # room for interface children (generation cap 3)
+    rec = fga._dev(e["receivers"], torch.float64)
+    nseg = max(1, min(args.segments, e["nsteps"]))
+    seg = -(-e["nsteps"] // nseg)
+    state = {"ws": None, "seis": torch.empty((rec.shape[0], e["nsteps"], 3, 2), dtype=torch.float64, device="cuda")}
+
+    def step():
+        fga.fga_decompose_point_source(med, src, beams=beams)
+        n0 = beams.count
+        if state["ws"] is None:
+            state["ws"] = fga._workspace(fga.workspace_bytes("evolve", beams=beams, nsteps=seg,
+                                                             n_receivers=rec.shape[0], eps=e["eps"], tau=e["tau"]))
+        tot = {"beam_steps": 0, "evals": 0, "crossings": 0, "spawned": 0, "capped": 0}
+        for s0 in range(0, e["nsteps"], seg):
+            n = min(seg, e["nsteps"] - s0)
+            part, st = fga.fga_evolve(med, beams, e["dt"], n, receivers=rec, eps=e["eps"], tau=e["tau"],
+                                      ws=state["ws"])
+            state["seis"][:, s0:s0 + n].copy_(part)
+            for k in tot:
+                tot[k] += st[k]
+            print("bench: steps %d..%d done, %d beams" % (s0, s0 + n, beams.count), file=sys.stderr, flush=True)
+        return n0, tot
+
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fga.fga_profile_enable(True)
+    t0 = time.perf_counter()
+    acc = {"beam_steps": 0, "evals": 0, "crossings": 0, "spawned": 0, "capped": 0, "beams": 0}
+    for _ in range(args.steps):
+        n0, tot = step()
+        acc["beams"] += n0
+        for k in tot:
+            acc[k] += tot[k]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {fga.KERNEL_NAMES[k]: fga.fga_profile_read(k) for k in fga.KERNEL_NAMES}
+    fga.fga_profile_enable(False)
+    K = args.steps
+    roof, _ = roofline({"beam_steps": acc["beam_steps"], "ev_rec": acc["evals"], "ev_grid": 0}, prof, "layered")
+    line = {
+        "metric": "beam-steps/s + beam-point evals/s; served solves/s, p50/p99 at rel-L2<=1e-3",
+        "value": acc["beam_steps"] / elapsed, "unit": "beam-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "layered spherical Earth-like model, 4 shells (radii %s), point moment-tensor "
+                               "source with Ricker wavelet at r = %.3f, eps = 1/256, q %d^3 x %d directions x %d "
+                               "shells x 3 branches x 2 directions, %d RK4 steps to T = 1.5 with interface "
+                               "splitting (generation cap 3), %d surface receivers x %d samples, FP64"
+                               % (", ".join("%.3f" % r for r in e["bounds"]), float(np.linalg.norm(e["x0"])),
+                                  e["nq"], e["ndir"], e["nshell"], e["nsteps"], rec.shape[0], e["nsteps"]),
+                   "beams": int(acc["beams"] / K), "parallelism": "single GPU"},
+        "beam_point_evals_per_s": acc["evals"] / elapsed,
+        "interface_hits_per_step": acc["crossings"] // K, "children_per_step": acc["spawned"] // K,
+        "capped_per_step": acc["capped"] // K, "beams_at_end": int(beams.count),
+        "kernel_ms_per_step": {k: v[1] / K for k, v in prof.items()},
+        "roofline": roof,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def serve(args):
     """Serving sweep: 4 resident smooth models (128^3), requests from the
     seeded sweep generator; phase 1 submits all requests at once (saturated
@@ -373,6 +448,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve(args)
+        return
+    if args.workload == "layered":
+        layered(args)
         return
     if args.copy_calibration:
         import torch

@@ -246,3 +246,55 @@ def sweep_request(i: int, nmodels: int = 4, nsteps: int = 250, dt: float = 2e-3,
         "x0": x0, "M": M, "nq": nq, "ndir": ndir, "nshell": nshell,
         "receivers": uniform_points(nrec, g),
     }
+
+
+# ---------------------------------------------------------------------------
+# layered spherical Earth-like model with a point source (config 3)
+# ---------------------------------------------------------------------------
+
+def fibonacci_sphere(n: int, g: np.random.Generator) -> np.ndarray:
+    """n points of a Fibonacci lattice on the unit sphere, randomly rotated;
+    returned in Cartesian coordinates."""
+    i = np.arange(n)
+    z = 1.0 - (2.0 * i + 1.0) / n
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    ph = i * math.pi * (3.0 - math.sqrt(5.0))
+    pts = np.stack([r * np.cos(ph), r * np.sin(ph), z], axis=1)
+    q, _ = np.linalg.qr(g.standard_normal((3, 3)))
+    return pts @ q.T
+
+
+def spherical_to_cartesian(r, theta, phi):
+    """Receiver coordinates given as radius, longitude theta and latitude
+    phi: x = (r cos(theta) cos(phi), r sin(theta) cos(phi), r sin(phi))."""
+    return np.stack([r * np.cos(theta) * np.cos(phi), r * np.sin(theta) * np.cos(phi), r * np.sin(phi)], axis=-1)
+
+
+def layered_earth(config: int = 3, eps: float = 1.0 / 256, nq: int = 8, ndir: int = 1600, nshell: int = 4,
+                  nsteps: int = 2000, T: float = 1.5, nrec: int = 512) -> dict:
+    """Unit sphere with 4 layers: 3 interface radii in (0.3, 0.95) at least
+    0.1 apart; the top layer has c_P = sqrt(3), c_S = 1, rho = 1 and each
+    deeper layer multiplies each of them by U[1.05, 1.20]; a point
+    moment-tensor source with a Ricker wavelet at radius U[0.6, 0.9] in a
+    random direction; receivers on a Fibonacci lattice of the surface r = 1,
+    given as (r, longitude, latitude) and mapped to Cartesian."""
+    g = rng(config, 1)
+    while True:
+        radii = np.sort(g.uniform(0.3, 0.95, 3))[::-1]
+        if np.all(-np.diff(radii) >= 0.1):
+            break
+    cp, cs, rho = [SQRT3], [1.0], [1.0]
+    for _ in range(3):
+        cp.append(cp[-1] * g.uniform(1.05, 1.20))
+        cs.append(cs[-1] * g.uniform(1.05, 1.20))
+        rho.append(rho[-1] * g.uniform(1.05, 1.20))
+    gs = rng(config, 2)
+    d = unit_vector(gs)
+    x0 = d * gs.uniform(0.6, 0.9)
+    M = moment_tensor(gs)
+    pts = fibonacci_sphere(nrec, rng(config, 3))
+    theta = np.arctan2(pts[:, 1], pts[:, 0])
+    phi = np.arcsin(np.clip(pts[:, 2], -1.0, 1.0))
+    rec = spherical_to_cartesian(np.ones(nrec), theta, phi)
+    return {"bounds": list(radii), "cp": cp, "cs": cs, "rho": rho, "x0": x0, "M": M, "eps": eps, "nq": nq,
+            "ndir": ndir, "nshell": nshell, "nsteps": nsteps, "dt": T / nsteps, "receivers": rec, "tau": 25.0}
