@@ -30,9 +30,17 @@ __device__ __forceinline__ bool layer_exit(const DevMedium &m, int L, const doub
 // Speed of wave type sp (0 = P, 1 = S) at x: c, gradient g and Hessian H
 // (xx, yy, zz, xy, xz, yz).  Grid media interpolate the ten precomputed node
 // fields trilinearly (periodic); each node is one 128-byte record.
+// A block of MEDBLK^3 grid nodes held in LDS by a workgroup: the ten fields
+// of node (o + l) (periodic) at lds[10 (l_z MEDBLK^2 + l_y MEDBLK + l_x)].
+constexpr int MEDBLK = 12;
+struct MedBlock {
+  const double *lds;  // NULL: no block
+  int o[3];
+};
+
 template <int MK>
 __device__ __forceinline__ void medium_eval(const DevMedium &m, int sp, int layer, const double *x,
-                                            double &c, double g[3], double H[6])
+                                            double &c, double g[3], double H[6], const MedBlock *blk = nullptr)
 {
   if constexpr (MK == MK_HOMOG) {
     c = sp == 0 ? m.cp : m.cs;
@@ -58,28 +66,58 @@ __device__ __forceinline__ void medium_eval(const DevMedium &m, int sp, int laye
       double u = (x[d] - m.lo[d]) * m.ih[d];
       double fl = floor(u);
       t[d] = u - fl;
-      int ii = (int)fl % m.n[d];
-      if (ii < 0) ii += m.n[d];
+      int ii = (int)fl;
+      if (ii < 0 || ii >= m.n[d]) ii = ((ii % m.n[d]) + m.n[d]) % m.n[d];  // periodic (rare)
       i0[d] = ii;
       i1[d] = ii + 1 == m.n[d] ? 0 : ii + 1;
     }
     double v[10];
 #pragma unroll
     for (int f = 0; f < 10; ++f) v[f] = 0.0;
-#pragma unroll 2
-    for (int corner = 0; corner < 8; ++corner) {
-      const int ix = (corner & 1) ? i1[0] : i0[0];
-      const int iy = (corner & 2) ? i1[1] : i0[1];
-      const int iz = (corner & 4) ? i1[2] : i0[2];
-      const double w = ((corner & 1) ? t[0] : 1.0 - t[0]) * ((corner & 2) ? t[1] : 1.0 - t[1]) *
-                       ((corner & 4) ? t[2] : 1.0 - t[2]);
-      const double2 *p = reinterpret_cast<const double2 *>(
-          tab + (size_t)FGA_GRID_NODE_DOUBLES * (((size_t)iz * m.n[1] + iy) * m.n[0] + ix));
+    // the cell's eight nodes from the LDS block when they all lie in it
+    bool inblk = blk != nullptr && blk->lds != nullptr;
+    int l[3] = {0, 0, 0};
+    if (inblk) {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const double2 a = p[k];
-        v[2 * k] += w * a.x;
-        v[2 * k + 1] += w * a.y;
+      for (int d = 0; d < 3; ++d) {
+        int li = i0[d] - blk->o[d];
+        if (li < 0) li += m.n[d];
+        l[d] = li;
+        inblk = inblk && li <= MEDBLK - 2;
+      }
+    }
+    // LDS path when every lane of the wavefront has its cell in the block
+    // (the common case: Morton-ordered neighbours), else global memory for all
+    if (__all(inblk)) {
+#pragma unroll 8
+      for (int corner = 0; corner < 8; ++corner) {
+        const int lx = l[0] + (corner & 1), ly = l[1] + ((corner >> 1) & 1), lz = l[2] + ((corner >> 2) & 1);
+        const double w = ((corner & 1) ? t[0] : 1.0 - t[0]) * ((corner & 2) ? t[1] : 1.0 - t[1]) *
+                         ((corner & 4) ? t[2] : 1.0 - t[2]);
+        const double2 *p = reinterpret_cast<const double2 *>(blk->lds + 10 * ((lz * MEDBLK + ly) * MEDBLK + lx));
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const double2 a = p[k];
+          v[2 * k] += w * a.x;
+          v[2 * k + 1] += w * a.y;
+        }
+      }
+    } else {
+#pragma unroll 2
+      for (int corner = 0; corner < 8; ++corner) {
+        const int ix = (corner & 1) ? i1[0] : i0[0];
+        const int iy = (corner & 2) ? i1[1] : i0[1];
+        const int iz = (corner & 4) ? i1[2] : i0[2];
+        const double w = ((corner & 1) ? t[0] : 1.0 - t[0]) * ((corner & 2) ? t[1] : 1.0 - t[1]) *
+                         ((corner & 4) ? t[2] : 1.0 - t[2]);
+        const double2 *p = reinterpret_cast<const double2 *>(
+            tab + (size_t)FGA_GRID_NODE_DOUBLES * (((size_t)iz * m.n[1] + iy) * m.n[0] + ix));
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const double2 a = p[k];
+          v[2 * k] += w * a.x;
+          v[2 * k + 1] += w * a.y;
+        }
       }
     }
     c = scale * v[0];

@@ -67,6 +67,53 @@ __global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs 
   const int64_t i = a.beg + (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool active = i < a.end;
   unsigned long long steps_done = 0, culled = 0, quar = 0;
+  // Grid media: the workgroup's beams are neighbours in Morton order, so the
+  // nodes they interpolate from for the whole launch mostly lie in one small
+  // block around them; that block is staged in LDS once and the trilinear
+  // gathers read it (cells outside it fall back to global memory).
+  MedBlock blk{nullptr, {0, 0, 0}};
+  if constexpr (MK == MK_GRID) {
+    __shared__ double lds_med[MEDBLK * MEDBLK * MEDBLK * 10];
+    __shared__ int bb[6];
+    if (!med.two_fields) {
+      if (threadIdx.x < 3) {
+        bb[threadIdx.x] = 0x7fffffff;
+        bb[3 + threadIdx.x] = -0x7fffffff;
+      }
+      __syncthreads();
+      if (active && (a.i32[FGA_FLAGS * a.cap + i] & FGA_FLAG_ALIVE)) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double u = (a.f64[(FGA_Q + d) * a.cap + i] - med.lo[d]) * med.ih[d];
+          const int cell = (int)fmax(fmin(floor(u), 1.0e9), -1.0e9);
+          atomicMin(&bb[d], cell);
+          atomicMax(&bb[3 + d], cell);
+        }
+      }
+      __syncthreads();
+      if (bb[0] <= bb[3]) {
+        int o[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int c0 = bb[d] / 2 + bb[3 + d] / 2 - MEDBLK / 2 + 1;
+          o[d] = ((c0 % med.n[d]) + med.n[d]) % med.n[d];
+        }
+        for (int idx = threadIdx.x; idx < MEDBLK * MEDBLK * MEDBLK; idx += 256) {
+          const int lx = idx % MEDBLK, ly = (idx / MEDBLK) % MEDBLK, lz = idx / (MEDBLK * MEDBLK);
+          const int nx = (o[0] + lx) % med.n[0], ny = (o[1] + ly) % med.n[1], nz = (o[2] + lz) % med.n[2];
+          const double *src =
+              med.table + (size_t)FGA_GRID_NODE_DOUBLES * (((size_t)nz * med.n[1] + ny) * med.n[0] + nx);
+#pragma unroll
+          for (int f = 0; f < 10; ++f) lds_med[10 * idx + f] = src[f];
+        }
+        __syncthreads();
+        blk.lds = lds_med;
+        blk.o[0] = o[0];
+        blk.o[1] = o[1];
+        blk.o[2] = o[2];
+      }
+    }
+  }
   if (active) {
     const int64_t cap = a.cap;
     const int64_t nb = a.end - a.beg;
@@ -94,7 +141,7 @@ __global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs 
       const double ieps = 1.0 / a.eps_emit;
       bool crossed = false;
       for (int s = 0; s < a.nsteps; ++s) {
-        rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt);
+        rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt, &blk);
         if constexpr (MK == MK_LAYERED) {
           // left the layer: the interface step redoes this step from the
           // stored state, which is therefore not overwritten

@@ -27,10 +27,11 @@ constexpr double COS10 = 0.98480775301220805936;  // cos(10 degrees)
 template <int MK>
 __device__ __forceinline__ void stage(const DevMedium &med, int sp, int layer, double sg, bool isS,
                                       const double e[3], const double *__restrict__ y, double *__restrict__ yt,
-                                      double *__restrict__ acc, double wacc, double cnext)
+                                      double *__restrict__ acc, double wacc, double cnext,
+                                      const MedBlock *blk = nullptr)
 {
   double c, g[3], H6[6];
-  medium_eval<MK>(med, sp, layer, yt + IQ, c, g, H6);
+  medium_eval<MK>(med, sp, layer, yt + IQ, c, g, H6, blk);
   const double H[3][3] = {{H6[0], H6[3], H6[4]}, {H6[3], H6[1], H6[5]}, {H6[4], H6[5], H6[2]}};
   const double P0 = yt[IP], P1 = yt[IP + 1], P2 = yt[IP + 2];
   const double np = sqrt(P0 * P0 + P1 * P1 + P2 * P2);
@@ -178,7 +179,7 @@ __device__ __forceinline__ void reframe_s(double *y, double e[3])
 // the four stages run as a loop so that only y, acc and the stage input stay live.
 template <int MK>
 __device__ __forceinline__ void rk4_step(const DevMedium &med, int sp, int layer, double sg, bool isS,
-                                         const double e[3], double *y, double dt)
+                                         const double e[3], double *y, double dt, const MedBlock *blk = nullptr)
 {
   double acc[NS], yt[NS];
 #pragma unroll
@@ -188,7 +189,7 @@ __device__ __forceinline__ void rk4_step(const DevMedium &med, int sp, int layer
   for (int st = 0; st < 4; ++st) {
     const double wacc = (st == 0 || st == 3) ? 1.0 : 2.0;
     const double cnext = st == 2 ? dt : (st == 3 ? 0.0 : h2);
-    stage<MK>(med, sp, layer, sg, isS, e, y, yt, acc, wacc, cnext);
+    stage<MK>(med, sp, layer, sg, isS, e, y, yt, acc, wacc, cnext, blk);
   }
 #pragma unroll
   for (int f = 0; f < NS; ++f) y[f] += h6 * acc[f];
