@@ -1,26 +1,26 @@
 // Step 3 at scattered points (eq:FGA): receivers and seismograms.
 //
-// Beam-major layout.  A wavefront owns RW points and walks a range of beams
-// 64 at a time, one beam per lane, each lane holding its beam's emission
-// record (Q, P/eps, B = w e^{iS/eps} A) in registers and RW complex 3-vector
-// sums.  The beam set is kept in Morton order of Q, so the 64 beams of a
-// tile are close together and the window test against one point is
-// (nearly) the same on every lane: evaluation is divergence-free and a point
-// whose window misses all 64 beams costs one test.  A workgroup covers one
-// sample, 32 points (four wavefronts) and one beam range; each beam tile is
-// read from memory once per workgroup and shared through LDS, double-
-// buffered so the next tile's loads overlap this tile's sums.  Tiles out of
-// reach of all of a workgroup's points (by bounding boxes) are not loaded.
-// After the beam range the sums are reduced over the lanes in a fixed order
-// and written once per wavefront; per-workgroup partials are then reduced in
-// a fixed order, so the sums are bitwise reproducible and need no atomics.
+// Beam-major layout.  A wavefront owns RW = 4 points and walks a range of
+// beams 64 at a time, one beam per lane, each lane holding its beam's
+// emission record (Q, P/eps, B = w e^{iS/eps} A) in registers (fetched one
+// tile ahead) and RW complex 3-vector sums; the four points are evaluated
+// together, four independent exponential chains per lane.  The beam set is
+// kept in Morton order of Q, so the 64 beams of a tile are close together
+// and the window test against one point is (nearly) the same on every lane;
+// a tile whose bounding box lies out of reach of all the wavefront's points
+// is skipped without loading it.  A workgroup covers one sample, 16 points
+// (four wavefronts) and one beam range; workgroups sharing a beam range are
+// dealt to one XCD so its records are read from HBM once.  After the beam
+// range the sums are reduced over the lanes in a fixed order and written
+// once per wavefront; per-workgroup partials are then reduced in a fixed
+// order, so the sums are bitwise reproducible and need no atomics.
 #include "device_common.h"
 #include "fastmath.h"
 
 namespace fga {
 namespace {
 
-constexpr int RW = 8;  // points per wavefront
+constexpr int RW = 4;  // points per wavefront
 constexpr int PG = 4 * RW;  // points per workgroup
 
 // Workgroup -> (point group, beam range, sample).  Workgroups are dealt to
