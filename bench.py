@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 #   one RK4 beam-step (4 right-hand sides + the update), per medium kind,
 #   one receiver/point term (window test excluded), one grid term.
 FLOP_BEAM_STEP = {"homogeneous": 3390, "grid": 4186, "layered": 3390}
-FLOP_POINT_EVAL = 87      # FP64 flops per in-window receiver term (window test, exponent, phase, table
+FLOP_POINT_EVAL = 79      # FP64 flops per in-window receiver term (window test, exponent, phase, table
                           # exp and sincos, 12 accumulating FMAs), FMA = 2, counted in the gfx950 code
 FLOP_GRID_EVAL = 24       # 3 complex multiply-adds
 PEAK_FP64 = 78.6e12       # FP64 vector and FP64 matrix peak, MI355X

@@ -1,13 +1,14 @@
 // Table-driven FP64 complex exponential for bounded arguments:
-//   cexp_neg(g, phi) = exp(-g) (cos phi + i sin phi),  0 <= g <~ 700, |phi| < 2^20 pi/32.
+//   cexp_neg(g, phi) = exp(-g) (cos phi + i sin phi),  0 <= g <~ 700 (larger g: exactly 0 up to g ~ 2800),
+//   |phi| < 2^20 pi/128.
 //
-// exp: Tang's table-driven method.  x = -g = (64 m + j) ln2/64 + r with
-//   |r| <= ln2/128, so exp(x) = 2^m 2^{j/64} (1 + r + r^2/2 + ... + r^5/120);
-//   the omitted r^6/720 term is below 4e-17 relative.
-// sin/cos: reduction by multiples of pi/32 (three-part Cody-Waite constant),
-//   |r| <= pi/64, Taylor polynomials of r (through r^9 for sin, r^8 for cos,
-//   truncation below 1e-17), then the angle-addition formulas with
-//   sin(j pi/32), cos(j pi/32) from a 64-entry table.
+// exp: Tang's table-driven method.  x = -g = (256 m + j) ln2/256 + r with
+//   |r| <= ln2/512, so exp(x) = 2^m 2^{j/256} (1 + r + r^2/2 + r^3/6 + r^4/24);
+//   the omitted r^5/120 term is below 4e-17 relative.
+// sin/cos: reduction by multiples of pi/128 (three-part Cody-Waite constant),
+//   |r| <= pi/256, Taylor polynomials of r (through r^5 for sin, r^6 for cos,
+//   truncation below 1e-17 absolute), then the angle-addition formulas with
+//   sin(j pi/128), cos(j pi/128) from a 256-entry table.
 // The tables are filled per workgroup from the device library's exp2/sincos,
 // so every entry is correctly rounded or within an ulp.
 #pragma once
@@ -16,65 +17,62 @@
 
 namespace fga {
 
+constexpr int TRIG_N = 256;
 struct TrigTables {
-  double e2[64];    // 2^(j/64)
-  double sn[64];    // sin(j pi/32)
-  double cs[64];    // cos(j pi/32)
+  double e2[TRIG_N];    // 2^(j/256)
+  double sn[TRIG_N];    // sin(j pi/128)
+  double cs[TRIG_N];    // cos(j pi/128)
 };
 
 // Fill the tables; call from every thread of the block, then __syncthreads().
 __device__ __forceinline__ void fill_tables(TrigTables &t)
 {
-  for (int j = threadIdx.x; j < 64; j += blockDim.x) {
-    t.e2[j] = exp2((double)j / 64.0);
+  for (int j = threadIdx.x; j < TRIG_N; j += blockDim.x) {
+    t.e2[j] = exp2((double)j / 256.0);
     double s, c;
-    sincospi((double)j / 32.0, &s, &c);
+    sincospi((double)j / 128.0, &s, &c);
     t.sn[j] = s;
     t.cs[j] = c;
   }
 }
 
-// 64/ln2, ln2/64 split so that k*LN2_64_HI is exact for |k| < 2^20
-// (hi has 32 significant bits; hi + lo = ln2/64 to ~1e-29).
-constexpr double INV_LN2_64 = 92.33248261689366;
-constexpr double LN2_64_HI = 0.010830424696905538;
-constexpr double LN2_64_LO = -6.563929801064195e-13;
-// 32/pi and pi/32 in three parts (hi and mid with 32 significant bits).
-constexpr double INV_PI_32 = 10.185916357881302;
-constexpr double PI_32_HI = 0.09817477042088285;
-constexpr double PI_32_MID = 3.798187816439979e-12;
-constexpr double PI_32_LO = 1.2639164054974691e-22;
+// 256/ln2, ln2/256 split so that k*LN2_256_HI is exact for |k| < 2^20
+// (hi has 32 significant bits; hi + lo = ln2/256 to ~5e-30).
+constexpr double INV_LN2_256 = 369.3299304675746;
+constexpr double LN2_256_HI = 0.0027076061742263846;
+constexpr double LN2_256_LO = -1.6409824502660487e-13;
+// 128/pi and pi/128 in three parts (hi and mid with 32 significant bits).
+constexpr double INV_PI_128 = 40.74366543152521;
+constexpr double PI_128_HI = 0.024543692605220713;
+constexpr double PI_128_MID = 9.495469541099947e-13;
+constexpr double PI_128_LO = 3.159791013743673e-23;
 
 __device__ __forceinline__ void cexp_neg(const TrigTables &t, double g, double phi, double &re, double &im)
 {
   // exp(-g)
   const double x = -g;
-  const double kd = rint(x * INV_LN2_64);
+  const double kd = rint(x * INV_LN2_256);
   const int k = (int)kd;
-  const int j = k & 63;
-  const int m = (k - j) >> 6;
-  double r = fma(-kd, LN2_64_HI, x);
-  r = fma(-kd, LN2_64_LO, r);
-  double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-  q = fma(r, q, 1.0 / 6.0);
+  const int j = k & (TRIG_N - 1);
+  const int m = (k - j) >> 8;
+  double r = fma(-kd, LN2_256_HI, x);
+  r = fma(-kd, LN2_256_LO, r);
+  double q = fma(r, 1.0 / 24.0, 1.0 / 6.0);
   q = fma(r, q, 0.5);
   q = fma(r, q, 1.0);
   q = q * r;  // p(r) - 1
   const double tj = t.e2[j];
   const double ex = ldexp(fma(tj, q, tj), m);
   // sin / cos
-  const double nd = rint(phi * INV_PI_32);
-  const int n = (int)nd & 63;
-  double u = fma(-nd, PI_32_HI, phi);
-  u = fma(-nd, PI_32_MID, u);
-  u = fma(-nd, PI_32_LO, u);
+  const double nd = rint(phi * INV_PI_128);
+  const int n = (int)nd & (TRIG_N - 1);
+  double u = fma(-nd, PI_128_HI, phi);
+  u = fma(-nd, PI_128_MID, u);
+  u = fma(-nd, PI_128_LO, u);
   const double u2 = u * u;
-  double sp = fma(u2, 1.0 / 362880.0, -1.0 / 5040.0);
-  sp = fma(u2, sp, 1.0 / 120.0);
-  sp = fma(u2, sp, -1.0 / 6.0);
+  const double sp = fma(u2, 1.0 / 120.0, -1.0 / 6.0);
   const double su = fma(u * u2, sp, u);
-  double cp = fma(u2, 1.0 / 40320.0, -1.0 / 720.0);
-  cp = fma(u2, cp, 1.0 / 24.0);
+  double cp = fma(u2, -1.0 / 720.0, 1.0 / 24.0);
   cp = fma(u2, cp, -0.5);
   const double cu = fma(u2, cp, 1.0);
   const double sj = t.sn[n], cj = t.cs[n];
