@@ -205,8 +205,10 @@ struct TileSmem : ListSmem {
 // One batch of `cnt` (<= NB) accepted beams, listed by sorted position in
 // sm.list[0..cnt): build the window-masked 1-D factors and W Ez, then the
 // K = 2 cnt (re, im) slice of the tile GEMM on the matrix cores.
+// This workgroup's wavefronts own tile rows j = j0 + RB w + rb, rb < RB.
+template <int RB>
 __device__ __forceinline__ void grid_batch(const GridGeom &g, const double *__restrict__ rec, TileSmem &sm, int cnt,
-                                           const int tc[3], d4 acc[4][6])
+                                           const int tc[3], d4 acc[RB][6], int j0)
 {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const double hieps = 0.5 / g.eps;
@@ -239,10 +241,10 @@ __device__ __forceinline__ void grid_batch(const GridGeom &g, const double *__re
   for (int ks = 0; ks < nks; ++ks) {
     const int jb = 2 * ks + (kk >> 1);
     const double2 xv = sm.Ex[jb][li];
-    double a[4];
+    double a[RB];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const double2 yv = sm.Ey[jb][4 * w + rb];
+    for (int rb = 0; rb < RB; ++rb) {
+      const double2 yv = sm.Ey[jb][j0 + RB * w + rb];
       double xr, xi;
       cmul(xv.x, xv.y, yv.x, yv.y, xr, xi);
       a[rb] = part ? xi : xr;
@@ -255,7 +257,7 @@ __device__ __forceinline__ void grid_batch(const GridGeom &g, const double *__re
       b[3 + c] = part ? v.x : v.y;  // columns of Im U
     }
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 6; ++cb)
         acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
@@ -263,29 +265,33 @@ __device__ __forceinline__ void grid_batch(const GridGeom &g, const double *__re
   __syncthreads();
 }
 
+// FP64: a tile's 16 rows are split over two workgroups (8 rows each), which
+// halves the accumulators so that two wavefronts fit per SIMD and one's
+// factor work overlaps the other's matrix-core work.
 struct PolicyF64 {
+  static constexpr int SPLIT = 2, RB = 4 / SPLIT;
   typedef TileSmem Smem;
-  typedef d4 Acc[4][6];
+  typedef d4 Acc[RB][6];
   static __device__ void init(Smem &sm) { fill_tables(sm.tab); }
   static __device__ void zero(Acc &acc)
   {
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
   }
   static __device__ void batch(const GridGeom &g, const double *rec, Smem &sm, int cnt, const int tc[3], Acc &acc,
-                               double)
+                               double, int half)
   {
-    grid_batch(g, rec, sm, cnt, tc, acc);
+    grid_batch<RB>(g, rec, sm, cnt, tc, acc, half * (16 / SPLIT));
   }
   // result register r of lane holds D[lane/16 + 4r][lane % 16] (row: x index i; column: z index l)
-  static __device__ void store(const Acc &acc, double *P, double)
+  static __device__ void store(const Acc &acc, double *P, double, int half)
   {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int j = 4 * w + rb;
+    for (int rb = 0; rb < RB; ++rb) {
+      const int j = half * (16 / SPLIT) + RB * w + rb;
 #pragma unroll
       for (int cb = 0; cb < 6; ++cb) {
         const int u = cb / 3, c = cb % 3;
@@ -358,6 +364,7 @@ __device__ __forceinline__ void mx_factors(const GridGeom &g, const double *__re
 }
 
 template <int PREC> struct PolicyMx {
+  static constexpr int SPLIT = 1;
   typedef MxSmem Smem;
   typedef f4 Acc[4][6];
   static __device__ void init(Smem &) {}
@@ -378,7 +385,7 @@ template <int PREC> struct PolicyMx {
     }
   }
   static __device__ void batch(const GridGeom &g, const double *rec, Smem &sm, int cnt, const int tc[3], Acc &acc,
-                               double iws)
+                               double iws, int)
   {
     mx_factors(g, rec, sm, cnt, tc, iws);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -457,7 +464,7 @@ template <int PREC> struct PolicyMx {
     __syncthreads();
   }
   // result register r of lane holds D[4 (lane/16) + r][lane % 16]; scaled back by wmax
-  static __device__ void store(const Acc &acc, double *P, double ws)
+  static __device__ void store(const Acc &acc, double *P, double ws, int)
   {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -486,7 +493,9 @@ __global__ __launch_bounds__(256) void k_grid_tile(GridGeom g, const int64_t *__
   Pol::init(sm);
   const double ws = wmax ? __longlong_as_double((long long)*wmax) : 1.0;
   const double iws = ws > 0.0 ? 1.0 / ws : 0.0;
-  const Item it = items[blockIdx.x];
+  const int64_t item = blockIdx.x / Pol::SPLIT;
+  const int half = blockIdx.x % Pol::SPLIT;
+  const Item it = items[item];
   const int t = it.tile;
   const int tc[3] = {t % g.nt[0], (t / g.nt[0]) % g.nt[1], t / (g.nt[0] * g.nt[1])};
   const int nr = (2 * g.reach[1] + 1) * (2 * g.reach[2] + 1);
@@ -543,7 +552,7 @@ __global__ __launch_bounds__(256) void k_grid_tile(GridGeom g, const int64_t *__
     __syncthreads();
     int ln = base + tot;
     while (ln >= NB) {
-      Pol::batch(g, rec, sm, NB, tc, acc, iws);
+      Pol::batch(g, rec, sm, NB, tc, acc, iws, half);
       nexec += NB;
       const int32_t v = tid + NB < ln ? sm.list[tid + NB] : 0;
       __syncthreads();
@@ -555,12 +564,12 @@ __global__ __launch_bounds__(256) void k_grid_tile(GridGeom g, const int64_t *__
   }
   if (sm.listn > 0) {
     const int cnt = sm.listn;
-    Pol::batch(g, rec, sm, cnt, tc, acc, iws);
+    Pol::batch(g, rec, sm, cnt, tc, acc, iws, half);
     nexec += cnt;
   }
-  if (tid == 0 && executed && nexec) atomicAdd(executed, nexec);
+  if (tid == 0 && half == 0 && executed && nexec) atomicAdd(executed, nexec);
   // partial tile [c][l][j][i] complex
-  Pol::store(acc, partial + (int64_t)blockIdx.x * (3 * T * T * T * 2), ws);
+  Pol::store(acc, partial + item * (3 * T * T * T * 2), ws, half);
 }
 
 // out[c][z][y][x] = sum of the tile's partials (fixed item order); points
@@ -690,7 +699,8 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
     const unsigned nwg = (unsigned)hi.size();
     switch (precision) {
       case FGA_FP64:
-        hipLaunchKernelGGL(k_grid_tile<PolicyF64>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1, nullptr);
+        hipLaunchKernelGGL(k_grid_tile<PolicyF64>, nwg * PolicyF64::SPLIT, 256, 0, st, g, start, items, rec, partial,
+                           ev + 1, nullptr);
         break;
       case FGA_FP32:
         hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_FP32>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
