@@ -21,6 +21,7 @@ namespace fga {
 namespace {
 
 constexpr int RW = 4;  // points per wavefront
+constexpr int GRP = RW < 4 ? RW : 4;  // points evaluated together
 constexpr int PG = 4 * RW;  // points per workgroup
 
 // Workgroup -> (point group, beam range, sample).  Workgroups are dealt to
@@ -138,12 +139,12 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
     // window a term gets the argument g = 2048, whose exponential underflows
     // to exactly zero.
 #pragma unroll
-    for (int k = 0; k < RW; k += 4) {
-      double dd[4][3];
-      bool in[4];
+    for (int k = 0; k < RW; k += GRP) {
+      double dd[GRP][3];
+      bool in[GRP];
       bool any = false;
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
+      for (int h = 0; h < GRP; ++h) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) dd[h][d] = xr[k + h][d] - q[d];
         in[h] = !(fmax(fabs(dd[h][0]), fmax(fabs(dd[h][1]), fabs(dd[h][2]))) > R);
@@ -151,9 +152,9 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
         any = any || in[h];
       }
       if (!__any(any)) continue;
-      double er[4], ei[4];
+      double er[GRP], ei[GRP];
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
+      for (int h = 0; h < GRP; ++h) {
         const double g = in[h] ? (dd[h][0] * dd[h][0] + dd[h][1] * dd[h][1] + dd[h][2] * dd[h][2]) * hieps : 2048.0;
         const double ph = in[h] ? pe[0] * dd[h][0] + pe[1] * dd[h][1] + pe[2] * dd[h][2] : 0.0;
         if constexpr (MIXED) {
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
         }
       }
 #pragma unroll
-      for (int h = 0; h < 4; ++h)
+      for (int h = 0; h < GRP; ++h)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           u[k + h][2 * c] = fma(er[h], B[2 * c], fma(-ei[h], B[2 * c + 1], u[k + h][2 * c]));
