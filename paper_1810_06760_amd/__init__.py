@@ -239,11 +239,19 @@ class BeamSet:
     def count(self) -> int:
         return int(self.c.count)
 
-    def export(self) -> dict:
-        """Host copy of the live beams: dict of numpy arrays."""
-        n = self.count
-        F = self.f64[:, :n].cpu().numpy()
-        I = self.i32[:, :n].cpu().numpy()
+    def export(self, index=None) -> dict:
+        """Host copy of the live beams (or of the slots in `index`, a device
+        int64 tensor): dict of numpy arrays."""
+        if index is None:
+            n = self.count
+            F = self.f64[:, :n].cpu().numpy()
+            I = self.i32[:, :n].cpu().numpy()
+            lin = self.lineage[:n].cpu().numpy().copy()
+        else:
+            n = int(index.numel())
+            F = self.f64[:, index].cpu().numpy()
+            I = self.i32[:, index].cpu().numpy()
+            lin = self.lineage[index].cpu().numpy().copy()
         ZQ = (F[FGA_ZQ_RE:FGA_ZQ_RE + 9] + 1j * F[FGA_ZQ_IM:FGA_ZQ_IM + 9]).T.reshape(n, 3, 3)
         ZP = (F[FGA_ZP_RE:FGA_ZP_RE + 9] + 1j * F[FGA_ZP_IM:FGA_ZP_IM + 9]).T.reshape(n, 3, 3)
         a = np.stack([F[FGA_A0_RE] + 1j * F[FGA_A0_IM], F[FGA_A1_RE] + 1j * F[FGA_A1_IM]], axis=1)
@@ -252,7 +260,7 @@ class BeamSet:
             "S": F[FGA_S].copy(), "w": F[FGA_W_RE] + 1j * F[FGA_W_IM], "e": F[FGA_E:FGA_E + 3].T.copy(),
             "branch": I[FGA_BRANCH].copy(), "sigma": I[FGA_SIGMA].copy(), "layer": I[FGA_LAYER].copy(),
             "gen": I[FGA_GEN].copy(), "flags": I[FGA_FLAGS].copy(),
-            "lineage": self.lineage[:n].cpu().numpy().copy(),
+            "lineage": lin,
         }
 
     def load(self, d: dict) -> None:

@@ -1,0 +1,92 @@
+"""Parity at the benchmark's full size: smooth random medium, eps = 1/128,
+q 32^3 x p 8^3 x 3 branches (49 M beams after the cull), 1000 FP64 RK4
+steps with 256 receivers sampled after every step, 128^3 grid at T = 1, run
+in the launch configuration the benchmark times (the evolution as 4 calls of
+250 steps sharing one workspace).
+
+Outputs the oracle can compute one by one are compared with it: every beam
+of 200 seeded (q, p) pairs, decomposed and evolved 1000 steps by the oracle,
+against the GPU beam of the same lineage (the GPU set is re-sorted in space
+during the run).  Sums over all 49 M beams are beyond the oracle; for them
+the test checks properties that hold at any size: the MFMA grid tiles and
+the ALU point sums (independent kernels) agree at 512 seeded grid points,
+and the last seismogram sample, summed from the records the integrator
+emits, equals a point sum at the receivers over the final beams."""
+import sys
+
+import numpy as np
+import pytest
+
+import fga_inputs as fi
+import oracle as om
+from test_gpu_parity import compare_states, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+SEGMENTS = 4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.timeout(600)
+def test_smooth_medium_full_size():
+    import torch
+    import paper_1810_06760_amd as m
+    m.lib()
+    say("full size: smooth medium, 32^3 x 8^3 x 3, 1000 steps, 256 receivers, 128^3 grid")
+    w = fi.smooth_medium_packet()
+    med = m.medium_for(w)
+    mesh = m.mesh_for(w)
+    beams = m.BeamSet(w.qmesh.count * w.pmesh.count * 3)
+    m.fga_decompose(med, mesh, m._complex_dev(w.f), beams=beams)
+    n0 = beams.count
+    say("  decomposed", n0)
+    assert n0 > 4.5e7
+    seg = w.nsteps // SEGMENTS
+    nrec = len(w.receivers)
+    ws = m._workspace(m.workspace_bytes("evolve", beams=beams, nsteps=seg, n_receivers=nrec, eps=w.eps, tau=w.tau))
+    seis = torch.empty((nrec, w.nsteps, 3, 2), dtype=torch.float64, device="cuda")
+    steps = 0
+    for s0 in range(0, w.nsteps, seg):
+        part, st = m.fga_evolve(med, beams, w.dt, seg, receivers=w.receivers, eps=w.eps, tau=w.tau, ws=ws)
+        seis[:, s0:s0 + seg].copy_(part)
+        steps += st["beam_steps"]
+        say("  steps", s0 + seg)
+    assert beams.count == n0 and steps == n0 * w.nsteps
+    grid, evg = m.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid)
+    torch.cuda.synchronize()
+    say("  grid done, evals", evg)
+
+    # sampled beams: oracle decompose + 1000 steps
+    g = np.random.default_rng(4243)
+    pick = g.choice(w.qmesh.count * w.pmesh.count, size=200, replace=False)
+    iq, ip = pick % w.qmesh.count, pick // w.qmesh.count
+    ob = om.decompose(w, iq=iq, ip=ip)
+    om.evolve(om.medium_for(w), ob, w.dt, w.nsteps)
+    say("  oracle beams", len(ob))
+    lin = torch.from_numpy(ob["lineage"].astype(np.int64)).cuda()
+    idx = torch.isin(beams.lineage[:beams.count], lin).nonzero().squeeze(1)
+    assert idx.numel() == len(ob)
+    compare_states(beams.export(idx), ob)
+
+    # MFMA grid tiles against ALU point sums at sampled grid points
+    n = w.out_grid.n[0]
+    sel = g.choice(w.out_grid.count, size=512, replace=False)
+    pts = w.out_grid.points()[sel]
+    up, _ = m.fga_reconstruct_points(beams, w.eps, w.tau, pts)
+    G = m.to_complex(grid)                      # [3][z][y][x]
+    zi, yi, xi = sel // (n * n), (sel // n) % n, sel % n
+    ug = G[:, zi, yi, xi].T
+    err = rel_l2(ug, m.to_complex(up))
+    say("  grid vs points", err)
+    assert err <= RTOL
+
+    # last seismogram sample against a point sum at the receivers
+    ur, _ = m.fga_reconstruct_points(beams, w.eps, w.tau, w.receivers)
+    err = rel_l2(m.to_complex(seis[:, -1]), m.to_complex(ur))
+    say("  seismogram vs points", err)
+    assert err <= RTOL
