@@ -11,6 +11,11 @@
 //   sin(j pi/128), cos(j pi/128) from a 256-entry table.
 // The tables are filled per workgroup from the device library's exp2/sincos,
 // so every entry is correctly rounded or within an ulp.
+//
+// cexp_neg_units takes the phase in units of pi/128 (v = phi 128/pi, so the
+// reduction is v - rint(v) with no constant to split) and a mask; both
+// roundings to an integer add 1.5 2^52, which leaves round-to-nearest(x) in
+// the low mantissa bits for |x| < 2^51.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -69,6 +74,48 @@ __device__ __forceinline__ void cexp_neg(const TrigTables &t, double g, double p
   double u = fma(-nd, PI_128_HI, phi);
   u = fma(-nd, PI_128_MID, u);
   u = fma(-nd, PI_128_LO, u);
+  const double u2 = u * u;
+  const double sp = fma(u2, 1.0 / 120.0, -1.0 / 6.0);
+  const double su = fma(u * u2, sp, u);
+  double cp = fma(u2, -1.0 / 720.0, 1.0 / 24.0);
+  cp = fma(u2, cp, -0.5);
+  const double cu = fma(u2, cp, 1.0);
+  const double sj = t.sn[n], cj = t.cs[n];
+  const double sphi = fma(su, cj, cu * sj);
+  const double cphi = fma(cu, cj, -(su * sj));
+  re = ex * cphi;
+  im = ex * sphi;
+}
+
+constexpr double RND_MAGIC = 6755399441055744.0;  // 1.5 * 2^52
+constexpr double PI_128 = 0.02454369260617026;      // pi/128
+
+// in ? exp(-g) (cos(v pi/128) + i sin(v pi/128)) : 0, for 0 <= g <~ 700 and
+// |v| < 2^51 where in is true; where it is false g >= 0 and v may be any
+// finite values (the magnitude is replaced by 0 before it meets the phase).
+__device__ __forceinline__ void cexp_neg_units(const TrigTables &t, double g, double v, bool in, double &re,
+                                               double &im)
+{
+  // exp(-g)
+  const double tk = fma(g, -INV_LN2_256, RND_MAGIC);
+  const double kd = tk - RND_MAGIC;
+  const int k = __double2loint(tk);
+  const int j = k & (TRIG_N - 1);
+  const int m = k >> 8;  // floor(k / 256)
+  double r = fma(-kd, LN2_256_HI, -g);
+  r = fma(-kd, LN2_256_LO, r);
+  double q = fma(r, 1.0 / 24.0, 1.0 / 6.0);
+  q = fma(r, q, 0.5);
+  q = fma(r, q, 1.0);
+  q = q * r;  // p(r) - 1
+  const double tj = t.e2[j];
+  double ex = ldexp(fma(tj, q, tj), m);
+  ex = in ? ex : 0.0;
+  // sin / cos: v - rint(v) is exact, |u| <= pi/256
+  const double tn = v + RND_MAGIC;
+  const double nd = tn - RND_MAGIC;
+  const int n = __double2loint(tn) & (TRIG_N - 1);
+  const double u = (v - nd) * PI_128;
   const double u2 = u * u;
   const double sp = fma(u2, 1.0 / 120.0, -1.0 / 6.0);
   const double su = fma(u * u2, sp, u);

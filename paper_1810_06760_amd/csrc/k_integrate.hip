@@ -7,6 +7,7 @@
 // back (the right-hand side and the RK4 step are in rk4.h).  In layered media
 // a beam whose centre leaves its layer during a step keeps its stored state
 // and is flagged for the interface step.
+#include "fastmath.h"
 #include "rk4.h"
 
 namespace fga {
@@ -14,7 +15,7 @@ namespace {
 
 using namespace rk;
 
-// Emission record of the current state: Q (3), P (3), B = w e^{iS/eps} A (3 complex).
+// Emission record of the current state: Q (3), P 128/(pi eps) (3), B = w e^{iS/eps} A (3 complex).
 __device__ __forceinline__ void emit_record(double *__restrict__ out, int64_t nb, int64_t j,
                                             const double *y, const double e[3], double wr, double wi,
                                             bool isS, double ieps)
@@ -40,10 +41,11 @@ __device__ __forceinline__ void emit_record(double *__restrict__ out, int64_t nb
   double sn, cs;
   sincos(y[IS] * ieps, &sn, &cs);
   const double Wr = wr * cs - wi * sn, Wi = wr * sn + wi * cs;
+  const double pscale = ieps * INV_PI_128;
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     out[f * nb + j] = y[IQ + f];
-    out[(3 + f) * nb + j] = y[IP + f] * ieps;  // P/eps: the phase is (P/eps).(x - Q)
+    out[(3 + f) * nb + j] = y[IP + f] * pscale;  // the phase (P/eps).(x - Q) in units of pi/128
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {

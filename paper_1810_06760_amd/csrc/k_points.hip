@@ -2,7 +2,7 @@
 //
 // Beam-major layout.  A wavefront owns RW = 4 points and walks a range of
 // beams 64 at a time, one beam per lane, each lane holding its beam's
-// emission record (Q, P/eps, B = w e^{iS/eps} A) in registers (fetched one
+// emission record (Q, P 128/(pi eps), B = w e^{iS/eps} A) in registers (fetched one
 // tile ahead) and RW complex 3-vector sums; the four points are evaluated
 // together, four independent exponential chains per lane.  The beam set is
 // kept in Morton order of Q, so the 64 beams of a tile are close together
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
 #pragma unroll
   for (int k = 0; k < RW; ++k)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xr[k][d] = r0 + k < a.n ? a.xyz[3 * (r0 + k) + d] : 1.0e300;
+    for (int d = 0; d < 3; ++d) xr[k][d] = r0 + k < a.n ? a.xyz[3 * (r0 + k) + d] : 1.0e30;
   const double R = sqrt(2.0 * a.tau * a.eps);
   const double hieps = 0.5 / a.eps;
   const int64_t b0 = wk.blk * a.beams_per_block;
@@ -136,8 +136,7 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
     // points four at a time: unless no lane's beam is in any of the four
     // windows, the four terms are evaluated together (four independent
     // exponential chains per lane hide each other's latency).  Outside its
-    // window a term gets the argument g = 2048, whose exponential underflows
-    // to exactly zero.
+    // window a term's magnitude is replaced by zero.
 #pragma unroll
     for (int k = 0; k < RW; k += GRP) {
       double dd[GRP][3];
@@ -155,16 +154,16 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
       double er[GRP], ei[GRP];
 #pragma unroll
       for (int h = 0; h < GRP; ++h) {
-        const double g = in[h] ? (dd[h][0] * dd[h][0] + dd[h][1] * dd[h][1] + dd[h][2] * dd[h][2]) * hieps : 2048.0;
-        const double ph = in[h] ? pe[0] * dd[h][0] + pe[1] * dd[h][1] + pe[2] * dd[h][2] : 0.0;
+        const double g = (dd[h][0] * dd[h][0] + dd[h][1] * dd[h][1] + dd[h][2] * dd[h][2]) * hieps;
+        const double v = pe[0] * dd[h][0] + pe[1] * dd[h][1] + pe[2] * dd[h][2];  // phase in units of pi/128
         if constexpr (MIXED) {
-          const double rev = ph * INV_2PI;
+          const double rev = v * (1.0 / 256.0);
           const float r = (float)(rev - rint(rev));
           const float amp = in[h] ? __builtin_amdgcn_exp2f((float)(-g * LOG2E)) : 0.0f;
           er[h] = (double)(amp * __builtin_amdgcn_cosf(r));
           ei[h] = (double)(amp * __builtin_amdgcn_sinf(r));
         } else {
-          cexp_neg(tab, g, ph, er[h], ei[h]);
+          cexp_neg_units(tab, g, v, in[h], er[h], ei[h]);
         }
       }
 #pragma unroll
