@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered"])
+    ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered", "mixed"])
+    ap.add_argument("--waves", type=int, default=4, help="beam waves of the mixed-precision workload")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -439,6 +440,103 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def mixed(args):
+    """Mixed-precision grid summation at eps = 1/512: config 2's medium and
+    packet form, q 50^3 x p 8^3 x 3 branches in waves (q slabs along z);
+    each wave is decomposed, evolved 250 FP64 RK4 steps to T = 0.25 and summed
+    onto the 256^3 grid (tau = 16) by every variant (FP64, FP32, BF16 hi+lo,
+    FP16 hi+lo), each added into its own output.  Reports per variant the
+    tile-kernel time, algorithmic evals/s and its fraction of the operand
+    type's dense MFMA peak, and the relative L2 error against the FP64 sum
+    (itself at oracle parity).  --scale shrinks the q mesh per axis."""
+    import torch
+    import fga_inputs as fi
+    import paper_1810_06760_amd as fga
+
+    nq = max(4, int(round(50 * args.scale)))
+    w, slabs = fi.mixed_waves(nq=nq, waves=args.waves)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    med = fga.medium_for(w)
+    f = fga._complex_dev(w.f)
+    cap = max(q.count for q in slabs) * w.pmesh.count * 3
+    beams = fga.BeamSet(cap)
+    n = w.out_grid.n
+    variants = ["fp64", "fp32", "bf16x3", "fp16x3"]
+    outs = {v: torch.zeros((3, n[2], n[1], n[0], 2), dtype=torch.float64, device=dev) for v in variants}
+    stats = {v: {"tile_ms": 0.0, "call_s": 0.0, "evals": 0} for v in variants}
+    ws = {}
+    tot = {"beams": 0, "beam_steps": 0, "decompose_s": 0.0, "evolve_s": 0.0}
+    torch.cuda.synchronize()
+    fga.fga_profile_enable(True)
+    t0 = time.perf_counter()
+    for k, qm in enumerate(slabs):
+        mesh = fga.make_mesh(w.eps, qm, w.pmesh, w.ymesh, cull_abs=w.cull_abs)
+        t = time.perf_counter()
+        if "dec" not in ws:
+            ws["dec"] = fga._workspace(fga.workspace_bytes("decompose", mesh=mesh))
+        fga.fga_decompose(med, mesh, f, beams=beams, ws=ws["dec"])
+        tot["decompose_s"] += time.perf_counter() - t
+        t = time.perf_counter()
+        if "ev" not in ws:
+            ws["ev"] = fga._workspace(fga.workspace_bytes("evolve", beams=beams, nsteps=w.nsteps))
+        _, st = fga.fga_evolve(med, beams, w.dt, w.nsteps, ws=ws["ev"])
+        torch.cuda.synchronize()
+        tot["evolve_s"] += time.perf_counter() - t
+        tot["beams"] += beams.count
+        tot["beam_steps"] += st["beam_steps"]
+        print("bench: wave %d/%d: %d beams decomposed and evolved" % (k + 1, len(slabs), beams.count),
+              file=sys.stderr, flush=True)
+        for v in variants:
+            gw = fga._workspace(fga.workspace_bytes("grid", beams=beams, mesh=w.out_grid, eps=w.eps, tau=w.tau),
+                                ws.get("grid"))
+            ws["grid"] = gw
+            fga.fga_profile_read(fga.FGA_K_GRID_TILE, reset=True)
+            t = time.perf_counter()
+            _, ev = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid, precision=GRID_PREC[v][0],
+                                             out=outs[v], ws=gw, add=k > 0)
+            torch.cuda.synchronize()
+            stats[v]["call_s"] += time.perf_counter() - t
+            stats[v]["tile_ms"] += fga.fga_profile_read(fga.FGA_K_GRID_TILE, reset=True)[1]
+            stats[v]["evals"] += ev
+            print("bench: wave %d/%d: grid %s done" % (k + 1, len(slabs), v), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fga.fga_profile_enable(False)
+    ref = outs["fp64"]
+    nref = float(torch.linalg.vector_norm(ref))
+    var = {}
+    for v in variants:
+        s_ = stats[v]
+        ach = FLOP_GRID_EVAL * s_["evals"] / (s_["tile_ms"] * 1e-3)
+        var[v] = {"tile_kernel_s": s_["tile_ms"] * 1e-3, "call_s": s_["call_s"], "evals": s_["evals"],
+                  "evals_per_s": s_["evals"] / (s_["tile_ms"] * 1e-3),
+                  "achieved_tflops_algorithmic": ach / 1e12, "peak_tflops": GRID_PREC[v][1] / 1e12,
+                  "frac_algorithmic": ach / GRID_PREC[v][1],
+                  "mfma_flops_per_term": 72 if v.endswith("x3") else 24,
+                  "rel_l2_vs_fp64": float(torch.linalg.vector_norm(outs[v] - ref)) / nref}
+    dom = max(variants, key=lambda v: stats[v]["tile_ms"])
+    line = {
+        "metric": "beam-steps/s + beam-point evals/s; served solves/s, p50/p99 at rel-L2<=1e-3",
+        "value": tot["beam_steps"] / elapsed,
+        "unit": "beam-steps/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * elapsed,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32/bf16/f16", "data": "synthetic",
+        "config": {"workload": "mixed-precision grid: config-2 medium and packet at eps=1/512, q %d^3 x p 8^3 x 3 "
+                               "branches in %d waves, 250 FP64 RK4 steps to T=0.25, 256^3 grid (tau=16) summed by "
+                               "FP64, FP32, BF16 hi+lo and FP16 hi+lo tile GEMMs" % (nq, len(slabs)),
+                   "beams": tot["beams"], "waves": len(slabs), "parallelism": "single GPU"},
+        "beam_point_evals_per_s": sum(stats[v]["evals"] for v in variants) / elapsed,
+        "decompose_s": tot["decompose_s"], "evolve_s": tot["evolve_s"],
+        "variants": var,
+        "roofline": {"bound": "mfma", "kernel": "grid_tile/" + dom,
+                     "achieved": var[dom]["achieved_tflops_algorithmic"], "peak": var[dom]["peak_tflops"],
+                     "unit": "TFLOP/s", "frac": var[dom]["frac_algorithmic"], "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -451,6 +549,9 @@ def main():
         return
     if args.workload == "layered":
         layered(args)
+        return
+    if args.workload == "mixed":
+        mixed(args)
         return
     if args.copy_calibration:
         import torch

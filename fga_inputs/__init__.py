@@ -205,6 +205,21 @@ def smooth_medium_packet(name="c2", eps=1.0 / 128, nq=32, np_=8, ny=128, nmed=12
     )
 
 
+def mixed_waves(eps=1.0 / 512, nq=50, np_=8, ny=256, nsteps=250, dt=1e-3, nout=256, tau=16.0, waves=4):
+    """The smooth random medium and packet form of config 2 at eps = 1/512,
+    q nq^3 x p np_^3 x 3 branches, evolved to T = nsteps dt and summed on an
+    nout^3 grid of [0,1]^3.  The q mesh is cut into `waves` slabs along z
+    (sizes differing by at most one plane), each decomposed, evolved and summed
+    on its own.  Returns (workload, list of the slabs' q meshes)."""
+    w = smooth_medium_packet(name="c4", eps=eps, nq=nq, np_=np_, ny=ny, nsteps=nsteps, dt=dt, nout=nout, nrec=0,
+                             config=2, tau=tau)
+    q = w.qmesh
+    cuts = [round(k * q.n[2] / waves) for k in range(waves + 1)]
+    slabs = [Mesh3((q.n[0], q.n[1], cuts[k + 1] - cuts[k]), (q.lo[0], q.lo[1], q.lo[2] + cuts[k] * q.h[2]), q.h)
+             for k in range(waves) if cuts[k + 1] > cuts[k]]
+    return w, slabs
+
+
 # ---------------------------------------------------------------------------
 # tomography-style request sweep (serving)
 # ---------------------------------------------------------------------------

@@ -331,6 +331,14 @@ fga_status fga_reconstruct_grid(const fga_beams *beams, double eps, double tau, 
                                 const double lo[3], const double h[3], int precision, double *out,
                                 void *workspace, size_t workspace_bytes, void *stream,
                                 int64_t *evals);
+/* The same sum added to out (out += u) instead of overwriting it, for beam
+ * sets summed in waves (Step 3 is linear in the beams, eq:FGA).  Arguments,
+ * workspace and errors as fga_reconstruct_grid; out must hold the previous
+ * partial sum (or zeros). */
+fga_status fga_reconstruct_grid_add(const fga_beams *beams, double eps, double tau, const int n[3],
+                                    const double lo[3], const double h[3], int precision, double *out,
+                                    void *workspace, size_t workspace_bytes, void *stream,
+                                    int64_t *evals);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: forward solves for many sources on one GPU (tomography sweeps)   */

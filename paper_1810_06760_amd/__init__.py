@@ -38,6 +38,7 @@ EXPORTED = ["fga_last_error", "fga_version", "fga_medium_grid_table_bytes", "fga
             "fga_decompose_workspace_bytes", "fga_decompose_candidates", "fga_decompose",
             "fga_evolve_workspace_bytes", "fga_evolve", "fga_reconstruct_points_workspace_bytes",
             "fga_reconstruct_points", "fga_reconstruct_grid_workspace_bytes", "fga_reconstruct_grid",
+            "fga_reconstruct_grid_add",
             "fga_profile_enable", "fga_profile_read", "fga_server_footprint", "fga_server_create",
             "fga_server_submit", "fga_server_poll", "fga_server_status", "fga_server_destroy",
             "fga_point_source_candidates", "fga_decompose_point_source_workspace_bytes",
@@ -144,6 +145,8 @@ def lib():
         L.fga_reconstruct_grid_workspace_bytes.argtypes = [vp, vp, C.c_double, C.c_double, vp]
         L.fga_reconstruct_grid.restype = st
         L.fga_reconstruct_grid.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp, C.c_int, vp, vp, sz, vp, vp]
+        L.fga_reconstruct_grid_add.restype = st
+        L.fga_reconstruct_grid_add.argtypes = L.fga_reconstruct_grid.argtypes
         L.fga_profile_enable.restype = st
         L.fga_profile_enable.argtypes = [C.c_int]
         L.fga_profile_read.restype = st
@@ -467,9 +470,9 @@ def fga_reconstruct_points(beams: BeamSet, eps: float, tau: float, xyz, precisio
 
 
 def fga_reconstruct_grid(beams: BeamSet, eps: float, tau: float, mesh, precision: int = FGA_FP64, out=None,
-                         ws=None):
+                         ws=None, add: bool = False):
     """Step 3 on the grid mesh.lo + i*mesh.h.  Returns (float64 tensor
-    [3, nz, ny, nx, 2], evals)."""
+    [3, nz, ny, nx, 2], evals).  add: sum into `out` (fga_reconstruct_grid_add)."""
     torch = _torch()
     L = lib()
     n = (C.c_int * 3)(*[int(v) for v in mesh.n])
@@ -479,8 +482,11 @@ def fga_reconstruct_grid(beams: BeamSet, eps: float, tau: float, mesh, precision
         out = torch.empty((3, n[2], n[1], n[0], 2), dtype=torch.float64, device="cuda")
     ws = _workspace(L.fga_reconstruct_grid_workspace_bytes(C.byref(beams.c), n, eps, tau, h), ws)
     ev = C.c_int64(0)
-    _check(L.fga_reconstruct_grid(C.byref(beams.c), eps, tau, n, lo, h, precision, _ptr(out), _ptr(ws), ws.numel(),
-                                  _stream(), C.byref(ev)))
+    if add and out is None:
+        raise ValueError("add=True needs the partial sum in out")
+    fn = L.fga_reconstruct_grid_add if add else L.fga_reconstruct_grid
+    _check(fn(C.byref(beams.c), eps, tau, n, lo, h, precision, _ptr(out), _ptr(ws), ws.numel(), _stream(),
+              C.byref(ev)))
     return out, ev.value
 
 

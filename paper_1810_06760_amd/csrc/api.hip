@@ -648,9 +648,9 @@ size_t fga_reconstruct_grid_workspace_bytes(const fga_beams *beams, const int n[
   return need;
 }
 
-fga_status fga_reconstruct_grid(const fga_beams *beams, double eps, double tau, const int n[3], const double lo[3],
-                                const double h[3], int precision, double *out, void *workspace,
-                                size_t workspace_bytes, void *stream, int64_t *evals)
+static fga_status reconstruct_grid(const fga_beams *beams, double eps, double tau, const int n[3],
+                                   const double lo[3], const double h[3], int precision, double *out,
+                                   void *workspace, size_t workspace_bytes, void *stream, int64_t *evals, bool add)
 {
   fga_status s;
   if ((s = check_beams(beams)) != FGA_OK) return s;
@@ -662,7 +662,24 @@ fga_status fga_reconstruct_grid(const fga_beams *beams, double eps, double tau, 
   if (!(eps > 0) || !(tau > 0)) return fail(FGA_EINVAL, "eps and tau must be > 0");
   Arena ar(workspace, workspace_bytes);
   size_t need = 0;
-  return grid_sum_impl(beams, eps, tau, n, lo, h, precision, out, ar, (hipStream_t)stream, false, &need, evals);
+  return grid_sum_impl(beams, eps, tau, n, lo, h, precision, out, ar, (hipStream_t)stream, false, &need, evals,
+                       add);
+}
+
+fga_status fga_reconstruct_grid(const fga_beams *beams, double eps, double tau, const int n[3], const double lo[3],
+                                const double h[3], int precision, double *out, void *workspace,
+                                size_t workspace_bytes, void *stream, int64_t *evals)
+{
+  return reconstruct_grid(beams, eps, tau, n, lo, h, precision, out, workspace, workspace_bytes, stream, evals,
+                          false);
+}
+
+fga_status fga_reconstruct_grid_add(const fga_beams *beams, double eps, double tau, const int n[3],
+                                    const double lo[3], const double h[3], int precision, double *out,
+                                    void *workspace, size_t workspace_bytes, void *stream, int64_t *evals)
+{
+  return reconstruct_grid(beams, eps, tau, n, lo, h, precision, out, workspace, workspace_bytes, stream, evals,
+                          true);
 }
 
 }  // extern "C"

@@ -176,6 +176,6 @@ fga_status compact_beams(fga_beams *b, Arena &ar, hipStream_t st, bool size_only
 // grid summation
 fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n[3], const double lo[3],
                          const double h[3], int precision, double *out, Arena &ar, hipStream_t st,
-                         bool size_only, size_t *need, int64_t *evals);
+                         bool size_only, size_t *need, int64_t *evals, bool add = false);
 
 }  // namespace fga

@@ -572,11 +572,13 @@ __global__ __launch_bounds__(256) void k_grid_tile(GridGeom g, const int64_t *__
   Pol::store(acc, partial + item * (3 * T * T * T * 2), ws, half);
 }
 
-// out[c][z][y][x] = sum of the tile's partials (fixed item order); points
-// outside the grid of a ragged tile are skipped.
+// out[c][z][y][x] = sum of the tile's partials (fixed item order), added to
+// the previous contents with `add`; points outside the grid of a ragged tile
+// are skipped.
 __global__ __launch_bounds__(256) void k_grid_reduce(GridGeom g, const int32_t *__restrict__ first,
                                                      const int32_t *__restrict__ nitems,
-                                                     const double *__restrict__ partial, double *__restrict__ out)
+                                                     const double *__restrict__ partial, double *__restrict__ out,
+                                                     int add)
 {
   const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t plane = (int64_t)g.n[0] * g.n[1] * g.n[2];
@@ -592,6 +594,10 @@ __global__ __launch_bounds__(256) void k_grid_reduce(GridGeom g, const int32_t *
     const double *P = partial + (int64_t)(f + k) * (3 * T * T * T * 2) + ((((int64_t)c * T + l) * T + j) * T + i) * 2;
     re += P[0];
     im += P[1];
+  }
+  if (add) {
+    re = out[2 * id] + re;
+    im = out[2 * id + 1] + im;
   }
   out[2 * id] = re;
   out[2 * id + 1] = im;
@@ -617,7 +623,7 @@ GridGeom make_geom(const int n[3], const double lo[3], const double h[3], double
 
 fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n[3], const double lo[3],
                          const double h[3], int precision, double *out, Arena &ar, hipStream_t st, bool size_only,
-                         size_t *need, int64_t *evals_out)
+                         size_t *need, int64_t *evals_out, bool add)
 {
   if (precision != FGA_FP64 && precision != FGA_FP32 && precision != FGA_BF16X3 && precision != FGA_FP16X3)
     return fail(FGA_EINVAL, "unknown grid summation precision %d", precision);
@@ -718,7 +724,8 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
     FGA_LAUNCH_CHECK();
   }
   const int64_t plane = (int64_t)n[0] * n[1] * n[2];
-  hipLaunchKernelGGL(k_grid_reduce, (unsigned)((3 * plane + 255) / 256), 256, 0, st, g, first, nitems, partial, out);
+  hipLaunchKernelGGL(k_grid_reduce, (unsigned)((3 * plane + 255) / 256), 256, 0, st, g, first, nitems, partial, out,
+                     add ? 1 : 0);
   FGA_LAUNCH_CHECK();
   // the host vectors above must outlive the copies that read them
   FGA_HIP(hipStreamSynchronize(st));

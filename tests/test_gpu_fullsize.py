@@ -90,3 +90,36 @@ def test_smooth_medium_full_size():
     err = rel_l2(m.to_complex(seis[:, -1]), m.to_complex(ur))
     say("  seismogram vs points", err)
     assert err <= RTOL
+
+
+@pytest.mark.timeout(600)
+def test_homogeneous_full_size():
+    """The homogeneous packet at its full size (eps = 1/32, q 8^3 x p 4^3 x 3
+    branches = 98,304 beams, 100 steps to T = 0.5, 32^3 grid), evolved in 4
+    calls of 25 steps: every beam against the oracle, and the grid at 2048
+    seeded points against the oracle's direct sum over all beams."""
+    import torch
+    import paper_1810_06760_amd as m
+    m.lib()
+    say("full size: homogeneous packet, 8^3 x 4^3 x 3, 100 steps, 32^3 grid")
+    w = fi.homogeneous_packet()
+    med = m.medium_for(w)
+    beams = m.fga_decompose(med, m.mesh_for(w), m._complex_dev(w.f))
+    seg = w.nsteps // SEGMENTS
+    ws = m._workspace(m.workspace_bytes("evolve", beams=beams, nsteps=seg))
+    for s0 in range(0, w.nsteps, seg):
+        m.fga_evolve(med, beams, w.dt, seg, ws=ws)
+    grid, _ = m.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid)
+    torch.cuda.synchronize()
+    ob = om.decompose(w)
+    om.evolve(om.medium_for(w), ob, w.dt, w.nsteps)
+    say("  beams", beams.count, len(ob))
+    compare_states(beams.export(), ob)
+    n = w.out_grid.n[0]
+    sel = np.random.default_rng(4244).choice(w.out_grid.count, size=2048, replace=False)
+    uo, _ = om.sum_points(ob, w.out_grid.points()[sel], w.eps, w.tau)
+    G = m.to_complex(grid)
+    ug = G[:, sel // (n * n), (sel // n) % n, sel % n].T
+    err = rel_l2(ug, uo)
+    say("  grid vs oracle", err)
+    assert err <= RTOL

@@ -291,6 +291,32 @@ def test_grid_mixed_precision(prec):
         assert err <= 1e-4   # FP32 factors and 16-bit hi+lo splits carry ~1e-5
 
 
+@pytest.mark.parametrize("prec", ["FGA_FP64", "FGA_BF16X3"])
+def test_grid_add_in_waves(prec):
+    """A beam set summed in three waves (fga_reconstruct_grid then
+    fga_reconstruct_grid_add twice) against the oracle's direct sum over all
+    beams; the in-window counts of the waves add up to the oracle's."""
+    m = fga()
+    say("grid in waves", prec)
+    w = small_c1(nq=5, np_=3, ny=16)
+    ob = evolved_beams(w, 30, 0.005)
+    grid = fi.cell_centred(37, -0.1, 1.1)
+    tau = 16.0
+    cuts = [0, len(ob) // 3, 2 * len(ob) // 3 + 5, len(ob)]
+    ug, ctot = None, 0
+    for k in range(3):
+        part = ob[cuts[k]:cuts[k + 1]]
+        bs = m.BeamSet(len(part))
+        bs.load(oracle_to_dict(part))
+        ug, c = m.fga_reconstruct_grid(bs, w.eps, tau, grid, precision=getattr(m, prec), out=ug, add=k > 0)
+        ctot += c
+    uo, co = om.sum_points(ob, grid.points(), w.eps, tau)
+    assert ctot == co
+    err = rel_l2(m.to_complex(ug).reshape(3, -1).T, uo)
+    say("  rel L2", err)
+    assert err <= (RTOL if prec == "FGA_FP64" else 1e-4)
+
+
 def test_seismogram_parity():
     """Receivers sampled after every step during the evolution."""
     m = fga()
