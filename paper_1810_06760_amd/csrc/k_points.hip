@@ -109,30 +109,21 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
     while (t0 < b1 && !live(t0)) t0 += 64;
     return t0;
   };
-  // records of the lane's beam, software-pipelined one tile ahead so the
-  // global loads overlap the previous tile's arithmetic
-  double nq[3], npe[3], nB[6];
+  // records of the lane's beam for the current tile
+  double q[3], pe[3], B[6];
   auto fetch = [&](int64_t t0) {
     const int64_t j = t0 + lane;
     const bool v = j < b1;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      nq[d] = v ? E[d * a.nb + j] : -1.0e300;
-      npe[d] = v ? E[(3 + d) * a.nb + j] : 0.0;
+      q[d] = v ? E[d * a.nb + j] : -1.0e300;
+      pe[d] = v ? E[(3 + d) * a.nb + j] : 0.0;
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) nB[c] = v ? E[(6 + c) * a.nb + j] : 0.0;
+    for (int c = 0; c < 6; ++c) B[c] = v ? E[(6 + c) * a.nb + j] : 0.0;
   };
-  int64_t t0 = next_live(b0);
-  if (t0 < b1) fetch(t0);
-  while (t0 < b1) {
-    double q[3], pe[3], B[6];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) { q[d] = nq[d]; pe[d] = npe[d]; }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) B[c] = nB[c];
-    const int64_t tn = next_live(t0 + 64);
-    if (tn < b1) fetch(tn);
+  for (int64_t t0 = next_live(b0); t0 < b1; t0 = next_live(t0 + 64)) {
+    fetch(t0);
     // points four at a time: unless no lane's beam is in any of the four
     // windows, the four terms are evaluated together (four independent
     // exponential chains per lane hide each other's latency).  Outside its
@@ -174,7 +165,6 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
           u[k + h][2 * c + 1] = fma(er[h], B[2 * c + 1], fma(ei[h], B[2 * c], u[k + h][2 * c + 1]));
         }
     }
-    t0 = tn;
   }
   // lane reduction in a fixed butterfly order; every lane ends with the total
 #pragma unroll
