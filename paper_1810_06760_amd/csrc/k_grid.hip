@@ -155,12 +155,13 @@ __global__ __launch_bounds__(256) void k_grid_records(const double *__restrict__
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (s >= n || keys[s] == 0x7fffffff) return;
   const int64_t bi = order[s];
+  const double pscale = ieps * INV_PI_128;  // the phase (P/eps).(x - Q) in units of pi/128
   double P[3], e[3];
   double *o = rec + s * 12;
   for (int d = 0; d < 3; ++d) {
     o[d] = F[(FGA_Q + d) * cap + bi];
     P[d] = F[(FGA_P + d) * cap + bi];
-    o[3 + d] = P[d] * ieps;
+    o[3 + d] = P[d] * pscale;
     e[d] = F[(FGA_E + d) * cap + bi];
   }
   const double a0r = F[FGA_A0_RE * cap + bi], a0i = F[FGA_A0_IM * cap + bi];
@@ -221,8 +222,8 @@ __device__ __forceinline__ void grid_batch(const GridGeom &g, const double *__re
     const int jb = e / (3 * T), d = (e / T) % 3, ii = e % T;
     const double x = axis_coord(g, d, T * tc[d] + ii);
     const double u = x - sm.brec[jb][d];
-    double2 E = make_double2(0.0, 0.0);
-    if (fabs(u) <= g.R) cexp_neg(sm.tab, u * u * hieps, sm.brec[jb][3 + d] * u, E.x, E.y);
+    double2 E;
+    cexp_neg_units(sm.tab, u * u * hieps, sm.brec[jb][3 + d] * u, fabs(u) <= g.R, E.x, E.y);
     if (d == 0) sm.Ex[jb][ii] = E;
     else if (d == 1) sm.Ey[jb][ii] = E;
     else sm.Ez[jb][ii] = E;
@@ -313,14 +314,28 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 constexpr double INV_2PI = 0.15915494309189535;
 constexpr double LOG2E = 1.4426950408889634;
 
+// 16-bit operands of one column block: per (column block, l, lane quarter)
+// the 8 consecutive K entries a lane feeds to the matrix core (16 bytes)
+struct alignas(16) H8Raw {
+  uint16_t v[8];
+};
+
 struct MxSmem : ListSmem {
   float2 Ex[NB][T], Ey[NB][T], V[NB][3][T];
+  H8Raw Bh[6][T][4], Bl[6][T][4];
 };
+
+template <class S> __device__ __forceinline__ uint16_t half_bits(S x) { return __builtin_bit_cast(uint16_t, x); }
 
 // Window-masked 1-D factors in FP32 from FP64 arguments: the Gaussian
 // exponent and the phase (in revolutions, reduced to [-1/2, 1/2]) are formed
 // in FP64; exp2 and sin/cos of 2 pi r run on the FP32 transcendental unit.
-// V = (W / wmax) Ez.
+// V = (W / wmax) Ez.  One thread per (beam, tile index): all three axes, so
+// no wavefront diverges.  For the 16-bit products (S = __bf16 / _Float16)
+// the B operand's hi and lo halves are written once per batch, in the K
+// order of the matrix instruction: k = 2 beam + part, with column block c
+// (Re U) taking (Re V, -Im V) and c + 3 (Im U) taking (Im V, Re V).
+template <class S>
 __device__ __forceinline__ void mx_factors(const GridGeom &g, const double *__restrict__ rec, MxSmem &sm, int cnt,
                                            const int tc[3], double iws)
 {
@@ -331,34 +346,50 @@ __device__ __forceinline__ void mx_factors(const GridGeom &g, const double *__re
     sm.brec[jb][f] = jb < cnt ? rec[(int64_t)sm.list[jb] * 12 + f] : (f < 3 ? -1.0e300 : 0.0);
   }
   __syncthreads();
-  for (int e = tid; e < NB * 3 * T; e += 256) {
-    const int jb = e / (3 * T), d = (e / T) % 3, ii = e % T;
-    const double x = axis_coord(g, d, T * tc[d] + ii);
-    const double u = x - sm.brec[jb][d];
-    // balance a small |W| between the two operands by an exact power of two
-    // (Ex scaled by 2^kb, V by 2^-kb, |W| / wmax ~ 2^(2 kb)), so that neither
-    // leaves the normal range of a 16-bit type sooner than it must
-    double wm = 0.0;
+  const int jb = tid >> 4, ii = tid & 15;  // NB * T == 256
+  const double *br = sm.brec[jb];
+  // balance a small |W| between the two operands by an exact power of two
+  // (Ex scaled by 2^kb, V by 2^-kb, |W| / wmax ~ 2^(2 kb)), so that neither
+  // leaves the normal range of a 16-bit type sooner than it must
+  double wm = 0.0;
 #pragma unroll
-    for (int f = 6; f < 12; ++f) wm = fmax(wm, fabs(sm.brec[jb][f]));
-    wm *= iws;
-    const int kb = wm > 0.0 ? ilogb(wm) / 2 : 0;
-    float2 E = make_float2(0.0f, 0.0f);
+  for (int f = 6; f < 12; ++f) wm = fmax(wm, fabs(br[f]));
+  wm *= iws;
+  const int kb = wm > 0.0 ? ilogb(wm) / 2 : 0;
+  float2 E[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double u = axis_coord(g, d, T * tc[d] + ii) - br[d];
+    E[d] = make_float2(0.0f, 0.0f);
     if (fabs(u) <= g.R) {
-      const double rev = sm.brec[jb][3 + d] * u * INV_2PI;
+      const double rev = br[3 + d] * u * (1.0 / 256.0);
       const float r = (float)(rev - rint(rev));
       const float amp = __builtin_amdgcn_exp2f((float)(-(u * u * hieps) * LOG2E));
-      E = make_float2(amp * __builtin_amdgcn_cosf(r), amp * __builtin_amdgcn_sinf(r));
+      E[d] = make_float2(amp * __builtin_amdgcn_cosf(r), amp * __builtin_amdgcn_sinf(r));
     }
-    if (d == 0) sm.Ex[jb][ii] = make_float2(ldexpf(E.x, kb), ldexpf(E.y, kb));
-    else if (d == 1) sm.Ey[jb][ii] = E;
-    else
+  }
+  sm.Ex[jb][ii] = make_float2(ldexpf(E[0].x, kb), ldexpf(E[0].y, kb));
+  sm.Ey[jb][ii] = E[1];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float wr = (float)ldexp(sm.brec[jb][6 + 2 * c] * iws, -kb);
-        const float wi = (float)ldexp(sm.brec[jb][7 + 2 * c] * iws, -kb);
-        sm.V[jb][c][ii] = make_float2(wr * E.x - wi * E.y, wr * E.y + wi * E.x);
-      }
+  for (int c = 0; c < 3; ++c) {
+    const float wr = (float)ldexp(br[6 + 2 * c] * iws, -kb);
+    const float wi = (float)ldexp(br[7 + 2 * c] * iws, -kb);
+    const float vx = wr * E[2].x - wi * E[2].y, vy = wr * E[2].y + wi * E[2].x;
+    if constexpr (std::is_same<S, float>::value) {
+      sm.V[jb][c][ii] = make_float2(vx, vy);
+    } else {
+      const S xh = (S)vx, yh = (S)vy;
+      const S xl = (S)(vx - (float)xh), yl = (S)(vy - (float)yh);
+      const int q = jb >> 2, t = 2 * (jb & 3);
+      sm.Bh[c][ii][q].v[t] = half_bits(xh);
+      sm.Bh[c][ii][q].v[t + 1] = half_bits((S)(-yh));
+      sm.Bl[c][ii][q].v[t] = half_bits(xl);
+      sm.Bl[c][ii][q].v[t + 1] = half_bits((S)(-yl));
+      sm.Bh[c + 3][ii][q].v[t] = half_bits(yh);
+      sm.Bh[c + 3][ii][q].v[t + 1] = half_bits(xh);
+      sm.Bl[c + 3][ii][q].v[t] = half_bits(yl);
+      sm.Bl[c + 3][ii][q].v[t + 1] = half_bits(xl);
+    }
   }
   __syncthreads();
 }
@@ -375,19 +406,21 @@ template <int PREC> struct PolicyMx {
 #pragma unroll
       for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   }
-  template <class V8, class S> static __device__ void split(const float (&x)[8], V8 &hi, V8 &lo)
+  template <class V8, class H> static __device__ void split(const float (&x)[8], V8 &hi, V8 &lo)
   {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const S h = (S)x[i];
+      const H h = (H)x[i];
       hi[i] = h;
-      lo[i] = (S)(x[i] - (float)h);
+      lo[i] = (H)(x[i] - (float)h);
     }
   }
+  typedef typename std::conditional<PREC == FGA_BF16X3, __bf16,
+                                    typename std::conditional<PREC == FGA_FP16X3, _Float16, float>::type>::type S;
   static __device__ void batch(const GridGeom &g, const double *rec, Smem &sm, int cnt, const int tc[3], Acc &acc,
                                double iws, int)
   {
-    mx_factors(g, rec, sm, cnt, tc, iws);
+    mx_factors<S>(g, rec, sm, cnt, tc, iws);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, kq = lane >> 4;
     if constexpr (PREC == FGA_FP32) {
@@ -421,7 +454,6 @@ template <int PREC> struct PolicyMx {
       // holds A[i = li][k = 8 kq + t] and B[k = 8 kq + t][l = li], t < 8,
       // k = 2 beam + part
       typedef typename std::conditional<PREC == FGA_BF16X3, bf8, h8>::type V8;
-      typedef typename std::conditional<PREC == FGA_BF16X3, __bf16, _Float16>::type S;
       V8 ahi[4], alo[4];
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
@@ -437,16 +469,8 @@ template <int PREC> struct PolicyMx {
       }
 #pragma unroll
       for (int cb = 0; cb < 6; ++cb) {
-        const int c = cb % 3;
-        float x[8];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const float2 v = sm.V[4 * kq + t][c][li];
-          x[2 * t] = cb < 3 ? v.x : v.y;       // part 0 (Re X rows)
-          x[2 * t + 1] = cb < 3 ? -v.y : v.x;  // part 1 (Im X rows)
-        }
-        V8 bhi, blo;
-        split<V8, S>(x, bhi, blo);
+        const V8 bhi = __builtin_bit_cast(V8, sm.Bh[cb][li][kq]);
+        const V8 blo = __builtin_bit_cast(V8, sm.Bl[cb][li][kq]);
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
           if constexpr (PREC == FGA_BF16X3) {
