@@ -314,18 +314,22 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 constexpr double INV_2PI = 0.15915494309189535;
 constexpr double LOG2E = 1.4426950408889634;
 
-// 16-bit operands of one column block: per (column block, l, lane quarter)
-// the 8 consecutive K entries a lane feeds to the matrix core (16 bytes)
+// 16-bit operands of one column block: per (column block, lane quarter, l)
+// the 8 consecutive K entries a lane feeds to the matrix core (16 bytes);
+// the 16 lanes of a quarter read 16 consecutive entries (no bank conflicts)
 struct alignas(16) H8Raw {
-  uint16_t v[8];
+  uint32_t v[4];  // pairs of 16-bit values (K order: low half first)
 };
 
 struct MxSmem : ListSmem {
   float2 Ex[NB][T], Ey[NB][T], V[NB][3][T];
-  H8Raw Bh[6][T][4], Bl[6][T][4];
+  H8Raw Bh[6][4][T], Bl[6][4][T];
 };
 
-template <class S> __device__ __forceinline__ uint16_t half_bits(S x) { return __builtin_bit_cast(uint16_t, x); }
+template <class S> __device__ __forceinline__ uint32_t half_pair(S lo16, S hi16)
+{
+  return (uint32_t)__builtin_bit_cast(uint16_t, lo16) | ((uint32_t)__builtin_bit_cast(uint16_t, hi16) << 16);
+}
 
 // Window-masked 1-D factors in FP32 from FP64 arguments: the Gaussian
 // exponent and the phase (in revolutions, reduced to [-1/2, 1/2]) are formed
@@ -380,15 +384,11 @@ __device__ __forceinline__ void mx_factors(const GridGeom &g, const double *__re
     } else {
       const S xh = (S)vx, yh = (S)vy;
       const S xl = (S)(vx - (float)xh), yl = (S)(vy - (float)yh);
-      const int q = jb >> 2, t = 2 * (jb & 3);
-      sm.Bh[c][ii][q].v[t] = half_bits(xh);
-      sm.Bh[c][ii][q].v[t + 1] = half_bits((S)(-yh));
-      sm.Bl[c][ii][q].v[t] = half_bits(xl);
-      sm.Bl[c][ii][q].v[t + 1] = half_bits((S)(-yl));
-      sm.Bh[c + 3][ii][q].v[t] = half_bits(yh);
-      sm.Bh[c + 3][ii][q].v[t + 1] = half_bits(xh);
-      sm.Bl[c + 3][ii][q].v[t] = half_bits(yl);
-      sm.Bl[c + 3][ii][q].v[t + 1] = half_bits(xl);
+      const int q = jb >> 2, t = jb & 3;  // K entries 2t, 2t + 1 of the lane's eight
+      sm.Bh[c][q][ii].v[t] = half_pair(xh, (S)(-yh));
+      sm.Bl[c][q][ii].v[t] = half_pair(xl, (S)(-yl));
+      sm.Bh[c + 3][q][ii].v[t] = half_pair(yh, xh);
+      sm.Bl[c + 3][q][ii].v[t] = half_pair(yl, xl);
     }
   }
   __syncthreads();
@@ -469,8 +469,8 @@ template <int PREC> struct PolicyMx {
       }
 #pragma unroll
       for (int cb = 0; cb < 6; ++cb) {
-        const V8 bhi = __builtin_bit_cast(V8, sm.Bh[cb][li][kq]);
-        const V8 blo = __builtin_bit_cast(V8, sm.Bl[cb][li][kq]);
+        const V8 bhi = __builtin_bit_cast(V8, sm.Bh[cb][kq][li]);
+        const V8 blo = __builtin_bit_cast(V8, sm.Bl[cb][kq][li]);
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
           if constexpr (PREC == FGA_BF16X3) {
