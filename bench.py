@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered", "mixed"])
     ap.add_argument("--waves", type=int, default=4, help="beam waves of the mixed-precision workload")
+    ap.add_argument("--batch", type=int, default=0, help="beams per receiver-sum batch in the evolution (0: library default)")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -112,7 +113,7 @@ def gpu_run(w, args):
         if state["ws_ev"] is None:
             state["ws_ev"] = fga._workspace(fga.workspace_bytes(
                 "evolve", beams=beams, nsteps=seg, n_receivers=0 if rec is None else rec.shape[0],
-                eps=w.eps, tau=w.tau))
+                eps=w.eps, tau=w.tau, batch=args.batch))
             if rec is not None:
                 state["seis"] = torch.empty((rec.shape[0], w.nsteps, 3, 2), dtype=torch.float64, device=dev)
         # the evolution in a few calls of `seg` steps (progress lines between)
@@ -120,7 +121,7 @@ def gpu_run(w, args):
         for s0 in range(0, w.nsteps, seg):
             n = min(seg, w.nsteps - s0)
             part, st_k = fga.fga_evolve(med, beams, w.dt, n, receivers=rec, eps=w.eps, tau=w.tau,
-                                        ws=state["ws_ev"])
+                                        ws=state["ws_ev"], batch=args.batch)
             if rec is not None:
                 state["seis"][:, s0:s0 + n].copy_(part)
             st["beam_steps"] += st_k["beam_steps"]
@@ -269,12 +270,13 @@ def layered(args):
         n0 = beams.count
         if state["ws"] is None:
             state["ws"] = fga._workspace(fga.workspace_bytes("evolve", beams=beams, nsteps=seg,
-                                                             n_receivers=rec.shape[0], eps=e["eps"], tau=e["tau"]))
+                                                             n_receivers=rec.shape[0], eps=e["eps"], tau=e["tau"],
+                                                             batch=args.batch))
         tot = {"beam_steps": 0, "evals": 0, "crossings": 0, "spawned": 0, "capped": 0}
         for s0 in range(0, e["nsteps"], seg):
             n = min(seg, e["nsteps"] - s0)
             part, st = fga.fga_evolve(med, beams, e["dt"], n, receivers=rec, eps=e["eps"], tau=e["tau"],
-                                      ws=state["ws"])
+                                      ws=state["ws"], batch=args.batch)
             state["seis"][:, s0:s0 + n].copy_(part)
             for k in tot:
                 tot[k] += st[k]

@@ -53,7 +53,7 @@ constexpr double LOG2E = 1.4426950408889634;
 // are formed in FP64, then exp2 / sin / cos run on the FP32 transcendental
 // unit; sums stay FP64.  Otherwise the FP64 table-driven exponential.
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, int64_t nblk)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_sum_points(PointsArgs a, int groups, int64_t nblk)
 {
   __shared__ TrigTables tab;
   fill_tables(tab);
@@ -98,16 +98,33 @@ __global__ __launch_bounds__(256) void k_sum_points(PointsArgs a, int groups, in
       }
   }
   const double *TB = a.tile_box + (int64_t)s * a.ntiles * 6;
-  auto live = [&](int64_t t0) {
-    const double *tb = TB + (t0 >> 6) * 6;  // lo[3], hi[3]
-    bool ok = true;
+  // The range's tiles are tested 64 at a time, one per lane (box loads in
+  // parallel), and walked through the ballot of the live ones; a tile whose
+  // box lies more than R from the points' box along an axis is skipped.
+  const int64_t tb0 = b0 >> 6, tb1 = (b1 + 63) >> 6;  // b0 is a multiple of 64
+  int64_t mbase = -1;
+  uint64_t mask = 0;
+  auto next_live = [&](int64_t t0) {  // first beam of the next live tile at or after t0, else b1
+    int64_t t = t0 >> 6;
+    while (t < tb1) {
+      const int64_t base = t & ~(int64_t)63;
+      if (base != mbase) {
+        const int64_t tt = base + lane;
+        bool ok = false;
+        if (tt >= tb0 && tt < tb1) {
+          const double *tb = TB + tt * 6;  // lo[3], hi[3]
+          ok = true;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) ok = ok && !(tb[d] - phi[d] > R) && !(plo[d] - tb[3 + d] > R);
-    return ok;
-  };
-  auto next_live = [&](int64_t t0) {
-    while (t0 < b1 && !live(t0)) t0 += 64;
-    return t0;
+          for (int d = 0; d < 3; ++d) ok = ok && !(tb[d] - phi[d] > R) && !(plo[d] - tb[3 + d] > R);
+        }
+        mask = __ballot(ok);
+        mbase = base;
+      }
+      const uint64_t rest = mask >> (t - base);
+      if (rest) return (t + __ffsll((long long)rest) - 1) << 6;
+      t = base + 64;
+    }
+    return b1;
   };
   // records of the lane's beam for the current tile
   double q[3], pe[3], B[6];
