@@ -35,7 +35,8 @@ FLOP_POINT_EVAL = 79      # FP64 flops per in-window receiver term (window test,
 FLOP_GRID_EVAL = 24       # 3 complex multiply-adds
 PEAK_FP64 = 78.6e12       # FP64 vector and FP64 matrix peak, MI355X
 # grid summation variants: (library code, dense MFMA peak of the operand type)
-GRID_PREC = {"fp64": (0, 78.6e12), "fp32": (1, 157.3e12), "bf16x3": (2, 2.5e15), "fp16x3": (3, 2.5e15)}
+GRID_PREC = {"fp64": (0, 78.6e12), "fp32": (1, 157.3e12), "bf16x3": (2, 2.5e15), "fp16x3": (3, 2.5e15),
+             "fp16x2": (4, 2.5e15)}
 HBM_PEAK = 8.0e12
 # HBM bytes per launch of a kernel on the default workload (smooth, scale 1), from rocprofv3
 # FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy calibration; valid only while the kernel's
@@ -447,7 +448,7 @@ def mixed(args):
     packet form, q 50^3 x p 8^3 x 3 branches in waves (q slabs along z);
     each wave is decomposed, evolved 250 FP64 RK4 steps to T = 0.25 and summed
     onto the 256^3 grid (tau = 16) by every variant (FP64, FP32, BF16 hi+lo,
-    FP16 hi+lo), each added into its own output.  Reports per variant the
+    FP16 hi+lo, FP16 rows x hi+lo factors), each added into its own output.  Reports per variant the
     tile-kernel time, algorithmic evals/s and its fraction of the operand
     type's dense MFMA peak, and the relative L2 error against the FP64 sum
     (itself at oracle parity).  --scale shrinks the q mesh per axis."""
@@ -464,7 +465,7 @@ def mixed(args):
     cap = max(q.count for q in slabs) * w.pmesh.count * 3
     beams = fga.BeamSet(cap)
     n = w.out_grid.n
-    variants = ["fp64", "fp32", "bf16x3", "fp16x3"]
+    variants = ["fp64", "fp32", "bf16x3", "fp16x3", "fp16x2"]
     outs = {v: torch.zeros((3, n[2], n[1], n[0], 2), dtype=torch.float64, device=dev) for v in variants}
     stats = {v: {"tile_ms": 0.0, "call_s": 0.0, "evals": 0} for v in variants}
     ws = {}
@@ -515,7 +516,7 @@ def mixed(args):
                   "evals_per_s": s_["evals"] / (s_["tile_ms"] * 1e-3),
                   "achieved_tflops_algorithmic": ach / 1e12, "peak_tflops": GRID_PREC[v][1] / 1e12,
                   "frac_algorithmic": ach / GRID_PREC[v][1],
-                  "mfma_flops_per_term": 72 if v.endswith("x3") else 24,
+                  "mfma_flops_per_term": {"x3": 72, "x2": 48}.get(v[-2:], 24),
                   "rel_l2_vs_fp64": float(torch.linalg.vector_norm(outs[v] - ref)) / nref}
     dom = max(variants, key=lambda v: stats[v]["tile_ms"])
     line = {
@@ -527,7 +528,7 @@ def mixed(args):
         "dtype": "f64+f32/bf16/f16", "data": "synthetic",
         "config": {"workload": "mixed-precision grid: config-2 medium and packet at eps=1/512, q %d^3 x p 8^3 x 3 "
                                "branches in %d waves, 250 FP64 RK4 steps to T=0.25, 256^3 grid (tau=16) summed by "
-                               "FP64, FP32, BF16 hi+lo and FP16 hi+lo tile GEMMs" % (nq, len(slabs)),
+                               "FP64, FP32, BF16 hi+lo, FP16 hi+lo and FP16 x (hi+lo) tile GEMMs" % (nq, len(slabs)),
                    "beams": tot["beams"], "waves": len(slabs), "parallelism": "single GPU"},
         "beam_point_evals_per_s": sum(stats[v]["evals"] for v in variants) / elapsed,
         "decompose_s": tot["decompose_s"], "evolve_s": tot["evolve_s"],

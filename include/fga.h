@@ -227,7 +227,7 @@ fga_status fga_decompose_point_source(const fga_medium *med, const fga_point_sou
 /* eq:amp_P, eq:amp_SV, eq:amp_SH; Sec. 2.3 fixed-step RK4)                  */
 /* ------------------------------------------------------------------------ */
 
-typedef enum { FGA_FP64 = 0, FGA_FP32 = 1, FGA_BF16X3 = 2, FGA_FP16X3 = 3 } fga_precision;
+typedef enum { FGA_FP64 = 0, FGA_FP32 = 1, FGA_BF16X3 = 2, FGA_FP16X3 = 3, FGA_FP16X2 = 4 } fga_precision;
 
 typedef struct {
   int64_t n;               /* receivers                                                */
@@ -323,6 +323,7 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
  * Khatri-Rao x factor product on the matrix cores.  out: device complex
  * [3][n2][n1][n0] (overwritten).  precision: FGA_FP64 (FP64 matrix cores),
  * FGA_FP32, FGA_BF16X3 or FGA_FP16X3 (split hi+lo factors, FP32 accumulation;
+ * FGA_FP16X2: the Khatri-Rao rows in single FP16, the other factor split hi+lo;
  * phases reduced modulo 2 pi in FP64 before the cast).  evals (host, may be
  * NULL): algorithmic in-window (beam, point) terms. */
 size_t fga_reconstruct_grid_workspace_bytes(const fga_beams *beams, const int n[3], double eps,

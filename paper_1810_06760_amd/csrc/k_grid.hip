@@ -15,7 +15,8 @@
 // accumulation on v_mfma_f32_16x16x4_f32 (FGA_FP32), or with each operand
 // split into hi + lo halves, hi = round(x), lo = round(x - hi), and the three
 // products hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_{bf16,f16}
-// (FGA_BF16X3, FGA_FP16X3).
+// (FGA_BF16X3, FGA_FP16X3); FGA_FP16X2 rounds the Khatri-Rao rows to FP16
+// once (2^-11 relative) and splits only the factor block, two products.
 //
 // Beams are binned by the tile-sized cell of Q (radix sort of cell keys); a
 // tile's candidates are the (2r+1)^2 contiguous runs of cells within reach of
@@ -416,7 +417,7 @@ template <int PREC> struct PolicyMx {
     }
   }
   typedef typename std::conditional<PREC == FGA_BF16X3, __bf16,
-                                    typename std::conditional<PREC == FGA_FP16X3, _Float16, float>::type>::type S;
+                                    typename std::conditional<PREC == FGA_FP32, float, _Float16>::type>::type S;
   static __device__ void batch(const GridGeom &g, const double *rec, Smem &sm, int cnt, const int tc[3], Acc &acc,
                                double iws, int)
   {
@@ -465,7 +466,12 @@ template <int PREC> struct PolicyMx {
           x[2 * t] = xv.x * yv.x - xv.y * yv.y;
           x[2 * t + 1] = xv.x * yv.y + xv.y * yv.x;
         }
-        split<V8, S>(x, ahi[rb], alo[rb]);
+        if constexpr (PREC == FGA_FP16X2) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) ahi[rb][i] = (S)x[i];
+        } else {
+          split<V8, S>(x, ahi[rb], alo[rb]);
+        }
       }
 #pragma unroll
       for (int cb = 0; cb < 6; ++cb) {
@@ -477,6 +483,9 @@ template <int PREC> struct PolicyMx {
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
+          } else if constexpr (PREC == FGA_FP16X2) {
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
           } else {
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
@@ -649,7 +658,8 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
                          const double h[3], int precision, double *out, Arena &ar, hipStream_t st, bool size_only,
                          size_t *need, int64_t *evals_out, bool add)
 {
-  if (precision != FGA_FP64 && precision != FGA_FP32 && precision != FGA_BF16X3 && precision != FGA_FP16X3)
+  if (precision != FGA_FP64 && precision != FGA_FP32 && precision != FGA_BF16X3 && precision != FGA_FP16X3 &&
+      precision != FGA_FP16X2)
     return fail(FGA_EINVAL, "unknown grid summation precision %d", precision);
   const GridGeom g = make_geom(n, lo, h, eps, tau);
   if ((2 * g.reach[1] + 1) * (2 * g.reach[2] + 1) > MAXR)
@@ -740,8 +750,12 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
         hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_BF16X3>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
                            ev + 2);
         break;
-      default:
+      case FGA_FP16X3:
         hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_FP16X3>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
+                           ev + 2);
+        break;
+      default:
+        hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_FP16X2>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
                            ev + 2);
         break;
     }
