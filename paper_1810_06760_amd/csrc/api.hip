@@ -323,6 +323,10 @@ struct EvolveBufs {
   double *emit = nullptr, *partial = nullptr, *xs = nullptr, *box = nullptr;
   int32_t *perm = nullptr;
   int64_t *blk_extra = nullptr, *blk_off = nullptr, *total = nullptr;  // interface step
+  int32_t *cross_list = nullptr, *cross_sorted = nullptr;
+  unsigned long long *cross_count = nullptr;
+  void *cross_tmp = nullptr;
+  size_t cross_tmp_bytes = 0;
 };
 
 EvolveBufs evolve_layout(const EvolvePlan &p, const fga_receivers *r, int64_t cap, Arena &ar)
@@ -333,6 +337,11 @@ EvolveBufs evolve_layout(const EvolvePlan &p, const fga_receivers *r, int64_t ca
   b.blk_extra = ar.take<int64_t>(nblk_all);
   b.blk_off = ar.take<int64_t>(nblk_all);
   b.total = ar.take<int64_t>(1);
+  b.cross_list = ar.take<int32_t>(cap + 1);
+  b.cross_sorted = ar.take<int32_t>(cap + 1);
+  b.cross_count = ar.take<unsigned long long>(1);
+  b.cross_tmp_bytes = cross_sort_bytes(cap);
+  b.cross_tmp = ar.take<char>(b.cross_tmp_bytes);
   if (r) {
     const int m = (p.chunk + r->stride - 1) / r->stride + 1;
     b.emit = ar.take<double>((size_t)m * 12 * p.batch);
@@ -398,7 +407,8 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
   const EvolveBufs wb = evolve_layout(p, rec, beams->capacity, ar);
   unsigned long long *ctr = wb.ctr;
   double *emit = wb.emit, *partial = wb.partial;
-  if (!ctr || !wb.blk_extra || !wb.blk_off || !wb.total ||
+  if (!ctr || !wb.blk_extra || !wb.blk_off || !wb.total || !wb.cross_list || !wb.cross_sorted ||
+      !wb.cross_count || !wb.cross_tmp ||
       (rec && (!emit || !partial || !wb.box || !wb.xs || !wb.perm)))
     return fail(FGA_ENOMEM, "evolve workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
   const size_t sort_base = ar.used;
@@ -445,9 +455,16 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
       ia.blk_extra = wb.blk_extra;
       ia.blk_off = wb.blk_off;
       ia.counters = ctr + 4;
-      if (n > 0) {
+      // the crossing beams, in slot order (children slots as if every beam
+      // were visited in order)
+      int64_t ncross = 0;
+      FGA_HIP(collect_crossers(beams->i32 + FGA_FLAGS * beams->capacity, n, wb.cross_list, wb.cross_sorted,
+                               wb.cross_count, wb.cross_tmp, wb.cross_tmp_bytes, st, &ncross));
+      ia.list = wb.cross_sorted;
+      ia.nlist = ncross;
+      if (ncross > 0) {
         FGA_HIP(launch_interface(dm, ia, 0, st));
-        FGA_HIP(launch_scan(wb.blk_extra, wb.blk_off, (n + 255) / 256, wb.total, st));
+        FGA_HIP(launch_scan(wb.blk_extra, wb.blk_off, (ncross + 255) / 256, wb.total, st));
         int64_t extra = 0;
         FGA_HIP(hipMemcpyAsync(&extra, wb.total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         FGA_HIP(hipStreamSynchronize(st));

@@ -152,17 +152,26 @@ struct InterfaceArgs {
   int64_t *lineage;
   int64_t cap;
   int64_t n;                 // beams in the set before the step
+  const int32_t *list;       // [nlist] the crossing beams' slots, increasing
+  int64_t nlist;
   double dt;
   int gen_max;
   double child_cut;
-  int64_t *blk_extra;        // [ceil(n / 256)] extra slots per workgroup (pass 1 output)
-  int64_t *blk_off;          // [ceil(n / 256)] exclusive scan of blk_extra (pass 2 input)
+  int64_t *blk_extra;        // [ceil(nlist / 256)] extra slots per workgroup (pass 1 output)
+  int64_t *blk_off;          // [ceil(nlist / 256)] exclusive scan of blk_extra (pass 2 input)
   unsigned long long *counters;  // [0] crossings, [1] children, [2] retired at the generation cap
 };
 // pass 1 (write = 0): per-workgroup counts of extra slots; pass 2 (write = 1):
 // children written (first child in the parent's slot, the others appended at
 // n + blk_off + rank)
 hipError_t launch_interface(const DevMedium &m, const InterfaceArgs &a, int write, hipStream_t st);
+// The slots of [0, n) flagged FGA_FLAG_CROSS, in increasing order, into
+// sorted[0, *ncross) (list: unordered scratch of the same size; count: one
+// device counter; tmp: cross_sort_bytes(cap) bytes).  Synchronises st.
+size_t cross_sort_bytes(int64_t cap);
+hipError_t collect_crossers(const int32_t *flags, int64_t n, int32_t *list, int32_t *sorted,
+                            unsigned long long *count, void *tmp, size_t tmp_bytes, hipStream_t st,
+                            int64_t *ncross);
 
 // exclusive scan of n int64 values (one workgroup); total = sum
 hipError_t launch_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st);

@@ -27,6 +27,8 @@
 // own layer.  The first child reuses the parent's slot; the others go after
 // the current count, at offsets from a two-pass count / exclusive scan over
 // workgroups, so slot assignment is deterministic.
+#include <hipcub/hipcub.hpp>
+
 #include "rk4.h"
 
 namespace fga {
@@ -354,8 +356,9 @@ __device__ int block_exscan(int v, int *tot)
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_interface(DevMedium m, InterfaceArgs a)
 {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool mine = i < a.n && (a.i32[FGA_FLAGS * a.cap + i] & FGA_FLAG_CROSS);
+  const int64_t li = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = li < a.nlist ? a.list[li] : 0;
+  const bool mine = li < a.nlist && (a.i32[FGA_FLAGS * a.cap + i] & FGA_FLAG_CROSS);
   if (!__syncthreads_or(mine)) {
     if (!WRITE && threadIdx.x == 0) a.blk_extra[blockIdx.x] = 0;
     return;
@@ -449,12 +452,59 @@ __global__ __launch_bounds__(256) void k_interface(DevMedium m, InterfaceArgs a)
   }
 }
 
+
+// Crossing beams of [0, n): one atomic per wavefront reserves its run of the
+// (unordered) list; the list is then sorted, so the children's slots do not
+// depend on the order in which wavefronts ran.
+__global__ __launch_bounds__(256) void k_collect_cross(const int32_t *__restrict__ flags, int64_t n,
+                                                       int32_t *__restrict__ list, unsigned long long *__restrict__ count)
+{
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool c = i < n && (flags[i] & FGA_FLAG_CROSS);
+  const unsigned long long b = __ballot(c);
+  if (b == 0) return;
+  const int lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(b));
+  base = __shfl(base, 0);
+  if (c) list[base + __popcll(b & ((1ull << lane) - 1))] = (int32_t)i;
+}
+
 }  // namespace
+
+size_t cross_sort_bytes(int64_t cap)
+{
+  size_t bytes = 0;
+  hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                    (int)(cap > 0 ? cap : 1), 0, 32);
+  return bytes;
+}
+
+hipError_t collect_crossers(const int32_t *flags, int64_t n, int32_t *list, int32_t *sorted,
+                            unsigned long long *count, void *tmp, size_t tmp_bytes, hipStream_t st,
+                            int64_t *ncross)
+{
+  *ncross = 0;
+  if (n <= 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(count, 0, sizeof(unsigned long long), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_collect_cross, (unsigned)((n + 255) / 256), 256, 0, st, flags, n, list, count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  unsigned long long h = 0;
+  if ((e = hipMemcpyAsync(&h, count, sizeof h, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if (h == 0) return hipSuccess;
+  if ((e = hipcub::DeviceRadixSort::SortKeys(tmp, tmp_bytes, list, sorted, (int)h, 0, 32, st)) != hipSuccess)
+    return e;
+  *ncross = (int64_t)h;
+  return hipSuccess;
+}
+
 
 hipError_t launch_interface(const DevMedium &m, const InterfaceArgs &a, int write, hipStream_t st)
 {
-  if (a.n <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((a.n + 255) / 256);
+  if (a.nlist <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((a.nlist + 255) / 256);
   if (write) hipLaunchKernelGGL(k_interface<true>, blocks, 256, 0, st, m, a);
   else hipLaunchKernelGGL(k_interface<false>, blocks, 256, 0, st, m, a);
   return hipGetLastError();
