@@ -17,11 +17,14 @@
 // products hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_{bf16,f16}
 // (FGA_BF16X3, FGA_FP16X3); FGA_FP16X2 rounds the Khatri-Rao rows to FP16
 // once (2^-11 relative) and splits only the factor block, two products.
+// The mixed tiles are software-pipelined: one batch of beams on the matrix
+// cores while the next one's factors are built, one barrier per batch.
 //
 // Beams are binned by the tile-sized cell of Q (radix sort of cell keys); a
 // tile's candidates are the (2r+1)^2 contiguous runs of cells within reach of
 // it.  Each tile's candidate list is split into segments, one workgroup per
 // segment, whose partial tiles are then reduced in a fixed order.
+#include <algorithm>
 #include <hipcub/hipcub.hpp>
 #include <type_traits>
 
@@ -36,6 +39,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int T = 16;       // tile edge (points)
 constexpr int NB = 16;      // beams per LDS batch
 constexpr int MAXR = 1024;  // max candidate runs per tile: (2 reach + 1)^2
+constexpr int NSEG = 4096;  // work items per launch beyond one per tile (at most 8 per tile)
 
 struct GridGeom {
   int n[3], nt[3], nc[3], reach[3];
@@ -312,8 +316,51 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
-constexpr double INV_2PI = 0.15915494309189535;
 constexpr double LOG2E = 1.4426950408889634;
+constexpr int LCAP = 1024;  // ring of accepted candidates (power of two)
+
+// Mixed record, written over the FP64 record of the same beam once the
+// largest |W| is known: Q and the phase rate in FP64, the weights in FP32
+// scaled by 1 / max |W| and balanced against the x factor by an exact power
+// of two (Ex scaled by 2^kb, W by 2^-kb, |W| / wmax ~ 2^(2 kb)), so that
+// neither operand leaves the normal range of a 16-bit type sooner than it
+// must.
+struct alignas(16) MxRec {
+  double q[3];
+  double rev[3];  // P / (2 pi eps): the phase in revolutions per unit length
+  float w[6];     // (re, im) of W_c / wmax * 2^-kb, c = 0..2
+  float xs;       // 2^kb
+  float pad;
+};
+static_assert(sizeof(MxRec) <= 12 * sizeof(double), "the mixed record fits in the FP64 record's stride");
+
+__global__ __launch_bounds__(256) void k_mx_records(double *__restrict__ rec, const int32_t *__restrict__ keys,
+                                                    int64_t n, const unsigned long long *__restrict__ wmax)
+{
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n || keys[s] == 0x7fffffff) return;
+  const double ws = __longlong_as_double((long long)*wmax);
+  const double iws = ws > 0.0 ? 1.0 / ws : 0.0;
+  double *o = rec + s * 12;
+  double W[6], wm = 0.0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    W[f] = o[6 + f] * iws;
+    wm = fmax(wm, fabs(W[f]));
+  }
+  const int kb = wm > 0.0 ? ilogb(wm) / 2 : 0;
+  MxRec r;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    r.q[d] = o[d];
+    r.rev[d] = o[3 + d] * (1.0 / 256.0);  // from units of pi/128 to revolutions
+  }
+#pragma unroll
+  for (int f = 0; f < 6; ++f) r.w[f] = (float)ldexp(W[f], -kb);
+  r.xs = ldexpf(1.0f, kb);
+  r.pad = 0.0f;
+  *reinterpret_cast<MxRec *>(o) = r;  // every field above depends on the loads
+}
 
 // 16-bit operands of one column block: per (column block, lane quarter, l)
 // the 8 consecutive K entries a lane feeds to the matrix core (16 bytes);
@@ -322,9 +369,21 @@ struct alignas(16) H8Raw {
   uint32_t v[4];  // pairs of 16-bit values (K order: low half first)
 };
 
-struct MxSmem : ListSmem {
-  float2 Ex[NB][T], Ey[NB][T], V[NB][3][T];
+// Factors of one batch of NB beams: Ex, Ey (FP32) and the factor block
+// V = W Ez, as FP32 (FGA_FP32) or split into 16-bit hi and lo in the matrix
+// instruction's K order.
+template <int PREC> struct MxBuf {
+  float2 Ex[NB][T], Ey[NB][T];
   H8Raw Bh[6][4][T], Bl[6][4][T];
+};
+template <> struct MxBuf<FGA_FP32> {
+  float2 Ex[NB][T], Ey[NB][T], V[NB][3][T];
+};
+
+template <int PREC> struct MxSmem {
+  int64_t run_b[MAXR], run_pre[MAXR + 1];
+  int32_t ring[LCAP];
+  MxBuf<PREC> fb[2];
 };
 
 template <class S> __device__ __forceinline__ uint32_t half_pair(S lo16, S hi16)
@@ -332,193 +391,284 @@ template <class S> __device__ __forceinline__ uint32_t half_pair(S lo16, S hi16)
   return (uint32_t)__builtin_bit_cast(uint16_t, lo16) | ((uint32_t)__builtin_bit_cast(uint16_t, hi16) << 16);
 }
 
-// Window-masked 1-D factors in FP32 from FP64 arguments: the Gaussian
-// exponent and the phase (in revolutions, reduced to [-1/2, 1/2]) are formed
-// in FP64; exp2 and sin/cos of 2 pi r run on the FP32 transcendental unit.
-// V = (W / wmax) Ez.  One thread per (beam, tile index): all three axes, so
-// no wavefront diverges.  For the 16-bit products (S = __bf16 / _Float16)
-// the B operand's hi and lo halves are written once per batch, in the K
-// order of the matrix instruction: k = 2 beam + part, with column block c
-// (Re U) taking (Re V, -Im V) and c + 3 (Im U) taking (Im V, Re V).
-template <class S>
-__device__ __forceinline__ void mx_factors(const GridGeom &g, const double *__restrict__ rec, MxSmem &sm, int cnt,
-                                           const int tc[3], double iws)
+// One thread's copy of the mixed record of beam jb of a batch (every thread
+// of the beam's 16 reads it; the loads of one wavefront touch 4 records).
+struct MxRegs {
+  double2 a, b, c;  // (q0, q1), (q2, rev0), (rev1, rev2)
+  float4 d, e;      // (w0, w1, w2, w3), (w4, w5, xs, pad)
+};
+
+__device__ __forceinline__ void mx_fetch(const double *__restrict__ rec, const int32_t *ring, int64_t p, int jb,
+                                         int cnt, MxRegs &r)
 {
-  const int tid = threadIdx.x;
-  const double hieps = 0.5 / g.eps;
-  for (int e = tid; e < NB * 12; e += 256) {
-    const int jb = e / 12, f = e % 12;
-    sm.brec[jb][f] = jb < cnt ? rec[(int64_t)sm.list[jb] * 12 + f] : (f < 3 ? -1.0e300 : 0.0);
+  if (jb < cnt) {
+    const double2 *src = reinterpret_cast<const double2 *>(rec + (int64_t)ring[(p + jb) & (LCAP - 1)] * 12);
+    r.a = src[0];
+    r.b = src[1];
+    r.c = src[2];
+    const float4 *fs = reinterpret_cast<const float4 *>(src + 3);
+    r.d = fs[0];
+    r.e = fs[1];
+  } else {  // idle slot: outside every window, zero weight
+    r.a = make_double2(-1.0e300, -1.0e300);
+    r.b = make_double2(-1.0e300, 0.0);
+    r.c = make_double2(0.0, 0.0);
+    r.d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    r.e = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
   }
-  __syncthreads();
-  const int jb = tid >> 4, ii = tid & 15;  // NB * T == 256
-  const double *br = sm.brec[jb];
-  // balance a small |W| between the two operands by an exact power of two
-  // (Ex scaled by 2^kb, V by 2^-kb, |W| / wmax ~ 2^(2 kb)), so that neither
-  // leaves the normal range of a 16-bit type sooner than it must
-  double wm = 0.0;
-#pragma unroll
-  for (int f = 6; f < 12; ++f) wm = fmax(wm, fabs(br[f]));
-  wm *= iws;
-  const int kb = wm > 0.0 ? ilogb(wm) / 2 : 0;
+}
+
+// Window-masked 1-D factors in FP32 from FP64 arguments, thread (jb, ii):
+// the Gaussian exponent and the phase (in revolutions, reduced to
+// [-1/2, 1/2]) are formed in FP64; exp2 and sin/cos of 2 pi r run on the
+// FP32 transcendental unit.  For the 16-bit products (S = __bf16 / _Float16)
+// the B operand's hi and lo halves are written in the K order of the matrix
+// instruction: k = 2 beam + part, with column block c (Re U) taking
+// (Re V, -Im V) and c + 3 (Im U) taking (Im V, Re V).
+template <int PREC>
+__device__ __forceinline__ void mx_make(const GridGeom &g, const double (&xq)[3], double hl2, const MxRegs &r,
+                                        MxBuf<PREC> &fb, int jb, int ii)
+{
+  typedef typename std::conditional<PREC == FGA_BF16X3, __bf16, _Float16>::type S;
+  const double q[3] = {r.a.x, r.a.y, r.b.x};
+  const double rv[3] = {r.b.y, r.c.x, r.c.y};
   float2 E[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const double u = axis_coord(g, d, T * tc[d] + ii) - br[d];
-    E[d] = make_float2(0.0f, 0.0f);
-    if (fabs(u) <= g.R) {
-      const double rev = br[3 + d] * u * (1.0 / 256.0);
-      const float r = (float)(rev - rint(rev));
-      const float amp = __builtin_amdgcn_exp2f((float)(-(u * u * hieps) * LOG2E));
-      E[d] = make_float2(amp * __builtin_amdgcn_cosf(r), amp * __builtin_amdgcn_sinf(r));
-    }
+    // outside the window the offset is replaced by one whose Gaussian is
+    // exactly 0 in FP32 (and whose phase is 0), so nothing branches
+    const double u0 = xq[d] - q[d];
+    const double u = fabs(u0) <= g.R ? u0 : 1.0e30;
+    const double rev = rv[d] * u;
+    const float rf = (float)(rev - rint(rev));
+    const float amp = __builtin_amdgcn_exp2f((float)(u * u * hl2));
+    E[d] = make_float2(amp * __builtin_amdgcn_cosf(rf), amp * __builtin_amdgcn_sinf(rf));
   }
-  sm.Ex[jb][ii] = make_float2(ldexpf(E[0].x, kb), ldexpf(E[0].y, kb));
-  sm.Ey[jb][ii] = E[1];
+  const float xs = r.e.z;
+  fb.Ex[jb][ii] = make_float2(E[0].x * xs, E[0].y * xs);
+  fb.Ey[jb][ii] = E[1];
+  const float w[6] = {r.d.x, r.d.y, r.d.z, r.d.w, r.e.x, r.e.y};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const float wr = (float)ldexp(br[6 + 2 * c] * iws, -kb);
-    const float wi = (float)ldexp(br[7 + 2 * c] * iws, -kb);
+    const float wr = w[2 * c], wi = w[2 * c + 1];
     const float vx = wr * E[2].x - wi * E[2].y, vy = wr * E[2].y + wi * E[2].x;
-    if constexpr (std::is_same<S, float>::value) {
-      sm.V[jb][c][ii] = make_float2(vx, vy);
+    if constexpr (PREC == FGA_FP32) {
+      fb.V[jb][c][ii] = make_float2(vx, vy);
     } else {
       const S xh = (S)vx, yh = (S)vy;
       const S xl = (S)(vx - (float)xh), yl = (S)(vy - (float)yh);
-      const int q = jb >> 2, t = jb & 3;  // K entries 2t, 2t + 1 of the lane's eight
-      sm.Bh[c][q][ii].v[t] = half_pair(xh, (S)(-yh));
-      sm.Bl[c][q][ii].v[t] = half_pair(xl, (S)(-yl));
-      sm.Bh[c + 3][q][ii].v[t] = half_pair(yh, xh);
-      sm.Bl[c + 3][q][ii].v[t] = half_pair(yl, xl);
+      const int q4 = jb >> 2, t = jb & 3;  // K entries 2t, 2t + 1 of the lane's eight
+      fb.Bh[c][q4][ii].v[t] = half_pair(xh, (S)(-yh));
+      fb.Bl[c][q4][ii].v[t] = half_pair(xl, (S)(-yl));
+      fb.Bh[c + 3][q4][ii].v[t] = half_pair(yh, xh);
+      fb.Bl[c + 3][q4][ii].v[t] = half_pair(yl, xl);
     }
   }
-  __syncthreads();
 }
 
-template <int PREC> struct PolicyMx {
-  static constexpr int SPLIT = 1;
-  typedef MxSmem Smem;
-  typedef f4 Acc[4][6];
-  static __device__ void init(Smem &) {}
-  static __device__ void zero(Acc &acc)
-  {
+// The K = 2 NB (re, im) slice of the tile GEMM for one batch; wavefront w
+// owns tile rows j = 4 w + rb.
+template <int PREC>
+__device__ __forceinline__ void mx_mma(const MxBuf<PREC> &fb, f4 (&acc)[4][6], int w, int lane)
+{
+  const int li = lane & 15, kq = lane >> 4;
+  if constexpr (PREC == FGA_FP32) {
+    // K = 4 per instruction: 2 beams x (re, im); lane holds A[i = li][k = kq], B[k = kq][l = li]
+    const int part = kq & 1;
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-  }
-  template <class V8, class H> static __device__ void split(const float (&x)[8], V8 &hi, V8 &lo)
-  {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const H h = (H)x[i];
-      hi[i] = h;
-      lo[i] = (H)(x[i] - (float)h);
-    }
-  }
-  typedef typename std::conditional<PREC == FGA_BF16X3, __bf16,
-                                    typename std::conditional<PREC == FGA_FP32, float, _Float16>::type>::type S;
-  static __device__ void batch(const GridGeom &g, const double *rec, Smem &sm, int cnt, const int tc[3], Acc &acc,
-                               double iws, int)
-  {
-    mx_factors<S>(g, rec, sm, cnt, tc, iws);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int li = lane & 15, kq = lane >> 4;
-    if constexpr (PREC == FGA_FP32) {
-      // K = 4 per instruction: 2 beams x (re, im); lane holds A[i = li][k = kq], B[k = kq][l = li]
-      const int part = kq & 1;
-      const int nks = (cnt + 1) / 2;
-      for (int ks = 0; ks < nks; ++ks) {
-        const int jb = 2 * ks + (kq >> 1);
-        const float2 xv = sm.Ex[jb][li];
-        float a[4];
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          const float2 yv = sm.Ey[jb][4 * w + rb];
-          a[rb] = part ? xv.x * yv.y + xv.y * yv.x : xv.x * yv.x - xv.y * yv.y;
-        }
-        float b[6];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float2 v = sm.V[jb][c][li];
-          b[c] = part ? -v.y : v.x;
-          b[3 + c] = part ? v.x : v.y;
-        }
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-          for (int cb = 0; cb < 6; ++cb)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
-      }
-    } else {
-      // K = 32 per instruction: the 16 beams of the batch x (re, im); lane
-      // holds A[i = li][k = 8 kq + t] and B[k = 8 kq + t][l = li], t < 8,
-      // k = 2 beam + part
-      typedef typename std::conditional<PREC == FGA_BF16X3, bf8, h8>::type V8;
-      V8 ahi[4], alo[4];
+    for (int ks = 0; ks < NB / 2; ++ks) {
+      const int jb = 2 * ks + (kq >> 1);
+      const float2 xv = fb.Ex[jb][li];
+      float a[4];
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
-        float x[8];
+        const float2 yv = fb.Ey[jb][4 * w + rb];
+        a[rb] = part ? xv.x * yv.y + xv.y * yv.x : xv.x * yv.x - xv.y * yv.y;
+      }
+      float b[6];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int jb = 4 * kq + t;
-          const float2 xv = sm.Ex[jb][li], yv = sm.Ey[jb][4 * w + rb];
-          x[2 * t] = xv.x * yv.x - xv.y * yv.y;
-          x[2 * t + 1] = xv.x * yv.y + xv.y * yv.x;
-        }
-        if constexpr (PREC == FGA_FP16X2) {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) ahi[rb][i] = (S)x[i];
-        } else {
-          split<V8, S>(x, ahi[rb], alo[rb]);
-        }
+      for (int c = 0; c < 3; ++c) {
+        const float2 v = fb.V[jb][c][li];
+        b[c] = part ? -v.y : v.x;
+        b[3 + c] = part ? v.x : v.y;
       }
 #pragma unroll
-      for (int cb = 0; cb < 6; ++cb) {
-        const V8 bhi = __builtin_bit_cast(V8, sm.Bh[cb][kq][li]);
-        const V8 blo = __builtin_bit_cast(V8, sm.Bl[cb][kq][li]);
+      for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          if constexpr (PREC == FGA_BF16X3) {
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
-          } else if constexpr (PREC == FGA_FP16X2) {
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
-          } else {
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
-          }
-        }
-      }
+        for (int cb = 0; cb < 6; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
     }
-    __syncthreads();
-  }
-  // result register r of lane holds D[4 (lane/16) + r][lane % 16]; scaled back by wmax
-  static __device__ void store(const Acc &acc, double *P, double ws, int)
-  {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  } else {
+    // K = 32 per instruction: the 16 beams of the batch x (re, im); lane
+    // holds A[i = li][k = 8 kq + t] and B[k = 8 kq + t][l = li], t < 8,
+    // k = 2 beam + part
+    typedef typename std::conditional<PREC == FGA_BF16X3, __bf16, _Float16>::type S;
+    typedef typename std::conditional<PREC == FGA_BF16X3, bf8, h8>::type V8;
+    V8 ahi[4], alo[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
-      const int j = 4 * w + rb;
 #pragma unroll
-      for (int cb = 0; cb < 6; ++cb) {
-        const int u = cb / 3, c = cb % 3;
+      for (int t = 0; t < 4; ++t) {
+        const int jb = 4 * kq + t;
+        const float2 xv = fb.Ex[jb][li], yv = fb.Ey[jb][4 * w + rb];
+        const float x0 = xv.x * yv.x - xv.y * yv.y;
+        const float x1 = xv.x * yv.y + xv.y * yv.x;
+        const S h0 = (S)x0, h1 = (S)x1;
+        ahi[rb][2 * t] = h0;
+        ahi[rb][2 * t + 1] = h1;
+        if constexpr (PREC != FGA_FP16X2) {
+          alo[rb][2 * t] = (S)(x0 - (float)h0);
+          alo[rb][2 * t + 1] = (S)(x1 - (float)h1);
+        }
+      }
+    }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 4 * (lane >> 4) + r, l = lane & 15;
-          P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = (double)acc[rb][cb][r] * ws;
+    for (int cb = 0; cb < 6; ++cb) {
+      const V8 bhi = __builtin_bit_cast(V8, fb.Bh[cb][kq][li]);
+      const V8 blo = __builtin_bit_cast(V8, fb.Bl[cb][kq][li]);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        if constexpr (PREC == FGA_BF16X3) {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
+        } else if constexpr (PREC == FGA_FP16X2) {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
+        } else {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
         }
       }
     }
   }
-};
+}
+
+// Mixed-precision tile work item, software-pipelined over batches of NB
+// accepted beams: while the matrix cores take batch n from one factor
+// buffer, the same wavefronts fetch batch n + 1's records and build its
+// factors into the other, with one barrier per batch.  Accepted
+// candidates (window box meets the tile's point box) are appended to a ring
+// 256 candidates at a time, kept at least one batch ahead of the fetch.
+template <int PREC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mx_tile(GridGeom g, const int64_t *__restrict__ start,
+                                                 const Item *__restrict__ items, const int32_t *__restrict__ sched,
+                                                 const double *__restrict__ rec,
+                                                 double *__restrict__ partial,
+                                                 unsigned long long *__restrict__ executed,
+                                                 const unsigned long long *__restrict__ wmax)
+{
+  __shared__ MxSmem<PREC> sm;
+  const double ws = __longlong_as_double((long long)*wmax);
+  const int64_t item = sched[blockIdx.x];
+  const Item it = items[item];
+  const int t = it.tile;
+  const int tc[3] = {t % g.nt[0], (t / g.nt[0]) % g.nt[1], t / (g.nt[0] * g.nt[1])};
+  const int nr = (2 * g.reach[1] + 1) * (2 * g.reach[2] + 1);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int jb = tid >> 4, ii = tid & 15;  // NB * T == 256
+  double plo[3], phi[3], xq[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int i1 = T * tc[d] + T - 1 < g.n[d] - 1 ? T * tc[d] + T - 1 : g.n[d] - 1;
+    plo[d] = axis_coord(g, d, T * tc[d]);
+    phi[d] = axis_coord(g, d, i1);
+    xq[d] = axis_coord(g, d, T * tc[d] + ii);
+  }
+  const double hl2 = -0.5 / g.eps * LOG2E;
+  if (tid == 0) {
+    int64_t s = 0;
+    for (int r = 0; r < nr; ++r) {
+      int64_t b, len;
+      tile_run(g, start, tc[0], tc[1], tc[2], r, b, len);
+      sm.run_b[r] = b;
+      sm.run_pre[r] = s;
+      s += len;
+    }
+    sm.run_pre[nr] = s;
+  }
+  __syncthreads();
+
+  f4 acc[4][6];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  int64_t cand = it.k0, tail = 0;
+  auto refill = [&]() {
+    const int64_t k = cand + tid;
+    bool ok = false;
+    int32_t s = -1;
+    if (k < it.k1) {
+      int lo = 0, hi = nr - 1;  // last run with run_pre <= k
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sm.run_pre[mid] <= k) lo = mid;
+        else hi = mid - 1;
+      }
+      s = (int32_t)(sm.run_b[lo] + (k - sm.run_pre[lo]));
+      const double *q = rec + (int64_t)s * 12;
+      ok = q[0] + g.R >= plo[0] && q[0] - g.R <= phi[0] && q[1] + g.R >= plo[1] && q[1] - g.R <= phi[1] &&
+           q[2] + g.R >= plo[2] && q[2] - g.R <= phi[2];
+    }
+    int tot;
+    const int rk = block_rank(ok, &tot);
+    if (ok) sm.ring[(tail + rk) & (LCAP - 1)] = s;
+    tail += tot;
+    cand += 256;
+    __syncthreads();
+  };
+  auto clampnb = [](int64_t v) { return (int)(v < 0 ? 0 : v > NB ? NB : v); };
+
+  // prologue: batch 0's factors into buffer 0
+  while (tail < NB && cand < it.k1) refill();
+  int64_t p = 0;  // ring position of the batch on the matrix cores
+  int cc = clampnb(tail);
+  MxRegs ra;
+  mx_fetch(rec, sm.ring, 0, jb, cc, ra);
+  mx_make<PREC>(g, xq, hl2, ra, sm.fb[0], jb, ii);
+  __syncthreads();
+
+  unsigned long long nexec = 0;
+  int buf = 0;
+  while (cc > 0) {
+    while (tail - (p + NB) < NB && cand < it.k1) refill();
+    const int cn = clampnb(tail - (p + NB));
+    mx_fetch(rec, sm.ring, p + NB, jb, cn, ra);  // in flight while the matrix cores run
+    mx_mma<PREC>(sm.fb[buf], acc, w, lane);
+    mx_make<PREC>(g, xq, hl2, ra, sm.fb[buf ^ 1], jb, ii);  // zeros after the last batch
+    __syncthreads();
+    nexec += cc;
+    buf ^= 1;
+    p += NB;
+    cc = cn;
+  }
+  if (tid == 0 && executed && nexec) atomicAdd(executed, nexec);
+
+  // partial tile [c][l][j][i] complex; result register r of lane holds
+  // D[4 (lane/16) + r][lane % 16], scaled back by wmax
+  double *P = partial + item * (3 * T * T * T * 2);
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int j = 4 * w + rb;
+#pragma unroll
+    for (int cb = 0; cb < 6; ++cb) {
+      const int u = cb / 3, c = cb % 3;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * (lane >> 4) + r, l = lane & 15;
+        P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = (double)acc[rb][cb][r] * ws;
+      }
+    }
+  }
+}
 
 template <class Pol>
 __global__ __launch_bounds__(256) void k_grid_tile(GridGeom g, const int64_t *__restrict__ start,
-                                                   const Item *__restrict__ items, const double *__restrict__ rec,
+                                                   const Item *__restrict__ items, const int32_t *__restrict__ sched,
+                                                   const double *__restrict__ rec,
                                                    double *__restrict__ partial, unsigned long long *__restrict__ executed,
                                                    const unsigned long long *__restrict__ wmax)
 {
@@ -526,7 +676,7 @@ __global__ __launch_bounds__(256) void k_grid_tile(GridGeom g, const int64_t *__
   Pol::init(sm);
   const double ws = wmax ? __longlong_as_double((long long)*wmax) : 1.0;
   const double iws = ws > 0.0 ? 1.0 / ws : 0.0;
-  const int64_t item = blockIdx.x / Pol::SPLIT;
+  const int64_t item = sched[blockIdx.x / Pol::SPLIT];
   const int half = blockIdx.x % Pol::SPLIT;
   const Item it = items[item];
   const int t = it.tile;
@@ -669,13 +819,15 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
   const int ntile = g.nt[0] * g.nt[1] * g.nt[2];
   const int64_t ncells = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
   if (ncells >= 0x7fffffff) return fail(FGA_EUNSUPPORTED, "too many cells");
-  const int max_items = 1024 + ntile;
+  const int nseg = NSEG < 8 * ntile ? NSEG : 8 * ntile;
+  const int max_items = nseg + ntile;
 
   int32_t *keys = ar.take<int32_t>(nb + 1), *keys2 = ar.take<int32_t>(nb + 1);
   int32_t *vals = ar.take<int32_t>(nb + 1), *vals2 = ar.take<int32_t>(nb + 1);
   int64_t *start = ar.take<int64_t>(ncells + 1);
   int64_t *tcount = ar.take<int64_t>(ntile);
   Item *items = ar.take<Item>(max_items);
+  int32_t *sched = ar.take<int32_t>(max_items);
   int32_t *first = ar.take<int32_t>(ntile), *nitems = ar.take<int32_t>(ntile);
   unsigned long long *ev = ar.take<unsigned long long>(3);  // evals, executed, max |W| bits
   double *partial = ar.take<double>((size_t)max_items * 3 * T * T * T * 2);
@@ -689,7 +841,7 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
     *need = ar.used;
     return FGA_OK;
   }
-  if (!keys || !keys2 || !vals || !vals2 || !start || !tcount || !items || !first || !nitems || !ev || !partial ||
+  if (!keys || !keys2 || !vals || !vals2 || !start || !tcount || !items || !sched || !first || !nitems || !ev || !partial ||
       !sort_tmp || !rec)
     return fail(FGA_ENOMEM, "grid summation workspace too small (%zu bytes given)", ar.size);
   if (nb > 0x7fffffff) return fail(FGA_EUNSUPPORTED, "more than 2^31 beams in one grid summation");
@@ -703,6 +855,10 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
     hipLaunchKernelGGL(k_grid_records, (unsigned)((nb + 255) / 256), 256, 0, st, b->f64, b->i32, b->capacity, keys2,
                        vals2, nb, 1.0 / eps, rec, precision == FGA_FP64 ? nullptr : ev + 2);
     FGA_LAUNCH_CHECK();
+    if (precision != FGA_FP64) {
+      hipLaunchKernelGGL(k_mx_records, (unsigned)((nb + 255) / 256), 256, 0, st, rec, keys2, nb, ev + 2);
+      FGA_LAUNCH_CHECK();
+    }
   }
   hipLaunchKernelGGL(k_cell_start, (unsigned)((ncells + 1 + 255) / 256), 256, 0, st, keys2, nb, (int32_t)ncells,
                      start);
@@ -718,7 +874,7 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
 
   int64_t total = 0;
   for (int t = 0; t < ntile; ++t) total += hc[t];
-  int64_t seg = (total + 1023) / 1024;
+  int64_t seg = (total + nseg - 1) / nseg;
   if (seg < 64) seg = 64;
   seg = (seg + NB - 1) / NB * NB;
   std::vector<Item> hi;
@@ -729,8 +885,15 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
     hn[t] = (int32_t)hi.size() - hf[t];
   }
   if ((int)hi.size() > max_items) return fail(FGA_EDEVICE, "internal: %zu work items > %d", hi.size(), max_items);
+  // launch order: the longest items first, so that the short ones fill the
+  // tail of the launch (greedy longest-processing-time scheduling)
+  std::vector<int32_t> hs(hi.size());
+  for (size_t k = 0; k < hi.size(); ++k) hs[k] = (int32_t)k;
+  std::stable_sort(hs.begin(), hs.end(),
+                   [&](int32_t a, int32_t b) { return hi[a].k1 - hi[a].k0 > hi[b].k1 - hi[b].k0; });
   if (!hi.empty()) {
     FGA_HIP(hipMemcpyAsync(items, hi.data(), hi.size() * sizeof(Item), hipMemcpyHostToDevice, st));
+    FGA_HIP(hipMemcpyAsync(sched, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
   }
   FGA_HIP(hipMemcpyAsync(first, hf.data(), ntile * sizeof(int32_t), hipMemcpyHostToDevice, st));
   FGA_HIP(hipMemcpyAsync(nitems, hn.data(), ntile * sizeof(int32_t), hipMemcpyHostToDevice, st));
@@ -739,24 +902,20 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
     const unsigned nwg = (unsigned)hi.size();
     switch (precision) {
       case FGA_FP64:
-        hipLaunchKernelGGL(k_grid_tile<PolicyF64>, nwg * PolicyF64::SPLIT, 256, 0, st, g, start, items, rec, partial,
+        hipLaunchKernelGGL(k_grid_tile<PolicyF64>, nwg * PolicyF64::SPLIT, 256, 0, st, g, start, items, sched, rec, partial,
                            ev + 1, nullptr);
         break;
       case FGA_FP32:
-        hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_FP32>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
-                           ev + 2);
+        hipLaunchKernelGGL(k_mx_tile<FGA_FP32>, nwg, 256, 0, st, g, start, items, sched, rec, partial, ev + 1, ev + 2);
         break;
       case FGA_BF16X3:
-        hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_BF16X3>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
-                           ev + 2);
+        hipLaunchKernelGGL(k_mx_tile<FGA_BF16X3>, nwg, 256, 0, st, g, start, items, sched, rec, partial, ev + 1, ev + 2);
         break;
       case FGA_FP16X3:
-        hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_FP16X3>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
-                           ev + 2);
+        hipLaunchKernelGGL(k_mx_tile<FGA_FP16X3>, nwg, 256, 0, st, g, start, items, sched, rec, partial, ev + 1, ev + 2);
         break;
       default:
-        hipLaunchKernelGGL(k_grid_tile<PolicyMx<FGA_FP16X2>>, nwg, 256, 0, st, g, start, items, rec, partial, ev + 1,
-                           ev + 2);
+        hipLaunchKernelGGL(k_mx_tile<FGA_FP16X2>, nwg, 256, 0, st, g, start, items, sched, rec, partial, ev + 1, ev + 2);
         break;
     }
     FGA_LAUNCH_CHECK();
