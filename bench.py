@@ -26,7 +26,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 operations per unit of algorithmic work (derivation in the design doc):
+# FP64 operations per unit of algorithmic work, counted in the gfx950 code (FMA = 2):
 #   one RK4 beam-step (4 right-hand sides + the update), per medium kind,
 #   one receiver/point term (window test excluded), one grid term.
 FLOP_BEAM_STEP = {"homogeneous": 3390, "grid": 4186, "layered": 3390}
@@ -444,8 +444,8 @@ def serve(args):
 
 
 def mixed(args):
-    """Mixed-precision grid summation at eps = 1/512: config 2's medium and
-    packet form, q 50^3 x p 8^3 x 3 branches in waves (q slabs along z);
+    """Mixed-precision grid summation at eps = 1/512: the smooth random
+    medium (128^3 table) and packet form of the default workload, q 50^3 x p 8^3 x 3 branches in waves (q slabs along z);
     each wave is decomposed, evolved 250 FP64 RK4 steps to T = 0.25 and summed
     onto the 256^3 grid (tau = 16) by every variant (FP64, FP32, BF16 hi+lo,
     FP16 hi+lo, FP16 rows x hi+lo factors), each added into its own output.  Reports per variant the
@@ -526,7 +526,7 @@ def mixed(args):
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * elapsed,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32/bf16/f16", "data": "synthetic",
-        "config": {"workload": "mixed-precision grid: config-2 medium and packet at eps=1/512, q %d^3 x p 8^3 x 3 "
+        "config": {"workload": "mixed-precision grid: smooth random medium and packet at eps=1/512, q %d^3 x p 8^3 x 3 "
                                "branches in %d waves, 250 FP64 RK4 steps to T=0.25, 256^3 grid (tau=16) summed by "
                                "FP64, FP32, BF16 hi+lo, FP16 hi+lo and FP16 x (hi+lo) tile GEMMs" % (nq, len(slabs)),
                    "beams": tot["beams"], "waves": len(slabs), "parallelism": "single GPU"},

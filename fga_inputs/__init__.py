@@ -206,7 +206,7 @@ def smooth_medium_packet(name="c2", eps=1.0 / 128, nq=32, np_=8, ny=128, nmed=12
 
 
 def mixed_waves(eps=1.0 / 512, nq=50, np_=8, ny=256, nsteps=250, dt=1e-3, nout=256, tau=16.0, waves=4):
-    """The smooth random medium and packet form of config 2 at eps = 1/512,
+    """The smooth random medium and packet form of the smooth-medium workload at eps = 1/512,
     q nq^3 x p np_^3 x 3 branches, evolved to T = nsteps dt and summed on an
     nout^3 grid of [0,1]^3.  The q mesh is cut into `waves` slabs along z
     (sizes differing by at most one plane), each decomposed, evolved and summed
@@ -264,7 +264,7 @@ def sweep_request(i: int, nmodels: int = 4, nsteps: int = 250, dt: float = 2e-3,
 
 
 # ---------------------------------------------------------------------------
-# layered spherical Earth-like model with a point source (config 3)
+# layered spherical Earth-like model with a point source
 # ---------------------------------------------------------------------------
 
 def fibonacci_sphere(n: int, g: np.random.Generator) -> np.ndarray:

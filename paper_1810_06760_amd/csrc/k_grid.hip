@@ -17,7 +17,7 @@
 // products hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_{bf16,f16}
 // (FGA_BF16X3, FGA_FP16X3); FGA_FP16X2 rounds the Khatri-Rao rows to FP16
 // once (2^-11 relative) and splits only the factor block, two products.
-// The mixed tiles are software-pipelined: one batch of beams on the matrix
+// Every tile kernel is software-pipelined: one batch of beams on the matrix
 // cores while the next one's factors are built, one barrier per batch.
 //
 // Beams are binned by the tile-sized cell of Q (radix sort of cell keys); a
@@ -196,121 +196,6 @@ __global__ __launch_bounds__(256) void k_grid_records(const double *__restrict__
   if (wmax && m > 0.0 && m < INFINITY) atomicMax(wmax, (unsigned long long)__double_as_longlong(m));
 }
 
-struct ListSmem {
-  int64_t run_b[MAXR], run_pre[MAXR + 1];
-  int32_t list[256 + NB];
-  int listn;
-  double brec[NB][12];
-};
-
-struct TileSmem : ListSmem {
-  double2 Ex[NB][T], Ey[NB][T], Ez[NB][T], V[NB][3][T];
-  TrigTables tab;
-};
-
-// One batch of `cnt` (<= NB) accepted beams, listed by sorted position in
-// sm.list[0..cnt): build the window-masked 1-D factors and W Ez, then the
-// K = 2 cnt (re, im) slice of the tile GEMM on the matrix cores.
-// This workgroup's wavefronts own tile rows j = j0 + RB w + rb, rb < RB.
-template <int RB>
-__device__ __forceinline__ void grid_batch(const GridGeom &g, const double *__restrict__ rec, TileSmem &sm, int cnt,
-                                           const int tc[3], d4 acc[RB][6], int j0)
-{
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const double hieps = 0.5 / g.eps;
-  for (int e = tid; e < NB * 12; e += 256) {
-    const int jb = e / 12, f = e % 12;
-    sm.brec[jb][f] = jb < cnt ? rec[(int64_t)sm.list[jb] * 12 + f] : (f < 3 ? -1.0e300 : 0.0);
-  }
-  __syncthreads();
-  for (int e = tid; e < NB * 3 * T; e += 256) {
-    const int jb = e / (3 * T), d = (e / T) % 3, ii = e % T;
-    const double x = axis_coord(g, d, T * tc[d] + ii);
-    const double u = x - sm.brec[jb][d];
-    double2 E;
-    cexp_neg_units(sm.tab, u * u * hieps, sm.brec[jb][3 + d] * u, fabs(u) <= g.R, E.x, E.y);
-    if (d == 0) sm.Ex[jb][ii] = E;
-    else if (d == 1) sm.Ey[jb][ii] = E;
-    else sm.Ez[jb][ii] = E;
-  }
-  __syncthreads();
-  for (int e = tid; e < NB * 3 * T; e += 256) {
-    const int jb = e / (3 * T), c = (e / T) % 3, l = e % T;
-    double r_, i_;
-    cmul(sm.brec[jb][6 + 2 * c], sm.brec[jb][7 + 2 * c], sm.Ez[jb][l].x, sm.Ez[jb][l].y, r_, i_);
-    sm.V[jb][c][l] = make_double2(r_, i_);
-  }
-  __syncthreads();
-  const int li = lane & 15, kk = lane >> 4, part = kk & 1;
-  const int nks = (cnt + 1) / 2;
-#pragma unroll 2
-  for (int ks = 0; ks < nks; ++ks) {
-    const int jb = 2 * ks + (kk >> 1);
-    const double2 xv = sm.Ex[jb][li];
-    double a[RB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const double2 yv = sm.Ey[jb][j0 + RB * w + rb];
-      double xr, xi;
-      cmul(xv.x, xv.y, yv.x, yv.y, xr, xi);
-      a[rb] = part ? xi : xr;
-    }
-    double b[6];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double2 v = sm.V[jb][c][li];
-      b[c] = part ? -v.y : v.x;     // columns of Re U
-      b[3 + c] = part ? v.x : v.y;  // columns of Im U
-    }
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 6; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
-  }
-  __syncthreads();
-}
-
-// FP64: a tile's 16 rows are split over two workgroups (8 rows each), which
-// halves the accumulators so that two wavefronts fit per SIMD and one's
-// factor work overlaps the other's matrix-core work.
-struct PolicyF64 {
-  static constexpr int SPLIT = 2, RB = 4 / SPLIT;
-  typedef TileSmem Smem;
-  typedef d4 Acc[RB][6];
-  static __device__ void init(Smem &sm) { fill_tables(sm.tab); }
-  static __device__ void zero(Acc &acc)
-  {
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
-  }
-  static __device__ void batch(const GridGeom &g, const double *rec, Smem &sm, int cnt, const int tc[3], Acc &acc,
-                               double, int half)
-  {
-    grid_batch<RB>(g, rec, sm, cnt, tc, acc, half * (16 / SPLIT));
-  }
-  // result register r of lane holds D[lane/16 + 4r][lane % 16] (row: x index i; column: z index l)
-  static __device__ void store(const Acc &acc, double *P, double, int half)
-  {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int j = half * (16 / SPLIT) + RB * w + rb;
-#pragma unroll
-      for (int cb = 0; cb < 6; ++cb) {
-        const int u = cb / 3, c = cb % 3;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = (lane >> 4) + 4 * r, l = lane & 15;
-          P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = acc[rb][cb][r];
-        }
-      }
-    }
-  }
-};
-
 // ------------------------------------------------------ mixed precision --
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -378,12 +263,6 @@ template <int PREC> struct MxBuf {
 };
 template <> struct MxBuf<FGA_FP32> {
   float2 Ex[NB][T], Ey[NB][T], V[NB][3][T];
-};
-
-template <int PREC> struct MxSmem {
-  int64_t run_b[MAXR], run_pre[MAXR + 1];
-  int32_t ring[LCAP];
-  MxBuf<PREC> fb[2];
 };
 
 template <class S> __device__ __forceinline__ uint32_t half_pair(S lo16, S hi16)
@@ -545,23 +424,198 @@ __device__ __forceinline__ void mx_mma(const MxBuf<PREC> &fb, f4 (&acc)[4][6], i
   }
 }
 
-// Mixed-precision tile work item, software-pipelined over batches of NB
-// accepted beams: while the matrix cores take batch n from one factor
-// buffer, the same wavefronts fetch batch n + 1's records and build its
-// factors into the other, with one barrier per batch.  Accepted
-// candidates (window box meets the tile's point box) are appended to a ring
-// 256 candidates at a time, kept at least one batch ahead of the fetch.
-template <int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mx_tile(GridGeom g, const int64_t *__restrict__ start,
-                                                 const Item *__restrict__ items, const int32_t *__restrict__ sched,
-                                                 const double *__restrict__ rec,
-                                                 double *__restrict__ partial,
-                                                 unsigned long long *__restrict__ executed,
-                                                 const unsigned long long *__restrict__ wmax)
+// Mixed policy: 16 rows of the tile per workgroup (4 per wavefront), FP32
+// accumulators scaled back by max |W| at the store.
+template <int PREC> struct PolMx {
+  static constexpr int SPLIT = 1;
+  typedef MxBuf<PREC> Buf;
+  typedef MxRegs Regs;
+  typedef f4 Acc[4][6];
+  struct Extra {};
+  static __device__ void init(Extra &) {}
+  static __device__ double arg(const GridGeom &g) { return -0.5 / g.eps * LOG2E; }
+  static __device__ void zero(Acc &acc)
+  {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  static __device__ void fetch(const double *rec, const int32_t *ring, int64_t p, int jb, int cnt, Regs &r)
+  {
+    mx_fetch(rec, ring, p, jb, cnt, r);
+  }
+  static __device__ void make(const GridGeom &g, const double (&xq)[3], double hl2, const Regs &r, Buf &fb,
+                              const Extra &, int jb, int ii)
+  {
+    mx_make<PREC>(g, xq, hl2, r, fb, jb, ii);
+  }
+  static __device__ void mma(const Buf &fb, Acc &acc, int w, int lane, int) { mx_mma<PREC>(fb, acc, w, lane); }
+  // result register r of lane holds D[4 (lane/16) + r][lane % 16]
+  static __device__ void store(const Acc &acc, double *P, double ws, int)
+  {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int j = 4 * w + rb;
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) {
+        const int u = cb / 3, c = cb % 3;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * (lane >> 4) + r, l = lane & 15;
+          P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = (double)acc[rb][cb][r] * ws;
+        }
+      }
+    }
+  }
+};
+
+// ------------------------------------------------------------------ FP64 --
+// Factors of one batch in FP64 (table-driven complex exponential) and the
+// factor block V = W Ez.
+struct F64Buf {
+  double2 Ex[NB][T], Ey[NB][T], V[NB][3][T];
+};
+
+// One thread's copy of the FP64 record of beam jb of a batch:
+// (q0, q1), (q2, v0), (v1, v2), W_0, W_1, W_2 (v: phase rate in units of pi/128).
+struct F64Regs {
+  double2 r[6];
+};
+
+// FP64 policy: a tile's 16 rows are split over two workgroups (8 rows each,
+// 2 per wavefront), which halves the accumulators so that two wavefronts fit
+// per SIMD.
+struct PolF64 {
+  static constexpr int SPLIT = 2, RB = 2;
+  typedef F64Buf Buf;
+  typedef F64Regs Regs;
+  typedef d4 Acc[RB][6];
+  struct Extra {
+    TrigTables tab;
+  };
+  static __device__ void init(Extra &x) { fill_tables(x.tab); }
+  static __device__ double arg(const GridGeom &g) { return 0.5 / g.eps; }
+  static __device__ void zero(Acc &acc)
+  {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  static __device__ void fetch(const double *__restrict__ rec, const int32_t *ring, int64_t p, int jb, int cnt,
+                               Regs &r)
+  {
+    if (jb < cnt) {
+      const double2 *src = reinterpret_cast<const double2 *>(rec + (int64_t)ring[(p + jb) & (LCAP - 1)] * 12);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) r.r[k] = src[k];
+    } else {  // idle slot: outside every window, zero weight
+      r.r[0] = make_double2(-1.0e300, -1.0e300);
+      r.r[1] = make_double2(-1.0e300, 0.0);
+#pragma unroll
+      for (int k = 2; k < 6; ++k) r.r[k] = make_double2(0.0, 0.0);
+    }
+  }
+  // thread (jb, ii): Ex(ii), Ey(ii), Ez(ii) of beam jb and V(ii) = W Ez(ii)
+  static __device__ void make(const GridGeom &g, const double (&xq)[3], double hieps, const Regs &r, Buf &fb,
+                              const Extra &x, int jb, int ii)
+  {
+    const double q[3] = {r.r[0].x, r.r[0].y, r.r[1].x};
+    const double v[3] = {r.r[1].y, r.r[2].x, r.r[2].y};
+    double2 E[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double u = xq[d] - q[d];
+      cexp_neg_units(x.tab, u * u * hieps, v[d] * u, fabs(u) <= g.R, E[d].x, E[d].y);
+    }
+    fb.Ex[jb][ii] = E[0];
+    fb.Ey[jb][ii] = E[1];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double vr, vi;
+      cmul(r.r[3 + c].x, r.r[3 + c].y, E[2].x, E[2].y, vr, vi);
+      fb.V[jb][c][ii] = make_double2(vr, vi);
+    }
+  }
+  // K = 4 per instruction: 2 beams x (re, im); lane holds A[i = li][k = kk],
+  // B[k = kk][l = li]; this workgroup's wavefronts own rows j = 8 half + 2 w + rb
+  static __device__ void mma(const Buf &fb, Acc &acc, int w, int lane, int half)
+  {
+    const int li = lane & 15, kk = lane >> 4, part = kk & 1;
+    const int j0 = 8 * half + RB * w;
+#pragma unroll 2
+    for (int ks = 0; ks < NB / 2; ++ks) {
+      const int jb = 2 * ks + (kk >> 1);
+      const double2 xv = fb.Ex[jb][li];
+      double a[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const double2 yv = fb.Ey[jb][j0 + rb];
+        double xr, xi;
+        cmul(xv.x, xv.y, yv.x, yv.y, xr, xi);
+        a[rb] = part ? xi : xr;
+      }
+      double b[6];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double2 v = fb.V[jb][c][li];
+        b[c] = part ? -v.y : v.x;     // columns of Re U
+        b[3 + c] = part ? v.x : v.y;  // columns of Im U
+      }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 6; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+    }
+  }
+  // result register r of lane holds D[lane/16 + 4r][lane % 16] (row: x index i; column: z index l)
+  static __device__ void store(const Acc &acc, double *P, double, int half)
+  {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int j = 8 * half + RB * w + rb;
+#pragma unroll
+      for (int cb = 0; cb < 6; ++cb) {
+        const int u = cb / 3, c = cb % 3;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = (lane >> 4) + 4 * r, l = lane & 15;
+          P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = acc[rb][cb][r];
+        }
+      }
+    }
+  }
+};
+
+template <class Pol> struct PipeSmem {
+  int64_t run_b[MAXR], run_pre[MAXR + 1];
+  int32_t ring[LCAP];
+  typename Pol::Buf fb[2];
+  typename Pol::Extra x;
+};
+
+// One work item (a tile's candidate segment; with SPLIT = 2, half of the
+// tile's rows), software-pipelined over batches of NB accepted beams: while
+// the matrix cores take batch n from one factor buffer, the same wavefronts
+// fetch batch n + 1's records and build its factors into the other, with one
+// barrier per batch.  Accepted candidates (window box meets the tile's point
+// box) are appended to a ring 256 candidates at a time, kept at least one
+// batch ahead.
+template <class Pol>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_grid_tile(
+    GridGeom g, const int64_t *__restrict__ start, const Item *__restrict__ items, const int32_t *__restrict__ sched,
+    const double *__restrict__ rec, double *__restrict__ partial, unsigned long long *__restrict__ executed,
+    const unsigned long long *__restrict__ wmax)
 {
-  __shared__ MxSmem<PREC> sm;
-  const double ws = __longlong_as_double((long long)*wmax);
-  const int64_t item = sched[blockIdx.x];
+  __shared__ PipeSmem<Pol> sm;
+  Pol::init(sm.x);
+  const double ws = wmax ? __longlong_as_double((long long)*wmax) : 1.0;
+  const int64_t item = sched[blockIdx.x / Pol::SPLIT];
+  const int half = blockIdx.x % Pol::SPLIT;
   const Item it = items[item];
   const int t = it.tile;
   const int tc[3] = {t % g.nt[0], (t / g.nt[0]) % g.nt[1], t / (g.nt[0] * g.nt[1])};
@@ -576,7 +630,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     phi[d] = axis_coord(g, d, i1);
     xq[d] = axis_coord(g, d, T * tc[d] + ii);
   }
-  const double hl2 = -0.5 / g.eps * LOG2E;
+  const double c0 = Pol::arg(g);
   if (tid == 0) {
     int64_t s = 0;
     for (int r = 0; r < nr; ++r) {
@@ -590,11 +644,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
   __syncthreads();
 
-  f4 acc[4][6];
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 6; ++cb) acc[rb][cb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  typename Pol::Acc acc;
+  Pol::zero(acc);
 
   int64_t cand = it.k0, tail = 0;
   auto refill = [&]() {
@@ -626,9 +677,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   while (tail < NB && cand < it.k1) refill();
   int64_t p = 0;  // ring position of the batch on the matrix cores
   int cc = clampnb(tail);
-  MxRegs ra;
-  mx_fetch(rec, sm.ring, 0, jb, cc, ra);
-  mx_make<PREC>(g, xq, hl2, ra, sm.fb[0], jb, ii);
+  typename Pol::Regs ra;
+  Pol::fetch(rec, sm.ring, 0, jb, cc, ra);
+  Pol::make(g, xq, c0, ra, sm.fb[0], sm.x, jb, ii);
   __syncthreads();
 
   unsigned long long nexec = 0;
@@ -636,119 +687,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   while (cc > 0) {
     while (tail - (p + NB) < NB && cand < it.k1) refill();
     const int cn = clampnb(tail - (p + NB));
-    mx_fetch(rec, sm.ring, p + NB, jb, cn, ra);  // in flight while the matrix cores run
-    mx_mma<PREC>(sm.fb[buf], acc, w, lane);
-    mx_make<PREC>(g, xq, hl2, ra, sm.fb[buf ^ 1], jb, ii);  // zeros after the last batch
+    Pol::fetch(rec, sm.ring, p + NB, jb, cn, ra);  // in flight while the matrix cores run
+    Pol::mma(sm.fb[buf], acc, w, lane, half);
+    Pol::make(g, xq, c0, ra, sm.fb[buf ^ 1], sm.x, jb, ii);  // zeros after the last batch
     __syncthreads();
     nexec += cc;
     buf ^= 1;
     p += NB;
     cc = cn;
-  }
-  if (tid == 0 && executed && nexec) atomicAdd(executed, nexec);
-
-  // partial tile [c][l][j][i] complex; result register r of lane holds
-  // D[4 (lane/16) + r][lane % 16], scaled back by wmax
-  double *P = partial + item * (3 * T * T * T * 2);
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb) {
-    const int j = 4 * w + rb;
-#pragma unroll
-    for (int cb = 0; cb < 6; ++cb) {
-      const int u = cb / 3, c = cb % 3;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 4 * (lane >> 4) + r, l = lane & 15;
-        P[((((int64_t)c * T + l) * T + j) * T + i) * 2 + u] = (double)acc[rb][cb][r] * ws;
-      }
-    }
-  }
-}
-
-template <class Pol>
-__global__ __launch_bounds__(256) void k_grid_tile(GridGeom g, const int64_t *__restrict__ start,
-                                                   const Item *__restrict__ items, const int32_t *__restrict__ sched,
-                                                   const double *__restrict__ rec,
-                                                   double *__restrict__ partial, unsigned long long *__restrict__ executed,
-                                                   const unsigned long long *__restrict__ wmax)
-{
-  __shared__ typename Pol::Smem sm;
-  Pol::init(sm);
-  const double ws = wmax ? __longlong_as_double((long long)*wmax) : 1.0;
-  const double iws = ws > 0.0 ? 1.0 / ws : 0.0;
-  const int64_t item = sched[blockIdx.x / Pol::SPLIT];
-  const int half = blockIdx.x % Pol::SPLIT;
-  const Item it = items[item];
-  const int t = it.tile;
-  const int tc[3] = {t % g.nt[0], (t / g.nt[0]) % g.nt[1], t / (g.nt[0] * g.nt[1])};
-  const int nr = (2 * g.reach[1] + 1) * (2 * g.reach[2] + 1);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // point box of the tile (ragged tiles end at the grid edge)
-  double plo[3], phi[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int i1 = T * tc[d] + T - 1 < g.n[d] - 1 ? T * tc[d] + T - 1 : g.n[d] - 1;
-    plo[d] = axis_coord(g, d, T * tc[d]);
-    phi[d] = axis_coord(g, d, i1);
-  }
-  if (tid == 0) {
-    int64_t s = 0;
-    for (int r = 0; r < nr; ++r) {
-      int64_t b, len;
-      tile_run(g, start, tc[0], tc[1], tc[2], r, b, len);
-      sm.run_b[r] = b;
-      sm.run_pre[r] = s;
-      s += len;
-    }
-    sm.run_pre[nr] = s;
-    sm.listn = 0;
-  }
-  __syncthreads();
-
-  typename Pol::Acc acc;
-  Pol::zero(acc);
-
-  unsigned long long nexec = 0;
-  for (int64_t c0 = it.k0; c0 < it.k1; c0 += 256) {
-    // candidates -> beams whose window box meets the tile's point box
-    const int64_t k = c0 + tid;
-    bool ok = false;
-    int32_t s = -1;
-    if (k < it.k1) {
-      int lo = 0, hi = nr - 1;  // last run with run_pre <= k
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sm.run_pre[mid] <= k) lo = mid;
-        else hi = mid - 1;
-      }
-      s = (int32_t)(sm.run_b[lo] + (k - sm.run_pre[lo]));
-      const double *q = rec + (int64_t)s * 12;
-      ok = q[0] + g.R >= plo[0] && q[0] - g.R <= phi[0] && q[1] + g.R >= plo[1] && q[1] - g.R <= phi[1] &&
-           q[2] + g.R >= plo[2] && q[2] - g.R <= phi[2];
-    }
-    int tot;
-    const int rk = block_rank(ok, &tot);
-    const int base = sm.listn;
-    if (ok) sm.list[base + rk] = s;
-    __syncthreads();
-    if (tid == 0) sm.listn = base + tot;
-    __syncthreads();
-    int ln = base + tot;
-    while (ln >= NB) {
-      Pol::batch(g, rec, sm, NB, tc, acc, iws, half);
-      nexec += NB;
-      const int32_t v = tid + NB < ln ? sm.list[tid + NB] : 0;
-      __syncthreads();
-      if (tid + NB < ln) sm.list[tid] = v;
-      ln -= NB;
-      if (tid == 0) sm.listn = ln;
-      __syncthreads();
-    }
-  }
-  if (sm.listn > 0) {
-    const int cnt = sm.listn;
-    Pol::batch(g, rec, sm, cnt, tc, acc, iws, half);
-    nexec += cnt;
   }
   if (tid == 0 && half == 0 && executed && nexec) atomicAdd(executed, nexec);
   // partial tile [c][l][j][i] complex
@@ -902,20 +848,24 @@ fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n
     const unsigned nwg = (unsigned)hi.size();
     switch (precision) {
       case FGA_FP64:
-        hipLaunchKernelGGL(k_grid_tile<PolicyF64>, nwg * PolicyF64::SPLIT, 256, 0, st, g, start, items, sched, rec, partial,
+        hipLaunchKernelGGL(k_grid_tile<PolF64>, nwg * PolF64::SPLIT, 256, 0, st, g, start, items, sched, rec, partial,
                            ev + 1, nullptr);
         break;
       case FGA_FP32:
-        hipLaunchKernelGGL(k_mx_tile<FGA_FP32>, nwg, 256, 0, st, g, start, items, sched, rec, partial, ev + 1, ev + 2);
+        hipLaunchKernelGGL(k_grid_tile<PolMx<FGA_FP32>>, nwg, 256, 0, st, g, start, items, sched, rec, partial,
+                           ev + 1, ev + 2);
         break;
       case FGA_BF16X3:
-        hipLaunchKernelGGL(k_mx_tile<FGA_BF16X3>, nwg, 256, 0, st, g, start, items, sched, rec, partial, ev + 1, ev + 2);
+        hipLaunchKernelGGL(k_grid_tile<PolMx<FGA_BF16X3>>, nwg, 256, 0, st, g, start, items, sched, rec, partial,
+                           ev + 1, ev + 2);
         break;
       case FGA_FP16X3:
-        hipLaunchKernelGGL(k_mx_tile<FGA_FP16X3>, nwg, 256, 0, st, g, start, items, sched, rec, partial, ev + 1, ev + 2);
+        hipLaunchKernelGGL(k_grid_tile<PolMx<FGA_FP16X3>>, nwg, 256, 0, st, g, start, items, sched, rec, partial,
+                           ev + 1, ev + 2);
         break;
       default:
-        hipLaunchKernelGGL(k_mx_tile<FGA_FP16X2>, nwg, 256, 0, st, g, start, items, sched, rec, partial, ev + 1, ev + 2);
+        hipLaunchKernelGGL(k_grid_tile<PolMx<FGA_FP16X2>>, nwg, 256, 0, st, g, start, items, sched, rec, partial,
+                           ev + 1, ev + 2);
         break;
     }
     FGA_LAUNCH_CHECK();

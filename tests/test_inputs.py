@@ -15,6 +15,6 @@ def test_mixed_waves_partition_the_q_mesh():
     assert np.abs(parts[key(parts)] - full[key(full)]).max() <= 1e-14
     assert sum(s.n[2] for s in slabs) == 10
     assert max(s.n[2] for s in slabs) - min(s.n[2] for s in slabs) <= 1
-    # the medium and packet are config 2's, at the requested eps
+    # the medium and packet are the smooth-medium workload's, at the requested eps
     w2 = fi.smooth_medium_packet(nq=10, ny=16, nout=16, nrec=0, eps=1.0 / 512)
     assert np.array_equal(w.medium_nodes, w2.medium_nodes) and np.array_equal(w.f, w2.f)
