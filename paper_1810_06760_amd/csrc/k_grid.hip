@@ -265,11 +265,6 @@ template <> struct MxBuf<FGA_FP32> {
   float2 Ex[NB][T], Ey[NB][T], V[NB][3][T];
 };
 
-template <class S> __device__ __forceinline__ uint32_t half_pair(S lo16, S hi16)
-{
-  return (uint32_t)__builtin_bit_cast(uint16_t, lo16) | ((uint32_t)__builtin_bit_cast(uint16_t, hi16) << 16);
-}
-
 // One thread's copy of the mixed record of beam jb of a batch (every thread
 // of the beam's 16 reads it; the loads of one wavefront touch 4 records).
 struct MxRegs {
@@ -334,13 +329,21 @@ __device__ __forceinline__ void mx_make(const GridGeom &g, const double (&xq)[3]
     if constexpr (PREC == FGA_FP32) {
       fb.V[jb][c][ii] = make_float2(vx, vy);
     } else {
-      const S xh = (S)vx, yh = (S)vy;
-      const S xl = (S)(vx - (float)xh), yl = (S)(vy - (float)yh);
+      // packed conversions: hi = (round(vx), round(-vy)), lo = the rounded
+      // remainders (rounding to nearest is odd-symmetric, so the Im U pairs
+      // are the same values swapped and re-signed)
+      typedef S s2 __attribute__((ext_vector_type(2)));
+      typedef float fl2 __attribute__((ext_vector_type(2)));
+      const s2 h1 = __builtin_convertvector((fl2){vx, -vy}, s2);
+      const float rx = vx - (float)h1.x, rny = -vy - (float)h1.y;
+      const s2 l1 = __builtin_convertvector((fl2){rx, rny}, s2);
+      const s2 h2 = __builtin_convertvector((fl2){vy, vx}, s2);
+      const s2 l2 = __builtin_convertvector((fl2){-rny, rx}, s2);
       const int q4 = jb >> 2, t = jb & 3;  // K entries 2t, 2t + 1 of the lane's eight
-      fb.Bh[c][q4][ii].v[t] = half_pair(xh, (S)(-yh));
-      fb.Bl[c][q4][ii].v[t] = half_pair(xl, (S)(-yl));
-      fb.Bh[c + 3][q4][ii].v[t] = half_pair(yh, xh);
-      fb.Bl[c + 3][q4][ii].v[t] = half_pair(yl, xl);
+      fb.Bh[c][q4][ii].v[t] = __builtin_bit_cast(uint32_t, h1);
+      fb.Bl[c][q4][ii].v[t] = __builtin_bit_cast(uint32_t, l1);
+      fb.Bh[c + 3][q4][ii].v[t] = __builtin_bit_cast(uint32_t, h2);
+      fb.Bl[c + 3][q4][ii].v[t] = __builtin_bit_cast(uint32_t, l2);
     }
   }
 }
@@ -383,6 +386,8 @@ __device__ __forceinline__ void mx_mma(const MxBuf<PREC> &fb, f4 (&acc)[4][6], i
     // k = 2 beam + part
     typedef typename std::conditional<PREC == FGA_BF16X3, __bf16, _Float16>::type S;
     typedef typename std::conditional<PREC == FGA_BF16X3, bf8, h8>::type V8;
+    typedef S s2 __attribute__((ext_vector_type(2)));
+    typedef float fl2 __attribute__((ext_vector_type(2)));
     V8 ahi[4], alo[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
@@ -392,12 +397,13 @@ __device__ __forceinline__ void mx_mma(const MxBuf<PREC> &fb, f4 (&acc)[4][6], i
         const float2 xv = fb.Ex[jb][li], yv = fb.Ey[jb][4 * w + rb];
         const float x0 = xv.x * yv.x - xv.y * yv.y;
         const float x1 = xv.x * yv.y + xv.y * yv.x;
-        const S h0 = (S)x0, h1 = (S)x1;
-        ahi[rb][2 * t] = h0;
-        ahi[rb][2 * t + 1] = h1;
+        const s2 h = __builtin_convertvector((fl2){x0, x1}, s2);  // one packed conversion per beam
+        ahi[rb][2 * t] = h.x;
+        ahi[rb][2 * t + 1] = h.y;
         if constexpr (PREC != FGA_FP16X2) {
-          alo[rb][2 * t] = (S)(x0 - (float)h0);
-          alo[rb][2 * t + 1] = (S)(x1 - (float)h1);
+          const s2 l = __builtin_convertvector((fl2){x0 - (float)h.x, x1 - (float)h.y}, s2);
+          alo[rb][2 * t] = l.x;
+          alo[rb][2 * t + 1] = l.y;
         }
       }
     }
