@@ -14,7 +14,7 @@ Conventions
   meshes of a box ``[a, b]`` use ``lo = a + h/2``.
 * 3-D arrays are stored ``[z][y][x]`` (x fastest); vector fields are
   ``[component][z][y][x]``.
-* Every random draw uses ``numpy.random.default_rng(1000*config + purpose)``.
+* Every random draw uses ``numpy.random.default_rng(1000*family + purpose)``.
 """
 from __future__ import annotations
 
@@ -26,9 +26,9 @@ import numpy as np
 SQRT3 = math.sqrt(3.0)
 
 
-def rng(config: int, purpose: int) -> np.random.Generator:
-    """Seeded generator for input ``purpose`` of workload ``config``."""
-    return np.random.default_rng(1000 * config + purpose)
+def rng(family: int, purpose: int) -> np.random.Generator:
+    """Seeded generator for input ``purpose`` of the seed family ``family`` (one per workload)."""
+    return np.random.default_rng(1000 * family + purpose)
 
 
 @dataclass
@@ -155,12 +155,12 @@ class Workload:
 
 
 def homogeneous_packet(name="c1", eps=1.0 / 32, nq=8, np_=4, ny=64, nsteps=100,
-                       dt=0.005, nout=32, config=1, tau=25.0) -> Workload:
+                       dt=0.005, nout=32, family=1, tau=25.0) -> Workload:
     """Plain FGA in a homogeneous medium (cp = sqrt(3), cs = 1): a Gaussian
     plane-wave packet of width 0.1 centred at (0.5,0.5,0.5) travelling along
     x, one-way data, q nq^3 on [0,1]^3, p np^3 around k0 = (1,0,0)."""
     width, centre, k0 = 0.1, (0.5, 0.5, 0.5), (1.0, 0.0, 0.0)
-    d = unit_vector(rng(config, 1))
+    d = unit_vector(rng(family, 1))
     ymesh = cell_centred(ny, 0.0, 1.0)
     return Workload(
         name=name, eps=eps, cp0=SQRT3, cs0=1.0,
@@ -176,18 +176,18 @@ def homogeneous_packet(name="c1", eps=1.0 / 32, nq=8, np_=4, ny=64, nsteps=100,
 
 
 def smooth_medium_packet(name="c2", eps=1.0 / 128, nq=32, np_=8, ny=128, nmed=128,
-                         nsteps=1000, dt=1e-3, nout=128, nrec=256, config=2,
+                         nsteps=1000, dt=1e-3, nout=128, nrec=256, family=2,
                          tau=25.0, cull_rel=1e-10) -> Workload:
     """Smooth heterogeneous medium cp = sqrt(3)(1 + 0.2 g), cs = cp/sqrt(3),
     g a periodic Gaussian random field (correlation length 0.2, std 1/3,
     clipped to |g| <= 1) on an nmed^3 node grid; Gaussian plane-wave packet
     initial data; receivers uniform in [0,1]^3."""
     width, centre, k0 = 0.1, (0.5, 0.5, 0.5), (1.0, 0.0, 0.0)
-    gfield = gaussian_random_field(nmed, 0.2, 1.0 / 3.0, 1.0, rng(config, 1))
+    gfield = gaussian_random_field(nmed, 0.2, 1.0 / 3.0, 1.0, rng(family, 1))
     cp_nodes = SQRT3 * (1.0 + 0.2 * gfield)
-    d = unit_vector(rng(config, 3))
+    d = unit_vector(rng(family, 3))
     ymesh = cell_centred(ny, 0.0, 1.0)
-    rec = uniform_points(nrec, rng(config, 2)) if nrec else None
+    rec = uniform_points(nrec, rng(family, 2)) if nrec else None
     # Peak |psi| of this data is bounded by the y-integral of |f|, which is at
     # most (2 pi width^2)^{3/2}; beams below cull_rel times that are not made.
     peak = (2.0 * math.pi * width ** 2) ** 1.5
@@ -212,7 +212,7 @@ def mixed_waves(eps=1.0 / 512, nq=50, np_=8, ny=256, nsteps=250, dt=1e-3, nout=2
     (sizes differing by at most one plane), each decomposed, evolved and summed
     on its own.  Returns (workload, list of the slabs' q meshes)."""
     w = smooth_medium_packet(name="c4", eps=eps, nq=nq, np_=np_, ny=ny, nsteps=nsteps, dt=dt, nout=nout, nrec=0,
-                             config=2, tau=tau)
+                             family=2, tau=tau)
     q = w.qmesh
     cuts = [round(k * q.n[2] / waves) for k in range(waves + 1)]
     slabs = [Mesh3((q.n[0], q.n[1], cuts[k + 1] - cuts[k]), (q.lo[0], q.lo[1], q.lo[2] + cuts[k] * q.h[2]), q.h)
@@ -285,7 +285,7 @@ def spherical_to_cartesian(r, theta, phi):
     return np.stack([r * np.cos(theta) * np.cos(phi), r * np.sin(theta) * np.cos(phi), r * np.sin(phi)], axis=-1)
 
 
-def layered_earth(config: int = 3, eps: float = 1.0 / 256, nq: int = 8, ndir: int = 1600, nshell: int = 4,
+def layered_earth(family: int = 3, eps: float = 1.0 / 256, nq: int = 8, ndir: int = 1600, nshell: int = 4,
                   nsteps: int = 2000, T: float = 1.5, nrec: int = 512) -> dict:
     """Unit sphere with 4 layers: 3 interface radii in (0.3, 0.95) at least
     0.1 apart; the top layer has c_P = sqrt(3), c_S = 1, rho = 1 and each
@@ -293,7 +293,7 @@ def layered_earth(config: int = 3, eps: float = 1.0 / 256, nq: int = 8, ndir: in
     moment-tensor source with a Ricker wavelet at radius U[0.6, 0.9] in a
     random direction; receivers on a Fibonacci lattice of the surface r = 1,
     given as (r, longitude, latitude) and mapped to Cartesian."""
-    g = rng(config, 1)
+    g = rng(family, 1)
     while True:
         radii = np.sort(g.uniform(0.3, 0.95, 3))[::-1]
         if np.all(-np.diff(radii) >= 0.1):
@@ -303,11 +303,11 @@ def layered_earth(config: int = 3, eps: float = 1.0 / 256, nq: int = 8, ndir: in
         cp.append(cp[-1] * g.uniform(1.05, 1.20))
         cs.append(cs[-1] * g.uniform(1.05, 1.20))
         rho.append(rho[-1] * g.uniform(1.05, 1.20))
-    gs = rng(config, 2)
+    gs = rng(family, 2)
     d = unit_vector(gs)
     x0 = d * gs.uniform(0.6, 0.9)
     M = moment_tensor(gs)
-    pts = fibonacci_sphere(nrec, rng(config, 3))
+    pts = fibonacci_sphere(nrec, rng(family, 3))
     theta = np.arctan2(pts[:, 1], pts[:, 0])
     phi = np.arcsin(np.clip(pts[:, 2], -1.0, 1.0))
     rec = spherical_to_cartesian(np.ones(nrec), theta, phi)

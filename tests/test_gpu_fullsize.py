@@ -123,3 +123,42 @@ def test_homogeneous_full_size():
     err = rel_l2(ug, uo)
     say("  grid vs oracle", err)
     assert err <= RTOL
+
+
+@pytest.mark.timeout(600)
+def test_mixed_grid_256():
+    """The mixed-precision workload's 256^3 grid (eps = 1/512, tau = 16) over
+    one wave of its packet (q 16^3 x p 8^3 x 3 branches, 250 FP64 steps in the
+    smooth random medium), so that every tile's candidate list is thousands of
+    beams long and its work is split into several items.  The FP64 tiles
+    agree with point sums at 512 seeded grid points to 1e-10; every mixed
+    variant is within 1e-3 of the FP64 tiles over the whole grid (relative
+    L2), and all report the same in-window count."""
+    import torch
+    import paper_1810_06760_amd as m
+    m.lib()
+    say("mixed grid: eps 1/512, q 16^3 x p 8^3 x 3, 250 steps, 256^3 grid")
+    w, slabs = fi.mixed_waves(nq=16, waves=1)
+    med = m.medium_for(w)
+    mesh = m.make_mesh(w.eps, slabs[0], w.pmesh, w.ymesh, cull_abs=w.cull_abs)
+    beams = m.fga_decompose(med, mesh, m._complex_dev(w.f))
+    m.fga_evolve(med, beams, w.dt, w.nsteps)
+    say("  beams", beams.count)
+    ref, ev = m.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid)
+    torch.cuda.synchronize()
+    say("  fp64 tiles, evals", ev)
+    n = w.out_grid.n[0]
+    sel = np.random.default_rng(4245).choice(w.out_grid.count, size=512, replace=False)
+    up, _ = m.fga_reconstruct_points(beams, w.eps, w.tau, w.out_grid.points()[sel])
+    zi, yi, xi = sel // (n * n), (sel // n) % n, sel % n
+    err = rel_l2(m.to_complex(ref)[:, zi, yi, xi].T, m.to_complex(up))
+    say("  fp64 tiles vs points", err)
+    assert err <= RTOL
+    nref = float(torch.linalg.vector_norm(ref))
+    for prec in ("FGA_FP32", "FGA_BF16X3", "FGA_FP16X3", "FGA_FP16X2"):
+        u, evm = m.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid, precision=getattr(m, prec))
+        e = float(torch.linalg.vector_norm(u - ref)) / nref
+        say("  %s vs fp64 tiles: %.3g" % (prec, e))
+        assert evm == ev
+        assert e <= 1e-3
+        del u
