@@ -265,6 +265,24 @@ template <> struct MxBuf<FGA_FP32> {
   float2 Ex[NB][T], Ey[NB][T], V[NB][3][T];
 };
 
+// -1 that the compiler cannot fold, so that x - hi below stays an FMA with
+// hi as a (16-bit) source: for FP16 one v_fma_mix_f32 reads hi as stored,
+// with no separate conversion back to FP32.
+__device__ __forceinline__ float opaque_m1()
+{
+  float m = -1.0f;
+  asm volatile("" : "+v"(m));
+  return m;
+}
+
+// x - hi, hi the 16-bit rounding of x (exact in FP32); a BF16 value widens
+// by a shift, which the plain difference uses
+template <class S> __device__ __forceinline__ float rem16(float x, S hi, float m1)
+{
+  if constexpr (std::is_same<S, _Float16>::value) return __builtin_fmaf((float)hi, m1, x);
+  else return x - (float)hi;
+}
+
 // One thread's copy of the mixed record of beam jb of a batch (every thread
 // of the beam's 16 reads it; the loads of one wavefront touch 4 records).
 struct MxRegs {
@@ -335,7 +353,8 @@ __device__ __forceinline__ void mx_make(const GridGeom &g, const double (&xq)[3]
       typedef S s2 __attribute__((ext_vector_type(2)));
       typedef float fl2 __attribute__((ext_vector_type(2)));
       const s2 h1 = __builtin_convertvector((fl2){vx, -vy}, s2);
-      const float rx = vx - (float)h1.x, rny = -vy - (float)h1.y;
+      const float m1 = std::is_same<S, _Float16>::value ? opaque_m1() : -1.0f;
+      const float rx = rem16(vx, h1.x, m1), rny = rem16(-vy, h1.y, m1);
       const s2 l1 = __builtin_convertvector((fl2){rx, rny}, s2);
       const s2 h2 = __builtin_convertvector((fl2){vy, vx}, s2);
       const s2 l2 = __builtin_convertvector((fl2){-rny, rx}, s2);
@@ -388,6 +407,7 @@ __device__ __forceinline__ void mx_mma(const MxBuf<PREC> &fb, f4 (&acc)[4][6], i
     typedef typename std::conditional<PREC == FGA_BF16X3, bf8, h8>::type V8;
     typedef S s2 __attribute__((ext_vector_type(2)));
     typedef float fl2 __attribute__((ext_vector_type(2)));
+    const float m1 = std::is_same<S, _Float16>::value ? opaque_m1() : -1.0f;
     V8 ahi[4], alo[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
@@ -401,7 +421,7 @@ __device__ __forceinline__ void mx_mma(const MxBuf<PREC> &fb, f4 (&acc)[4][6], i
         ahi[rb][2 * t] = h.x;
         ahi[rb][2 * t + 1] = h.y;
         if constexpr (PREC != FGA_FP16X2) {
-          const s2 l = __builtin_convertvector((fl2){x0 - (float)h.x, x1 - (float)h.y}, s2);
+          const s2 l = __builtin_convertvector((fl2){rem16(x0, h.x, m1), rem16(x1, h.y, m1)}, s2);
           alo[rb][2 * t] = l.x;
           alo[rb][2 * t + 1] = l.y;
         }
