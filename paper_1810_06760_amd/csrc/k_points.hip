@@ -49,6 +49,37 @@ __device__ __forceinline__ PointsWork points_work(int64_t id, int groups, int64_
 constexpr double INV_2PI = 0.15915494309189535;
 constexpr double LOG2E = 1.4426950408889634;
 
+// One term's complex factor exp(-|d|^2/(2 eps) + i P.d/eps), zero outside
+// the window (in false).  MIXED: the exponent and the phase (in revolutions,
+// reduced to [-1/2, 1/2]) are formed in FP64, then exp2 / sin / cos run on
+// the FP32 transcendental unit.  Otherwise the FP64 table-driven exponential.
+template <bool MIXED>
+__device__ __forceinline__ void point_term(const TrigTables &tab, const double (&dd)[3], const double (&pe)[3],
+                                           bool in, double hieps, double &er, double &ei)
+{
+  const double g = (dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]) * hieps;
+  const double v = pe[0] * dd[0] + pe[1] * dd[1] + pe[2] * dd[2];  // phase in units of pi/128
+  if constexpr (MIXED) {
+    const double rev = v * (1.0 / 256.0);
+    const float r = (float)(rev - rint(rev));
+    const float amp = in ? __builtin_amdgcn_exp2f((float)(-g * LOG2E)) : 0.0f;
+    er = (double)(amp * __builtin_amdgcn_cosf(r));
+    ei = (double)(amp * __builtin_amdgcn_sinf(r));
+  } else {
+    cexp_neg_units(tab, g, v, in, er, ei);
+  }
+}
+
+// u_c += (er + i ei) B_c, c = 0..2 (complex)
+__device__ __forceinline__ void accumulate_term(double (&u)[6], const double (&B)[6], double er, double ei)
+{
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    u[2 * c] = fma(er, B[2 * c], fma(-ei, B[2 * c + 1], u[2 * c]));
+    u[2 * c + 1] = fma(er, B[2 * c + 1], fma(ei, B[2 * c], u[2 * c + 1]));
+  }
+}
+
 // MIXED: the exponent and the phase (in revolutions, reduced to [-1/2, 1/2])
 // are formed in FP64, then exp2 / sin / cos run on the FP32 transcendental
 // unit; sums stay FP64.  Otherwise the FP64 table-driven exponential.
@@ -141,45 +172,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   };
   for (int64_t t0 = next_live(b0); t0 < b1; t0 = next_live(t0 + 64)) {
     fetch(t0);
-    // points four at a time: unless no lane's beam is in any of the four
-    // windows, the four terms are evaluated together (four independent
-    // exponential chains per lane hide each other's latency).  Outside its
-    // window a term's magnitude is replaced by zero.
+    // points four at a time: when every one of the four windows holds some
+    // lane's beam, the four terms are evaluated together (four independent
+    // exponential chains per lane hide each other's latency); otherwise only
+    // the points whose window holds a beam of the tile, one chain each.
+    // Outside its window a term's magnitude is replaced by zero, so skipping
+    // a point no lane reaches changes no sum.
 #pragma unroll
     for (int k = 0; k < RW; k += GRP) {
       double dd[GRP][3];
       bool in[GRP];
-      bool any = false;
+      unsigned need = 0;  // wave-uniform: points with at least one lane in window
 #pragma unroll
       for (int h = 0; h < GRP; ++h) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) dd[h][d] = xr[k + h][d] - q[d];
         in[h] = !(fmax(fabs(dd[h][0]), fmax(fabs(dd[h][1]), fabs(dd[h][2]))) > R);
-        cnt += __popcll(__ballot(in[h]));
-        any = any || in[h];
+        const uint64_t bal = __ballot(in[h]);
+        cnt += __popcll(bal);
+        need |= bal ? 1u << h : 0u;
       }
-      if (!__any(any)) continue;
-      double er[GRP], ei[GRP];
-#pragma unroll
-      for (int h = 0; h < GRP; ++h) {
-        const double g = (dd[h][0] * dd[h][0] + dd[h][1] * dd[h][1] + dd[h][2] * dd[h][2]) * hieps;
-        const double v = pe[0] * dd[h][0] + pe[1] * dd[h][1] + pe[2] * dd[h][2];  // phase in units of pi/128
-        if constexpr (MIXED) {
-          const double rev = v * (1.0 / 256.0);
-          const float r = (float)(rev - rint(rev));
-          const float amp = in[h] ? __builtin_amdgcn_exp2f((float)(-g * LOG2E)) : 0.0f;
-          er[h] = (double)(amp * __builtin_amdgcn_cosf(r));
-          ei[h] = (double)(amp * __builtin_amdgcn_sinf(r));
-        } else {
-          cexp_neg_units(tab, g, v, in[h], er[h], ei[h]);
-        }
-      }
+      if (!need) continue;
 #pragma unroll
       for (int h = 0; h < GRP; ++h)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          u[k + h][2 * c] = fma(er[h], B[2 * c], fma(-ei[h], B[2 * c + 1], u[k + h][2 * c]));
-          u[k + h][2 * c + 1] = fma(er[h], B[2 * c + 1], fma(ei[h], B[2 * c], u[k + h][2 * c + 1]));
+        if (need & (1u << h)) {
+          double er, ei;
+          point_term<MIXED>(tab, dd[h], pe, in[h], hieps, er, ei);
+          accumulate_term(u[k + h], B, er, ei);
         }
     }
   }
