@@ -25,8 +25,7 @@ namespace fga {
 constexpr int TRIG_N = 256;
 struct TrigTables {
   double e2[TRIG_N];    // 2^(j/256)
-  double sn[TRIG_N];    // sin(j pi/128)
-  double cs[TRIG_N];    // cos(j pi/128)
+  double2 sc[TRIG_N];   // (sin(j pi/128), cos(j pi/128)): one 16-byte read per lookup
 };
 
 // Fill the tables; call from every thread of the block, then __syncthreads().
@@ -36,8 +35,7 @@ __device__ __forceinline__ void fill_tables(TrigTables &t)
     t.e2[j] = exp2((double)j / 256.0);
     double s, c;
     sincospi((double)j / 128.0, &s, &c);
-    t.sn[j] = s;
-    t.cs[j] = c;
+    t.sc[j] = make_double2(s, c);
   }
 }
 
@@ -80,7 +78,8 @@ __device__ __forceinline__ void cexp_neg(const TrigTables &t, double g, double p
   double cp = fma(u2, -1.0 / 720.0, 1.0 / 24.0);
   cp = fma(u2, cp, -0.5);
   const double cu = fma(u2, cp, 1.0);
-  const double sj = t.sn[n], cj = t.cs[n];
+  const double2 scn = t.sc[n];
+  const double sj = scn.x, cj = scn.y;
   const double sphi = fma(su, cj, cu * sj);
   const double cphi = fma(cu, cj, -(su * sj));
   re = ex * cphi;
@@ -122,7 +121,8 @@ __device__ __forceinline__ void cexp_neg_units(const TrigTables &t, double g, do
   double cp = fma(u2, -1.0 / 720.0, 1.0 / 24.0);
   cp = fma(u2, cp, -0.5);
   const double cu = fma(u2, cp, 1.0);
-  const double sj = t.sn[n], cj = t.cs[n];
+  const double2 scn = t.sc[n];
+  const double sj = scn.x, cj = scn.y;
   const double sphi = fma(su, cj, cu * sj);
   const double cphi = fma(cu, cj, -(su * sj));
   re = ex * cphi;
