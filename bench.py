@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered", "mixed"])
     ap.add_argument("--waves", type=int, default=4, help="beam waves of the mixed-precision workload")
     ap.add_argument("--batch", type=int, default=0, help="beams per receiver-sum batch in the evolution (0: library default)")
+    ap.add_argument("--resort", type=int, default=0,
+                    help="steps between spatial re-sorts of the beams in the evolution (0: library default, <0 never)")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -122,7 +124,7 @@ def gpu_run(w, args):
         for s0 in range(0, w.nsteps, seg):
             n = min(seg, w.nsteps - s0)
             part, st_k = fga.fga_evolve(med, beams, w.dt, n, receivers=rec, eps=w.eps, tau=w.tau,
-                                        ws=state["ws_ev"], batch=args.batch)
+                                        ws=state["ws_ev"], batch=args.batch, resort=args.resort)
             if rec is not None:
                 state["seis"][:, s0:s0 + n].copy_(part)
             st["beam_steps"] += st_k["beam_steps"]
