@@ -22,8 +22,9 @@
 //
 // Beams are binned by the tile-sized cell of Q (radix sort of cell keys); a
 // tile's candidates are the (2r+1)^2 contiguous runs of cells within reach of
-// it.  Each tile's candidate list is split into segments, one workgroup per
-// segment, whose partial tiles are then reduced in a fixed order.
+// it.  Each tile's candidate list is split into segments (work items, one
+// workgroup each, launched longest first so that short items fill the end of
+// the launch), whose partial tiles are then reduced in a fixed order.
 #include <algorithm>
 #include <hipcub/hipcub.hpp>
 #include <type_traits>

@@ -46,7 +46,6 @@ __device__ __forceinline__ PointsWork points_work(int64_t id, int groups, int64_
   return w;
 }
 
-constexpr double INV_2PI = 0.15915494309189535;
 constexpr double LOG2E = 1.4426950408889634;
 
 // One term's complex factor exp(-|d|^2/(2 eps) + i P.d/eps), zero outside
