@@ -259,22 +259,39 @@ __global__ __launch_bounds__(256) void k_tile_box(const double *__restrict__ emi
   }
 }
 
-// out[perm[r]][s0 + s][c] (+)= sum over blocks of partial[blk][s][r][c], blocks in order.
-__global__ __launch_bounds__(256) void k_reduce_points(const double *__restrict__ partial, int nblk, int m, int64_t n,
-                                                       const int32_t *__restrict__ perm, double *__restrict__ out,
-                                                       int64_t out_samples, int s0, int accumulate)
+// out[perm[r]][s0 + s][c] (+)= sum over blocks of partial[blk][s][r][c].
+// A workgroup takes 64 consecutive outputs (one per lane, so every block row
+// is read coalesced); its RG wavefronts sum the blocks b = w, w + RG, ... in
+// order, and lane l of wavefront 0 adds the RG partial sums in order: a
+// fixed summation order, bitwise reproducible, with RG times the parallelism
+// of one thread per output.
+constexpr int RG = 16;
+__global__ __launch_bounds__(64 * RG) void k_reduce_points(const double *__restrict__ partial, int nblk, int m,
+                                                           int64_t n, const int32_t *__restrict__ perm,
+                                                           double *__restrict__ out, int64_t out_samples, int s0,
+                                                           int accumulate)
 {
-  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;  // (s, r, c6)
+  __shared__ double part[RG][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t id = (int64_t)blockIdx.x * 64 + lane;  // (s, r, c6)
   const int64_t total = (int64_t)m * n * 6;
-  if (id >= total) return;
-  const int c6 = (int)(id % 6);
-  const int64_t r = (id / 6) % n;
-  const int s = (int)(id / (6 * n));
+  const int64_t row = (int64_t)m * n * 6;  // doubles per block
   double v = 0.0;
-  for (int b = 0; b < nblk; ++b) v += partial[(((int64_t)b * m + s) * n + r) * 6 + c6];
-  const int64_t ro = perm ? perm[r] : r;
-  double *o = out + (ro * out_samples + s0 + s) * 6 + c6;
-  *o = accumulate ? *o + v : v;
+  if (id < total)
+    for (int b = w; b < nblk; b += RG) v += partial[(int64_t)b * row + id];
+  part[w][lane] = v;
+  __syncthreads();
+  if (w == 0 && id < total) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < RG; ++k) t += part[k][lane];
+    const int c6 = (int)(id % 6);
+    const int64_t r = (id / 6) % n;
+    const int s = (int)(id / (6 * n));
+    const int64_t ro = perm ? perm[r] : r;
+    double *o = out + (ro * out_samples + s0 + s) * 6 + c6;
+    *o = accumulate ? *o + t : t;
+  }
 }
 
 }  // namespace
@@ -319,7 +336,7 @@ hipError_t launch_reduce_points(const double *partial, int nblk, int m, int64_t 
 {
   const int64_t total = (int64_t)m * n * 6;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_points, (unsigned)((total + 255) / 256), 256, 0, st, partial, nblk, m, n, perm, out,
+  hipLaunchKernelGGL(k_reduce_points, (unsigned)((total + 63) / 64), 64 * RG, 0, st, partial, nblk, m, n, perm, out,
                      out_samples, s0, accumulate);
   return hipGetLastError();
 }
