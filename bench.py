@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 # FP64 operations per unit of algorithmic work, counted in the gfx950 code (FMA = 2):
 #   one RK4 beam-step (4 right-hand sides + the update), per medium kind,
 #   one receiver/point term (window test excluded), one grid term.
-FLOP_BEAM_STEP = {"homogeneous": 3390, "grid": 4186, "layered": 3390}
+FLOP_BEAM_STEP = {"homogeneous": 1647, "grid": 4186, "layered": 1647}  # grad c = 0: the step of rk4_step_pc
 FLOP_POINT_EVAL = 79      # FP64 flops per in-window receiver term (window test, exponent, phase, table
                           # exp and sincos, 12 accumulating FMAs), FMA = 2, counted in the gfx950 code
 FLOP_GRID_EVAL = 24       # 3 complex multiply-adds

@@ -143,7 +143,8 @@ __global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs 
       const double ieps = 1.0 / a.eps_emit;
       bool crossed = false;
       for (int s = 0; s < a.nsteps; ++s) {
-        rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt, &blk);
+        if constexpr (MK == MK_GRID) rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt, &blk);
+        else rk4_step_pc<MK>(med, sp, layer, sg, isS, y, dt);  // grad c = 0
         if constexpr (MK == MK_LAYERED) {
           // left the layer: the interface step redoes this step from the
           // stored state, which is therefore not overwritten

@@ -283,7 +283,7 @@ __device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, d
   for (int d = 0; d < 3; ++d) e[d] = a.f64[(FGA_E + d) * cap + i];
   double y1[NS];
   for (int f = 0; f < NS; ++f) y1[f] = y[f];
-  rk4_step<MK_LAYERED>(m, sp, L, sg, sp == 1, e, y1, a.dt);
+  rk4_step_pc<MK_LAYERED>(m, sp, L, sg, sp == 1, y1, a.dt);
   int iface = 0, newL = L;
   c.nkeep = 0;
   c.capped = false;
@@ -296,7 +296,7 @@ __device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, d
   }
   c.newL = newL;
   c.th = crossing(m, iface, y + IQ, y1 + IQ);
-  rk4_step<MK_LAYERED>(m, sp, L, sg, sp == 1, e, y, c.th * a.dt);
+  rk4_step_pc<MK_LAYERED>(m, sp, L, sg, sp == 1, y, c.th * a.dt);
   const double rb = m.bound[iface];
   if (m.geometry == 1) {
     const double r = sqrt(dot3(y + IQ, y + IQ));
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256) void k_interface(DevMedium m, InterfaceArgs a)
       z[IA + 2] = ash.r;
       z[IA + 3] = ash.i;
     }
-    rk4_step<MK_LAYERED>(m, spc, layc, (double)sigma, spc == 1, ec, z, (1.0 - c.th) * a.dt);
+    rk4_step_pc<MK_LAYERED>(m, spc, layc, (double)sigma, spc == 1, z, (1.0 - c.th) * a.dt);
     if (spc == 1) reframe_s(z, ec);
     for (int f = 0; f < NS; ++f) a.f64[f * cap + slot] = z[f];
     for (int d = 0; d < 3; ++d) a.f64[(FGA_E + d) * cap + slot] = ec[d];

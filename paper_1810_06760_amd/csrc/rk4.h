@@ -195,5 +195,105 @@ __device__ __forceinline__ void rk4_step(const DevMedium &med, int sp, int layer
   for (int f = 0; f < NS; ++f) y[f] += h6 * acc[f];
 }
 
+// The same classic RK4 step where grad c = 0 (a homogeneous medium, or
+// inside one layer of a layered medium).  There P and dzP have zero
+// derivative and Q, dzQ and S constant ones, so every stage's derivative of
+// those equals the first and the stage inputs y + c k are formed from it
+// directly; only the amplitudes' derivative depends on the stage (through
+// Z = dzQ + i dzP at the stage input, in tr(Z^{-1} dZ/dt)).  The stage
+// formulas, weights and summation order are those of rk4_step with the
+// medium's gradient and Hessian at zero (omega = 0 for S beams), so the two
+// agree to rounding, with about half the live registers and work.
+template <int MK>
+__device__ __forceinline__ void rk4_step_pc(const DevMedium &med, int sp, int layer, double sg, bool isS, double *y,
+                                            double dt)
+{
+  double c, g[3], H6[6];
+  medium_eval<MK>(med, sp, layer, y + IQ, c, g, H6);
+  const double P0 = y[IP], P1 = y[IP + 1], P2 = y[IP + 2];
+  const double np = sqrt(P0 * P0 + P1 * P1 + P2 * P2);
+  const double inp = 1.0 / np;
+  const double ph[3] = {P0 * inp, P1 * inp, P2 * inp};
+  const double sc = sg * c;
+  const double ci = sc * inp;
+  // the constant derivatives: dQ/dt, d(dzQ)/dt (re, im), dS/dt
+  double kQ[3], kr[9], ki[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) kQ[j] = sc * ph[j];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const double vr = y[IZPR + 3 * m] * ph[0] + y[IZPR + 3 * m + 1] * ph[1] + y[IZPR + 3 * m + 2] * ph[2];
+    const double vi = y[IZPI + 3 * m] * ph[0] + y[IZPI + 3 * m + 1] * ph[1] + y[IZPI + 3 * m + 2] * ph[2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      kr[3 * m + j] = ci * (y[IZPR + 3 * m + j] - vr * ph[j]);
+      ki[3 * m + j] = ci * (y[IZPI + 3 * m + j] - vi * ph[j]);
+    }
+  }
+  const double kS = P0 * kQ[0] + P1 * kQ[1] + P2 * kQ[2] - sc * np;
+
+  const double h2 = 0.5 * dt, h6 = dt / 6.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double a[4] = {y[IA], y[IA + 1], y[IA + 2], y[IA + 3]};  // amplitude stage input
+#pragma nounroll
+  for (int st = 0; st < 4; ++st) {
+    const double cs = st == 0 ? 0.0 : (st == 3 ? dt : h2);  // this stage's input: y + cs k
+    const double wacc = (st == 0 || st == 3) ? 1.0 : 2.0;
+    const double cnext = st == 2 ? dt : (st == 3 ? 0.0 : h2);
+    // Z at the stage input, Z = dzQ + i dzP
+    double zr[9], zi[9];
+#pragma unroll
+    for (int o = 0; o < 9; ++o) {
+      const double qr = st == 0 ? y[IZQR + o] : y[IZQR + o] + cs * kr[o];
+      const double qi = st == 0 ? y[IZQI + o] : y[IZQI + o] + cs * ki[o];
+      zr[o] = qr - y[IZPI + o];
+      zi[o] = qi + y[IZPR + o];
+    }
+    // cofactors (cyclic index form), det Z and T = cof(Z) : dZ/dt, dZ/dt = d(dzQ)/dt
+    double detr = 0.0, deti = 0.0, Tr = 0.0, Ti = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        const int ia = 3 * i1 + j1, ib = 3 * i2 + j2, ic = 3 * i1 + j2, id = 3 * i2 + j1;
+        const double Cr = (zr[ia] * zr[ib] - zi[ia] * zi[ib]) - (zr[ic] * zr[id] - zi[ic] * zi[id]);
+        const double Ci = (zr[ia] * zi[ib] + zi[ia] * zr[ib]) - (zr[ic] * zi[id] + zi[ic] * zr[id]);
+        if (i == 0) {
+          detr += zr[j] * Cr - zi[j] * Ci;
+          deti += zr[j] * Ci + zi[j] * Cr;
+        }
+        Tr += Cr * kr[3 * i + j] - Ci * ki[3 * i + j];
+        Ti += Cr * ki[3 * i + j] + Ci * kr[3 * i + j];
+      }
+    }
+    const double idd = 1.0 / (detr * detr + deti * deti);
+    const double sr = 0.5 * ((Tr * detr + Ti * deti) * idd);
+    const double si = 0.5 * ((Ti * detr - Tr * deti) * idd);
+    double ka[4];
+    ka[0] = sr * a[0] - si * a[1];
+    ka[1] = sr * a[1] + si * a[0];
+    ka[2] = isS ? sr * a[2] - si * a[3] : 0.0;
+    ka[3] = isS ? sr * a[3] + si * a[2] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[t] += wacc * ka[t];
+      a[t] = y[IA + t] + cnext * ka[t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) y[IA + t] += h6 * acc[t];
+  // k1 + 2 k2 + 2 k3 + k4 with equal stages, summed in rk4_step's order
+#pragma unroll
+  for (int j = 0; j < 3; ++j) y[IQ + j] += h6 * (((kQ[j] + 2.0 * kQ[j]) + 2.0 * kQ[j]) + kQ[j]);
+#pragma unroll
+  for (int o = 0; o < 9; ++o) {
+    y[IZQR + o] += h6 * (((kr[o] + 2.0 * kr[o]) + 2.0 * kr[o]) + kr[o]);
+    y[IZQI + o] += h6 * (((ki[o] + 2.0 * ki[o]) + 2.0 * ki[o]) + ki[o]);
+  }
+  y[IS] += h6 * (((kS + 2.0 * kS) + 2.0 * kS) + kS);
+}
+
 }  // namespace rk
 }  // namespace fga
