@@ -279,7 +279,7 @@ def layered(args):
         for s0 in range(0, e["nsteps"], seg):
             n = min(seg, e["nsteps"] - s0)
             part, st = fga.fga_evolve(med, beams, e["dt"], n, receivers=rec, eps=e["eps"], tau=e["tau"],
-                                      ws=state["ws"], batch=args.batch)
+                                      ws=state["ws"], batch=args.batch, resort=args.resort)
             state["seis"][:, s0:s0 + n].copy_(part)
             for k in tot:
                 tot[k] += st[k]
