@@ -1,4 +1,4 @@
-"""Parity at the benchmark's full size: smooth random medium, eps = 1/128,
+"""Parity at the workloads' full sizes.  Smooth random medium (the benchmark), eps = 1/128,
 q 32^3 x p 8^3 x 3 branches (49 M beams after the cull), 1000 FP64 RK4
 steps with 256 receivers sampled after every step, 128^3 grid at T = 1, run
 in the launch configuration the benchmark times (the evolution as 4 calls of
@@ -11,7 +11,9 @@ during the run).  Sums over all 49 M beams are beyond the oracle; for them
 the test checks properties that hold at any size: the MFMA grid tiles and
 the ALU point sums (independent kernels) agree at 512 seeded grid points,
 and the last seismogram sample, summed from the records the integrator
-emits, equals a point sum at the receivers over the final beams."""
+emits, equals a point sum at the receivers over the final beams.  The
+homogeneous packet, the mixed-precision 256^3 grid and the layered Earth
+have tests of their own below."""
 import sys
 
 import numpy as np
@@ -19,7 +21,7 @@ import pytest
 
 import fga_inputs as fi
 import oracle as om
-from test_gpu_parity import compare_states, rel_l2
+from test_gpu_parity import alive_by_lineage, by_lineage, compare_states, oracle_to_dict, phys_amp_gpu, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -162,3 +164,70 @@ def test_mixed_grid_256():
         assert evm == ev
         assert e <= 1e-3
         del u
+
+
+@pytest.mark.timeout(900)
+def test_layered_earth_full_size():
+    """The layered Earth workload at its full size: a point moment-tensor
+    source at eps = 1/256 (q 8^3 x 1600 directions x 4 shells x 3 branches x
+    2 directions = 19,660,800 beams) in the 4-shell model with interface
+    splitting (generation cap 3) and 512 surface receivers sampled after
+    every step, for 400 of its 2000 steps in calls of 100 steps as the
+    benchmark runs them (the set grows past 10^8 beams).  The oracle
+    decomposes the full source and evolves the beams of 48 seeded initial
+    lineages with all their descendants; the GPU beams of the same lineages
+    match them (lineage, generation, layer, branch and sigma exactly; states
+    and amplitudes to 1e-10).  The last seismogram sample equals a point sum
+    at the receivers over the final beams."""
+    import torch
+    import paper_1810_06760_amd as m
+    m.lib()
+    e = fi.layered_earth()
+    nsteps, seg = 400, 100
+    say("full size: layered Earth, %d of %d steps" % (nsteps, e["nsteps"]))
+    med_g = m.Medium.layered(1, e["bounds"], e["cp"], e["cs"], e["rho"])
+    kw = dict(nq=e["nq"], ndir=e["ndir"], nshell=e["nshell"])
+    src = m.point_source(e["eps"], e["x0"], e["M"], **kw)
+    ncand = int(m.lib().fga_point_source_candidates(m.C.byref(src)))
+    beams = m.BeamSet(12 * ncand)
+    m.fga_decompose_point_source(med_g, src, beams=beams)
+    n0 = beams.count
+    say("  decomposed", n0)
+    rec = m._dev(e["receivers"], torch.float64)
+    nrec = rec.shape[0]
+    ws = m._workspace(m.workspace_bytes("evolve", beams=beams, nsteps=seg, n_receivers=nrec, eps=e["eps"],
+                                        tau=e["tau"]))
+    seis = torch.empty((nrec, nsteps, 3, 2), dtype=torch.float64, device="cuda")
+    for s0 in range(0, nsteps, seg):
+        part, _ = m.fga_evolve(med_g, beams, e["dt"], seg, receivers=rec, eps=e["eps"], tau=e["tau"], ws=ws)
+        seis[:, s0:s0 + seg].copy_(part)
+        say("  steps", s0 + seg, "beams", beams.count)
+    torch.cuda.synchronize()
+
+    med_o = om.layered(1, e["bounds"], e["cp"], e["cs"], e["rho"])
+    ob_all = om.point_source_beams(med_o, om.point_source(e["eps"], e["x0"], e["M"], **kw))
+    assert len(ob_all) == n0
+    pick = np.sort(np.random.default_rng(4246).choice(len(ob_all), size=48, replace=False))
+    ob = ob_all[pick].copy()
+    del ob_all
+    out, _ = om.evolve_layered(med_o, ob, e["dt"], nsteps, gmax=3, child_cut=1e-3)
+    ref = alive_by_lineage(oracle_to_dict(out))
+    ref = {k: v[np.argsort(ref["lineage"], kind="stable")] for k, v in ref.items()}
+    say("  oracle beams", len(out), "alive", len(ref["lineage"]), "max generation", int(out["gen"].max()))
+    assert int(out["gen"].max()) >= 2, "the sample should include interface children"
+    lin = torch.from_numpy(ref["lineage"].astype(np.int64)).cuda()
+    idx = torch.isin(beams.lineage[:beams.count], lin).nonzero().squeeze(1)
+    g = by_lineage(alive_by_lineage(beams.export(idx)))
+    assert np.array_equal(g["lineage"], ref["lineage"])
+    for k in ("gen", "layer", "branch", "sigma"):
+        assert np.array_equal(g[k], ref[k]), k
+    for k in ("Q", "P", "ZQ", "ZP"):
+        assert rel_l2(g[k], ref[k]) <= RTOL, k
+    keep = out["alive"] == 1
+    A_ref = om.amplitude_vectors(out[keep][np.argsort(out["lineage"][keep], kind="stable")])
+    assert rel_l2(phys_amp_gpu(g), A_ref) <= RTOL
+
+    ur, _ = m.fga_reconstruct_points(beams, e["eps"], e["tau"], e["receivers"])
+    err = rel_l2(m.to_complex(seis[:, -1]), m.to_complex(ur))
+    say("  seismogram vs points", err)
+    assert err <= RTOL
