@@ -246,7 +246,7 @@ typedef struct {
   int compact;             /* 1: compact the beam set after culling (stable order)     */
   int64_t batch;           /* beams per receiver batch (0: library default)            */
   int resort;              /* steps between spatial re-orderings of the beam set
-                              (0: library default, 16 with receivers in grid and
+                              (0: library default, 32 with receivers in grid and
                                homogeneous media, else 64; < 0: never reorder)         */
   int gen_max;             /* layered media: interface generation cap (0: default 3)   */
   double child_cut;        /* layered media: children with |A_child| < child_cut |A_in|

@@ -313,7 +313,7 @@ EvolvePlan evolve_plan(const fga_beams *b, int nsteps, const fga_evolve_opts *o,
   if (p.batch > b->capacity) p.batch = b->capacity > 0 ? b->capacity : 1;
   p.nsamp = r ? nsteps / r->stride : 0;
   p.bpb = r ? points_beams_per_block(p.batch, r->n, (p.chunk + r->stride - 1) / r->stride + 1) : 1024;
-  p.resort = (o && o->resort < 0) ? 0 : ((o && o->resort > 0) ? o->resort : (r ? 16 : 64));
+  p.resort = (o && o->resort < 0) ? 0 : ((o && o->resort > 0) ? o->resort : (r ? 32 : 64));
   if (p.resort > 0 && p.resort < p.chunk) p.resort = p.chunk;
   return p;
 }
