@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered", "mixed"])
     ap.add_argument("--waves", type=int, default=4, help="beam waves of the mixed-precision workload")
     ap.add_argument("--batch", type=int, default=0, help="beams per receiver-sum batch in the evolution (0: library default)")
+    ap.add_argument("--chunk", type=int, default=0, help="RK4 steps per integrator launch (0: library default)")
     ap.add_argument("--resort", type=int, default=0,
                     help="steps between spatial re-sorts of the beams in the evolution (0: library default, <0 never)")
     ap.add_argument("--scale", type=float, default=1.0,
@@ -116,7 +117,7 @@ def gpu_run(w, args):
         if state["ws_ev"] is None:
             state["ws_ev"] = fga._workspace(fga.workspace_bytes(
                 "evolve", beams=beams, nsteps=seg, n_receivers=0 if rec is None else rec.shape[0],
-                eps=w.eps, tau=w.tau, batch=args.batch))
+                eps=w.eps, tau=w.tau, batch=args.batch, chunk=args.chunk))
             if rec is not None:
                 state["seis"] = torch.empty((rec.shape[0], w.nsteps, 3, 2), dtype=torch.float64, device=dev)
         # the evolution in a few calls of `seg` steps (progress lines between)
@@ -124,7 +125,7 @@ def gpu_run(w, args):
         for s0 in range(0, w.nsteps, seg):
             n = min(seg, w.nsteps - s0)
             part, st_k = fga.fga_evolve(med, beams, w.dt, n, receivers=rec, eps=w.eps, tau=w.tau,
-                                        ws=state["ws_ev"], batch=args.batch, resort=args.resort)
+                                        ws=state["ws_ev"], batch=args.batch, resort=args.resort, chunk=args.chunk)
             if rec is not None:
                 state["seis"][:, s0:s0 + n].copy_(part)
             st["beam_steps"] += st_k["beam_steps"]
