@@ -1,8 +1,9 @@
 """Accuracy of the whole FGA pipeline against the exact solution of the
 elastic wave equation (a convergence check of the method, not a parity
 test): homogeneous medium c_P = sqrt(3), c_S = 1, the Gaussian plane-wave
-packet of width 0.1 moving along x with one-way data (only the "+" direction,
-reading A3), decomposed on phase-space meshes fine enough that the FBI frame
+packet of width 0.1 moving along x with one-way data (only the "+" direction
+is made, psi_- = 0, which is the initial velocity -i c_b |D| f on branch b),
+decomposed on phase-space meshes fine enough that the FBI frame
 does not alias (p spacing below 2 pi eps / R, R the window half-width),
 evolved to T = 0.25 and summed on a grid.
 
