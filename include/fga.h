@@ -246,8 +246,9 @@ typedef struct {
   int compact;             /* 1: compact the beam set after culling (stable order)     */
   int64_t batch;           /* beams per receiver batch (0: library default)            */
   int resort;              /* steps between spatial re-orderings of the beam set
-                              (0: library default, 32 with receivers in grid and
-                               homogeneous media, else 64; < 0: never reorder)         */
+                              (0: library default: with receivers in grid and
+                               homogeneous media 32 for sets of 2^23 beams or more,
+                               16 below, else 64; < 0: never reorder)                 */
   int gen_max;             /* layered media: interface generation cap (0: default 3)   */
   double child_cut;        /* layered media: children with |A_child| < child_cut |A_in|
                               are not made (0: default 1e-3; < 0: keep all)            */
