@@ -2,13 +2,13 @@
 //
 // Beam-major layout.  A wavefront owns RW = 4 points and walks a range of
 // beams 64 at a time, one beam per lane, each lane holding its beam's
-// emission record (Q, P 128/(pi eps), B = w e^{iS/eps} A) in registers (fetched one
-// tile ahead) and RW complex 3-vector sums; the four points are evaluated
-// together, four independent exponential chains per lane.  The beam set is
-// kept in Morton order of Q, so the 64 beams of a tile are close together
-// and the window test against one point is (nearly) the same on every lane;
-// a tile whose bounding box lies out of reach of all the wavefront's points
-// is skipped without loading it.  A workgroup covers one sample, 16 points
+// emission record (Q, P 128/(pi eps), B = w e^{iS/eps} A) in registers and
+// RW complex 3-vector sums; of the four points, only those whose window
+// holds some beam of the tile are evaluated.  The beam set is kept in
+// Morton order of Q, so the 64 beams of a tile are close together and the
+// window test against one point is (nearly) the same on every lane; a tile
+// whose bounding box lies out of reach of all the wavefront's points is
+// skipped without loading its records.  A workgroup covers one sample, 16 points
 // (four wavefronts) and one beam range; workgroups sharing a beam range are
 // dealt to one XCD so its records are read from HBM once.  After the beam
 // range the sums are reduced over the lanes in a fixed order and written
