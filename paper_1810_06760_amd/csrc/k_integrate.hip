@@ -181,7 +181,10 @@ __global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs 
         }
       }
 #pragma unroll
-      for (int f = 0; f < NS; ++f) F[f * cap + i] = y[f];
+      // where grad c = 0 the step leaves P and dzP as they were: not stored
+#pragma unroll
+      for (int f = 0; f < NS; ++f)
+        if (MK == MK_GRID || !((f >= IP && f < IP + 3) || (f >= IZPR && f < IZPR + 18))) F[f * cap + i] = y[f];
 #pragma unroll
       for (int d = 0; d < 3; ++d) F[(FGA_E + d) * cap + i] = e[d];
       a.i32[FGA_FLAGS * cap + i] = flags;
