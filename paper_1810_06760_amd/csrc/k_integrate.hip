@@ -64,7 +64,7 @@ __device__ __forceinline__ void emit_dead(double *__restrict__ out, int64_t nb, 
 }
 
 template <int MK>
-__global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs a)
+__device__ __forceinline__ void integrate_body(const DevMedium &med, const IntegrateArgs &a)
 {
   const int64_t i = a.beg + (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool active = i < a.end;
@@ -180,7 +180,6 @@ __global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs 
           culled = 1;
         }
       }
-#pragma unroll
       // where grad c = 0 the step leaves P and dzP as they were: not stored
 #pragma unroll
       for (int f = 0; f < NS; ++f)
@@ -193,6 +192,134 @@ __global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs 
   }
 done:
   // wavefront-level reduction of the counters, one atomic per wavefront
+  for (int off = 32; off > 0; off >>= 1) {
+    steps_done += __shfl_down(steps_done, off);
+    culled += __shfl_down(culled, off);
+    quar += __shfl_down(quar, off);
+  }
+  if ((threadIdx.x & 63) == 0 && a.counters) {
+    if (steps_done) atomicAdd(a.counters + 0, steps_done);
+    if (culled) atomicAdd(a.counters + 1, culled);
+    if (quar) atomicAdd(a.counters + 2, quar);
+  }
+}
+
+template <int MK>
+__global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs a)
+{
+  integrate_body<MK>(med, a);
+}
+
+// One step of every beam in a layered medium, the interface step's cadence
+// (no emission).  The same arithmetic as the general kernel with
+// rk4_step_pc, ordered so that little stays live: the ray (Q, S) advances
+// first and a beam leaving its layer stops there, flagged, with its stored
+// state untouched; otherwise Q, S and dzQ are stored as soon as they are
+// formed, dzP enters only through Z0 = dzQ + i dzP and K = d(dzQ)/dt, and P
+// and dzP are not stored (unchanged by the step).  That fits two wavefronts
+// per SIMD, so one wavefront's loads overlap another's arithmetic.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_layered(DevMedium med,
+                                                                                                 IntegrateArgs a)
+{
+  const int64_t i = a.beg + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long steps_done = 0, culled = 0, quar = 0;
+  if (i < a.end) {
+    const int64_t cap = a.cap;
+    double *__restrict__ F = a.f64;
+    int32_t flags = a.i32[FGA_FLAGS * cap + i];
+    const int br = a.i32[FGA_BRANCH * cap + i];
+    const int sgi = a.i32[FGA_SIGMA * cap + i];
+    const int layer = a.i32[FGA_LAYER * cap + i];
+    if (flags & FGA_FLAG_ALIVE) {
+      steps_done = 1;
+      const double sg = (double)sgi;
+      const bool isS = br != 0;
+      const double dt = a.dt, h6 = dt / 6.0;
+      // all of the state, and the layer's speed and bounding interfaces, are
+      // requested at once (one memory latency per beam)
+      const double c = isS ? med.csl[layer] : med.cpl[layer];
+      const double b_in = med.bound[layer], b_out = med.bound[layer > 0 ? layer - 1 : 0];
+      double Q[3], P[3], e[3], A[4], qr[9], qi[9], pr[9], pi[9];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        Q[d] = F[(FGA_Q + d) * cap + i];
+        P[d] = F[(FGA_P + d) * cap + i];
+      }
+      const double S = F[FGA_S * cap + i];
+#pragma unroll
+      for (int o = 0; o < 9; ++o) {
+        qr[o] = F[(FGA_ZQ_RE + o) * cap + i];
+        qi[o] = F[(FGA_ZQ_IM + o) * cap + i];
+        pr[o] = F[(FGA_ZP_RE + o) * cap + i];
+        pi[o] = F[(FGA_ZP_IM + o) * cap + i];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A[t] = F[(FGA_A0_RE + t) * cap + i];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) e[d] = F[(FGA_E + d) * cap + i];
+      double kQ[3], kS, ph[3], ci;
+      pc_ray_rates(c, sg, P, kQ, kS, ph, ci);
+      double Qn[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Qn[d] = rk4_const(Q[d], kQ[d], h6);
+      // the test of layer_exit: interface `layer` below (flat) or inside
+      // (spherical), interface layer - 1 above or outside
+      const bool in_ok = layer < med.nlayer - 1, out_ok = layer > 0;
+      bool crossed;
+      if (med.geometry == 1) {
+        const double r = sqrt(Qn[0] * Qn[0] + Qn[1] * Qn[1] + Qn[2] * Qn[2]);
+        crossed = (in_ok && r < b_in) || (out_ok && r > b_out);
+      } else {
+        crossed = (in_ok && Qn[2] > b_in) || (out_ok && Qn[2] < b_out);
+      }
+      if (crossed) {
+        // the interface step redoes this step from the stored state
+        a.i32[FGA_FLAGS * cap + i] = flags | FGA_FLAG_CROSS;
+      } else {
+        const double Sn = rk4_const(S, kS, h6);
+        bool finite = isfinite(Sn) && isfinite(P[0]) && isfinite(P[1]) && isfinite(P[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          F[(FGA_Q + d) * cap + i] = Qn[d];
+          finite = finite && isfinite(Qn[d]);
+        }
+        F[FGA_S * cap + i] = Sn;
+        double kr[9], ki[9], z0r[9], z0i[9];
+        pc_jac_rates(ph, ci, pr, pi, kr, ki);
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+          z0r[o] = qr[o] - pi[o];
+          z0i[o] = qi[o] + pr[o];
+          const double nr = rk4_const(qr[o], kr[o], h6), ni = rk4_const(qi[o], ki[o], h6);
+          F[(FGA_ZQ_RE + o) * cap + i] = nr;
+          F[(FGA_ZQ_IM + o) * cap + i] = ni;
+          finite = finite && isfinite(nr) && isfinite(ni) && isfinite(pr[o]) && isfinite(pi[o]);
+        }
+        pc_amplitude(z0r, z0i, kr, ki, isS, A, dt);
+        if (isS) reframe_s(P, A, e);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) finite = finite && isfinite(A[t]);
+        if (!finite) {
+          flags = FGA_FLAG_QUARANTINED;
+          quar = 1;
+        } else if (a.cutoff_abs > 0.0) {
+          const double wr = F[FGA_W_RE * cap + i], wi = F[FGA_W_IM * cap + i];
+          const double m0 = A[0] * A[0] + A[1] * A[1];
+          const double m1 = A[2] * A[2] + A[3] * A[3];
+          const double amax = sqrt(m0 > m1 ? m0 : m1);
+          if (sqrt(wr * wr + wi * wi) * amax < a.cutoff_abs) {
+            flags = 0;
+            culled = 1;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) F[(FGA_A0_RE + t) * cap + i] = A[t];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[(FGA_E + d) * cap + i] = e[d];
+        a.i32[FGA_FLAGS * cap + i] = flags;
+      }
+    }
+  }
   for (int off = 32; off > 0; off >>= 1) {
     steps_done += __shfl_down(steps_done, off);
     culled += __shfl_down(culled, off);
@@ -232,7 +359,10 @@ hipError_t launch_integrate(const DevMedium &m, const IntegrateArgs &a, hipStrea
   switch (m.kind) {
   case FGA_MEDIUM_HOMOGENEOUS: hipLaunchKernelGGL(k_integrate<MK_HOMOG>, blocks, 256, 0, st, m, a); break;
   case FGA_MEDIUM_GRID: hipLaunchKernelGGL(k_integrate<MK_GRID>, blocks, 256, 0, st, m, a); break;
-  default: hipLaunchKernelGGL(k_integrate<MK_LAYERED>, blocks, 256, 0, st, m, a); break;
+  default:
+    if (a.nsteps == 1 && a.stride == 0) hipLaunchKernelGGL(k_step_layered, blocks, 256, 0, st, m, a);
+    else hipLaunchKernelGGL(k_integrate<MK_LAYERED>, blocks, 256, 0, st, m, a);
+    break;
   }
   return hipGetLastError();
 }

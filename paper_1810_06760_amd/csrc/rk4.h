@@ -150,30 +150,32 @@ __device__ __forceinline__ void stage(const DevMedium &med, int sp, int layer, d
 // After a step: an S beam whose P has come within 10 degrees of its frame
 // axis switches axis (e_z <-> e_x) and re-expresses (a_SV, a_SH) so that the
 // physical polarisation a_SV N_SV + a_SH N_SH is unchanged.
-__device__ __forceinline__ void reframe_s(double *y, double e[3])
+__device__ __forceinline__ void reframe_s(const double P[3], double A[4], double e[3])
 {
-  const double np = sqrt(y[IP] * y[IP] + y[IP + 1] * y[IP + 1] + y[IP + 2] * y[IP + 2]);
-  const double pe = y[IP] * e[0] + y[IP + 1] * e[1] + y[IP + 2] * e[2];
+  const double np = sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+  const double pe = P[0] * e[0] + P[1] * e[1] + P[2] * e[2];
   if (fabs(pe) / np > COS10) {
     double nsh[3], nsv[3];
-    s_frame(y + IP, e, nsh, nsv);
+    s_frame(P, e, nsh, nsv);
     double Ar[3], Ai[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      Ar[c] = y[IA] * nsv[c] + y[IA + 2] * nsh[c];
-      Ai[c] = y[IA + 1] * nsv[c] + y[IA + 3] * nsh[c];
+      Ar[c] = A[0] * nsv[c] + A[2] * nsh[c];
+      Ai[c] = A[1] * nsv[c] + A[3] * nsh[c];
     }
     const bool was_z = e[2] != 0.0 && e[0] == 0.0 && e[1] == 0.0;
     e[0] = was_z ? 1.0 : 0.0;
     e[1] = 0.0;
     e[2] = was_z ? 0.0 : 1.0;
-    s_frame(y + IP, e, nsh, nsv);
-    y[IA] = Ar[0] * nsv[0] + Ar[1] * nsv[1] + Ar[2] * nsv[2];
-    y[IA + 1] = Ai[0] * nsv[0] + Ai[1] * nsv[1] + Ai[2] * nsv[2];
-    y[IA + 2] = Ar[0] * nsh[0] + Ar[1] * nsh[1] + Ar[2] * nsh[2];
-    y[IA + 3] = Ai[0] * nsh[0] + Ai[1] * nsh[1] + Ai[2] * nsh[2];
+    s_frame(P, e, nsh, nsv);
+    A[0] = Ar[0] * nsv[0] + Ar[1] * nsv[1] + Ar[2] * nsv[2];
+    A[1] = Ai[0] * nsv[0] + Ai[1] * nsv[1] + Ai[2] * nsv[2];
+    A[2] = Ar[0] * nsh[0] + Ar[1] * nsh[1] + Ar[2] * nsh[2];
+    A[3] = Ai[0] * nsh[0] + Ai[1] * nsh[1] + Ai[2] * nsh[2];
   }
 }
+
+__device__ __forceinline__ void reframe_s(double *y, double e[3]) { reframe_s(y + IP, y + IA, e); }
 
 // One classic RK4 step of size dt in place, y' = y + dt/6 (k1 + 2 k2 + 2 k3 + k4);
 // the four stages run as a loop so that only y, acc and the stage input stay live.
@@ -195,61 +197,78 @@ __device__ __forceinline__ void rk4_step(const DevMedium &med, int sp, int layer
   for (int f = 0; f < NS; ++f) y[f] += h6 * acc[f];
 }
 
-// The same classic RK4 step where grad c = 0 (a homogeneous medium, or
-// inside one layer of a layered medium).  There P and dzP have zero
+// The pieces of the classic RK4 step where grad c = 0 (a homogeneous medium,
+// or inside one layer of a layered medium).  There P and dzP have zero
 // derivative and Q, dzQ and S constant ones, so every stage's derivative of
-// those equals the first and the stage inputs y + c k are formed from it
-// directly; only the amplitudes' derivative depends on the stage (through
-// Z = dzQ + i dzP at the stage input, in tr(Z^{-1} dZ/dt)).  The stage
-// formulas, weights and summation order are those of rk4_step with the
-// medium's gradient and Hessian at zero (omega = 0 for S beams), so the two
-// agree to rounding, with about half the live registers and work.
-template <int MK>
-__device__ __forceinline__ void rk4_step_pc(const DevMedium &med, int sp, int layer, double sg, bool isS, double *y,
-                                            double dt)
+// those equals the first; only the amplitudes' derivative depends on the
+// stage, through Z = dzQ + i dzP at the stage input in tr(Z^{-1} dZ/dt).
+// Since dzP is fixed, Z at a stage input is Z0 + c K with Z0 = Z at the step's
+// start and K = d(dzQ)/dt.  The stage formulas, weights and summation order
+// are those of rk4_step with the medium's gradient and Hessian at zero
+// (omega = 0 for S beams), so the two agree to rounding.
+
+// y0 + dt/6 (k + 2k + 2k + k) for a derivative equal in all four stages,
+// summed in rk4_step's order.
+__device__ __forceinline__ double rk4_const(double y0, double k, double h6)
 {
-  double c, g[3], H6[6];
-  medium_eval<MK>(med, sp, layer, y + IQ, c, g, H6);
-  const double P0 = y[IP], P1 = y[IP + 1], P2 = y[IP + 2];
-  const double np = sqrt(P0 * P0 + P1 * P1 + P2 * P2);
+  return y0 + h6 * (((k + 2.0 * k) + 2.0 * k) + k);
+}
+
+// dQ/dt and dS/dt for speed c (eq:char_plus, eq:char_minus); also P/|P| and
+// sigma c / |P| for the Jacobian rates.
+__device__ __forceinline__ void pc_ray_rates(double c, double sg, const double P[3], double kQ[3], double &kS,
+                                             double ph[3], double &ci)
+{
+  const double np = sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
   const double inp = 1.0 / np;
-  const double ph[3] = {P0 * inp, P1 * inp, P2 * inp};
+  ph[0] = P[0] * inp;
+  ph[1] = P[1] * inp;
+  ph[2] = P[2] * inp;
   const double sc = sg * c;
-  const double ci = sc * inp;
-  // the constant derivatives: dQ/dt, d(dzQ)/dt (re, im), dS/dt
-  double kQ[3], kr[9], ki[9];
+  ci = sc * inp;
 #pragma unroll
   for (int j = 0; j < 3; ++j) kQ[j] = sc * ph[j];
+  kS = P[0] * kQ[0] + P[1] * kQ[1] + P[2] * kQ[2] - sc * np;
+}
+
+// d(dzQ)/dt = sigma c dzP (I - P (x) P/|P|^2)/|P| (eq:DzDt with grad c = 0),
+// rows m, real and imaginary parts; dzr/dzi are dzP's.
+__device__ __forceinline__ void pc_jac_rates(const double ph[3], double ci, const double dzr[9],
+                                             const double dzi[9], double kr[9], double ki[9])
+{
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    const double vr = y[IZPR + 3 * m] * ph[0] + y[IZPR + 3 * m + 1] * ph[1] + y[IZPR + 3 * m + 2] * ph[2];
-    const double vi = y[IZPI + 3 * m] * ph[0] + y[IZPI + 3 * m + 1] * ph[1] + y[IZPI + 3 * m + 2] * ph[2];
+    const double vr = dzr[3 * m] * ph[0] + dzr[3 * m + 1] * ph[1] + dzr[3 * m + 2] * ph[2];
+    const double vi = dzi[3 * m] * ph[0] + dzi[3 * m + 1] * ph[1] + dzi[3 * m + 2] * ph[2];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      kr[3 * m + j] = ci * (y[IZPR + 3 * m + j] - vr * ph[j]);
-      ki[3 * m + j] = ci * (y[IZPI + 3 * m + j] - vi * ph[j]);
+      kr[3 * m + j] = ci * (dzr[3 * m + j] - vr * ph[j]);
+      ki[3 * m + j] = ci * (dzi[3 * m + j] - vi * ph[j]);
     }
   }
-  const double kS = P0 * kQ[0] + P1 * kQ[1] + P2 * kQ[2] - sc * np;
+}
 
+// The four stages of the amplitudes (eq:amp_P, eq:amp_SV, eq:amp_SH with
+// grad c = 0: da/dt = a tr(Z^{-1} dZ/dt)/2), a[4] = (re, im) of a_P or of
+// (a_SV, a_SH), advanced in place.
+__device__ __forceinline__ void pc_amplitude(const double z0r[9], const double z0i[9], const double kr[9],
+                                             const double ki[9], bool isS, double a0[4], double dt)
+{
   const double h2 = 0.5 * dt, h6 = dt / 6.0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  double a[4] = {y[IA], y[IA + 1], y[IA + 2], y[IA + 3]};  // amplitude stage input
+  double a[4] = {a0[0], a0[1], a0[2], a0[3]};  // stage input
 #pragma nounroll
   for (int st = 0; st < 4; ++st) {
-    const double cs = st == 0 ? 0.0 : (st == 3 ? dt : h2);  // this stage's input: y + cs k
+    const double cs = st == 0 ? 0.0 : (st == 3 ? dt : h2);  // this stage's input: Z0 + cs K
     const double wacc = (st == 0 || st == 3) ? 1.0 : 2.0;
     const double cnext = st == 2 ? dt : (st == 3 ? 0.0 : h2);
-    // Z at the stage input, Z = dzQ + i dzP
     double zr[9], zi[9];
 #pragma unroll
     for (int o = 0; o < 9; ++o) {
-      const double qr = st == 0 ? y[IZQR + o] : y[IZQR + o] + cs * kr[o];
-      const double qi = st == 0 ? y[IZQI + o] : y[IZQI + o] + cs * ki[o];
-      zr[o] = qr - y[IZPI + o];
-      zi[o] = qi + y[IZPR + o];
+      zr[o] = z0r[o] + cs * kr[o];
+      zi[o] = z0i[o] + cs * ki[o];
     }
-    // cofactors (cyclic index form), det Z and T = cof(Z) : dZ/dt, dZ/dt = d(dzQ)/dt
+    // cofactors (cyclic index form), det Z and T = cof(Z) : dZ/dt, dZ/dt = K
     double detr = 0.0, deti = 0.0, Tr = 0.0, Ti = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -279,20 +298,38 @@ __device__ __forceinline__ void rk4_step_pc(const DevMedium &med, int sp, int la
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       acc[t] += wacc * ka[t];
-      a[t] = y[IA + t] + cnext * ka[t];
+      a[t] = a0[t] + cnext * ka[t];
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) y[IA + t] += h6 * acc[t];
-  // k1 + 2 k2 + 2 k3 + k4 with equal stages, summed in rk4_step's order
-#pragma unroll
-  for (int j = 0; j < 3; ++j) y[IQ + j] += h6 * (((kQ[j] + 2.0 * kQ[j]) + 2.0 * kQ[j]) + kQ[j]);
+  for (int t = 0; t < 4; ++t) a0[t] += h6 * acc[t];
+}
+
+// One classic RK4 step of the whole state y where grad c = 0, in place.
+template <int MK>
+__device__ __forceinline__ void rk4_step_pc(const DevMedium &med, int sp, int layer, double sg, bool isS, double *y,
+                                            double dt)
+{
+  double c, g[3], H6[6];
+  medium_eval<MK>(med, sp, layer, y + IQ, c, g, H6);
+  double kQ[3], kS, ph[3], ci, kr[9], ki[9], z0r[9], z0i[9];
+  pc_ray_rates(c, sg, y + IP, kQ, kS, ph, ci);
+  pc_jac_rates(ph, ci, y + IZPR, y + IZPI, kr, ki);
 #pragma unroll
   for (int o = 0; o < 9; ++o) {
-    y[IZQR + o] += h6 * (((kr[o] + 2.0 * kr[o]) + 2.0 * kr[o]) + kr[o]);
-    y[IZQI + o] += h6 * (((ki[o] + 2.0 * ki[o]) + 2.0 * ki[o]) + ki[o]);
+    z0r[o] = y[IZQR + o] - y[IZPI + o];
+    z0i[o] = y[IZQI + o] + y[IZPR + o];
   }
-  y[IS] += h6 * (((kS + 2.0 * kS) + 2.0 * kS) + kS);
+  pc_amplitude(z0r, z0i, kr, ki, isS, y + IA, dt);
+  const double h6 = dt / 6.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) y[IQ + j] = rk4_const(y[IQ + j], kQ[j], h6);
+#pragma unroll
+  for (int o = 0; o < 9; ++o) {
+    y[IZQR + o] = rk4_const(y[IZQR + o], kr[o], h6);
+    y[IZQI + o] = rk4_const(y[IZQI + o], ki[o], h6);
+  }
+  y[IS] = rk4_const(y[IS], kS, h6);
 }
 
 }  // namespace rk
