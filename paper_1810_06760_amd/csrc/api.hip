@@ -488,7 +488,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
         if (nb == 0) FGA_HIP(launch_reduce_points(partial, 0, 1, rec->n, wb.perm, seis, p.nsamp, sample, 0, st));
         for (int64_t b0 = 0; b0 < nb; b0 += p.batch) {
           const int64_t b1 = b0 + p.batch < nb ? b0 + p.batch : nb;
-          FGA_HIP(launch_emit(beams->f64, beams->i32, beams->capacity, b0, b1, rec->eps, emit, st));
+          FGA_HIP(launch_emit(beams->f64, beams->i32, beams->capacity, b0, b1, rec->eps, emit, wb.box, st));
           PointsArgs pa{};
           pa.emit = emit;
           pa.nb = b1 - b0;
@@ -502,6 +502,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
           pa.evals = ctr + 3;
           pa.tile_box = wb.box;
           pa.ntiles = (pa.nb + 63) / 64;
+          pa.boxes_ready = 1;
           pa.precision = rec->precision;
           int nblk = 0;
           FGA_HIP(launch_sum_points(pa, &nblk, st));
@@ -634,7 +635,7 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
   if (nb == 0) FGA_HIP(launch_reduce_points(partial, 0, 1, n, nullptr, out, 1, 0, 0, st));
   for (int64_t b0 = 0; b0 < nb; b0 += batch) {
     const int64_t b1 = b0 + batch < nb ? b0 + batch : nb;
-    FGA_HIP(launch_emit(beams->f64, beams->i32, beams->capacity, b0, b1, eps, emit, st));
+    FGA_HIP(launch_emit(beams->f64, beams->i32, beams->capacity, b0, b1, eps, emit, box, st));
     PointsArgs pa{};
     pa.emit = emit;
     pa.nb = b1 - b0;
@@ -648,6 +649,7 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
     pa.evals = ctr;
     pa.tile_box = box;
     pa.ntiles = (pa.nb + 63) / 64;
+    pa.boxes_ready = 1;
     pa.precision = precision;
     int nblk = 0;
     FGA_HIP(launch_sum_points(pa, &nblk, st));

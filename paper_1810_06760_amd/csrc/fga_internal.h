@@ -111,6 +111,7 @@ struct PointsArgs {
   unsigned long long *evals;
   double *tile_box;          // scratch [m][ntiles][6], ntiles = ceil(nb / 64)
   int64_t ntiles;
+  int boxes_ready;           // tile_box already holds the boxes (written with the records)
   int precision;             // FGA_FP64, or FGA_FP32: FP32 exp/sin/cos of FP64-reduced arguments
 };
 hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st);
@@ -126,8 +127,9 @@ hipError_t launch_reduce_points(const double *partial, int nblk, int m, int64_t 
 fga_status sort_points(const double *xyz, int64_t n, double *xyz_sorted, int32_t *perm, hipStream_t st);
 
 // beams -> emission records (current state, one sample)
+// box (may be NULL): also the tile boxes of the records, [ceil((end - beg) / 64)][6]
 hipError_t launch_emit(const double *f64, const int32_t *i32, int64_t cap, int64_t beg, int64_t end,
-                       double eps, double *emit, hipStream_t st);
+                       double eps, double *emit, double *box, hipStream_t st);
 
 // decomposition
 struct DecompArgs {

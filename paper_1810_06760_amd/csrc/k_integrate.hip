@@ -4,9 +4,10 @@
 // planes (coalesced), advances it by `nsteps` classic RK4 steps held entirely
 // in registers, optionally writes an emission record (Q, P, w e^{iS/eps} A)
 // after every sample step for the receiver summation, and stores the state
-// back (the right-hand side and the RK4 step are in rk4.h).  In layered media
-// a beam whose centre leaves its layer during a step keeps its stored state
-// and is flagged for the interface step.
+// back (the right-hand side and the RK4 step are in rk4.h).  Layered media
+// have a one-step kernel of their own (k_step_layered): there a beam whose
+// centre leaves its layer during the step keeps its stored state and is
+// flagged for the interface step.
 #include "fastmath.h"
 #include "rk4.h"
 
@@ -141,29 +142,15 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
       const double wr = F[FGA_W_RE * cap + i], wi = F[FGA_W_IM * cap + i];
       const double dt = a.dt;
       const double ieps = 1.0 / a.eps_emit;
-      bool crossed = false;
       for (int s = 0; s < a.nsteps; ++s) {
         if constexpr (MK == MK_GRID) rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt, &blk);
         else rk4_step_pc<MK>(med, sp, layer, sg, isS, y, dt);  // grad c = 0
-        if constexpr (MK == MK_LAYERED) {
-          // left the layer: the interface step redoes this step from the
-          // stored state, which is therefore not overwritten
-          int iface, newL;
-          if (layer_exit(med, layer, y + IQ, iface, newL)) {
-            crossed = true;
-            break;
-          }
-        }
         if (isS) reframe_s(y, e);
         if (a.stride && (a.step0 + s + 1) % a.stride == 0)
           emit_record(a.emit + (int64_t)((a.step0 + s + 1) / a.stride - 1 - first_emit) * 12 * nb, nb, j,
                       y, e, wr, wi, isS, ieps);
       }
       steps_done = (unsigned long long)a.nsteps;
-      if (crossed) {
-        a.i32[FGA_FLAGS * cap + i] = flags | FGA_FLAG_CROSS;
-        goto done;
-      }
       {
       bool finite = true;
 #pragma unroll
@@ -190,7 +177,6 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
       }
     }
   }
-done:
   // wavefront-level reduction of the counters, one atomic per wavefront
   for (int off = 32; off > 0; off >>= 1) {
     steps_done += __shfl_down(steps_done, off);
@@ -332,20 +318,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
-// Emission records of the current state (no stepping), e.g. for t = 0 samples.
+// Emission records of the current state (no stepping), e.g. for t = 0
+// samples.  With box: each wavefront is one 64-beam tile of the records and
+// also writes that tile's bounding box of the live centres Q (lo[3], hi[3];
+// +inf / -inf when no beam of the tile is live), as k_tile_box would from
+// the records.
 __global__ __launch_bounds__(256) void k_emit(const double *__restrict__ F, const int32_t *__restrict__ I,
                                               int64_t cap, int64_t beg, int64_t end, double ieps,
-                                              double *__restrict__ out)
+                                              double *__restrict__ out, double *__restrict__ box)
 {
   const int64_t i = beg + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= end) return;
   const int64_t nb = end - beg, j = i - beg;
-  if (!(I[FGA_FLAGS * cap + i] & FGA_FLAG_ALIVE)) { emit_dead(out, nb, j); return; }
-  double y[NS];
+  double q[3] = {-1.0e300, -1.0e300, -1.0e300};  // dead beams and the ragged tail
+  if (i < end) {
+    if (!(I[FGA_FLAGS * cap + i] & FGA_FLAG_ALIVE)) {
+      emit_dead(out, nb, j);
+    } else {
+      double y[NS];
 #pragma unroll
-  for (int f = 0; f < NS; ++f) y[f] = F[f * cap + i];
-  const double e[3] = {F[(FGA_E + 0) * cap + i], F[(FGA_E + 1) * cap + i], F[(FGA_E + 2) * cap + i]};
-  emit_record(out, nb, j, y, e, F[FGA_W_RE * cap + i], F[FGA_W_IM * cap + i], I[FGA_BRANCH * cap + i] != 0, ieps);
+      for (int f = 0; f < NS; ++f) y[f] = F[f * cap + i];
+      const double e[3] = {F[(FGA_E + 0) * cap + i], F[(FGA_E + 1) * cap + i], F[(FGA_E + 2) * cap + i]};
+      emit_record(out, nb, j, y, e, F[FGA_W_RE * cap + i], F[FGA_W_IM * cap + i], I[FGA_BRANCH * cap + i] != 0,
+                  ieps);
+      q[0] = y[IQ];
+      q[1] = y[IQ + 1];
+      q[2] = y[IQ + 2];
+    }
+  }
+  if (box) {
+    const int lane = threadIdx.x & 63;
+    double lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const bool dead = !(q[d] > -1.0e299);
+      lo[d] = dead ? INFINITY : q[d];
+      hi[d] = dead ? -INFINITY : q[d];
+      for (int off = 32; off > 0; off >>= 1) {
+        lo[d] = fmin(lo[d], __shfl_xor(lo[d], off));
+        hi[d] = fmax(hi[d], __shfl_xor(hi[d], off));
+      }
+    }
+    const int64_t t = (j - lane) >> 6;  // this wavefront's tile
+    if (lane < 6 && t * 64 < nb) {
+      double v = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (lane == d) v = lo[d];
+        if (lane == 3 + d) v = hi[d];
+      }
+      box[t * 6 + lane] = v;
+    }
+  }
 }
 
 }  // namespace
@@ -360,19 +383,21 @@ hipError_t launch_integrate(const DevMedium &m, const IntegrateArgs &a, hipStrea
   case FGA_MEDIUM_HOMOGENEOUS: hipLaunchKernelGGL(k_integrate<MK_HOMOG>, blocks, 256, 0, st, m, a); break;
   case FGA_MEDIUM_GRID: hipLaunchKernelGGL(k_integrate<MK_GRID>, blocks, 256, 0, st, m, a); break;
   default:
-    if (a.nsteps == 1 && a.stride == 0) hipLaunchKernelGGL(k_step_layered, blocks, 256, 0, st, m, a);
-    else hipLaunchKernelGGL(k_integrate<MK_LAYERED>, blocks, 256, 0, st, m, a);
+    // layered media advance one step per launch, the interface step between
+    if (a.nsteps != 1 || a.stride != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_layered, blocks, 256, 0, st, m, a);
     break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_emit(const double *f64, const int32_t *i32, int64_t cap, int64_t beg, int64_t end,
-                       double eps, double *emit, hipStream_t st)
+                       double eps, double *emit, double *box, hipStream_t st)
 {
   const int64_t n = end - beg;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_emit, (unsigned)((n + 255) / 256), 256, 0, st, f64, i32, cap, beg, end, 1.0 / eps, emit);
+  hipLaunchKernelGGL(k_emit, (unsigned)((n + 255) / 256), 256, 0, st, f64, i32, cap, beg, end, 1.0 / eps, emit,
+                     box);
   return hipGetLastError();
 }
 

@@ -317,10 +317,12 @@ hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st)
   if (a.m > 65535) return hipErrorInvalidConfiguration;
   const int64_t ntiles = (a.nb + 63) / 64;
   if (ntiles != a.ntiles) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tile_box, dim3((unsigned)((ntiles + 3) / 4), (unsigned)a.m), 256, 0, st, a.emit, a.nb, ntiles,
-                     a.tile_box);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (!a.boxes_ready) {
+    hipLaunchKernelGGL(k_tile_box, dim3((unsigned)((ntiles + 3) / 4), (unsigned)a.m), 256, 0, st, a.emit, a.nb,
+                       ntiles, a.tile_box);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const int groups = (int)((a.n + PG - 1) / PG);
   const int64_t units = (nblk * a.m + 7) / 8 * 8;
   const int64_t nwg = units * groups;
