@@ -41,7 +41,7 @@ HBM_PEAK = 8.0e12
 # HBM bytes per launch of a kernel on the default workload (smooth, scale 1), from rocprofv3
 # FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy calibration; valid only while the kernel's
 # source is unchanged (sha256 prefix), else reported as null
-TRAFFIC = {"sum_points": {"source": "paper_1810_06760_amd/csrc/k_points.hip", "sha256": "3d24b35a3d8c0f98",
+TRAFFIC = {"sum_points": {"source": "paper_1810_06760_amd/csrc/k_points.hip", "sha256": "59bdb0187dd2497e",
                           "bytes_per_launch": 2.0397e+10}}
 
 
