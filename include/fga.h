@@ -244,7 +244,9 @@ typedef struct {
   int chunk;               /* RK4 steps per integrator launch (0: library default)     */
   double cutoff_abs;       /* drop beams with |w| max(|a0|,|a1|) < cutoff_abs (0: off)  */
   int compact;             /* 1: compact the beam set after culling (stable order)     */
-  int64_t batch;           /* beams per receiver batch (0: library default)            */
+  int64_t batch;           /* beams per receiver batch (0: library default 2^22); in
+                              layered media, which sum one sample per step, a batch
+                              holds (chunk + stride - 1) / stride + 1 times as many  */
   int resort;              /* steps between spatial re-orderings of the beam set
                               (0: library default: with receivers in grid and
                                homogeneous media 32 for sets of 2^23 beams or more,

@@ -486,8 +486,12 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
         const int sample = (s0 + 1) / rec->stride - 1;
         const int64_t nb = beams->count;
         if (nb == 0) FGA_HIP(launch_reduce_points(partial, 0, 1, rec->n, wb.perm, seis, p.nsamp, sample, 0, st));
-        for (int64_t b0 = 0; b0 < nb; b0 += p.batch) {
-          const int64_t b1 = b0 + p.batch < nb ? b0 + p.batch : nb;
+        // one sample per step here: the records, boxes and partials laid out
+        // for m samples of p.batch beams hold one sample of m * p.batch beams
+        // (with the same beams per workgroup, which depends on beams x samples)
+        const int64_t lbatch = p.batch * (int64_t)((p.chunk + rec->stride - 1) / rec->stride + 1);
+        for (int64_t b0 = 0; b0 < nb; b0 += lbatch) {
+          const int64_t b1 = b0 + lbatch < nb ? b0 + lbatch : nb;
           FGA_HIP(launch_emit(beams->f64, beams->i32, beams->capacity, b0, b1, rec->eps, emit, wb.box, st));
           PointsArgs pa{};
           pa.emit = emit;

@@ -436,16 +436,20 @@ def test_interface_parity(name):
     assert rel_l2(phys_amp_gpu(g), A_ref) <= RTOL
 
 
-def test_interface_seismogram_parity():
-    """Receiver sums during a layered run, children included."""
+@pytest.mark.parametrize("batch", [0, 100])
+def test_interface_seismogram_parity(batch):
+    """Receiver sums during a layered run, children included; batch 100 splits
+    each step's sum over several ragged beam batches (a layered run sums
+    (chunk + stride - 1) / stride + 1 = 7 times the batch at once here)."""
     m = fga()
-    say("interface seismograms")
+    say("interface seismograms, batch %d" % batch)
     w, ob, med_o, med_g = layered_case("flat")
     rec = fi.uniform_points(9, np.random.default_rng(9), 0.2, 0.8)
     nsteps, dt, tau, stride = 30, 0.005, 25.0, 3
     bs = m.BeamSet(4 * len(ob))
     bs.load(oracle_to_dict(ob))
-    seis, st = m.fga_evolve(med_g, bs, dt, nsteps, receivers=rec, eps=w.eps, tau=tau, stride=stride)
+    seis, st = m.fga_evolve(med_g, bs, dt, nsteps, receivers=rec, eps=w.eps, tau=tau, stride=stride, batch=batch)
+    say("beams %d -> %d" % (len(ob), bs.count))
     ref = np.zeros((len(rec), nsteps // stride, 3), dtype=np.complex128)
     cnt = 0
     cur = ob.copy()
