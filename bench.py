@@ -1,16 +1,22 @@
 #!/usr/bin/env python
 """Benchmark of the FGA hot path on one MI355X.
 
-One step = the whole hot path over one batch of synthetic input:
-  decompose (FBI weights of the initial packet on the 32^3 q x 8^3 p mesh,
-  3 branches) -> evolve (1,000 FP64 RK4 steps of every beam in the smooth
-  random medium, with 3-component seismograms at 256 receivers after every
-  step) -> reconstruct (wavefield at T = 1 on the 128^3 grid, FP64 tile GEMMs
-  on the matrix cores).
-Inputs (medium table, initial data, receivers) are resident in HBM before the
-timed region.  Prints one JSON line.
+Default workload: the smooth random medium (cp = sqrt3 (1 + 0.2 g) on a 128^3
+node grid), eps = 1/128, the Gaussian packet decomposed on the 32^3 q x 8^3 p
+mesh with 3 branches (49,095,784 beams after the cull), RK4 with dt = 1e-3 to
+T = 1 and 3-component seismograms at 256 receivers after every step, the
+wavefield on the 128^3 grid.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload smooth|homogeneous] [--scale S]
+One bench step = one FP64 RK4 time step of the whole beam set together with
+its seismogram sample at the 256 receivers (integrator + receiver sums, the
+library's chunked launches).  The beams are decomposed and advanced untimed to
+the window (t = 0.5 by default: --window is the fraction of the horizon), W
+warm-up steps follow, then K steps are timed with inputs resident in HBM.
+Decompose and the 128^3 grid sum (at the window's end) are one-time per
+solve and are timed on their own (decompose_s, grid_s).  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload smooth|homogeneous|layered|mixed]
+                  [--scale S] [--serve ...]
 """
 from __future__ import annotations
 
@@ -26,30 +32,36 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 operations per unit of algorithmic work, counted in the gfx950 code (FMA = 2):
-#   one RK4 beam-step (4 right-hand sides + the update), per medium kind,
-#   one receiver/point term (window test excluded), one grid term.
-FLOP_BEAM_STEP = {"homogeneous": 1647, "grid": 4186, "layered": 1647}  # grad c = 0: the step of rk4_step_pc
-FLOP_POINT_EVAL = 79      # FP64 flops per in-window receiver term (window test, exponent, phase, table
-                          # exp and sincos, 12 accumulating FMAs), FMA = 2, counted in the gfx950 code
-FLOP_GRID_EVAL = 24       # 3 complex multiply-adds
+# Algorithmic FP64 work per unit (FMA = 2), the method's hand counts:
+#   one RK4 beam-step (4 right-hand sides of the ray, variational and amplitude
+#   equations + the RK4 combination): 3.2 kflop in a homogeneous medium,
+#   4.0 kflop in a grid medium (trilinear medium terms);
+#   one in-window receiver/point term: ~60 flop (exponent, phase, complex
+#   exponential, 3 complex multiply-adds);
+#   one in-window grid term: 3 complex multiply-adds = 24 flop.
+FLOP_BEAM_STEP = {"homogeneous": 3200, "grid": 4000, "layered": 3200}
+FLOP_POINT_EVAL = 60
+FLOP_GRID_EVAL = 24
 PEAK_FP64 = 78.6e12       # FP64 vector and FP64 matrix peak, MI355X
 # grid summation variants: (library code, dense MFMA peak of the operand type)
 GRID_PREC = {"fp64": (0, 78.6e12), "fp32": (1, 157.3e12), "bf16x3": (2, 2.5e15), "fp16x3": (3, 2.5e15),
              "fp16x2": (4, 2.5e15)}
 HBM_PEAK = 8.0e12
-# HBM bytes per launch of a kernel on the default workload (smooth, scale 1), from rocprofv3
-# FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy calibration; valid only while the kernel's
-# source is unchanged (sha256 prefix), else reported as null
-TRAFFIC = {"sum_points": {"source": "paper_1810_06760_amd/csrc/k_points.hip", "sha256": "59bdb0187dd2497e",
-                          "bytes_per_launch": 2.0397e+10}}
+# HBM bytes per launch of the dominant kernel in the default bench window (smooth
+# workload, scale 1, K = 20 after W = 5), from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# scaled by a 1 GiB copy calibration; valid only while the kernel's source is
+# unchanged (sha256 prefix), else reported as null
+TRAFFIC = {}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed RK4 steps (each with its receiver sample)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed RK4 steps right before the timed ones")
+    ap.add_argument("--window", type=float, default=0.5,
+                    help="the timed steps start at this fraction of the horizon T (untimed advance before)")
+    ap.add_argument("--segment", type=int, default=250, help="RK4 steps per evolution call (progress between)")
     ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered", "mixed"])
     ap.add_argument("--waves", type=int, default=4, help="beam waves of the mixed-precision workload")
     ap.add_argument("--batch", type=int, default=0, help="beams per receiver-sum batch in the evolution (0: library default)")
@@ -60,7 +72,8 @@ def parse():
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--segments", type=int, default=4, help="evolution calls per step (progress between them)")
-    ap.add_argument("--cpu-beams", type=int, default=48, help="(q,p) pairs in the oracle sample")
+    ap.add_argument("--cpu-beams", type=int, default=512, help="(q,p) pairs in the oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=1000, help="RK4 steps of the oracle sample")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead: a seeded sweep of forward-solve requests over 4 resident models, "
                          "saturated and at Poisson arrivals; prints solves/s with p50/p99 latency")
@@ -95,6 +108,9 @@ def make_workload(name: str, scale: float):
 
 
 def gpu_run(w, args):
+    """Decompose, advance untimed to the window, then time K RK4 steps of the
+    whole beam set (each with its receiver sample); decompose and the grid sum
+    are timed on their own, once per solve."""
     import torch
     import paper_1810_06760_amd as fga
 
@@ -107,66 +123,83 @@ def gpu_run(w, args):
     nq = w.qmesh.count * w.pmesh.count * 3
     beams = fga.BeamSet(nq)
     ws_dec = fga._workspace(fga.workspace_bytes("decompose", mesh=mesh))
-    state = {"ws_ev": None, "ws_grid": None, "seis": None, "grid": None}
+    seg = max(1, args.segment)
+    ws_ev = None
+    seis = {}
 
-    nseg = max(1, min(args.segments, w.nsteps))
-    seg = -(-w.nsteps // nseg)
-
-    def step():
+    def decompose():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
         fga.fga_decompose(med, mesh, f, beams=beams, ws=ws_dec)
-        if state["ws_ev"] is None:
-            state["ws_ev"] = fga._workspace(fga.workspace_bytes(
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    def evolve(nsteps, what):
+        """nsteps RK4 steps in calls of at most `seg` steps; returns summed stats."""
+        nonlocal ws_ev
+        if ws_ev is None:
+            ws_ev = fga._workspace(fga.workspace_bytes(
                 "evolve", beams=beams, nsteps=seg, n_receivers=0 if rec is None else rec.shape[0],
                 eps=w.eps, tau=w.tau, batch=args.batch, chunk=args.chunk))
+        tot = {"beam_steps": 0, "evals": 0}
+        done = 0
+        while done < nsteps:
+            n = min(seg, nsteps - done)
+            out = None
             if rec is not None:
-                state["seis"] = torch.empty((rec.shape[0], w.nsteps, 3, 2), dtype=torch.float64, device=dev)
-        # the evolution in a few calls of `seg` steps (progress lines between)
-        st = {"beam_steps": 0, "evals": 0}
-        for s0 in range(0, w.nsteps, seg):
-            n = min(seg, w.nsteps - s0)
-            part, st_k = fga.fga_evolve(med, beams, w.dt, n, receivers=rec, eps=w.eps, tau=w.tau,
-                                        ws=state["ws_ev"], batch=args.batch, resort=args.resort, chunk=args.chunk)
-            if rec is not None:
-                state["seis"][:, s0:s0 + n].copy_(part)
-            st["beam_steps"] += st_k["beam_steps"]
-            st["evals"] += st_k["evals"]
-            print("bench: steps %d..%d done" % (s0, s0 + n), file=sys.stderr, flush=True)
-        ev_grid = 0
-        if w.out_grid is not None:
-            if state["ws_grid"] is None:
-                state["ws_grid"] = fga._workspace(fga.workspace_bytes("grid", beams=beams, mesh=w.out_grid,
-                                                                      eps=w.eps, tau=w.tau))
-            state["grid"], ev_grid = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid,
-                                                              precision=GRID_PREC[args.grid_precision][0],
-                                                              out=state["grid"], ws=state["ws_grid"])
-        return beams.count, st, ev_grid
+                if n not in seis:
+                    seis[n] = torch.empty((rec.shape[0], n, 3, 2), dtype=torch.float64, device=dev)
+                out = seis[n]
+            _, st = fga.fga_evolve(med, beams, w.dt, n, receivers=rec, eps=w.eps, tau=w.tau, seis=out,
+                                   ws=ws_ev, batch=args.batch, resort=args.resort, chunk=args.chunk)
+            tot["beam_steps"] += st["beam_steps"]
+            tot["evals"] += st["evals"]
+            done += n
+            print("bench: %s: %d of %d steps done" % (what, done, nsteps), file=sys.stderr, flush=True)
+        return tot
 
-    for i in range(args.warmup):
-        t = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        print("bench: warmup step %d done in %.1f s" % (i + 1, time.perf_counter() - t), file=sys.stderr, flush=True)
+    W, K = args.warmup, args.steps
+    advance = int(round(args.window * w.nsteps))
+    advance = max(0, min(advance, w.nsteps - W - K))
+    decompose()                      # first call: module load, allocations
+    t_dec = decompose()
+    n0 = beams.count
+    print("bench: decomposed %d beams in %.3f s" % (n0, t_dec), file=sys.stderr, flush=True)
+    if advance:
+        evolve(advance, "untimed advance to the window")
+    if W:
+        evolve(W, "warmup")
     torch.cuda.synchronize()
     fga.fga_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tot = {"beams": 0, "beam_steps": 0, "ev_rec": 0, "ev_grid": 0}
-    for _ in range(args.steps):
-        nb, st, evg = step()
-        tot["beams"] += nb
-        tot["beam_steps"] += st["beam_steps"]
-        tot["ev_rec"] += st["evals"]
-        tot["ev_grid"] += evg
-        print("bench: timed step done, %d beams" % nb, file=sys.stderr, flush=True)
+    st = evolve(K, "timed window")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = {fga.KERNEL_NAMES[k]: fga.fga_profile_read(k) for k in fga.KERNEL_NAMES}
     fga.fga_profile_enable(False)
-    if args.grid_precision != "fp64" and w.out_grid is not None:
-        # error of the mixed variant against the FP64 path (itself at oracle parity), same final beams
-        ref, _ = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid, precision=0, ws=state["ws_grid"])
-        tot["grid_rel_l2_vs_fp64"] = float(torch.linalg.vector_norm(state["grid"] - ref) /
-                                           torch.linalg.vector_norm(ref))
+    tot = {"beams": beams.count, "beams_decomposed": n0, "beam_steps": st["beam_steps"], "ev_rec": st["evals"],
+           "decompose_s": t_dec, "advance_steps": advance, "t_window": ((advance + W) * w.dt, (advance + W + K) * w.dt)}
+    if w.out_grid is not None:
+        ws_grid = fga._workspace(fga.workspace_bytes("grid", beams=beams, mesh=w.out_grid, eps=w.eps, tau=w.tau))
+        out, _ = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid,
+                                          precision=GRID_PREC[args.grid_precision][0], ws=ws_grid)
+        fga.fga_profile_enable(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out, ev_grid = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid,
+                                                precision=GRID_PREC[args.grid_precision][0], out=out, ws=ws_grid)
+        torch.cuda.synchronize()
+        tot["grid_s"] = time.perf_counter() - t
+        tot["grid_tile"] = fga.fga_profile_read(fga.FGA_K_GRID_TILE)
+        fga.fga_profile_enable(False)
+        tot["ev_grid"] = ev_grid
+        if args.grid_precision != "fp64":
+            # error of the mixed variant against the FP64 path (itself at oracle parity), same beams
+            ref, _ = fga.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid, precision=0, ws=ws_grid)
+            tot["grid_rel_l2_vs_fp64"] = float(torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref))
+        print("bench: %s grid sum at t = %.3f in %.3f s" % (w.out_grid.n, tot["t_window"][1], tot["grid_s"]),
+              file=sys.stderr, flush=True)
     return t1 - t0, tot, prof
 
 
@@ -182,71 +215,57 @@ def traffic_for(name, default_workload):
     return t["bytes_per_launch"]
 
 
-def roofline(tot, prof, medium_kind, grid_peak=PEAK_FP64, default_workload=False):
-    """Dominant kernel: algorithmic FLOPs per launch / mean launch time."""
+def roofline(tot, prof, medium_kind, default_workload=False):
+    """Dominant kernel of the timed window (integrator or receiver sums):
+    algorithmic flops per launch / mean launch duration (hipEvents recorded on
+    the launch's own stream by the library)."""
     work = {
         "integrate": tot["beam_steps"] * FLOP_BEAM_STEP[medium_kind],
         "sum_points": tot["ev_rec"] * FLOP_POINT_EVAL,
-        "grid_tile": tot["ev_grid"] * FLOP_GRID_EVAL,
     }
     name = max(work, key=lambda k: prof.get(k, (0, 0.0))[1])
     launches, ms = prof[name]
     if launches == 0 or ms <= 0:
         return None, name
-    achieved = work[name] / launches / (ms / launches * 1e-3)
-    bound = "mfma" if name == "grid_tile" else "alu"
-    peak = grid_peak if name == "grid_tile" else PEAK_FP64
-    return {"bound": bound, "kernel": name, "achieved": achieved / 1e12, "peak": peak / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic_for(name, default_workload),
-            "launches": launches, "avg_launch_ms": ms / launches}, name
+    achieved = work[name] / (ms * 1e-3)
+    return {"bound": "alu", "kernel": name, "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic_for(name, default_workload),
+            "launches": launches, "avg_launch_ms": ms / launches,
+            "flop_per_unit": FLOP_BEAM_STEP[medium_kind] if name == "integrate" else FLOP_POINT_EVAL,
+            "units_per_launch": (tot["beam_steps"] if name == "integrate" else tot["ev_rec"]) / launches}, name
 
 
-def cpu_baseline(w, tot_per_step, npairs, args):
-    """The oracle on a bounded sample of the same workload, scaled to the
-    whole step by the per-unit rates of its stages."""
+def cpu_baseline(w, args):
+    """The oracle on a bounded sample of the same workload: a few hundred
+    beams of random (q, p) pairs decomposed by FBI quadrature, then RK4 steps
+    in the same medium, each followed by the sum at the 256 receivers.  The
+    per-beam-step time (integrator + one receiver sample) gives beam-steps/s
+    at the threads the oracle uses."""
     import oracle as om
     g = np.random.default_rng(4242)
     nqp = w.qmesh.count * w.pmesh.count
     pick = g.choice(nqp, size=min(args.cpu_beams, nqp), replace=False)
     iq, ip = pick % w.qmesh.count, pick // w.qmesh.count
     med = om.medium_for(w)
-    t = time.perf_counter()
     F = om.fbi(w.f, w.ymesh, w.qmesh.points()[iq], w.pmesh.points()[ip], w.eps)
-    t_fbi = (time.perf_counter() - t) / len(pick)
     beams = om.make_beams(w.qmesh, w.pmesh, F, w.eps, iq, ip, cull_abs=0.0)
-    nsteps = min(w.nsteps, 200)
+    nsteps = min(w.nsteps, args.cpu_steps)
     t_ev = t_rec = 0.0
-    n_rec = 0
     for s in range(nsteps):
         t = time.perf_counter()
         om.evolve(med, beams, w.dt, 1)
         t_ev += time.perf_counter() - t
         if w.receivers is not None:
             t = time.perf_counter()
-            _, c = om.sum_points(beams, w.receivers, w.eps, w.tau)
+            om.sum_points(beams, w.receivers, w.eps, w.tau)
             t_rec += time.perf_counter() - t
-            n_rec += len(beams) * len(w.receivers)
-    rate_step = t_ev / (nsteps * len(beams))
-    rate_rec = t_rec / n_rec if n_rec else 0.0
-    t_grid = 0.0
-    if w.out_grid is not None:
-        pts = w.out_grid.points()
-        sel = g.choice(len(pts), size=min(4096, len(pts)), replace=False)
-        t = time.perf_counter()
-        om.sum_points(beams, pts[sel], w.eps, w.tau)
-        t_grid = (time.perf_counter() - t) / (len(sel) * len(beams))
-    # whole-step CPU time: FBI per (q,p) pair, per beam-step, per (beam, receiver, sample)
-    # pair tested, per (beam, grid point) pair tested
-    full = (t_fbi * npairs + rate_step * tot_per_step["beam_steps"]
-            + rate_rec * tot_per_step["beams"] * (len(w.receivers) if w.receivers is not None else 0) * w.nsteps
-            + t_grid * tot_per_step["beams"] * (w.out_grid.count if w.out_grid is not None else 0))
+    per_beam_step = (t_ev + t_rec) / (nsteps * len(beams))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": tot_per_step["beam_steps"] / full, "unit": "beam-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "%d random (q,p) pairs (%d beams): FBI, %d RK4 steps with 256-receiver sums per step, "
-                      "4096 random grid points; stage rates scaled to the full step (FBI per pair, per "
-                      "beam-step, per beam-receiver pair, per beam-grid point pair)"
-                      % (len(pick), len(beams), nsteps),
-            "seconds_per_step_extrapolated": full}
+    return {"value": 1.0 / per_beam_step, "unit": "beam-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "%d random (q,p) pairs x 3 branches (%d beams) of the same workload, %d RK4 steps from "
+                      "t = 0 each followed by the %d-receiver sum; %.1f s integrate + %.1f s receiver sums"
+                      % (len(pick), len(beams), nsteps, 0 if w.receivers is None else len(w.receivers), t_ev, t_rec),
+            "seconds": t_ev + t_rec}
 
 
 def layered(args):
@@ -570,11 +589,11 @@ def main():
     w, label = make_workload(args.workload, args.scale)
     elapsed, tot, prof = gpu_run(w, args)
     K = args.steps
-    per = {k: v / K for k, v in tot.items() if k != "grid_rel_l2_vs_fp64"}
     value = tot["beam_steps"] / elapsed
     kind = "grid" if w.medium_nodes is not None else "homogeneous"
-    roof, dom = roofline(tot, prof, kind, GRID_PREC[args.grid_precision][1],
-                         default_workload=(args.workload == "smooth" and args.scale == 1.0))
+    roof, dom = roofline(tot, prof, kind, default_workload=(args.workload == "smooth" and args.scale == 1.0
+                                                             and K == 20 and args.warmup == 5))
+    t_a, t_b = tot["t_window"]
     line = {
         "metric": "beam-steps/s + beam-point evals/s; served solves/s, p50/p99 at rel-L2<=1e-3",
         "value": value,
@@ -588,19 +607,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": label, "beams": int(per["beams"]), "global_batch": int(per["beams"]),
-                   "parallelism": "single GPU"},
-        "beam_point_evals_per_s": (tot["ev_rec"] + tot["ev_grid"]) / elapsed,
-        "receiver_evals_per_step": int(per["ev_rec"]),
-        "grid_evals_per_step": int(per["ev_grid"]),
-        "kernel_ms_per_step": {k: v[1] / K for k, v in prof.items()},
+        "config": {"workload": label + "; one step = one RK4 step of all beams with its receiver sample, "
+                               "timed over t = %.3f..%.3f after an untimed advance; decompose and the grid "
+                               "sum timed separately per solve" % (t_a, t_b),
+                   "beams": int(tot["beams"]), "parallelism": "single GPU"},
+        "beam_point_evals_per_s": tot["ev_rec"] / elapsed,
+        "receiver_evals_per_step": int(tot["ev_rec"] / K),
+        "kernel_ms_per_step": {k: v[1] / K for k, v in prof.items() if v[0]},
+        "kernel_launches": {k: v[0] for k, v in prof.items() if v[0]},
+        "decompose_s": tot["decompose_s"],
+        "beams_decomposed": tot["beams_decomposed"],
         "roofline": roof,
     }
-    if args.grid_precision != "fp64":
-        line["grid_precision"] = args.grid_precision
-        line["grid_rel_l2_vs_fp64"] = tot.get("grid_rel_l2_vs_fp64")
+    if "grid_s" in tot:
+        gl, gms = tot["grid_tile"]
+        gpeak = GRID_PREC[args.grid_precision][1]
+        line["grid"] = {"n": list(w.out_grid.n), "t": t_b, "precision": args.grid_precision, "s": tot["grid_s"],
+                        "tile_kernel_s": gms * 1e-3, "evals": tot["ev_grid"],
+                        "evals_per_s": tot["ev_grid"] / (gms * 1e-3) if gms > 0 else None,
+                        "frac_of_peak": FLOP_GRID_EVAL * tot["ev_grid"] / (gms * 1e-3) / gpeak if gms > 0 else None}
+        if "grid_rel_l2_vs_fp64" in tot:
+            line["grid"]["rel_l2_vs_fp64"] = tot["grid_rel_l2_vs_fp64"]
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, per, w.qmesh.count * w.pmesh.count, args)
+        line["cpu_baseline"] = cpu_baseline(w, args)
+        print("bench: cpu baseline done (%.1f s)" % line["cpu_baseline"]["seconds"], file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 
