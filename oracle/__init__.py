@@ -82,6 +82,9 @@ def lib():
         L.om_sum_points.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_double, C.c_double, vp]
         L.om_evolve.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_int]
         L.om_fbi_many.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, C.c_double, vp]
+        L.om_make_beams_many.restype = C.c_int64
+        L.om_make_beams_many.argtypes = [vp, vp, vp, vp, C.c_int64, vp, vp, C.c_int64, C.c_int64, C.c_int,
+                                         C.c_double, C.c_double, C.c_double, C.c_int, C.c_double, vp]
         L.om_make_beams.restype = C.c_int
         L.om_make_beams.argtypes = [vp, vp, vp, vp, C.c_int, C.c_double, C.c_double, C.c_double,
                                     C.c_int, C.c_double, C.c_int64, C.c_int64, vp]
@@ -117,6 +120,13 @@ def lib():
                                % (L.om_beam_size(), BEAM_DTYPE.itemsize))
         _lib = L
     return _lib
+
+
+def take_beams(b: np.ndarray, index) -> np.ndarray:
+    """b[index] for a beam array, copied as raw records (numpy's per-field
+    gather of this structured type is two orders of magnitude slower)."""
+    raw = np.ascontiguousarray(b).view(np.dtype((np.void, BEAM_DTYPE.itemsize)))
+    return raw[np.asarray(index)].view(BEAM_DTYPE)
 
 
 def _p(a: np.ndarray):
@@ -228,25 +238,19 @@ def make_beams(qmesh, pmesh, Ft: np.ndarray, eps: float, iq: np.ndarray, ip: np.
     Ft (n,3) (and Gt (n,2,3) = FBI[g/c_P], FBI[g/c_S] when g != 0).
     Returned sorted by lineage."""
     lib_ = lib()
-    qs = qmesh.points()[iq]
-    ps = pmesh.points()[ip]
+    iq = np.ascontiguousarray(iq, dtype=np.int64)
+    ip = np.ascontiguousarray(ip, dtype=np.int64)
+    qs = np.ascontiguousarray(qmesh.points()[iq])
+    ps = np.ascontiguousarray(pmesh.points()[ip])
     nq, npm = qmesh.count, pmesh.count
     dq, dp = qmesh.cell_volume, pmesh.cell_volume
+    F = np.ascontiguousarray(Ft, dtype=np.complex128).reshape(-1, 3)
+    G = None if Gt is None else np.ascontiguousarray(Gt, dtype=np.complex128).reshape(-1, 2, 3)
     out = np.zeros(6 * len(iq), dtype=BEAM_DTYPE)
-    tmp = np.zeros(6, dtype=BEAM_DTYPE)
-    k = 0
-    for i in range(len(iq)):
-        q = np.ascontiguousarray(qs[i])
-        p = np.ascontiguousarray(ps[i])
-        F = np.ascontiguousarray(Ft[i], dtype=np.complex128)
-        G = None if Gt is None else np.ascontiguousarray(Gt[i], dtype=np.complex128)
-        nb = lib_.om_make_beams(_p(q), _p(p), _p(F), None if G is None else _p(G),
-                                1 if one_way else 0, eps, dq, dp, branch_mask, cull_abs,
-                                int(ip[i]) * nq + int(iq[i]), nq * npm, _p(tmp))
-        out[k:k + nb] = tmp[:nb]
-        k += nb
+    k = lib_.om_make_beams_many(_p(qs), _p(ps), _p(F), None if G is None else _p(G), len(iq), _p(iq), _p(ip),
+                                nq, npm, 1 if one_way else 0, eps, dq, dp, branch_mask, cull_abs, _p(out))
     out = out[:k]
-    return out[np.argsort(out["lineage"], kind="stable")]
+    return take_beams(out, np.argsort(out["lineage"], kind="stable"))
 
 
 def decompose(work, one_way: bool = True, iq=None, ip=None, branch_mask: int = 7) -> np.ndarray:
@@ -260,6 +264,34 @@ def decompose(work, one_way: bool = True, iq=None, ip=None, branch_mask: int = 7
     Ft = fbi(work.f, work.ymesh, work.qmesh.points()[iq], work.pmesh.points()[ip], work.eps)
     return make_beams(work.qmesh, work.pmesh, Ft, work.eps, iq, ip, one_way=one_way,
                       branch_mask=branch_mask, cull_abs=work.cull_abs)
+
+
+def decompose_two_way(work, g: np.ndarray, iq=None, ip=None, branch_mask: int = 7) -> np.ndarray:
+    """Step 1 with both directions (eq:psi, eq:alpha^k): initial displacement
+    work.f and velocity g (complex [3][z][y][x] on work.ymesh); the speeds
+    c_P, c_S at the quadrature points come from the work's medium."""
+    if iq is None:
+        iq_all, ip_all = np.meshgrid(np.arange(work.qmesh.count), np.arange(work.pmesh.count), indexing="xy")
+        iq, ip = iq_all.ravel(), ip_all.ravel()
+    iq = np.asarray(iq, dtype=np.int64)
+    ip = np.asarray(ip, dtype=np.int64)
+    qs, ps = work.qmesh.points()[iq], work.pmesh.points()[ip]
+    Ft = fbi(work.f, work.ymesh, qs, ps, work.eps)
+    med = medium_for(work)
+    y = work.ymesh.points()
+    n = tuple(int(v) for v in work.ymesh.n[::-1])
+    Gt = np.empty((len(iq), 2, 3), dtype=np.complex128)
+    for sp in (0, 1):
+        c = speed(med, sp, y)[0].reshape(n)
+        Gt[:, sp] = fbi(np.asarray(g) / c[None], work.ymesh, qs, ps, work.eps)
+    return make_beams(work.qmesh, work.pmesh, Ft, work.eps, iq, ip, one_way=False, Gt=Gt,
+                      branch_mask=branch_mask, cull_abs=work.cull_abs)
+
+
+def plant_two_way_error(kind: int) -> None:
+    """Plant a known mistake in the two-way weight (see om_plant_twoway_error
+    in fga_oracle.c; 0 removes it).  Only the pins of that weight call this."""
+    C.c_int.in_dll(lib(), "om_plant_twoway_error").value = int(kind)
 
 
 # ---------------------------------------------------------------------------

@@ -491,6 +491,29 @@ static void om_polarisation(int branch, const double p[3], const double e[3], do
   }
 }
 
+/* Test hook, 0 in every use but one: the pins of the two-way weight set it to
+ * plant a known mistake in om_psi (1: the g-term doubled, 2: the g-term's sign
+ * flipped, 3: |p|^3 in place of |p|, 4: the 1/2 on f dropped) and check that
+ * their test then fails. */
+int om_plant_twoway_error = 0;
+
+/* Weight of one beam from the branch projections fn = FBI[f].n_b and
+ * gn = FBI[g/c_b].n_b for direction sigma = +-1 (eq:psi with eq:alpha^k read
+ * with prefactor 1/(2 k c |p|), k = 1/eps):
+ *   psi = (1/2) fn + sigma (i eps / (2 |p|)) gn. */
+static cplx om_psi(cplx fn, cplx gn, int sigma, double eps, double np)
+{
+  double half = 0.5, gscale = 1.0, pden = np;
+  switch (om_plant_twoway_error) {
+  case 1: gscale = 2.0; break;
+  case 2: gscale = -1.0; break;
+  case 3: pden = np * np * np; break;
+  case 4: half = 1.0; break;
+  default: break;
+  }
+  return half * fn + gscale * sigma * I * eps / (2.0 * pden) * gn;
+}
+
 /* Build the beams of one (q, p) mesh point from the FBI transforms Ft = FBI[f]
  * and Gt[b] = FBI[g / c_b] (Gt may be NULL when g = 0).
  *   alpha_{+-} = (1/2)(f +- i g/(k c |p|)) . n_b          (eq:alpha^k read with
@@ -519,12 +542,12 @@ int om_make_beams(const double q[3], const double p[3], const cplx Ft[3], const 
       cplx psi;
       if (one_way) psi = fn;
       else {
-        psi = 0.5 * fn;
+        cplx gn = 0.0;
         if (Gt) {
           const cplx *G = Gt + 3 * (br == 0 ? 0 : 1);
-          cplx gn = G[0] * nh[0] + G[1] * nh[1] + G[2] * nh[2];
-          psi += sg * I * eps / (2.0 * np) * gn;
+          gn = G[0] * nh[0] + G[1] * nh[1] + G[2] * nh[2];
         }
+        psi = om_psi(fn, gn, sg, eps, np);
       }
       int64_t lin = lineage_base + (int64_t)(br * 2 + si) * lineage_stride;
       if (cabs(psi) < cull_abs) continue;
@@ -734,7 +757,7 @@ int64_t om_point_source_beams(const om_medium *m, const om_point_source *src, om
             G[i] /= rho0;
           }
           const cplx gn = G[0] * nh[0] + G[1] * nh[1] + G[2] * nh[2];
-          const cplx psi = sg * I * eps / (2.0 * np) * gn * rk;
+          const cplx psi = om_psi(0.0, gn, sg, eps, np) * rk;
           if (cabs(psi) < src->cull_abs) continue;
           om_beam *b = &out[nb++];
           memset(b, 0, sizeof(*b));
@@ -1123,6 +1146,21 @@ void om_fbi_many(const cplx *f, const int yn[3], const double ylo[3], const doub
 }
 
 /* rhs of one beam at its stored state, for tests of the ODE itself */
+/* om_make_beams over many mesh points: pair i is (q[i], p[i]) with FBI values
+ * Ft[i] and Gt[i] (Gt NULL or [n][2][3]: FBI[g/c_P], FBI[g/c_S]) and lineage
+ * base ip[i]*nq_all + iq[i]; beams are written in pair order.  Returns the
+ * number of beams written. */
+int64_t om_make_beams_many(const double *q, const double *p, const cplx *Ft, const cplx *Gt, int64_t n,
+                           const int64_t *iq, const int64_t *ip, int64_t nq_all, int64_t np_all, int one_way,
+                           double eps, double dq, double dp, int branch_mask, double cull_abs, om_beam *out)
+{
+  int64_t k = 0;
+  for (int64_t i = 0; i < n; ++i)
+    k += om_make_beams(q + 3 * i, p + 3 * i, Ft + 3 * i, Gt ? Gt + 6 * i : NULL, one_way, eps, dq, dp, branch_mask,
+                       cull_abs, ip[i] * nq_all + iq[i], nq_all * np_all, out + k);
+  return k;
+}
+
 void om_rhs_beam(const om_medium *m, const om_beam *b, om_beam *d)
 {
   om_state y, dy;

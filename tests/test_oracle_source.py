@@ -2,8 +2,10 @@
 u(0) = 0, u_t(0) = -(1/rho0) M grad delta(x - x0); Sec. 2.1 eq:psi with
 eq:alpha^k at f = 0):
 
-  - the closed-form FBI[g / c_b] equals a direct quadrature of the FBI of the
-    same source smoothed by a narrow Gaussian, to O(sigma^2) (homogeneous and
+  - each beam's weight from the closed-form FBI[g / c_b] equals the two-way
+    weight of the packet decomposition (itself pinned by the u(0) = f and
+    u_t(0) = g tests) applied to a direct quadrature of the FBI of the same
+    source smoothed by a narrow Gaussian, to O(sigma^2) (homogeneous and
     linear-gradient media, so both the kernel-derivative and the speed-
     gradient terms are checked);
   - Gauss-Legendre shells reproduce numpy's nodes and integrate polynomials
@@ -78,6 +80,21 @@ def smoothed_source_fbi(med, cb_fn, x0, M, rho0, sigma, q, p, eps, h):
     return om.fbi(f, mesh, q[None, :], p[None, :], eps)[0]
 
 
+def two_way_psi(b, G, eps):
+    """psi of the two-way decomposition (f = 0, FBI[g/c_b] = G) for the branch
+    and direction of beam b at its (q, p): the oracle's own weight, pinned by
+    tests/test_oracle_twoway.py, on a one-point mesh of unit cell measure."""
+    br = int(b["branch"])
+    qm = fi.Mesh3((1, 1, 1), tuple(b["Q"]), (1.0, 1.0, 1.0))
+    pm = fi.Mesh3((1, 1, 1), tuple(b["P"]), (1.0, 1.0, 1.0))
+    Gt = np.zeros((1, 2, 3), dtype=np.complex128)
+    Gt[0, 0 if br == 0 else 1] = G
+    bb = om.make_beams(qm, pm, np.zeros((1, 3), dtype=np.complex128), eps, np.array([0]), np.array([0]),
+                       one_way=False, Gt=Gt, branch_mask=1 << br)
+    sel = bb[bb["sigma"] == b["sigma"]]
+    return sel["w"][0] * (2 * math.pi * eps) ** 4.5
+
+
 @pytest.mark.parametrize("medium_kind", ["homogeneous", "linear"])
 def test_closed_form_against_smoothed_quadrature(medium_kind):
     eps = 1.0 / 16
@@ -111,14 +128,12 @@ def test_closed_form_against_smoothed_quadrature(medium_kind):
         sh = ip // ndir
         np_ = xs[sh]
         dp = np_ ** 2 * ws[sh] * 4 * math.pi / ndir
-        psi = b["w"] / (dq * dp * norm)
+        got = b["w"] / (dq * dp * norm)                        # psi of the closed form
         p = b["P"]
-        nh = om.amplitude_vectors(b.reshape(1))[0] / 2 ** 1.5   # polarisation (a = 2^{3/2} on it)
-        got = psi / (b["sigma"] * 1j * eps / (2 * np_))          # FBI[g/c_b] . n_b
         refs = []
         for sigma in (0.006, 0.003):
             G = smoothed_source_fbi(med, lambda Y: cb(Y, c0), x0, M6, rho0, sigma, b["Q"], p, eps, sigma / 6)
-            refs.append(np.dot(G, nh.real))
+            refs.append(two_way_psi(b, G, eps))
         e0, e1 = abs(got - refs[0]), abs(got - refs[1])
         assert 3.0 < e0 / e1 < 5.0               # O(sigma^2) approach to the closed form
         extrap = (4.0 * refs[1] - refs[0]) / 3.0  # Richardson: the sigma^2 term removed
