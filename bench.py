@@ -78,6 +78,9 @@ def parse():
                     help="serving run instead: a seeded sweep of forward-solve requests over 4 resident models, "
                          "saturated and at Poisson arrivals; prints solves/s with p50/p99 latency")
     ap.add_argument("--requests", type=int, default=48, help="requests per serving phase")
+    ap.add_argument("--sweep", default="small", choices=["small", "stated"],
+                    help="serving requests: 'stated' = eps 1/64..1/512, 1e5..5e7 beams, 2000 samples (the "
+                         "tomography sweep's own sizes); 'small' = eps 1/32..1/128, 250 samples")
     ap.add_argument("--slots", type=int, default=4, help="concurrent request slots of the server")
     ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="server device-memory budget")
     ap.add_argument("--load", type=float, default=0.8, help="Poisson arrival rate as a fraction of saturated")
@@ -283,7 +286,7 @@ def layered(args):
     src = fga.point_source(e["eps"], e["x0"], e["M"], nq=e["nq"], ndir=e["ndir"], nshell=e["nshell"])
     ncand = int(fga.lib().fga_point_source_candidates(fga.C.byref(src)))
     beams = fga.BeamSet(12 * ncand)   # room for interface children (generation cap 3)
-    rec = fga._dev(e["receivers"], torch.float64)
+    rec = fga._dev(e["receivers_rtp"], torch.float64)   # stations as (r, longitude, latitude)
     nseg = max(1, min(args.segments, e["nsteps"]))
     seg = -(-e["nsteps"] // nseg)
     state = {"ws": None, "seis": torch.empty((rec.shape[0], e["nsteps"], 3, 2), dtype=torch.float64, device="cuda")}
@@ -294,12 +297,13 @@ def layered(args):
         if state["ws"] is None:
             state["ws"] = fga._workspace(fga.workspace_bytes("evolve", beams=beams, nsteps=seg,
                                                              n_receivers=rec.shape[0], eps=e["eps"], tau=e["tau"],
-                                                             batch=args.batch))
+                                                             batch=args.batch, coords=fga.FGA_COORDS_SPHERICAL))
         tot = {"beam_steps": 0, "evals": 0, "crossings": 0, "spawned": 0, "capped": 0}
         for s0 in range(0, e["nsteps"], seg):
             n = min(seg, e["nsteps"] - s0)
             part, st = fga.fga_evolve(med, beams, e["dt"], n, receivers=rec, eps=e["eps"], tau=e["tau"],
-                                      ws=state["ws"], batch=args.batch, resort=args.resort)
+                                      ws=state["ws"], batch=args.batch, resort=args.resort,
+                                      coords=fga.FGA_COORDS_SPHERICAL)
             state["seis"][:, s0:s0 + n].copy_(part)
             for k in tot:
                 tot[k] += st[k]
@@ -354,7 +358,13 @@ def serve(args):
     import paper_1810_06760_amd as fga
     torch.cuda.set_device(0)
     models = [fga.Medium.grid(fi.sweep_model(j), fi.node_grid(128), cs_ratio=1.0 / math.sqrt(3.0)) for j in range(4)]
-    reqs = [fi.sweep_request(i) for i in range(args.requests)]
+    stated = args.sweep == "stated"
+    if stated:
+        # each eps of the stated sweep equally often (i mod 4), in a seeded random order
+        order = np.random.default_rng(5998).permutation(args.requests)
+        reqs = [fi.sweep5_request(int(i), eps_index=int(i) % 4) for i in order]
+    else:
+        reqs = [fi.sweep_request(i) for i in range(args.requests)]
 
     prec = fga.FGA_FP32 if args.serve_precision == "mixed" else fga.FGA_FP64
 
@@ -364,9 +374,9 @@ def serve(args):
                                 rq["nsteps"], 1, precision=prec if precision is None else precision, source=src)
 
     budget = int(args.hbm_budget_gb * 2 ** 30)
-    # warm-up: one solve (module load, first allocations)
+    # warm-up: one solve of the smallest request (module load, first allocations)
     srv = fga.Server(budget, 1)
-    r, sz, keep = request(reqs[0])
+    r, sz, keep = request(min(reqs, key=lambda q: q["ndir"] * q["nshell"] / q["eps"]))
     srv.submit(r, keep=(keep, sz))
     assert srv.poll(1, wait_ms=600000)[0]["status"] == 0
     srv.close()
@@ -420,11 +430,12 @@ def serve(args):
     beams = np.array(sat["beams"])
     err = None
     if prec != fga.FGA_FP64:
-        # the same first 8 requests in FP64, one slot
+        # the same requests in FP64 (the 8 smallest), one slot
         srv = fga.Server(budget, args.slots)
         ref = {}
+        small = sorted(range(len(reqs)), key=lambda k: reqs[k]["ndir"] * reqs[k]["nshell"] / reqs[k]["eps"])[:8]
         try:
-            for k in range(min(8, len(reqs))):
+            for k in small:
                 r, sz, keep = request(reqs[k], fga.FGA_FP64)
                 ref[srv.submit(r, keep=(keep, sz))] = (k, sz)
             got = []
@@ -447,11 +458,14 @@ def serve(args):
         "dtype": "f64" if prec == fga.FGA_FP64 else "f64+f32",
         "data": "synthetic",
         "config": {"workload": "tomography sweep: %d requests over 4 resident 128^3 smooth random models, point "
-                               "moment-tensor sources (Ricker) at random positions, eps in {1/32, 1/64, 1/128}, "
-                               "128..1024 receivers x 250 samples, 250 FP64 RK4 steps, %s receiver sums; "
-                               "Poisson arrivals at %.2f x saturated rate"
-                               % (len(reqs), "FP64" if prec == fga.FGA_FP64 else "mixed (FP32 exp/sin/cos)",
-                                  args.load),
+                               "moment-tensor sources (Ricker) at random positions, %s, "
+                               "128..1024 receivers, %s receiver sums; Poisson arrivals at %.2f x saturated rate"
+                               % (len(reqs),
+                                  "eps in {1/64, 1/128, 1/256, 1/512} (each 1/4 of the requests; 9.8e4, 8.0e5, "
+                                  "6.4e6, 5.1e7 candidate beams), 2000 FP64 RK4 steps to T = 1 with a sample after "
+                                  "every step" if stated else
+                                  "eps in {1/32, 1/64, 1/128}, 250 FP64 RK4 steps with a sample after every step",
+                                  "FP64" if prec == fga.FGA_FP64 else "mixed (FP32 exp/sin/cos)", args.load),
                    "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb, "parallelism": "single GPU"},
         "p50_s": poi["p50_s"], "p99_s": poi["p99_s"], "arrival_rate": rate,
         "saturated": {k: sat[k] for k in ("solves_per_s", "p50_s", "p99_s", "makespan_s", "peak_running")},
@@ -461,7 +475,7 @@ def serve(args):
         "evals_per_s_saturated": sat["evals"] / sat["makespan_s"],
     }
     if err is not None:
-        line["max_rel_l2_vs_fp64_first8"] = err
+        line["max_rel_l2_vs_fp64_smallest8"] = err
     print(json.dumps(line), flush=True)
 
 

@@ -263,6 +263,34 @@ def sweep_request(i: int, nmodels: int = 4, nsteps: int = 250, dt: float = 2e-3,
     }
 
 
+# The tomography sweep at its stated sizes: eps from {1/64, 1/128, 1/256,
+# 1/512}; the point-source meshes (q 8^3 x directions x shells x 3 branches x
+# 2 directions) give about 1e5, 8e5, 6.4e6 and 5.1e7 candidate beams; 2000
+# samples over T = 1.
+SWEEP5_MESHES = {1.0 / 64: (8, 16, 2), 1.0 / 128: (8, 65, 4), 1.0 / 256: (8, 520, 4), 1.0 / 512: (8, 4167, 4)}
+
+
+def sweep5_request(i: int, nmodels: int = 4, nsteps: int = 2000, T: float = 1.0, tau: float = 25.0,
+                   eps_index: int = None) -> dict:
+    """Request i of the sweep at its stated sizes: model index, a point
+    moment-tensor source (Ricker) at a uniform position in [0.25, 0.75]^3
+    with a random moment tensor, eps drawn uniformly from SWEEP5_MESHES (or
+    the given index), 128..1024 receivers uniform in [0,1]^3, nsteps samples."""
+    g = rng(5, 400 + i)
+    model = int(g.integers(0, nmodels))
+    x0 = g.uniform(0.25, 0.75, 3)
+    M = moment_tensor(g)
+    k = int(g.integers(0, len(SWEEP5_MESHES)))
+    eps = list(SWEEP5_MESHES)[k if eps_index is None else eps_index]
+    nq, ndir, nshell = SWEEP5_MESHES[eps]
+    nrec = int(g.integers(128, 1025))
+    return {
+        "model": model, "eps": eps, "nsteps": nsteps, "dt": T / nsteps, "tau": tau,
+        "x0": x0, "M": M, "nq": nq, "ndir": ndir, "nshell": nshell,
+        "receivers": uniform_points(nrec, g),
+    }
+
+
 # ---------------------------------------------------------------------------
 # layered spherical Earth-like model with a point source
 # ---------------------------------------------------------------------------
@@ -279,12 +307,6 @@ def fibonacci_sphere(n: int, g: np.random.Generator) -> np.ndarray:
     return pts @ q.T
 
 
-def spherical_to_cartesian(r, theta, phi):
-    """Receiver coordinates given as radius, longitude theta and latitude
-    phi: x = (r cos(theta) cos(phi), r sin(theta) cos(phi), r sin(phi))."""
-    return np.stack([r * np.cos(theta) * np.cos(phi), r * np.sin(theta) * np.cos(phi), r * np.sin(phi)], axis=-1)
-
-
 def layered_earth(family: int = 3, eps: float = 1.0 / 256, nq: int = 8, ndir: int = 1600, nshell: int = 4,
                   nsteps: int = 2000, T: float = 1.5, nrec: int = 512) -> dict:
     """Unit sphere with 4 layers: 3 interface radii in (0.3, 0.95) at least
@@ -292,7 +314,8 @@ def layered_earth(family: int = 3, eps: float = 1.0 / 256, nq: int = 8, ndir: in
     deeper layer multiplies each of them by U[1.05, 1.20]; a point
     moment-tensor source with a Ricker wavelet at radius U[0.6, 0.9] in a
     random direction; receivers on a Fibonacci lattice of the surface r = 1,
-    given as (r, longitude, latitude) and mapped to Cartesian."""
+    given in spherical coordinates (r, longitude, latitude) as the Earth
+    examples give stations ("receivers_rtp")."""
     g = rng(family, 1)
     while True:
         radii = np.sort(g.uniform(0.3, 0.95, 3))[::-1]
@@ -310,6 +333,6 @@ def layered_earth(family: int = 3, eps: float = 1.0 / 256, nq: int = 8, ndir: in
     pts = fibonacci_sphere(nrec, rng(family, 3))
     theta = np.arctan2(pts[:, 1], pts[:, 0])
     phi = np.arcsin(np.clip(pts[:, 2], -1.0, 1.0))
-    rec = spherical_to_cartesian(np.ones(nrec), theta, phi)
+    rtp = np.stack([np.ones(nrec), theta, phi], axis=1)
     return {"bounds": list(radii), "cp": cp, "cs": cs, "rho": rho, "x0": x0, "M": M, "eps": eps, "nq": nq,
-            "ndir": ndir, "nshell": nshell, "nsteps": nsteps, "dt": T / nsteps, "receivers": rec, "tau": 25.0}
+            "ndir": ndir, "nshell": nshell, "nsteps": nsteps, "dt": T / nsteps, "receivers_rtp": rtp, "tau": 25.0}

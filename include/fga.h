@@ -229,21 +229,31 @@ fga_status fga_decompose_point_source(const fga_medium *med, const fga_point_sou
 
 typedef enum { FGA_FP64 = 0, FGA_FP32 = 1, FGA_BF16X3 = 2, FGA_FP16X3 = 3, FGA_FP16X2 = 4 } fga_precision;
 
+enum { FGA_COORDS_CARTESIAN = 0, FGA_COORDS_SPHERICAL = 1 };
+
 typedef struct {
   int64_t n;               /* receivers                                                */
-  const double *xyz;       /* device, [n][3] Cartesian positions                       */
+  const double *xyz;       /* device, [n][3] positions: Cartesian (x, y, z), or with
+                              coords = FGA_COORDS_SPHERICAL (r, theta, phi), theta the
+                              longitude and phi the latitude, mapped by the library to
+                              (r cos theta cos phi, r sin theta cos phi, r sin phi)
+                              (the Earth examples' coordinates, opening of Sec. 3)    */
   int stride;              /* a sample after every `stride` steps (>= 1)               */
   double eps, tau;         /* summation: 1/k and window exp(-tau) (half-width
                               sqrt(2 tau eps) per axis)                                */
   int precision;           /* FGA_FP64: FP64 sums; FGA_FP32 (mixed): the Gaussian
                               exponent and the phase reduced modulo 2 pi in FP64, then
                               exp / sin / cos in FP32, sums in FP64                    */
+  int coords;              /* FGA_COORDS_CARTESIAN (0) or FGA_COORDS_SPHERICAL         */
 } fga_receivers;
 
 typedef struct {
   int chunk;               /* RK4 steps per integrator launch (0: library default)     */
-  double cutoff_abs;       /* drop beams with |w| max(|a0|,|a1|) < cutoff_abs (0: off)  */
-  int compact;             /* 1: compact the beam set after culling (stable order)     */
+  double cutoff_abs;       /* after every step, drop beams with |w| max(|a0|,|a1|) <
+                              cutoff_abs (0: off); a dropped beam takes no further
+                              step and is not summed from that step's sample on      */
+  int compact;             /* 1: compact the beam set at the end of the call (stable
+                              order; dead, culled and quarantined beams leave)        */
   int64_t batch;           /* beams per receiver batch (0: library default 2^22); in
                               layered media, which sum one sample per step, a batch
                               holds (chunk + stride - 1) / stride + 1 times as many  */
@@ -260,7 +270,10 @@ typedef struct {
   int64_t beam_steps;      /* RK4 steps taken by live beams                            */
   int64_t evals;           /* in-window (beam, receiver, sample) terms summed          */
   int64_t culled;          /* beams dropped by the cutoff                              */
-  int64_t quarantined;     /* beams dropped for non-finite state                       */
+  int64_t quarantined;     /* beams dropped for non-finite state: after a step, a beam
+                              whose Q, P, amplitudes or action are not finite (or whose
+                              weight or frame axis is not) is flagged QUARANTINED, takes
+                              no further step and is never summed                     */
   int64_t crossings;       /* interface hits (layered media)                           */
   int64_t spawned;         /* beams made at interfaces                                 */
   int64_t capped;          /* beams retired at an interface at the generation cap      */
@@ -368,6 +381,8 @@ typedef struct {
   int precision;            /* receiver sums: FGA_FP64 or FGA_FP32 (mixed)            */
   int point_source;         /* 1: the initial data is `source` (mesh and f unused)    */
   fga_point_source source;
+  int receiver_coords;      /* FGA_COORDS_CARTESIAN or FGA_COORDS_SPHERICAL, as in
+                               fga_receivers                                         */
 } fga_request;
 
 typedef struct {
@@ -384,14 +399,18 @@ typedef struct fga_server fga_server;
  * seismograms); admission compares this with the budget. */
 size_t fga_server_footprint(const fga_request *r);
 
-/* A request server on the current device.  Requests are admitted in
- * arrival order, skipping ahead to the first queued one that fits, whenever
- * a slot is free (at most max_active at once) and the device bytes held by
- * running requests plus the new one's footprint stay within hbm_budget.
+/* A request server on the current device.  It takes one device pool of
+ * hbm_budget bytes at creation (its only allocation; freed by
+ * fga_server_destroy); each request runs in a block of the pool of its
+ * footprint, so solves allocate and free nothing on the device.  Requests
+ * are admitted in arrival order, skipping ahead to the first queued one that
+ * fits, whenever a slot is free (at most max_active at once) and a block of
+ * the request's footprint is free in the pool (first fit).
  * Each slot runs its request on its own stream from its own host thread,
  * so admitted requests overlap on the device; a request's result does not
  * depend on what runs beside it (each solve is deterministic).
- * Errors: FGA_EINVAL (max_active < 1), FGA_EDEVICE. */
+ * Errors: FGA_EINVAL (max_active < 1), FGA_ENOMEM (the pool cannot be
+ * allocated), FGA_EDEVICE. */
 fga_status fga_server_create(size_t hbm_budget, int max_active, fga_server **out);
 /* Queues a request (non-blocking; f and receivers are copied).  Errors:
  * FGA_EINVAL (invalid request), FGA_ECAPACITY (footprint above the budget:

@@ -64,6 +64,7 @@ class Medium(C.Structure):
 HOMOGENEOUS, GRID, BUMP, LINEAR, LAYERED = 0, 1, 2, 3, 4
 
 
+
 class PointSource(C.Structure):
     _fields_ = [("eps", C.c_double), ("x0", C.c_double * 3), ("M", C.c_double * 6), ("rho0", C.c_double),
                 ("nq", C.c_int), ("qhalf", C.c_double), ("ndir", C.c_int), ("nshell", C.c_int),
@@ -415,6 +416,15 @@ def amplitude_vectors(beams: np.ndarray) -> np.ndarray:
 
 def reframe(beams: np.ndarray) -> None:
     lib().om_reframe_many(_p(beams), beams.shape[0])
+
+
+def spherical_to_cartesian(rtp: np.ndarray) -> np.ndarray:
+    """Stations given as (r, theta, phi), theta the longitude and phi the
+    latitude (the coordinates of the Earth examples, opening of Sec. 3):
+    x = (r cos theta cos phi, r sin theta cos phi, r sin phi)."""
+    rtp = np.asarray(rtp, dtype=np.float64).reshape(-1, 3)
+    r, th, ph = rtp[:, 0], rtp[:, 1], rtp[:, 2]
+    return np.stack([r * np.cos(th) * np.cos(ph), r * np.sin(th) * np.cos(ph), r * np.sin(ph)], axis=1)
 
 
 def sum_points(beams: np.ndarray, x: np.ndarray, eps: float, tau: float):

@@ -19,6 +19,7 @@
  *   - Gaussian summation of the beams                            (Sec. 2.1, eq:FGA)
  *   - flat / spherical interface map: Snell, Zoeppritz, F and W  (Sec. 3.1, eq:p:int, eq:Yilmaz, eq:Inter_DzQDzP)
  *   - point moment-tensor source weights (closed-form FBI)      (Sec. 2.1 eq:psi with f = 0)
+ *   - point force with a time function, Duhamel superposition   (Sec. 2.3 eq:ex_homo; eq:psi with f = 0)
  *
  * Readings where the paper is silent or garbled are noted at each use.
  * Parity status: every function here is pinned by a CPU test against closed
@@ -785,6 +786,128 @@ int64_t om_point_source_beams(const om_medium *m, const om_point_source *src, om
 }
 
 size_t om_point_source_size(void) { return sizeof(om_point_source); }
+
+/* Point force with a time function (the accuracy experiment of Sec. 2.3,
+ * eq:ex_homo): rho u_tt = L u + F(t) d delta(x - x0) with
+ * F(t) = cos(Omega (t + T0)) exp(-(t + T0)^2 / width^2).  Reading used here:
+ * by Duhamel's principle u(t) = int ds U(t - s; s), U(.; s) the free wave with
+ * U = 0, U_t = F(s) d delta(x - x0)/rho0 at its start, whose two-way weights
+ * (eq:psi, eq:alpha^k with f = 0) are
+ *   psi_{b,+-}(q, p; s) = +-(i eps/(2|p|)) F(s) (d.n_b)/(rho0 c_b) K(x0; q, p),
+ * FBI[delta(. - x0)] = K(x0; q, p) = exp(-i p.(x0 - q)/eps - |x0 - q|^2/(2 eps)).
+ * A beam launched at time s from (q, p) has, with the speed c = c_b(x0) near
+ * the source, the centre a beam launched at the reference time t_ref from
+ * q' = q - sigma c (s - t_ref) p/|p| has; the beams are launched at t_ref
+ * from (q', p) with the time integral of the weights folded in:
+ *   W(q', p) = int ds psi(q' + sigma c (s - t_ref) p/|p|, p; s),
+ * which is a Gaussian integral in s (v = s + T0, v0 = T0 + t_ref,
+ * D = x0 - q', D_par = D.p/|p|):
+ *   W = sigma (i eps/(2|p|)) (d.n_b)/(rho0 c) exp(-i p.D/eps - |D|^2/(2 eps))
+ *       (1/2) sum_{+-} sqrt(pi/A) exp(B_+-^2/(4A) + C),
+ *   A = 1/width^2 + c^2/(2 eps),
+ *   B_+- = c^2 v0/eps + sigma c D_par/eps + i (sigma c |p|/eps +- Omega),
+ *   C = -c^2 v0^2/(2 eps) - sigma c D_par v0/eps - i sigma c |p| v0/eps.
+ * (The beams' amplitude change over the source duration is left out.)
+ * Meshes, frames, cull and lineage as for the moment-tensor source. */
+typedef struct {
+  double eps;
+  double x0[3];
+  double d[3];           /* force vector                                  */
+  double rho0;
+  int nq;
+  double qhalf;
+  int ndir, nshell;
+  double shell_lo, shell_hi;
+  double omega, t0, width, t_ref;
+  int branch_mask;
+  double cull_abs;
+} om_point_force;
+
+size_t om_point_force_size(void) { return sizeof(om_point_force); }
+
+/* The time integral of the weights of one beam; see om_point_force. */
+static cplx om_force_time_integral(double c, double np, double dpar, int sg, const om_point_force *src)
+{
+  const double eps = src->eps, v0 = src->t0 + src->t_ref;
+  const double A = 1.0 / (src->width * src->width) + c * c / (2.0 * eps);
+  const cplx C = -c * c * v0 * v0 / (2.0 * eps) - sg * c * dpar * v0 / eps - I * (sg * c * np * v0 / eps);
+  cplx sum = 0.0;
+  for (int k = 0; k < 2; ++k) {
+    const double om = k == 0 ? src->omega : -src->omega;
+    const cplx B = c * c * v0 / eps + sg * c * dpar / eps + I * (sg * c * np / eps + om);
+    sum += sqrt(M_PI / A) * cexp(B * B / (4.0 * A) + C);
+  }
+  return 0.5 * sum;
+}
+
+int64_t om_point_force_beams(const om_medium *m, const om_point_force *src, om_beam *out)
+{
+  const int L0 = om_layer_of(m, src->x0);
+  double cP, gP[3], HP[3][3];
+  om_speed(m, 0, L0, src->x0, &cP, gP, HP);
+  const double rho0 = src->rho0 > 0.0 ? src->rho0
+                      : (m->kind == OM_LAYERED ? m->rhol[L0] : (m->rho > 0.0 ? m->rho : 1.0));
+  const int nq = src->nq, Nq = nq * nq * nq, Np = src->ndir * src->nshell;
+  const double hq = 2.0 * src->qhalf / nq, dq = hq * hq * hq;
+  double *dirs = malloc(sizeof(double) * 3 * src->ndir);
+  double *xs = malloc(sizeof(double) * src->nshell), *ws = malloc(sizeof(double) * src->nshell);
+  om_fibonacci_dirs(src->ndir, dirs);
+  const double eps = src->eps, norm = pow(2.0 * M_PI * eps, -4.5);
+  int64_t nb = 0;
+  for (int br = 0; br < 3; ++br) {
+    if (!(src->branch_mask & (1 << br))) continue;
+    const int sp = br == 0 ? 0 : 1;
+    double cb, gb[3], Hb[3][3];
+    om_speed(m, sp, L0, src->x0, &cb, gb, Hb);
+    om_gauss_legendre(src->nshell, src->shell_lo * cP / cb, src->shell_hi * cP / cb, xs, ws);
+    for (int si = 0; si < 2; ++si) {
+      const int sg = si == 0 ? 1 : -1;
+      for (int ip = 0; ip < Np; ++ip) {
+        const int sh = ip / src->ndir, dj = ip % src->ndir;
+        double p[3], ph[3];
+        for (int k = 0; k < 3; ++k) {
+          p[k] = xs[sh] * dirs[3 * dj + k];
+          ph[k] = dirs[3 * dj + k];
+        }
+        const double np = xs[sh];
+        const double dp = np * np * ws[sh] * 4.0 * M_PI / src->ndir;
+        double e[3], nh[3];
+        om_initial_axis(p, e);
+        om_polarisation(br, p, e, nh);
+        const double dn = src->d[0] * nh[0] + src->d[1] * nh[1] + src->d[2] * nh[2];
+        for (int iq = 0; iq < Nq; ++iq) {
+          const int ix = iq % nq, iy = (iq / nq) % nq, iz = iq / (nq * nq);
+          double q[3] = {src->x0[0] - src->qhalf + (ix + 0.5) * hq, src->x0[1] - src->qhalf + (iy + 0.5) * hq,
+                         src->x0[2] - src->qhalf + (iz + 0.5) * hq};
+          double D[3] = {src->x0[0] - q[0], src->x0[1] - q[1], src->x0[2] - q[2]};
+          const cplx K = cexp(-I * dot3(p, D) / eps - dot3(D, D) / (2.0 * eps));
+          const cplx gn = dn / (rho0 * cb) * K * om_force_time_integral(cb, np, dot3(D, ph), sg, src);
+          const cplx psi = om_psi(0.0, gn, sg, eps, np);
+          if (cabs(psi) < src->cull_abs) continue;
+          om_beam *b = &out[nb++];
+          memset(b, 0, sizeof(*b));
+          memcpy(b->Q, q, sizeof(q));
+          memcpy(b->P, p, sizeof(p));
+          for (int i = 0; i < 3; ++i) { b->ZQ[i][i] = 1.0; b->ZP[i][i] = -I; }
+          const double a0 = pow(2.0, 1.5);
+          if (br == 1) { b->a[0] = 0; b->a[1] = a0; }
+          else { b->a[0] = a0; b->a[1] = 0; }
+          b->w = psi * dq * dp * norm;
+          memcpy(b->e, e, sizeof(e));
+          b->branch = br;
+          b->sigma = sg;
+          b->layer = om_layer_of(m, q);
+          b->alive = 1;
+          b->lineage = ((int64_t)(br * 2 + si) * Np + ip) * Nq + iq;
+        }
+      }
+    }
+  }
+  free(dirs);
+  free(xs);
+  free(ws);
+  return nb;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Interfaces (Sec. 3.1, eq:p:int, eq:Yilmaz, eq:Inter_DzQDzP)               */

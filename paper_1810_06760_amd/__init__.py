@@ -30,6 +30,7 @@ FGA_BRANCH, FGA_SIGMA, FGA_LAYER, FGA_GEN, FGA_FLAGS, FGA_NI32 = 0, 1, 2, 3, 4, 
 FGA_FLAG_ALIVE, FGA_FLAG_QUARANTINED = 1, 2
 FGA_MEDIUM_HOMOGENEOUS, FGA_MEDIUM_GRID, FGA_MEDIUM_LAYERED = 0, 1, 2
 FGA_FP64, FGA_FP32, FGA_BF16X3, FGA_FP16X3, FGA_FP16X2 = 0, 1, 2, 3, 4
+FGA_COORDS_CARTESIAN, FGA_COORDS_SPHERICAL = 0, 1
 FGA_GRID_NODE_DOUBLES = 16
 STATUS = {0: "FGA_OK", 1: "FGA_EINVAL", 2: "FGA_ENOMEM", 3: "FGA_EDEVICE", 4: "FGA_ENUMERIC",
           5: "FGA_ECAPACITY", 6: "FGA_EUNSUPPORTED"}
@@ -76,7 +77,7 @@ class MeshC(C.Structure):
 
 class ReceiversC(C.Structure):
     _fields_ = [("n", C.c_int64), ("xyz", C.c_void_p), ("stride", C.c_int), ("eps", C.c_double),
-                ("tau", C.c_double), ("precision", C.c_int)]
+                ("tau", C.c_double), ("precision", C.c_int), ("coords", C.c_int)]
 
 
 class EvolveOptsC(C.Structure):
@@ -100,7 +101,7 @@ class RequestC(C.Structure):
     _fields_ = [("medium", MediumC), ("mesh", MeshC), ("f", C.c_void_p), ("n_receivers", C.c_int64),
                 ("receivers", C.c_void_p), ("tau", C.c_double), ("dt", C.c_double), ("nsteps", C.c_int),
                 ("stride", C.c_int), ("seis_out", C.c_void_p), ("precision", C.c_int), ("point_source", C.c_int),
-                ("source", PointSourceC)]
+                ("source", PointSourceC), ("receiver_coords", C.c_int)]
 
 
 class CompletionC(C.Structure):
@@ -425,7 +426,7 @@ def fga_decompose_point_source(medium: Medium, src: PointSourceC, beams: BeamSet
 def fga_evolve(medium: Medium, beams: BeamSet, dt: float, nsteps: int, receivers=None, eps: float = None,
                tau: float = 25.0, stride: int = 1, chunk: int = 0, cutoff_abs: float = 0.0, compact: bool = False,
                batch: int = 0, precision: int = FGA_FP64, seis=None, ws=None, resort: int = 0, gen_max: int = 0,
-               child_cut: float = 0.0):
+               child_cut: float = 0.0, coords: int = FGA_COORDS_CARTESIAN):
     """Step 2.  Returns (seis or None, stats dict).  receivers: (n,3) array;
     seis is complex [n][nsteps/stride][3] as a float64 tensor [n, ns, 3, 2].
     resort: steps between spatial reorderings (0 default, < 0 never).
@@ -438,7 +439,7 @@ def fga_evolve(medium: Medium, beams: BeamSet, dt: float, nsteps: int, receivers
     xyz = None
     if receivers is not None:
         xyz = _dev(receivers, torch.float64)
-        rec = ReceiversC(xyz.shape[0], xyz.data_ptr(), stride, eps, tau, precision)
+        rec = ReceiversC(xyz.shape[0], xyz.data_ptr(), stride, eps, tau, precision, coords)
         ns = nsteps // stride
         if seis is None:
             seis = torch.empty((xyz.shape[0], ns, 3, 2), dtype=torch.float64, device="cuda")
@@ -501,7 +502,7 @@ def workspace_bytes(kind: str, **kw) -> int:
         rec = None
         if kw.get("n_receivers"):
             rec = ReceiversC(kw["n_receivers"], 0, kw.get("stride", 1), kw["eps"], kw.get("tau", 25.0),
-                             kw.get("precision", FGA_FP64))
+                             kw.get("precision", FGA_FP64), kw.get("coords", FGA_COORDS_CARTESIAN))
         return L.fga_evolve_workspace_bytes(C.byref(kw["beams"].c), kw["nsteps"], C.byref(opts),
                                             C.byref(rec) if rec is not None else None)
     if kind == "grid":
@@ -535,7 +536,7 @@ def to_complex(t) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def make_request(medium: Medium, mesh, f, receivers, tau: float, dt: float, nsteps: int, stride: int = 1,
-                 precision: int = FGA_FP64, source: "PointSourceC" = None):
+                 precision: int = FGA_FP64, source: "PointSourceC" = None, coords: int = FGA_COORDS_CARTESIAN):
     """A forward-solve request: host initial data f (complex [3, nz, ny, nx])
     and receivers (n, 3).  Returns (RequestC, seismogram array it fills:
     complex [n, nsteps // stride, 3]); both must stay alive until completion."""
@@ -552,6 +553,7 @@ def make_request(medium: Medium, mesh, f, receivers, tau: float, dt: float, nste
     r.tau, r.dt, r.nsteps, r.stride = tau, dt, nsteps, stride
     r.seis_out = seis.ctypes.data
     r.precision = precision
+    r.receiver_coords = coords
     if source is not None:
         r.point_source = 1
         r.source = source

@@ -323,7 +323,7 @@ EvolvePlan evolve_plan(const fga_beams *b, int nsteps, const fga_evolve_opts *o,
 
 struct EvolveBufs {
   unsigned long long *ctr = nullptr;
-  double *emit = nullptr, *partial = nullptr, *xs = nullptr, *box = nullptr;
+  double *emit = nullptr, *partial = nullptr, *xs = nullptr, *box = nullptr, *xc = nullptr;
   int32_t *perm = nullptr;
   int64_t *blk_extra = nullptr, *blk_off = nullptr, *total = nullptr;  // interface step
   int32_t *cross_list = nullptr, *cross_sorted = nullptr;
@@ -353,6 +353,7 @@ EvolveBufs evolve_layout(const EvolvePlan &p, const fga_receivers *r, int64_t ca
     b.box = ar.take<double>((size_t)m * ((p.batch + 63) / 64) * 6);
     b.xs = ar.take<double>((size_t)3 * r->n + 1);
     b.perm = ar.take<int32_t>((size_t)r->n + 1);
+    if (r->coords == FGA_COORDS_SPHERICAL) b.xc = ar.take<double>((size_t)3 * r->n + 1);
   }
   return b;
 }
@@ -367,21 +368,24 @@ size_t fga_evolve_workspace_bytes(const fga_beams *beams, int nsteps, const fga_
   const EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
   Arena ar(nullptr, 0);
   evolve_layout(p, rec, beams->capacity, ar);
-  // sized for a full beam set: interface splitting can grow it up to capacity
-  if (p.resort > 0) {
-    size_t ns = 0;
-    fga_beams bb = *beams;
-    bb.count = bb.capacity;
-    sort_beams_spatial(&bb, ar, nullptr, true, &ns);
-  }
+  // the re-sort and the compaction work behind the evolution's buffers (the
+  // counters among them stay intact), sized for a full beam set: interface
+  // splitting can grow it up to capacity
+  const size_t base = Arena::need(ar.used);
   size_t need = ar.used;
+  fga_beams bb = *beams;
+  bb.count = bb.capacity;
+  if (p.resort > 0) {
+    Arena sa(nullptr, 0);
+    size_t ns = 0;
+    sort_beams_spatial(&bb, sa, nullptr, true, &ns);
+    need = need > base + ns ? need : base + ns;
+  }
   if (opts && opts->compact) {
     Arena a2(nullptr, 0);
     size_t n2 = 0;
-    fga_beams bb = *beams;
-    bb.count = bb.capacity;
     compact_beams(&bb, a2, nullptr, true, &n2);
-    need = need > n2 ? need : n2;
+    need = need > base + n2 ? need : base + n2;
   }
   return need;
 }
@@ -403,6 +407,8 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
     if (rec->precision != FGA_FP64 && rec->precision != FGA_FP32)
       return fail(FGA_EUNSUPPORTED, "receiver precision %d not built (FGA_FP64, FGA_FP32)", rec->precision);
     if (!seis && rec->n > 0 && nsteps / rec->stride > 0) return fail(FGA_EINVAL, "seis is NULL");
+    if (rec->coords != FGA_COORDS_CARTESIAN && rec->coords != FGA_COORDS_SPHERICAL)
+      return fail(FGA_EINVAL, "receiver coords must be FGA_COORDS_CARTESIAN or FGA_COORDS_SPHERICAL");
   }
   hipStream_t st = (hipStream_t)stream;
   EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
@@ -417,11 +423,20 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
   double *emit = wb.emit, *partial = wb.partial;
   if (!ctr || !wb.blk_extra || !wb.blk_off || !wb.total || !wb.cross_list || !wb.cross_sorted ||
       !wb.cross_count || !wb.cross_tmp ||
-      (rec && (!emit || !partial || !wb.box || !wb.xs || !wb.perm)))
+      (rec && (!emit || !partial || !wb.box || !wb.xs || !wb.perm ||
+               (rec->coords == FGA_COORDS_SPHERICAL && !wb.xc))))
     return fail(FGA_ENOMEM, "evolve workspace too small (%zu bytes given, %zu needed)", workspace_bytes, ar.used);
-  const size_t sort_base = ar.used;
+  const size_t sort_base = Arena::need(ar.used);  // re-sort and compaction work here, behind the counters
+  const size_t sub_bytes = workspace_bytes > sort_base ? workspace_bytes - sort_base : 0;
   FGA_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), st));
-  if (rec && rec->n > 0 && (s = sort_points(rec->xyz, rec->n, wb.xs, wb.perm, st)) != FGA_OK) return s;
+  if (rec && rec->n > 0) {
+    const double *xyz = rec->xyz;
+    if (rec->coords == FGA_COORDS_SPHERICAL) {
+      FGA_HIP(launch_spherical_to_cartesian(rec->xyz, rec->n, wb.xc, st));
+      xyz = wb.xc;
+    }
+    if ((s = sort_points(xyz, rec->n, wb.xs, wb.perm, st)) != FGA_OK) return s;
+  }
 
   const double cutoff = opts ? opts->cutoff_abs : 0.0;
   int last_sort = -1;
@@ -431,7 +446,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
     const double child_cut = (opts && opts->child_cut != 0.0) ? (opts->child_cut < 0.0 ? 0.0 : opts->child_cut) : 1e-3;
     for (int s0 = 0; s0 < nsteps; ++s0) {
       if (p.resort > 0 && (last_sort < 0 || s0 - last_sort >= p.resort)) {
-        Arena sa(static_cast<char *>(workspace) + sort_base, workspace_bytes - sort_base);
+        Arena sa(static_cast<char *>(workspace) + sort_base, sub_bytes);
         size_t need = 0;
         if ((s = sort_beams_spatial(beams, sa, st, false, &need)) != FGA_OK) return s;
         last_sort = s0;
@@ -448,7 +463,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
       a.step0 = s0;
       a.stride = 0;
       a.eps_emit = 1.0;
-      a.cutoff_abs = s0 + 1 >= nsteps ? cutoff : 0.0;
+      a.cutoff_abs = cutoff;
       a.counters = ctr;
       FGA_HIP(launch_integrate(dm, a, st));
       InterfaceArgs ia{};
@@ -517,14 +532,13 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
   }
   for (int s0 = 0; s0 < (dm.kind == FGA_MEDIUM_LAYERED ? 0 : nsteps); s0 += p.chunk) {
     if (p.resort > 0 && (last_sort < 0 || s0 - last_sort >= p.resort)) {
-      Arena sa(static_cast<char *>(workspace) + sort_base, workspace_bytes - sort_base);
+      Arena sa(static_cast<char *>(workspace) + sort_base, sub_bytes);
       size_t need = 0;
       if ((s = sort_beams_spatial(beams, sa, st, false, &need)) != FGA_OK) return s;
       last_sort = s0;
     }
     const int64_t n = beams->count;
     const int m = s0 + p.chunk <= nsteps ? p.chunk : nsteps - s0;
-    const bool last = s0 + m >= nsteps;
     int ns = 0, sfirst = 0;
     if (rec) {
       sfirst = s0 / rec->stride;
@@ -544,7 +558,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
       a.stride = (rec && ns > 0) ? rec->stride : 0;
       a.emit = emit;
       a.eps_emit = rec ? rec->eps : 1.0;
-      a.cutoff_abs = last ? cutoff : 0.0;
+      a.cutoff_abs = cutoff;
       a.counters = ctr;
       FGA_HIP(launch_integrate(dm, a, st));
       if (rec && ns > 0 && rec->n > 0) {
@@ -572,7 +586,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
       FGA_HIP(launch_reduce_points(partial, 0, ns, rec->n, wb.perm, seis, p.nsamp, sfirst, 0, st));
   }
   if (opts && opts->compact && cutoff > 0 && nsteps > 0) {
-    Arena a2(workspace, workspace_bytes);
+    Arena a2(static_cast<char *>(workspace) + sort_base, sub_bytes);
     size_t need = 0;
     if ((s = compact_beams(beams, a2, st, false, &need)) != FGA_OK) return s;
   }

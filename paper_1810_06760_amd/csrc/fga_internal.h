@@ -125,6 +125,8 @@ hipError_t launch_reduce_points(const double *partial, int nblk, int m, int64_t 
 // Copies n points (device [n][3]) into xyz_sorted in Morton order of their
 // positions and sets perm[k] = original index of sorted point k.  Synchronises st.
 fga_status sort_points(const double *xyz, int64_t n, double *xyz_sorted, int32_t *perm, hipStream_t st);
+// rtp (device [n][3]: radius, longitude, latitude) -> xyz (device [n][3])
+hipError_t launch_spherical_to_cartesian(const double *rtp, int64_t n, double *xyz, hipStream_t st);
 
 // beams -> emission records (current state, one sample)
 // box (may be NULL): also the tile boxes of the records, [ceil((end - beg) / 64)][6]

@@ -43,16 +43,24 @@ __device__ __forceinline__ void emit_record(double *__restrict__ out, int64_t nb
   sincos(y[IS] * ieps, &sn, &cs);
   const double Wr = wr * cs - wi * sn, Wi = wr * sn + wi * cs;
   const double pscale = ieps * INV_PI_128;
+  double r[12];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    out[f * nb + j] = y[IQ + f];
-    out[(3 + f) * nb + j] = y[IP + f] * pscale;  // the phase (P/eps).(x - Q) in units of pi/128
+    r[f] = y[IQ + f];
+    r[3 + f] = y[IP + f] * pscale;  // the phase (P/eps).(x - Q) in units of pi/128
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    out[(6 + 2 * c) * nb + j] = Wr * A[2 * c] - Wi * A[2 * c + 1];
-    out[(7 + 2 * c) * nb + j] = Wr * A[2 * c + 1] + Wi * A[2 * c];
+    r[6 + 2 * c] = Wr * A[2 * c] - Wi * A[2 * c + 1];
+    r[7 + 2 * c] = Wr * A[2 * c + 1] + Wi * A[2 * c];
   }
+  // a record with a non-finite entry is written as a dead one: it never
+  // enters a window, so no sum takes a NaN from it
+  bool finite = true;
+#pragma unroll
+  for (int f = 0; f < 12; ++f) finite = finite && isfinite(r[f]);
+#pragma unroll
+  for (int f = 0; f < 12; ++f) out[f * nb + j] = finite ? r[f] : (f < 3 ? -1.0e300 : 0.0);
 }
 
 __device__ __forceinline__ void emit_dead(double *__restrict__ out, int64_t nb, int64_t j)
@@ -62,6 +70,18 @@ __device__ __forceinline__ void emit_dead(double *__restrict__ out, int64_t nb, 
   for (int f = 0; f < 3; ++f) out[f * nb + j] = -1.0e300;
 #pragma unroll
   for (int f = 3; f < 12; ++f) out[f * nb + j] = 0.0;
+}
+
+// Whether the quantities a step's sample is formed from (Q, P, the
+// amplitudes and S) are finite.
+__device__ __forceinline__ bool emitted_finite(const double *y)
+{
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ok = ok && isfinite(y[IQ + d]) && isfinite(y[IP + d]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) ok = ok && isfinite(y[IA + t]);
+  return ok && isfinite(y[IS]);
 }
 
 template <int MK>
@@ -142,29 +162,49 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
       const double wr = F[FGA_W_RE * cap + i], wi = F[FGA_W_IM * cap + i];
       const double dt = a.dt;
       const double ieps = 1.0 / a.eps_emit;
-      for (int s = 0; s < a.nsteps; ++s) {
-        if constexpr (MK == MK_GRID) rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt, &blk);
-        else rk4_step_pc<MK>(med, sp, layer, sg, isS, y, dt);  // grad c = 0
-        if (isS) reframe_s(y, e);
-        if (a.stride && (a.step0 + s + 1) % a.stride == 0)
-          emit_record(a.emit + (int64_t)((a.step0 + s + 1) / a.stride - 1 - first_emit) * 12 * nb, nb, j,
-                      y, e, wr, wi, isS, ieps);
-      }
-      steps_done = (unsigned long long)a.nsteps;
-      {
-      bool finite = true;
-#pragma unroll
-      for (int f = 0; f < NS; ++f) finite = finite && isfinite(y[f]);
-      if (!finite) {
+      const double wabs = sqrt(wr * wr + wi * wi);
+      // After every step: a beam whose sampled quantities are no longer finite
+      // is quarantined, and one with |w| max|a| below the cutoff is dropped;
+      // either stops stepping and emits dead records from that step's sample on.
+      bool live = isfinite(wabs) && isfinite(e[0]) && isfinite(e[1]) && isfinite(e[2]);
+      if (!live) {
         flags = FGA_FLAG_QUARANTINED;
         quar = 1;
-      } else if (a.cutoff_abs > 0.0) {
-        const double m0 = y[IA] * y[IA] + y[IA + 1] * y[IA + 1];
-        const double m1 = y[IA + 2] * y[IA + 2] + y[IA + 3] * y[IA + 3];
-        const double amax = sqrt(m0 > m1 ? m0 : m1);
-        if (sqrt(wr * wr + wi * wi) * amax < a.cutoff_abs) {
-          flags = 0;
-          culled = 1;
+      }
+      for (int s = 0; s < a.nsteps; ++s) {
+        if (live) {
+          if constexpr (MK == MK_GRID) rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt, &blk);
+          else rk4_step_pc<MK>(med, sp, layer, sg, isS, y, dt);  // grad c = 0
+          if (isS) reframe_s(y, e);
+          ++steps_done;
+          if (!emitted_finite(y)) {
+            live = false;
+            flags = FGA_FLAG_QUARANTINED;
+            quar = 1;
+          } else if (a.cutoff_abs > 0.0) {
+            const double m0 = y[IA] * y[IA] + y[IA + 1] * y[IA + 1];
+            const double m1 = y[IA + 2] * y[IA + 2] + y[IA + 3] * y[IA + 3];
+            if (wabs * sqrt(m0 > m1 ? m0 : m1) < a.cutoff_abs) {
+              live = false;
+              flags = 0;
+              culled = 1;
+            }
+          }
+        }
+        if (a.stride && (a.step0 + s + 1) % a.stride == 0) {
+          double *rec = a.emit + (int64_t)((a.step0 + s + 1) / a.stride - 1 - first_emit) * 12 * nb;
+          if (live) emit_record(rec, nb, j, y, e, wr, wi, isS, ieps);
+          else emit_dead(rec, nb, j);
+        }
+      }
+      {
+      if (live) {
+        bool finite = true;
+#pragma unroll
+        for (int f = 0; f < NS; ++f) finite = finite && isfinite(y[f]);
+        if (!finite) {
+          flags = FGA_FLAG_QUARANTINED;
+          quar = 1;
         }
       }
       // where grad c = 0 the step leaves P and dzP as they were: not stored

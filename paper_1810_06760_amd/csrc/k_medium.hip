@@ -42,4 +42,28 @@ hipError_t launch_grid_build(const int n[3], const double h[3], const double *c,
   return hipGetLastError();
 }
 
+// Receivers given in spherical coordinates (r, theta, phi) with theta the
+// longitude and phi the latitude (the coordinates of the Earth examples,
+// opening of Sec. 3): x = (r cos theta cos phi, r sin theta cos phi, r sin phi).
+__global__ __launch_bounds__(256) void k_spherical_to_cartesian(const double *__restrict__ rtp, int64_t n,
+                                                                double *__restrict__ xyz)
+{
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double r = rtp[3 * i], th = rtp[3 * i + 1], ph = rtp[3 * i + 2];
+  double st, ct, sp, cp;
+  sincos(th, &st, &ct);
+  sincos(ph, &sp, &cp);
+  xyz[3 * i] = r * ct * cp;
+  xyz[3 * i + 1] = r * st * cp;
+  xyz[3 * i + 2] = r * sp;
+}
+
+hipError_t launch_spherical_to_cartesian(const double *rtp, int64_t n, double *xyz, hipStream_t st)
+{
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spherical_to_cartesian, (unsigned)((n + 255) / 256), 256, 0, st, rtp, n, xyz);
+  return hipGetLastError();
+}
+
 }  // namespace fga

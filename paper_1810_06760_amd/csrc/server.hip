@@ -1,18 +1,24 @@
 // Request server for many forward solves on one GPU (tomography sweeps).
 //
 // Requests (initial data + receivers on a resident velocity model) queue on
-// the host.  A fixed set of slots, each a host thread with its own HIP
-// stream, takes the first queued request whose device footprint fits the
-// budget next to the requests already running; a slot runs its request to
-// completion (decompose -> evolve with receiver sums -> seismograms to host)
-// and frees its memory, and the next request is admitted as soon as a slot
-// and memory are free.  Running requests overlap on the device through their
-// separate streams.  Every solve is deterministic and uses only its own
-// buffers, so a result is the same alone or in a mix.
+// the host.  The server holds one device pool of the budget's size, taken
+// once at creation; a request's buffers (beams, workspace, inputs,
+// seismograms) are one block of that pool, found first-fit, so a solve never
+// calls hipMalloc or hipFree (hipFree would synchronise the whole device and
+// stall the other slots).  A fixed set of slots, each a host thread with its
+// own HIP stream, takes the first queued request whose block fits in the pool
+// next to the running ones; a slot runs its request to completion (decompose
+// -> evolve with receiver sums -> seismograms to host), returns the block, and
+// the next request is admitted as soon as a slot and a block are free.
+// Running requests overlap on the device through their separate streams.
+// Every solve is deterministic and uses only its own block, so a result is
+// the same alone or in a mix.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <iterator>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -32,6 +38,7 @@ bool request_sizes(const fga_request *r, Sizes *z)
 {
   if (!r || r->nsteps < 0 || r->stride < 1 || r->n_receivers < 0) return false;
   if (r->precision != FGA_FP64 && r->precision != FGA_FP32) return false;
+  if (r->receiver_coords != FGA_COORDS_CARTESIAN && r->receiver_coords != FGA_COORDS_SPHERICAL) return false;
   const int64_t cand = r->point_source ? fga_point_source_candidates(&r->source) : fga_decompose_candidates(&r->mesh);
   if (cand <= 0) return false;
   // layered media grow the beam set at interfaces
@@ -56,6 +63,7 @@ bool request_sizes(const fga_request *r, Sizes *z)
   rc.eps = r->point_source ? r->source.eps : r->mesh.eps;
   rc.tau = r->tau;
   rc.precision = r->precision;
+  rc.coords = r->receiver_coords;
   const size_t wd = r->point_source ? fga_decompose_point_source_workspace_bytes(&r->source)
                                     : fga_decompose_workspace_bytes(&r->mesh, 0);
   const size_t we = fga_evolve_workspace_bytes(&b, r->nsteps, nullptr, r->n_receivers > 0 ? &rc : nullptr);
@@ -75,6 +83,50 @@ struct Job {
   std::vector<double> f, rec;
   Sizes sz;
   double t_submit;
+  size_t off = 0;  // the request's block in the pool
+};
+
+// First-fit allocator of 256-byte-aligned blocks in [0, size), free blocks
+// coalesced with their neighbours on release (host bookkeeping only).
+class BlockPool {
+ public:
+  void reset(size_t size)
+  {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool take(size_t n, size_t *off)
+  {
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n;
+        const size_t at = it->first + n;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    return false;
+  }
+  void give(size_t off, size_t n)
+  {
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;  // offset -> length
 };
 
 }  // namespace
@@ -82,6 +134,8 @@ struct Job {
 struct fga_server {
   int device = 0;
   size_t budget = 0;
+  char *pool = nullptr;  // device, `budget` bytes
+  BlockPool blocks;
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -105,14 +159,8 @@ fga_completion fga_server::run(Job &j, hipStream_t st)
   c.t_start = now_s(t0);
   c.footprint = j.sz.total;
   const fga_request &r = j.req;
-  char *buf = nullptr;
   fga_status s = FGA_OK;
-  if (hipMalloc(&buf, j.sz.total) != hipSuccess) {
-    c.status = FGA_ENOMEM;
-    c.t_done = now_s(t0);
-    return c;
-  }
-  char *p = buf;
+  char *p = pool + j.off;
   fga_beams b{};
   b.capacity = j.sz.capacity;
   b.count = 0;
@@ -148,6 +196,7 @@ fga_completion fga_server::run(Job &j, hipStream_t st)
     rc.eps = r.point_source ? r.source.eps : r.mesh.eps;
     rc.tau = r.tau;
     rc.precision = r.precision;
+    rc.coords = r.receiver_coords;
     fga_evolve_stats es{};
     if ((s = fga_evolve(&r.medium, &b, r.dt, r.nsteps, nullptr, r.n_receivers > 0 ? &rc : nullptr, sd, ws, j.sz.ws,
                         st, &es)) != FGA_OK)
@@ -163,7 +212,6 @@ fga_completion fga_server::run(Job &j, hipStream_t st)
     if (hipStreamSynchronize(st) != hipSuccess) s = FGA_EDEVICE;
   } while (false);
   (void)hipStreamSynchronize(st);
-  (void)hipFree(buf);
   c.status = s;
   c.t_done = now_s(t0);
   return c;
@@ -179,12 +227,14 @@ void fga_server::slot_main()
     {
       std::unique_lock<std::mutex> lk(mu);
       for (;;) {
-        // first queued request that fits next to the running ones
+        // first queued request whose block fits in the pool next to the running ones
         auto it = queue.begin();
+        size_t off = 0;
         for (; it != queue.end(); ++it)
-          if (held + it->sz.total <= budget) break;
+          if (blocks.take(it->sz.total, &off)) break;
         if (it != queue.end()) {
           j = std::move(*it);
+          j.off = off;
           queue.erase(it);
           held += j.sz.total;
           ++running;
@@ -205,6 +255,7 @@ void fga_server::slot_main()
     }
     {
       std::lock_guard<std::mutex> lk(mu);
+      blocks.give(j.off, j.sz.total);
       held -= j.sz.total;
       --running;
       done.push_back(c);
@@ -230,7 +281,13 @@ fga_status fga_server_create(size_t hbm_budget, int max_active, fga_server **out
     delete s;
     return fga::fail(FGA_EDEVICE, "no current HIP device");
   }
-  s->budget = hbm_budget;
+  s->budget = hbm_budget & ~size_t(255);  // footprints are multiples of 256 bytes
+  if (s->budget == 0 || hipMalloc(&s->pool, s->budget) != hipSuccess) {
+    (void)hipGetLastError();
+    delete s;
+    return fga::fail(FGA_ENOMEM, "cannot hold a device pool of %zu bytes for the server budget", hbm_budget);
+  }
+  s->blocks.reset(s->budget);
   s->t0 = std::chrono::steady_clock::now();
   for (int k = 0; k < max_active; ++k) s->slots.emplace_back([s] { s->slot_main(); });
   *out = s;
@@ -301,6 +358,8 @@ fga_status fga_server_destroy(fga_server *s)
   }
   s->cv_work.notify_all();
   for (auto &t : s->slots) t.join();
+  // every slot has synchronised its stream after its last solve
+  if (s->pool) (void)hipFree(s->pool);
   delete s;
   return FGA_OK;
 }

@@ -91,3 +91,4 @@ def test_fga_converges_to_exact_solution():
     # measured: 0.036, 0.016, 0.0089 -- the error halves with eps
     assert e64 < 0.65 * e32 and e128 < 0.7 * e64
     assert e128 < 0.012
+

@@ -167,6 +167,61 @@ def test_mixed_grid_256():
 
 
 @pytest.mark.timeout(900)
+def test_mixed_grid_256_against_oracle():
+    """The mixed-precision workload at its own sizes (eps = 1/512, q 50^3 x
+    p 8^3 x 3 branches, second of its four z-slab waves, 250 FP64 RK4 steps
+    in the smooth random medium, 256^3 grid with tau = 16) on a seeded subset
+    the oracle can decompose and evolve: 2,000 (q, p) pairs of the wave,
+    decomposed by the oracle's own quadrature on the 256^3 y mesh.  The GPU
+    takes the beams of the same lineages from its decomposition of the whole
+    wave, evolves them and sums them on the full 256^3 grid with every
+    variant; at 2,000 seeded grid points the FP64 tiles equal the oracle's
+    direct sum to 1e-10 and every mixed variant is within 1e-3 of it."""
+    import torch
+    import paper_1810_06760_amd as m
+    m.lib()
+    say("mixed grid vs oracle: eps 1/512, q 50^3 x p 8^3 x 3, wave 2 of 4, 2000-pair subset")
+    w, slabs = fi.mixed_waves(nq=50, waves=4)
+    qm = slabs[1]
+    med = m.medium_for(w)
+    mesh = m.make_mesh(w.eps, qm, w.pmesh, w.ymesh, cull_abs=w.cull_abs)
+    full = m.fga_decompose(med, mesh, m._complex_dev(w.f))
+    say("  wave beams", full.count)
+    g = np.random.default_rng(4401)
+    pick = g.choice(qm.count * w.pmesh.count, size=2000, replace=False)
+    iq, ip = pick % qm.count, pick // qm.count
+    Ft = om.fbi(w.f, w.ymesh, qm.points()[iq], w.pmesh.points()[ip], w.eps)
+    ob = om.make_beams(qm, w.pmesh, Ft, w.eps, iq, ip, one_way=True, cull_abs=w.cull_abs)
+    # the GPU beams of the subset's lineages (kept by the GPU's own cull)
+    lin_gpu = full.lineage[:full.count].cpu().numpy()
+    base = (ip * qm.count + iq).astype(np.int64)
+    want = np.sort(np.concatenate([base + b * 2 * w.pmesh.count * qm.count for b in range(3)]))
+    slots = np.searchsorted(lin_gpu, want)
+    slots = slots[(slots < len(lin_gpu)) & (lin_gpu[np.minimum(slots, len(lin_gpu) - 1)] == want)]
+    sub = full.export(torch.from_numpy(slots).to("cuda"))
+    del full
+    torch.cuda.empty_cache()
+    assert np.array_equal(sub["lineage"], ob["lineage"]), (len(sub["lineage"]), len(ob))
+    beams = m.BeamSet(len(ob))
+    beams.load(sub)
+    m.fga_evolve(med, beams, w.dt, w.nsteps, resort=-1)
+    om.evolve(om.medium_for(w), ob, w.dt, w.nsteps)
+    say("  subset beams", len(ob))
+    n = w.out_grid.n[0]
+    sel = np.random.default_rng(4402).choice(w.out_grid.count, size=2000, replace=False)
+    ref, _ = om.sum_points(ob, w.out_grid.points()[sel], w.eps, w.tau)
+    zi, yi, xi = (torch.from_numpy(v).to("cuda") for v in (sel // (n * n), (sel // n) % n, sel % n))
+    for prec, tol in (("FGA_FP64", RTOL), ("FGA_FP32", 1e-3), ("FGA_BF16X3", 1e-3), ("FGA_FP16X3", 1e-3),
+                      ("FGA_FP16X2", 1e-3)):
+        u, _ = m.fga_reconstruct_grid(beams, w.eps, w.tau, w.out_grid, precision=getattr(m, prec))
+        got = m.to_complex(u[:, zi, yi, xi])
+        e = rel_l2(got.T, ref)
+        say("  %s vs oracle at 2000 grid points: %.3g" % (prec, e))
+        assert e <= tol
+        del u
+
+
+@pytest.mark.timeout(900)
 def test_layered_earth_full_size():
     """The layered Earth workload at its full size: a point moment-tensor
     source at eps = 1/256 (q 8^3 x 1600 directions x 4 shells x 3 branches x
@@ -178,7 +233,9 @@ def test_layered_earth_full_size():
     lineages with all their descendants; the GPU beams of the same lineages
     match them (lineage, generation, layer, branch and sigma exactly; states
     and amplitudes to 1e-10).  The last seismogram sample equals a point sum
-    at the receivers over the final beams."""
+    at the receivers over the final beams; the stations are given to the
+    library in spherical coordinates and to the point sum as the oracle maps
+    them."""
     import torch
     import paper_1810_06760_amd as m
     m.lib()
@@ -193,13 +250,14 @@ def test_layered_earth_full_size():
     m.fga_decompose_point_source(med_g, src, beams=beams)
     n0 = beams.count
     say("  decomposed", n0)
-    rec = m._dev(e["receivers"], torch.float64)
+    rec = m._dev(e["receivers_rtp"], torch.float64)        # stations as (r, longitude, latitude)
     nrec = rec.shape[0]
     ws = m._workspace(m.workspace_bytes("evolve", beams=beams, nsteps=seg, n_receivers=nrec, eps=e["eps"],
-                                        tau=e["tau"]))
+                                        tau=e["tau"], coords=m.FGA_COORDS_SPHERICAL))
     seis = torch.empty((nrec, nsteps, 3, 2), dtype=torch.float64, device="cuda")
     for s0 in range(0, nsteps, seg):
-        part, _ = m.fga_evolve(med_g, beams, e["dt"], seg, receivers=rec, eps=e["eps"], tau=e["tau"], ws=ws)
+        part, _ = m.fga_evolve(med_g, beams, e["dt"], seg, receivers=rec, eps=e["eps"], tau=e["tau"], ws=ws,
+                               coords=m.FGA_COORDS_SPHERICAL)
         seis[:, s0:s0 + seg].copy_(part)
         say("  steps", s0 + seg, "beams", beams.count)
     torch.cuda.synchronize()
@@ -227,7 +285,7 @@ def test_layered_earth_full_size():
     A_ref = om.amplitude_vectors(out[keep][np.argsort(out["lineage"][keep], kind="stable")])
     assert rel_l2(phys_amp_gpu(g), A_ref) <= RTOL
 
-    ur, _ = m.fga_reconstruct_points(beams, e["eps"], e["tau"], e["receivers"])
+    ur, _ = m.fga_reconstruct_points(beams, e["eps"], e["tau"], om.spherical_to_cartesian(e["receivers_rtp"]))
     err = rel_l2(m.to_complex(seis[:, -1]), m.to_complex(ur))
     say("  seismogram vs points", err)
     assert err <= RTOL

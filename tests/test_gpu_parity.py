@@ -174,6 +174,51 @@ def test_decompose_cull_parity():
     assert np.all(np.diff(g["lineage"]) > 0)
 
 
+def two_way_velocity(w):
+    """A seeded initial velocity on the work's quadrature mesh: a second
+    Gaussian packet (own polarisation, amplitude 2, wave vector (1, 0.5, 0))."""
+    d = fi.unit_vector(fi.rng(2, 77))
+    return 2.0 * fi.gaussian_plane_wave(w.ymesh, w.eps, (0.45, 0.5, 0.55), 0.12, (1.0, 0.5, 0.0), d)
+
+
+@pytest.mark.parametrize("case,cull", [("homogeneous", False), ("grid", False), ("grid", True)])
+def test_decompose_two_way_parity(case, cull):
+    """Step 1 with both directions and u_t(0) = g != 0 (eq:psi, eq:alpha^k):
+    psi_{b,+-} = 1/2 FBI[f].n_b +- (i eps/(2|p|)) FBI[g/c_b].n_b, with c_b
+    taken from the medium at the quadrature points; with a cull at the median
+    |psi| the kept sets agree outside a 1e-9 band around the threshold."""
+    m = fga()
+    say("decompose two-way parity", case, cull)
+    w = small_c1(nq=4, np_=3, ny=16) if case == "homogeneous" else small_c2(nq=4, np_=3, ny=16, nmed=16)
+    w.cull_abs = 0.0
+    g = two_way_velocity(w)
+    ob_all = om.decompose_two_way(w, g)
+    n_all, n_cand = len(ob_all), 6 * w.qmesh.count * w.pmesh.count
+    assert n_all == n_cand, (n_all, n_cand)
+    norm = w.qmesh.cell_volume * w.pmesh.cell_volume * (2 * math.pi * w.eps) ** -4.5
+    if cull:
+        psi_abs = np.abs(ob_all["w"])
+        thr = np.quantile(psi_abs, 0.5)
+        w.cull_abs = thr / norm
+    bs = m.fga_decompose(m.medium_for(w), m.mesh_for(w, one_way=False), w.f, g=g)
+    gexp = bs.export()
+    assert np.all(np.diff(gexp["lineage"]) > 0)
+    if not cull:
+        assert bs.count == len(ob_all)
+        assert np.array_equal(gexp["lineage"], ob_all["lineage"])
+        assert np.array_equal(gexp["sigma"], ob_all["sigma"])
+        assert rel_l2(gexp["w"], ob_all["w"]) <= RTOL
+        compare_states(gexp, ob_all)
+        return
+    keep_o = set(ob_all["lineage"][psi_abs >= thr].tolist())
+    amb = set(ob_all["lineage"][np.abs(psi_abs - thr) <= 1e-9 * thr].tolist())
+    keep_g = set(gexp["lineage"].tolist())
+    assert keep_o - amb <= keep_g and keep_g - amb <= keep_o
+    both = np.isin(ob_all["lineage"], gexp["lineage"])
+    sel = np.isin(gexp["lineage"], ob_all["lineage"][both])
+    assert rel_l2(gexp["w"][sel], ob_all["w"][both]) <= RTOL
+
+
 def evolved_beams(w, nsteps, dt):
     ob = om.decompose(w)
     om.evolve(om.medium_for(w), ob, dt, nsteps)
@@ -342,6 +387,98 @@ def test_seismogram_parity():
     assert rel_l2(m.to_complex(seis), ref) <= RTOL
 
 
+def amp_measure(ob):
+    """|w| max(|a0|, |a1|) of oracle beams (the cutoff's measure)."""
+    return np.abs(ob["w"]) * np.max(np.abs(ob["a"]), axis=1)
+
+
+@pytest.mark.parametrize("compact", [False, True])
+def test_evolve_cutoff_parity(compact):
+    """Culling after every step (the benchmark spec: beams whose amplitude falls below
+    the cutoff are dropped): the oracle steps all beams one step at a time,
+    drops those with |w| max|a| < cutoff after each step and sums the rest at
+    the receivers; the GPU (chunks of 7 steps, receivers every step) must
+    drop the same lineages (no decision within 1e-9 of the threshold), count
+    them, keep the survivors' states and give the same seismograms."""
+    m = fga()
+    say("evolve cutoff parity, compact", compact)
+    w = small_c2(nq=4, np_=3, ny=16)
+    ob = om.decompose(w)
+    n0 = len(ob)
+    cut = float(np.quantile(amp_measure(ob), 0.35))
+    bs = m.BeamSet(n0)
+    bs.load(oracle_to_dict(ob))
+    rec = w.receivers
+    nsteps, dt = 60, 2e-3
+    seis, st = m.fga_evolve(m.medium_for(w), bs, dt, nsteps, receivers=rec, eps=w.eps, tau=w.tau, chunk=7,
+                            cutoff_abs=cut, compact=compact, resort=-1)
+    med_o = om.medium_for(w)
+    ref = np.zeros((len(rec), nsteps, 3), dtype=np.complex128)
+    closest = np.inf
+    steps = 0
+    for s in range(nsteps):
+        live = ob["alive"] == 1
+        steps += int(live.sum())
+        om.evolve(med_o, ob, dt, 1)
+        meas = amp_measure(ob)
+        closest = min(closest, float(np.min(np.abs(meas[live] / cut - 1.0))))
+        ob["alive"][live & (meas < cut)] = 0
+        ref[:, s, :], _ = om.sum_points(ob, rec, w.eps, w.tau)
+    assert closest > 1e-9, closest                       # no decision at the threshold
+    kept = ob["alive"] == 1
+    say("  %d beams, %d culled by the oracle, %d by the GPU" % (n0, n0 - kept.sum(), st["culled"]))
+    assert 0 < st["culled"] == n0 - int(kept.sum())
+    assert st["beam_steps"] == steps
+    g = bs.export()
+    if compact:
+        assert bs.count == int(kept.sum())
+        assert np.all(g["flags"] == m.FGA_FLAG_ALIVE)
+    else:
+        assert bs.count == n0
+        assert np.array_equal(g["flags"] == m.FGA_FLAG_ALIVE, kept)
+        g = {k: v[g["flags"] == m.FGA_FLAG_ALIVE] for k, v in g.items()}
+    compare_states(g, om.take_beams(ob, np.nonzero(kept)[0]))
+    assert rel_l2(m.to_complex(seis), ref) <= RTOL
+
+
+@pytest.mark.parametrize("case", ["homogeneous", "grid"])
+def test_quarantine_non_finite_beam(case):
+    """A beam loaded with a NaN in dzQ (its amplitude turns non-finite in the
+    first step) is quarantined and counted, takes no further step, and no
+    seismogram sample takes a NaN from it; every other beam and the
+    seismograms equal the oracle's without that beam."""
+    m = fga()
+    say("quarantine", case)
+    w = small_c1(nq=4, np_=2) if case == "homogeneous" else small_c2(nq=4, np_=2, ny=16)
+    ob = om.decompose(w)
+    bad = len(ob) // 3
+    d = oracle_to_dict(ob)
+    d["ZQ"] = d["ZQ"].copy()
+    d["ZQ"][bad, 1, 1] = np.nan
+    bs = m.BeamSet(len(ob))
+    bs.load(d)
+    rec = fi.uniform_points(12, fi.rng(1, 55)) if w.receivers is None else w.receivers
+    nsteps, dt = 20, 2e-3
+    seis, st = m.fga_evolve(m.medium_for(w), bs, dt, nsteps, receivers=rec, eps=w.eps, tau=w.tau, chunk=6,
+                            resort=-1)
+    assert st["quarantined"] == 1 and st["culled"] == 0
+    g = bs.export()
+    assert g["flags"][bad] == m.FGA_FLAG_QUARANTINED
+    others = np.arange(len(ob)) != bad
+    assert np.all(g["flags"][others] == m.FGA_FLAG_ALIVE)
+    assert st["beam_steps"] == nsteps * (len(ob) - 1) + 1
+    ob["alive"][bad] = 0
+    med_o = om.medium_for(w)
+    ref = np.zeros((len(rec), nsteps, 3), dtype=np.complex128)
+    for s in range(nsteps):
+        om.evolve(med_o, ob, dt, 1)
+        ref[:, s, :], _ = om.sum_points(ob, rec, w.eps, w.tau)
+    out = m.to_complex(seis)
+    assert np.all(np.isfinite(out))
+    assert rel_l2(out, ref) <= RTOL
+    compare_states({k: v[others] for k, v in g.items()}, om.take_beams(ob, np.nonzero(others)[0]))
+
+
 def test_seismogram_mixed_precision():
     m = fga()
     say("seismogram mixed")
@@ -461,6 +598,33 @@ def test_interface_seismogram_parity(batch):
         cnt += c
     assert st["spawned"] > 0
     assert st["evals"] == cnt
+    assert rel_l2(m.to_complex(seis), ref) <= RTOL
+
+
+def test_spherical_receivers_parity():
+    """Stations given as (r, longitude, latitude) (opening of Sec. 3) are
+    mapped by the library; a layered run in the spherical-shell model samples
+    them as the oracle does at its own mapping of the same coordinates."""
+    m = fga()
+    say("spherical receivers")
+    w, ob, med_o, med_g = layered_case("sphere")
+    g = np.random.default_rng(19)
+    rtp = np.stack([g.uniform(0.75, 0.95, 11), g.uniform(0.6, 1.0, 11), g.uniform(0.45, 0.8, 11)], axis=1)
+    nsteps, dt, tau, stride = 24, 0.005, 25.0, 2
+    bs = m.BeamSet(4 * len(ob))
+    bs.load(oracle_to_dict(ob))
+    seis, st = m.fga_evolve(med_g, bs, dt, nsteps, receivers=rtp, eps=w.eps, tau=tau, stride=stride,
+                            coords=m.FGA_COORDS_SPHERICAL)
+    x = om.spherical_to_cartesian(rtp)
+    ref = np.zeros((len(rtp), nsteps // stride, 3), dtype=np.complex128)
+    cnt = 0
+    cur = ob.copy()
+    for s in range(nsteps // stride):
+        cur, _ = om.evolve_layered(med_o, cur, dt, stride, gmax=3, child_cut=1e-3)
+        cur = cur[cur["alive"] == 1].copy()
+        ref[:, s, :], c = om.sum_points(cur, x, w.eps, tau)
+        cnt += c
+    assert st["evals"] == cnt > 0
     assert rel_l2(m.to_complex(seis), ref) <= RTOL
 
 

@@ -429,3 +429,22 @@ def test_grid_medium_second_order():
     for k in range(3):
         r = errs[1][k] / errs[2][k]
         assert 3.0 < r < 5.5, (k, errs)
+
+
+# ---------------------------------------------------------------------------
+# Station coordinates of the Earth examples (radius, longitude, latitude)
+# ---------------------------------------------------------------------------
+
+def test_spherical_station_coordinates():
+    """The axes land where the coordinates name them, the radius is the
+    distance from the centre, and the longitude and latitude are recovered
+    by arctan2 and arcsin of the Cartesian point."""
+    axes = om.spherical_to_cartesian([[1, 0, 0], [1, math.pi / 2, 0], [1, 0, math.pi / 2], [2, math.pi, 0],
+                                      [3, -math.pi / 2, -math.pi / 2]])
+    assert np.allclose(axes, [[1, 0, 0], [0, 1, 0], [0, 0, 1], [-2, 0, 0], [0, 0, -3]], atol=1e-15)
+    g = np.random.default_rng(8)
+    rtp = np.stack([g.uniform(0.2, 2.0, 50), g.uniform(-math.pi, math.pi, 50), g.uniform(-1.5, 1.5, 50)], axis=1)
+    x = om.spherical_to_cartesian(rtp)
+    assert np.allclose(np.linalg.norm(x, axis=1), rtp[:, 0], rtol=1e-14)
+    assert np.allclose(np.arctan2(x[:, 1], x[:, 0]), rtp[:, 1], atol=1e-13)
+    assert np.allclose(np.arcsin(x[:, 2] / rtp[:, 0]), rtp[:, 2], atol=1e-13)

@@ -197,3 +197,47 @@ def test_footprint_is_a_host_query():
     more_beams = m.make_request(m.medium_for(w2), m.mesh_for(w2), w2.f, np.zeros((4, 3)), 25.0, 0.005, 20, 1)[0]
     f0, f1, f2 = (m.Server.footprint(r) for r in (small, more_rec, more_beams))
     assert 0 < f0 < f1 and f0 < f2
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_served_solve_matches_oracle(precision):
+    """A served point-source solve in a smooth grid medium (the sweep's model
+    recipe) against the oracle's decompose -> evolve -> sum at the receivers
+    (Steps 1-3): relative L2 <= 1e-10 in FP64, <= 1e-3 with the mixed
+    receiver sums; a second, larger request served beside it changes nothing."""
+    import oracle as om
+    m = fga()
+    say("served solve vs oracle", precision)
+    nodes = fi.sweep_model(1, nmed=32)
+    mesh = fi.node_grid(32)
+    med = m.Medium.grid(nodes, mesh, cs_ratio=1.0 / np.sqrt(3.0))
+    rq = fi.sweep_request(3, nsteps=30)
+    eps, nsteps, dt, stride = 1.0 / 32, 30, 2e-3, 3
+    src = m.point_source(eps, rq["x0"], rq["M"], nq=3, ndir=16, nshell=2)
+    x = rq["receivers"][:10]
+    prec = m.FGA_FP64 if precision == "fp64" else m.FGA_FP32
+    other = m.point_source(eps, rq["x0"] + 0.05, rq["M"], nq=4, ndir=24, nshell=2)
+    srv = m.Server(1 << 32, 2)
+    try:
+        r, seis, keep = m.make_request(med, None, None, x, 25.0, dt, nsteps, stride, precision=prec, source=src)
+        r2, seis2, keep2 = m.make_request(med, None, None, rq["receivers"][:40], 25.0, dt, nsteps, 1,
+                                          precision=prec, source=other)
+        srv.submit(r2, keep=(keep2, seis2))
+        srv.submit(r, keep=(keep, seis))
+        got = []
+        while len(got) < 2:
+            got += srv.poll(4, wait_ms=20000)
+    finally:
+        srv.close()
+    assert all(c["status"] == 0 for c in got)
+    med_o = om.grid(nodes, mesh, cs_ratio=1.0 / np.sqrt(3.0))
+    src_o = om.point_source(eps, rq["x0"], rq["M"], nq=3, ndir=16, nshell=2)
+    ob = om.point_source_beams(med_o, src_o)
+    ref = np.zeros((len(x), nsteps // stride, 3), dtype=np.complex128)
+    for s in range(nsteps // stride):
+        om.evolve(med_o, ob, dt, stride)
+        ref[:, s, :], _ = om.sum_points(ob, x, eps, 25.0)
+    err = np.linalg.norm(seis - ref) / np.linalg.norm(ref)
+    say("  rel-L2 vs oracle %.2e (%d beams)" % (err, len(ob)))
+    assert err <= (1e-10 if precision == "fp64" else 1e-3)
