@@ -334,6 +334,26 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
                                   void *workspace, size_t workspace_bytes, void *stream,
                                   int64_t *evals);
 
+/* The sum of fga_reconstruct_points for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments without a workspace.  Its records,
+ * tile boxes, partial sums and term counter live in a fixed scratch array
+ * that the library holds on each device it runs on until the process ends
+ * (fga_reconstruct_points_noalloc_max_bytes() bytes, 64 MiB); the call itself
+ * allocates nothing.  Beams are taken in batches of whole 64-beam tiles sized
+ * so that records and partial sums fit; the points are used in the order
+ * given (fga_reconstruct_points first sorts them by position, which only
+ * speeds up the sum), and must be finite (not checked).  Every call on a
+ * device shares that device's scratch: calls that overlap on one device (on
+ * different streams or host threads) race and give wrong results.  The
+ * counter is cleared by a kernel, not a memset.
+ * Errors: as fga_reconstruct_points; FGA_ENOMEM when n points need more
+ * scratch than the array holds even for one tile (about 1.3 million points). */
+size_t fga_reconstruct_points_noalloc_max_bytes(void);
+fga_status fga_reconstruct_points_noalloc(const fga_beams *beams, double eps, double tau, int64_t n,
+                                          const double *xyz, int precision, double *out, void *stream,
+                                          int64_t *evals);
+
 /* The same sum on the grid points lo + i*h (i < n per axis), using the
  * separability of the window and the phase: each 16^3 tile is a complex
  * Khatri-Rao x factor product on the matrix cores.  out: device complex

@@ -38,7 +38,8 @@ STATUS = {0: "FGA_OK", 1: "FGA_EINVAL", 2: "FGA_ENOMEM", 3: "FGA_EDEVICE", 4: "F
 EXPORTED = ["fga_last_error", "fga_version", "fga_medium_grid_table_bytes", "fga_medium_grid_build",
             "fga_decompose_workspace_bytes", "fga_decompose_candidates", "fga_decompose",
             "fga_evolve_workspace_bytes", "fga_evolve", "fga_reconstruct_points_workspace_bytes",
-            "fga_reconstruct_points", "fga_reconstruct_grid_workspace_bytes", "fga_reconstruct_grid",
+            "fga_reconstruct_points", "fga_reconstruct_points_noalloc_max_bytes", "fga_reconstruct_points_noalloc",
+            "fga_reconstruct_grid_workspace_bytes", "fga_reconstruct_grid",
             "fga_reconstruct_grid_add",
             "fga_profile_enable", "fga_profile_read", "fga_server_footprint", "fga_server_create",
             "fga_server_submit", "fga_server_poll", "fga_server_status", "fga_server_destroy",
@@ -142,6 +143,10 @@ def lib():
         L.fga_reconstruct_points_workspace_bytes.argtypes = [vp, i64]
         L.fga_reconstruct_points.restype = st
         L.fga_reconstruct_points.argtypes = [vp, C.c_double, C.c_double, i64, vp, C.c_int, vp, vp, sz, vp, vp]
+        L.fga_reconstruct_points_noalloc_max_bytes.restype = sz
+        L.fga_reconstruct_points_noalloc_max_bytes.argtypes = []
+        L.fga_reconstruct_points_noalloc.restype = st
+        L.fga_reconstruct_points_noalloc.argtypes = [vp, C.c_double, C.c_double, i64, vp, C.c_int, vp, vp, vp]
         L.fga_reconstruct_grid_workspace_bytes.restype = sz
         L.fga_reconstruct_grid_workspace_bytes.argtypes = [vp, vp, C.c_double, C.c_double, vp]
         L.fga_reconstruct_grid.restype = st
@@ -468,6 +473,20 @@ def fga_reconstruct_points(beams: BeamSet, eps: float, tau: float, xyz, precisio
     _check(L.fga_reconstruct_points(C.byref(beams.c), eps, tau, n, _ptr(x), precision, _ptr(out), _ptr(ws),
                                     ws.numel(), _stream(), C.byref(ev)))
     return out, ev.value
+
+
+def fga_reconstruct_points_noalloc(beams: BeamSet, eps: float, tau: float, xyz, out,
+                                   precision: int = FGA_FP64, want_evals: bool = True):
+    """Step 3 at points without any allocation in the call: xyz (device
+    float64 [n,3]) and out (device float64 [n,3,2]) are caller tensors; the
+    library's fixed per-device scratch holds everything else.  Returns
+    (out, evals or None)."""
+    L = lib()
+    n = int(xyz.shape[0])
+    ev = C.c_int64(0)
+    _check(L.fga_reconstruct_points_noalloc(C.byref(beams.c), eps, tau, n, _ptr(xyz), precision, _ptr(out),
+                                            _stream(), C.byref(ev) if want_evals else None))
+    return out, (ev.value if want_evals else None)
 
 
 def fga_reconstruct_grid(beams: BeamSet, eps: float, tau: float, mesh, precision: int = FGA_FP64, out=None,

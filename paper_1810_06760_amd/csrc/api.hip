@@ -4,6 +4,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "device_common.h"
@@ -672,6 +673,130 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
     int nblk = 0;
     FGA_HIP(launch_sum_points(pa, &nblk, st));
     FGA_HIP(launch_reduce_points(partial, nblk, 1, n, perm, out, 1, 0, b0 > 0 ? 1 : 0, st));
+  }
+  if (evals) {
+    unsigned long long h = 0;
+    FGA_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, st));
+    FGA_HIP(hipStreamSynchronize(st));
+    *evals = (int64_t)h;
+  }
+  return FGA_OK;
+}
+
+// ------------------------------------------ points without allocation --
+
+}  // extern "C"
+
+namespace {
+
+// Scratch memory of fga_reconstruct_points_noalloc: one array per device,
+// held by the code object until the process ends.  Host code never uses the
+// array's name as a device address: the address of each device's copy comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+__attribute__((used)) static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+fga_status scratch_of_current_device(char **out)
+{
+  int dev = -1;
+  FGA_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FGA_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FGA_EDEVICE, "hipGetSymbolAddress of the scratch array failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<char *>(g_scratch_ptr[dev]);
+  return FGA_OK;
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n)
+{
+  const int i = threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// Bytes of the no-allocation layout for `batch` beams and n points (the
+// carving below in the same order).
+size_t noalloc_bytes(int64_t batch, int64_t n)
+{
+  Arena ar(nullptr, 0);
+  ar.take<unsigned long long>(1);
+  ar.take<double>((size_t)12 * batch);
+  const int bpb = points_beams_per_block(batch, n, 1);
+  ar.take<double>((size_t)((batch + bpb - 1) / bpb) * n * 6);
+  ar.take<double>((size_t)((batch + 63) / 64) * 6);
+  return ar.used;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fga_reconstruct_points_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+fga_status fga_reconstruct_points_noalloc(const fga_beams *beams, double eps, double tau, int64_t n,
+                                          const double *xyz, int precision, double *out, void *stream,
+                                          int64_t *evals)
+{
+  fga_status s;
+  if ((s = check_beams(beams)) != FGA_OK) return s;
+  if (n < 0 || (n > 0 && (!xyz || !out))) return fail(FGA_EINVAL, "points invalid");
+  if (!(eps > 0) || !(tau > 0)) return fail(FGA_EINVAL, "eps and tau must be > 0");
+  if (precision != FGA_FP64 && precision != FGA_FP32)
+    return fail(FGA_EUNSUPPORTED, "point precision %d not built (FGA_FP64, FGA_FP32)", precision);
+  if (n > 0x7fffffff) return fail(FGA_EUNSUPPORTED, "more than 2^31 points");
+  // beams per batch: the largest whole number of 64-beam tiles (at most 2^22
+  // and the set) whose records, boxes and partial sums fit in the scratch
+  const int64_t nb = beams->count;
+  int64_t batch = nb < ((int64_t)1 << 22) ? ((nb > 0 ? nb : 1) + 63) / 64 * 64 : ((int64_t)1 << 22);
+  while (batch > 64 && noalloc_bytes(batch, n) > kNoAllocScratchBytes) batch = (batch / 2 + 63) / 64 * 64;
+  if (noalloc_bytes(batch, n) > kNoAllocScratchBytes)
+    return fail(FGA_ENOMEM, "%lld points need %zu bytes of scratch even for one 64-beam tile; the no-allocation "
+                "call holds %zu (use fga_reconstruct_points)", (long long)n, noalloc_bytes(batch, n),
+                kNoAllocScratchBytes);
+  char *base = nullptr;
+  if ((s = scratch_of_current_device(&base)) != FGA_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  Arena ar(base, kNoAllocScratchBytes);
+  unsigned long long *ctr = ar.take<unsigned long long>(1);
+  double *emit = ar.take<double>((size_t)12 * batch);
+  const int bpb = points_beams_per_block(batch, n, 1);
+  double *partial = ar.take<double>((size_t)((batch + bpb - 1) / bpb) * n * 6);
+  double *box = ar.take<double>((size_t)((batch + 63) / 64) * 6);
+  if (!ctr || !emit || !partial || !box) return fail(FGA_ENOMEM, "scratch layout does not fit");
+  hipLaunchKernelGGL(k_zero_u64, 1, 64, 0, st, ctr, 1);
+  FGA_HIP(hipGetLastError());
+  if (nb == 0) FGA_HIP(launch_reduce_points(partial, 0, 1, n, nullptr, out, 1, 0, 0, st));
+  for (int64_t b0 = 0; b0 < nb; b0 += batch) {
+    const int64_t b1 = b0 + batch < nb ? b0 + batch : nb;
+    FGA_HIP(launch_emit(beams->f64, beams->i32, beams->capacity, b0, b1, eps, emit, box, st));
+    PointsArgs pa{};
+    pa.emit = emit;
+    pa.nb = b1 - b0;
+    pa.m = 1;
+    pa.xyz = xyz;
+    pa.n = n;
+    pa.eps = eps;
+    pa.tau = tau;
+    pa.partial = partial;
+    pa.beams_per_block = bpb;
+    pa.evals = ctr;
+    pa.tile_box = box;
+    pa.ntiles = (pa.nb + 63) / 64;
+    pa.boxes_ready = 1;
+    pa.precision = precision;
+    int nblk = 0;
+    FGA_HIP(launch_sum_points(pa, &nblk, st));
+    FGA_HIP(launch_reduce_points(partial, nblk, 1, n, nullptr, out, 1, 0, b0 > 0 ? 1 : 0, st));
   }
   if (evals) {
     unsigned long long h = 0;
