@@ -64,6 +64,12 @@ class Medium(C.Structure):
 HOMOGENEOUS, GRID, BUMP, LINEAR, LAYERED = 0, 1, 2, 3, 4
 
 
+class PointForce(C.Structure):
+    _fields_ = [("eps", C.c_double), ("x0", C.c_double * 3), ("d", C.c_double * 3), ("rho0", C.c_double),
+                ("nq", C.c_int), ("qhalf", C.c_double), ("ndir", C.c_int), ("nshell", C.c_int),
+                ("shell_lo", C.c_double), ("shell_hi", C.c_double), ("omega", C.c_double), ("t0", C.c_double),
+                ("width", C.c_double), ("t_ref", C.c_double), ("branch_mask", C.c_int), ("cull_abs", C.c_double)]
+
 
 class PointSource(C.Structure):
     _fields_ = [("eps", C.c_double), ("x0", C.c_double * 3), ("M", C.c_double * 6), ("rho0", C.c_double),
@@ -107,6 +113,11 @@ def lib():
         L.om_point_source_beams.restype = C.c_int64
         L.om_point_source_beams.argtypes = [vp, vp, vp]
         L.om_point_source_size.restype = C.c_size_t
+        L.om_point_force_beams.restype = C.c_int64
+        L.om_point_force_beams.argtypes = [vp, vp, vp]
+        L.om_point_force_size.restype = C.c_size_t
+        if L.om_point_force_size() != C.sizeof(PointForce):
+            raise RuntimeError("oracle point-force layout mismatch")
         L.om_fibonacci_dirs.argtypes = [C.c_int, vp]
         L.om_gauss_legendre.argtypes = [C.c_int, C.c_double, C.c_double, vp, vp]
         L.om_ricker.restype = C.c_double
@@ -374,6 +385,31 @@ def point_source_beams(med: OracleMedium, src: PointSource) -> np.ndarray:
     """Beams of a point moment-tensor source (closed-form weights), lineage order."""
     out = np.zeros(point_source_candidates(src), dtype=BEAM_DTYPE)
     n = lib().om_point_source_beams(med.ref, C.byref(src), _p(out))
+    return out[:n].copy()
+
+
+def point_force(eps, x0, d, nq, qhalf, ndir, nshell, omega, t0, width, t_ref, shell_lo=0.2, shell_hi=2.5,
+                rho0=0.0, branch_mask=7, cull_abs=0.0) -> PointForce:
+    """Parameters of a point force d F(t), F(t) = cos(omega (t + t0)) exp(-(t + t0)^2/width^2),
+    whose beams are launched at t_ref."""
+    src = PointForce()
+    src.eps = eps
+    src.x0[:] = list(x0)
+    src.d[:] = list(d)
+    src.rho0 = rho0
+    src.nq, src.qhalf, src.ndir, src.nshell = nq, qhalf, ndir, nshell
+    src.shell_lo, src.shell_hi = shell_lo, shell_hi
+    src.omega, src.t0, src.width, src.t_ref = omega, t0, width, t_ref
+    src.branch_mask = branch_mask
+    src.cull_abs = cull_abs
+    return src
+
+
+def point_force_beams(med: OracleMedium, src: PointForce) -> np.ndarray:
+    """Beams of a point force with its time function folded in (Duhamel), lineage order."""
+    ncand = src.nq ** 3 * src.ndir * src.nshell * bin(src.branch_mask & 7).count("1") * 2
+    out = np.zeros(ncand, dtype=BEAM_DTYPE)
+    n = lib().om_point_force_beams(med.ref, C.byref(src), _p(out))
     return out[:n].copy()
 
 
