@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--window", type=float, default=0.5,
                     help="the timed steps start at this fraction of the horizon T (untimed advance before)")
     ap.add_argument("--segment", type=int, default=250, help="RK4 steps per evolution call (progress between)")
-    ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered", "mixed"])
+    ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered", "mixed",
+                                                             "pointforce"])
     ap.add_argument("--waves", type=int, default=4, help="beam waves of the mixed-precision workload")
     ap.add_argument("--batch", type=int, default=0, help="beams per receiver-sum batch in the evolution (0: library default)")
     ap.add_argument("--chunk", type=int, default=0, help="RK4 steps per integrator launch (0: library default)")
@@ -348,6 +349,98 @@ def layered(args):
     print(json.dumps(line), flush=True)
 
 
+def pointforce(args):
+    """The accuracy experiment of Sec. 2.3 in box units (c_S = 1): a point
+    force d F(t), d = (1, 1, 1), F(t) = cos(256 (t + T0)) exp(-(t + T0)^2 / (1/32)^2)
+    (1.4702 Hz, eps_S = 1/256), homogeneous c_P = sqrt(3), c_S = 1, rho = 1;
+    two-way point-force beams launched at t = -T0 (q 14^3 x 2000 directions x
+    40 shells x 3 branches x 2 directions, cull 1e-4), RK4 to t = 0.25 (6.93 s)
+    and the field on the 128^2 grid of the plane y = 1/2.  One step = one
+    whole solve; reports its parts and the relative L2 error against the
+    closed-form solution (eq:ex_anal; evaluated by tests/point_force_exact.py)."""
+    import torch
+    import paper_1810_06760_amd as fga
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import point_force_exact as pfe
+    torch.cuda.set_device(0)
+    eps, cp, cs = 1.0 / 256, math.sqrt(3.0), 1.0
+    omega, t0, sig, T = 256.0, 0.1768 / (128.0 / 4.619), 1.0 / 32, 0.25
+    x0, d = (0.5, 0.5, 0.5), (1.0, 1.0, 1.0)
+    qhalf = 4 * math.sqrt(eps) + 3 * cp * sig
+    nq = int(math.ceil(2 * qhalf / math.sqrt(eps)))
+    pc = omega * eps / cp
+    A = 1.0 / sig ** 2 + cp * cp / (2 * eps)
+    psi_scale = eps / (2 * pc) * math.sqrt(3.0) / cp * math.sqrt(math.pi / A)
+    src = fga.point_force(eps, x0, d, nq=nq, qhalf=qhalf, ndir=2000, nshell=40, omega=omega, t0=t0, width=sig,
+                          t_ref=-t0, shell_lo=0.3 * pc, shell_hi=1.7 * pc, cull_abs=1e-4 * psi_scale)
+    med = fga.Medium.homogeneous(cp, cs, 1.0)
+    ncand = int(fga.lib().fga_point_force_candidates(fga.C.byref(src)))
+    beams = fga.BeamSet(ncand // 12)
+    n = 128
+    ax = (np.arange(n) + 0.5) / n
+    X, Z = np.meshgrid(ax, ax, indexing="xy")
+    pts = np.stack([X.ravel(), np.full(n * n, 0.5), Z.ravel()], axis=1)
+    xyz = fga._dev(pts, torch.float64)
+    nsteps = 64
+    ws_ev = fga._workspace(fga.workspace_bytes("evolve", beams=beams, nsteps=nsteps))
+
+    def solve():
+        t = {}
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        fga.fga_decompose_point_force(med, src, beams=beams)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        _, st = fga.fga_evolve(med, beams, (T + t0) / nsteps, nsteps, ws=ws_ev)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        u, ev = fga.fga_reconstruct_points(beams, eps, 25.0, xyz)
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        t.update(decompose_s=b - a, evolve_s=c - b, reconstruct_s=e - c, beam_steps=st["beam_steps"], evals=ev)
+        return u, t
+
+    for i in range(args.warmup):
+        solve()
+        print("bench: warm-up solve %d done" % (i + 1), file=sys.stderr, flush=True)
+    fga.fga_profile_enable(True)
+    t0w = time.perf_counter()
+    parts = []
+    for i in range(args.steps):
+        u, t = solve()
+        parts.append(t)
+        print("bench: solve %d done" % (i + 1), file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0w
+    prof = {fga.KERNEL_NAMES[k]: fga.fga_profile_read(k) for k in fga.KERNEL_NAMES}
+    fga.fga_profile_enable(False)
+    got = fga.to_complex(u)
+    ref = pfe.displacement(pts, T, x0, d, cp, cs, 1.0, omega, t0, sig)
+    err = float(np.linalg.norm(got.real - ref) / np.linalg.norm(ref))
+    K = args.steps
+    roof, _ = roofline({"beam_steps": sum(p["beam_steps"] for p in parts), "ev_rec": sum(p["evals"] for p in parts)},
+                       prof, "homogeneous")
+    line = {
+        "metric": "beam-steps/s + beam-point evals/s; served solves/s, p50/p99 at rel-L2<=1e-3",
+        "value": sum(p["beam_steps"] for p in parts) / elapsed, "unit": "beam-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "point force with its time function in a homogeneous medium (the accuracy "
+                               "experiment of Sec. 2.3 in box units, eps_S = 1/256): %d beams of %d candidates "
+                               "(q %d^3 x 2000 directions x 40 shells x 3 branches x 2 directions), %d RK4 steps "
+                               "to t = 0.25, field on a 128^2 plane; one step = one whole solve"
+                               % (beams.count, ncand, nq, nsteps),
+                   "beams": beams.count, "parallelism": "single GPU"},
+        "rel_l2_vs_exact": err,
+        "paper_rel_l2_vs_exact": 0.0384,
+        "solve_parts_s": {k: float(np.mean([p[k] for p in parts])) for k in ("decompose_s", "evolve_s",
+                                                                             "reconstruct_s")},
+        "beam_point_evals_per_s": sum(p["evals"] for p in parts) / elapsed,
+        "kernel_ms_per_step": {k: v[1] / K for k, v in prof.items() if v[0]},
+        "roofline": roof,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def serve(args):
     """Serving sweep: 4 resident smooth models (128^3), requests from the
     seeded sweep generator; phase 1 submits all requests at once (saturated
@@ -591,6 +684,9 @@ def main():
         return
     if args.workload == "mixed":
         mixed(args)
+        return
+    if args.workload == "pointforce":
+        pointforce(args)
         return
     if args.copy_calibration:
         import torch

@@ -222,6 +222,47 @@ fga_status fga_decompose_point_source(const fga_medium *med, const fga_point_sou
                                       fga_beams *beams, void *workspace, size_t workspace_bytes,
                                       void *stream);
 
+/* Point force with a time function, the source of the accuracy experiment
+ * of Sec. 2.3 (eq:ex_homo): rho u_tt = L u + d F(t) delta(x - x0) with
+ * F(t) = cos(omega (t + t0)) exp(-(t + t0)^2 / width^2).  Reading used here
+ * (the paper does not give its source treatment): by Duhamel's principle the
+ * field is the superposition over source times s of free waves started with
+ * u = 0, u_t = d F(s) delta(x - x0)/rho0, whose two-way weights are
+ * psi_{b,+-} = +-(i eps/(2|p|)) F(s) (d.n_b)/(rho0 c_b) K(x0; q, p) (eq:psi,
+ * eq:alpha^k with f = 0; K the FBI kernel).  The beam launched at time s from
+ * (q, p) is represented by the beam launched at t_ref from
+ * q' = q - sigma c_b(x0) (s - t_ref) p/|p| (exact for the beam centre in a
+ * homogeneous medium; the amplitude's change over the source's duration is
+ * left out), so each beam's weight is the integral over s of those weights,
+ * a Gaussian integral done in closed form.  Evolving the beams by tau gives
+ * the field at t_ref + tau.  Meshes, frames, cull (on |psi|) and lineage are
+ * those of fga_point_source (q cube x0 +- qhalf; Fibonacci directions x
+ * Gauss-Legendre shells on [shell_lo, shell_hi] c_P(x0)/c_b(x0)); both
+ * directions and the branches of branch_mask are made.  The q cube must
+ * reach as far as the wave travels during the source (about
+ * 4 sqrt(eps) + 3 c_P width). */
+typedef struct {
+  double eps;
+  double x0[3];
+  double d[3];              /* force vector                                           */
+  double rho0;              /* density at x0 (<= 0: the medium's)                     */
+  int nq;
+  double qhalf;
+  int ndir, nshell;         /* 1 <= nshell <= 64                                      */
+  double shell_lo, shell_hi;
+  double omega, t0, width;  /* the time function F                                    */
+  double t_ref;             /* the time the beams describe before any evolution      */
+  int branch_mask;
+  double cull_abs;
+} fga_point_force;
+
+int64_t fga_point_force_candidates(const fga_point_force *src);
+size_t fga_decompose_point_force_workspace_bytes(const fga_point_force *src);
+/* Writes the kept beams in lineage order and sets beams->count (synchronises
+ * `stream`).  Errors: FGA_EINVAL, FGA_ENOMEM (workspace), FGA_ECAPACITY. */
+fga_status fga_decompose_point_force(const fga_medium *med, const fga_point_force *src, fga_beams *beams,
+                                     void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Step 2: evolution (Sec. 2.2, eq:char_plus, eq:char_minus, eq:DzDt,        */
 /* eq:amp_P, eq:amp_SV, eq:amp_SH; Sec. 2.3 fixed-step RK4)                  */

@@ -44,7 +44,8 @@ EXPORTED = ["fga_last_error", "fga_version", "fga_medium_grid_table_bytes", "fga
             "fga_profile_enable", "fga_profile_read", "fga_server_footprint", "fga_server_create",
             "fga_server_submit", "fga_server_poll", "fga_server_status", "fga_server_destroy",
             "fga_point_source_candidates", "fga_decompose_point_source_workspace_bytes",
-            "fga_decompose_point_source"]
+            "fga_decompose_point_source", "fga_point_force_candidates", "fga_decompose_point_force_workspace_bytes",
+            "fga_decompose_point_force"]
 FGA_K_INTEGRATE, FGA_K_SUM_POINTS, FGA_K_GRID_TILE, FGA_K_FBI_GEMM = 0, 1, 2, 3
 KERNEL_NAMES = {0: "integrate", 1: "sum_points", 2: "grid_tile", 3: "fbi_gemm"}
 
@@ -96,6 +97,13 @@ class PointSourceC(C.Structure):
                 ("nq", C.c_int), ("qhalf", C.c_double), ("ndir", C.c_int), ("nshell", C.c_int),
                 ("shell_lo", C.c_double), ("shell_hi", C.c_double), ("ricker", C.c_int), ("branch_mask", C.c_int),
                 ("cull_abs", C.c_double)]
+
+
+class PointForceC(C.Structure):
+    _fields_ = [("eps", C.c_double), ("x0", C.c_double * 3), ("d", C.c_double * 3), ("rho0", C.c_double),
+                ("nq", C.c_int), ("qhalf", C.c_double), ("ndir", C.c_int), ("nshell", C.c_int),
+                ("shell_lo", C.c_double), ("shell_hi", C.c_double), ("omega", C.c_double), ("t0", C.c_double),
+                ("width", C.c_double), ("t_ref", C.c_double), ("branch_mask", C.c_int), ("cull_abs", C.c_double)]
 
 
 class RequestC(C.Structure):
@@ -163,6 +171,12 @@ def lib():
         L.fga_decompose_point_source_workspace_bytes.argtypes = [vp]
         L.fga_decompose_point_source.restype = st
         L.fga_decompose_point_source.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.fga_point_force_candidates.restype = i64
+        L.fga_point_force_candidates.argtypes = [vp]
+        L.fga_decompose_point_force_workspace_bytes.restype = sz
+        L.fga_decompose_point_force_workspace_bytes.argtypes = [vp]
+        L.fga_decompose_point_force.restype = st
+        L.fga_decompose_point_force.argtypes = [vp, vp, vp, vp, sz, vp]
         L.fga_server_footprint.restype = sz
         L.fga_server_footprint.argtypes = [vp]
         L.fga_server_create.restype = st
@@ -425,6 +439,33 @@ def fga_decompose_point_source(medium: Medium, src: PointSourceC, beams: BeamSet
     ws = _workspace(L.fga_decompose_point_source_workspace_bytes(C.byref(src)), ws)
     _check(L.fga_decompose_point_source(C.byref(medium.c), C.byref(src), C.byref(beams.c), _ptr(ws), ws.numel(),
                                         _stream()))
+    return beams
+
+
+def point_force(eps, x0, d, nq, qhalf, ndir, nshell, omega, t0, width, t_ref, shell_lo=0.2, shell_hi=2.5,
+                rho0=0.0, branch_mask=7, cull_abs=0.0) -> PointForceC:
+    """Point force d F(t), F(t) = cos(omega (t + t0)) exp(-(t + t0)^2/width^2); beams launched at t_ref."""
+    s = PointForceC()
+    s.eps = eps
+    s.x0[:] = [float(v) for v in x0]
+    s.d[:] = [float(v) for v in d]
+    s.rho0 = rho0
+    s.nq, s.qhalf, s.ndir, s.nshell = nq, qhalf, ndir, nshell
+    s.shell_lo, s.shell_hi = shell_lo, shell_hi
+    s.omega, s.t0, s.width, s.t_ref = omega, t0, width, t_ref
+    s.branch_mask = branch_mask
+    s.cull_abs = cull_abs
+    return s
+
+
+def fga_decompose_point_force(medium: Medium, src: PointForceC, beams: BeamSet = None, ws=None) -> BeamSet:
+    """Step 1 for a point force with its time function (closed-form weights)."""
+    L = lib()
+    if beams is None:
+        beams = BeamSet(int(L.fga_point_force_candidates(C.byref(src))))
+    ws = _workspace(L.fga_decompose_point_force_workspace_bytes(C.byref(src)), ws)
+    _check(L.fga_decompose_point_force(C.byref(medium.c), C.byref(src), C.byref(beams.c), _ptr(ws), ws.numel(),
+                                       _stream()))
     return beams
 
 

@@ -23,7 +23,9 @@ namespace {
 constexpr int MAXSH = 64;
 
 struct SourceArgs {
+  int kind;                 // 0: moment tensor (Ricker optional); 1: point force with its time function
   double eps, x0[3], M[3][3], rho0;
+  double d[3], omega, t0, width, t_ref;  // point force
   int nq;
   double qhalf, hq;
   int ndir, nshell;
@@ -87,6 +89,42 @@ __device__ bool candidate(const DevMedium &m, const SourceArgs &a, int64_t L, do
   // K and grad(K / c_b) at x0
   const double d0 = a.x0[0] - q[0], d1 = a.x0[1] - q[1], d2 = a.x0[2] - q[2];
   const double ie = 1.0 / a.eps;
+  if (a.kind == 1) {
+    // point force: FBI[g/c_b] = F(s) (d.n_b)/(rho0 c_b) K(x0) of the impulse at time s,
+    // launched from q' = q - sigma c (s - t_ref) p/|p| and integrated over s in
+    // closed form: K(x0) I with the Gaussian integral I (v = s + t0,
+    // v0 = t0 + t_ref, D = x0 - q', D_par = D.p/|p|):
+    //   I = 1/2 sum_{+-} sqrt(pi/A) exp(B^2/(4A) + C), A = 1/width^2 + c^2/(2 eps),
+    //   B = c^2 v0/eps + sigma c D_par/eps + i (sigma c |p|/eps +- omega),
+    //   C = -c^2 v0^2/(2 eps) - sigma c D_par v0/eps - i sigma c |p| v0/eps
+    const double dpar = (p[0] * d0 + p[1] * d1 + p[2] * d2) / np;
+    const double v0 = a.t0 + a.t_ref;
+    const double A = 1.0 / (a.width * a.width) + cb * cb * 0.5 * ie;
+    const double Cr = -cb * cb * v0 * v0 * 0.5 * ie - sg * cb * dpar * v0 * ie;
+    const double Ci = -sg * cb * np * v0 * ie;
+    const double Br = cb * cb * v0 * ie + sg * cb * dpar * ie;
+    // K(x0) = exp(-i p.D/eps - |D|^2/(2 eps)) folded into the same exponent
+    const double Kre = -(d0 * d0 + d1 * d1 + d2 * d2) * 0.5 * ie;
+    const double Kim = -(p[0] * d0 + p[1] * d1 + p[2] * d2) * ie;
+    const double sq = sqrt(3.14159265358979323846 / A);
+    double Ir = 0.0, Ii = 0.0;
+    for (int k = 0; k < 2; ++k) {
+      const double Bi = sg * cb * np * ie + (k == 0 ? a.omega : -a.omega);
+      const double er = (Br * Br - Bi * Bi) / (4.0 * A) + Cr + Kre;
+      const double ei = (2.0 * Br * Bi) / (4.0 * A) + Ci + Kim;
+      double sn, cs;
+      sincos(ei, &sn, &cs);
+      const double mg = 0.5 * sq * exp(er);
+      Ir += mg * cs;
+      Ii += mg * sn;
+    }
+    const double dn = (a.d[0] * nh[0] + a.d[1] * nh[1] + a.d[2] * nh[2]) / (a.rho0 * cb);
+    // psi = sg (i eps / (2|p|)) (d.n/(rho0 c)) K I
+    const double f = sg * a.eps / (2.0 * np) * dn;
+    pr = -f * Ii;
+    pi = f * Ir;
+    return true;
+  }
   double ks, kc;
   sincos(-(p[0] * d0 + p[1] * d1 + p[2] * d2) * ie, &ks, &kc);
   const double kmag = exp(-(d0 * d0 + d1 * d1 + d2 * d2) * 0.5 * ie);
@@ -220,6 +258,38 @@ void gauss_legendre(int n, double *t, double *w)
   }
 }
 
+fga_status source_args(const fga_point_source *s, SourceArgs *a);
+
+// The point force in the candidate layout of the moment-tensor source.
+fga_status force_args(const fga_point_force *s, SourceArgs *a)
+{
+  if (!s) return fail(FGA_EINVAL, "point force is NULL");
+  if (!(s->width > 0) || !(s->omega >= 0))
+    return fail(FGA_EINVAL, "point force: need width > 0 and omega >= 0");
+  fga_point_source ps{};
+  ps.eps = s->eps;
+  for (int d = 0; d < 3; ++d) ps.x0[d] = s->x0[d];
+  ps.rho0 = s->rho0;
+  ps.nq = s->nq;
+  ps.qhalf = s->qhalf;
+  ps.ndir = s->ndir;
+  ps.nshell = s->nshell;
+  ps.shell_lo = s->shell_lo;
+  ps.shell_hi = s->shell_hi;
+  ps.ricker = 0;
+  ps.branch_mask = s->branch_mask;
+  ps.cull_abs = s->cull_abs;
+  fga_status st = source_args(&ps, a);
+  if (st != FGA_OK) return st;
+  a->kind = 1;
+  for (int d = 0; d < 3; ++d) a->d[d] = s->d[d];
+  a->omega = s->omega;
+  a->t0 = s->t0;
+  a->width = s->width;
+  a->t_ref = s->t_ref;
+  return FGA_OK;
+}
+
 fga_status source_args(const fga_point_source *s, SourceArgs *a)
 {
   if (!s) return fail(FGA_EINVAL, "point source is NULL");
@@ -229,6 +299,7 @@ fga_status source_args(const fga_point_source *s, SourceArgs *a)
                             "0 < shell_lo < shell_hi", MAXSH);
   std::memset(a, 0, sizeof(*a));
   a->eps = s->eps;
+  a->rho0 = s->rho0;  // <= 0: the medium's density at x0, set by the caller
   for (int d = 0; d < 3; ++d) a->x0[d] = s->x0[d];
   const double M[3][3] = {{s->M[0], s->M[3], s->M[4]}, {s->M[3], s->M[1], s->M[5]}, {s->M[4], s->M[5], s->M[2]}};
   std::memcpy(a->M, M, sizeof(M));
@@ -291,28 +362,63 @@ size_t fga_decompose_point_source_workspace_bytes(const fga_point_source *s)
   return Arena::need(nblk * sizeof(int64_t)) * 2 + Arena::need(sizeof(int64_t));
 }
 
+static fga_status decompose_source(const fga_medium *med, SourceArgs &a, fga_beams *beams, void *workspace,
+                                   size_t workspace_bytes, void *stream);
+
 fga_status fga_decompose_point_source(const fga_medium *med, const fga_point_source *src, fga_beams *beams,
                                       void *workspace, size_t workspace_bytes, void *stream)
+{
+  SourceArgs a;
+  fga_status s;
+  if ((s = source_args(src, &a)) != FGA_OK) return s;
+  return decompose_source(med, a, beams, workspace, workspace_bytes, stream);
+}
+
+int64_t fga_point_force_candidates(const fga_point_force *s)
+{
+  if (!s || s->nq < 1 || s->ndir < 1 || s->nshell < 1) return 0;
+  return 6 * (int64_t)s->nq * s->nq * s->nq * s->ndir * s->nshell;
+}
+
+size_t fga_decompose_point_force_workspace_bytes(const fga_point_force *s)
+{
+  const int64_t nc = fga_point_force_candidates(s);
+  const int64_t nblk = (nc + 255) / 256 + 1;
+  return Arena::need(nblk * sizeof(int64_t)) * 2 + Arena::need(sizeof(int64_t));
+}
+
+fga_status fga_decompose_point_force(const fga_medium *med, const fga_point_force *src, fga_beams *beams,
+                                     void *workspace, size_t workspace_bytes, void *stream)
+{
+  SourceArgs a;
+  fga_status s;
+  if ((s = force_args(src, &a)) != FGA_OK) return s;
+  return decompose_source(med, a, beams, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"
+
+static fga_status decompose_source(const fga_medium *med, SourceArgs &a, fga_beams *beams, void *workspace,
+                                   size_t workspace_bytes, void *stream)
 {
   fga_status s;
   DevMedium dm;
   if ((s = make_dev_medium(med, &dm)) != FGA_OK) return s;
   if (!beams || beams->capacity < 0 || (beams->capacity > 0 && (!beams->f64 || !beams->i32 || !beams->lineage)))
     return fail(FGA_EINVAL, "beams invalid");
-  SourceArgs a;
-  if ((s = source_args(src, &a)) != FGA_OK) return s;
+  const double *x0 = a.x0;
   // layer and density at x0
   if (dm.kind == FGA_MEDIUM_LAYERED) {
     int L = 0;
     if (dm.geometry == 1) {
-      const double r = std::sqrt(src->x0[0] * src->x0[0] + src->x0[1] * src->x0[1] + src->x0[2] * src->x0[2]);
+      const double r = std::sqrt(x0[0] * x0[0] + x0[1] * x0[1] + x0[2] * x0[2]);
       while (L < dm.nlayer - 1 && r < dm.bound[L]) ++L;
     } else {
-      while (L < dm.nlayer - 1 && src->x0[2] > dm.bound[L]) ++L;
+      while (L < dm.nlayer - 1 && x0[2] > dm.bound[L]) ++L;
     }
     a.layer0 = L;
   }
-  a.rho0 = src->rho0 > 0.0 ? src->rho0
+  a.rho0 = a.rho0 > 0.0 ? a.rho0
            : (dm.kind == FGA_MEDIUM_LAYERED ? dm.rhol[a.layer0] : (med->rho > 0.0 ? med->rho : 1.0));
   const int64_t nblk = (a.ncand + 255) / 256 + 1;
   Arena ar(workspace, workspace_bytes);
@@ -328,4 +434,4 @@ fga_status fga_decompose_point_source(const fga_medium *med, const fga_point_sou
   }
 }
 
-}  // extern "C"
+

@@ -678,6 +678,42 @@ def test_point_source_parity(medium):
     assert np.array_equal(g["e"], ob["e"])
 
 
+@pytest.mark.parametrize("medium", ["homogeneous", "grid"])
+def test_point_force_parity(medium):
+    """Point force with its time function (Sec. 2.3 eq:ex_homo, Duhamel
+    weights in closed form): the same lineage set, states and weights as the
+    oracle; evolved with receivers, the same seismograms."""
+    m = fga()
+    say("point force", medium)
+    eps = 1.0 / 64
+    if medium == "homogeneous":
+        mo, mg = om.homogeneous(math.sqrt(3), 1.0, 1.0), m.Medium.homogeneous(math.sqrt(3), 1.0)
+        x0 = [0.5, 0.5, 0.5]
+    else:
+        w = small_c2(nmed=16)
+        mo, mg = om.medium_for(w), m.medium_for(w)
+        x0 = [0.43, 0.52, 0.61]
+    kw = dict(nq=5, qhalf=0.3, ndir=24, nshell=3, omega=64.0, t0=0.01, width=0.05, t_ref=-0.01, shell_lo=0.3,
+              shell_hi=1.7)
+    d = [1.0, 1.0, 1.0]
+    ob = om.point_force_beams(mo, om.point_force(eps, x0, d, **kw))
+    bs = m.fga_decompose_point_force(mg, m.point_force(eps, x0, d, **kw))
+    g = bs.export()
+    assert np.array_equal(g["lineage"], ob["lineage"])
+    for k in ("branch", "sigma", "layer"):
+        assert np.array_equal(g[k], ob[k]), k
+    assert rel_l2(g["Q"], ob["Q"]) <= 1e-14
+    assert rel_l2(g["w"], ob["w"]) <= RTOL
+    rec = fi.uniform_points(7, fi.rng(1, 66), 0.3, 0.7)
+    nsteps, dt, stride = 24, 2e-3, 4
+    seis, _ = m.fga_evolve(mg, bs, dt, nsteps, receivers=rec, eps=eps, tau=25.0, stride=stride)
+    ref = np.zeros((len(rec), nsteps // stride, 3), dtype=np.complex128)
+    for k in range(nsteps // stride):
+        om.evolve(mo, ob, dt, stride)
+        ref[:, k, :], _ = om.sum_points(ob, rec, eps, 25.0)
+    assert rel_l2(m.to_complex(seis), ref) <= RTOL
+
+
 def source_psi_abs(b, eps, nq, qhalf, ndir, nshell, cP, cS, lo=0.2, hi=2.5):
     """|psi| of point-source beams in a homogeneous medium: |w| / (dq dp (2 pi eps)^{-9/2})."""
     dq = (2 * qhalf / nq) ** 3
