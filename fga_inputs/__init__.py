@@ -220,6 +220,22 @@ def mixed_waves(eps=1.0 / 512, nq=50, np_=8, ny=256, nsteps=250, dt=1e-3, nout=2
     return w, slabs
 
 
+def radial_shell(ymesh: Mesh3, r0: float, sigma: float, ell: float) -> np.ndarray:
+    """u = grad phi0(|y| - r0), phi0(s) = exp(-s^2/(2 sigma^2)) cos(2 pi s/ell): a
+    radially symmetric shell of P-wave displacement (the waveguide example's
+    initial data).  Returns complex128 [3][z][y][x] (real values)."""
+    x = ymesh.axis(0)[None, None, :]
+    y = ymesh.axis(1)[None, :, None]
+    z = ymesh.axis(2)[:, None, None]
+    r = np.sqrt(x * x + y * y + z * z)
+    s = r - r0
+    e = np.exp(-s * s / (2 * sigma * sigma))
+    dphi = -(s / sigma ** 2) * e * np.cos(2 * math.pi * s / ell) - (2 * math.pi / ell) * e * np.sin(2 * math.pi * s / ell)
+    rr = np.where(r > 0, r, 1.0)
+    out = np.stack([dphi * x / rr, dphi * y / rr, dphi * z / rr]).astype(np.complex128)
+    return np.ascontiguousarray(out)
+
+
 # ---------------------------------------------------------------------------
 # tomography-style request sweep (serving)
 # ---------------------------------------------------------------------------
