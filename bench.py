@@ -85,9 +85,10 @@ def parse():
     ap.add_argument("--slots", type=int, default=4, help="concurrent request slots of the server")
     ap.add_argument("--hbm-budget-gb", type=float, default=240.0, help="server device-memory budget")
     ap.add_argument("--load", type=float, default=0.8, help="Poisson arrival rate as a fraction of saturated")
-    ap.add_argument("--serve-precision", default="fp64", choices=["fp64", "mixed"],
-                    help="receiver sums of the served solves (mixed: FP32 exp/sin/cos of FP64-reduced arguments; "
-                         "the run then also reports its error against FP64 solves of the first 8 requests)")
+    ap.add_argument("--serve-precision", default="fp64", choices=["fp64", "mixed", "mixed32"],
+                    help="receiver sums of the served solves (mixed: FP32 exp/sin/cos of FP64-reduced arguments, "
+                         "FP64 products and sums; mixed32: FP32 products and per-lane sums as well; the mixed runs "
+                         "also report their error against FP64 solves of the 8 smallest requests)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (the known-size kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -459,7 +460,7 @@ def serve(args):
     else:
         reqs = [fi.sweep_request(i) for i in range(args.requests)]
 
-    prec = fga.FGA_FP32 if args.serve_precision == "mixed" else fga.FGA_FP64
+    prec = {"fp64": fga.FGA_FP64, "mixed": fga.FGA_FP32, "mixed32": fga.FGA_FP32_ACC32}[args.serve_precision]
 
     def request(rq, precision=None):
         src = fga.point_source(rq["eps"], rq["x0"], rq["M"], nq=rq["nq"], ndir=rq["ndir"], nshell=rq["nshell"])
@@ -481,15 +482,21 @@ def serve(args):
         t0 = time.perf_counter()
         try:
             for k, rq in enumerate(reqs):
-                wait = arrivals[k] - (time.perf_counter() - t0)
-                if wait > 0:
-                    done += srv.poll(64, wait_ms=int(wait * 1000))
-                    rest = arrivals[k] - (time.perf_counter() - t0)
-                    if rest > 0:
-                        time.sleep(rest)
+                # until request k arrives, collect completions (a line at least every 30 s)
+                while True:
+                    wait = arrivals[k] - (time.perf_counter() - t0)
+                    if wait <= 0:
+                        break
+                    got = srv.poll(64, wait_ms=max(1, int(min(wait, 30.0) * 1000)))
+                    done += got
+                    print("bench: %.1f s, %d of %d solves done, next arrival in %.1f s"
+                          % (time.perf_counter() - t0, len(done), len(reqs),
+                             max(0.0, arrivals[k] - (time.perf_counter() - t0))), file=sys.stderr, flush=True)
                 r, sz, keep = request(rq)
                 srv.submit(r, keep=(keep, sz))
                 held.append((r, sz, keep))
+                print("bench: request %d of %d submitted at %.1f s, %d done" % (k + 1, len(reqs),
+                      time.perf_counter() - t0, len(done)), file=sys.stderr, flush=True)
             while len(done) < len(reqs):
                 got = srv.poll(64, wait_ms=600000)
                 if not got:
@@ -534,6 +541,7 @@ def serve(args):
             got = []
             while len(got) < len(ref):
                 got += srv.poll(16, wait_ms=600000)
+                print("bench: FP64 reference %d of %d solves done" % (len(got), len(ref)), file=sys.stderr, flush=True)
         finally:
             srv.close()
         err = max(float(np.linalg.norm(sat["seis"][k] - sz) / np.linalg.norm(sz)) for k, sz in ref.values())
@@ -558,7 +566,9 @@ def serve(args):
                                   "6.4e6, 5.1e7 candidate beams), 2000 FP64 RK4 steps to T = 1 with a sample after "
                                   "every step" if stated else
                                   "eps in {1/32, 1/64, 1/128}, 250 FP64 RK4 steps with a sample after every step",
-                                  "FP64" if prec == fga.FGA_FP64 else "mixed (FP32 exp/sin/cos)", args.load),
+                                  {fga.FGA_FP64: "FP64", fga.FGA_FP32: "mixed (FP32 exp/sin/cos, FP64 sums)",
+                                   fga.FGA_FP32_ACC32: "mixed (FP32 exp/sin/cos, FP32 products and per-lane "
+                                   "sums)"}[prec], args.load),
                    "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb, "parallelism": "single GPU"},
         "p50_s": poi["p50_s"], "p99_s": poi["p99_s"], "arrival_rate": rate,
         "saturated": {k: sat[k] for k in ("solves_per_s", "p50_s", "p99_s", "makespan_s", "peak_running")},

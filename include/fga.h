@@ -268,7 +268,9 @@ fga_status fga_decompose_point_force(const fga_medium *med, const fga_point_forc
 /* eq:amp_P, eq:amp_SV, eq:amp_SH; Sec. 2.3 fixed-step RK4)                  */
 /* ------------------------------------------------------------------------ */
 
-typedef enum { FGA_FP64 = 0, FGA_FP32 = 1, FGA_BF16X3 = 2, FGA_FP16X3 = 3, FGA_FP16X2 = 4 } fga_precision;
+typedef enum {
+  FGA_FP64 = 0, FGA_FP32 = 1, FGA_BF16X3 = 2, FGA_FP16X3 = 3, FGA_FP16X2 = 4, FGA_FP32_ACC32 = 5
+} fga_precision;
 
 enum { FGA_COORDS_CARTESIAN = 0, FGA_COORDS_SPHERICAL = 1 };
 
@@ -284,7 +286,10 @@ typedef struct {
                               sqrt(2 tau eps) per axis)                                */
   int precision;           /* FGA_FP64: FP64 sums; FGA_FP32 (mixed): the Gaussian
                               exponent and the phase reduced modulo 2 pi in FP64, then
-                              exp / sin / cos in FP32, sums in FP64                    */
+                              exp / sin / cos in FP32, products and sums in FP64;
+                              FGA_FP32_ACC32: as FGA_FP32 with the products B e^{..}
+                              and each lane's running sums in FP32 (the reductions
+                              over lanes and beam ranges stay FP64)                    */
   int coords;              /* FGA_COORDS_CARTESIAN (0) or FGA_COORDS_SPHERICAL         */
 } fga_receivers;
 
@@ -366,8 +371,8 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
 /* u(x) = sum_b w_b exp(i S_b/eps) A_b exp(i P_b.(x-Q_b)/eps - |x-Q_b|^2/(2 eps))
  * over the beams with max_d |x_d - Q_d| <= sqrt(2 tau eps), A_b = a_P P/|P| or
  * a_SV N_SV + a_SH N_SH.  xyz: device [n][3]; out: device complex [n][3]
- * (overwritten).  precision: FGA_FP64 or FGA_FP32 (as in fga_receivers);
- * others give FGA_EUNSUPPORTED.  evals (host, may be NULL): number of
+ * (overwritten).  precision: FGA_FP64, FGA_FP32 or FGA_FP32_ACC32 (as in
+ * fga_receivers); * others give FGA_EUNSUPPORTED.  evals (host, may be NULL): number of
  * in-window terms; the call synchronises `stream` when evals != NULL. */
 size_t fga_reconstruct_points_workspace_bytes(const fga_beams *beams, int64_t n);
 fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau, int64_t n,
@@ -439,7 +444,7 @@ typedef struct {
   int stride;               /* a sample after every stride-th step                   */
   double *seis_out;         /* host, complex [n_receivers][nsteps/stride][3]; written
                                before the completion is reported; caller-owned       */
-  int precision;            /* receiver sums: FGA_FP64 or FGA_FP32 (mixed)            */
+  int precision;            /* receiver sums: FGA_FP64, FGA_FP32 or FGA_FP32_ACC32    */
   int point_source;         /* 1: the initial data is `source` (mesh and f unused)    */
   fga_point_source source;
   int receiver_coords;      /* FGA_COORDS_CARTESIAN or FGA_COORDS_SPHERICAL, as in

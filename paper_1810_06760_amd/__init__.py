@@ -29,7 +29,7 @@ FGA_NF64 = 52
 FGA_BRANCH, FGA_SIGMA, FGA_LAYER, FGA_GEN, FGA_FLAGS, FGA_NI32 = 0, 1, 2, 3, 4, 5
 FGA_FLAG_ALIVE, FGA_FLAG_QUARANTINED = 1, 2
 FGA_MEDIUM_HOMOGENEOUS, FGA_MEDIUM_GRID, FGA_MEDIUM_LAYERED = 0, 1, 2
-FGA_FP64, FGA_FP32, FGA_BF16X3, FGA_FP16X3, FGA_FP16X2 = 0, 1, 2, 3, 4
+FGA_FP64, FGA_FP32, FGA_BF16X3, FGA_FP16X3, FGA_FP16X2, FGA_FP32_ACC32 = 0, 1, 2, 3, 4, 5
 FGA_COORDS_CARTESIAN, FGA_COORDS_SPHERICAL = 0, 1
 FGA_GRID_NODE_DOUBLES = 16
 STATUS = {0: "FGA_OK", 1: "FGA_EINVAL", 2: "FGA_ENOMEM", 3: "FGA_EDEVICE", 4: "FGA_ENUMERIC",

@@ -173,6 +173,8 @@ fga_status sort_points(const double *xyz, int64_t n, double *xyz_sorted, int32_t
   return FGA_OK;
 }
 
+static bool point_precision_ok(int p) { return p == FGA_FP64 || p == FGA_FP32 || p == FGA_FP32_ACC32; }
+
 static fga_status check_beams(const fga_beams *b)
 {
   if (!b) return fail(FGA_EINVAL, "beams is NULL");
@@ -405,8 +407,9 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
     if (rec->stride < 1) return fail(FGA_EINVAL, "receiver stride must be >= 1");
     if (rec->n < 0 || (rec->n > 0 && !rec->xyz)) return fail(FGA_EINVAL, "receiver positions invalid");
     if (!(rec->eps > 0) || !(rec->tau > 0)) return fail(FGA_EINVAL, "receiver eps and tau must be > 0");
-    if (rec->precision != FGA_FP64 && rec->precision != FGA_FP32)
-      return fail(FGA_EUNSUPPORTED, "receiver precision %d not built (FGA_FP64, FGA_FP32)", rec->precision);
+    if (!point_precision_ok(rec->precision))
+      return fail(FGA_EUNSUPPORTED, "receiver precision %d not built (FGA_FP64, FGA_FP32, FGA_FP32_ACC32)",
+                  rec->precision);
     if (!seis && rec->n > 0 && nsteps / rec->stride > 0) return fail(FGA_EINVAL, "seis is NULL");
     if (rec->coords != FGA_COORDS_CARTESIAN && rec->coords != FGA_COORDS_SPHERICAL)
       return fail(FGA_EINVAL, "receiver coords must be FGA_COORDS_CARTESIAN or FGA_COORDS_SPHERICAL");
@@ -633,8 +636,8 @@ fga_status fga_reconstruct_points(const fga_beams *beams, double eps, double tau
   if ((s = check_beams(beams)) != FGA_OK) return s;
   if (n < 0 || (n > 0 && (!xyz || !out))) return fail(FGA_EINVAL, "points invalid");
   if (!(eps > 0) || !(tau > 0)) return fail(FGA_EINVAL, "eps and tau must be > 0");
-  if (precision != FGA_FP64 && precision != FGA_FP32)
-    return fail(FGA_EUNSUPPORTED, "point precision %d not built (FGA_FP64, FGA_FP32)", precision);
+  if (!point_precision_ok(precision))
+    return fail(FGA_EUNSUPPORTED, "point precision %d not built (FGA_FP64, FGA_FP32, FGA_FP32_ACC32)", precision);
   hipStream_t st = (hipStream_t)stream;
   const int64_t nb = beams->count;
   const int64_t batch = nb < ((int64_t)1 << 22) ? (nb > 0 ? nb : 1) : ((int64_t)1 << 22);
@@ -751,8 +754,8 @@ fga_status fga_reconstruct_points_noalloc(const fga_beams *beams, double eps, do
   if ((s = check_beams(beams)) != FGA_OK) return s;
   if (n < 0 || (n > 0 && (!xyz || !out))) return fail(FGA_EINVAL, "points invalid");
   if (!(eps > 0) || !(tau > 0)) return fail(FGA_EINVAL, "eps and tau must be > 0");
-  if (precision != FGA_FP64 && precision != FGA_FP32)
-    return fail(FGA_EUNSUPPORTED, "point precision %d not built (FGA_FP64, FGA_FP32)", precision);
+  if (!point_precision_ok(precision))
+    return fail(FGA_EUNSUPPORTED, "point precision %d not built (FGA_FP64, FGA_FP32, FGA_FP32_ACC32)", precision);
   if (n > 0x7fffffff) return fail(FGA_EUNSUPPORTED, "more than 2^31 points");
   // beams per batch: the largest whole number of 64-beam tiles (at most 2^22
   // and the set) whose records, boxes and partial sums fit in the scratch

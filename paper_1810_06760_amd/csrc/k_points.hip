@@ -14,6 +14,8 @@
 // range the sums are reduced over the lanes in a fixed order and written
 // once per wavefront; per-workgroup partials are then reduced in a fixed
 // order, so the sums are bitwise reproducible and need no atomics.
+#include <type_traits>
+
 #include "device_common.h"
 #include "fastmath.h"
 
@@ -48,29 +50,36 @@ __device__ __forceinline__ PointsWork points_work(int64_t id, int groups, int64_
 
 constexpr double LOG2E = 1.4426950408889634;
 
+// Summation modes: FP64 throughout; MIXED (FP32 exp / sin / cos, FP64
+// products and sums); MIXED32 (FP32 exp / sin / cos, products and per-lane
+// sums, the lane and block reductions in FP64).
+enum { SUM_FP64 = 0, SUM_MIXED = 1, SUM_MIXED32 = 2 };
+
 // One term's complex factor exp(-|d|^2/(2 eps) + i P.d/eps), zero outside
-// the window (in false).  MIXED: the exponent and the phase (in revolutions,
-// reduced to [-1/2, 1/2]) are formed in FP64, then exp2 / sin / cos run on
-// the FP32 transcendental unit.  Otherwise the FP64 table-driven exponential.
-template <bool MIXED>
+// the window (in false).  Mixed modes: the exponent and the phase (in
+// revolutions, reduced to [-1/2, 1/2]) are formed in FP64, then exp2 / sin /
+// cos run on the FP32 transcendental unit.  FP64: the table-driven
+// exponential.  T is the accumulation type (float only for MIXED32).
+template <int MODE, typename T>
 __device__ __forceinline__ void point_term(const TrigTables &tab, const double (&dd)[3], const double (&pe)[3],
-                                           bool in, double hieps, double &er, double &ei)
+                                           bool in, double hieps, T &er, T &ei)
 {
   const double g = (dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]) * hieps;
   const double v = pe[0] * dd[0] + pe[1] * dd[1] + pe[2] * dd[2];  // phase in units of pi/128
-  if constexpr (MIXED) {
+  if constexpr (MODE != SUM_FP64) {
     const double rev = v * (1.0 / 256.0);
     const float r = (float)(rev - rint(rev));
     const float amp = in ? __builtin_amdgcn_exp2f((float)(-g * LOG2E)) : 0.0f;
-    er = (double)(amp * __builtin_amdgcn_cosf(r));
-    ei = (double)(amp * __builtin_amdgcn_sinf(r));
+    er = (T)(amp * __builtin_amdgcn_cosf(r));
+    ei = (T)(amp * __builtin_amdgcn_sinf(r));
   } else {
     cexp_neg_units(tab, g, v, in, er, ei);
   }
 }
 
 // u_c += (er + i ei) B_c, c = 0..2 (complex)
-__device__ __forceinline__ void accumulate_term(double (&u)[6], const double (&B)[6], double er, double ei)
+template <typename T>
+__device__ __forceinline__ void accumulate_term(T (&u)[6], const T (&B)[6], T er, T ei)
 {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -79,12 +88,12 @@ __device__ __forceinline__ void accumulate_term(double (&u)[6], const double (&B
   }
 }
 
-// MIXED: the exponent and the phase (in revolutions, reduced to [-1/2, 1/2])
-// are formed in FP64, then exp2 / sin / cos run on the FP32 transcendental
-// unit; sums stay FP64.  Otherwise the FP64 table-driven exponential.
-template <bool MIXED>
+// MODE: SUM_FP64, SUM_MIXED or SUM_MIXED32 (the term and its sum as stated
+// at point_term; MIXED32 holds the tile's records B and the sums in FP32).
+template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_sum_points(PointsArgs a, int groups, int64_t nblk)
 {
+  using Acc = typename std::conditional<MODE == SUM_MIXED32, float, double>::type;
   __shared__ TrigTables tab;
   fill_tables(tab);
   __syncthreads();
@@ -106,11 +115,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int s = wk.s;
   const double *E = a.emit + (int64_t)s * 12 * a.nb;
   uint64_t cnt = 0;          // wave-uniform in-window count
-  double u[RW][6];
+  Acc u[RW][6];
 #pragma unroll
   for (int k = 0; k < RW; ++k)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) u[k][c] = 0.0;
+    for (int c = 0; c < 6; ++c) u[k][c] = (Acc)0;
 
   // bounding box of the wavefront's points; a beam tile whose box lies more
   // than R away from it along some axis holds no term for any of them (the
@@ -157,7 +166,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     return b1;
   };
   // records of the lane's beam for the current tile
-  double q[3], pe[3], B[6];
+  double q[3], pe[3];
+  Acc B[6];
   auto fetch = [&](int64_t t0) {
     const int64_t j = t0 + lane;
     const bool v = j < b1;
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       pe[d] = v ? E[(3 + d) * a.nb + j] : 0.0;
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) B[c] = v ? E[(6 + c) * a.nb + j] : 0.0;
+    for (int c = 0; c < 6; ++c) B[c] = v ? (Acc)E[(6 + c) * a.nb + j] : (Acc)0;
   };
   for (int64_t t0 = next_live(b0); t0 < b1; t0 = next_live(t0 + 64)) {
     fetch(t0);
@@ -186,7 +196,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       for (int h = 0; h < GRP; ++h) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) dd[h][d] = xr[k + h][d] - q[d];
-        in[h] = !(fmax(fabs(dd[h][0]), fmax(fabs(dd[h][1]), fabs(dd[h][2]))) > R);
+        in[h] = fmax(fabs(dd[h][0]), fmax(fabs(dd[h][1]), fabs(dd[h][2]))) <= R;  // false for an all-NaN offset
         const uint64_t bal = __ballot(in[h]);
         cnt += __popcll(bal);
         need |= bal ? 1u << h : 0u;
@@ -195,20 +205,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
       for (int h = 0; h < GRP; ++h)
         if (need & (1u << h)) {
-          double er, ei;
-          point_term<MIXED>(tab, dd[h], pe, in[h], hieps, er, ei);
+          Acc er, ei;
+          point_term<MODE>(tab, dd[h], pe, in[h], hieps, er, ei);
           accumulate_term(u[k + h], B, er, ei);
         }
     }
   }
-  // lane reduction in a fixed butterfly order; every lane ends with the total
+  // lane reduction in FP64 in a fixed butterfly order; every lane ends with the total
+  double ud[RW][6];
 #pragma unroll
   for (int k = 0; k < RW; ++k)
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      double v = u[k][c];
+      double v = (double)u[k][c];
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      u[k][c] = v;
+      ud[k][c] = v;
     }
   if (lane < RW * 6) {
     const int k = lane / 6, c = lane % 6;
@@ -217,7 +228,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int kk = 0; kk < RW; ++kk)
 #pragma unroll
       for (int cc = 0; cc < 6; ++cc)
-        if (kk == k && cc == c) v = u[kk][cc];
+        if (kk == k && cc == c) v = ud[kk][cc];
     if (r0 + k < a.n) a.partial[((wk.blk * a.m + s) * a.n + r0 + k) * 6 + c] = v;
   }
   if (a.evals && lane == 0 && cnt) atomicAdd(a.evals, (unsigned long long)cnt);
@@ -328,8 +339,12 @@ hipError_t launch_sum_points(const PointsArgs &a, int *nblk_out, hipStream_t st)
   const int64_t nwg = units * groups;
   if (nwg > 0x7fffffff) return hipErrorInvalidConfiguration;
   ProfScope prof(FGA_K_SUM_POINTS, st);
-  if (a.precision == FGA_FP32) hipLaunchKernelGGL(k_sum_points<true>, dim3((unsigned)nwg), 256, 0, st, a, groups, nblk);
-  else hipLaunchKernelGGL(k_sum_points<false>, dim3((unsigned)nwg), 256, 0, st, a, groups, nblk);
+  if (a.precision == FGA_FP32)
+    hipLaunchKernelGGL(k_sum_points<SUM_MIXED>, dim3((unsigned)nwg), 256, 0, st, a, groups, nblk);
+  else if (a.precision == FGA_FP32_ACC32)
+    hipLaunchKernelGGL(k_sum_points<SUM_MIXED32>, dim3((unsigned)nwg), 256, 0, st, a, groups, nblk);
+  else
+    hipLaunchKernelGGL(k_sum_points<SUM_FP64>, dim3((unsigned)nwg), 256, 0, st, a, groups, nblk);
   return hipGetLastError();
 }
 

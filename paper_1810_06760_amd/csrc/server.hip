@@ -37,7 +37,7 @@ struct Sizes {
 bool request_sizes(const fga_request *r, Sizes *z)
 {
   if (!r || r->nsteps < 0 || r->stride < 1 || r->n_receivers < 0) return false;
-  if (r->precision != FGA_FP64 && r->precision != FGA_FP32) return false;
+  if (r->precision != FGA_FP64 && r->precision != FGA_FP32 && r->precision != FGA_FP32_ACC32) return false;
   if (r->receiver_coords != FGA_COORDS_CARTESIAN && r->receiver_coords != FGA_COORDS_SPHERICAL) return false;
   const int64_t cand = r->point_source ? fga_point_source_candidates(&r->source) : fga_decompose_candidates(&r->mesh);
   if (cand <= 0) return false;

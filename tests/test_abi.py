@@ -46,7 +46,9 @@ def test_plane_layout_matches_header():
     import paper_1810_06760_amd as fga
     text = open(HEADER).read()
     for name in ("FGA_Q", "FGA_P", "FGA_ZQ_RE", "FGA_ZQ_IM", "FGA_ZP_RE", "FGA_ZP_IM", "FGA_A0_RE", "FGA_A1_IM",
-                 "FGA_S", "FGA_W_RE", "FGA_W_IM", "FGA_E", "FGA_NF64", "FGA_BRANCH", "FGA_FLAGS", "FGA_NI32"):
+                 "FGA_S", "FGA_W_RE", "FGA_W_IM", "FGA_E", "FGA_NF64", "FGA_BRANCH", "FGA_FLAGS", "FGA_NI32",
+                 "FGA_FP64", "FGA_FP32", "FGA_BF16X3", "FGA_FP16X3", "FGA_FP16X2", "FGA_FP32_ACC32",
+                 "FGA_COORDS_CARTESIAN", "FGA_COORDS_SPHERICAL"):
         m = re.search(r"\b%s = (\d+)" % name, text)
         assert m, name
         assert getattr(fga, name) == int(m.group(1)), name

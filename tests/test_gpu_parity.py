@@ -240,18 +240,20 @@ def test_points_parity():
         assert rel_l2(m.to_complex(ug), uo) <= RTOL
 
 
-def test_points_mixed_precision():
-    """Receiver sums in mixed mode (FP64 arguments, FP32 exp/sin/cos, FP64
-    sums) against the oracle: relative L2 <= 1e-3, exact in-window count."""
+@pytest.mark.parametrize("prec", ["FGA_FP32", "FGA_FP32_ACC32"])
+def test_points_mixed_precision(prec):
+    """Receiver sums in the mixed modes (FP64 arguments, FP32 exp/sin/cos;
+    FP64 products and sums, or FP32 products and per-lane sums) against the
+    oracle: relative L2 <= 1e-3, exact in-window count."""
     m = fga()
-    say("points mixed")
+    say("points mixed", prec)
     w = small_c1(nq=5, np_=3, ny=16)
     ob = evolved_beams(w, 40, 0.005)
     bs = m.BeamSet(len(ob))
     bs.load(oracle_to_dict(ob))
     x = fi.uniform_points(300, np.random.default_rng(2), -0.2, 1.2)
     uo, co = om.sum_points(ob, x, w.eps, 16.0)
-    ug, cg = m.fga_reconstruct_points(bs, w.eps, 16.0, x, precision=m.FGA_FP32)
+    ug, cg = m.fga_reconstruct_points(bs, w.eps, 16.0, x, precision=getattr(m, prec))
     assert cg == co
     err = rel_l2(m.to_complex(ug), uo)
     say("  rel L2", err)
@@ -479,9 +481,10 @@ def test_quarantine_non_finite_beam(case):
     compare_states({k: v[others] for k, v in g.items()}, om.take_beams(ob, np.nonzero(others)[0]))
 
 
-def test_seismogram_mixed_precision():
+@pytest.mark.parametrize("prec", ["FGA_FP32", "FGA_FP32_ACC32"])
+def test_seismogram_mixed_precision(prec):
     m = fga()
-    say("seismogram mixed")
+    say("seismogram mixed", prec)
     w = small_c2(nq=4, np_=2, ny=16)
     ob = om.decompose(w)
     bs = m.BeamSet(len(ob))
@@ -489,7 +492,7 @@ def test_seismogram_mixed_precision():
     rec = w.receivers
     nsteps, dt, tau = 24, 2e-3, 16.0
     seis, st = m.fga_evolve(m.medium_for(w), bs, dt, nsteps, receivers=rec, eps=w.eps, tau=tau, stride=3,
-                            precision=m.FGA_FP32)
+                            precision=getattr(m, prec))
     med_o = om.medium_for(w)
     ref = np.zeros((len(rec), nsteps // 3, 3), dtype=np.complex128)
     for s in range(nsteps // 3):

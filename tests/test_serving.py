@@ -200,7 +200,7 @@ def test_footprint_is_a_host_query():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed32"])
 def test_served_solve_matches_oracle(precision):
     """A served point-source solve in a smooth grid medium (the sweep's model
     recipe) against the oracle's decompose -> evolve -> sum at the receivers
@@ -216,7 +216,7 @@ def test_served_solve_matches_oracle(precision):
     eps, nsteps, dt, stride = 1.0 / 32, 30, 2e-3, 3
     src = m.point_source(eps, rq["x0"], rq["M"], nq=3, ndir=16, nshell=2)
     x = rq["receivers"][:10]
-    prec = m.FGA_FP64 if precision == "fp64" else m.FGA_FP32
+    prec = {"fp64": m.FGA_FP64, "mixed": m.FGA_FP32, "mixed32": m.FGA_FP32_ACC32}[precision]
     other = m.point_source(eps, rq["x0"] + 0.05, rq["M"], nq=4, ndir=24, nshell=2)
     srv = m.Server(1 << 32, 2)
     try:
