@@ -105,7 +105,7 @@ def lib():
         L.om_evolve_layered.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_double,
                                         vp]
         L.om_interface_modes.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, vp, vp, vp]
-        L.om_interface_jacobians.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, vp, vp]
+        L.om_interface_jacobians.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, vp, vp]
         L.om_child_lineage.restype = C.c_int64
         L.om_child_lineage.argtypes = [C.c_int64, C.c_int, C.c_int]
         L.om_layer_exit.restype = C.c_int
@@ -348,14 +348,15 @@ def interface_modes(med: OracleMedium, layer: int, new_layer: int, normal, sp_in
     return out
 
 
-def interface_jacobians(normal, Pin, Pout, c_in, c_out, ZQ, ZP, grad_in=(0, 0, 0), grad_out=(0, 0, 0)):
-    """Map (dzQ, dzP) across an interface to one outgoing mode."""
+def interface_jacobians(normal, Pin, Pout, c_in, c_out, ZQ, ZP, grad_in=(0, 0, 0), grad_out=(0, 0, 0), kcurv=0.0):
+    """Map (dzQ, dzP) across an interface to one outgoing mode (kcurv: the
+    signed curvature s/R of a spherical interface, 0 for a flat one)."""
     ZQ = np.array(ZQ, dtype=np.complex128, order="C")
     ZP = np.array(ZP, dtype=np.complex128, order="C")
     args = [np.ascontiguousarray(v, dtype=np.float64) for v in (normal, Pin, Pout)]
     g = [np.ascontiguousarray(v, dtype=np.float64) for v in (grad_in, grad_out)]
     lib().om_interface_jacobians(_p(args[0]), _p(args[1]), _p(args[2]), c_in, c_out, _p(g[0]), _p(g[1]),
-                                 _p(ZQ), _p(ZP))
+                                 float(kcurv), _p(ZQ), _p(ZP))
     return ZQ, ZP
 
 

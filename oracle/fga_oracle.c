@@ -1139,9 +1139,20 @@ int64_t om_child_lineage(int64_t parent, int gen_parent, int k)
  *   dzP' = dzP W - |Pout| / (c_out p_n') (dzQ' grad c_out - dzQ grad c_in) (x) n,
  *   W = F^{-T} = I - v (x) n / (kappa p_n' / p_n)
  * (the printed 3x3 F written in any frame whose third axis is n; rows of dzQ
- * are the z-derivatives, columns the spatial components). */
+ * are the z-derivatives, columns the spatial components).
+ *
+ * The printed map is that of a flat interface.  On a curved one the normal
+ * turns with the crossing point: with the shape operator K = dn/dx (for a
+ * sphere of radius R and n = s x/|x|, K = (s/R)(I - n (x) n)) the outgoing
+ * momentum P' = P + mu n(x*), mu = p_n' - p_n, gains mu K dzQ*, where
+ * dzQ* = dzQ - (dzQ.n) Pin/p_n is the z-derivative of the crossing point
+ * (tangent to the interface), and keeping H = c|P| fixed moves the normal
+ * part by -mu (Pout.K dzQ*)/p_n'.  For the sphere (K dzQ* = (s/R) dzQ*):
+ *   dzP' += kcurv mu (dzQ* - n (Pout.dzQ*)/p_n'),   kcurv = s/R,
+ * and kcurv = 0 on a flat interface.  The derivation holds where grad c = 0
+ * at the crossing (homogeneous layers, the media this map is used in). */
 void om_interface_jacobians(const double n[3], const double Pin[3], const double Pout[3], double c_in, double c_out,
-                            const double gin[3], const double gout[3], cplx ZQ[3][3], cplx ZP[3][3])
+                            const double gin[3], const double gout[3], double kcurv, cplx ZQ[3][3], cplx ZP[3][3])
 {
   const double pn = dot3(Pin, n), pno = dot3(Pout, n);
   const double kap = (c_out / c_in) * (c_out / c_in);
@@ -1162,6 +1173,16 @@ void om_interface_jacobians(const double n[3], const double Pin[3], const double
     cplx g = 0.0;
     for (int i = 0; i < 3; ++i) g += ZQo[mrow][i] * gout[i] - ZQ[mrow][i] * gin[i];
     for (int j = 0; j < 3; ++j) ZPo[mrow][j] -= f * g * n[j];
+  }
+  if (kcurv != 0.0) {
+    const double mu = pno - pn;
+    for (int mrow = 0; mrow < 3; ++mrow) {
+      cplx qn = 0.0, ps = 0.0, qs[3];
+      for (int i = 0; i < 3; ++i) qn += ZQ[mrow][i] * n[i];
+      for (int i = 0; i < 3; ++i) qs[i] = ZQ[mrow][i] - qn * Pin[i] / pn;
+      for (int i = 0; i < 3; ++i) ps += Pout[i] * qs[i];
+      for (int j = 0; j < 3; ++j) ZPo[mrow][j] += kcurv * mu * (qs[j] - n[j] * ps / pno);
+    }
   }
   memcpy(ZQ, ZQo, sizeof(ZQo));
   memcpy(ZP, ZPo, sizeof(ZPo));
@@ -1201,10 +1222,12 @@ int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t
       om_rk4_step(m, &x, th * dt);
       /* exactly onto the interface */
       double nrm[3] = {0.0, 0.0, 0.0};
+      double kcurv = 0.0;
       if (m->geometry == 1) {
         const double r = sqrt(dot3(x.Q, x.Q));
         for (int k = 0; k < 3; ++k) x.Q[k] *= m->bound[iface] / r;
-        for (int k = 0; k < 3; ++k) nrm[k] = (newL > y0.layer ? -1.0 : 1.0) * x.Q[k] / m->bound[iface];
+        kcurv = (newL > y0.layer ? -1.0 : 1.0) / m->bound[iface];
+        for (int k = 0; k < 3; ++k) nrm[k] = kcurv * x.Q[k];
       } else {
         x.Q[2] = m->bound[iface];
         nrm[2] = newL > y0.layer ? 1.0 : -1.0;
@@ -1232,7 +1255,7 @@ int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t
         const double c_out = md[k].sp == 0 ? m->cpl[lay] : m->csl[lay];
         double gz[3] = {0.0, 0.0, 0.0};
         memcpy(c.P, md[k].P, sizeof c.P);
-        om_interface_jacobians(nrm, x.P, c.P, c_in, c_out, gz, gz, c.ZQ, c.ZP);
+        om_interface_jacobians(nrm, x.P, c.P, c_in, c_out, gz, gz, kcurv, c.ZQ, c.ZP);
         c.layer = lay;
         c.branch = md[k].sp == 0 ? 0 : 2;
         c.gen = x.gen + 1;

@@ -21,7 +21,11 @@
 //   - Jacobians: dzQ' = dzQ F, dzP' = dzP F^{-T} - (gradient terms, zero in
 //     homogeneous layers), with F = I + n (x) v in any frame with third axis
 //     n, v = (kappa - 1) p_t / p_n + (kappa p_n' / p_n - 1) n,
-//     kappa = (c_out / c_in)^2.
+//     kappa = (c_out / c_in)^2.  That is the flat-interface map; on a sphere
+//     of radius R the normal n = s x/R turns with the crossing point, which
+//     adds kcurv mu (dzQ* - n (P'.dzQ*)/p_n') to each row of dzP', with
+//     kcurv = s/R, mu = p_n' - p_n and dzQ* = dzQ - (dzQ.n) P/p_n the
+//     crossing point's derivative (from P' = P + mu n(x*) and c|P| fixed).
 // Children with |A_child| >= child_cut |A_in| are made (generation + 1,
 // lineage FGA_LINEAGE_CHILD) and take the remaining (1 - theta) dt in their
 // own layer.  The first child reuses the parent's slot; the others go after
@@ -223,17 +227,20 @@ __device__ void outgoing_modes(const DevMedium &m, int L, int L2, const double n
 }
 
 // dzQ, dzP (planes of y) mapped to an outgoing mode with momentum Pout and
-// speed ratio c_out / c_in across normal n (homogeneous layers: no gradient terms).
+// speed ratio c_out / c_in across normal n (homogeneous layers: no gradient
+// terms); kcurv: signed curvature s/R of a spherical interface, 0 if flat.
 __device__ void map_jacobians(double *y, const double n[3], const double Pin[3], const double Pout[3], double c_in,
-                              double c_out)
+                              double c_out, double kcurv)
 {
   const double pn = dot3(Pin, n), pno = dot3(Pout, n);
   const double kap = (c_out / c_in) * (c_out / c_in);
   double v[3];
   for (int d = 0; d < 3; ++d) v[d] = (kap - 1.0) * (Pin[d] - pn * n[d]) / pn + (kap * pno / pn - 1.0) * n[d];
   const double den = kap * pno / pn;
+  const double kmu = kcurv * (pno - pn);
   for (int r = 0; r < 3; ++r) {
-    // row r of dzQ gains (row . n) v; row r of dzP loses (row . v) / den n
+    // row r of dzQ gains (row . n) v; row r of dzP loses (row . v) / den n and
+    // gains kmu (qs - n (Pout . qs) / p_n') with qs = row - (row . n) Pin / p_n
     double qnr = 0.0, qni = 0.0, pvr = 0.0, pvi = 0.0;
     for (int d = 0; d < 3; ++d) {
       qnr += y[IZQR + 3 * r + d] * n[d];
@@ -241,11 +248,18 @@ __device__ void map_jacobians(double *y, const double n[3], const double Pin[3],
       pvr += y[IZPR + 3 * r + d] * v[d];
       pvi += y[IZPI + 3 * r + d] * v[d];
     }
+    double qsr[3], qsi[3], psr = 0.0, psi = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      qsr[d] = y[IZQR + 3 * r + d] - qnr * Pin[d] / pn;
+      qsi[d] = y[IZQI + 3 * r + d] - qni * Pin[d] / pn;
+      psr += Pout[d] * qsr[d];
+      psi += Pout[d] * qsi[d];
+    }
     for (int d = 0; d < 3; ++d) {
       y[IZQR + 3 * r + d] += qnr * v[d];
       y[IZQI + 3 * r + d] += qni * v[d];
-      y[IZPR + 3 * r + d] -= pvr / den * n[d];
-      y[IZPI + 3 * r + d] -= pvi / den * n[d];
+      y[IZPR + 3 * r + d] += kmu * (qsr[d] - n[d] * psr / pno) - pvr / den * n[d];
+      y[IZPI + 3 * r + d] += kmu * (qsi[d] - n[d] * psi / pno) - pvi / den * n[d];
     }
   }
 }
@@ -265,6 +279,7 @@ struct Crossing {
   double th;
   int newL;
   double n[3];
+  double kcurv;  // signed curvature of the interface at the crossing (0: flat)
   Modes md;
   bool keep[4];
   int nkeep;
@@ -301,9 +316,11 @@ __device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, d
   if (m.geometry == 1) {
     const double r = sqrt(dot3(y + IQ, y + IQ));
     for (int d = 0; d < 3; ++d) y[IQ + d] *= rb / r;
-    for (int d = 0; d < 3; ++d) c.n[d] = (newL > L ? -1.0 : 1.0) * y[IQ + d] / rb;
+    c.kcurv = (newL > L ? -1.0 : 1.0) / rb;
+    for (int d = 0; d < 3; ++d) c.n[d] = c.kcurv * y[IQ + d];
   } else {
     y[IQ + 2] = rb;
+    c.kcurv = 0.0;
     c.n[0] = c.n[1] = 0.0;
     c.n[2] = newL > L ? 1.0 : -1.0;
   }
@@ -408,7 +425,7 @@ __global__ __launch_bounds__(256) void k_interface(DevMedium m, InterfaceArgs a)
     double z[NS], ec[3];
     for (int f = 0; f < NS; ++f) z[f] = y[f];
     for (int d = 0; d < 3; ++d) z[IP + d] = c.md.P[k][d];
-    map_jacobians(z, c.n, y + IP, z + IP, c_in, c_out);
+    map_jacobians(z, c.n, y + IP, z + IP, c_in, c_out, c.kcurv);
     initial_axis(z + IP, ec);
     if (spc == 0) {
       const double ip = 1.0 / sqrt(dot3(z + IP, z + IP));
