@@ -146,3 +146,95 @@ def test_point_force_against_exact_solution():
     say("  relative L2 error on the plane y = 1/2 at t = 0.25: %.4f (imaginary part %.4f), %d beams, %d terms"
         % (err, imag, beams.count, ev))
     assert err < 0.03
+
+
+@pytest.mark.timeout(900)
+def _waveguide(radii, cp, cs, rho, stations=(0.34, 0.42, 0.5), nsteps=250, full=False):
+    """FGA of the radially symmetric shell (eps = 1/128, both directions,
+    P/SV/SH beams; in layered media spherical interfaces with splitting)
+    against the radial finite-difference solution of the same elastic problem
+    (tests/radial_fd.py, pinned in test_oracle_radial.py): the radial
+    displacement at three stations on the x axis, r = 0.34, 0.42, 0.5, after
+    every step to t = 0.25.  Returns the relative L2 error over all samples.
+
+    Meshes: y 96^3 on [-0.45, 0.45]^3 (the shell lies inside with its
+    Gaussian tails); q 9^3 on the same cube; p 54^3 on [-2.4, 2.4]^3, which
+    holds the shell's wavenumbers (2 pi/l = 128 = 1/eps, envelope width 1/sigma
+    = 45, so |p| up to about 2.1) with the window's spread.  A numpy
+    evaluation of the t = 0 sum on these meshes recovers the initial data
+    within 0.6 % on the axis."""
+    import torch
+    import paper_1810_06760_amd as m
+    import radial_fd as rf
+    m.lib()
+    eps, r0, sig, ell = 1.0 / 128, 0.3, 0.022, 0.049
+    ym = fi.cell_centred(96, -0.45, 0.45)
+    f = fi.radial_shell(ym, r0, sig, ell)
+    qm = fi.cell_centred(9, -0.45, 0.45)
+    pm = fi.cell_centred(54, -2.4, 2.4)
+    # cull at 3e-3 of the largest weight (|psi| = |FBI[f].n|/2, at most 0.024 for this shell; the
+    # beams kept hold all but 1.3e-4 of sum |psi|^2): about 2e7 beams of 6.9e8 candidates
+    mesh = m.make_mesh(eps, qm, pm, ym, one_way=False, cull_abs=7.2e-5)
+    med = m.Medium.layered(1, radii, cp, cs, rho) if radii else m.Medium.homogeneous(cp[0], cs[0], rho[0])
+    ncand = int(m.lib().fga_decompose_candidates(m.C.byref(mesh)))
+    big = m.BeamSet(100_000_000)                     # room for the interface children (444 B per beam)
+    m.fga_decompose(med, mesh, f, beams=big)
+    n0 = big.count
+    wmax = float(torch.hypot(big.f64[m.FGA_W_RE, :n0], big.f64[m.FGA_W_IM, :n0]).max())
+    say("waveguide (%d interfaces): %d beams of %d candidates, max |w| %.3e" % (len(radii), n0, ncand, wmax))
+    # the same level for the evolution: a beam (interface children included) whose |w| max|a|
+    # falls below 3e-3 of the largest initial weight is dropped, and the set is compacted
+    # after every call of 25 steps
+    dt, seg = 1e-3, 25
+    st = np.array([[r, 0.0, 0.0] for r in stations])
+    parts = []
+    tot = {"crossings": 0, "spawned": 0, "culled": 0}
+    for k in range(nsteps // seg):
+        seis, stats = m.fga_evolve(med, big, dt, seg, receivers=st, eps=eps, tau=25.0, cutoff_abs=3e-3 * wmax,
+                                   compact=True)
+        parts.append(m.to_complex(seis))
+        for key in tot:
+            tot[key] += stats[key]
+        say("  t = %.3f: %d beams" % ((k + 1) * seg * dt, big.count))
+    say("  %d interface hits, %d children, %d culled" % (tot["crossings"], tot["spawned"], tot["culled"]))
+    got = np.concatenate(parts, axis=1).real[:, :, 0]    # x component = radial on the x axis, [station][sample]
+    times = np.arange(0, nsteps + 1) * dt
+    ref, _ = rf.solve(radii, cp, cs, rho, lambda r: _dphi(r - r0, sig, ell), 1.2, times[-1], ell / 60, times,
+                      st[:, 0])
+    ref = ref[1:].T
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    per = [np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k]) for k in range(len(st))]
+    say("  relative L2 error of the radial displacement: %.4f (stations: %s)" % (err, ", ".join("%.4f" % v for v in per)))
+    return (err, got, ref) if full else err
+
+
+def test_radial_shell_homogeneous_against_fd():
+    """The shell of the waveguide check in one homogeneous medium (c_P 1.7,
+    c_S 1.0, rho 1.0): straight rays through the focus at the centre; the FGA
+    seismograms within 5 % of the radial finite-difference solution."""
+    assert _waveguide([], [1.7], [1.0], [1.0]) < 0.05
+
+
+def test_radial_waveguide_against_fd():
+    """The waveguide check of Sec. 3.2 (eq:we_radially_symmetric) in box
+    units: concentric shells (interfaces at r = 0.75 and 0.55; c_P 1.9, 1.8,
+    1.7; c_S 1.1, 1.05, 1.0; rho 1.3, 1.15, 1.0 from the outside in) around
+    the shell of initial displacement u = grad phi0(|x| - 0.3), u_t = 0, to
+    t = 0.45: a station inside (r = 0.2: the inward pulse, its passage
+    through the focus at the centre and the reflection from r = 0.55) and two
+    outside both interfaces (r = 0.95, 1.05: the pulse transmitted twice).
+    The FGA seismograms, with the spherical interface map and the Zoeppritz
+    amplitudes of every beam, within 10 % of the radial finite-difference
+    solution of the same elastic problem.  The stations stay at least 0.2
+    (2.3 beam widths sqrt(eps)) from the interfaces: closer in, the
+    children's Gaussian tails on the far side of an interface stand in for
+    the parent's (a method error of the order of the reflection
+    coefficient)."""
+    err = _waveguide([0.75, 0.55], [1.9, 1.8, 1.7], [1.1, 1.05, 1.0], [1.3, 1.15, 1.0],
+                     stations=(0.2, 0.95, 1.05), nsteps=450)
+    assert err < 0.10
+
+
+def _dphi(s, sig, ell):
+    e = np.exp(-s * s / (2 * sig * sig))
+    return -(s / sig ** 2) * e * np.cos(2 * math.pi * s / ell) - (2 * math.pi / ell) * e * np.sin(2 * math.pi * s / ell)
