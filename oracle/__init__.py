@@ -57,7 +57,7 @@ class Medium(C.Structure):
         ("tab", C.POINTER(C.c_double)), ("cs_ratio", C.c_double), ("two_fields", C.c_int),
         ("x0", C.c_double * 3), ("amp", C.c_double), ("s", C.c_double), ("g", C.c_double * 3),
         ("nlayer", C.c_int), ("bound", C.c_double * 8),
-        ("cpl", C.c_double * 8), ("csl", C.c_double * 8), ("rhol", C.c_double * 8),
+        ("cpl", C.c_double * 8), ("csl", C.c_double * 8), ("rhol", C.c_double * 8), ("gradl", C.c_double * 8),
     ]
 
 
@@ -104,7 +104,7 @@ def lib():
         L.om_evolve_layered.restype = C.c_int64
         L.om_evolve_layered.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_double,
                                         vp]
-        L.om_interface_modes.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, vp, vp, vp]
+        L.om_interface_modes.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, vp]
         L.om_interface_jacobians.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, vp, vp]
         L.om_child_lineage.restype = C.c_int64
         L.om_child_lineage.argtypes = [C.c_int64, C.c_int, C.c_int]
@@ -204,7 +204,9 @@ def grid(cp_nodes: np.ndarray, mesh, cs_ratio: float = None, cs_nodes: np.ndarra
     return OracleMedium(m, keep=[tab, n, h])
 
 
-def layered(geometry: int, bounds, cp, cs, rho) -> OracleMedium:
+def layered(geometry: int, bounds, cp, cs, rho, grad=None) -> OracleMedium:
+    """Flat (geometry 0) or spherical (1) layers; grad: relative gradient per
+    layer, c_b(x) = c_b,i (1 + grad[i] v(x)) with v = z or |x| (None: constant)."""
     m = Medium()
     m.kind, m.geometry = LAYERED, geometry
     m.nlayer = len(cp)
@@ -212,6 +214,8 @@ def layered(geometry: int, bounds, cp, cs, rho) -> OracleMedium:
     m.cpl[:len(cp)] = list(cp)
     m.csl[:len(cs)] = list(cs)
     m.rhol[:len(rho)] = list(rho)
+    if grad is not None:
+        m.gradl[:len(grad)] = list(grad)
     m.cp, m.cs, m.rho = cp[0], cs[0], rho[0]
     return OracleMedium(m)
 
@@ -337,14 +341,15 @@ MODE_DTYPE = np.dtype([("exists", np.int32), ("sp", np.int32), ("side", np.int32
                        ("A", np.complex128, 3)], align=True)
 
 
-def interface_modes(med: OracleMedium, layer: int, new_layer: int, normal, sp_in: int, P, A):
-    """Snell / elastic boundary problem at one interface point: returns the
+def interface_modes(med: OracleMedium, layer: int, new_layer: int, normal, sp_in: int, P, A, x=(0.0, 0.0, 0.0)):
+    """Snell / elastic boundary problem at the interface point x: returns the
     4 outgoing modes (P reflected, S reflected, P transmitted, S transmitted)."""
     out = np.zeros(4, dtype=MODE_DTYPE)
     n = np.ascontiguousarray(normal, dtype=np.float64)
     P = np.ascontiguousarray(P, dtype=np.float64)
     A = np.ascontiguousarray(A, dtype=np.complex128)
-    lib().om_interface_modes(med.ref, layer, new_layer, _p(n), sp_in, _p(P), _p(A), _p(out))
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    lib().om_interface_modes(med.ref, layer, new_layer, _p(xx), _p(n), sp_in, _p(P), _p(A), _p(out))
     return out
 
 

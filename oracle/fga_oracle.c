@@ -42,7 +42,8 @@ enum {
   OM_GRID = 1,         /* periodic node grid of c_P (and c_S or a fixed ratio)      */
   OM_BUMP = 2,         /* c_b(x) = c0_b (1 + amp exp(-|x-x0|^2/(2 s^2)))            */
   OM_LINEAR = 3,       /* c_b(x) = c0_b (1 + g.x)                                   */
-  OM_LAYERED = 4       /* flat layers in z or spherical shells, constant per layer */
+  OM_LAYERED = 4       /* flat layers in z or spherical shells, each with a speed that is
+                          constant or linear in the level (z or |x|)                  */
 };
 
 #define OM_MAXL 8
@@ -64,6 +65,9 @@ typedef struct {
   int nlayer;
   double bound[OM_MAXL];
   double cpl[OM_MAXL], csl[OM_MAXL], rhol[OM_MAXL];
+  /* relative gradient of each layer: c_b(x) = c_b,i (1 + gradl[i] v(x)) with the level
+     v = z (flat) or |x| (spherical); 0 for a constant layer                               */
+  double gradl[OM_MAXL];
 } om_medium;
 
 /* Derived fields of one scalar node field: c, dc/dx, dc/dy, dc/dz,
@@ -123,9 +127,26 @@ void om_speed(const om_medium *m, int sp, int layer, const double x[3],
   case OM_HOMOGENEOUS:
     *c = sp == 0 ? m->cp : m->cs;
     return;
-  case OM_LAYERED:
-    *c = sp == 0 ? m->cpl[layer] : m->csl[layer];
+  case OM_LAYERED: {
+    const double c0 = sp == 0 ? m->cpl[layer] : m->csl[layer];
+    const double gm = m->gradl[layer];
+    if (gm == 0.0) {
+      *c = c0;
+      return;
+    }
+    if (m->geometry == 1) {
+      /* c = c0 (1 + gm r): grad c = c0 gm x/r, Hess c = c0 gm (I - x x^T/r^2)/r */
+      const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+      *c = c0 * (1.0 + gm * r);
+      for (int i = 0; i < 3; ++i) gc[i] = c0 * gm * x[i] / r;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) H[i][j] = c0 * gm * ((i == j ? 1.0 : 0.0) - x[i] * x[j] / (r * r)) / r;
+    } else {
+      *c = c0 * (1.0 + gm * x[2]);
+      gc[2] = c0 * gm;
+    }
     return;
+  }
   case OM_BUMP: {
     double c0 = sp == 0 ? m->cp : m->cs;
     double d[3] = {x[0] - m->x0[0], x[1] - m->x0[1], x[2] - m->x0[2]};
@@ -1012,10 +1033,20 @@ typedef struct {
  *   in the local frame e3 = n, e1 = tangential momentum direction,
  *   e2 = e3 x e1.
  * out[0..3] = (P reflected, S reflected, P transmitted, S transmitted). */
-void om_interface_modes(const om_medium *m, int L, int newL, const double n[3], int sp_in, const double Pin[3],
-                        const cplx Ain[3], om_mode out[4])
+void om_interface_modes(const om_medium *m, int L, int newL, const double xc[3], const double n[3], int sp_in,
+                        const double Pin[3], const cplx Ain[3], om_mode out[4])
 {
-  const double c_in = sp_in == 0 ? m->cpl[L] : m->csl[L];
+  /* speeds of both wave types on both sides at the crossing point xc (the
+     layer constants where the layers are homogeneous) */
+  double cP[2], cS[2];
+  {
+    double gdum[3], Hdum[3][3];
+    om_speed(m, 0, L, xc, &cP[0], gdum, Hdum);
+    om_speed(m, 1, L, xc, &cS[0], gdum, Hdum);
+    om_speed(m, 0, newL, xc, &cP[1], gdum, Hdum);
+    om_speed(m, 1, newL, xc, &cS[1], gdum, Hdum);
+  }
+  const double c_in = sp_in == 0 ? cP[0] : cS[0];
   const double H = c_in * sqrt(dot3(Pin, Pin));
   const double pn = dot3(Pin, n);
   double pt[3] = {Pin[0] - pn * n[0], Pin[1] - pn * n[1], Pin[2] - pn * n[2]};
@@ -1036,7 +1067,6 @@ void om_interface_modes(const om_medium *m, int L, int newL, const double n[3], 
   const double sgn = pn >= 0.0 ? 1.0 : -1.0;
   /* media of the two sides */
   const double rho[2] = {m->rhol[L], m->rhol[newL]};
-  const double cP[2] = {m->cpl[L], m->cpl[newL]}, cS[2] = {m->csl[L], m->csl[newL]};
   double lam[2], mu[2];
   for (int s = 0; s < 2; ++s) {
     mu[s] = rho[s] * cS[s] * cS[s];
@@ -1132,67 +1162,91 @@ int64_t om_child_lineage(int64_t parent, int gen_parent, int k)
   return ((int64_t)(gen_parent + 1) << 58) | (path << 2) | k;
 }
 
-/* Map of the state of a beam at an interface point to one outgoing mode
- * (eq:Inter_DzQDzP): with n the unit normal, p_n = Pin.n, p_n' = Pout.n and
- * kappa = (c_out / c_in)^2,
- *   dzQ' = dzQ F,  F = I + n (x) v,  v = (kappa - 1) p_t / p_n + (kappa p_n'/p_n - 1) n
- *   dzP' = dzP W - |Pout| / (c_out p_n') (dzQ' grad c_out - dzQ grad c_in) (x) n,
- *   W = F^{-T} = I - v (x) n / (kappa p_n' / p_n)
- * (the printed 3x3 F written in any frame whose third axis is n; rows of dzQ
- * are the z-derivatives, columns the spatial components).
- *
- * The printed map is that of a flat interface.  On a curved one the normal
- * turns with the crossing point: with the shape operator K = dn/dx (for a
- * sphere of radius R and n = s x/|x|, K = (s/R)(I - n (x) n)) the outgoing
- * momentum P' = P + mu n(x*), mu = p_n' - p_n, gains mu K dzQ*, where
- * dzQ* = dzQ - (dzQ.n) Pin/p_n is the z-derivative of the crossing point
- * (tangent to the interface), and keeping H = c|P| fixed moves the normal
- * part by -mu (Pout.K dzQ*)/p_n'.  For the sphere (K dzQ* = (s/R) dzQ*):
- *   dzP' += kcurv mu (dzQ* - n (Pout.dzQ*)/p_n'),   kcurv = s/R,
- * and kcurv = 0 on a flat interface.  The derivation holds where grad c = 0
- * at the crossing (homogeneous layers, the media this map is used in). */
+/* Map of the state of a beam at an interface point x* to one outgoing mode
+ * (eq:Inter_DzQDzP; row m of dzQ, dzP is the derivative by z_m, columns the
+ * spatial components).  With n the unit normal, V = c P/|P| (the sign sigma
+ * of the branch cancels throughout), s = V_in.n, p_n = Pin.n, p_n' = Pout.n,
+ * mu = p_n' - p_n, per row (q_n = dzQ.n):
+ *   the crossing time and point move with z: dtau = -q_n / s,
+ *     dzQ* = dzQ - V_in q_n / s  (tangent to the interface);
+ *   P at the crossing: dzP* = dzP + |Pin| grad c_in q_n / s;
+ *   the outgoing momentum P' = P + mu n(x*) keeps the tangential part and
+ *   H = c|P|, so with the shape operator K = dn/dx (K = kcurv (I - n n^T) on
+ *   a sphere, kcurv = s/R for n = s x/R; 0 on a plane)
+ *     dmu = [(V_in - V_out).dzP* + (|Pin| grad c_in - |Pout| grad c_out).dzQ*
+ *            - mu V_out.(K dzQ*)] / (V_out.n),
+ *     dzP'* = dzP* + n dmu + mu K dzQ*;
+ *   and the child, started at the crossing, at the same instant:
+ *     dzQ' = dzQ* + V_out q_n / s,   dzP' = dzP'* - |Pout| grad c_out q_n / s.
+ * Where grad c = 0 and the interface is flat this is the printed map
+ * (dzQ' = dzQ F, dzP' = dzP F^{-T} with F = I + n (x) v, v = (kappa - 1) p_t/p_n
+ * + (kappa p_n'/p_n - 1) n, kappa = (c_out/c_in)^2).  The printed gradient
+ * terms are replaced by the ones above, and the curvature term added: with
+ * them the map equals finite-difference Jacobians of neighbouring rays on
+ * planes and spheres, in constant and in linear-gradient layers.  c_in, c_out,
+ * gin, gout: speeds and gradients of the incident and outgoing modes at x*. */
 void om_interface_jacobians(const double n[3], const double Pin[3], const double Pout[3], double c_in, double c_out,
                             const double gin[3], const double gout[3], double kcurv, cplx ZQ[3][3], cplx ZP[3][3])
 {
   const double pn = dot3(Pin, n), pno = dot3(Pout, n);
-  const double kap = (c_out / c_in) * (c_out / c_in);
-  double v[3];
-  for (int i = 0; i < 3; ++i) v[i] = (kap - 1.0) * (Pin[i] - pn * n[i]) / pn + (kap * pno / pn - 1.0) * n[i];
-  const double den = kap * pno / pn;
+  const double Pi = sqrt(dot3(Pin, Pin)), Po = sqrt(dot3(Pout, Pout));
+  double vin[3], vout[3];
+  for (int i = 0; i < 3; ++i) { vin[i] = c_in * Pin[i] / Pi; vout[i] = c_out * Pout[i] / Po; }
+  const double s_in = dot3(vin, n), s_out = dot3(vout, n), mu = pno - pn;
   cplx ZQo[3][3], ZPo[3][3];
-  for (int mrow = 0; mrow < 3; ++mrow) {
-    cplx qn = 0.0, pv = 0.0;
-    for (int i = 0; i < 3; ++i) { qn += ZQ[mrow][i] * n[i]; pv += ZP[mrow][i] * v[i]; }
+  for (int m = 0; m < 3; ++m) {
+    cplx qn = 0.0;
+    for (int i = 0; i < 3; ++i) qn += ZQ[m][i] * n[i];
+    cplx dQs[3], dPi[3], Kd[3], qsn = 0.0;
+    for (int i = 0; i < 3; ++i) dQs[i] = ZQ[m][i] - vin[i] * qn / s_in;
+    for (int i = 0; i < 3; ++i) qsn += dQs[i] * n[i];
+    for (int i = 0; i < 3; ++i) Kd[i] = kcurv * (dQs[i] - n[i] * qsn);
+    for (int i = 0; i < 3; ++i) dPi[i] = ZP[m][i] + Pi * gin[i] * qn / s_in;
+    cplx num = 0.0;
+    for (int i = 0; i < 3; ++i)
+      num += (vin[i] - vout[i]) * dPi[i] + (Pi * gin[i] - Po * gout[i]) * dQs[i] - mu * vout[i] * Kd[i];
+    const cplx dmu = num / s_out;
     for (int j = 0; j < 3; ++j) {
-      ZQo[mrow][j] = ZQ[mrow][j] + qn * v[j];
-      ZPo[mrow][j] = ZP[mrow][j] - pv / den * n[j];
-    }
-  }
-  const double f = sqrt(dot3(Pout, Pout)) / (c_out * pno);
-  for (int mrow = 0; mrow < 3; ++mrow) {
-    cplx g = 0.0;
-    for (int i = 0; i < 3; ++i) g += ZQo[mrow][i] * gout[i] - ZQ[mrow][i] * gin[i];
-    for (int j = 0; j < 3; ++j) ZPo[mrow][j] -= f * g * n[j];
-  }
-  if (kcurv != 0.0) {
-    const double mu = pno - pn;
-    for (int mrow = 0; mrow < 3; ++mrow) {
-      cplx qn = 0.0, ps = 0.0, qs[3];
-      for (int i = 0; i < 3; ++i) qn += ZQ[mrow][i] * n[i];
-      for (int i = 0; i < 3; ++i) qs[i] = ZQ[mrow][i] - qn * Pin[i] / pn;
-      for (int i = 0; i < 3; ++i) ps += Pout[i] * qs[i];
-      for (int j = 0; j < 3; ++j) ZPo[mrow][j] += kcurv * mu * (qs[j] - n[j] * ps / pno);
+      ZQo[m][j] = dQs[j] + vout[j] * qn / s_in;
+      ZPo[m][j] = dPi[j] + n[j] * dmu + mu * Kd[j] - Po * gout[j] * qn / s_in;
     }
   }
   memcpy(ZQ, ZQo, sizeof(ZQo));
   memcpy(ZP, ZPo, sizeof(ZPo));
 }
 
+/* Crossing fraction theta of a step from y0 in a layer whose speed varies
+ * (curved ray): four secant iterations on the level of the RK4 sub-step of
+ * theta dt from y0, started from 0 and from the straight-ray estimate. */
+static double om_crossing_secant(const om_medium *m, const om_beam *y0, int iface, double dt, double th0)
+{
+  const double b = m->bound[iface];
+  double ta = 0.0, fa = (m->geometry == 1 ? sqrt(dot3(y0->Q, y0->Q)) : y0->Q[2]) - b;
+  double tb = th0;
+  om_beam x = *y0;
+  om_rk4_step(m, &x, tb * dt);
+  double fb = (m->geometry == 1 ? sqrt(dot3(x.Q, x.Q)) : x.Q[2]) - b;
+  for (int it = 0; it < 4; ++it) {
+    if (fb == fa) break;
+    double tn = tb - fb * (tb - ta) / (fb - fa);
+    tn = tn < 0.0 ? 0.0 : (tn > 1.0 ? 1.0 : tn);
+    ta = tb;
+    fa = fb;
+    tb = tn;
+    x = *y0;
+    om_rk4_step(m, &x, tb * dt);
+    fb = (m->geometry == 1 ? sqrt(dot3(x.Q, x.Q)) : x.Q[2]) - b;
+  }
+  return tb;
+}
+
 /* Advance n beams (array capacity cap) by nsteps RK4 steps in a layered
  * medium with interfaces.  After each step a beam whose centre has left its
  * layer is split: it is moved back to the start of the step and advanced by
- * theta dt to the crossing (theta from the straight ray), Q is put exactly on
- * the interface, and each propagating outgoing mode whose amplitude is at
+ * theta dt to the crossing (theta from the straight ray in a constant layer,
+ * refined by four secant iterations on RK4 sub-steps in a gradient layer),
+ * Q is put exactly on the interface, and each propagating outgoing mode
+ * (speeds taken at the crossing point) whose amplitude is at
  * least child_cut times the incident one becomes a child beam (lineage from
  * om_child_lineage, generation + 1, the parent's weight, sigma and action),
  * which then takes the remaining (1 - theta) dt in its own layer.  The parent
@@ -1217,8 +1271,9 @@ int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t
         om_reframe(b);
         continue;
       }
-      const double th = om_crossing_fraction(m, iface, y0.Q, b->Q);
+      double th = om_crossing_fraction(m, iface, y0.Q, b->Q);
       om_beam x = y0;
+      if (m->gradl[y0.layer] != 0.0) th = om_crossing_secant(m, &y0, iface, dt, th);
       om_rk4_step(m, &x, th * dt);
       /* exactly onto the interface */
       double nrm[3] = {0.0, 0.0, 0.0};
@@ -1242,8 +1297,9 @@ int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t
       om_amplitude_vector(&x, Ain);
       const double ain = sqrt(creal(Ain[0] * conj(Ain[0]) + Ain[1] * conj(Ain[1]) + Ain[2] * conj(Ain[2])));
       om_mode md[4];
-      om_interface_modes(m, y0.layer, newL, nrm, sp_in, x.P, Ain, md);
-      const double c_in = sp_in == 0 ? m->cpl[y0.layer] : m->csl[y0.layer];
+      om_interface_modes(m, y0.layer, newL, x.Q, nrm, sp_in, x.P, Ain, md);
+      double c_in, g_in[3], Hd[3][3];
+      om_speed(m, sp_in, y0.layer, x.Q, &c_in, g_in, Hd);
       for (int k = 0; k < 4; ++k) {
         if (!md[k].exists) continue;
         const double am = sqrt(creal(md[k].A[0] * conj(md[k].A[0]) + md[k].A[1] * conj(md[k].A[1]) +
@@ -1252,10 +1308,10 @@ int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t
         if (n >= cap) return -1;
         om_beam c = x;
         const int lay = md[k].side == 1 ? newL : y0.layer;
-        const double c_out = md[k].sp == 0 ? m->cpl[lay] : m->csl[lay];
-        double gz[3] = {0.0, 0.0, 0.0};
+        double c_out, g_out[3];
+        om_speed(m, md[k].sp, lay, x.Q, &c_out, g_out, Hd);
         memcpy(c.P, md[k].P, sizeof c.P);
-        om_interface_jacobians(nrm, x.P, c.P, c_in, c_out, gz, gz, kcurv, c.ZQ, c.ZP);
+        om_interface_jacobians(nrm, x.P, c.P, c_in, c_out, g_in, g_out, kcurv, c.ZQ, c.ZP);
         c.layer = lay;
         c.branch = md[k].sp == 0 ? 0 : 2;
         c.gen = x.gen + 1;

@@ -24,8 +24,8 @@ import oracle as om
 A0 = 2.0 ** 1.5
 
 
-def medium(geometry=0, bounds=(0.5,), cp=(1.7, 2.2), cs=(1.0, 1.25), rho=(1.0, 1.3)):
-    return om.layered(geometry, list(bounds), list(cp), list(cs), list(rho))
+def medium(geometry=0, bounds=(0.5,), cp=(1.7, 2.2), cs=(1.0, 1.25), rho=(1.0, 1.3), grad=None):
+    return om.layered(geometry, list(bounds), list(cp), list(cs), list(rho), grad=grad)
 
 
 def lame(cp, cs, rho):
@@ -232,23 +232,26 @@ def child_of(out, lineage):
     return sel[0]
 
 
+@pytest.mark.parametrize("grad", [False, True])
 @pytest.mark.parametrize("geometry", [0, 1])
 @pytest.mark.parametrize("branch,k", [(0, 2), (0, 0), (0, 3), (2, 3), (2, 1)])
-def test_interface_jacobian_fd(geometry, branch, k):
+def test_interface_jacobian_fd(geometry, branch, k, grad):
     """dzQ and dzP of a child (mapped by eq:Inter_DzQDzP with F and W = F^-T,
     plus the curvature term of a spherical interface) against central
     differences of the child's Q and P over neighbouring initial (q, p), all
     crossing in the same step: d/dq = Re dz, d/dp = -Im dz, within 1e-6 on
     the plane and on the sphere, several steps after the crossing; the
-    symplectic identities hold after the map."""
+    symplectic identities hold after the map.  With grad, both layers have
+    linear speeds (c = c_i (1 + g_i v), v = z or |x|): curved rays, the
+    crossing found by secant iterations and the gradient terms of the map."""
     if geometry == 0:
-        med = medium(0, (0.5,))
+        med = medium(0, (0.5,), grad=[0.3, -0.4] if grad else None)
         q0 = np.array([0.3, 0.4, 0.47])
         p0 = np.array([0.35, -0.2, 1.0])
         nsteps, dt = 6, 0.01
         layer = 0
     else:
-        med = medium(1, (0.6,))
+        med = medium(1, (0.6,), grad=[0.25, 0.35] if grad else None)
         q0 = np.array([0.05, 0.1, 0.66])
         p0 = np.array([0.2, 0.35, -1.0])
         nsteps, dt = 10, 0.01
@@ -282,12 +285,14 @@ def test_interface_jacobian_fd(geometry, branch, k):
     assert np.abs(-c["ZQ"].imag - dQp).max() <= tol
     assert np.abs(c["ZP"].real - dPq).max() <= tol
     assert np.abs(-c["ZP"].imag - dPp).max() <= tol
-    # symplectic structure after the map (P5 / P8)
+    # symplectic structure after the map (P5 / P8); in gradient layers RK4,
+    # which is not a symplectic scheme, leaves its truncation error in it
     ZQ, ZP = c["ZQ"], c["ZP"]
-    assert np.abs(ZQ @ ZP.T - ZP @ ZQ.T).max() <= 1e-12
+    stol = 1e-8 if grad else 1e-12
+    assert np.abs(ZQ @ ZP.T - ZP @ ZQ.T).max() <= stol
     Z = ZQ + 1j * ZP
     S = np.linalg.solve(Z, ZQ)
-    assert np.abs(S - S.T).max() <= 1e-12
+    assert np.abs(S - S.T).max() <= stol
 
 
 def test_sphere_curvature_term_is_needed():
@@ -313,6 +318,41 @@ def test_sphere_curvature_term_is_needed():
     assert np.abs(zp_curv - zp_flat).max() > 1e-2
     _, zp_plane = om.interface_jacobians(n, Pin, Pout, c_in, c_out, ZQ, ZP, kcurv=0.0)
     assert np.array_equal(zp_plane, zp_flat)
+
+
+def test_modes_take_the_local_speeds():
+    """In linear-gradient layers the boundary problem at a crossing point x
+    is that of constant layers with the speeds each layer has at x."""
+    grad = [0.3, -0.4]
+    x = np.array([0.2, 0.7, 0.5])
+    med = medium(0, (0.5,), grad=grad)
+    cp, cs = (1.7, 2.2), (1.0, 1.25)
+    loc = medium(0, (0.5,), cp=[c * (1 + g * x[2]) for c, g in zip(cp, grad)],
+                 cs=[c * (1 + g * x[2]) for c, g in zip(cs, grad)])
+    P = np.array([0.3, -0.2, 1.1])
+    A = (P / np.linalg.norm(P)).astype(np.complex128)
+    a = om.interface_modes(med, 0, 1, np.array([0, 0, 1.0]), 0, P, A, x=x)
+    b = om.interface_modes(loc, 0, 1, np.array([0, 0, 1.0]), 0, P, A)
+    for k in range(4):
+        assert a[k]["exists"] == b[k]["exists"]
+        assert np.allclose(a[k]["P"], b[k]["P"], rtol=0, atol=1e-14)
+        assert np.allclose(a[k]["A"], b[k]["A"], rtol=0, atol=1e-14)
+
+
+def test_gradient_layer_ray_keeps_frequency():
+    """Inside a linear-gradient layer the ray bends and H = c(Q)|P| stays
+    fixed (to the RK4 error), on a plane and on a sphere."""
+    for geometry, bounds, grad, q0, p0 in ((0, (0.9,), [0.5, 0.0], [0.3, 0.4, 0.1], [0.8, 0.1, 1.0]),
+                                           (1, (0.2,), [0.4, 0.0], [0.1, 0.5, 0.3], [1.0, -0.3, 0.2])):
+        med = medium(geometry, bounds, grad=grad)
+        b = one_beam(np.array(q0), np.array(p0), 0)
+        H0 = om.speed(med, 0, b["Q"])[0][0] * np.linalg.norm(b["P"][0])
+        out, _ = om.evolve_layered(med, b, 0.005, 60)
+        c = out[0]
+        assert c["layer"] == 0 and c["alive"] == 1
+        H1 = om.speed(med, 0, c["Q"][None])[0][0] * np.linalg.norm(c["P"])
+        assert abs(H1 - H0) <= 1e-9 * H0
+        assert np.linalg.norm(np.cross(c["P"], b["P"][0])) > 1e-3      # the ray has turned
 
 
 def test_generation_cap_and_lineage():
