@@ -112,8 +112,8 @@ typedef enum {
   FGA_MEDIUM_HOMOGENEOUS = 0,  /* constant c_P, c_S                                   */
   FGA_MEDIUM_GRID = 1,         /* periodic node grid, trilinear interpolation of c and
                                   of its central-difference gradient and Hessian      */
-  FGA_MEDIUM_LAYERED = 2       /* constant speeds per layer: flat layers in z or
-                                  concentric spherical shells                          */
+  FGA_MEDIUM_LAYERED = 2       /* flat layers in z or concentric spherical shells, the
+                                  speeds constant or linear in the level per layer     */
 } fga_medium_kind;
 
 #define FGA_MAX_LAYERS 8
@@ -136,6 +136,12 @@ typedef struct {
   int nlayer;
   double bound[FGA_MAX_LAYERS];
   double cpl[FGA_MAX_LAYERS], csl[FGA_MAX_LAYERS], rhol[FGA_MAX_LAYERS];
+  /* relative gradient per layer: c_b(x) = c_b,l (1 + gradl[l] v(x)), v = z (geometry 0)
+     or |x| (geometry 1); 0 for a constant layer.  In a gradient layer rays bend and
+     the crossing is found by secant iterations on RK4 sub-steps (Sec. 3.1).  The
+     innermost spherical layer must be constant (|x| is not smooth at the centre);
+     the speed must stay positive where beams go (not checked).                      */
+  double gradl[FGA_MAX_LAYERS];
 } fga_medium;
 
 /* Bytes of the derived-field table of a grid medium with n[0]*n[1]*n[2] nodes. */

@@ -111,12 +111,19 @@ fga_status make_dev_medium(const fga_medium *m, DevMedium *o)
     if (m->geometry != 0 && m->geometry != 1) return fail(FGA_EINVAL, "layered geometry must be 0 or 1");
     o->geometry = m->geometry;
     o->nlayer = m->nlayer;
+    o->any_grad = 0;
     for (int l = 0; l < FGA_MAX_LAYERS; ++l) {
       o->bound[l] = m->bound[l];
       o->cpl[l] = m->cpl[l];
       o->csl[l] = m->csl[l];
       o->rhol[l] = m->rhol[l];
+      o->gradl[l] = l < m->nlayer ? m->gradl[l] : 0.0;
+      if (l < m->nlayer && m->gradl[l] != 0.0) o->any_grad = 1;
     }
+    for (int l = 0; l < m->nlayer; ++l)
+      if (!std::isfinite(m->gradl[l])) return fail(FGA_EINVAL, "layer %d has a non-finite gradient", l);
+    if (m->geometry == 1 && m->gradl[m->nlayer - 1] != 0.0)
+      return fail(FGA_EINVAL, "the innermost spherical layer must have a constant speed");
     for (int l = 0; l < m->nlayer; ++l)
       if (!(m->cpl[l] > 0) || !(m->csl[l] > 0) || !(m->rhol[l] > 0))
         return fail(FGA_EINVAL, "layer %d has non-positive speed or density", l);

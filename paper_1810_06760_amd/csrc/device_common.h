@@ -48,10 +48,32 @@ __device__ __forceinline__ void medium_eval(const DevMedium &m, int sp, int laye
 #pragma unroll
     for (int i = 0; i < 6; ++i) H[i] = 0.0;
   } else if constexpr (MK == MK_LAYERED) {
-    c = sp == 0 ? m.cpl[layer] : m.csl[layer];
+    const double c0 = sp == 0 ? m.cpl[layer] : m.csl[layer];
+    const double gm = m.gradl[layer];
     g[0] = g[1] = g[2] = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) H[i] = 0.0;
+    c = c0;
+    if (gm != 0.0) {
+      if (m.geometry == 1) {
+        // c = c0 (1 + gm r): grad c = c0 gm x/r, Hess c = c0 gm (I - x x^T/r^2)/r
+        const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        const double k = c0 * gm / r;
+        c = c0 * (1.0 + gm * r);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[d] = k * x[d];
+        const double ir2 = 1.0 / (r * r);
+        H[0] = k * (1.0 - x[0] * x[0] * ir2);
+        H[1] = k * (1.0 - x[1] * x[1] * ir2);
+        H[2] = k * (1.0 - x[2] * x[2] * ir2);
+        H[3] = -k * x[0] * x[1] * ir2;
+        H[4] = -k * x[0] * x[2] * ir2;
+        H[5] = -k * x[1] * x[2] * ir2;
+      } else {
+        c = c0 * (1.0 + gm * x[2]);
+        g[2] = c0 * gm;
+      }
+    }
   } else {
     const double *tab = m.table;
     double scale = 1.0;

@@ -75,6 +75,8 @@ struct DevMedium {
   int geometry, nlayer;
   double bound[FGA_MAX_LAYERS];
   double cpl[FGA_MAX_LAYERS], csl[FGA_MAX_LAYERS], rhol[FGA_MAX_LAYERS];
+  double gradl[FGA_MAX_LAYERS];  // relative speed gradient per layer (0: constant)
+  int any_grad;                  // some layer has a gradient: the general RK4 step
 };
 
 fga_status make_dev_medium(const fga_medium *m, DevMedium *out);

@@ -358,6 +358,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
+// One step of every beam in a layered medium where some layer has a speed
+// gradient: the general RK4 step (medium_eval gives c, grad c and Hess c of
+// the beam's layer at each stage), and a beam whose centre has left its
+// layer is flagged with its stored state untouched, as in k_step_layered.
+__global__ __launch_bounds__(256) void k_step_layered_grad(DevMedium med, IntegrateArgs a)
+{
+  const int64_t i = a.beg + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long steps_done = 0, culled = 0, quar = 0;
+  if (i < a.end) {
+    const int64_t cap = a.cap;
+    double *__restrict__ F = a.f64;
+    int32_t flags = a.i32[FGA_FLAGS * cap + i];
+    if (flags & FGA_FLAG_ALIVE) {
+      steps_done = 1;
+      const int br = a.i32[FGA_BRANCH * cap + i];
+      const double sg = (double)a.i32[FGA_SIGMA * cap + i];
+      const int layer = a.i32[FGA_LAYER * cap + i];
+      const int sp = br == 0 ? 0 : 1;
+      const bool isS = br != 0;
+      double y[NS], e[3];
+#pragma unroll
+      for (int f = 0; f < NS; ++f) y[f] = F[f * cap + i];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) e[d] = F[(FGA_E + d) * cap + i];
+      rk4_step<MK_LAYERED>(med, sp, layer, sg, isS, e, y, a.dt);
+      int iface, nl;
+      if (layer_exit(med, layer, y + IQ, iface, nl)) {
+        // the interface step redoes this step from the stored state
+        a.i32[FGA_FLAGS * cap + i] = flags | FGA_FLAG_CROSS;
+      } else {
+        if (isS) reframe_s(y, e);
+        bool finite = true;
+#pragma unroll
+        for (int f = 0; f < NS; ++f) finite = finite && isfinite(y[f]);
+        if (!finite) {
+          flags = FGA_FLAG_QUARANTINED;
+          quar = 1;
+        } else if (a.cutoff_abs > 0.0) {
+          const double wr = F[FGA_W_RE * cap + i], wi = F[FGA_W_IM * cap + i];
+          const double m0 = y[IA] * y[IA] + y[IA + 1] * y[IA + 1];
+          const double m1 = y[IA + 2] * y[IA + 2] + y[IA + 3] * y[IA + 3];
+          if (sqrt(wr * wr + wi * wi) * sqrt(m0 > m1 ? m0 : m1) < a.cutoff_abs) {
+            flags = 0;
+            culled = 1;
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < NS; ++f) F[f * cap + i] = y[f];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[(FGA_E + d) * cap + i] = e[d];
+        a.i32[FGA_FLAGS * cap + i] = flags;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    steps_done += __shfl_down(steps_done, off);
+    culled += __shfl_down(culled, off);
+    quar += __shfl_down(quar, off);
+  }
+  if ((threadIdx.x & 63) == 0 && a.counters) {
+    if (steps_done) atomicAdd(a.counters + 0, steps_done);
+    if (culled) atomicAdd(a.counters + 1, culled);
+    if (quar) atomicAdd(a.counters + 2, quar);
+  }
+}
+
 // Emission records of the current state (no stepping), e.g. for t = 0
 // samples.  With box: each wavefront is one 64-beam tile of the records and
 // also writes that tile's bounding box of the live centres Q (lo[3], hi[3];
@@ -425,7 +491,8 @@ hipError_t launch_integrate(const DevMedium &m, const IntegrateArgs &a, hipStrea
   default:
     // layered media advance one step per launch, the interface step between
     if (a.nsteps != 1 || a.stride != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_layered, blocks, 256, 0, st, m, a);
+    if (m.any_grad) hipLaunchKernelGGL(k_step_layered_grad, blocks, 256, 0, st, m, a);
+    else hipLaunchKernelGGL(k_step_layered, blocks, 256, 0, st, m, a);
     break;
   }
   return hipGetLastError();

@@ -18,14 +18,15 @@
 //     the in-plane (P, SV) part is a 4x4 complex system for (R_P, R_S, T_P,
 //     T_S) and the SH part a 2x2 one; P modes are polarised along k/|k|,
 //     in-plane S modes along e2 x k/|k|, SH modes along e2.
-//   - Jacobians: dzQ' = dzQ F, dzP' = dzP F^{-T} - (gradient terms, zero in
-//     homogeneous layers), with F = I + n (x) v in any frame with third axis
-//     n, v = (kappa - 1) p_t / p_n + (kappa p_n' / p_n - 1) n,
-//     kappa = (c_out / c_in)^2.  That is the flat-interface map; on a sphere
-//     of radius R the normal n = s x/R turns with the crossing point, which
-//     adds kcurv mu (dzQ* - n (P'.dzQ*)/p_n') to each row of dzP', with
-//     kcurv = s/R, mu = p_n' - p_n and dzQ* = dzQ - (dzQ.n) P/p_n the
-//     crossing point's derivative (from P' = P + mu n(x*) and c|P| fixed).
+//   - Jacobians (map_jacobians): from the crossing-time constraint, the
+//     Snell update P' = P + mu n(x*) with H = c|P| fixed, and the child
+//     started at the crossing.  Where grad c = 0 on a plane this is
+//     dzQ' = dzQ F, dzP' = dzP F^{-T}, F = I + n (x) v in any frame with third
+//     axis n, v = (kappa - 1) p_t / p_n + (kappa p_n' / p_n - 1) n,
+//     kappa = (c_out / c_in)^2; the turning normal of a sphere (shape
+//     operator kcurv (I - n n^T), kcurv = s/R) and speed gradients add terms.
+// In layers with a speed gradient rays bend: the step is the general RK4
+// step, and theta is refined by four secant iterations on RK4 sub-steps.
 // Children with |A_child| >= child_cut |A_in| are made (generation + 1,
 // lineage FGA_LINEAGE_CHILD) and take the remaining (1 - theta) dt in their
 // own layer.  The first child reuses the parent's slot; the others go after
@@ -113,12 +114,20 @@ struct Modes {
 
 // Outgoing modes (0 P reflected, 1 S reflected, 2 P transmitted,
 // 3 S transmitted) for the plane wave (Pin, Ain) of type sp_in hitting the
-// interface from layer L into layer L2 across unit normal n.
-__device__ void outgoing_modes(const DevMedium &m, int L, int L2, const double n[3], int sp_in, const double Pin[3],
-                               const cx Ain[3], Modes &o)
+// interface from layer L into layer L2 across unit normal n at the point xc
+// (where the speeds of both layers are taken).
+__device__ void outgoing_modes(const DevMedium &m, int L, int L2, const double xc[3], const double n[3], int sp_in,
+                               const double Pin[3], const cx Ain[3], Modes &o)
 {
+  const int lay[2] = {L, L2};
+  double cP[2], cS[2];
+  for (int s = 0; s < 2; ++s) {
+    double g[3], H6[6];
+    medium_eval<MK_LAYERED>(m, 0, lay[s], xc, cP[s], g, H6);
+    medium_eval<MK_LAYERED>(m, 1, lay[s], xc, cS[s], g, H6);
+  }
   const double pabs = sqrt(dot3(Pin, Pin));
-  const double c_in = sp_in == 0 ? m.cpl[L] : m.csl[L];
+  const double c_in = sp_in == 0 ? cP[0] : cS[0];
   const double H = c_in * pabs;
   const double pn = dot3(Pin, n);
   double e1[3], e2[3], t[3];
@@ -140,10 +149,9 @@ __device__ void outgoing_modes(const DevMedium &m, int L, int L2, const double n
   e2[1] = n[2] * e1[0] - n[0] * e1[2];
   e2[2] = n[0] * e1[1] - n[1] * e1[0];
   const double dirn = pn >= 0.0 ? 1.0 : -1.0;
-  const int lay[2] = {L, L2};
   double lam[2], mu[2];
   for (int s = 0; s < 2; ++s) {
-    const double rho = m.rhol[lay[s]], a = m.cpl[lay[s]], b = m.csl[lay[s]];
+    const double rho = m.rhol[lay[s]], a = cP[s], b = cS[s];
     mu[s] = rho * b * b;
     lam[s] = rho * (a * a - 2.0 * b * b);
   }
@@ -157,7 +165,7 @@ __device__ void outgoing_modes(const DevMedium &m, int L, int L2, const double n
     if (w < 4) {
       spw = w & 1;
       s = w >> 1;
-      kabs = H / (spw == 0 ? m.cpl[lay[s]] : m.csl[lay[s]]);
+      kabs = H / (spw == 0 ? cP[s] : cS[s]);
       const double rad = kabs * kabs - p1 * p1;
       if (rad >= 0.0) {
         k3[w] = mk((s == 1 ? dirn : -dirn) * sqrt(rad));
@@ -226,42 +234,43 @@ __device__ void outgoing_modes(const DevMedium &m, int L, int L2, const double n
   }
 }
 
-// dzQ, dzP (planes of y) mapped to an outgoing mode with momentum Pout and
-// speed ratio c_out / c_in across normal n (homogeneous layers: no gradient
-// terms); kcurv: signed curvature s/R of a spherical interface, 0 if flat.
+// dzQ, dzP (planes of y) mapped to an outgoing mode with momentum Pout at
+// the crossing point, for each row (the derivative by one z_m), with
+// V = c P/|P|, s = V_in.n, q_n = row(dzQ).n, mu = p_n' - p_n:
+//   dzQ* = dzQ - V_in q_n / s (the crossing point), dzP* = dzP + |Pin| gin q_n / s,
+//   dmu = [(V_in - V_out).dzP* + (|Pin| gin - |Pout| gout).dzQ* - mu V_out.K dzQ*] / V_out.n,
+//   dzQ' = dzQ* + V_out q_n / s,  dzP' = dzP* + n dmu + mu K dzQ* - |Pout| gout q_n / s,
+// K dzQ* = kcurv dzQ* (dzQ* is tangent); gin, gout: gradients of the incident
+// and outgoing speeds at the crossing point; kcurv: s/R on a sphere, 0 flat.
 __device__ void map_jacobians(double *y, const double n[3], const double Pin[3], const double Pout[3], double c_in,
-                              double c_out, double kcurv)
+                              double c_out, const double gin[3], const double gout[3], double kcurv)
 {
-  const double pn = dot3(Pin, n), pno = dot3(Pout, n);
-  const double kap = (c_out / c_in) * (c_out / c_in);
-  double v[3];
-  for (int d = 0; d < 3; ++d) v[d] = (kap - 1.0) * (Pin[d] - pn * n[d]) / pn + (kap * pno / pn - 1.0) * n[d];
-  const double den = kap * pno / pn;
-  const double kmu = kcurv * (pno - pn);
-  for (int r = 0; r < 3; ++r) {
-    // row r of dzQ gains (row . n) v; row r of dzP loses (row . v) / den n and
-    // gains kmu (qs - n (Pout . qs) / p_n') with qs = row - (row . n) Pin / p_n
-    double qnr = 0.0, qni = 0.0, pvr = 0.0, pvi = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      qnr += y[IZQR + 3 * r + d] * n[d];
-      qni += y[IZQI + 3 * r + d] * n[d];
-      pvr += y[IZPR + 3 * r + d] * v[d];
-      pvi += y[IZPI + 3 * r + d] * v[d];
-    }
-    double qsr[3], qsi[3], psr = 0.0, psi = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      qsr[d] = y[IZQR + 3 * r + d] - qnr * Pin[d] / pn;
-      qsi[d] = y[IZQI + 3 * r + d] - qni * Pin[d] / pn;
-      psr += Pout[d] * qsr[d];
-      psi += Pout[d] * qsi[d];
-    }
-    for (int d = 0; d < 3; ++d) {
-      y[IZQR + 3 * r + d] += qnr * v[d];
-      y[IZQI + 3 * r + d] += qni * v[d];
-      y[IZPR + 3 * r + d] += kmu * (qsr[d] - n[d] * psr / pno) - pvr / den * n[d];
-      y[IZPI + 3 * r + d] += kmu * (qsi[d] - n[d] * psi / pno) - pvi / den * n[d];
-    }
+  const double Pi = sqrt(dot3(Pin, Pin)), Po = sqrt(dot3(Pout, Pout));
+  double vin[3], vout[3];
+  for (int d = 0; d < 3; ++d) {
+    vin[d] = c_in * Pin[d] / Pi;
+    vout[d] = c_out * Pout[d] / Po;
   }
+  const double s_in = dot3(vin, n), s_out = dot3(vout, n), mu = dot3(Pout, n) - dot3(Pin, n);
+  const int base[2][2] = {{IZQR, IZPR}, {IZQI, IZPI}};
+  for (int r = 0; r < 3; ++r)
+    for (int ri = 0; ri < 2; ++ri) {  // real and imaginary parts map alike
+      double *zq = y + base[ri][0] + 3 * r, *zp = y + base[ri][1] + 3 * r;
+      const double qn = (zq[0] * n[0] + zq[1] * n[1] + zq[2] * n[2]) / s_in;
+      double qs[3], ps[3];
+      for (int d = 0; d < 3; ++d) {
+        qs[d] = zq[d] - vin[d] * qn;
+        ps[d] = zp[d] + Pi * gin[d] * qn;
+      }
+      double num = 0.0;
+      for (int d = 0; d < 3; ++d)
+        num += (vin[d] - vout[d]) * ps[d] + (Pi * gin[d] - Po * gout[d]) * qs[d] - mu * kcurv * vout[d] * qs[d];
+      const double dmu = num / s_out;
+      for (int d = 0; d < 3; ++d) {
+        zq[d] = qs[d] + vout[d] * qn;
+        zp[d] = ps[d] + n[d] * dmu + mu * kcurv * qs[d] - Po * gout[d] * qn;
+      }
+    }
 }
 
 __device__ __forceinline__ void initial_axis(const double P[3], double e[3])
@@ -271,6 +280,45 @@ __device__ __forceinline__ void initial_axis(const double P[3], double e[3])
   e[0] = nearz ? 1.0 : 0.0;
   e[1] = 0.0;
   e[2] = nearz ? 0.0 : 1.0;
+}
+
+// One RK4 step of a layered-medium beam: the specialised step where the
+// medium has no gradient, else the general one.
+__device__ __forceinline__ void layered_step(const DevMedium &m, int sp, int L, double sg, const double e[3],
+                                             double *y, double h)
+{
+  if (m.any_grad) rk4_step<MK_LAYERED>(m, sp, L, sg, sp == 1, e, y, h);
+  else rk4_step_pc<MK_LAYERED>(m, sp, L, sg, sp == 1, y, h);
+}
+
+__device__ __forceinline__ double level_of(const DevMedium &m, const double *Q)
+{
+  return m.geometry == 1 ? sqrt(dot3(Q, Q)) : Q[2];
+}
+
+// Crossing fraction of the step from y0 in a layer whose speed varies (a
+// curved ray): four secant iterations on the level of the RK4 sub-step of
+// theta dt from y0, started from theta = 0 and the straight-ray estimate.
+__device__ double crossing_secant(const DevMedium &m, int sp, int L, double sg, const double e[3],
+                                  const double *y0, int iface, double dt, double th0)
+{
+  const double b = m.bound[iface];
+  double ta = 0.0, fa = level_of(m, y0 + IQ) - b, tb = th0;
+  double x[NS];
+  for (int f = 0; f < NS; ++f) x[f] = y0[f];
+  layered_step(m, sp, L, sg, e, x, tb * dt);
+  double fb = level_of(m, x + IQ) - b;
+  for (int it = 0; it < 4; ++it) {
+    if (fb == fa) break;
+    const double tn = fmin(fmax(tb - fb * (tb - ta) / (fb - fa), 0.0), 1.0);
+    ta = tb;
+    fa = fb;
+    tb = tn;
+    for (int f = 0; f < NS; ++f) x[f] = y0[f];
+    layered_step(m, sp, L, sg, e, x, tb * dt);
+    fb = level_of(m, x + IQ) - b;
+  }
+  return tb;
 }
 
 // Per crossing beam: the crossing point state (in y), the modes, and which
@@ -298,7 +346,7 @@ __device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, d
   for (int d = 0; d < 3; ++d) e[d] = a.f64[(FGA_E + d) * cap + i];
   double y1[NS];
   for (int f = 0; f < NS; ++f) y1[f] = y[f];
-  rk4_step_pc<MK_LAYERED>(m, sp, L, sg, sp == 1, y1, a.dt);
+  layered_step(m, sp, L, sg, e, y1, a.dt);
   int iface = 0, newL = L;
   c.nkeep = 0;
   c.capped = false;
@@ -311,7 +359,8 @@ __device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, d
   }
   c.newL = newL;
   c.th = crossing(m, iface, y + IQ, y1 + IQ);
-  rk4_step_pc<MK_LAYERED>(m, sp, L, sg, sp == 1, y, c.th * a.dt);
+  if (m.gradl[L] != 0.0) c.th = crossing_secant(m, sp, L, sg, e, y, iface, a.dt, c.th);
+  layered_step(m, sp, L, sg, e, y, c.th * a.dt);
   const double rb = m.bound[iface];
   if (m.geometry == 1) {
     const double r = sqrt(dot3(y + IQ, y + IQ));
@@ -340,7 +389,7 @@ __device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, d
       Ain[d] = mk(y[IA] * nsv[d] + y[IA + 2] * nsh[d], y[IA + 1] * nsv[d] + y[IA + 3] * nsh[d]);
   }
   const double ain = sqrt(cabs2(Ain[0]) + cabs2(Ain[1]) + cabs2(Ain[2]));
-  outgoing_modes(m, L, newL, c.n, sp, y + IP, Ain, c.md);
+  outgoing_modes(m, L, newL, y + IQ, c.n, sp, y + IP, Ain, c.md);
   for (int k = 0; k < 4; ++k) {
     const double am = sqrt(cabs2(c.md.A[k][0]) + cabs2(c.md.A[k][1]) + cabs2(c.md.A[k][2]));
     c.keep[k] = c.md.exists[k] && am >= a.child_cut * ain;
@@ -413,7 +462,8 @@ __global__ __launch_bounds__(256) void k_interface(DevMedium m, InterfaceArgs a)
   }
   unsigned long long nchild = 0;
   if (c.nkeep == 0) a.i32[FGA_FLAGS * cap + i] = 0;  // retired (generation cap or no child)
-  const double c_in = sp_in == 0 ? m.cpl[L] : m.csl[L];
+  double c_in, g_in[3], H6[6];
+  medium_eval<MK_LAYERED>(m, sp_in, L, y + IQ, c_in, g_in, H6);  // at the crossing point
   int j = 0;
   for (int k = 0; k < 4; ++k) {
     if (!c.keep[k]) continue;
@@ -421,11 +471,12 @@ __global__ __launch_bounds__(256) void k_interface(DevMedium m, InterfaceArgs a)
     ++j;
     const int layc = c.md.side[k] == 1 ? c.newL : L;
     const int spc = c.md.sp[k];
-    const double c_out = spc == 0 ? m.cpl[layc] : m.csl[layc];
+    double c_out, g_out[3];
+    medium_eval<MK_LAYERED>(m, spc, layc, y + IQ, c_out, g_out, H6);
     double z[NS], ec[3];
     for (int f = 0; f < NS; ++f) z[f] = y[f];
     for (int d = 0; d < 3; ++d) z[IP + d] = c.md.P[k][d];
-    map_jacobians(z, c.n, y + IP, z + IP, c_in, c_out, c.kcurv);
+    map_jacobians(z, c.n, y + IP, z + IP, c_in, c_out, g_in, g_out, c.kcurv);
     initial_axis(z + IP, ec);
     if (spc == 0) {
       const double ip = 1.0 / sqrt(dot3(z + IP, z + IP));
@@ -448,7 +499,7 @@ __global__ __launch_bounds__(256) void k_interface(DevMedium m, InterfaceArgs a)
       z[IA + 2] = ash.r;
       z[IA + 3] = ash.i;
     }
-    rk4_step_pc<MK_LAYERED>(m, spc, layc, (double)sigma, spc == 1, z, (1.0 - c.th) * a.dt);
+    layered_step(m, spc, layc, (double)sigma, ec, z, (1.0 - c.th) * a.dt);
     if (spc == 1) reframe_s(z, ec);
     for (int f = 0; f < NS; ++f) a.f64[f * cap + slot] = z[f];
     for (int d = 0; d < 3; ++d) a.f64[(FGA_E + d) * cap + slot] = ec[d];

@@ -519,8 +519,11 @@ def test_empty_beam_set():
 # ---------------------------------------------------------------------------
 
 LAYERED = {
-    "flat": (0, [0.42, 0.58], [1.7, 2.2, 1.9], [1.0, 1.3, 1.1], [1.0, 1.35, 1.2]),
-    "sphere": (1, [0.95, 0.8], [1.7, 2.1, 2.4], [1.0, 1.2, 1.4], [1.0, 1.25, 1.5]),
+    "flat": (0, [0.42, 0.58], [1.7, 2.2, 1.9], [1.0, 1.3, 1.1], [1.0, 1.35, 1.2], None),
+    "sphere": (1, [0.95, 0.8], [1.7, 2.1, 2.4], [1.0, 1.2, 1.4], [1.0, 1.25, 1.5], None),
+    # linear speeds per layer (c = c_l (1 + g_l v), v = z or |x|): curved rays
+    "flat_grad": (0, [0.42, 0.58], [1.7, 2.2, 1.9], [1.0, 1.3, 1.1], [1.0, 1.35, 1.2], [0.5, -0.4, 0.3]),
+    "sphere_grad": (1, [0.95, 0.8], [1.7, 2.1, 2.4], [1.0, 1.2, 1.4], [1.0, 1.25, 1.5], [-0.3, 0.35, 0.0]),
 }
 
 
@@ -535,11 +538,12 @@ def initial_layers(ob, geometry, bounds):
 
 
 def layered_case(name, nq=4, np_=2):
-    geo, bounds, cp, cs, rho = LAYERED[name]
+    geo, bounds, cp, cs, rho, grad = LAYERED[name]
     w = small_c1(nq=nq, np_=np_, ny=16)
     ob = om.decompose(w)
     ob["layer"] = initial_layers(ob, geo, bounds)
-    return w, ob, om.layered(geo, bounds, cp, cs, rho), fga().Medium.layered(geo, bounds, cp, cs, rho)
+    return (w, ob, om.layered(geo, bounds, cp, cs, rho, grad=grad),
+            fga().Medium.layered(geo, bounds, cp, cs, rho, grad=grad))
 
 
 def alive_by_lineage(d):
@@ -547,10 +551,11 @@ def alive_by_lineage(d):
     return {k: v[keep] for k, v in d.items()}
 
 
-@pytest.mark.parametrize("name", ["flat", "sphere"])
+@pytest.mark.parametrize("name", ["flat", "sphere", "flat_grad", "sphere_grad"])
 def test_interface_parity(name):
-    """Beams crossing flat or spherical interfaces split into the same
-    children (lineage, generation, layer, branch) with the same states."""
+    """Beams crossing flat or spherical interfaces, between constant or
+    linear-gradient layers, split into the same children (lineage,
+    generation, layer, branch) with the same states."""
     m = fga()
     say("interface parity", name)
     w, ob, med_o, med_g = layered_case(name)
@@ -576,14 +581,14 @@ def test_interface_parity(name):
     assert rel_l2(phys_amp_gpu(g), A_ref) <= RTOL
 
 
-@pytest.mark.parametrize("batch", [0, 100])
-def test_interface_seismogram_parity(batch):
+@pytest.mark.parametrize("name,batch", [("flat", 0), ("flat", 100), ("sphere_grad", 0)])
+def test_interface_seismogram_parity(name, batch):
     """Receiver sums during a layered run, children included; batch 100 splits
     each step's sum over several ragged beam batches (a layered run sums
     (chunk + stride - 1) / stride + 1 = 7 times the batch at once here)."""
     m = fga()
-    say("interface seismograms, batch %d" % batch)
-    w, ob, med_o, med_g = layered_case("flat")
+    say("interface seismograms, %s, batch %d" % (name, batch))
+    w, ob, med_o, med_g = layered_case(name)
     rec = fi.uniform_points(9, np.random.default_rng(9), 0.2, 0.8)
     nsteps, dt, tau, stride = 30, 0.005, 25.0, 3
     bs = m.BeamSet(4 * len(ob))
@@ -665,7 +670,7 @@ def test_point_source_parity(medium):
         mo, mg = om.medium_for(w), m.medium_for(w)
         x0, rho0 = [0.43, 0.52, 0.61], 1.0
     else:
-        geo, bounds, cp, cs, rho = LAYERED["sphere"]
+        geo, bounds, cp, cs, rho, grad = LAYERED["sphere"]
         mo, mg = om.layered(geo, bounds, cp, cs, rho), m.Medium.layered(geo, bounds, cp, cs, rho)
         x0, rho0 = [0.3, 0.4, 0.75], 0.0
     kw = dict(nq=5, ndir=40, nshell=3, ricker=True, rho0=rho0)
