@@ -51,7 +51,12 @@ HBM_PEAK = 8.0e12
 # workload, scale 1, K = 20 after W = 5), from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # scaled by a 1 GiB copy calibration; valid only while the kernel's source is
 # unchanged (sha256 prefix), else reported as null
-TRAFFIC = {}
+TRAFFIC = {
+    "sum_points": {"source": "paper_1810_06760_amd/csrc/k_points.hip", "sha256": "3dcf9e5942bdf416",
+                   "bytes_per_launch": 1.5052e10},
+    "integrate": {"source": "paper_1810_06760_amd/csrc/k_integrate.hip", "sha256": "df809355f53329b0",
+                  "bytes_per_launch": 9.462e9},
+}
 
 
 def parse():
