@@ -58,6 +58,7 @@ class Medium(C.Structure):
         ("x0", C.c_double * 3), ("amp", C.c_double), ("s", C.c_double), ("g", C.c_double * 3),
         ("nlayer", C.c_int), ("bound", C.c_double * 8),
         ("cpl", C.c_double * 8), ("csl", C.c_double * 8), ("rhol", C.c_double * 8), ("gradl", C.c_double * 8),
+        ("surface", C.c_double),
     ]
 
 
@@ -105,6 +106,7 @@ def lib():
         L.om_evolve_layered.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_double,
                                         vp]
         L.om_interface_modes.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, vp]
+        L.om_free_surface_modes.argtypes = [vp, C.c_int, vp, vp, C.c_int, vp, vp, vp]
         L.om_interface_jacobians.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, vp, vp]
         L.om_child_lineage.restype = C.c_int64
         L.om_child_lineage.argtypes = [C.c_int64, C.c_int, C.c_int]
@@ -204,9 +206,11 @@ def grid(cp_nodes: np.ndarray, mesh, cs_ratio: float = None, cs_nodes: np.ndarra
     return OracleMedium(m, keep=[tab, n, h])
 
 
-def layered(geometry: int, bounds, cp, cs, rho, grad=None) -> OracleMedium:
+def layered(geometry: int, bounds, cp, cs, rho, grad=None, surface=0.0) -> OracleMedium:
     """Flat (geometry 0) or spherical (1) layers; grad: relative gradient per
-    layer, c_b(x) = c_b,i (1 + grad[i] v(x)) with v = z or |x| (None: constant)."""
+    layer, c_b(x) = c_b,i (1 + grad[i] v(x)) with v = z or |x| (None: constant);
+    surface > 0: a traction-free surface at z = surface above the last layer
+    (flat) or |x| = surface around layer 0 (spherical)."""
     m = Medium()
     m.kind, m.geometry = LAYERED, geometry
     m.nlayer = len(cp)
@@ -216,6 +220,7 @@ def layered(geometry: int, bounds, cp, cs, rho, grad=None) -> OracleMedium:
     m.rhol[:len(rho)] = list(rho)
     if grad is not None:
         m.gradl[:len(grad)] = list(grad)
+    m.surface = float(surface)
     m.cp, m.cs, m.rho = cp[0], cs[0], rho[0]
     return OracleMedium(m)
 
@@ -350,6 +355,18 @@ def interface_modes(med: OracleMedium, layer: int, new_layer: int, normal, sp_in
     A = np.ascontiguousarray(A, dtype=np.complex128)
     xx = np.ascontiguousarray(x, dtype=np.float64)
     lib().om_interface_modes(med.ref, layer, new_layer, _p(xx), _p(n), sp_in, _p(P), _p(A), _p(out))
+    return out
+
+
+def free_surface_modes(med: OracleMedium, layer: int, normal, sp_in: int, P, A, x=(0.0, 0.0, 0.0)):
+    """Reflected modes (P, S; the transmitted two do not exist) of a plane
+    wave at a traction-free surface with outward normal `normal` at x."""
+    out = np.zeros(4, dtype=MODE_DTYPE)
+    n = np.ascontiguousarray(normal, dtype=np.float64)
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    lib().om_free_surface_modes(med.ref, layer, _p(xx), _p(n), sp_in, _p(P), _p(A), _p(out))
     return out
 
 

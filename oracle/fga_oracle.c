@@ -68,7 +68,12 @@ typedef struct {
   /* relative gradient of each layer: c_b(x) = c_b,i (1 + gradl[i] v(x)) with the level
      v = z (flat) or |x| (spherical); 0 for a constant layer                               */
   double gradl[OM_MAXL];
+  /* > 0: a traction-free surface closing the outermost region (spherical: |x| = surface
+     around layer 0; flat: z = surface above the last layer); 0: none                      */
+  double surface;
 } om_medium;
+
+#define OM_SURFACE (-1) /* interface index of the free surface */
 
 /* Derived fields of one scalar node field: c, dc/dx, dc/dy, dc/dz,
  * d2c/dx2, d2c/dy2, d2c/dz2, d2c/dxdy, d2c/dxdz, d2c/dydz, from second-order
@@ -947,19 +952,24 @@ int om_layer_exit(const om_medium *m, int L, const double Q[3], int *iface, int 
   if (m->geometry == 1) {
     if (L < nl - 1 && v < m->bound[L]) { *iface = L; *newL = L + 1; return 1; }
     if (L > 0 && v > m->bound[L - 1]) { *iface = L - 1; *newL = L - 1; return 1; }
+    if (L == 0 && m->surface > 0.0 && v > m->surface) { *iface = OM_SURFACE; *newL = 0; return 1; }
   } else {
     if (L < nl - 1 && v > m->bound[L]) { *iface = L; *newL = L + 1; return 1; }
     if (L > 0 && v < m->bound[L - 1]) { *iface = L - 1; *newL = L - 1; return 1; }
+    if (L == nl - 1 && m->surface > 0.0 && v > m->surface) { *iface = OM_SURFACE; *newL = L; return 1; }
   }
   return 0;
 }
+
+/* Level (z or radius) of interface iface, or of the free surface. */
+static double om_iface_level(const om_medium *m, int iface) { return iface == OM_SURFACE ? m->surface : m->bound[iface]; }
 
 /* Fraction theta in [0, 1] of the straight segment Q0 -> Q1 at which it meets
  * interface `iface` (layers are homogeneous, so a ray inside one is a
  * straight line and an RK4 step moves Q along it exactly). */
 double om_crossing_fraction(const om_medium *m, int iface, const double Q0[3], const double Q1[3])
 {
-  const double r = m->bound[iface];
+  const double r = om_iface_level(m, iface);
   double th;
   if (m->geometry == 1) {
     /* |Q0 + th D| = r: a th^2 + 2 b th + c = 0; the root where the segment
@@ -1153,6 +1163,103 @@ void om_interface_modes(const om_medium *m, int L, int newL, const double xc[3],
   }
 }
 
+/* The same plane-wave problem at a traction-free surface (the outer side is
+ * empty): only the reflected modes exist, and the conditions are sigma.n = 0
+ * for the incident plus reflected waves, in the local frame of
+ * om_interface_modes (e3 = n pointing out of the medium, e1 = tangential
+ * momentum direction).  In-plane (P, SV): rows t1, t3, unknowns R_P, R_S;
+ * SH: mu (k3_in a_SH + k3_r R_SH) = 0.  out[2], out[3] (transmitted) do not
+ * exist.  Speeds at the surface point xc. */
+void om_free_surface_modes(const om_medium *m, int L, const double xc[3], const double n[3], int sp_in,
+                           const double Pin[3], const cplx Ain[3], om_mode out[4])
+{
+  double cP, cS;
+  {
+    double gdum[3], Hdum[3][3];
+    om_speed(m, 0, L, xc, &cP, gdum, Hdum);
+    om_speed(m, 1, L, xc, &cS, gdum, Hdum);
+  }
+  const double c_in = sp_in == 0 ? cP : cS;
+  const double H = c_in * sqrt(dot3(Pin, Pin));
+  const double pn = dot3(Pin, n);
+  double pt[3] = {Pin[0] - pn * n[0], Pin[1] - pn * n[1], Pin[2] - pn * n[2]};
+  const double p1 = sqrt(dot3(pt, pt));
+  double e1[3], e2[3];
+  const int oblique = p1 > 1e-12 * sqrt(dot3(Pin, Pin));
+  if (oblique) {
+    for (int i = 0; i < 3; ++i) e1[i] = pt[i] / p1;
+  } else {
+    double t[3] = {1.0, 0.0, 0.0};
+    if (fabs(n[0]) > 0.9) { t[0] = 0.0; t[1] = 1.0; }
+    const double tn = dot3(t, n);
+    for (int i = 0; i < 3; ++i) t[i] -= tn * n[i];
+    const double nt = sqrt(dot3(t, t));
+    for (int i = 0; i < 3; ++i) e1[i] = t[i] / nt;
+  }
+  cross3(n, e1, e2);
+  const double p1l = oblique ? p1 : 0.0;
+  const double sgn = pn >= 0.0 ? 1.0 : -1.0;
+  const double rho = m->rhol[L];
+  const double mu = rho * cS * cS, lam = rho * (cP * cP - 2.0 * cS * cS);
+  /* waves 0 (P reflected), 1 (S reflected), 2 (incident) */
+  cplx k3[3], d1[3], d3[3];
+  double kk[3];
+  int exists[2];
+  for (int w = 0; w < 2; ++w) {
+    const double c = w == 0 ? cP : cS;
+    const double kabs = H / c, rad = kabs * kabs - p1l * p1l;
+    kk[w] = kabs;
+    if (rad >= 0.0) {
+      k3[w] = -sgn * sqrt(rad);
+      exists[w] = 1;
+    } else {
+      k3[w] = -I * sqrt(-rad); /* decays into the medium (x3 < 0) */
+      exists[w] = 0;
+    }
+  }
+  kk[2] = H / c_in;
+  k3[2] = pn;
+  for (int w = 0; w < 3; ++w) {
+    const int sp = w == 2 ? sp_in : w;
+    const cplx h1 = p1l / kk[w], h3 = k3[w] / kk[w];
+    if (sp == 0) { d1[w] = h1; d3[w] = h3; }
+    else { d1[w] = h3; d3[w] = -h1; }
+  }
+  const cplx A1 = Ain[0] * e1[0] + Ain[1] * e1[1] + Ain[2] * e1[2];
+  const cplx A2 = Ain[0] * e2[0] + Ain[1] * e2[1] + Ain[2] * e2[2];
+  const cplx A3 = Ain[0] * n[0] + Ain[1] * n[1] + Ain[2] * n[2];
+  const cplx a_inplane = A1 * d1[2] + A3 * d3[2];
+  const cplx a_sh = sp_in == 0 ? 0.0 : A2;
+  cplx M[4][4], b[4], x[4];
+  for (int w = 0; w < 3; ++w) {
+    const cplx k1 = p1l;
+    const cplx kd = k1 * d1[w] + k3[w] * d3[w];
+    const cplx t1 = mu * (k1 * d3[w] + k3[w] * d1[w]);
+    const cplx t3 = lam * kd + 2.0 * mu * k3[w] * d3[w];
+    if (w == 2) {
+      b[0] = -a_inplane * t1;
+      b[1] = -a_inplane * t3;
+    } else {
+      M[0][w] = t1;
+      M[1][w] = t3;
+    }
+  }
+  csolve_n(2, M, b, x);
+  const cplx ysh = sp_in == 1 ? -k3[2] * a_sh / k3[1] : 0.0;
+  for (int w = 0; w < 4; ++w) {
+    om_mode *o = &out[w];
+    o->sp = w & 1;
+    o->side = w >> 1;
+    o->exists = w < 2 ? exists[w] : 0;
+    for (int i = 0; i < 3; ++i) { o->P[i] = 0.0; o->A[i] = 0.0; }
+    if (w >= 2) continue;
+    const double k3r = creal(k3[w]);
+    for (int i = 0; i < 3; ++i) o->P[i] = p1l * e1[i] + k3r * n[i];
+    const cplx ash = w == 1 ? ysh : 0.0;
+    for (int i = 0; i < 3; ++i) o->A[i] = x[w] * (d1[w] * e1[i] + d3[w] * n[i]) + ash * e2[i];
+  }
+}
+
 /* Lineage number of child k (0..3: P reflected, S reflected, P transmitted,
  * S transmitted) of a beam: generation in the top bits, then the parent's
  * path shifted by two bits. */
@@ -1220,7 +1327,7 @@ void om_interface_jacobians(const double n[3], const double Pin[3], const double
  * theta dt from y0, started from 0 and from the straight-ray estimate. */
 static double om_crossing_secant(const om_medium *m, const om_beam *y0, int iface, double dt, double th0)
 {
-  const double b = m->bound[iface];
+  const double b = om_iface_level(m, iface);
   double ta = 0.0, fa = (m->geometry == 1 ? sqrt(dot3(y0->Q, y0->Q)) : y0->Q[2]) - b;
   double tb = th0;
   om_beam x = *y0;
@@ -1280,12 +1387,13 @@ int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t
       double kcurv = 0.0;
       if (m->geometry == 1) {
         const double r = sqrt(dot3(x.Q, x.Q));
-        for (int k = 0; k < 3; ++k) x.Q[k] *= m->bound[iface] / r;
-        kcurv = (newL > y0.layer ? -1.0 : 1.0) / m->bound[iface];
+        const double R = om_iface_level(m, iface);
+        for (int k = 0; k < 3; ++k) x.Q[k] *= R / r;
+        kcurv = (iface == OM_SURFACE ? 1.0 : (newL > y0.layer ? -1.0 : 1.0)) / R;
         for (int k = 0; k < 3; ++k) nrm[k] = kcurv * x.Q[k];
       } else {
-        x.Q[2] = m->bound[iface];
-        nrm[2] = newL > y0.layer ? 1.0 : -1.0;
+        x.Q[2] = om_iface_level(m, iface);
+        nrm[2] = iface == OM_SURFACE ? 1.0 : (newL > y0.layer ? 1.0 : -1.0);
       }
       b->alive = 0;
       if (x.gen >= gmax) {
@@ -1297,7 +1405,8 @@ int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t
       om_amplitude_vector(&x, Ain);
       const double ain = sqrt(creal(Ain[0] * conj(Ain[0]) + Ain[1] * conj(Ain[1]) + Ain[2] * conj(Ain[2])));
       om_mode md[4];
-      om_interface_modes(m, y0.layer, newL, x.Q, nrm, sp_in, x.P, Ain, md);
+      if (iface == OM_SURFACE) om_free_surface_modes(m, y0.layer, x.Q, nrm, sp_in, x.P, Ain, md);
+      else om_interface_modes(m, y0.layer, newL, x.Q, nrm, sp_in, x.P, Ain, md);
       double c_in, g_in[3], Hd[3][3];
       om_speed(m, sp_in, y0.layer, x.Q, &c_in, g_in, Hd);
       for (int k = 0; k < 4; ++k) {

@@ -208,6 +208,39 @@ def test_post_critical_drops_evanescent_mode():
     assert abs(np.angle(md[0]["A"][2])) > 1e-3   # a phase shift appears
 
 
+@pytest.mark.parametrize("sp,theta", [(0, 0.0), (0, 0.4), (0, 1.2), (1, 0.3), (1, 0.5), (1, 0.9)])
+def test_free_surface_is_traction_free(sp, theta):
+    """At a traction-free surface the incident plus reflected plane waves
+    exert no traction (re-evaluated from the 3-D stress tensor, before the
+    critical angle, where every reflected wave propagates); no wave is
+    transmitted; the reflected energy flux equals the incident one (past the
+    critical angle the evanescent P carries none); normal P incidence
+    reflects P alone with the same displacement (the surface doubles it)."""
+    cp, cs, rho = 1.7, 1.0, 1.3
+    med = om.layered(0, [], [cp], [cs], [rho], surface=0.8)
+    lam, mu = lame(cp, cs, rho)
+    P, A = incident(sp, theta)
+    P = P * (1.0 / (cp if sp == 0 else cs))
+    n = np.array([0, 0, 1.0])
+    md = om.free_surface_modes(med, 0, n, sp, P, A)
+    assert not md[2]["exists"] and not md[3]["exists"]
+    c_in = cp if sp == 0 else cs
+    flux_in = rho * c_in * abs(P[2]) / np.linalg.norm(P) * np.vdot(A, A).real
+    flux = sum(rho * (cp if m["sp"] == 0 else cs) * abs(m["P"][2]) / np.linalg.norm(m["P"]) * np.vdot(m["A"], m["A"]).real
+               for m in md[:2] if m["exists"])
+    assert abs(flux - flux_in) <= 1e-12 * flux_in     # past the critical angle the evanescent P carries none
+    if all(m["exists"] for m in md[:2]):
+        t = traction(P, A, lam, mu, n)
+        for m in md[:2]:
+            t = t + traction(m["P"], m["A"], lam, mu, n)
+        scale = np.linalg.norm(A) * np.linalg.norm(P) * (lam + 2 * mu)
+        assert np.linalg.norm(t) <= 1e-13 * scale
+    if sp == 0 and theta == 0.0:
+        assert np.linalg.norm(md[1]["A"]) <= 1e-14
+        assert abs(abs(md[0]["A"][2]) - abs(A[2])) <= 1e-14 * abs(A[2])
+        assert abs((A[2] + md[0]["A"][2]) - 2 * A[2]) <= 1e-14 * abs(A[2])
+
+
 def one_beam(q, p, branch, sigma=1, layer=0):
     b = np.zeros(1, dtype=om.BEAM_DTYPE)
     b["Q"][0] = q
@@ -293,6 +326,48 @@ def test_interface_jacobian_fd(geometry, branch, k, grad):
     Z = ZQ + 1j * ZP
     S = np.linalg.solve(Z, ZQ)
     assert np.abs(S - S.T).max() <= stol
+
+
+@pytest.mark.parametrize("geometry", [0, 1])
+@pytest.mark.parametrize("branch,k", [(0, 0), (0, 1), (2, 1), (2, 0)])
+def test_free_surface_jacobian_fd(geometry, branch, k):
+    """Children reflected at a free surface (plane z = 0.5 or sphere |x| =
+    0.6 around a gradient layer): dzQ, dzP equal finite differences of
+    neighbouring rays (1e-6), as at an interface."""
+    if geometry == 0:
+        med = om.layered(0, [], [1.7], [1.0], [1.0], grad=[0.3], surface=0.5)
+        q0 = np.array([0.3, 0.4, 0.47])
+        p0 = np.array([0.35, -0.2, 1.0])
+        nsteps, dt = 6, 0.01
+    else:
+        med = om.layered(1, [], [1.7], [1.0], [1.0], surface=0.6)
+        q0 = np.array([0.05, 0.1, 0.55])
+        p0 = np.array([0.2, 0.35, 1.0])
+        nsteps, dt = 10, 0.01
+    p0 = p0 / np.linalg.norm(p0) * 1.3
+    out, _ = om.evolve_layered(med, one_beam(q0, p0, branch), dt, nsteps)
+    lin = om.child_lineage(5, 0, k)
+    c = child_of(out, lin)
+    assert c["gen"] == 1 and c["layer"] == 0
+    h = 1e-5
+    d = {}
+    for m in range(3):
+        for which in ("q", "p"):
+            res = []
+            for sgn in (1, -1):
+                q, p = q0.copy(), p0.copy()
+                (q if which == "q" else p)[m] += sgn * h
+                o, _ = om.evolve_layered(med, one_beam(q, p, branch), dt, nsteps)
+                res.append(child_of(o, lin))
+            d[(which, m)] = ((res[0]["Q"] - res[1]["Q"]) / (2 * h), (res[0]["P"] - res[1]["P"]) / (2 * h))
+    dQq = np.array([d[("q", m)][0] for m in range(3)])
+    dPq = np.array([d[("q", m)][1] for m in range(3)])
+    dQp = np.array([d[("p", m)][0] for m in range(3)])
+    dPp = np.array([d[("p", m)][1] for m in range(3)])
+    assert np.abs(c["ZQ"].real - dQq).max() <= 1e-6
+    assert np.abs(-c["ZQ"].imag - dQp).max() <= 1e-6
+    assert np.abs(c["ZP"].real - dPq).max() <= 1e-6
+    assert np.abs(-c["ZP"].imag - dPp).max() <= 1e-6
 
 
 def test_sphere_curvature_term_is_needed():
