@@ -142,6 +142,12 @@ typedef struct {
      innermost spherical layer must be constant (|x| is not smooth at the centre);
      the speed must stay positive where beams go (not checked).                      */
   double gradl[FGA_MAX_LAYERS];
+  /* > 0: a traction-free surface closing the outermost region, |x| = surface around
+     layer 0 (geometry 1) or z = surface above the last layer (geometry 0): a beam
+     reaching it is split into the reflected P and S beams of the free-surface
+     problem (sigma.n = 0); 0: no surface (the outermost layer extends without end).
+     Beams must start inside the surface.                                            */
+  double surface;
 } fga_medium;
 
 /* Bytes of the derived-field table of a grid medium with n[0]*n[1]*n[2] nodes. */

@@ -66,7 +66,8 @@ class MediumC(C.Structure):
                 ("n", C.c_int * 3), ("lo", C.c_double * 3), ("h", C.c_double * 3), ("table", C.c_void_p),
                 ("two_fields", C.c_int), ("cs_ratio", C.c_double), ("geometry", C.c_int), ("nlayer", C.c_int),
                 ("bound", C.c_double * 8), ("cpl", C.c_double * 8), ("csl", C.c_double * 8),
-                ("rhol", C.c_double * 8), ("gradl", C.c_double * 8)]
+                ("rhol", C.c_double * 8), ("gradl", C.c_double * 8),
+                ("surface", C.c_double)]
 
 
 class MeshC(C.Structure):
@@ -356,9 +357,11 @@ class Medium:
         return Medium(m, keep=[table, cp, cs])
 
     @staticmethod
-    def layered(geometry: int, bounds, cp, cs, rho, grad=None) -> "Medium":
+    def layered(geometry: int, bounds, cp, cs, rho, grad=None, surface=0.0) -> "Medium":
         """Flat (geometry 0) or spherical (1) layers; grad: relative gradient
-        per layer, c_b(x) = c_b,l (1 + grad[l] v(x)), v = z or |x| (None: constant)."""
+        per layer, c_b(x) = c_b,l (1 + grad[l] v(x)), v = z or |x| (None: constant);
+        surface > 0: a traction-free surface at z = surface above the last layer
+        (flat) or |x| = surface around layer 0 (spherical)."""
         m = MediumC()
         m.kind, m.geometry, m.nlayer = FGA_MEDIUM_LAYERED, geometry, len(cp)
         m.bound[:len(bounds)] = list(bounds)
@@ -367,6 +370,7 @@ class Medium:
         m.rhol[:len(rho)] = list(rho)
         if grad is not None:
             m.gradl[:len(grad)] = list(grad)
+        m.surface = float(surface)
         m.cp, m.cs, m.rho = cp[0], cs[0], rho[0]
         return Medium(m)
 

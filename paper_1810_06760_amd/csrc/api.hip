@@ -124,6 +124,11 @@ fga_status make_dev_medium(const fga_medium *m, DevMedium *o)
       if (!std::isfinite(m->gradl[l])) return fail(FGA_EINVAL, "layer %d has a non-finite gradient", l);
     if (m->geometry == 1 && m->gradl[m->nlayer - 1] != 0.0)
       return fail(FGA_EINVAL, "the innermost spherical layer must have a constant speed");
+    o->surface = m->surface;
+    if (!(m->surface >= 0.0)) return fail(FGA_EINVAL, "surface must be >= 0 (0: none)");
+    if (m->surface > 0.0 && m->nlayer > 1 &&
+        (m->geometry == 1 ? !(m->surface > m->bound[0]) : !(m->surface > m->bound[m->nlayer - 2])))
+      return fail(FGA_EINVAL, "the free surface must lie outside every interface");
     for (int l = 0; l < m->nlayer; ++l)
       if (!(m->cpl[l] > 0) || !(m->csl[l] > 0) || !(m->rhol[l] > 0))
         return fail(FGA_EINVAL, "layer %d has non-positive speed or density", l);

@@ -12,7 +12,9 @@ enum { MK_HOMOG = 0, MK_GRID = 1, MK_LAYERED = 2 };
 // Layered media: if Q lies outside layer L, the interface crossed and the
 // layer beyond it (points on an interface count as inside).  Flat: interface
 // i is z = bound[i] between layer i (below) and i+1; spherical: |x| = bound[i]
-// between layer i (outside) and i+1 (inside).
+// between layer i (outside) and i+1 (inside).  The free surface, if any, is
+// interface IFACE_SURFACE with the beam's own layer beyond it.
+constexpr int IFACE_SURFACE = -1;
 __device__ __forceinline__ bool layer_exit(const DevMedium &m, int L, const double Q[3], int &iface, int &newL)
 {
   const int nl = m.nlayer;
@@ -20,11 +22,19 @@ __device__ __forceinline__ bool layer_exit(const DevMedium &m, int L, const doub
     const double r = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
     if (L < nl - 1 && r < m.bound[L]) { iface = L; newL = L + 1; return true; }
     if (L > 0 && r > m.bound[L - 1]) { iface = L - 1; newL = L - 1; return true; }
+    if (L == 0 && m.surface > 0.0 && r > m.surface) { iface = IFACE_SURFACE; newL = 0; return true; }
   } else {
     if (L < nl - 1 && Q[2] > m.bound[L]) { iface = L; newL = L + 1; return true; }
     if (L > 0 && Q[2] < m.bound[L - 1]) { iface = L - 1; newL = L - 1; return true; }
+    if (L == nl - 1 && m.surface > 0.0 && Q[2] > m.surface) { iface = IFACE_SURFACE; newL = L; return true; }
   }
   return false;
+}
+
+// Level (z or radius) of interface iface, or of the free surface.
+__device__ __forceinline__ double iface_level(const DevMedium &m, int iface)
+{
+  return iface == IFACE_SURFACE ? m.surface : m.bound[iface];
 }
 
 // Speed of wave type sp (0 = P, 1 = S) at x: c, gradient g and Hessian H

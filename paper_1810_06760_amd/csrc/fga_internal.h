@@ -77,6 +77,7 @@ struct DevMedium {
   double cpl[FGA_MAX_LAYERS], csl[FGA_MAX_LAYERS], rhol[FGA_MAX_LAYERS];
   double gradl[FGA_MAX_LAYERS];  // relative speed gradient per layer (0: constant)
   int any_grad;                  // some layer has a gradient: the general RK4 step
+  double surface;                // > 0: traction-free surface closing the outermost region
 };
 
 fga_status make_dev_medium(const fga_medium *m, DevMedium *out);

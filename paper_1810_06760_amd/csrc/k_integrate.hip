@@ -294,9 +294,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       bool crossed;
       if (med.geometry == 1) {
         const double r = sqrt(Qn[0] * Qn[0] + Qn[1] * Qn[1] + Qn[2] * Qn[2]);
-        crossed = (in_ok && r < b_in) || (out_ok && r > b_out);
+        crossed = (in_ok && r < b_in) || (out_ok && r > b_out) || (layer == 0 && med.surface > 0.0 && r > med.surface);
       } else {
-        crossed = (in_ok && Qn[2] > b_in) || (out_ok && Qn[2] < b_out);
+        crossed = (in_ok && Qn[2] > b_in) || (out_ok && Qn[2] < b_out) ||
+                  (layer == med.nlayer - 1 && med.surface > 0.0 && Qn[2] > med.surface);
       }
       if (crossed) {
         // the interface step redoes this step from the stored state

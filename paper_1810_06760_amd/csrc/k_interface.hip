@@ -92,7 +92,7 @@ __device__ void solve_small(int n, cx A[4][4], cx b[4], cx x[4])
 // Crossing fraction of the straight segment Q0 -> Q1 with interface `iface`.
 __device__ double crossing(const DevMedium &m, int iface, const double *Q0, const double *Q1)
 {
-  const double r = m.bound[iface];
+  const double r = iface_level(m, iface);
   double th;
   if (m.geometry == 1) {
     const double D[3] = {Q1[0] - Q0[0], Q1[1] - Q0[1], Q1[2] - Q0[2]};
@@ -115,9 +115,11 @@ struct Modes {
 // Outgoing modes (0 P reflected, 1 S reflected, 2 P transmitted,
 // 3 S transmitted) for the plane wave (Pin, Ain) of type sp_in hitting the
 // interface from layer L into layer L2 across unit normal n at the point xc
-// (where the speeds of both layers are taken).
+// (where the speeds of both layers are taken).  free: a traction-free surface
+// (nothing beyond it): only the reflected modes, from sigma.n = 0 (rows t1,
+// t3 in plane; mu (k3_in A_SH + k3_r R_SH) = 0 for SH).
 __device__ void outgoing_modes(const DevMedium &m, int L, int L2, const double xc[3], const double n[3], int sp_in,
-                               const double Pin[3], const cx Ain[3], Modes &o)
+                               const double Pin[3], const cx Ain[3], Modes &o, bool free = false)
 {
   const int lay[2] = {L, L2};
   double cP[2], cS[2];
@@ -212,10 +214,24 @@ __device__ void outgoing_modes(const DevMedium &m, int L, int L2, const double x
       else M[r][w] = s == 0 ? col[r] : -col[r];
     }
   }
-  solve_small(4, M, rhs, x);
+  if (free) {
+    // rows t1, t3 and the reflected columns only
+    cx F[4][4], bf[4];
+    for (int r = 0; r < 2; ++r) {
+      bf[r] = rhs[2 + r];
+      for (int w = 0; w < 2; ++w) F[r][w] = M[2 + r][w];
+    }
+    solve_small(2, F, bf, x);
+    x[2] = x[3] = mk(0.0);
+    o.exists[2] = o.exists[3] = false;
+  } else {
+    solve_small(4, M, rhs, x);
+  }
   // SH: rows u2, t2 (polarisation e2 for every SH wave)
   cx y[2] = {mk(0.0), mk(0.0)};
-  if (sp_in == 1) {
+  if (sp_in == 1 && free) {
+    y[0] = -((k3[4] * A2) / k3[1]);
+  } else if (sp_in == 1) {
     cx S[4][4], bs[4], xs[4];
     S[0][0] = mk(1.0);
     S[0][1] = mk(-1.0);
@@ -302,7 +318,7 @@ __device__ __forceinline__ double level_of(const DevMedium &m, const double *Q)
 __device__ double crossing_secant(const DevMedium &m, int sp, int L, double sg, const double e[3],
                                   const double *y0, int iface, double dt, double th0)
 {
-  const double b = m.bound[iface];
+  const double b = iface_level(m, iface);
   double ta = 0.0, fa = level_of(m, y0 + IQ) - b, tb = th0;
   double x[NS];
   for (int f = 0; f < NS; ++f) x[f] = y0[f];
@@ -361,17 +377,18 @@ __device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, d
   c.th = crossing(m, iface, y + IQ, y1 + IQ);
   if (m.gradl[L] != 0.0) c.th = crossing_secant(m, sp, L, sg, e, y, iface, a.dt, c.th);
   layered_step(m, sp, L, sg, e, y, c.th * a.dt);
-  const double rb = m.bound[iface];
+  const double rb = iface_level(m, iface);
+  const bool surf = iface == IFACE_SURFACE;
   if (m.geometry == 1) {
     const double r = sqrt(dot3(y + IQ, y + IQ));
     for (int d = 0; d < 3; ++d) y[IQ + d] *= rb / r;
-    c.kcurv = (newL > L ? -1.0 : 1.0) / rb;
+    c.kcurv = (surf ? 1.0 : (newL > L ? -1.0 : 1.0)) / rb;
     for (int d = 0; d < 3; ++d) c.n[d] = c.kcurv * y[IQ + d];
   } else {
     y[IQ + 2] = rb;
     c.kcurv = 0.0;
     c.n[0] = c.n[1] = 0.0;
-    c.n[2] = newL > L ? 1.0 : -1.0;
+    c.n[2] = surf ? 1.0 : (newL > L ? 1.0 : -1.0);
   }
   if (gen >= a.gen_max) {
     c.capped = true;
@@ -389,7 +406,7 @@ __device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, d
       Ain[d] = mk(y[IA] * nsv[d] + y[IA + 2] * nsh[d], y[IA + 1] * nsv[d] + y[IA + 3] * nsh[d]);
   }
   const double ain = sqrt(cabs2(Ain[0]) + cabs2(Ain[1]) + cabs2(Ain[2]));
-  outgoing_modes(m, L, newL, y + IQ, c.n, sp, y + IP, Ain, c.md);
+  outgoing_modes(m, L, newL, y + IQ, c.n, sp, y + IP, Ain, c.md, surf);
   for (int k = 0; k < 4; ++k) {
     const double am = sqrt(cabs2(c.md.A[k][0]) + cabs2(c.md.A[k][1]) + cabs2(c.md.A[k][2]));
     c.keep[k] = c.md.exists[k] && am >= a.child_cut * ain;

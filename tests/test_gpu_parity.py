@@ -524,7 +524,11 @@ LAYERED = {
     # linear speeds per layer (c = c_l (1 + g_l v), v = z or |x|): curved rays
     "flat_grad": (0, [0.42, 0.58], [1.7, 2.2, 1.9], [1.0, 1.3, 1.1], [1.0, 1.35, 1.2], [0.5, -0.4, 0.3]),
     "sphere_grad": (1, [0.95, 0.8], [1.7, 2.1, 2.4], [1.0, 1.2, 1.4], [1.0, 1.25, 1.5], [-0.3, 0.35, 0.0]),
+    # a traction-free surface closing the outermost region
+    "flat_free": (0, [0.42, 0.58], [1.7, 2.2, 1.9], [1.0, 1.3, 1.1], [1.0, 1.35, 1.2], None),
+    "sphere_free": (1, [0.95, 0.8], [1.7, 2.1, 2.4], [1.0, 1.2, 1.4], [1.0, 1.25, 1.5], [-0.3, 0.35, 0.0]),
 }
+SURFACE = {"flat_free": 0.72, "sphere_free": 1.12}
 
 
 def initial_layers(ob, geometry, bounds):
@@ -542,8 +546,13 @@ def layered_case(name, nq=4, np_=2):
     w = small_c1(nq=nq, np_=np_, ny=16)
     ob = om.decompose(w)
     ob["layer"] = initial_layers(ob, geo, bounds)
-    return (w, ob, om.layered(geo, bounds, cp, cs, rho, grad=grad),
-            fga().Medium.layered(geo, bounds, cp, cs, rho, grad=grad))
+    sf = SURFACE.get(name, 0.0)
+    if sf > 0.0:
+        # the beams start inside the free surface (the medium ends there)
+        lev = ob["Q"][:, 2] if geo == 0 else np.linalg.norm(ob["Q"], axis=1)
+        ob = om.take_beams(ob, np.nonzero(lev < sf)[0])
+    return (w, ob, om.layered(geo, bounds, cp, cs, rho, grad=grad, surface=sf),
+            fga().Medium.layered(geo, bounds, cp, cs, rho, grad=grad, surface=sf))
 
 
 def alive_by_lineage(d):
@@ -551,11 +560,12 @@ def alive_by_lineage(d):
     return {k: v[keep] for k, v in d.items()}
 
 
-@pytest.mark.parametrize("name", ["flat", "sphere", "flat_grad", "sphere_grad"])
+@pytest.mark.parametrize("name", ["flat", "sphere", "flat_grad", "sphere_grad", "flat_free", "sphere_free"])
 def test_interface_parity(name):
     """Beams crossing flat or spherical interfaces, between constant or
-    linear-gradient layers, split into the same children (lineage,
-    generation, layer, branch) with the same states."""
+    linear-gradient layers, or reflected at a traction-free surface, split
+    into the same children (lineage, generation, layer, branch) with the
+    same states."""
     m = fga()
     say("interface parity", name)
     w, ob, med_o, med_g = layered_case(name)
@@ -581,7 +591,7 @@ def test_interface_parity(name):
     assert rel_l2(phys_amp_gpu(g), A_ref) <= RTOL
 
 
-@pytest.mark.parametrize("name,batch", [("flat", 0), ("flat", 100), ("sphere_grad", 0)])
+@pytest.mark.parametrize("name,batch", [("flat", 0), ("flat", 100), ("sphere_grad", 0), ("sphere_free", 0)])
 def test_interface_seismogram_parity(name, batch):
     """Receiver sums during a layered run, children included; batch 100 splits
     each step's sum over several ragged beam batches (a layered run sums
@@ -591,7 +601,7 @@ def test_interface_seismogram_parity(name, batch):
     w, ob, med_o, med_g = layered_case(name)
     rec = fi.uniform_points(9, np.random.default_rng(9), 0.2, 0.8)
     nsteps, dt, tau, stride = 30, 0.005, 25.0, 3
-    bs = m.BeamSet(4 * len(ob))
+    bs = m.BeamSet(8 * len(ob))
     bs.load(oracle_to_dict(ob))
     seis, st = m.fga_evolve(med_g, bs, dt, nsteps, receivers=rec, eps=w.eps, tau=tau, stride=stride, batch=batch)
     say("beams %d -> %d" % (len(ob), bs.count))
