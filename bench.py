@@ -52,10 +52,10 @@ HBM_PEAK = 8.0e12
 # scaled by a 1 GiB copy calibration; valid only while the kernel's source is
 # unchanged (sha256 prefix), else reported as null
 TRAFFIC = {
-    "sum_points": {"source": "paper_1810_06760_amd/csrc/k_points.hip", "sha256": "3dcf9e5942bdf416",
-                   "bytes_per_launch": 1.5052e10},
-    "integrate": {"source": "paper_1810_06760_amd/csrc/k_integrate.hip", "sha256": "df809355f53329b0",
-                  "bytes_per_launch": 9.462e9},
+    "sum_points": {"source": "paper_1810_06760_amd/csrc/k_points.hip", "sha256": "262f9ec0539f99f6",
+                   "bytes_per_launch": 2.3897e10},
+    "integrate": {"source": "paper_1810_06760_amd/csrc/k_integrate.hip", "sha256": "a6b636620063c52f",
+                  "bytes_per_launch": 9.4622e9},
 }
 
 
@@ -78,7 +78,7 @@ def parse():
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--segments", type=int, default=4, help="evolution calls per step (progress between them)")
-    ap.add_argument("--cpu-beams", type=int, default=512, help="(q,p) pairs in the oracle sample")
+    ap.add_argument("--cpu-beams", type=int, default=8192, help="(q,p) pairs in the oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=1000, help="RK4 steps of the oracle sample")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead: a seeded sweep of forward-solve requests over 4 resident models, "
@@ -246,8 +246,8 @@ def roofline(tot, prof, medium_kind, default_workload=False):
 
 
 def cpu_baseline(w, args):
-    """The oracle on a bounded sample of the same workload: a few hundred
-    beams of random (q, p) pairs decomposed by FBI quadrature, then RK4 steps
+    """The oracle on a bounded sample of the same workload (about 10-20 s of
+    host work): 8192 random (q, p) pairs decomposed by FBI quadrature, then RK4 steps
     in the same medium, each followed by the sum at the 256 receivers.  The
     per-beam-step time (integrator + one receiver sample) gives beam-steps/s
     at the threads the oracle uses."""
