@@ -148,6 +148,7 @@ class Workload:
     medium_nodes: np.ndarray | None = None   # c_p node values [z][y][x] (grid media)
     medium_grid: Mesh3 | None = None
     cs_ratio: float = 1.0 / SQRT3
+    medium_smooth: bool = False    # grid media: cubic B-spline of the nodes instead of trilinear
     branches: tuple = (0, 1, 2)    # P, SH, SV
     tau: float = 25.0
     cull_abs: float = 0.0          # |psi| threshold below which a beam is not created

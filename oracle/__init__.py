@@ -55,6 +55,7 @@ class Medium(C.Structure):
         ("cp", C.c_double), ("cs", C.c_double), ("rho", C.c_double),
         ("n", C.c_int * 3), ("lo", C.c_double * 3), ("h", C.c_double * 3),
         ("tab", C.POINTER(C.c_double)), ("cs_ratio", C.c_double), ("two_fields", C.c_int),
+        ("smooth", C.c_int), ("coef", C.POINTER(C.c_double)),
         ("x0", C.c_double * 3), ("amp", C.c_double), ("s", C.c_double), ("g", C.c_double * 3),
         ("nlayer", C.c_int), ("bound", C.c_double * 8),
         ("cpl", C.c_double * 8), ("csl", C.c_double * 8), ("rhol", C.c_double * 8), ("gradl", C.c_double * 8),
@@ -97,6 +98,7 @@ def lib():
         L.om_make_beams.argtypes = [vp, vp, vp, vp, C.c_int, C.c_double, C.c_double, C.c_double,
                                     C.c_int, C.c_double, C.c_int64, C.c_int64, vp]
         L.om_grid_fields.argtypes = [vp, vp, vp, vp]
+        L.om_grid_spline_coefficients.argtypes = [vp, vp, vp]
         L.om_speed_many.argtypes = [vp, C.c_int, vp, C.c_int64, vp]
         L.om_rhs_beam.argtypes = [vp, vp, vp]
         L.om_amplitude_vectors.argtypes = [vp, C.c_int64, vp]
@@ -184,8 +186,13 @@ def linear(cp: float, cs: float, g) -> OracleMedium:
     return OracleMedium(m)
 
 
-def grid(cp_nodes: np.ndarray, mesh, cs_ratio: float = None, cs_nodes: np.ndarray = None) -> OracleMedium:
-    """Periodic node-grid medium; nodes mesh.lo + i*mesh.h, arrays [z][y][x]."""
+def grid(cp_nodes: np.ndarray, mesh, cs_ratio: float = None, cs_nodes: np.ndarray = None,
+         smooth: bool = False) -> OracleMedium:
+    """Periodic node-grid medium; nodes mesh.lo + i*mesh.h, arrays [z][y][x].
+    smooth=False: trilinear interpolation of node values of c, grad c and
+    its Hessian (grad c and H by finite differences on the nodes);
+    smooth=True: c is the periodic cubic B-spline through the node values
+    (C^2, grad c and H its exact derivatives)."""
     lib_ = lib()
     n = np.array(mesh.n, dtype=np.int32)
     h = np.array(mesh.h, dtype=np.float64)
@@ -203,7 +210,15 @@ def grid(cp_nodes: np.ndarray, mesh, cs_ratio: float = None, cs_nodes: np.ndarra
     m.tab = tab.ctypes.data_as(C.POINTER(C.c_double))
     m.two_fields = 1 if cs_nodes is not None else 0
     m.cs_ratio = 0.0 if cs_ratio is None else cs_ratio
-    return OracleMedium(m, keep=[tab, n, h])
+    keep = [tab, n, h]
+    if smooth:
+        coef = np.empty((len(fields),) + tuple(int(v) for v in mesh.n[::-1]), dtype=np.float64)
+        for i, f in enumerate(fields):
+            lib_.om_grid_spline_coefficients(_p(f), _p(n), _p(coef[i]))
+        m.smooth = 1
+        m.coef = coef.ctypes.data_as(C.POINTER(C.c_double))
+        keep.append(coef)
+    return OracleMedium(m, keep=keep)
 
 
 def layered(geometry: int, bounds, cp, cs, rho, grad=None, surface=0.0) -> OracleMedium:
@@ -499,4 +514,4 @@ def sum_points(beams: np.ndarray, x: np.ndarray, eps: float, tau: float):
 def medium_for(work) -> OracleMedium:
     if work.medium_nodes is None:
         return homogeneous(work.cp0, work.cs0)
-    return grid(work.medium_nodes, work.medium_grid, cs_ratio=work.cs_ratio)
+    return grid(work.medium_nodes, work.medium_grid, cs_ratio=work.cs_ratio, smooth=work.medium_smooth)

@@ -58,6 +58,8 @@ typedef struct {
   const double *tab;     /* derived fields, [speed 0/1][node][10], built by om_grid_fields */
   double cs_ratio;       /* c_S = cs_ratio * c_P when only one node field is given          */
   int two_fields;        /* 1: tab holds independent c_P and c_S fields                     */
+  int smooth;            /* 1: c is the periodic cubic B-spline through the node values    */
+  const double *coef;    /* its coefficients, [speed 0/1][node], from om_grid_spline_coefficients */
   /* analytic media                                                                         */
   double x0[3], amp, s, g[3];
   /* layered media: layer i occupies level in (bound[i], bound[i-1]) for geometry 1        */
@@ -104,6 +106,81 @@ void om_grid_fields(const double *c, const int n[3], const double h[3], double *
                (4.0 * h[1] * h[2]);
       }
 #undef C
+}
+
+/* Coefficients of the periodic cubic B-spline that takes the node values c
+ * at the nodes (the C^2 reading of a gridded medium): along each axis in
+ * turn, the periodic system (a_{i-1} + 4 a_i + a_{i+1}) / 6 = f_i, solved by
+ * elimination of the cyclic tridiagonal system (the Sherman-Morrison form of
+ * the Thomas algorithm).  Arrays [z][y][x]. */
+static void om_cyclic_solve(int n, const double *f, double *a, double *wk)
+{
+  /* A = tridiag(1, 4, 1)/6 with corners 1/6; A = T + u v^T, T tridiagonal */
+  if (n == 1) { a[0] = f[0]; return; }
+  const double lo = 1.0 / 6.0, di = 4.0 / 6.0, gam = -di;
+  double *cp = wk, *y = wk + n, *z = wk + 2 * n, *rhs = wk + 3 * n;
+  /* T has diagonal di - gam at 0, di - lo*lo/gam at n-1, di elsewhere */
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i < n; ++i) rhs[i] = pass == 0 ? f[i] : (i == 0 ? gam : (i == n - 1 ? lo : 0.0));
+    double *out = pass == 0 ? y : z;
+    double b0 = di - gam;
+    cp[0] = lo / b0;
+    out[0] = rhs[0] / b0;
+    for (int i = 1; i < n; ++i) {
+      const double bi = (i == n - 1 ? di - lo * lo / gam : di) - lo * cp[i - 1];
+      cp[i] = lo / bi;
+      out[i] = (rhs[i] - lo * out[i - 1]) / bi;
+    }
+    for (int i = n - 2; i >= 0; --i) out[i] -= cp[i] * out[i + 1];
+  }
+  /* v = (1, 0, ..., 0, lo/gam) */
+  const double vy = y[0] + lo / gam * y[n - 1], vz = z[0] + lo / gam * z[n - 1];
+  const double fac = vy / (1.0 + vz);
+  for (int i = 0; i < n; ++i) a[i] = y[i] - fac * z[i];
+}
+
+void om_grid_spline_coefficients(const double *c, const int n[3], double *out)
+{
+  const int nx = n[0], ny = n[1], nz = n[2];
+  const size_t N = (size_t)nx * ny * nz;
+  memcpy(out, c, N * sizeof(double));
+  const int nm = nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz);
+  double *f = (double *)malloc(sizeof(double) * nm), *a = (double *)malloc(sizeof(double) * nm);
+  double *wk = (double *)malloc(sizeof(double) * 4 * nm);
+  for (int axis = 0; axis < 3; ++axis) {
+    const int len = n[axis];
+    const size_t stride = axis == 0 ? 1 : (axis == 1 ? (size_t)nx : (size_t)nx * ny);
+    for (size_t base = 0; base < N; ++base) {
+      /* one line per base index whose coordinate along the axis is 0 */
+      const size_t coord = (base / stride) % len;
+      if (coord != 0) continue;
+      for (int i = 0; i < len; ++i) f[i] = out[base + i * stride];
+      om_cyclic_solve(len, f, a, wk);
+      for (int i = 0; i < len; ++i) out[base + i * stride] = a[i];
+    }
+  }
+  free(f);
+  free(a);
+  free(wk);
+}
+
+/* Cubic B-spline weights of the four nodes i-1 .. i+2 at fraction t, and
+ * their first and second derivatives in t. */
+static void om_bspline(double t, double w[4], double d1[4], double d2[4])
+{
+  const double s = 1.0 - t;
+  w[0] = s * s * s / 6.0;
+  w[1] = (3.0 * t * t * t - 6.0 * t * t + 4.0) / 6.0;
+  w[2] = (-3.0 * t * t * t + 3.0 * t * t + 3.0 * t + 1.0) / 6.0;
+  w[3] = t * t * t / 6.0;
+  d1[0] = -s * s / 2.0;
+  d1[1] = (9.0 * t * t - 12.0 * t) / 6.0;
+  d1[2] = (-9.0 * t * t + 6.0 * t + 3.0) / 6.0;
+  d1[3] = t * t / 2.0;
+  d2[0] = s;
+  d2[1] = 3.0 * t - 2.0;
+  d2[2] = -3.0 * t + 1.0;
+  d2[3] = t;
 }
 
 /* Layer index of point x in a layered medium. */
@@ -172,8 +249,56 @@ void om_speed(const om_medium *m, int sp, int layer, const double x[3],
     return;
   }
   case OM_GRID: {
-    /* trilinear interpolation of the ten derived node fields */
     const int nx = m->n[0], ny = m->n[1], nz = m->n[2];
+    if (m->smooth) {
+      /* the periodic cubic B-spline through the node values and its derivatives */
+      int i0[3];
+      double w[3][4], d1[3][4], d2[3][4];
+      for (int d = 0; d < 3; ++d) {
+        double u = (x[d] - m->lo[d]) / m->h[d];
+        double fl = floor(u);
+        long long ii = (long long)fl % m->n[d];
+        if (ii < 0) ii += m->n[d];
+        i0[d] = (int)ii;
+        om_bspline(u - fl, w[d], d1[d], d2[d]);
+        for (int a = 0; a < 4; ++a) {
+          d1[d][a] /= m->h[d];
+          d2[d][a] /= m->h[d] * m->h[d];
+        }
+      }
+      const double *cf = m->coef;
+      double scale = 1.0;
+      if (sp == 1) {
+        if (m->two_fields) cf += (size_t)nx * ny * nz;
+        else scale = m->cs_ratio;
+      }
+      double v = 0.0, g[3] = {0, 0, 0}, hh[3][3] = {{0}};
+      for (int c3 = 0; c3 < 4; ++c3)
+        for (int b = 0; b < 4; ++b)
+          for (int a = 0; a < 4; ++a) {
+            const int ix = (i0[0] - 1 + a + nx) % nx, iy = (i0[1] - 1 + b + ny) % ny, iz = (i0[2] - 1 + c3 + nz) % nz;
+            const double co = cf[((size_t)iz * ny + iy) * nx + ix];
+            const double wx = w[0][a], wy = w[1][b], wz = w[2][c3];
+            v += co * wx * wy * wz;
+            g[0] += co * d1[0][a] * wy * wz;
+            g[1] += co * wx * d1[1][b] * wz;
+            g[2] += co * wx * wy * d1[2][c3];
+            hh[0][0] += co * d2[0][a] * wy * wz;
+            hh[1][1] += co * wx * d2[1][b] * wz;
+            hh[2][2] += co * wx * wy * d2[2][c3];
+            hh[0][1] += co * d1[0][a] * d1[1][b] * wz;
+            hh[0][2] += co * d1[0][a] * wy * d1[2][c3];
+            hh[1][2] += co * wx * d1[1][b] * d1[2][c3];
+          }
+      *c = scale * v;
+      for (int i = 0; i < 3; ++i) gc[i] = scale * g[i];
+      H[0][0] = scale * hh[0][0]; H[1][1] = scale * hh[1][1]; H[2][2] = scale * hh[2][2];
+      H[0][1] = H[1][0] = scale * hh[0][1];
+      H[0][2] = H[2][0] = scale * hh[0][2];
+      H[1][2] = H[2][1] = scale * hh[1][2];
+      return;
+    }
+    /* trilinear interpolation of the ten derived node fields */
     int i0[3];
     double t[3];
     for (int d = 0; d < 3; ++d) {
