@@ -289,6 +289,47 @@ def make_beams(qmesh, pmesh, Ft: np.ndarray, eps: float, iq: np.ndarray, ip: np.
     return take_beams(out, np.argsort(out["lineage"], kind="stable"))
 
 
+def merge_s_beams(beams: np.ndarray, nqp: int) -> np.ndarray:
+    """One S beam per (q, p, direction) in place of the SH and SV pair.
+
+    The SH and SV beams of one (q, p, direction) start from the same data and
+    both move with c_S, so their rays (Q, P, dzQ, dzP, S, frame axis e) are the
+    same at every time (eq:char_plus, eq:char_minus, eq:DzDt), and the S
+    amplitude equations (eq:amp_SV, eq:amp_SH) are linear in (a_SV, a_SH).
+    The pair's contribution w_SH A_SH + w_SV A_SV to eq:FGA is therefore that
+    of one beam on the common ray with weight 1 and amplitude
+    w_SH a_SH + w_SV a_SV.  nqp = Nq Np: an SV beam's lineage is that of its
+    SH partner plus 2 nqp (lineage ((b 2 + dir) Np + ip) Nq + iq); a beam
+    whose partner is missing (culled) keeps only its own term.  The merged
+    beam has the SH lineage and branch 1.  Returned sorted by lineage."""
+    b = np.ascontiguousarray(beams)
+    pb = b[b["branch"] == 0]
+    sh, sv = b[b["branch"] == 1], b[b["branch"] == 2]
+    key_sv = sv["lineage"] - 2 * nqp
+    keys = np.union1d(sh["lineage"], key_sv)
+    out = np.zeros(len(keys), dtype=BEAM_DTYPE)
+    out["a"] = 0.0
+    ray = ("Q", "P", "ZQ", "ZP", "S", "e", "sigma", "layer", "gen", "alive")
+    for src, key in ((sh, sh["lineage"]), (sv, key_sv)):
+        at = np.searchsorted(keys, key)
+        for f in ray:
+            out[f][at] = src[f]
+        out["a"][at] += src["w"][:, None] * src["a"]
+    # the two members of a pair share the ray exactly
+    both_sh = np.isin(sh["lineage"], key_sv)
+    both_sv = np.isin(key_sv, sh["lineage"])
+    a_, b_ = sh[both_sh], sv[both_sv][np.argsort(key_sv[both_sv], kind="stable")]
+    a_ = a_[np.argsort(a_["lineage"], kind="stable")]
+    for f in ("Q", "P", "ZQ", "ZP", "S", "e", "sigma"):
+        if not np.array_equal(a_[f], b_[f]):
+            raise ValueError("SH and SV beams of one (q, p, direction) differ in " + f)
+    out["lineage"] = keys
+    out["branch"] = 1
+    out["w"] = 1.0
+    m = np.concatenate([pb, out])
+    return take_beams(m, np.argsort(m["lineage"], kind="stable"))
+
+
 def decompose(work, one_way: bool = True, iq=None, ip=None, branch_mask: int = 7) -> np.ndarray:
     """Step 1 of the method (Sec. 2.2 algorithm): FBI weights and initial
     beams for all mesh points, or for the listed (iq, ip) pairs."""
