@@ -110,8 +110,10 @@ typedef struct {
 
 typedef enum {
   FGA_MEDIUM_HOMOGENEOUS = 0,  /* constant c_P, c_S                                   */
-  FGA_MEDIUM_GRID = 1,         /* periodic node grid, trilinear interpolation of c and
-                                  of its central-difference gradient and Hessian      */
+  FGA_MEDIUM_GRID = 1,         /* periodic node grid: trilinear interpolation of c and
+                                  of its central-difference gradient and Hessian, or
+                                  (smooth = 1) the periodic cubic B-spline through the
+                                  node values with its exact derivatives               */
   FGA_MEDIUM_LAYERED = 2       /* flat layers in z or concentric spherical shells, the
                                   speeds constant or linear in the level per layer     */
 } fga_medium_kind;
@@ -148,16 +150,31 @@ typedef struct {
      problem (sigma.n = 0); 0: no surface (the outermost layer extends without end).
      Beams must start inside the surface.                                            */
   double surface;
+  /* FGA_MEDIUM_GRID: 0: trilinear interpolation of the derived node fields (C^0);
+     1: c is the periodic cubic B-spline through the node values (C^2), its gradient
+     and Hessian the exact derivatives of the spline.  Both read the same table.     */
+  int smooth;
 } fga_medium;
 
-/* Bytes of the derived-field table of a grid medium with n[0]*n[1]*n[2] nodes. */
+/* Bytes of the table of a grid medium with N = n[0]*n[1]*n[2] nodes: per node
+ * field (c_P, then c_S if two_fields) N records of FGA_GRID_NODE_DOUBLES
+ * doubles, then per node field the N cubic B-spline coefficients. */
 size_t fga_medium_grid_table_bytes(const int n[3], int two_fields);
 
-/* Builds the per-node fields c, grad c (3), Hessian (xx, yy, zz, xy, xz, yz)
- * of each node field by second-order periodic central differences (the paper
- * gives no discretisation of gridded media; this is the reading the library
- * uses).  cp_nodes, cs_nodes (NULL unless two_fields): device, [z][y][x].
- * table: device, fga_medium_grid_table_bytes(n, two_fields) bytes.
+/* Builds the table of a gridded medium (Sec. 2: the ray and variational
+ * equations need c, grad c and its Hessian of a smooth medium; the paper gives
+ * no discretisation of gridded media, these are the readings the library
+ * uses): for each node field
+ *   - per node c, grad c (3), Hessian (xx, yy, zz, xy, xz, yz) by second-order
+ *     periodic central differences (slots 0..9 of the node record), read by
+ *     trilinear interpolation when the medium's smooth = 0;
+ *   - the coefficients a of the periodic cubic B-spline that takes the node
+ *     values, (a[i-1] + 4 a[i] + a[i+1]) / 6 = c[i] along each axis in turn,
+ *     by the recursive filter of the spline's two poles with periodic start
+ *     values (Unser, Aldroubi and Eden, IEEE Trans. Signal Process. 41, 1993),
+ *     read when smooth = 1.
+ * cp_nodes, cs_nodes (NULL unless two_fields): device, [z][y][x].
+ * table: device, fga_medium_grid_table_bytes(n, cs_nodes != NULL) bytes.
  * Errors: FGA_EINVAL for n < 3 or non-positive h or NULL pointers. */
 fga_status fga_medium_grid_build(const int n[3], const double h[3], const double *cp_nodes,
                                  const double *cs_nodes, double *table, void *stream);

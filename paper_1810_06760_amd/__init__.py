@@ -67,7 +67,7 @@ class MediumC(C.Structure):
                 ("two_fields", C.c_int), ("cs_ratio", C.c_double), ("geometry", C.c_int), ("nlayer", C.c_int),
                 ("bound", C.c_double * 8), ("cpl", C.c_double * 8), ("csl", C.c_double * 8),
                 ("rhol", C.c_double * 8), ("gradl", C.c_double * 8),
-                ("surface", C.c_double)]
+                ("surface", C.c_double), ("smooth", C.c_int)]
 
 
 class MeshC(C.Structure):
@@ -334,8 +334,10 @@ class Medium:
         return Medium(m)
 
     @staticmethod
-    def grid(cp_nodes, mesh, cs_ratio: float = None, cs_nodes=None) -> "Medium":
-        """Periodic node grid (nodes mesh.lo + i*mesh.h), arrays [z][y][x]."""
+    def grid(cp_nodes, mesh, cs_ratio: float = None, cs_nodes=None, smooth: bool = False) -> "Medium":
+        """Periodic node grid (nodes mesh.lo + i*mesh.h), arrays [z][y][x];
+        smooth: c is the cubic B-spline through the node values (C^2) instead
+        of the trilinear interpolation of central-difference node fields."""
         torch = _torch()
         n = (C.c_int * 3)(*[int(v) for v in mesh.n])
         h = (C.c_double * 3)(*[float(v) for v in mesh.h])
@@ -354,6 +356,7 @@ class Medium:
         m.table = table.data_ptr()
         m.two_fields = 1 if cs is not None else 0
         m.cs_ratio = 0.0 if cs_ratio is None else float(cs_ratio)
+        m.smooth = 1 if smooth else 0
         return Medium(m, keep=[table, cp, cs])
 
     @staticmethod
@@ -378,7 +381,7 @@ class Medium:
 def medium_for(work) -> Medium:
     if work.medium_nodes is None:
         return Medium.homogeneous(work.cp0, work.cs0)
-    return Medium.grid(work.medium_nodes, work.medium_grid, cs_ratio=work.cs_ratio)
+    return Medium.grid(work.medium_nodes, work.medium_grid, cs_ratio=work.cs_ratio, smooth=work.medium_smooth)
 
 
 # ---------------------------------------------------------------------------

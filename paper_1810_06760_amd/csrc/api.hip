@@ -104,6 +104,9 @@ fga_status make_dev_medium(const fga_medium *m, DevMedium *o)
     o->two_fields = m->two_fields ? 1 : 0;
     o->cs_ratio = m->cs_ratio;
     o->field_stride = (int64_t)FGA_GRID_NODE_DOUBLES * m->n[0] * m->n[1] * m->n[2];
+    o->smooth = m->smooth ? 1 : 0;
+    o->coef_stride = (int64_t)m->n[0] * m->n[1] * m->n[2];
+    o->coef = m->table + o->field_stride * (o->two_fields ? 2 : 1);
     if (!o->two_fields && !(m->cs_ratio > 0)) return fail(FGA_EINVAL, "grid medium needs cs_ratio > 0");
     return FGA_OK;
   case FGA_MEDIUM_LAYERED:
@@ -257,7 +260,7 @@ const char *fga_version(void) { return "fga-gfx950 0.1"; }
 size_t fga_medium_grid_table_bytes(const int n[3], int two_fields)
 {
   if (!n || n[0] < 1 || n[1] < 1 || n[2] < 1) return 0;
-  return sizeof(double) * FGA_GRID_NODE_DOUBLES * (size_t)n[0] * n[1] * n[2] * (two_fields ? 2 : 1);
+  return sizeof(double) * (FGA_GRID_NODE_DOUBLES + 1) * (size_t)n[0] * n[1] * n[2] * (two_fields ? 2 : 1);
 }
 
 fga_status fga_medium_grid_build(const int n[3], const double h[3], const double *cp_nodes, const double *cs_nodes,
@@ -269,9 +272,15 @@ fga_status fga_medium_grid_build(const int n[3], const double h[3], const double
     if (!(h[d] > 0)) return fail(FGA_EINVAL, "grid needs h > 0");
   }
   hipStream_t st = (hipStream_t)stream;
+  const size_t N = (size_t)n[0] * n[1] * n[2];
+  const int nf = cs_nodes ? 2 : 1;
+  double *coef = table + (size_t)FGA_GRID_NODE_DOUBLES * N * nf;
   FGA_HIP(launch_grid_build(n, h, cp_nodes, table, st));
-  if (cs_nodes)
-    FGA_HIP(launch_grid_build(n, h, cs_nodes, table + (size_t)FGA_GRID_NODE_DOUBLES * n[0] * n[1] * n[2], st));
+  FGA_HIP(launch_spline_coefficients(n, cp_nodes, coef, st));
+  if (cs_nodes) {
+    FGA_HIP(launch_grid_build(n, h, cs_nodes, table + (size_t)FGA_GRID_NODE_DOUBLES * N, st));
+    FGA_HIP(launch_spline_coefficients(n, cs_nodes, coef + N, st));
+  }
   return FGA_OK;
 }
 

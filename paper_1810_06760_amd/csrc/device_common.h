@@ -7,7 +7,8 @@
 namespace fga {
 
 // Medium kinds a kernel is specialised for.
-enum { MK_HOMOG = 0, MK_GRID = 1, MK_LAYERED = 2 };
+// MK_GRID: trilinear node records; MK_GRID3: cubic B-spline of the node values.
+enum { MK_HOMOG = 0, MK_GRID = 1, MK_LAYERED = 2, MK_GRID3 = 3 };
 
 // Layered media: if Q lies outside layer L, the interface crossed and the
 // layer beyond it (points on an interface count as inside).  Flat: interface
@@ -43,10 +44,74 @@ __device__ __forceinline__ double iface_level(const DevMedium &m, int iface)
 // A block of MEDBLK^3 grid nodes held in LDS by a workgroup: the ten fields
 // of node (o + l) (periodic) at lds[10 (l_z MEDBLK^2 + l_y MEDBLK + l_x)].
 constexpr int MEDBLK = 12;
+// Cubic media: a block of MEDBLK3^3 spline coefficients per node field, the
+// c_S field (two_fields) MEDBLK3^3 doubles after the c_P field.
+constexpr int MEDBLK3 = 16;
 struct MedBlock {
   const double *lds;  // NULL: no block
   int o[3];
 };
+
+// Cubic B-spline weights of the nodes i-1 .. i+2 at the fraction t of cell i,
+// and their first and second derivatives in x (ih = 1/h).
+__device__ __forceinline__ void bspline_weights(double t, double ih, double w[4], double d1[4], double d2[4])
+{
+  const double s = 1.0 - t, t2 = t * t, t3 = t2 * t, i6 = 1.0 / 6.0, ih2 = ih * ih;
+  w[0] = s * s * s * i6;
+  w[1] = (3.0 * t3 - 6.0 * t2 + 4.0) * i6;
+  w[2] = (-3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0) * i6;
+  w[3] = t3 * i6;
+  d1[0] = -0.5 * s * s * ih;
+  d1[1] = (1.5 * t2 - 2.0 * t) * ih;
+  d1[2] = (-1.5 * t2 + t + 0.5) * ih;
+  d1[3] = 0.5 * t2 * ih;
+  d2[0] = s * ih2;
+  d2[1] = (3.0 * t - 2.0) * ih2;
+  d2[2] = (1.0 - 3.0 * t) * ih2;
+  d2[3] = t * ih2;
+}
+
+// Tensor-product sum of the 4x4x4 coefficients ld(a, b, c) (x, y, z offsets)
+// giving c, grad c and the Hessian (xx, yy, zz, xy, xz, yz) in v[10]: the x
+// sums first (value, first, second derivative per row), then y, then z.
+template <class Load>
+__device__ __forceinline__ void bspline_sum(const double w[3][4], const double d1[3][4], const double d2[3][4],
+                                            Load ld, double v[10])
+{
+#pragma unroll
+  for (int k = 0; k < 10; ++k) v[k] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double y00 = 0.0, y10 = 0.0, y01 = 0.0, y20 = 0.0, y11 = 0.0, y02 = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const double q = ld(a, b, c);
+        x0 += w[0][a] * q;
+        x1 += d1[0][a] * q;
+        x2 += d2[0][a] * q;
+      }
+      y00 += w[1][b] * x0;
+      y10 += w[1][b] * x1;
+      y20 += w[1][b] * x2;
+      y01 += d1[1][b] * x0;
+      y11 += d1[1][b] * x1;
+      y02 += d2[1][b] * x0;
+    }
+    v[0] += w[2][c] * y00;
+    v[1] += w[2][c] * y10;
+    v[2] += w[2][c] * y01;
+    v[3] += d1[2][c] * y00;
+    v[4] += w[2][c] * y20;
+    v[5] += w[2][c] * y02;
+    v[6] += d2[2][c] * y00;
+    v[7] += w[2][c] * y11;
+    v[8] += d1[2][c] * y10;
+    v[9] += d1[2][c] * y01;
+  }
+}
 
 template <int MK>
 __device__ __forceinline__ void medium_eval(const DevMedium &m, int sp, int layer, const double *x,
@@ -84,6 +149,60 @@ __device__ __forceinline__ void medium_eval(const DevMedium &m, int sp, int laye
         g[2] = c0 * gm;
       }
     }
+  } else if constexpr (MK == MK_GRID3) {
+    const double *cf = m.coef;
+    double scale = 1.0;
+    if (sp) {
+      if (m.two_fields) cf += m.coef_stride;
+      else scale = m.cs_ratio;
+    }
+    int i0[3];
+    double w[3][4], d1[3][4], d2[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double u = (x[d] - m.lo[d]) * m.ih[d];
+      const double fl = floor(u);
+      int ii = (int)fl;
+      if (ii < 0 || ii >= m.n[d]) ii = ((ii % m.n[d]) + m.n[d]) % m.n[d];  // periodic (rare)
+      i0[d] = ii;
+      bspline_weights(u - fl, m.ih[d], w[d], d1[d], d2[d]);
+    }
+    // the 4x4x4 stencil from the LDS block when it lies in it for every lane
+    bool inblk = blk != nullptr && blk->lds != nullptr;
+    int l[3] = {0, 0, 0};
+    if (inblk) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int li = i0[d] - 1 - blk->o[d];
+        if (li < 0) li += m.n[d];
+        l[d] = li;
+        inblk = inblk && li <= MEDBLK3 - 4;
+      }
+    }
+    double v[10];
+    if (__all(inblk)) {
+      const double *b0 = blk->lds + ((sp && m.two_fields) ? MEDBLK3 * MEDBLK3 * MEDBLK3 : 0) +
+                         (l[2] * MEDBLK3 + l[1]) * MEDBLK3 + l[0];
+      bspline_sum(w, d1, d2, [&](int ia, int ib, int ic) { return b0[(ic * MEDBLK3 + ib) * MEDBLK3 + ia]; }, v);
+    } else {
+      int ix[4], iy[4], iz[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ix[k] = i0[0] - 1 + k;
+        iy[k] = i0[1] - 1 + k;
+        iz[k] = i0[2] - 1 + k;
+        ix[k] += ix[k] < 0 ? m.n[0] : (ix[k] >= m.n[0] ? -m.n[0] : 0);
+        iy[k] += iy[k] < 0 ? m.n[1] : (iy[k] >= m.n[1] ? -m.n[1] : 0);
+        iz[k] += iz[k] < 0 ? m.n[2] : (iz[k] >= m.n[2] ? -m.n[2] : 0);
+      }
+      bspline_sum(w, d1, d2,
+                  [&](int ia, int ib, int ic) { return cf[((size_t)iz[ic] * m.n[1] + iy[ib]) * m.n[0] + ix[ia]]; }, v);
+    }
+    c = scale * v[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] = scale * v[1 + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) H[k] = scale * v[4 + k];
   } else {
     const double *tab = m.table;
     double scale = 1.0;

@@ -71,6 +71,9 @@ struct DevMedium {
   int64_t field_stride;   // doubles between the c_P and c_S tables
   int two_fields;
   double cs_ratio;
+  int smooth;             // 1: cubic B-spline of the node values (coef), 0: trilinear records
+  const double *coef;     // spline coefficients, c_P then c_S (coef_stride apart)
+  int64_t coef_stride;
   // layered
   int geometry, nlayer;
   double bound[FGA_MAX_LAYERS];
@@ -85,6 +88,7 @@ fga_status make_dev_medium(const fga_medium *m, DevMedium *out);
 // -------------------------------------------------------------- launchers --
 hipError_t launch_grid_build(const int n[3], const double h[3], const double *c, double *table,
                              hipStream_t st);
+hipError_t launch_spline_coefficients(const int n[3], const double *c, double *coef, hipStream_t st);
 
 struct IntegrateArgs {
   double *f64;

@@ -341,6 +341,7 @@ fga_status decompose_impl(const DevMedium &dm, const fga_mesh *m, const double *
                          m->ny[2], m->ylo[0], m->ylo[1], m->ylo[2], m->yh[0], m->yh[1], m->yh[2], gdiv);
     };
     if (dm.kind == FGA_MEDIUM_HOMOGENEOUS) dv(k_div_speed<MK_HOMOG>);
+    else if (dm.kind == FGA_MEDIUM_GRID && dm.smooth) dv(k_div_speed<MK_GRID3>);
     else if (dm.kind == FGA_MEDIUM_GRID) dv(k_div_speed<MK_GRID>);
     else dv(k_div_speed<MK_LAYERED>);
     FGA_LAUNCH_CHECK();

@@ -137,6 +137,48 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
       }
     }
   }
+  if constexpr (MK == MK_GRID3) {
+    // the same for the cubic stencils: a MEDBLK3^3 block of spline coefficients
+    // (both node fields when there are two) around the beams' cells
+    constexpr int B3 = MEDBLK3 * MEDBLK3 * MEDBLK3;
+    __shared__ double lds_cf[2 * B3];
+    __shared__ int bb[6];
+    if (threadIdx.x < 3) {
+      bb[threadIdx.x] = 0x7fffffff;
+      bb[3 + threadIdx.x] = -0x7fffffff;
+    }
+    __syncthreads();
+    if (active && (a.i32[FGA_FLAGS * a.cap + i] & FGA_FLAG_ALIVE)) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double u = (a.f64[(FGA_Q + d) * a.cap + i] - med.lo[d]) * med.ih[d];
+        const int cell = (int)fmax(fmin(floor(u), 1.0e9), -1.0e9);
+        atomicMin(&bb[d], cell);
+        atomicMax(&bb[3 + d], cell);
+      }
+    }
+    __syncthreads();
+    if (bb[0] <= bb[3]) {
+      int o[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int c0 = bb[d] / 2 + bb[3 + d] / 2 - MEDBLK3 / 2 + 1;
+        o[d] = ((c0 % med.n[d]) + med.n[d]) % med.n[d];
+      }
+      const int nf = med.two_fields ? 2 : 1;
+      for (int idx = threadIdx.x; idx < nf * B3; idx += 256) {
+        const int f = idx / B3, r = idx - f * B3;
+        const int lx = r % MEDBLK3, ly = (r / MEDBLK3) % MEDBLK3, lz = r / (MEDBLK3 * MEDBLK3);
+        const int nx = (o[0] + lx) % med.n[0], ny = (o[1] + ly) % med.n[1], nz = (o[2] + lz) % med.n[2];
+        lds_cf[idx] = med.coef[f * med.coef_stride + ((int64_t)nz * med.n[1] + ny) * med.n[0] + nx];
+      }
+      __syncthreads();
+      blk.lds = lds_cf;
+      blk.o[0] = o[0];
+      blk.o[1] = o[1];
+      blk.o[2] = o[2];
+    }
+  }
   if (active) {
     const int64_t cap = a.cap;
     const int64_t nb = a.end - a.beg;
@@ -173,7 +215,7 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
       }
       for (int s = 0; s < a.nsteps; ++s) {
         if (live) {
-          if constexpr (MK == MK_GRID) rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt, &blk);
+          if constexpr (MK == MK_GRID || MK == MK_GRID3) rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt, &blk);
           else rk4_step_pc<MK>(med, sp, layer, sg, isS, y, dt);  // grad c = 0
           if (isS) reframe_s(y, e);
           ++steps_done;
@@ -210,7 +252,8 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
       // where grad c = 0 the step leaves P and dzP as they were: not stored
 #pragma unroll
       for (int f = 0; f < NS; ++f)
-        if (MK == MK_GRID || !((f >= IP && f < IP + 3) || (f >= IZPR && f < IZPR + 18))) F[f * cap + i] = y[f];
+        if (MK == MK_GRID || MK == MK_GRID3 || !((f >= IP && f < IP + 3) || (f >= IZPR && f < IZPR + 18)))
+          F[f * cap + i] = y[f];
 #pragma unroll
       for (int d = 0; d < 3; ++d) F[(FGA_E + d) * cap + i] = e[d];
       a.i32[FGA_FLAGS * cap + i] = flags;
@@ -488,7 +531,10 @@ hipError_t launch_integrate(const DevMedium &m, const IntegrateArgs &a, hipStrea
   ProfScope prof(FGA_K_INTEGRATE, st);
   switch (m.kind) {
   case FGA_MEDIUM_HOMOGENEOUS: hipLaunchKernelGGL(k_integrate<MK_HOMOG>, blocks, 256, 0, st, m, a); break;
-  case FGA_MEDIUM_GRID: hipLaunchKernelGGL(k_integrate<MK_GRID>, blocks, 256, 0, st, m, a); break;
+  case FGA_MEDIUM_GRID:
+    if (m.smooth) hipLaunchKernelGGL(k_integrate<MK_GRID3>, blocks, 256, 0, st, m, a);
+    else hipLaunchKernelGGL(k_integrate<MK_GRID>, blocks, 256, 0, st, m, a);
+    break;
   default:
     // layered media advance one step per launch, the interface step between
     if (a.nsteps != 1 || a.stride != 0) return hipErrorInvalidValue;

@@ -429,7 +429,9 @@ static fga_status decompose_source(const fga_medium *med, SourceArgs &a, fga_bea
   hipStream_t st = (hipStream_t)stream;
   switch (dm.kind) {
   case FGA_MEDIUM_HOMOGENEOUS: return run_source<MK_HOMOG>(dm, a, beams, counts, offs, total, st);
-  case FGA_MEDIUM_GRID: return run_source<MK_GRID>(dm, a, beams, counts, offs, total, st);
+  case FGA_MEDIUM_GRID:
+    if (dm.smooth) return run_source<MK_GRID3>(dm, a, beams, counts, offs, total, st);
+    return run_source<MK_GRID>(dm, a, beams, counts, offs, total, st);
   default: return run_source<MK_LAYERED>(dm, a, beams, counts, offs, total, st);
   }
 }

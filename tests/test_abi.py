@@ -38,8 +38,8 @@ def test_host_only_queries():
     L = fga.lib()
     assert L.fga_version().decode().startswith("fga-gfx950")
     n = (ctypes.c_int * 3)(128, 128, 128)
-    assert L.fga_medium_grid_table_bytes(n, 0) == 8 * 16 * 128 ** 3
-    assert L.fga_medium_grid_table_bytes(n, 1) == 2 * 8 * 16 * 128 ** 3
+    assert L.fga_medium_grid_table_bytes(n, 0) == 8 * 17 * 128 ** 3     # records + spline coefficients
+    assert L.fga_medium_grid_table_bytes(n, 1) == 2 * 8 * 17 * 128 ** 3
 
 
 def test_plane_layout_matches_header():
