@@ -50,12 +50,12 @@ HBM_PEAK = 8.0e12
 # HBM bytes per launch of the dominant kernel in the default bench window (smooth
 # workload, scale 1, K = 20 after W = 5), from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # scaled by a 1 GiB copy calibration; valid only while the kernel's source is
-# unchanged (sha256 prefix), else reported as null
+# unchanged (sha256 prefix) and the beam set is the one profiled, else null
 TRAFFIC = {
     "sum_points": {"source": "paper_1810_06760_amd/csrc/k_points.hip", "sha256": "262f9ec0539f99f6",
-                   "bytes_per_launch": 2.3897e10},
+                   "beams": 49095784, "bytes_per_launch": 2.3897e10},
     "integrate": {"source": "paper_1810_06760_amd/csrc/k_integrate.hip", "sha256": "a6b636620063c52f",
-                  "bytes_per_launch": 9.4622e9},
+                  "beams": 49095784, "bytes_per_launch": 9.4622e9},
 }
 
 
@@ -78,7 +78,7 @@ def parse():
                     help="fraction of the q mesh per axis and of the time steps (quick runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--segments", type=int, default=4, help="evolution calls per step (progress between them)")
-    ap.add_argument("--cpu-beams", type=int, default=8192, help="(q,p) pairs in the oracle sample")
+    ap.add_argument("--cpu-beams", type=int, default=12288, help="(q,p) pairs in the oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=1000, help="RK4 steps of the oracle sample")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead: a seeded sweep of forward-solve requests over 4 resident models, "
@@ -97,6 +97,10 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (the known-size kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--unmerged", action="store_true",
+                    help="SH and SV as two beams per (q, p, direction) (default: one S beam carrying both)")
+    ap.add_argument("--medium-interp", default="trilinear", choices=["trilinear", "cubic"],
+                    help="smooth workload: trilinear node fields (default) or the C2 cubic B-spline medium")
     ap.add_argument("--grid-precision", default="fp64", choices=list(GRID_PREC),
                     help="grid summation variant (mixed variants also report their error against FP64)")
     return ap.parse_args()
@@ -127,7 +131,7 @@ def gpu_run(w, args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     med = fga.medium_for(w)
-    mesh = fga.mesh_for(w)
+    mesh = fga.mesh_for(w, merge_s=not args.unmerged)
     f = fga._complex_dev(w.f)
     rec = fga._dev(w.receivers, torch.float64) if w.receivers is not None else None
     nq = w.qmesh.count * w.pmesh.count * 3
@@ -213,11 +217,11 @@ def gpu_run(w, args):
     return t1 - t0, tot, prof
 
 
-def traffic_for(name, default_workload):
-    """Measured HBM bytes per launch, if taken on this workload and this kernel source."""
+def traffic_for(name, default_workload, beams):
+    """Measured HBM bytes per launch, if taken on this workload, beam set and kernel source."""
     import hashlib
     t = TRAFFIC.get(name)
-    if t is None or not default_workload:
+    if t is None or not default_workload or t["beams"] != beams:
         return None
     with open(os.path.join(ROOT, t["source"]), "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest()[:16] != t["sha256"]:
@@ -239,7 +243,7 @@ def roofline(tot, prof, medium_kind, default_workload=False):
         return None, name
     achieved = work[name] / (ms * 1e-3)
     return {"bound": "alu", "kernel": name, "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic_for(name, default_workload),
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic_for(name, default_workload, tot["beams"]),
             "launches": launches, "avg_launch_ms": ms / launches,
             "flop_per_unit": FLOP_BEAM_STEP[medium_kind] if name == "integrate" else FLOP_POINT_EVAL,
             "units_per_launch": (tot["beam_steps"] if name == "integrate" else tot["ev_rec"]) / launches}, name
@@ -247,7 +251,8 @@ def roofline(tot, prof, medium_kind, default_workload=False):
 
 def cpu_baseline(w, args):
     """The oracle on a bounded sample of the same workload (about 10-20 s of
-    host work): 8192 random (q, p) pairs decomposed by FBI quadrature, then RK4 steps
+    host work): 12288 random (q, p) pairs decomposed by FBI quadrature (SH and SV
+    merged unless --unmerged), then RK4 steps
     in the same medium, each followed by the sum at the 256 receivers.  The
     per-beam-step time (integrator + one receiver sample) gives beam-steps/s
     at the threads the oracle uses."""
@@ -259,6 +264,8 @@ def cpu_baseline(w, args):
     med = om.medium_for(w)
     F = om.fbi(w.f, w.ymesh, w.qmesh.points()[iq], w.pmesh.points()[ip], w.eps)
     beams = om.make_beams(w.qmesh, w.pmesh, F, w.eps, iq, ip, cull_abs=0.0)
+    if not args.unmerged:
+        beams = om.merge_s_beams(beams, nqp)
     nsteps = min(w.nsteps, args.cpu_steps)
     t_ev = t_rec = 0.0
     for s in range(nsteps):
@@ -272,9 +279,10 @@ def cpu_baseline(w, args):
     per_beam_step = (t_ev + t_rec) / (nsteps * len(beams))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / per_beam_step, "unit": "beam-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "%d random (q,p) pairs x 3 branches (%d beams) of the same workload, %d RK4 steps from "
+            "sample": "%d random (q,p) pairs x 3 branches (%d beams%s) of the same workload, %d RK4 steps from "
                       "t = 0 each followed by the %d-receiver sum; %.1f s integrate + %.1f s receiver sums"
-                      % (len(pick), len(beams), nsteps, 0 if w.receivers is None else len(w.receivers), t_ev, t_rec),
+                      % (len(pick), len(beams), "" if args.unmerged else ", SH and SV merged", nsteps,
+                         0 if w.receivers is None else len(w.receivers), t_ev, t_rec),
             "seconds": t_ev + t_rec}
 
 
@@ -290,7 +298,8 @@ def layered(args):
     sc = args.scale
     e = fi.layered_earth(ndir=max(16, int(round(1600 * sc))), nsteps=max(8, int(round(2000 * sc))))
     med = fga.Medium.layered(1, e["bounds"], e["cp"], e["cs"], e["rho"])
-    src = fga.point_source(e["eps"], e["x0"], e["M"], nq=e["nq"], ndir=e["ndir"], nshell=e["nshell"])
+    src = fga.point_source(e["eps"], e["x0"], e["M"], nq=e["nq"], ndir=e["ndir"], nshell=e["nshell"],
+                           merge_s=not args.unmerged)
     ncand = int(fga.lib().fga_point_source_candidates(fga.C.byref(src)))
     beams = fga.BeamSet(12 * ncand)   # room for interface children (generation cap 3)
     rec = fga._dev(e["receivers_rtp"], torch.float64)   # stations as (r, longitude, latitude)
@@ -339,7 +348,8 @@ def layered(args):
         "value": acc["beam_steps"] / elapsed, "unit": "beam-steps/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "layered spherical Earth-like model, 4 shells (radii %s), point moment-tensor "
+        "config": {"s_beams": "separate SH and SV" if args.unmerged else "SH and SV merged per (q, p, direction)",
+                   "workload": "layered spherical Earth-like model, 4 shells (radii %s), point moment-tensor "
                                "source with Ricker wavelet at r = %.3f, eps = 1/256, q %d^3 x %d directions x %d "
                                "shells x 3 branches x 2 directions, %d RK4 steps to T = 1.5 with interface "
                                "splitting (generation cap 3), %d surface receivers x %d samples, FP64"
@@ -378,7 +388,8 @@ def pointforce(args):
     A = 1.0 / sig ** 2 + cp * cp / (2 * eps)
     psi_scale = eps / (2 * pc) * math.sqrt(3.0) / cp * math.sqrt(math.pi / A)
     src = fga.point_force(eps, x0, d, nq=nq, qhalf=qhalf, ndir=2000, nshell=40, omega=omega, t0=t0, width=sig,
-                          t_ref=-t0, shell_lo=0.3 * pc, shell_hi=1.7 * pc, cull_abs=1e-4 * psi_scale)
+                          t_ref=-t0, shell_lo=0.3 * pc, shell_hi=1.7 * pc, cull_abs=1e-4 * psi_scale,
+                          merge_s=not args.unmerged)
     med = fga.Medium.homogeneous(cp, cs, 1.0)
     ncand = int(fga.lib().fga_point_force_candidates(fga.C.byref(src)))
     beams = fga.BeamSet(ncand // 12)
@@ -430,7 +441,8 @@ def pointforce(args):
         "value": sum(p["beam_steps"] for p in parts) / elapsed, "unit": "beam-steps/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "point force with its time function in a homogeneous medium (the accuracy "
+        "config": {"s_beams": "separate SH and SV" if args.unmerged else "SH and SV merged per (q, p, direction)",
+                   "workload": "point force with its time function in a homogeneous medium (the accuracy "
                                "experiment of Sec. 2.3 in box units, eps_S = 1/256): %d beams of %d candidates "
                                "(q %d^3 x 2000 directions x 40 shells x 3 branches x 2 directions), %d RK4 steps "
                                "to t = 0.25, field on a 128^2 plane; one step = one whole solve"
@@ -468,7 +480,8 @@ def serve(args):
     prec = {"fp64": fga.FGA_FP64, "mixed": fga.FGA_FP32, "mixed32": fga.FGA_FP32_ACC32}[args.serve_precision]
 
     def request(rq, precision=None):
-        src = fga.point_source(rq["eps"], rq["x0"], rq["M"], nq=rq["nq"], ndir=rq["ndir"], nshell=rq["nshell"])
+        src = fga.point_source(rq["eps"], rq["x0"], rq["M"], nq=rq["nq"], ndir=rq["ndir"], nshell=rq["nshell"],
+                               merge_s=not args.unmerged)
         return fga.make_request(models[rq["model"]], None, None, rq["receivers"], rq["tau"], rq["dt"],
                                 rq["nsteps"], 1, precision=prec if precision is None else precision, source=src)
 
@@ -563,7 +576,8 @@ def serve(args):
         "vs_baseline": None,
         "dtype": "f64" if prec == fga.FGA_FP64 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "tomography sweep: %d requests over 4 resident 128^3 smooth random models, point "
+        "config": {"s_beams": "separate SH and SV" if args.unmerged else "SH and SV merged per (q, p, direction)",
+                   "workload": "tomography sweep: %d requests over 4 resident 128^3 smooth random models, point "
                                "moment-tensor sources (Ricker) at random positions, %s, "
                                "128..1024 receivers, %s receiver sums; Poisson arrivals at %.2f x saturated rate"
                                % (len(reqs),
@@ -618,7 +632,7 @@ def mixed(args):
     fga.fga_profile_enable(True)
     t0 = time.perf_counter()
     for k, qm in enumerate(slabs):
-        mesh = fga.make_mesh(w.eps, qm, w.pmesh, w.ymesh, cull_abs=w.cull_abs)
+        mesh = fga.make_mesh(w.eps, qm, w.pmesh, w.ymesh, cull_abs=w.cull_abs, merge_s=not args.unmerged)
         t = time.perf_counter()
         if "dec" not in ws:
             ws["dec"] = fga._workspace(fga.workspace_bytes("decompose", mesh=mesh))
@@ -670,7 +684,8 @@ def mixed(args):
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * elapsed,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32/bf16/f16", "data": "synthetic",
-        "config": {"workload": "mixed-precision grid: smooth random medium and packet at eps=1/512, q %d^3 x p 8^3 x 3 "
+        "config": {"s_beams": "separate SH and SV" if args.unmerged else "SH and SV merged per (q, p, direction)",
+                   "workload": "mixed-precision grid: smooth random medium and packet at eps=1/512, q %d^3 x p 8^3 x 3 "
                                "branches in %d waves, 250 FP64 RK4 steps to T=0.25, 256^3 grid (tau=16) summed by "
                                "FP64, FP32, BF16 hi+lo, FP16 hi+lo and FP16 x (hi+lo) tile GEMMs" % (nq, len(slabs)),
                    "beams": tot["beams"], "waves": len(slabs), "parallelism": "single GPU"},
@@ -712,12 +727,16 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 8}), flush=True)
         return
     w, label = make_workload(args.workload, args.scale)
+    if args.medium_interp == "cubic" and w.medium_nodes is not None:
+        w.medium_smooth = True
+        label = label.replace("eps=1/128", "C2 cubic B-spline medium, eps=1/128")
     elapsed, tot, prof = gpu_run(w, args)
     K = args.steps
     value = tot["beam_steps"] / elapsed
     kind = "grid" if w.medium_nodes is not None else "homogeneous"
     roof, dom = roofline(tot, prof, kind, default_workload=(args.workload == "smooth" and args.scale == 1.0
-                                                             and K == 20 and args.warmup == 5))
+                                                             and K == 20 and args.warmup == 5
+                                                             and args.medium_interp == "trilinear"))
     t_a, t_b = tot["t_window"]
     line = {
         "metric": "beam-steps/s + beam-point evals/s; served solves/s, p50/p99 at rel-L2<=1e-3",
@@ -732,7 +751,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": label + "; one step = one RK4 step of all beams with its receiver sample, "
+        "config": {"s_beams": "separate SH and SV" if args.unmerged else "SH and SV merged per (q, p, direction)",
+                   "workload": label + "; one step = one RK4 step of all beams with its receiver sample, "
                                "timed over t = %.3f..%.3f after an untimed advance; decompose and the grid "
                                "sum timed separately per solve" % (t_a, t_b),
                    "beams": int(tot["beams"]), "parallelism": "single GPU"},

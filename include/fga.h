@@ -192,6 +192,14 @@ typedef struct {
   int one_way;             /* 1: only "+" beams, psi = FBI[f].n (f is taken as the
                               "+"-going part); 0: "+" and "-" beams per eq:alpha^k     */
   double cull_abs;         /* beams with |psi| < cull_abs are not created             */
+  /* 1 (with branch bits 1 and 2 set): one S beam per (q, p, direction) in place of
+     the SH and SV pair.  Both members start from the same data and move with c_S,
+     so their rays coincide, and the S amplitude equations (eq:amp_SV, eq:amp_SH) and
+     the interface split are linear: the pair's field is that of one beam on the
+     common ray with weight 1 and (a_SV, a_SH) = 2^{3/2} (w_SV, w_SH), a member's
+     term kept only if its own |psi| passes the cull.  The beam has the SH lineage
+     and branch 1; the S work per (q, p) is halved.  0: the pair as two beams.     */
+  int merge_s;
 } fga_mesh;
 
 /* Workspace bytes fga_decompose needs for this mesh (with_g: g != NULL). */
@@ -241,6 +249,7 @@ typedef struct {
   int ricker;
   int branch_mask;
   double cull_abs;          /* beams with |psi| < cull_abs are not made              */
+  int merge_s;              /* as in fga_mesh                                         */
 } fga_point_source;
 
 int64_t fga_point_source_candidates(const fga_point_source *src);
@@ -283,6 +292,7 @@ typedef struct {
   double t_ref;             /* the time the beams describe before any evolution      */
   int branch_mask;
   double cull_abs;
+  int merge_s;              /* as in fga_mesh                                         */
 } fga_point_force;
 
 int64_t fga_point_force_candidates(const fga_point_force *src);

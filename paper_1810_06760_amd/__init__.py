@@ -75,7 +75,7 @@ class MeshC(C.Structure):
                 ("nq", C.c_int * 3), ("qlo", C.c_double * 3), ("qh", C.c_double * 3),
                 ("np", C.c_int * 3), ("plo", C.c_double * 3), ("ph", C.c_double * 3),
                 ("ny", C.c_int * 3), ("ylo", C.c_double * 3), ("yh", C.c_double * 3),
-                ("branch_mask", C.c_int), ("one_way", C.c_int), ("cull_abs", C.c_double)]
+                ("branch_mask", C.c_int), ("one_way", C.c_int), ("cull_abs", C.c_double), ("merge_s", C.c_int)]
 
 
 class ReceiversC(C.Structure):
@@ -97,14 +97,15 @@ class PointSourceC(C.Structure):
     _fields_ = [("eps", C.c_double), ("x0", C.c_double * 3), ("M", C.c_double * 6), ("rho0", C.c_double),
                 ("nq", C.c_int), ("qhalf", C.c_double), ("ndir", C.c_int), ("nshell", C.c_int),
                 ("shell_lo", C.c_double), ("shell_hi", C.c_double), ("ricker", C.c_int), ("branch_mask", C.c_int),
-                ("cull_abs", C.c_double)]
+                ("cull_abs", C.c_double), ("merge_s", C.c_int)]
 
 
 class PointForceC(C.Structure):
     _fields_ = [("eps", C.c_double), ("x0", C.c_double * 3), ("d", C.c_double * 3), ("rho0", C.c_double),
                 ("nq", C.c_int), ("qhalf", C.c_double), ("ndir", C.c_int), ("nshell", C.c_int),
                 ("shell_lo", C.c_double), ("shell_hi", C.c_double), ("omega", C.c_double), ("t0", C.c_double),
-                ("width", C.c_double), ("t_ref", C.c_double), ("branch_mask", C.c_int), ("cull_abs", C.c_double)]
+                ("width", C.c_double), ("t_ref", C.c_double), ("branch_mask", C.c_int), ("cull_abs", C.c_double),
+                ("merge_s", C.c_int)]
 
 
 class RequestC(C.Structure):
@@ -392,19 +393,21 @@ def fga_medium_grid_build(n, h, cp_nodes, cs_nodes, table):
     _check(lib().fga_medium_grid_build(n, h, _ptr(cp_nodes), _ptr(cs_nodes), _ptr(table), _stream()))
 
 
-def make_mesh(eps, qmesh, pmesh, ymesh, branch_mask=7, one_way=True, cull_abs=0.0) -> MeshC:
+def make_mesh(eps, qmesh, pmesh, ymesh, branch_mask=7, one_way=True, cull_abs=0.0, merge_s=False) -> MeshC:
     m = MeshC()
     m.eps = eps
     m.nq[:], m.qlo[:], m.qh[:] = [int(v) for v in qmesh.n], list(qmesh.lo), list(qmesh.h)
     m.np[:], m.plo[:], m.ph[:] = [int(v) for v in pmesh.n], list(pmesh.lo), list(pmesh.h)
     m.ny[:], m.ylo[:], m.yh[:] = [int(v) for v in ymesh.n], list(ymesh.lo), list(ymesh.h)
     m.branch_mask, m.one_way, m.cull_abs = branch_mask, 1 if one_way else 0, cull_abs
+    m.merge_s = 1 if merge_s else 0
     return m
 
 
-def mesh_for(work, one_way=True, branch_mask=7) -> MeshC:
+def mesh_for(work, one_way=True, branch_mask=7, merge_s=False) -> MeshC:
+    """merge_s: one S beam per (q, p, direction) carrying the SH and SV weights."""
     return make_mesh(work.eps, work.qmesh, work.pmesh, work.ymesh, branch_mask=branch_mask, one_way=one_way,
-                     cull_abs=work.cull_abs)
+                     cull_abs=work.cull_abs, merge_s=merge_s)
 
 
 def fga_decompose(medium: Medium, mesh: MeshC, f, g=None, beams: BeamSet = None, ws=None) -> BeamSet:
@@ -425,7 +428,7 @@ def fga_decompose(medium: Medium, mesh: MeshC, f, g=None, beams: BeamSet = None,
 
 
 def point_source(eps, x0, M, nq, qhalf=None, ndir=64, nshell=4, shell_lo=0.2, shell_hi=2.5, ricker=True,
-                 rho0=0.0, branch_mask=7, cull_abs=0.0) -> PointSourceC:
+                 rho0=0.0, branch_mask=7, cull_abs=0.0, merge_s=False) -> PointSourceC:
     """Point moment-tensor source parameters (M = xx, yy, zz, xy, xz, yz)."""
     s = PointSourceC()
     s.eps = eps
@@ -439,6 +442,7 @@ def point_source(eps, x0, M, nq, qhalf=None, ndir=64, nshell=4, shell_lo=0.2, sh
     s.ricker = 1 if ricker else 0
     s.branch_mask = branch_mask
     s.cull_abs = cull_abs
+    s.merge_s = 1 if merge_s else 0
     return s
 
 
@@ -454,7 +458,7 @@ def fga_decompose_point_source(medium: Medium, src: PointSourceC, beams: BeamSet
 
 
 def point_force(eps, x0, d, nq, qhalf, ndir, nshell, omega, t0, width, t_ref, shell_lo=0.2, shell_hi=2.5,
-                rho0=0.0, branch_mask=7, cull_abs=0.0) -> PointForceC:
+                rho0=0.0, branch_mask=7, cull_abs=0.0, merge_s=False) -> PointForceC:
     """Point force d F(t), F(t) = cos(omega (t + t0)) exp(-(t + t0)^2/width^2); beams launched at t_ref."""
     s = PointForceC()
     s.eps = eps
@@ -466,6 +470,7 @@ def point_force(eps, x0, d, nq, qhalf, ndir, nshell, omega, t0, width, t_ref, sh
     s.omega, s.t0, s.width, s.t_ref = omega, t0, width, t_ref
     s.branch_mask = branch_mask
     s.cull_abs = cull_abs
+    s.merge_s = 1 if merge_s else 0
     return s
 
 

@@ -102,6 +102,7 @@ struct BeamInit {
   double qlo[3], qh[3], plo[3], ph[3];
   int64_t Nq, Np, ncand;
   int mask, one_way;
+  int merge;                // one S beam per (q, p, direction): SH candidates carry the SV term too
   double cull, eps, norm;
   const double2 *Ft, *Gt;   // [3][plane] and [2][3][plane]
   int64_t plane;
@@ -110,14 +111,17 @@ struct BeamInit {
   double bound[FGA_MAX_LAYERS];
 };
 
-// psi of candidate lineage L; returns false if L is not a candidate.
+// psi of candidate lineage L; returns false if L is not a candidate.  With
+// a.merge the SV candidates are not candidates, and an SH candidate also
+// returns the psi of its SV partner (s2r, s2i) for the merged beam.
 __device__ __forceinline__ bool candidate_psi(const BeamInit &a, int64_t L, double q[3], double p[3],
-                                              double e[3], double &psr, double &psi, int &br, int &sg)
+                                              double e[3], double &psr, double &psi, double &s2r, double &s2i,
+                                              int &br, int &sg)
 {
   br = (int)(L / (2 * a.Np * a.Nq));
   const int dir = (int)((L / (a.Np * a.Nq)) % 2);
   const int64_t ip = (L / a.Nq) % a.Np, iq = L % a.Nq;
-  if (!((a.mask >> br) & 1) || (a.one_way && dir == 1)) return false;
+  if (!((a.mask >> br) & 1) || (a.one_way && dir == 1) || (a.merge && br == 2)) return false;
   sg = dir == 0 ? 1 : -1;
   int iqd[3] = {(int)(iq % a.nq[0]), (int)((iq / a.nq[0]) % a.nq[1]), (int)(iq / ((int64_t)a.nq[0] * a.nq[1]))};
   int ipd[3] = {(int)(ip % a.np[0]), (int)((ip / a.np[0]) % a.np[1]), (int)(ip / ((int64_t)a.np[0] * a.np[1]))};
@@ -136,44 +140,62 @@ __device__ __forceinline__ bool candidate_psi(const BeamInit &a, int64_t L, doub
   e[0] = near_z ? 1.0 : 0.0;
   e[1] = 0.0;
   e[2] = near_z ? 0.0 : 1.0;
-  double n[3];
+  double n[3], n2[3] = {0.0, 0.0, 0.0};
   if (br == 0) {
     n[0] = p[0] / pn; n[1] = p[1] / pn; n[2] = p[2] / pn;
   } else {
     double nsh[3], nsv[3];
     s_frame(p, e, nsh, nsv);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) n[d] = br == 1 ? nsh[d] : nsv[d];
-  }
-  double fr = 0.0, fi = 0.0;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const double2 F = a.Ft[c * a.plane + idx];
-    fr += F.x * n[c];
-    fi += F.y * n[c];
-  }
-  if (a.one_way) {
-    psr = fr;
-    psi = fi;
-  } else {
-    psr = 0.5 * fr;
-    psi = 0.5 * fi;
-    if (a.Gt) {
-      const double2 *G = a.Gt + (br == 0 ? 0 : 3) * a.plane;
-      double gr = 0.0, gi = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double2 v = G[c * a.plane + idx];
-        gr += v.x * n[c];
-        gi += v.y * n[c];
-      }
-      // + sigma * (i eps / (2|p|)) * G.n
-      const double f = sg * a.eps / (2.0 * pn);
-      psr += -f * gi;
-      psi += f * gr;
+    for (int d = 0; d < 3; ++d) {
+      n[d] = br == 1 ? nsh[d] : nsv[d];
+      n2[d] = nsv[d];
     }
   }
+  // psi for the polarisation nn (eq:psi, eq:alpha^k)
+  auto project = [&](const double nn[3], double &r, double &im) {
+    double fr = 0.0, fi = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double2 F = a.Ft[c * a.plane + idx];
+      fr += F.x * nn[c];
+      fi += F.y * nn[c];
+    }
+    if (a.one_way) {
+      r = fr;
+      im = fi;
+    } else {
+      r = 0.5 * fr;
+      im = 0.5 * fi;
+      if (a.Gt) {
+        const double2 *G = a.Gt + (br == 0 ? 0 : 3) * a.plane;
+        double gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double2 v = G[c * a.plane + idx];
+          gr += v.x * nn[c];
+          gi += v.y * nn[c];
+        }
+        // + sigma * (i eps / (2|p|)) * G.n
+        const double f = sg * a.eps / (2.0 * pn);
+        r += -f * gi;
+        im += f * gr;
+      }
+    }
+  };
+  project(n, psr, psi);
+  s2r = s2i = 0.0;
+  if (a.merge && br == 1) project(n2, s2r, s2i);
   return true;
+}
+
+// Whether a candidate is kept: |psi| >= cull; a merged S candidate when
+// either member's is (each member's term is then kept only if its own is).
+__device__ __forceinline__ bool kept(const BeamInit &a, int br, double pr, double pi, double s2r, double s2i)
+{
+  const bool k1 = !(sqrt(pr * pr + pi * pi) < a.cull);
+  if (!(a.merge && br == 1)) return k1;
+  return k1 || !(sqrt(s2r * s2r + s2i * s2i) < a.cull);
 }
 
 __global__ __launch_bounds__(256) void k_beam_count(BeamInit a, int64_t *__restrict__ counts)
@@ -181,9 +203,9 @@ __global__ __launch_bounds__(256) void k_beam_count(BeamInit a, int64_t *__restr
   const int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x;
   bool keep = false;
   if (L < a.ncand) {
-    double q[3], p[3], e[3], pr, pi;
+    double q[3], p[3], e[3], pr, pi, s2r, s2i;
     int br, sg;
-    if (candidate_psi(a, L, q, p, e, pr, pi, br, sg)) keep = !(sqrt(pr * pr + pi * pi) < a.cull);
+    if (candidate_psi(a, L, q, p, e, pr, pi, s2r, s2i, br, sg)) keep = kept(a, br, pr, pi, s2r, s2i);
   }
   int total;
   block_rank(keep, &total);
@@ -195,10 +217,10 @@ __global__ __launch_bounds__(256) void k_beam_write(BeamInit a, const int64_t *_
 {
   const int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x;
   bool keep = false;
-  double q[3], p[3], e[3], pr = 0, pi = 0;
+  double q[3], p[3], e[3], pr = 0, pi = 0, s2r = 0, s2i = 0;
   int br = 0, sg = 1;
   if (L < a.ncand) {
-    if (candidate_psi(a, L, q, p, e, pr, pi, br, sg)) keep = !(sqrt(pr * pr + pi * pi) < a.cull);
+    if (candidate_psi(a, L, q, p, e, pr, pi, s2r, s2i, br, sg)) keep = kept(a, br, pr, pi, s2r, s2i);
   }
   int total;
   const int r = block_rank(keep, &total);
@@ -219,13 +241,24 @@ __global__ __launch_bounds__(256) void k_beam_write(BeamInit a, const int64_t *_
     F[(FGA_ZP_IM + o) * cap + i] = diag ? -1.0 : 0.0;
   }
   const double a0 = 2.8284271247461900976;  // 2^{3/2}
-  F[FGA_A0_RE * cap + i] = br == 1 ? 0.0 : a0;
-  F[FGA_A0_IM * cap + i] = 0.0;
-  F[FGA_A1_RE * cap + i] = br == 1 ? a0 : 0.0;
-  F[FGA_A1_IM * cap + i] = 0.0;
+  if (a.merge && br == 1) {
+    // merged S beam: weight 1, (a_SV, a_SH) = 2^{3/2} (w_SV, w_SH) of the kept members
+    const bool ksh = !(sqrt(pr * pr + pi * pi) < a.cull), ksv = !(sqrt(s2r * s2r + s2i * s2i) < a.cull);
+    F[FGA_A0_RE * cap + i] = ksv ? a0 * (s2r * a.norm) : 0.0;
+    F[FGA_A0_IM * cap + i] = ksv ? a0 * (s2i * a.norm) : 0.0;
+    F[FGA_A1_RE * cap + i] = ksh ? a0 * (pr * a.norm) : 0.0;
+    F[FGA_A1_IM * cap + i] = ksh ? a0 * (pi * a.norm) : 0.0;
+    F[FGA_W_RE * cap + i] = 1.0;
+    F[FGA_W_IM * cap + i] = 0.0;
+  } else {
+    F[FGA_A0_RE * cap + i] = br == 1 ? 0.0 : a0;
+    F[FGA_A0_IM * cap + i] = 0.0;
+    F[FGA_A1_RE * cap + i] = br == 1 ? a0 : 0.0;
+    F[FGA_A1_IM * cap + i] = 0.0;
+    F[FGA_W_RE * cap + i] = pr * a.norm;
+    F[FGA_W_IM * cap + i] = pi * a.norm;
+  }
   F[FGA_S * cap + i] = 0.0;
-  F[FGA_W_RE * cap + i] = pr * a.norm;
-  F[FGA_W_IM * cap + i] = pi * a.norm;
   int layer = 0;
   if (a.nlayer > 1) {
     if (a.geometry == 1) {
@@ -361,6 +394,7 @@ fga_status decompose_impl(const DevMedium &dm, const fga_mesh *m, const double *
   a.ncand = ncand;
   a.mask = m->branch_mask;
   a.one_way = m->one_way;
+  a.merge = m->merge_s && (m->branch_mask & 6) == 6;
   a.cull = m->cull_abs;
   a.eps = m->eps;
   const double dq = m->qh[0] * m->qh[1] * m->qh[2];

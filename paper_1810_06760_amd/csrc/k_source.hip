@@ -32,22 +32,27 @@ struct SourceArgs {
   double shell_lo, shell_hi;
   double gl_t[MAXSH], gl_w[MAXSH];  // Gauss-Legendre nodes and weights on [-1, 1]
   int ricker, mask;
+  int merge;                // one S beam per (q, p, direction): SH candidates carry the SV term too
   double cull, norm;
   int64_t Nq, Np, ncand;
   int layer0;
 };
 
-// psi (pr, pi) of candidate L and its p-cell measure dp; false for a masked branch
+// psi (pr, pi) of candidate L and its p-cell measure dp; false for a masked
+// branch.  With a.merge the SV candidates are not candidates, and an SH
+// candidate also returns the psi of its SV partner (s2r, s2i).
 template <int MK>
 __device__ bool candidate(const DevMedium &m, const SourceArgs &a, int64_t L, double q[3], double p[3], double e[3],
-                          double &pr, double &pi, double &dp, int &br, int &sg)
+                          double &pr, double &pi, double &s2r, double &s2i, double &dp, int &br, int &sg)
 {
   const int64_t iq = L % a.Nq;
   const int64_t ip = (L / a.Nq) % a.Np;
   const int bd = (int)(L / (a.Nq * a.Np));
   br = bd >> 1;
   sg = (bd & 1) ? -1 : 1;
-  if (!(a.mask & (1 << br))) return false;
+  if (!(a.mask & (1 << br)) || (a.merge && br == 2)) return false;
+  s2r = s2i = 0.0;
+  const bool two = a.merge && br == 1;
   const int sp = br == 0 ? 0 : 1;
   double cP, gP[3], H6[6], cb, gb[3];
   medium_eval<MK>(m, 0, a.layer0, a.x0, cP, gP, H6);
@@ -76,7 +81,7 @@ __device__ bool candidate(const DevMedium &m, const SourceArgs &a, int64_t L, do
   e[0] = nearz ? 1.0 : 0.0;
   e[1] = 0.0;
   e[2] = nearz ? 0.0 : 1.0;
-  double nh[3];
+  double nh[3], nh2[3] = {0.0, 0.0, 0.0};
   if (br == 0) {
     nh[0] = p[0] / np;
     nh[1] = p[1] / np;
@@ -84,7 +89,10 @@ __device__ bool candidate(const DevMedium &m, const SourceArgs &a, int64_t L, do
   } else {
     double nsh[3], nsv[3];
     s_frame(p, e, nsh, nsv);
-    for (int d = 0; d < 3; ++d) nh[d] = br == 1 ? nsh[d] : nsv[d];
+    for (int d = 0; d < 3; ++d) {
+      nh[d] = br == 1 ? nsh[d] : nsv[d];
+      nh2[d] = nsv[d];
+    }
   }
   // K and grad(K / c_b) at x0
   const double d0 = a.x0[0] - q[0], d1 = a.x0[1] - q[1], d2 = a.x0[2] - q[2];
@@ -118,11 +126,15 @@ __device__ bool candidate(const DevMedium &m, const SourceArgs &a, int64_t L, do
       Ir += mg * cs;
       Ii += mg * sn;
     }
-    const double dn = (a.d[0] * nh[0] + a.d[1] * nh[1] + a.d[2] * nh[2]) / (a.rho0 * cb);
     // psi = sg (i eps / (2|p|)) (d.n/(rho0 c)) K I
-    const double f = sg * a.eps / (2.0 * np) * dn;
-    pr = -f * Ii;
-    pi = f * Ir;
+    auto force_psi = [&](const double nn[3], double &r, double &im) {
+      const double dn = (a.d[0] * nn[0] + a.d[1] * nn[1] + a.d[2] * nn[2]) / (a.rho0 * cb);
+      const double f = sg * a.eps / (2.0 * np) * dn;
+      r = -f * Ii;
+      im = f * Ir;
+    };
+    force_psi(nh, pr, pi);
+    if (two) force_psi(nh2, s2r, s2i);
     return true;
   }
   double ks, kc;
@@ -137,29 +149,46 @@ __device__ bool candidate(const DevMedium &m, const SourceArgs &a, int64_t L, do
     gr[j] = (Kr * ar - Ki * ai) / cb - Kr * gb[j] / (cb * cb);
     gi[j] = (Kr * ai + Ki * ar) / cb - Ki * gb[j] / (cb * cb);
   }
-  double Gr = 0.0, Gi = 0.0;  // (M grad(K/c)).n / rho0
+  double mr[3], mi[3];  // M grad(K/c)
   for (int i = 0; i < 3; ++i) {
-    double mr = 0.0, mi = 0.0;
+    mr[i] = mi[i] = 0.0;
     for (int j = 0; j < 3; ++j) {
-      mr += a.M[i][j] * gr[j];
-      mi += a.M[i][j] * gi[j];
+      mr[i] += a.M[i][j] * gr[j];
+      mi[i] += a.M[i][j] * gi[j];
     }
-    Gr += mr * nh[i];
-    Gi += mi * nh[i];
   }
-  Gr /= a.rho0;
-  Gi /= a.rho0;
   double rk = 1.0;
   if (a.ricker) {
     const double w = cb * np / a.eps, w0 = cP / a.eps;
     const double x = (w / w0) * (w / w0);
     rk = x * exp(1.0 - x);
   }
-  // psi = sg (i eps / (2|p|)) G rk
-  const double f = sg * a.eps / (2.0 * np) * rk;
-  pr = -f * Gi;
-  pi = f * Gr;
+  // psi = sg (i eps / (2|p|)) G rk, G = (M grad(K/c)).n / rho0
+  auto mt_psi = [&](const double nn[3], double &r, double &im) {
+    double Gr = 0.0, Gi = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      Gr += mr[i] * nn[i];
+      Gi += mi[i] * nn[i];
+    }
+    Gr /= a.rho0;
+    Gi /= a.rho0;
+    const double f = sg * a.eps / (2.0 * np) * rk;
+    r = -f * Gi;
+    im = f * Gr;
+  };
+  mt_psi(nh, pr, pi);
+  if (two) mt_psi(nh2, s2r, s2i);
   return true;
+}
+
+// Whether a candidate is kept: |psi| >= cull; a merged S candidate when
+// either member's is (each member's term is then kept only if its own is).
+__device__ __forceinline__ bool source_kept(const SourceArgs &a, int br, double pr, double pi, double s2r,
+                                            double s2i)
+{
+  const bool k1 = !(sqrt(pr * pr + pi * pi) < a.cull);
+  if (!(a.merge && br == 1)) return k1;
+  return k1 || !(sqrt(s2r * s2r + s2i * s2i) < a.cull);
 }
 
 template <int MK>
@@ -168,9 +197,9 @@ __global__ __launch_bounds__(256) void k_source_count(DevMedium m, SourceArgs a,
   const int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x;
   bool keep = false;
   if (L < a.ncand) {
-    double q[3], p[3], e[3], pr = 0.0, pi = 0.0, dp = 0.0;
+    double q[3], p[3], e[3], pr = 0.0, pi = 0.0, s2r = 0.0, s2i = 0.0, dp = 0.0;
     int br, sg;
-    if (candidate<MK>(m, a, L, q, p, e, pr, pi, dp, br, sg)) keep = !(sqrt(pr * pr + pi * pi) < a.cull);
+    if (candidate<MK>(m, a, L, q, p, e, pr, pi, s2r, s2i, dp, br, sg)) keep = source_kept(a, br, pr, pi, s2r, s2i);
   }
   int total;
   block_rank(keep, &total);
@@ -184,10 +213,10 @@ __global__ __launch_bounds__(256) void k_source_write(DevMedium m, SourceArgs a,
 {
   const int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x;
   bool keep = false;
-  double q[3], p[3], e[3], pr = 0.0, pi = 0.0, dp = 0.0;
+  double q[3], p[3], e[3], pr = 0.0, pi = 0.0, s2r = 0.0, s2i = 0.0, dp = 0.0;
   int br = 0, sg = 1;
   if (L < a.ncand) {
-    if (candidate<MK>(m, a, L, q, p, e, pr, pi, dp, br, sg)) keep = !(sqrt(pr * pr + pi * pi) < a.cull);
+    if (candidate<MK>(m, a, L, q, p, e, pr, pi, s2r, s2i, dp, br, sg)) keep = source_kept(a, br, pr, pi, s2r, s2i);
   }
   int total;
   const int r = block_rank(keep, &total);
@@ -206,13 +235,24 @@ __global__ __launch_bounds__(256) void k_source_write(DevMedium m, SourceArgs a,
     F[(FGA_ZP_IM + o) * cap + i] = diag ? -1.0 : 0.0;
   }
   const double a0 = 2.8284271247461900976;  // 2^{3/2}
-  F[FGA_A0_RE * cap + i] = br == 1 ? 0.0 : a0;
-  F[FGA_A0_IM * cap + i] = 0.0;
-  F[FGA_A1_RE * cap + i] = br == 1 ? a0 : 0.0;
-  F[FGA_A1_IM * cap + i] = 0.0;
+  if (a.merge && br == 1) {
+    // merged S beam: weight 1, (a_SV, a_SH) = 2^{3/2} (w_SV, w_SH) of the kept members
+    const bool ksh = !(sqrt(pr * pr + pi * pi) < a.cull), ksv = !(sqrt(s2r * s2r + s2i * s2i) < a.cull);
+    F[FGA_A0_RE * cap + i] = ksv ? a0 * (s2r * dp * a.norm) : 0.0;
+    F[FGA_A0_IM * cap + i] = ksv ? a0 * (s2i * dp * a.norm) : 0.0;
+    F[FGA_A1_RE * cap + i] = ksh ? a0 * (pr * dp * a.norm) : 0.0;
+    F[FGA_A1_IM * cap + i] = ksh ? a0 * (pi * dp * a.norm) : 0.0;
+    F[FGA_W_RE * cap + i] = 1.0;
+    F[FGA_W_IM * cap + i] = 0.0;
+  } else {
+    F[FGA_A0_RE * cap + i] = br == 1 ? 0.0 : a0;
+    F[FGA_A0_IM * cap + i] = 0.0;
+    F[FGA_A1_RE * cap + i] = br == 1 ? a0 : 0.0;
+    F[FGA_A1_IM * cap + i] = 0.0;
+    F[FGA_W_RE * cap + i] = pr * dp * a.norm;  // w = psi dq dp (2 pi eps)^{-9/2}
+    F[FGA_W_IM * cap + i] = pi * dp * a.norm;
+  }
   F[FGA_S * cap + i] = 0.0;
-  F[FGA_W_RE * cap + i] = pr * dp * a.norm;  // w = psi dq dp (2 pi eps)^{-9/2}
-  F[FGA_W_IM * cap + i] = pi * dp * a.norm;
   int layer = 0;
   if (MK == MK_LAYERED) {
     int iface, nl;
@@ -279,6 +319,7 @@ fga_status force_args(const fga_point_force *s, SourceArgs *a)
   ps.ricker = 0;
   ps.branch_mask = s->branch_mask;
   ps.cull_abs = s->cull_abs;
+  ps.merge_s = s->merge_s;
   fga_status st = source_args(&ps, a);
   if (st != FGA_OK) return st;
   a->kind = 1;
@@ -313,6 +354,7 @@ fga_status source_args(const fga_point_source *s, SourceArgs *a)
   gauss_legendre(s->nshell, a->gl_t, a->gl_w);
   a->ricker = s->ricker ? 1 : 0;
   a->mask = s->branch_mask & 7;
+  a->merge = s->merge_s && (a->mask & 6) == 6;
   a->cull = s->cull_abs;
   a->Nq = (int64_t)s->nq * s->nq * s->nq;
   a->Np = (int64_t)s->ndir * s->nshell;
