@@ -90,6 +90,7 @@ def lib():
         L.om_sum_points.restype = C.c_int64
         L.om_sum_points.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_double, C.c_double, vp]
         L.om_evolve.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_int]
+        L.om_evolve_svec.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_int]
         L.om_fbi_many.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, C.c_double, vp]
         L.om_make_beams_many.restype = C.c_int64
         L.om_make_beams_many.argtypes = [vp, vp, vp, vp, C.c_int64, vp, vp, C.c_int64, C.c_int64, C.c_int,
@@ -375,10 +376,13 @@ def plant_two_way_error(kind: int) -> None:
 # evolution and reconstruction
 # ---------------------------------------------------------------------------
 
-def evolve(med: OracleMedium, beams: np.ndarray, dt: float, nsteps: int) -> None:
-    """Advance beams in place by nsteps classic RK4 steps."""
+def evolve(med: OracleMedium, beams: np.ndarray, dt: float, nsteps: int, s_vector: bool = False) -> None:
+    """Advance beams in place by nsteps classic RK4 steps.  s_vector: S
+    amplitudes advanced as the frame-free polarisation vector (parallel
+    transport along the ray) and returned to the beam's frame at the end."""
     assert beams.dtype == BEAM_DTYPE and beams.flags.c_contiguous
-    lib().om_evolve(med.ref, _p(beams), beams.shape[0], dt, nsteps)
+    f = lib().om_evolve_svec if s_vector else lib().om_evolve
+    f(med.ref, _p(beams), beams.shape[0], dt, nsteps)
 
 
 def evolve_layered(med: OracleMedium, beams: np.ndarray, dt: float, nsteps: int, gmax: int = 3,

@@ -440,7 +440,37 @@ static void csolve3(cplx Z[3][3], cplx B[3][3], cplx X[3][3])
  * The action S is not in the paper's ansatz; since H is homogeneous of degree
  * one in P it stays zero up to rounding, and is carried so that the phase
  * factor exp(i k S) is explicit. */
+static cplx om_rhs_core(const om_medium *m, const om_beam *b, const om_state *y, om_state *dy, double gc_out[3]);
+
 void om_rhs(const om_medium *m, const om_beam *b, const om_state *y, om_state *dy)
+{
+  double gc[3];
+  const cplx s = om_rhs_core(m, b, y, dy, gc);
+  const double *P = y->P;
+  if (b->branch == 0) {
+    dy->a[0] = s * y->a[0];
+    dy->a[1] = 0;
+  } else {
+    /* omega = dN_SH/dt . N_SV, with N_SH = (e x P)/|e x P| differentiated
+     * along dP/dt (e is fixed during a step). */
+    double ex[3], exd[3], nsh[3], nsv[3];
+    cross3(b->e, P, ex);
+    cross3(b->e, dy->P, exd);
+    double n2 = dot3(ex, ex), n = sqrt(n2);
+    double proj = dot3(ex, exd);
+    double dnsh[3];
+    for (int i = 0; i < 3; ++i) dnsh[i] = exd[i] / n - ex[i] * proj / (n2 * n);
+    om_s_frame(P, b->e, nsh, nsv);
+    double om = dot3(dnsh, nsv);
+    dy->a[0] = s * y->a[0] - om * y->a[1];
+    dy->a[1] = s * y->a[1] + om * y->a[0];
+  }
+}
+
+/* Everything but the amplitudes: dQ, dP, d(dzQ), d(dzP), dS; returns the
+ * amplitude rate s of eq:amp_P / eq:amp_SV / eq:amp_SH (without the frame
+ * coupling) and grad c. */
+static cplx om_rhs_core(const om_medium *m, const om_beam *b, const om_state *y, om_state *dy, double gc_out[3])
 {
   const int sp = b->branch == 0 ? 0 : 1;
   const double sg = (double)b->sigma;
@@ -477,25 +507,9 @@ void om_rhs(const om_medium *m, const om_beam *b, const om_state *y, om_state *d
   csolve3(Z, dZ, X);
   cplx tr = X[0][0] + X[1][1] + X[2][2];
   cplx s = sg * dot3(gc, P) / np + 0.5 * tr;
-  if (b->branch == 0) {
-    dy->a[0] = s * y->a[0];
-    dy->a[1] = 0;
-  } else {
-    /* omega = dN_SH/dt . N_SV, with N_SH = (e x P)/|e x P| differentiated
-     * along dP/dt (e is fixed during a step). */
-    double ex[3], exd[3], nsh[3], nsv[3];
-    cross3(b->e, P, ex);
-    cross3(b->e, dy->P, exd);
-    double n2 = dot3(ex, ex), n = sqrt(n2);
-    double proj = dot3(ex, exd);
-    double dnsh[3];
-    for (int i = 0; i < 3; ++i) dnsh[i] = exd[i] / n - ex[i] * proj / (n2 * n);
-    om_s_frame(P, b->e, nsh, nsv);
-    double om = dot3(dnsh, nsv);
-    dy->a[0] = s * y->a[0] - om * y->a[1];
-    dy->a[1] = s * y->a[1] + om * y->a[0];
-  }
   dy->S = dot3(P, dy->Q) - sg * c * np;
+  for (int i = 0; i < 3; ++i) gc_out[i] = gc[i];
+  return s;
 }
 
 static void st_from_beam(const om_beam *b, om_state *y)
@@ -591,6 +605,105 @@ void om_evolve(const om_medium *m, om_beam *beams, int64_t n, double dt, int nst
       om_rk4_step(m, &beams[i], dt);
       om_reframe(&beams[i]);
     }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Frame-free S polarisation                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* The S amplitude as the physical polarisation vector A = a_SV N_SV + a_SH N_SH
+ * (complex, orthogonal to P).  Differentiating that sum under the framed
+ * equations (eq:amp_SV, eq:amp_SH, coupling omega = dN_SH/dt . N_SV) leaves
+ *   dA/dt = s A - (A . dPhat/dt) Phat,  dPhat/dt = (dP/dt - Phat (Phat . dP/dt))/|P|,
+ * with the same scalar rate s: A is carried along the ray by parallel
+ * transport and needs no reference axis.  The rest of the state follows the
+ * same equations as in om_rhs. */
+static void om_rhs_vec(const om_medium *m, const om_beam *b, const om_state *y, const cplx A[3], om_state *dy,
+                       cplx dA[3])
+{
+  double gc[3];
+  const cplx s = om_rhs_core(m, b, y, dy, gc);
+  dy->a[0] = dy->a[1] = 0;
+  const double np = sqrt(dot3(y->P, y->P));
+  double ph[3], dph[3];
+  for (int i = 0; i < 3; ++i) ph[i] = y->P[i] / np;
+  const double pd = dot3(ph, dy->P);
+  for (int i = 0; i < 3; ++i) dph[i] = (dy->P[i] - ph[i] * pd) / np;
+  const cplx ad = A[0] * dph[0] + A[1] * dph[1] + A[2] * dph[2];
+  for (int i = 0; i < 3; ++i) dA[i] = s * A[i] - ad * ph[i];
+}
+
+/* One classic RK4 step of an S beam in the frame-free form; afterwards A is
+ * projected on the plane orthogonal to the new P (the exact solution stays
+ * there; the projection removes the step's truncation drift out of it). */
+static void om_rk4_step_vec(const om_medium *m, om_beam *b, cplx A[3], double dt)
+{
+  om_state y, k[4], t;
+  cplx kA[4][3], tA[3];
+  st_from_beam(b, &y);
+  const double h[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
+  for (int st = 0; st < 4; ++st) {
+    if (st == 0) {
+      t = y;
+      for (int i = 0; i < 3; ++i) tA[i] = A[i];
+    } else {
+      st_axpy(&t, &y, h[st], &k[st - 1]);
+      for (int i = 0; i < 3; ++i) tA[i] = A[i] + h[st] * kA[st - 1][i];
+    }
+    om_rhs_vec(m, b, &t, tA, &k[st], kA[st]);
+  }
+  om_state out;
+  for (int i = 0; i < 3; ++i) {
+    out.Q[i] = y.Q[i] + dt / 6.0 * (k[0].Q[i] + 2.0 * k[1].Q[i] + 2.0 * k[2].Q[i] + k[3].Q[i]);
+    out.P[i] = y.P[i] + dt / 6.0 * (k[0].P[i] + 2.0 * k[1].P[i] + 2.0 * k[2].P[i] + k[3].P[i]);
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      out.ZQ[i][j] = y.ZQ[i][j] + dt / 6.0 * (k[0].ZQ[i][j] + 2.0 * k[1].ZQ[i][j] + 2.0 * k[2].ZQ[i][j] + k[3].ZQ[i][j]);
+      out.ZP[i][j] = y.ZP[i][j] + dt / 6.0 * (k[0].ZP[i][j] + 2.0 * k[1].ZP[i][j] + 2.0 * k[2].ZP[i][j] + k[3].ZP[i][j]);
+    }
+  out.a[0] = y.a[0];
+  out.a[1] = y.a[1];
+  out.S = y.S + dt / 6.0 * (k[0].S + 2.0 * k[1].S + 2.0 * k[2].S + k[3].S);
+  for (int i = 0; i < 3; ++i) A[i] += dt / 6.0 * (kA[0][i] + 2.0 * kA[1][i] + 2.0 * kA[2][i] + kA[3][i]);
+  st_to_beam(&out, b);
+  const double np = sqrt(dot3(b->P, b->P));
+  double ph[3];
+  for (int i = 0; i < 3; ++i) ph[i] = b->P[i] / np;
+  const cplx ap = A[0] * ph[0] + A[1] * ph[1] + A[2] * ph[2];
+  for (int i = 0; i < 3; ++i) A[i] -= ap * ph[i];
+}
+
+/* Advance n beams by nsteps RK4 steps with S amplitudes in the frame-free
+ * form: A is formed from (a_SV, a_SH) and the beam's frame, advanced, and
+ * returned to the frame at the end (the axis switched first if P has come
+ * within 10 degrees of it, as om_reframe does).  P beams step as in om_evolve. */
+void om_evolve_svec(const om_medium *m, om_beam *beams, int64_t n, double dt, int nsteps)
+{
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    om_beam *b = &beams[i];
+    if (!b->alive) continue;
+    if (b->branch == 0) {
+      for (int s = 0; s < nsteps; ++s) om_rk4_step(m, b, dt);
+      continue;
+    }
+    double nsh[3], nsv[3];
+    om_s_frame(b->P, b->e, nsh, nsv);
+    cplx A[3];
+    for (int d = 0; d < 3; ++d) A[d] = b->a[0] * nsv[d] + b->a[1] * nsh[d];
+    for (int s = 0; s < nsteps; ++s) om_rk4_step_vec(m, b, A, dt);
+    const double np = sqrt(dot3(b->P, b->P));
+    if (fabs(dot3(b->P, b->e)) / np > cos(10.0 * M_PI / 180.0)) {
+      const int was_z = b->e[2] != 0.0 && b->e[0] == 0.0 && b->e[1] == 0.0;
+      b->e[0] = was_z ? 1.0 : 0.0;
+      b->e[1] = 0.0;
+      b->e[2] = was_z ? 0.0 : 1.0;
+    }
+    om_s_frame(b->P, b->e, nsh, nsv);
+    b->a[0] = A[0] * nsv[0] + A[1] * nsv[1] + A[2] * nsv[2];
+    b->a[1] = A[0] * nsh[0] + A[1] * nsh[1] + A[2] * nsh[2];
   }
 }
 
