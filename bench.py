@@ -53,9 +53,9 @@ HBM_PEAK = 8.0e12
 # unchanged (sha256 prefix) and the beam set is the one profiled, else null
 TRAFFIC = {
     "sum_points": {"source": "paper_1810_06760_amd/csrc/k_points.hip", "sha256": "262f9ec0539f99f6",
-                   "beams": 49095784, "bytes_per_launch": 2.3897e10},
-    "integrate": {"source": "paper_1810_06760_amd/csrc/k_integrate.hip", "sha256": "a6b636620063c52f",
-                  "beams": 49095784, "bytes_per_launch": 9.4622e9},
+                   "beams": 33044152, "bytes_per_launch": 2.3741e10},
+    "integrate": {"source": "paper_1810_06760_amd/csrc/k_integrate.hip", "sha256": "b905efd85e76b798",
+                  "beams": 33044152, "bytes_per_launch": 9.9295e9},
 }
 
 
