@@ -349,6 +349,17 @@ typedef struct {
   int gen_max;             /* layered media: interface generation cap (0: default 3)   */
   double child_cut;        /* layered media: children with |A_child| < child_cut |A_in|
                               are not made (0: default 1e-3; < 0: keep all)            */
+  int s_vector;            /* 1: frame-free S amplitudes: during each integrator launch
+                              an S beam carries its physical polarisation
+                              A = a_SV N_SV + a_SH N_SH, advanced by
+                              dA/dt = s A - (A . dPhat/dt) Phat (eq:amp_SV, eq:amp_SH
+                              with the frame rotation differentiated out) and
+                              projected orthogonal to P after each step; stored back
+                              in the beam's frame (axis switched near P) at the end of
+                              the launch.  The amplitude cutoff then uses |A|.  Agrees
+                              with the framed form to RK4 truncation; identical in a
+                              homogeneous medium.  Grid and homogeneous media only
+                              (FGA_EUNSUPPORTED for layered media).  0: framed.       */
 } fga_evolve_opts;
 
 typedef struct {

@@ -85,7 +85,7 @@ class ReceiversC(C.Structure):
 
 class EvolveOptsC(C.Structure):
     _fields_ = [("chunk", C.c_int), ("cutoff_abs", C.c_double), ("compact", C.c_int), ("batch", C.c_int64),
-                ("resort", C.c_int), ("gen_max", C.c_int), ("child_cut", C.c_double)]
+                ("resort", C.c_int), ("gen_max", C.c_int), ("child_cut", C.c_double), ("s_vector", C.c_int)]
 
 
 class EvolveStatsC(C.Structure):
@@ -488,15 +488,17 @@ def fga_decompose_point_force(medium: Medium, src: PointForceC, beams: BeamSet =
 def fga_evolve(medium: Medium, beams: BeamSet, dt: float, nsteps: int, receivers=None, eps: float = None,
                tau: float = 25.0, stride: int = 1, chunk: int = 0, cutoff_abs: float = 0.0, compact: bool = False,
                batch: int = 0, precision: int = FGA_FP64, seis=None, ws=None, resort: int = 0, gen_max: int = 0,
-               child_cut: float = 0.0, coords: int = FGA_COORDS_CARTESIAN):
+               child_cut: float = 0.0, coords: int = FGA_COORDS_CARTESIAN, s_vector: bool = False):
     """Step 2.  Returns (seis or None, stats dict).  receivers: (n,3) array;
     seis is complex [n][nsteps/stride][3] as a float64 tensor [n, ns, 3, 2].
     resort: steps between spatial reorderings (0 default, < 0 never).
     gen_max, child_cut: interface generation cap and child amplitude cut of
-    layered media (0: library defaults 3 and 1e-3; child_cut < 0 keeps all)."""
+    layered media (0: library defaults 3 and 1e-3; child_cut < 0 keeps all).
+    s_vector: frame-free S amplitudes (homogeneous and grid media)."""
     torch = _torch()
     L = lib()
-    opts = EvolveOptsC(chunk, cutoff_abs, 1 if compact else 0, batch, resort, gen_max, child_cut)
+    opts = EvolveOptsC(chunk, cutoff_abs, 1 if compact else 0, batch, resort, gen_max, child_cut,
+                       1 if s_vector else 0)
     rec = None
     xyz = None
     if receivers is not None:

@@ -435,6 +435,9 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
     if (rec->coords != FGA_COORDS_CARTESIAN && rec->coords != FGA_COORDS_SPHERICAL)
       return fail(FGA_EINVAL, "receiver coords must be FGA_COORDS_CARTESIAN or FGA_COORDS_SPHERICAL");
   }
+  const int s_vector = opts && opts->s_vector ? 1 : 0;
+  if (s_vector && dm.kind == FGA_MEDIUM_LAYERED)
+    return fail(FGA_EUNSUPPORTED, "frame-free S amplitudes (s_vector) are built for homogeneous and grid media");
   hipStream_t st = (hipStream_t)stream;
   EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
   // layered media step one step per launch and re-sort a beam set grown by
@@ -585,6 +588,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
       a.eps_emit = rec ? rec->eps : 1.0;
       a.cutoff_abs = cutoff;
       a.counters = ctr;
+      a.s_vector = s_vector;
       FGA_HIP(launch_integrate(dm, a, st));
       if (rec && ns > 0 && rec->n > 0) {
         PointsArgs pa{};

@@ -103,6 +103,7 @@ struct IntegrateArgs {
   double eps_emit;
   double cutoff_abs;
   unsigned long long *counters;  // [0] beam-steps, [1] culled, [2] quarantined
+  int s_vector;              // 1: frame-free S amplitudes (grid media)
 };
 hipError_t launch_integrate(const DevMedium &m, const IntegrateArgs &a, hipStream_t st);
 

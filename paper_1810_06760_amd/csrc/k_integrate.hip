@@ -17,12 +17,21 @@ namespace {
 using namespace rk;
 
 // Emission record of the current state: Q (3), P 128/(pi eps) (3), B = w e^{iS/eps} A (3 complex).
+// SV = 1: an S beam's state holds A itself (frame-free form).
+template <int SV = 0>
 __device__ __forceinline__ void emit_record(double *__restrict__ out, int64_t nb, int64_t j,
                                             const double *y, const double e[3], double wr, double wi,
                                             bool isS, double ieps)
 {
   double A[6];
-  if (!isS) {
+  if (SV && isS) {
+    A[0] = y[IA];
+    A[1] = y[IA + 1];
+    A[2] = y[IA + 2];
+    A[3] = y[IA + 3];
+    A[4] = y[IAZ];
+    A[5] = y[IAZ + 1];
+  } else if (!isS) {
     const double inp = 1.0 / sqrt(y[IP] * y[IP] + y[IP + 1] * y[IP + 1] + y[IP + 2] * y[IP + 2]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -74,6 +83,7 @@ __device__ __forceinline__ void emit_dead(double *__restrict__ out, int64_t nb, 
 
 // Whether the quantities a step's sample is formed from (Q, P, the
 // amplitudes and S) are finite.
+template <int SV = 0>
 __device__ __forceinline__ bool emitted_finite(const double *y)
 {
   bool ok = true;
@@ -81,10 +91,46 @@ __device__ __forceinline__ bool emitted_finite(const double *y)
   for (int d = 0; d < 3; ++d) ok = ok && isfinite(y[IQ + d]) && isfinite(y[IP + d]);
 #pragma unroll
   for (int t = 0; t < 4; ++t) ok = ok && isfinite(y[IA + t]);
+  if (SV) ok = ok && isfinite(y[IAZ]) && isfinite(y[IAZ + 1]);
   return ok && isfinite(y[IS]);
 }
 
-template <int MK>
+// Frame-free S amplitudes: (a_SV, a_SH) in the beam's frame -> A in y, and back.
+__device__ __forceinline__ void frame_to_vector(double *y, const double e[3])
+{
+  double nsh[3], nsv[3];
+  s_frame(y + IP, e, nsh, nsv);
+  const double a0r = y[IA], a0i = y[IA + 1], a1r = y[IA + 2], a1i = y[IA + 3];
+  y[IA] = a0r * nsv[0] + a1r * nsh[0];
+  y[IA + 1] = a0i * nsv[0] + a1i * nsh[0];
+  y[IA + 2] = a0r * nsv[1] + a1r * nsh[1];
+  y[IA + 3] = a0i * nsv[1] + a1i * nsh[1];
+  y[IAZ] = a0r * nsv[2] + a1r * nsh[2];
+  y[IAZ + 1] = a0i * nsv[2] + a1i * nsh[2];
+}
+
+// Back to the frame: the axis switched first if P has come within 10 degrees
+// of it (the rule of reframe_s), then (a_SV, a_SH) = (A . N_SV, A . N_SH).
+__device__ __forceinline__ void vector_to_frame(double *y, double e[3])
+{
+  const double np = sqrt(y[IP] * y[IP] + y[IP + 1] * y[IP + 1] + y[IP + 2] * y[IP + 2]);
+  const double pe = y[IP] * e[0] + y[IP + 1] * e[1] + y[IP + 2] * e[2];
+  if (fabs(pe) / np > COS10) {
+    const bool was_z = e[2] != 0.0 && e[0] == 0.0 && e[1] == 0.0;
+    e[0] = was_z ? 1.0 : 0.0;
+    e[1] = 0.0;
+    e[2] = was_z ? 0.0 : 1.0;
+  }
+  double nsh[3], nsv[3];
+  s_frame(y + IP, e, nsh, nsv);
+  const double Ar[3] = {y[IA], y[IA + 2], y[IAZ]}, Ai[3] = {y[IA + 1], y[IA + 3], y[IAZ + 1]};
+  y[IA] = Ar[0] * nsv[0] + Ar[1] * nsv[1] + Ar[2] * nsv[2];
+  y[IA + 1] = Ai[0] * nsv[0] + Ai[1] * nsv[1] + Ai[2] * nsv[2];
+  y[IA + 2] = Ar[0] * nsh[0] + Ar[1] * nsh[1] + Ar[2] * nsh[2];
+  y[IA + 3] = Ai[0] * nsh[0] + Ai[1] * nsh[1] + Ai[2] * nsh[2];
+}
+
+template <int MK, int SV = 0>
 __device__ __forceinline__ void integrate_body(const DevMedium &med, const IntegrateArgs &a)
 {
   const int64_t i = a.beg + (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -197,10 +243,15 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
       const int layer = a.i32[FGA_LAYER * cap + i];
       const int sp = br == 0 ? 0 : 1;
       const bool isS = br != 0;
-      double y[NS];
+      double y[nstate<SV>()];
 #pragma unroll
       for (int f = 0; f < NS; ++f) y[f] = F[f * cap + i];
       double e[3] = {F[(FGA_E + 0) * cap + i], F[(FGA_E + 1) * cap + i], F[(FGA_E + 2) * cap + i]};
+      if (SV) {
+        y[nstate<SV>() - 2] = 0.0;
+        y[nstate<SV>() - 1] = 0.0;
+        if (isS) frame_to_vector(y, e);
+      }
       const double wr = F[FGA_W_RE * cap + i], wi = F[FGA_W_IM * cap + i];
       const double dt = a.dt;
       const double ieps = 1.0 / a.eps_emit;
@@ -215,18 +266,22 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
       }
       for (int s = 0; s < a.nsteps; ++s) {
         if (live) {
-          if constexpr (MK == MK_GRID || MK == MK_GRID3) rk4_step<MK>(med, sp, layer, sg, isS, e, y, dt, &blk);
+          if constexpr (MK == MK_GRID || MK == MK_GRID3) rk4_step<MK, SV>(med, sp, layer, sg, isS, e, y, dt, &blk);
           else rk4_step_pc<MK>(med, sp, layer, sg, isS, y, dt);  // grad c = 0
-          if (isS) reframe_s(y, e);
+          if (isS && !SV) reframe_s(y, e);
           ++steps_done;
-          if (!emitted_finite(y)) {
+          if (!emitted_finite<SV>(y)) {
             live = false;
             flags = FGA_FLAG_QUARANTINED;
             quar = 1;
           } else if (a.cutoff_abs > 0.0) {
             const double m0 = y[IA] * y[IA] + y[IA + 1] * y[IA + 1];
-            const double m1 = y[IA + 2] * y[IA + 2] + y[IA + 3] * y[IA + 3];
-            if (wabs * sqrt(m0 > m1 ? m0 : m1) < a.cutoff_abs) {
+            double m1 = y[IA + 2] * y[IA + 2] + y[IA + 3] * y[IA + 3];
+            // frame-free S: the magnitude of the polarisation vector
+            const double mm = (SV && isS) ? m0 + m1 + y[nstate<SV>() - 2] * y[nstate<SV>() - 2] +
+                                                y[nstate<SV>() - 1] * y[nstate<SV>() - 1]
+                                          : (m0 > m1 ? m0 : m1);
+            if (wabs * sqrt(mm) < a.cutoff_abs) {
               live = false;
               flags = 0;
               culled = 1;
@@ -235,11 +290,12 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
         }
         if (a.stride && (a.step0 + s + 1) % a.stride == 0) {
           double *rec = a.emit + (int64_t)((a.step0 + s + 1) / a.stride - 1 - first_emit) * 12 * nb;
-          if (live) emit_record(rec, nb, j, y, e, wr, wi, isS, ieps);
+          if (live) emit_record<SV>(rec, nb, j, y, e, wr, wi, isS, ieps);
           else emit_dead(rec, nb, j);
         }
       }
       {
+      if (SV && isS) vector_to_frame(y, e);
       if (live) {
         bool finite = true;
 #pragma unroll
@@ -273,10 +329,10 @@ __device__ __forceinline__ void integrate_body(const DevMedium &med, const Integ
   }
 }
 
-template <int MK>
+template <int MK, int SV = 0>
 __global__ __launch_bounds__(256) void k_integrate(DevMedium med, IntegrateArgs a)
 {
-  integrate_body<MK>(med, a);
+  integrate_body<MK, SV>(med, a);
 }
 
 // One step of every beam in a layered medium, the interface step's cadence
@@ -532,7 +588,11 @@ hipError_t launch_integrate(const DevMedium &m, const IntegrateArgs &a, hipStrea
   switch (m.kind) {
   case FGA_MEDIUM_HOMOGENEOUS: hipLaunchKernelGGL(k_integrate<MK_HOMOG>, blocks, 256, 0, st, m, a); break;
   case FGA_MEDIUM_GRID:
-    if (m.smooth) hipLaunchKernelGGL(k_integrate<MK_GRID3>, blocks, 256, 0, st, m, a);
+    // frame-free S amplitudes: a variant of the grid-medium kernels (in a
+    // homogeneous medium P is constant and the two forms are one)
+    if (m.smooth && a.s_vector) hipLaunchKernelGGL((k_integrate<MK_GRID3, 1>), blocks, 256, 0, st, m, a);
+    else if (m.smooth) hipLaunchKernelGGL(k_integrate<MK_GRID3>, blocks, 256, 0, st, m, a);
+    else if (a.s_vector) hipLaunchKernelGGL((k_integrate<MK_GRID, 1>), blocks, 256, 0, st, m, a);
     else hipLaunchKernelGGL(k_integrate<MK_GRID>, blocks, 256, 0, st, m, a);
     break;
   default:

@@ -9,7 +9,10 @@
 //     omega = dN_SH/dt . N_SV = sigma (P.e) e.(grad c x P)/|e x P|^2  (eq:amp_SV, eq:amp_SH)
 //   dS/dt = P . dQ/dt - sigma c |P|
 // tr(Z^{-1} dZ/dt) is formed as (sum_ij cof(Z)_ij dZ_ij) / det Z, so no
-// matrix inverse is built.
+// matrix inverse is built.  Frame-free S amplitudes (SV = 1): the physical
+// polarisation A = a_SV N_SV + a_SH N_SH is advanced instead, by
+//   dA/dt = s A - (A . dPhat/dt) Phat,  dPhat/dt = (dP/dt - Phat (Phat . dP/dt))/|P|,
+// which is the framed system with the frame's rotation differentiated out.
 #pragma once
 
 #include "device_common.h"
@@ -19,12 +22,15 @@ namespace rk {
 
 constexpr int NS = 47;
 enum { IQ = 0, IP = 3, IZQR = 6, IZQI = 15, IZPR = 24, IZPI = 33, IA = 42, IS = 46 };
+// frame-free S state: A_x at IA, IA+1, A_y at IA+2, IA+3, A_z at IAZ, IAZ+1
+constexpr int IAZ = 47;
+template <int SV> constexpr int nstate() { return SV ? 49 : NS; }
 constexpr double COS10 = 0.98480775301220805936;  // cos(10 degrees)
 
 // One RK4 stage: k = f(yt); acc += wacc*k; yt <- y + cnext*k in place.  The
 // derivative is folded in as soon as each group of components is complete,
 // row by row for dzQ/dzP, so the live state stays at y, acc and yt.
-template <int MK>
+template <int MK, int SV = 0>
 __device__ __forceinline__ void stage(const DevMedium &med, int sp, int layer, double sg, bool isS,
                                       const double e[3], const double *__restrict__ y, double *__restrict__ yt,
                                       double *__restrict__ acc, double wacc, double cnext,
@@ -105,8 +111,21 @@ __device__ __forceinline__ void stage(const DevMedium &med, int sp, int layer, d
   const double tri = (Ti * detr - Tr * deti) * idd;
   const double sr = sg * (g[0] * ph[0] + g[1] * ph[1] + g[2] * ph[2]) + 0.5 * trr;
   const double si = 0.5 * tri;
-  double ka[4];
-  {
+  double ka[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (SV && isS) {
+    // parallel transport of A: dPhat/dt from dP/dt = -sigma |P| grad c
+    const double dq0 = -sg * g[0], dq1 = -sg * g[1], dq2 = -sg * g[2];   // (dP/dt)/|P|
+    const double pd = ph[0] * dq0 + ph[1] * dq1 + ph[2] * dq2;
+    const double dph[3] = {dq0 - ph[0] * pd, dq1 - ph[1] * pd, dq2 - ph[2] * pd};
+    const double Ar[3] = {yt[IA], yt[IA + 2], yt[IAZ]}, Ai[3] = {yt[IA + 1], yt[IA + 3], yt[IAZ + 1]};
+    const double adr = Ar[0] * dph[0] + Ar[1] * dph[1] + Ar[2] * dph[2];
+    const double adi = Ai[0] * dph[0] + Ai[1] * dph[1] + Ai[2] * dph[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ka[2 * c] = sr * Ar[c] - si * Ai[c] - adr * ph[c];
+      ka[2 * c + 1] = sr * Ai[c] + si * Ar[c] - adi * ph[c];
+    }
+  } else {
     const double a0r = yt[IA], a0i = yt[IA + 1], a1r = yt[IA + 2], a1i = yt[IA + 3];
     if (!isS) {
       ka[0] = sr * a0r - si * a0i;
@@ -134,8 +153,8 @@ __device__ __forceinline__ void stage(const DevMedium &med, int sp, int layer, d
   kr[6] = P0 * kr[0] + P1 * kr[1] + P2 * kr[2] - sc * np;
   const int fr[7] = {IQ, IQ + 1, IQ + 2, IP, IP + 1, IP + 2, IS};
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int f = IA + t;
+  for (int t = 0; t < (SV ? 6 : 4); ++t) {
+    const int f = t < 4 ? IA + t : IAZ + t - 4;
     acc[f] += wacc * ka[t];
     yt[f] = y[f] + cnext * ka[t];
   }
@@ -179,22 +198,38 @@ __device__ __forceinline__ void reframe_s(double *y, double e[3]) { reframe_s(y 
 
 // One classic RK4 step of size dt in place, y' = y + dt/6 (k1 + 2 k2 + 2 k3 + k4);
 // the four stages run as a loop so that only y, acc and the stage input stay live.
-template <int MK>
+// SV = 1: frame-free S amplitudes (y holds nstate<1>() values); after the
+// step A is projected on the plane orthogonal to the new P, which the exact
+// solution never leaves (the projection removes the step's truncation drift).
+template <int MK, int SV = 0>
 __device__ __forceinline__ void rk4_step(const DevMedium &med, int sp, int layer, double sg, bool isS,
                                          const double e[3], double *y, double dt, const MedBlock *blk = nullptr)
 {
-  double acc[NS], yt[NS];
+  constexpr int N = nstate<SV>();
+  double acc[N], yt[N];
 #pragma unroll
-  for (int f = 0; f < NS; ++f) { yt[f] = y[f]; acc[f] = 0.0; }
+  for (int f = 0; f < N; ++f) { yt[f] = y[f]; acc[f] = 0.0; }
   const double h2 = 0.5 * dt, h6 = dt / 6.0;
 #pragma nounroll
   for (int st = 0; st < 4; ++st) {
     const double wacc = (st == 0 || st == 3) ? 1.0 : 2.0;
     const double cnext = st == 2 ? dt : (st == 3 ? 0.0 : h2);
-    stage<MK>(med, sp, layer, sg, isS, e, y, yt, acc, wacc, cnext, blk);
+    stage<MK, SV>(med, sp, layer, sg, isS, e, y, yt, acc, wacc, cnext, blk);
   }
 #pragma unroll
-  for (int f = 0; f < NS; ++f) y[f] += h6 * acc[f];
+  for (int f = 0; f < N; ++f) y[f] += h6 * acc[f];
+  if (SV && isS) {
+    const double inp = 1.0 / sqrt(y[IP] * y[IP] + y[IP + 1] * y[IP + 1] + y[IP + 2] * y[IP + 2]);
+    const double ph[3] = {y[IP] * inp, y[IP + 1] * inp, y[IP + 2] * inp};
+    const double apr = y[IA] * ph[0] + y[IA + 2] * ph[1] + y[IAZ] * ph[2];
+    const double api = y[IA + 1] * ph[0] + y[IA + 3] * ph[1] + y[IAZ + 1] * ph[2];
+    y[IA] -= apr * ph[0];
+    y[IA + 2] -= apr * ph[1];
+    y[IAZ] -= apr * ph[2];
+    y[IA + 1] -= api * ph[0];
+    y[IA + 3] -= api * ph[1];
+    y[IAZ + 1] -= api * ph[2];
+  }
 }
 
 // The pieces of the classic RK4 step where grad c = 0 (a homogeneous medium,

@@ -1,0 +1,94 @@
+"""GPU parity of the frame-free S amplitudes (fga_evolve_opts.s_vector): S
+beams advanced as the physical polarisation vector A by parallel transport
+(eq:amp_SV, eq:amp_SH with the frame rotation differentiated out), against
+the oracle's frame-free evolution (oracle.evolve(..., s_vector=True)), on
+the same seeded beams:
+
+  - beam states and physical polarisations after RK4 evolution in trilinear
+    and C^2 gridded media that bend the rays (launches of 37 steps: the
+    library returns A to the frame at each launch end, the oracle once);
+  - seismograms sampled during the evolution (records formed from A);
+  - in a homogeneous medium the frame-free and framed forms coincide;
+  - layered media refuse the option.
+
+Bar: relative L2 <= 1e-10 (S: 1e-12 absolute).
+"""
+import numpy as np
+import pytest
+
+import fga_inputs as fi
+import oracle as om
+from test_gpu_parity import RTOL, compare_states, fga, oracle_to_dict, rel_l2, say
+from test_gpu_smooth_grid import fields, random_beams
+
+pytestmark = pytest.mark.gpu
+
+
+def media(smooth):
+    m = fga()
+    ms, cp, cs = fields((24, 20, 28), 33)
+    return (om.grid(cp, ms, cs_nodes=cs, smooth=smooth), m.Medium.grid(cp, ms, cs_nodes=cs, smooth=smooth))
+
+
+@pytest.mark.parametrize("smooth", [False, True])
+def test_svec_evolve_parity(smooth):
+    m = fga()
+    say("frame-free S evolve", smooth)
+    mo, mg = media(smooth)
+    ob = random_beams(600, -0.2, 1.2, 17)
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    m.fga_evolve(mg, bs, 2e-3, 120, chunk=37, s_vector=True)
+    ref = ob.copy()
+    om.evolve(mo, ref, 2e-3, 120, s_vector=True)
+    compare_states(bs.export(), ref)
+    # and it differs from the framed evolution only at RK4 truncation
+    fr = ob.copy()
+    om.evolve(mo, fr, 2e-3, 120)
+    d = rel_l2(om.amplitude_vectors(fr), om.amplitude_vectors(ref))
+    assert 0 < d < 1e-7, d
+
+
+def test_svec_seismogram_parity():
+    m = fga()
+    say("frame-free S seismograms")
+    mo, mg = media(True)
+    ob = random_beams(500, 0.3, 0.7, 19)
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    rec = fi.uniform_points(11, fi.rng(3, 5), 0.3, 0.7)
+    eps, tau, nsteps, dt, stride = 1.0 / 32, 25.0, 40, 2e-3, 5
+    seis, _ = m.fga_evolve(mg, bs, dt, nsteps, receivers=rec, eps=eps, tau=tau, stride=stride, s_vector=True)
+    ref = np.zeros((len(rec), nsteps // stride, 3), dtype=np.complex128)
+    cur = ob.copy()
+    for k in range(nsteps // stride):
+        om.evolve(mo, cur, dt, stride, s_vector=True)
+        ref[:, k, :], _ = om.sum_points(cur, rec, eps, tau)
+    assert np.abs(ref).max() > 0
+    assert rel_l2(m.to_complex(seis), ref) <= RTOL
+
+
+def test_svec_homogeneous_equals_framed():
+    m = fga()
+    say("frame-free S homogeneous")
+    mg = m.Medium.homogeneous(np.sqrt(3.0), 1.0)
+    ob = random_beams(300, 0.0, 1.0, 23)
+    a, b = m.BeamSet(len(ob)), m.BeamSet(len(ob))
+    a.load(oracle_to_dict(ob))
+    b.load(oracle_to_dict(ob))
+    m.fga_evolve(mg, a, 5e-3, 50, s_vector=True)
+    m.fga_evolve(mg, b, 5e-3, 50)
+    ga, gb = a.export(), b.export()
+    for k in ("Q", "P", "ZQ", "ZP", "a", "S", "e"):
+        assert np.array_equal(ga[k], gb[k]), k
+
+
+def test_svec_layered_is_refused():
+    m = fga()
+    mg = m.Medium.layered(0, [0.5], [1.7, 2.0], [1.0, 1.2], [1.0, 1.1])
+    ob = random_beams(10, 0.1, 0.3, 29)
+    ob["layer"] = 0
+    bs = m.BeamSet(100)
+    bs.load(oracle_to_dict(ob))
+    with pytest.raises(RuntimeError, match="s_vector"):
+        m.fga_evolve(mg, bs, 5e-3, 2, s_vector=True)
