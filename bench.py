@@ -243,7 +243,8 @@ def roofline(tot, prof, medium_kind, default_workload=False):
         return None, name
     achieved = work[name] / (ms * 1e-3)
     return {"bound": "alu", "kernel": name, "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic_for(name, default_workload, tot["beams"]),
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+            "traffic": traffic_for(name, default_workload, tot.get("beams")),
             "launches": launches, "avg_launch_ms": ms / launches,
             "flop_per_unit": FLOP_BEAM_STEP[medium_kind] if name == "integrate" else FLOP_POINT_EVAL,
             "units_per_launch": (tot["beam_steps"] if name == "integrate" else tot["ev_rec"]) / launches}, name
