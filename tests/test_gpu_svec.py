@@ -92,3 +92,28 @@ def test_svec_layered_is_refused():
     bs.load(oracle_to_dict(ob))
     with pytest.raises(RuntimeError, match="s_vector"):
         m.fga_evolve(mg, bs, 5e-3, 2, s_vector=True)
+
+
+def test_svec_with_merged_beams_in_the_c2_medium():
+    """The three options together: merged S beams decomposed in the C^2
+    medium and evolved frame-free with receivers, against the oracle's merge
+    of its own decomposition, evolved frame-free and summed."""
+    from test_gpu_parity import small_c2
+    m = fga()
+    say("frame-free S, merged beams, C2 medium")
+    w = small_c2(nq=4, np_=2, ny=16, nmed=24)
+    w.medium_smooth = True
+    ob = om.merge_s_beams(om.decompose(w), w.qmesh.count * w.pmesh.count)
+    mo, mg = om.medium_for(w), m.medium_for(w)
+    bs = m.fga_decompose(mg, m.mesh_for(w, merge_s=True), w.f)
+    assert bs.count == len(ob)
+    rec = fi.uniform_points(9, fi.rng(2, 91), 0.3, 0.7)
+    nsteps, dt, stride = 40, 2e-3, 5
+    seis, _ = m.fga_evolve(mg, bs, dt, nsteps, receivers=rec, eps=w.eps, tau=w.tau, stride=stride, s_vector=True)
+    ref = np.zeros((len(rec), nsteps // stride, 3), dtype=np.complex128)
+    for k in range(nsteps // stride):
+        om.evolve(mo, ob, dt, stride, s_vector=True)
+        ref[:, k, :], _ = om.sum_points(ob, rec, w.eps, w.tau)
+    assert np.abs(ref).max() > 0
+    assert rel_l2(m.to_complex(seis), ref) <= RTOL
+    compare_states(bs.export(), ob)
