@@ -104,6 +104,38 @@ typedef struct {
   int64_t *lineage;   /* device, capacity int64                                  */
 } fga_beams;
 
+/* Counts over the beams [0, count) of a set (flags, branch and generation
+ * planes), for monitoring a run and checking a checkpoint. */
+typedef struct {
+  int64_t count;          /* beams in [0, count)                                      */
+  int64_t alive;          /* FGA_FLAG_ALIVE set                                       */
+  int64_t quarantined;    /* FGA_FLAG_QUARANTINED set                                 */
+  int64_t by_branch[3];   /* alive beams per branch (0 P, 1 SH or merged S, 2 SV)     */
+  int64_t children;       /* alive beams made at an interface (generation > 0)        */
+} fga_beams_stats;
+
+#define FGA_BEAMS_INFO_WORKSPACE 64   /* bytes of device workspace fga_beams_info needs */
+
+/* Fills *out (synchronises `stream`).  workspace: device, at least
+ * FGA_BEAMS_INFO_WORKSPACE bytes, 8-byte aligned.
+ * Errors: FGA_EINVAL (NULL or inconsistent set, short workspace). */
+fga_status fga_beams_info(const fga_beams *beams, fga_beams_stats *out, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/* Copies the beams [0, count) out of a set, plane by plane: f64[f * count + i]
+ * (f < FGA_NF64), i32[f * count + i] (f < FGA_NI32), lineage[i].  The
+ * destinations may be host or device memory (any of them NULL: that part is
+ * not copied); the layout is the planes' own, so a checkpoint is the three
+ * arrays and the count.  Synchronises `stream`.  Errors: FGA_EINVAL. */
+fga_status fga_beams_export(const fga_beams *beams, double *f64, int32_t *i32, int64_t *lineage, void *stream);
+
+/* Sets a set's beams [0, n) from arrays in the layout fga_beams_export writes
+ * (host or device; count = n, so the rest of the planes is unused).
+ * Synchronises `stream`.  Errors: FGA_EINVAL (NULL arrays), FGA_ECAPACITY
+ * (n > capacity). */
+fga_status fga_beams_import(fga_beams *beams, int64_t n, const double *f64, const int32_t *i32,
+                            const int64_t *lineage, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Media (Sec. 2, eq:ps_speed; Sec. 3.1 for layers)                          */
 /* ------------------------------------------------------------------------ */

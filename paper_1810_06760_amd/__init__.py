@@ -45,7 +45,7 @@ EXPORTED = ["fga_last_error", "fga_version", "fga_medium_grid_table_bytes", "fga
             "fga_server_submit", "fga_server_poll", "fga_server_status", "fga_server_destroy",
             "fga_point_source_candidates", "fga_decompose_point_source_workspace_bytes",
             "fga_decompose_point_source", "fga_point_force_candidates", "fga_decompose_point_force_workspace_bytes",
-            "fga_decompose_point_force"]
+            "fga_decompose_point_force", "fga_beams_info", "fga_beams_export", "fga_beams_import"]
 FGA_K_INTEGRATE, FGA_K_SUM_POINTS, FGA_K_GRID_TILE, FGA_K_FBI_GEMM = 0, 1, 2, 3
 KERNEL_NAMES = {0: "integrate", 1: "sum_points", 2: "grid_tile", 3: "fbi_gemm"}
 
@@ -163,6 +163,12 @@ def lib():
         L.fga_reconstruct_grid.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp, C.c_int, vp, vp, sz, vp, vp]
         L.fga_reconstruct_grid_add.restype = st
         L.fga_reconstruct_grid_add.argtypes = L.fga_reconstruct_grid.argtypes
+        L.fga_beams_info.restype = st
+        L.fga_beams_info.argtypes = [vp, vp, vp, sz, vp]
+        L.fga_beams_export.restype = st
+        L.fga_beams_export.argtypes = [vp, vp, vp, vp, vp]
+        L.fga_beams_import.restype = st
+        L.fga_beams_import.argtypes = [vp, i64, vp, vp, vp, vp]
         L.fga_profile_enable.restype = st
         L.fga_profile_enable.argtypes = [C.c_int]
         L.fga_profile_read.restype = st
@@ -249,6 +255,14 @@ def _complex_dev(a):
 # beams
 # ---------------------------------------------------------------------------
 
+class BeamsStatsC(C.Structure):
+    _fields_ = [("count", C.c_int64), ("alive", C.c_int64), ("quarantined", C.c_int64),
+                ("by_branch", C.c_int64 * 3), ("children", C.c_int64)]
+
+
+FGA_BEAMS_INFO_WORKSPACE = 64
+
+
 class BeamSet:
     """Structure-of-arrays beam planes in device memory (caller-owned)."""
 
@@ -264,14 +278,26 @@ class BeamSet:
     def count(self) -> int:
         return int(self.c.count)
 
+    def info(self) -> dict:
+        """fga_beams_info: counts over the beams [0, count)."""
+        torch = _torch()
+        ws = torch.empty(FGA_BEAMS_INFO_WORKSPACE // 8, dtype=torch.float64, device="cuda")
+        out = BeamsStatsC()
+        _check(lib().fga_beams_info(C.byref(self.c), C.byref(out), ws.data_ptr(), FGA_BEAMS_INFO_WORKSPACE,
+                                    _stream()))
+        return {"count": out.count, "alive": out.alive, "quarantined": out.quarantined,
+                "by_branch": list(out.by_branch), "children": out.children}
+
     def export(self, index=None) -> dict:
-        """Host copy of the live beams (or of the slots in `index`, a device
-        int64 tensor): dict of numpy arrays."""
+        """Host copy of the live beams (fga_beams_export; or of the slots in
+        `index`, a device int64 tensor): dict of numpy arrays."""
         if index is None:
             n = self.count
-            F = self.f64[:, :n].cpu().numpy()
-            I = self.i32[:, :n].cpu().numpy()
-            lin = self.lineage[:n].cpu().numpy().copy()
+            F = np.empty((FGA_NF64, n))
+            I = np.empty((FGA_NI32, n), dtype=np.int32)
+            lin = np.empty(n, dtype=np.int64)
+            _check(lib().fga_beams_export(C.byref(self.c), F.ctypes.data, I.ctypes.data, lin.ctypes.data,
+                                          _stream()))
         else:
             n = int(index.numel())
             F = self.f64[:, index].cpu().numpy()
@@ -289,8 +315,8 @@ class BeamSet:
         }
 
     def load(self, d: dict) -> None:
-        """Set the live beams from host arrays (same keys as export())."""
-        torch = _torch()
+        """Set the live beams from host arrays (same keys as export();
+        fga_beams_import)."""
         n = len(d["Q"])
         if n > self.capacity:
             raise ValueError("capacity %d < %d beams" % (self.capacity, n))
@@ -311,10 +337,9 @@ class BeamSet:
         I[FGA_LAYER] = d.get("layer", 0)
         I[FGA_GEN] = d.get("gen", 0)
         I[FGA_FLAGS] = d.get("flags", FGA_FLAG_ALIVE)
-        self.f64[:, :n] = torch.from_numpy(F).to("cuda")
-        self.i32[:, :n] = torch.from_numpy(I).to("cuda")
-        self.lineage[:n] = torch.from_numpy(np.asarray(d["lineage"], dtype=np.int64)).to("cuda")
-        self.c.count = n
+        lin = np.ascontiguousarray(d["lineage"], dtype=np.int64)
+        _check(lib().fga_beams_import(C.byref(self.c), n, F.ctypes.data, I.ctypes.data, lin.ctypes.data,
+                                      _stream()))
 
 
 # ---------------------------------------------------------------------------

@@ -223,6 +223,77 @@ static fga_status check_mesh(const fga_mesh *m)
 
 using namespace fga;
 
+fga_status fga_beams_info(const fga_beams *beams, fga_beams_stats *out, void *workspace, size_t workspace_bytes,
+                          void *stream)
+{
+  fga_status s;
+  if ((s = check_beams(beams)) != FGA_OK) return s;
+  if (!out) return fail(FGA_EINVAL, "stats output is NULL");
+  if (!workspace || workspace_bytes < FGA_BEAMS_INFO_WORKSPACE || ((uintptr_t)workspace & 7))
+    return fail(FGA_EINVAL, "fga_beams_info needs %d bytes of 8-byte aligned device workspace",
+                FGA_BEAMS_INFO_WORKSPACE);
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long *ctr = static_cast<unsigned long long *>(workspace);
+  FGA_HIP(launch_beams_info(beams, ctr, st));
+  unsigned long long h[6];
+  FGA_HIP(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, st));
+  FGA_HIP(hipStreamSynchronize(st));
+  out->count = beams->count;
+  out->alive = (int64_t)h[0];
+  out->quarantined = (int64_t)h[1];
+  for (int b = 0; b < 3; ++b) out->by_branch[b] = (int64_t)h[2 + b];
+  out->children = (int64_t)h[5];
+  return FGA_OK;
+}
+
+// Plane-by-plane copies between a beam set and [plane][n] arrays (host or
+// device: hipMemcpyDefault lets the runtime tell them apart).
+template <typename T>
+static hipError_t copy_planes(T *dst, size_t dpitch, const T *src, size_t spitch, int64_t n, int planes,
+                              hipStream_t st)
+{
+  // one copy per plane (a 2-D copy's pitch would be limited to 2^31 bytes)
+  for (int f = 0; f < planes && n > 0; ++f) {
+    const hipError_t e =
+        hipMemcpyAsync(dst + f * dpitch, src + f * spitch, (size_t)n * sizeof(T), hipMemcpyDefault, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+fga_status fga_beams_export(const fga_beams *beams, double *f64, int32_t *i32, int64_t *lineage, void *stream)
+{
+  fga_status s;
+  if ((s = check_beams(beams)) != FGA_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = beams->count;
+  const size_t cap = (size_t)beams->capacity;
+  if (f64) FGA_HIP(copy_planes(f64, (size_t)n, beams->f64, cap, n, FGA_NF64, st));
+  if (i32) FGA_HIP(copy_planes(i32, (size_t)n, beams->i32, cap, n, FGA_NI32, st));
+  if (lineage) FGA_HIP(copy_planes(lineage, (size_t)n, beams->lineage, cap, n, 1, st));
+  FGA_HIP(hipStreamSynchronize(st));
+  return FGA_OK;
+}
+
+fga_status fga_beams_import(fga_beams *beams, int64_t n, const double *f64, const int32_t *i32,
+                            const int64_t *lineage, void *stream)
+{
+  fga_status s;
+  if ((s = check_beams(beams)) != FGA_OK) return s;
+  if (n < 0) return fail(FGA_EINVAL, "n < 0");
+  if (n > beams->capacity) return fail(FGA_ECAPACITY, "%lld beams do not fit a capacity of %lld", (long long)n,
+                                       (long long)beams->capacity);
+  if (n > 0 && (!f64 || !i32 || !lineage)) return fail(FGA_EINVAL, "import arrays are NULL");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t cap = (size_t)beams->capacity;
+  FGA_HIP(copy_planes(beams->f64, cap, f64, (size_t)n, n, FGA_NF64, st));
+  FGA_HIP(copy_planes(beams->i32, cap, i32, (size_t)n, n, FGA_NI32, st));
+  FGA_HIP(copy_planes(beams->lineage, cap, lineage, (size_t)n, n, 1, st));
+  FGA_HIP(hipStreamSynchronize(st));
+  beams->count = n;
+  return FGA_OK;
+}
+
 extern "C" {
 
 const char *fga_last_error(void) { return g_err.c_str(); }

@@ -193,6 +193,8 @@ fga_status sort_beams_spatial(fga_beams *b, Arena &ar, hipStream_t st, bool size
 
 // stable compaction of the beam set by FLAGS & ALIVE
 fga_status compact_beams(fga_beams *b, Arena &ar, hipStream_t st, bool size_only, size_t *need);
+// counts for fga_beams_info into ctr[6] (device)
+hipError_t launch_beams_info(const fga_beams *b, unsigned long long *ctr, hipStream_t st);
 
 // grid summation
 fga_status grid_sum_impl(const fga_beams *b, double eps, double tau, const int n[3], const double lo[3],

@@ -77,6 +77,44 @@ __global__ __launch_bounds__(256) void k_scatter(const T *__restrict__ src, cons
 
 }  // namespace
 
+// Beam-set counts for fga_beams_info: ctr[0] alive, [1] quarantined, [2..4]
+// alive per branch, [5] alive children (generation > 0); one ballot per
+// wavefront and counter, one atomic per wavefront.
+__global__ __launch_bounds__(64) void k_zero_counters(unsigned long long *ctr, int n)
+{
+  if ((int)threadIdx.x < n) ctr[threadIdx.x] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_beams_info(const int32_t *__restrict__ i32, int64_t cap, int64_t n,
+                                                    unsigned long long *__restrict__ ctr)
+{
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int32_t flags = 0, br = -1, gen = 0;
+  if (i < n) {
+    flags = i32[FGA_FLAGS * cap + i];
+    br = i32[FGA_BRANCH * cap + i];
+    gen = i32[FGA_GEN * cap + i];
+  }
+  const bool alive = i < n && (flags & FGA_FLAG_ALIVE);
+  const bool pred[6] = {alive, i < n && (flags & FGA_FLAG_QUARANTINED) != 0, alive && br == 0, alive && br == 1,
+                        alive && br == 2, alive && gen > 0};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const unsigned long long m = __ballot(pred[k]);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(ctr + k, (unsigned long long)__popcll(m));
+  }
+}
+
+hipError_t launch_beams_info(const fga_beams *b, unsigned long long *ctr, hipStream_t st)
+{
+  hipLaunchKernelGGL(k_zero_counters, 1, 64, 0, st, ctr, 6);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || b->count <= 0) return e;
+  hipLaunchKernelGGL(k_beams_info, (unsigned)((b->count + 255) / 256), 256, 0, st, b->i32, b->capacity, b->count,
+                     ctr);
+  return hipGetLastError();
+}
+
 fga_status compact_beams(fga_beams *b, Arena &ar, hipStream_t st, bool size_only, size_t *need)
 {
   const int64_t n = b->count;

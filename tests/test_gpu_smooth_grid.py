@@ -166,3 +166,17 @@ def test_smooth_seismogram_parity():
         ref[:, k, :], _ = om.sum_points(ob, rec, w.eps, w.tau)
     assert np.abs(ref).max() > 0
     assert rel_l2(m.to_complex(seis), ref) <= RTOL
+
+
+def test_smooth_evolve_tiny_grid():
+    """A 3 x 4 x 5 node grid: the 4-node stencils wrap onto the same nodes
+    (periodic images), in the LDS block and in global memory alike."""
+    m = fga()
+    say("smooth evolve, tiny grid")
+    mo, mg = media((3, 4, 5), True)
+    ob = random_beams(300, -0.5, 1.5, 8)
+    bs = m.BeamSet(len(ob))
+    bs.load(oracle_to_dict(ob))
+    m.fga_evolve(mg, bs, 2e-3, 60, chunk=25)
+    om.evolve(mo, ob, 2e-3, 60)
+    compare_states(bs.export(), ob)
