@@ -33,7 +33,7 @@ _lib = None
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, OpenMP)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp"
+        tmp = "%s.%d.tmp" % (_LIB_PATH, os.getpid())   # one per process: parallel test workers
         subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
@@ -59,6 +59,8 @@ class Medium(C.Structure):
         ("x0", C.c_double * 3), ("amp", C.c_double), ("s", C.c_double), ("g", C.c_double * 3),
         ("nlayer", C.c_int), ("bound", C.c_double * 8),
         ("cpl", C.c_double * 8), ("csl", C.c_double * 8), ("rhol", C.c_double * 8), ("gradl", C.c_double * 8),
+        ("anom_amp", C.c_double * 8), ("anom_beta", C.c_double * 8), ("anom_x", (C.c_double * 3) * 8),
+        ("anom_w", (C.c_double * 3) * 8),
         ("surface", C.c_double),
     ]
 
@@ -222,11 +224,13 @@ def grid(cp_nodes: np.ndarray, mesh, cs_ratio: float = None, cs_nodes: np.ndarra
     return OracleMedium(m, keep=keep)
 
 
-def layered(geometry: int, bounds, cp, cs, rho, grad=None, surface=0.0) -> OracleMedium:
+def layered(geometry: int, bounds, cp, cs, rho, grad=None, surface=0.0, anomaly=None) -> OracleMedium:
     """Flat (geometry 0) or spherical (1) layers; grad: relative gradient per
     layer, c_b(x) = c_b,i (1 + grad[i] v(x)) with v = z or |x| (None: constant);
     surface > 0: a traction-free surface at z = surface above the last layer
-    (flat) or |x| = surface around layer 0 (spherical)."""
+    (flat) or |x| = surface around layer 0 (spherical); anomaly: {layer:
+    (amp, beta, centre (3), axis weights (3))}, c_b multiplied by
+    1 - amp exp(-beta sum_d w_d (x_d - centre_d)^2) in that layer."""
     m = Medium()
     m.kind, m.geometry = LAYERED, geometry
     m.nlayer = len(cp)
@@ -236,6 +240,10 @@ def layered(geometry: int, bounds, cp, cs, rho, grad=None, surface=0.0) -> Oracl
     m.rhol[:len(rho)] = list(rho)
     if grad is not None:
         m.gradl[:len(grad)] = list(grad)
+    for L, (amp, beta, x0, wts) in (anomaly or {}).items():
+        m.anom_amp[L], m.anom_beta[L] = float(amp), float(beta)
+        m.anom_x[L][:] = [float(v) for v in x0]
+        m.anom_w[L][:] = [float(v) for v in wts]
     m.surface = float(surface)
     m.cp, m.cs, m.rho = cp[0], cs[0], rho[0]
     return OracleMedium(m)

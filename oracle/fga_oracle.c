@@ -70,6 +70,11 @@ typedef struct {
   /* relative gradient of each layer: c_b(x) = c_b,i (1 + gradl[i] v(x)) with the level
      v = z (flat) or |x| (spherical); 0 for a constant layer                               */
   double gradl[OM_MAXL];
+  /* Gaussian anomaly of each layer (the low-velocity region of the crosswell model,
+     Sec. 4 eq:true_c): c_b(x) is multiplied by 1 - anom_amp[i] exp(-anom_beta[i] q),
+     q = sum_d anom_w[i][d] (x_d - anom_x[i][d])^2 (weights 0 drop an axis: the
+     model is invariant along it); anom_amp[i] = 0: none                               */
+  double anom_amp[OM_MAXL], anom_beta[OM_MAXL], anom_x[OM_MAXL][3], anom_w[OM_MAXL][3];
   /* > 0: a traction-free surface closing the outermost region (spherical: |x| = surface
      around layer 0; flat: z = surface above the last layer); 0: none                      */
   double surface;
@@ -212,20 +217,48 @@ void om_speed(const om_medium *m, int sp, int layer, const double x[3],
   case OM_LAYERED: {
     const double c0 = sp == 0 ? m->cpl[layer] : m->csl[layer];
     const double gm = m->gradl[layer];
-    if (gm == 0.0) {
-      *c = c0;
-      return;
+    *c = c0;
+    if (gm != 0.0) {
+      if (m->geometry == 1) {
+        /* c = c0 (1 + gm r): grad c = c0 gm x/r, Hess c = c0 gm (I - x x^T/r^2)/r */
+        const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        *c = c0 * (1.0 + gm * r);
+        for (int i = 0; i < 3; ++i) gc[i] = c0 * gm * x[i] / r;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) H[i][j] = c0 * gm * ((i == j ? 1.0 : 0.0) - x[i] * x[j] / (r * r)) / r;
+      } else {
+        *c = c0 * (1.0 + gm * x[2]);
+        gc[2] = c0 * gm;
+      }
     }
-    if (m->geometry == 1) {
-      /* c = c0 (1 + gm r): grad c = c0 gm x/r, Hess c = c0 gm (I - x x^T/r^2)/r */
-      const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-      *c = c0 * (1.0 + gm * r);
-      for (int i = 0; i < 3; ++i) gc[i] = c0 * gm * x[i] / r;
+    const double al = m->anom_amp[layer];
+    if (al != 0.0) {
+      /* c = g f with f = 1 - al E, E = exp(-beta q): the product rule for the
+       * gradient, f H_g + grad g (x) grad f + grad f (x) grad g + g H_f for the Hessian;
+       * grad f = al E beta 2 w d, H_f = al E (2 beta diag(w) - 4 beta^2 (w d)(w d)^T) */
+      const double be = m->anom_beta[layer];
+      double wd[3], q = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        const double dd = x[d] - m->anom_x[layer][d];
+        wd[d] = m->anom_w[layer][d] * dd;
+        q += wd[d] * dd;
+      }
+      const double E = exp(-be * q);
+      const double f = 1.0 - al * E;
+      double gf[3], Hf[3][3];
+      for (int i = 0; i < 3; ++i) gf[i] = al * E * be * 2.0 * wd[i];
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) H[i][j] = c0 * gm * ((i == j ? 1.0 : 0.0) - x[i] * x[j] / (r * r)) / r;
-    } else {
-      *c = c0 * (1.0 + gm * x[2]);
-      gc[2] = c0 * gm;
+        for (int j = 0; j < 3; ++j)
+          Hf[i][j] = al * E * ((i == j ? 2.0 * be * m->anom_w[layer][i] : 0.0) - 4.0 * be * be * wd[i] * wd[j]);
+      const double g = *c;
+      double gg[3], Hg[3][3];
+      for (int i = 0; i < 3; ++i) gg[i] = gc[i];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Hg[i][j] = H[i][j];
+      *c = g * f;
+      for (int i = 0; i < 3; ++i) gc[i] = f * gg[i] + g * gf[i];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) H[i][j] = f * Hg[i][j] + gg[i] * gf[j] + gf[i] * gg[j] + g * Hf[i][j];
     }
     return;
   }
@@ -1618,7 +1651,9 @@ int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t
       }
       double th = om_crossing_fraction(m, iface, y0.Q, b->Q);
       om_beam x = y0;
-      if (m->gradl[y0.layer] != 0.0) th = om_crossing_secant(m, &y0, iface, dt, th);
+      /* curved rays (a gradient or an anomaly in the layer): secant iterations */
+      if (m->gradl[y0.layer] != 0.0 || m->anom_amp[y0.layer] != 0.0)
+        th = om_crossing_secant(m, &y0, iface, dt, th);
       om_rk4_step(m, &x, th * dt);
       /* exactly onto the interface */
       double nrm[3] = {0.0, 0.0, 0.0};
