@@ -176,6 +176,14 @@ typedef struct {
      innermost spherical layer must be constant (|x| is not smooth at the centre);
      the speed must stay positive where beams go (not checked).                      */
   double gradl[FGA_MAX_LAYERS];
+  /* Gaussian anomaly per layer (the low-velocity region of the crosswell model,
+     Sec. 4 eq:true_c): in layer l the speeds are multiplied by
+     1 - anom_amp[l] exp(-anom_beta[l] sum_d anom_w[l][d] (x_d - anom_x[l][d])^2);
+     a weight 0 drops an axis (the model is invariant along it).  anom_amp[l] = 0:
+     none.  Rays in such a layer curve: the general step and the secant crossing of
+     gradient layers are used.  The factor must stay positive (not checked).          */
+  double anom_amp[FGA_MAX_LAYERS], anom_beta[FGA_MAX_LAYERS];
+  double anom_x[FGA_MAX_LAYERS][3], anom_w[FGA_MAX_LAYERS][3];
   /* > 0: a traction-free surface closing the outermost region, |x| = surface around
      layer 0 (geometry 1) or z = surface above the last layer (geometry 0): a beam
      reaching it is split into the reflected P and S beams of the free-surface

@@ -67,6 +67,8 @@ class MediumC(C.Structure):
                 ("two_fields", C.c_int), ("cs_ratio", C.c_double), ("geometry", C.c_int), ("nlayer", C.c_int),
                 ("bound", C.c_double * 8), ("cpl", C.c_double * 8), ("csl", C.c_double * 8),
                 ("rhol", C.c_double * 8), ("gradl", C.c_double * 8),
+                ("anom_amp", C.c_double * 8), ("anom_beta", C.c_double * 8), ("anom_x", (C.c_double * 3) * 8),
+                ("anom_w", (C.c_double * 3) * 8),
                 ("surface", C.c_double), ("smooth", C.c_int)]
 
 
@@ -386,11 +388,13 @@ class Medium:
         return Medium(m, keep=[table, cp, cs])
 
     @staticmethod
-    def layered(geometry: int, bounds, cp, cs, rho, grad=None, surface=0.0) -> "Medium":
+    def layered(geometry: int, bounds, cp, cs, rho, grad=None, surface=0.0, anomaly=None) -> "Medium":
         """Flat (geometry 0) or spherical (1) layers; grad: relative gradient
         per layer, c_b(x) = c_b,l (1 + grad[l] v(x)), v = z or |x| (None: constant);
         surface > 0: a traction-free surface at z = surface above the last layer
-        (flat) or |x| = surface around layer 0 (spherical)."""
+        (flat) or |x| = surface around layer 0 (spherical); anomaly: {layer:
+        (amp, beta, centre (3), axis weights (3))}, the layer's speeds times
+        1 - amp exp(-beta sum_d w_d (x_d - centre_d)^2)."""
         m = MediumC()
         m.kind, m.geometry, m.nlayer = FGA_MEDIUM_LAYERED, geometry, len(cp)
         m.bound[:len(bounds)] = list(bounds)
@@ -399,6 +403,10 @@ class Medium:
         m.rhol[:len(rho)] = list(rho)
         if grad is not None:
             m.gradl[:len(grad)] = list(grad)
+        for L, (amp, beta, x0, wts) in (anomaly or {}).items():
+            m.anom_amp[L], m.anom_beta[L] = float(amp), float(beta)
+            m.anom_x[L][:] = [float(v) for v in x0]
+            m.anom_w[L][:] = [float(v) for v in wts]
         m.surface = float(surface)
         m.cp, m.cs, m.rho = cp[0], cs[0], rho[0]
         return Medium(m)

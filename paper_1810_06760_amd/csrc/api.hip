@@ -122,9 +122,25 @@ fga_status make_dev_medium(const fga_medium *m, DevMedium *o)
       o->rhol[l] = m->rhol[l];
       o->gradl[l] = l < m->nlayer ? m->gradl[l] : 0.0;
       if (l < m->nlayer && m->gradl[l] != 0.0) o->any_grad = 1;
+      // a Gaussian anomaly curves the rays too: the same general step and crossing
+      o->anom_amp[l] = l < m->nlayer ? m->anom_amp[l] : 0.0;
+      o->anom_beta[l] = m->anom_beta[l];
+      for (int d = 0; d < 3; ++d) {
+        o->anom_x[l][d] = m->anom_x[l][d];
+        o->anom_w[l][d] = m->anom_w[l][d];
+      }
+      if (l < m->nlayer && m->anom_amp[l] != 0.0) o->any_grad = 1;
     }
-    for (int l = 0; l < m->nlayer; ++l)
+    for (int l = 0; l < m->nlayer; ++l) {
       if (!std::isfinite(m->gradl[l])) return fail(FGA_EINVAL, "layer %d has a non-finite gradient", l);
+      if (m->anom_amp[l] != 0.0) {
+        bool ok = std::isfinite(m->anom_amp[l]) && std::isfinite(m->anom_beta[l]) && m->anom_beta[l] >= 0.0;
+        for (int d = 0; d < 3; ++d)
+          ok = ok && std::isfinite(m->anom_x[l][d]) && std::isfinite(m->anom_w[l][d]) && m->anom_w[l][d] >= 0.0;
+        if (!ok)
+          return fail(FGA_EINVAL, "layer %d: the anomaly needs finite values, beta >= 0 and weights >= 0", l);
+      }
+    }
     if (m->geometry == 1 && m->gradl[m->nlayer - 1] != 0.0)
       return fail(FGA_EINVAL, "the innermost spherical layer must have a constant speed");
     o->surface = m->surface;

@@ -149,6 +149,33 @@ __device__ __forceinline__ void medium_eval(const DevMedium &m, int sp, int laye
         g[2] = c0 * gm;
       }
     }
+    const double al = m.anom_amp[layer];
+    if (al != 0.0) {
+      // times f = 1 - al E, E = exp(-beta q), q = sum_d w_d d_d^2: grad f = 2 al beta E w d,
+      // Hess f = al E (2 beta diag(w) - 4 beta^2 (w d)(w d)^T); the product rule for c f
+      const double be = m.anom_beta[layer];
+      double wd[3], q = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double dd = x[d] - m.anom_x[layer][d];
+        wd[d] = m.anom_w[layer][d] * dd;
+        q += wd[d] * dd;
+      }
+      const double E = exp(-be * q);
+      const double f = 1.0 - al * E;
+      const double k1 = 2.0 * al * be * E, k2 = 4.0 * al * be * be * E;
+      const double gf[3] = {k1 * wd[0], k1 * wd[1], k1 * wd[2]};
+      const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int i = ii[t], j = jj[t];
+        const double hf = (i == j ? al * E * 2.0 * be * m.anom_w[layer][i] : 0.0) - k2 * wd[i] * wd[j];
+        H[t] = f * H[t] + g[i] * gf[j] + gf[i] * g[j] + c * hf;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) g[d] = f * g[d] + c * gf[d];
+      c *= f;
+    }
   } else if constexpr (MK == MK_GRID3) {
     const double *cf = m.coef;
     double scale = 1.0;

@@ -79,6 +79,8 @@ struct DevMedium {
   double bound[FGA_MAX_LAYERS];
   double cpl[FGA_MAX_LAYERS], csl[FGA_MAX_LAYERS], rhol[FGA_MAX_LAYERS];
   double gradl[FGA_MAX_LAYERS];  // relative speed gradient per layer (0: constant)
+  double anom_amp[FGA_MAX_LAYERS], anom_beta[FGA_MAX_LAYERS];  // Gaussian anomaly per layer (0: none)
+  double anom_x[FGA_MAX_LAYERS][3], anom_w[FGA_MAX_LAYERS][3];
   int any_grad;                  // some layer has a gradient: the general RK4 step
   double surface;                // > 0: traction-free surface closing the outermost region
 };

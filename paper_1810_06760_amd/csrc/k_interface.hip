@@ -375,7 +375,7 @@ __device__ void analyse(const DevMedium &m, const InterfaceArgs &a, int64_t i, d
   }
   c.newL = newL;
   c.th = crossing(m, iface, y + IQ, y1 + IQ);
-  if (m.gradl[L] != 0.0) c.th = crossing_secant(m, sp, L, sg, e, y, iface, a.dt, c.th);
+  if (m.gradl[L] != 0.0 || m.anom_amp[L] != 0.0) c.th = crossing_secant(m, sp, L, sg, e, y, iface, a.dt, c.th);
   layered_step(m, sp, L, sg, e, y, c.th * a.dt);
   const double rb = iface_level(m, iface);
   const bool surf = iface == IFACE_SURFACE;

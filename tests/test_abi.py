@@ -52,3 +52,37 @@ def test_plane_layout_matches_header():
         m = re.search(r"\b%s = (\d+)" % name, text)
         assert m, name
         assert getattr(fga, name) == int(m.group(1)), name
+
+
+STRUCTS = {"fga_beams": "Beams", "fga_medium": "MediumC", "fga_mesh": "MeshC", "fga_receivers": "ReceiversC",
+           "fga_evolve_opts": "EvolveOptsC", "fga_evolve_stats": "EvolveStatsC",
+           "fga_point_source": "PointSourceC", "fga_point_force": "PointForceC", "fga_request": "RequestC",
+           "fga_completion": "CompletionC", "fga_beams_stats": "BeamsStatsC"}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Size and every field offset of the binding's ctypes mirrors equal those
+    the C compiler gives the header's structs (gcc, host code only)."""
+    import shutil
+    import subprocess
+    import paper_1810_06760_amd as fga
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fga.h"', "int main(void) {"]
+    for cname, pname in STRUCTS.items():
+        py = getattr(fga, pname)
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, pname in STRUCTS.items():
+        py = getattr(fga, pname)
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

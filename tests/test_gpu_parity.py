@@ -527,8 +527,13 @@ LAYERED = {
     # a traction-free surface closing the outermost region
     "flat_free": (0, [0.42, 0.58], [1.7, 2.2, 1.9], [1.0, 1.3, 1.1], [1.0, 1.35, 1.2], None),
     "sphere_free": (1, [0.95, 0.8], [1.7, 2.1, 2.4], [1.0, 1.2, 1.4], [1.0, 1.25, 1.5], [-0.3, 0.35, 0.0]),
+    # a Gaussian low-velocity region in the middle layer (the crosswell model's form, eq:true_c)
+    "flat_anom": (0, [0.42, 0.58], [1.7, 2.2, 1.9], [1.0, 1.3, 1.1], [1.0, 1.35, 1.2], None),
+    "sphere_anom": (1, [0.95, 0.8], [1.7, 2.1, 2.4], [1.0, 1.2, 1.4], [1.0, 1.25, 1.5], None),
 }
 SURFACE = {"flat_free": 0.72, "sphere_free": 1.12}
+ANOMALY = {"flat_anom": {1: (0.2, 40.0, (0.5, 0.0, 0.5), (1.0, 0.0, 1.0))},
+           "sphere_anom": {0: (0.15, 30.0, (0.5, 0.5, 0.7), (1.0, 1.0, 1.0))}}
 
 
 def initial_layers(ob, geometry, bounds):
@@ -551,8 +556,9 @@ def layered_case(name, nq=4, np_=2):
         # the beams start inside the free surface (the medium ends there)
         lev = ob["Q"][:, 2] if geo == 0 else np.linalg.norm(ob["Q"], axis=1)
         ob = om.take_beams(ob, np.nonzero(lev < sf)[0])
-    return (w, ob, om.layered(geo, bounds, cp, cs, rho, grad=grad, surface=sf),
-            fga().Medium.layered(geo, bounds, cp, cs, rho, grad=grad, surface=sf))
+    an = ANOMALY.get(name)
+    return (w, ob, om.layered(geo, bounds, cp, cs, rho, grad=grad, surface=sf, anomaly=an),
+            fga().Medium.layered(geo, bounds, cp, cs, rho, grad=grad, surface=sf, anomaly=an))
 
 
 def alive_by_lineage(d):
@@ -560,7 +566,8 @@ def alive_by_lineage(d):
     return {k: v[keep] for k, v in d.items()}
 
 
-@pytest.mark.parametrize("name", ["flat", "sphere", "flat_grad", "sphere_grad", "flat_free", "sphere_free"])
+@pytest.mark.parametrize("name", ["flat", "sphere", "flat_grad", "sphere_grad", "flat_free", "sphere_free",
+                                  "flat_anom", "sphere_anom"])
 def test_interface_parity(name):
     """Beams crossing flat or spherical interfaces, between constant or
     linear-gradient layers, or reflected at a traction-free surface, split
@@ -591,7 +598,8 @@ def test_interface_parity(name):
     assert rel_l2(phys_amp_gpu(g), A_ref) <= RTOL
 
 
-@pytest.mark.parametrize("name,batch", [("flat", 0), ("flat", 100), ("sphere_grad", 0), ("sphere_free", 0)])
+@pytest.mark.parametrize("name,batch", [("flat", 0), ("flat", 100), ("sphere_grad", 0), ("sphere_free", 0),
+                                        ("flat_anom", 0)])
 def test_interface_seismogram_parity(name, batch):
     """Receiver sums during a layered run, children included; batch 100 splits
     each step's sum over several ragged beam batches (a layered run sums
