@@ -67,8 +67,8 @@ def parse():
     ap.add_argument("--window", type=float, default=0.5,
                     help="the timed steps start at this fraction of the horizon T (untimed advance before)")
     ap.add_argument("--segment", type=int, default=250, help="RK4 steps per evolution call (progress between)")
-    ap.add_argument("--workload", default="smooth", choices=["smooth", "homogeneous", "layered", "mixed",
-                                                             "pointforce"])
+    ap.add_argument("--workload", default="smooth",
+                    choices=["smooth", "homogeneous", "layered", "crosswell", "mixed", "pointforce"])
     ap.add_argument("--waves", type=int, default=4, help="beam waves of the mixed-precision workload")
     ap.add_argument("--batch", type=int, default=0, help="beams per receiver-sum batch in the evolution (0: library default)")
     ap.add_argument("--chunk", type=int, default=0, help="RK4 steps per integrator launch (0: library default)")
@@ -291,19 +291,31 @@ def layered(args):
     """Layered spherical Earth-like model (4 shells) with a point moment-tensor
     source (Ricker, eps = 1/256): decompose, then 2000 RK4 steps with
     interface splitting (generation cap 3) and 512 surface receivers sampled
-    every step.  --scale shrinks the direction count and the step count."""
+    every step.  --scale shrinks the direction count and the step count.
+    --workload crosswell runs the crosswell model of Sec. 4 the same way
+    (fga_inputs.crosswell: the ninth source, 32 receivers in the other well)."""
     import torch
     import fga_inputs as fi
     import paper_1810_06760_amd as fga
     torch.cuda.set_device(0)
     sc = args.scale
-    e = fi.layered_earth(ndir=max(16, int(round(1600 * sc))), nsteps=max(8, int(round(2000 * sc))))
-    med = fga.Medium.layered(1, e["bounds"], e["cp"], e["cs"], e["rho"])
+    cross = args.workload == "crosswell"
+    if cross:
+        # the crosswell model (Sec. 4): flat layers under a free surface, the low-velocity region
+        e = fi.crosswell(ndir=max(16, int(round(1600 * sc))), nsteps=max(8, int(round(2000 * sc))))
+        med = fga.Medium.layered(0, e["bounds"], e["cp"], e["cs"], e["rho"], surface=e["surface"],
+                                 anomaly=e["anomaly"])
+    else:
+        e = fi.layered_earth(ndir=max(16, int(round(1600 * sc))), nsteps=max(8, int(round(2000 * sc))))
+        med = fga.Medium.layered(1, e["bounds"], e["cp"], e["cs"], e["rho"])
     src = fga.point_source(e["eps"], e["x0"], e["M"], nq=e["nq"], ndir=e["ndir"], nshell=e["nshell"],
                            merge_s=not args.unmerged)
     ncand = int(fga.lib().fga_point_source_candidates(fga.C.byref(src)))
     beams = fga.BeamSet(12 * ncand)   # room for interface children (generation cap 3)
-    rec = fga._dev(e["receivers_rtp"], torch.float64)   # stations as (r, longitude, latitude)
+    if cross:
+        rec, coords = fga._dev(e["receivers"], torch.float64), fga.FGA_COORDS_CARTESIAN
+    else:   # stations as (r, longitude, latitude)
+        rec, coords = fga._dev(e["receivers_rtp"], torch.float64), fga.FGA_COORDS_SPHERICAL
     nseg = max(1, min(args.segments, e["nsteps"]))
     seg = -(-e["nsteps"] // nseg)
     state = {"ws": None, "seis": torch.empty((rec.shape[0], e["nsteps"], 3, 2), dtype=torch.float64, device="cuda")}
@@ -314,13 +326,12 @@ def layered(args):
         if state["ws"] is None:
             state["ws"] = fga._workspace(fga.workspace_bytes("evolve", beams=beams, nsteps=seg,
                                                              n_receivers=rec.shape[0], eps=e["eps"], tau=e["tau"],
-                                                             batch=args.batch, coords=fga.FGA_COORDS_SPHERICAL))
+                                                             batch=args.batch, coords=coords))
         tot = {"beam_steps": 0, "evals": 0, "crossings": 0, "spawned": 0, "capped": 0}
         for s0 in range(0, e["nsteps"], seg):
             n = min(seg, e["nsteps"] - s0)
             part, st = fga.fga_evolve(med, beams, e["dt"], n, receivers=rec, eps=e["eps"], tau=e["tau"],
-                                      ws=state["ws"], batch=args.batch, resort=args.resort,
-                                      coords=fga.FGA_COORDS_SPHERICAL)
+                                      ws=state["ws"], batch=args.batch, resort=args.resort, coords=coords)
             state["seis"][:, s0:s0 + n].copy_(part)
             for k in tot:
                 tot[k] += st[k]
@@ -350,12 +361,19 @@ def layered(args):
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"s_beams": "separate SH and SV" if args.unmerged else "SH and SV merged per (q, p, direction)",
-                   "workload": "layered spherical Earth-like model, 4 shells (radii %s), point moment-tensor "
-                               "source with Ricker wavelet at r = %.3f, eps = 1/256, q %d^3 x %d directions x %d "
-                               "shells x 3 branches x 2 directions, %d RK4 steps to T = 1.5 with interface "
-                               "splitting (generation cap 3), %d surface receivers x %d samples, FP64"
-                               % (", ".join("%.3f" % r for r in e["bounds"]), float(np.linalg.norm(e["x0"])),
-                                  e["nq"], e["ndir"], e["nshell"], e["nsteps"], rec.shape[0], e["nsteps"]),
+                   "workload": ("crosswell model (Sec. 4 eq:true_c, 100 m / 1000 m/s units): 3 flat layers "
+                                "under a free surface, Gaussian low-velocity region, explosion with Ricker "
+                                "wavelet at depth %.0f m, eps = 1/128, q %d^3 x %d directions x %d shells x "
+                                "3 branches x 2 directions, %d RK4 steps to T = 2 (0.2 s) with interface and "
+                                "surface splitting (generation cap 3), %d well receivers x %d samples, FP64"
+                                % (100 * (3.0 - e["x0"][2]), e["nq"], e["ndir"], e["nshell"], e["nsteps"],
+                                   rec.shape[0], e["nsteps"])) if cross else
+                               ("layered spherical Earth-like model, 4 shells (radii %s), point moment-tensor "
+                                "source with Ricker wavelet at r = %.3f, eps = 1/256, q %d^3 x %d directions x %d "
+                                "shells x 3 branches x 2 directions, %d RK4 steps to T = 1.5 with interface "
+                                "splitting (generation cap 3), %d surface receivers x %d samples, FP64"
+                                % (", ".join("%.3f" % r for r in e["bounds"]), float(np.linalg.norm(e["x0"])),
+                                   e["nq"], e["ndir"], e["nshell"], e["nsteps"], rec.shape[0], e["nsteps"])),
                    "beams": int(acc["beams"] / K), "parallelism": "single GPU"},
         "beam_point_evals_per_s": acc["evals"] / elapsed,
         "interface_hits_per_step": acc["crossings"] // K, "children_per_step": acc["spawned"] // K,
@@ -710,7 +728,7 @@ def main():
     if args.serve:
         serve(args)
         return
-    if args.workload == "layered":
+    if args.workload in ("layered", "crosswell"):
         layered(args)
         return
     if args.workload == "mixed":

@@ -353,3 +353,31 @@ def layered_earth(family: int = 3, eps: float = 1.0 / 256, nq: int = 8, ndir: in
     rtp = np.stack([np.ones(nrec), theta, phi], axis=1)
     return {"bounds": list(radii), "cp": cp, "cs": cs, "rho": rho, "x0": x0, "M": M, "eps": eps, "nq": nq,
             "ndir": ndir, "nshell": nshell, "nsteps": nsteps, "dt": T / nsteps, "receivers_rtp": rtp, "tau": 25.0}
+
+
+def crosswell(source: int = 8, eps: float = 1.0 / 128, nq: int = 8, ndir: int = 1600, nshell: int = 4,
+              nsteps: int = 2000, T: float = 2.0, true_model: bool = True) -> dict:
+    """The crosswell model of the tomography example (Sec. 4, eq:true_c; with
+    true_model=False the initial model eq:ini_c), nondimensional: lengths in
+    100 m, speeds in 1000 m/s (times in 0.1 s).  Three flat layers below a
+    traction-free surface: depth 0-100 m c_P = 1.8, 100-200 m c_P = 2.0 with
+    the Gaussian low-velocity region 1 - 0.1 exp(-(22.2)((x - 0.75)^2 + (z -
+    z_c)^2)) (beta = 1/450 m^-2, centre x 75 m, depth 150 m, invariant in y),
+    below 200 m c_P = 2.2; c_S = c_P/sqrt(3) throughout; density 1 (the paper
+    gives none).  Depth d maps to z = 3 - d/100 (z up; the surface at z = 3,
+    the interfaces at z = 2 and 1, layer 0 the deepest).  16 sources at x = 0
+    spaced 16 m in depth from 8 m, 32 receivers at x = 1.5 spaced 8 m from
+    4 m (the figure's positions are not given in the text); `source` picks
+    one (8: the ninth from the top).  The source is an explosion (moment
+    tensor I) with a Ricker wavelet; eps = 1/128 is about 400 Hz at 2000 m/s
+    (the text names no frequency)."""
+    depth_src = 0.08 + 0.16 * np.arange(16)
+    depth_rec = 0.04 + 0.08 * np.arange(32)
+    anomaly = {1: (0.1, 1.0e4 / 450.0, (0.75, 0.0, 1.5), (1.0, 0.0, 1.0))} if true_model else None
+    cp = [2.2, 2.0, 1.8]
+    return {"bounds": [1.0, 2.0], "cp": cp, "cs": [c / SQRT3 for c in cp], "rho": [1.0, 1.0, 1.0],
+            "anomaly": anomaly, "surface": 3.0,
+            "x0": np.array([0.0, 0.0, 3.0 - depth_src[source]]), "M": [1.0, 1.0, 1.0, 0.0, 0.0, 0.0],
+            "eps": eps, "nq": nq, "ndir": ndir, "nshell": nshell, "nsteps": nsteps, "dt": T / nsteps,
+            "receivers": np.stack([np.full(32, 1.5), np.zeros(32), 3.0 - depth_rec], axis=1), "tau": 25.0,
+            "sources": np.stack([np.zeros(16), np.zeros(16), 3.0 - depth_src], axis=1)}
