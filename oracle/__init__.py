@@ -109,7 +109,7 @@ def lib():
         L.om_rk4_step.argtypes = [vp, vp, C.c_double]
         L.om_evolve_layered.restype = C.c_int64
         L.om_evolve_layered.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_double,
-                                        vp]
+                                        vp, C.c_int]
         L.om_interface_modes.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, vp]
         L.om_free_surface_modes.argtypes = [vp, C.c_int, vp, vp, C.c_int, vp, vp, vp]
         L.om_interface_jacobians.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp, C.c_double, vp, vp]
@@ -394,16 +394,19 @@ def evolve(med: OracleMedium, beams: np.ndarray, dt: float, nsteps: int, s_vecto
 
 
 def evolve_layered(med: OracleMedium, beams: np.ndarray, dt: float, nsteps: int, gmax: int = 3,
-                   child_cut: float = 1e-3, capacity: int = None):
+                   child_cut: float = 1e-3, capacity: int = None, s_vector: bool = False):
     """Advance beams by nsteps RK4 steps in a layered medium, splitting beams
     at interfaces.  Returns (beam array holding parents and children; retired
-    beams have alive = 0, number of beams retired at the generation cap)."""
+    beams have alive = 0, number of beams retired at the generation cap).
+    s_vector: where some layer curves the rays, S beams take their regular
+    steps with the frame-free amplitude."""
     n = beams.shape[0]
     cap = capacity if capacity is not None else max(16, 8 * n)
     buf = np.zeros(cap, dtype=BEAM_DTYPE)
     buf[:n] = beams
     ncap = C.c_int64(0)
-    m = lib().om_evolve_layered(med.ref, _p(buf), n, cap, dt, nsteps, gmax, child_cut, C.byref(ncap))
+    m = lib().om_evolve_layered(med.ref, _p(buf), n, cap, dt, nsteps, gmax, child_cut, C.byref(ncap),
+                                1 if s_vector else 0)
     if m < 0:
         raise RuntimeError("beam capacity %d exceeded" % cap)
     return buf[:m].copy(), int(ncap.value)

@@ -1633,20 +1633,55 @@ static double om_crossing_secant(const om_medium *m, const om_beam *y0, int ifac
  * during a step are not stepped again in it.  Returns the new beam count, or
  * -1 if the capacity would be exceeded (then the beam set is partly
  * updated).  *capped receives the number of beams retired at the cap. */
+/* One regular step of an S beam with the frame-free amplitude: A from the
+ * frame, the vector RK4 step, and back to the frame (axis switched first if P
+ * has come within 10 degrees of it). */
+static void om_step_svec(const om_medium *m, om_beam *b, double dt)
+{
+  double nsh[3], nsv[3];
+  om_s_frame(b->P, b->e, nsh, nsv);
+  cplx A[3];
+  for (int d = 0; d < 3; ++d) A[d] = b->a[0] * nsv[d] + b->a[1] * nsh[d];
+  om_rk4_step_vec(m, b, A, dt);
+  const double np = sqrt(dot3(b->P, b->P));
+  if (fabs(dot3(b->P, b->e)) / np > cos(10.0 * M_PI / 180.0)) {
+    const int was_z = b->e[2] != 0.0 && b->e[0] == 0.0 && b->e[1] == 0.0;
+    b->e[0] = was_z ? 1.0 : 0.0;
+    b->e[1] = 0.0;
+    b->e[2] = was_z ? 0.0 : 1.0;
+  }
+  om_s_frame(b->P, b->e, nsh, nsv);
+  b->a[0] = A[0] * nsv[0] + A[1] * nsv[1] + A[2] * nsv[2];
+  b->a[1] = A[0] * nsh[0] + A[1] * nsh[1] + A[2] * nsh[2];
+}
+
+/* s_vector: in a medium with curved rays somewhere (a gradient or an anomaly
+ * in some layer), the regular steps of S beams take the frame-free amplitude
+ * (om_step_svec); steps that reach an interface and the children's partial
+ * steps stay in the framed form. */
 int64_t om_evolve_layered(const om_medium *m, om_beam *beams, int64_t n, int64_t cap, double dt, int nsteps,
-                          int gmax, double child_cut, int64_t *capped)
+                          int gmax, double child_cut, int64_t *capped, int s_vector)
 {
   int64_t ncap = 0;
+  int curved = 0;
+  for (int l = 0; l < m->nlayer; ++l) curved = curved || m->gradl[l] != 0.0 || m->anom_amp[l] != 0.0;
+  const int vec = s_vector && curved;
   for (int s = 0; s < nsteps; ++s) {
     const int64_t n0 = n;
     for (int64_t i = 0; i < n0; ++i) {
       om_beam *b = &beams[i];
       if (!b->alive) continue;
       om_beam y0 = *b;
+      om_beam yv = *b;
       om_rk4_step(m, b, dt);
       int iface, newL;
       if (!om_layer_exit(m, y0.layer, b->Q, &iface, &newL)) {
-        om_reframe(b);
+        if (vec && b->branch != 0) {
+          om_step_svec(m, &yv, dt);
+          *b = yv;
+        } else {
+          om_reframe(b);
+        }
         continue;
       }
       double th = om_crossing_fraction(m, iface, y0.Q, b->Q);

@@ -109,3 +109,35 @@ def test_p_beams_step_as_in_the_framed_evolution():
     bv, _ = run(med, ob, 0.2, 30, True)
     for k in ("Q", "P", "ZQ", "ZP", "a", "S"):
         assert np.array_equal(bf[k], bv[k]), k
+
+
+def test_layered_media_with_curved_rays():
+    """In layered media with a gradient layer and an anomaly, the frame-free
+    regular steps of S beams give the same children (the ray does not depend
+    on the amplitude) and polarisations within RK4 truncation of the framed
+    run, falling with the step."""
+    import fga_inputs as fi2
+    from test_oracle_interfaces import one_beam
+    med = om.layered(0, [0.5], [1.7, 2.2], [1.0, 1.25], [1.0, 1.3], grad=[0.4, -0.3],
+                     anomaly={1: (0.2, 30.0, (0.3, 0.0, 0.6), (1.0, 0.0, 1.0))})
+    g = np.random.default_rng(4)
+    beams = []
+    for k in range(12):
+        q = np.array([0.2, 0.3, 0.3]) + 0.1 * g.random(3)
+        p = g.standard_normal(3)
+        p[2] = abs(p[2]) + 0.5
+        b = one_beam(q, p / np.linalg.norm(p) * 1.3, 2)
+        b["lineage"] = k
+        beams.append(b)
+    ob = np.concatenate(beams)
+    errs = []
+    for n in (60, 120):
+        a, _ = om.evolve_layered(med, ob.copy(), 0.6 / n, n, child_cut=0.0)
+        v, _ = om.evolve_layered(med, ob.copy(), 0.6 / n, n, child_cut=0.0, s_vector=True)
+        a, v = a[a["alive"] == 1], v[v["alive"] == 1]
+        assert np.array_equal(a["lineage"], v["lineage"]) and np.array_equal(a["Q"], v["Q"])
+        assert np.sum(a["gen"] > 0) > 0
+        A, V = om.amplitude_vectors(a), om.amplitude_vectors(v)
+        errs.append(np.linalg.norm(A - V) / np.linalg.norm(A))
+    assert 0 < errs[1] < 1e-7, errs
+    assert errs[0] / errs[1] > 8.0, errs
