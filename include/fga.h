@@ -398,8 +398,10 @@ typedef struct {
                               in the beam's frame (axis switched near P) at the end of
                               the launch.  The amplitude cutoff then uses |A|.  Agrees
                               with the framed form to RK4 truncation; identical in a
-                              homogeneous medium.  Grid and homogeneous media only
-                              (FGA_EUNSUPPORTED for layered media).  0: framed.       */
+                              homogeneous medium.  Layered media: the regular steps of
+                              S beams where some layer curves the rays (a gradient or
+                              an anomaly); steps that reach an interface and the
+                              children's partial steps stay framed.  0: framed.       */
 } fga_evolve_opts;
 
 typedef struct {

@@ -523,8 +523,6 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
       return fail(FGA_EINVAL, "receiver coords must be FGA_COORDS_CARTESIAN or FGA_COORDS_SPHERICAL");
   }
   const int s_vector = opts && opts->s_vector ? 1 : 0;
-  if (s_vector && dm.kind == FGA_MEDIUM_LAYERED)
-    return fail(FGA_EUNSUPPORTED, "frame-free S amplitudes (s_vector) are built for homogeneous and grid media");
   hipStream_t st = (hipStream_t)stream;
   EvolvePlan p = evolve_plan(beams, nsteps, opts, rec);
   // layered media step one step per launch and re-sort a beam set grown by
@@ -580,6 +578,7 @@ fga_status fga_evolve(const fga_medium *med, fga_beams *beams, double dt, int ns
       a.eps_emit = 1.0;
       a.cutoff_abs = cutoff;
       a.counters = ctr;
+      a.s_vector = s_vector;
       FGA_HIP(launch_integrate(dm, a, st));
       InterfaceArgs ia{};
       ia.f64 = beams->f64;

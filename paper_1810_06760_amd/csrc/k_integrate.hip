@@ -462,6 +462,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // gradient: the general RK4 step (medium_eval gives c, grad c and Hess c of
 // the beam's layer at each stage), and a beam whose centre has left its
 // layer is flagged with its stored state untouched, as in k_step_layered.
+// SV = 1: S beams take the step with the frame-free amplitude (A formed from
+// the frame at the load and returned to it before the store).
+template <int SV = 0>
 __global__ __launch_bounds__(256) void k_step_layered_grad(DevMedium med, IntegrateArgs a)
 {
   const int64_t i = a.beg + (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -477,18 +480,24 @@ __global__ __launch_bounds__(256) void k_step_layered_grad(DevMedium med, Integr
       const int layer = a.i32[FGA_LAYER * cap + i];
       const int sp = br == 0 ? 0 : 1;
       const bool isS = br != 0;
-      double y[NS], e[3];
+      double y[nstate<SV>()], e[3];
 #pragma unroll
       for (int f = 0; f < NS; ++f) y[f] = F[f * cap + i];
 #pragma unroll
       for (int d = 0; d < 3; ++d) e[d] = F[(FGA_E + d) * cap + i];
-      rk4_step<MK_LAYERED>(med, sp, layer, sg, isS, e, y, a.dt);
+      if (SV) {
+        y[nstate<SV>() - 2] = 0.0;
+        y[nstate<SV>() - 1] = 0.0;
+        if (isS) frame_to_vector(y, e);
+      }
+      rk4_step<MK_LAYERED, SV>(med, sp, layer, sg, isS, e, y, a.dt);
       int iface, nl;
       if (layer_exit(med, layer, y + IQ, iface, nl)) {
         // the interface step redoes this step from the stored state
         a.i32[FGA_FLAGS * cap + i] = flags | FGA_FLAG_CROSS;
       } else {
-        if (isS) reframe_s(y, e);
+        if (isS && SV) vector_to_frame(y, e);
+        else if (isS) reframe_s(y, e);
         bool finite = true;
 #pragma unroll
         for (int f = 0; f < NS; ++f) finite = finite && isfinite(y[f]);
@@ -598,7 +607,8 @@ hipError_t launch_integrate(const DevMedium &m, const IntegrateArgs &a, hipStrea
   default:
     // layered media advance one step per launch, the interface step between
     if (a.nsteps != 1 || a.stride != 0) return hipErrorInvalidValue;
-    if (m.any_grad) hipLaunchKernelGGL(k_step_layered_grad, blocks, 256, 0, st, m, a);
+    if (m.any_grad && a.s_vector) hipLaunchKernelGGL(k_step_layered_grad<1>, blocks, 256, 0, st, m, a);
+    else if (m.any_grad) hipLaunchKernelGGL(k_step_layered_grad<0>, blocks, 256, 0, st, m, a);
     else hipLaunchKernelGGL(k_step_layered, blocks, 256, 0, st, m, a);
     break;
   }
