@@ -200,24 +200,28 @@ def test_footprint_is_a_host_query():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed32"])
-def test_served_solve_matches_oracle(precision):
+@pytest.mark.parametrize("precision,merge", [("fp64", False), ("mixed", False), ("mixed32", False), ("fp64", True),
+                                             ("mixed32", True)])
+def test_served_solve_matches_oracle(precision, merge):
     """A served point-source solve in a smooth grid medium (the sweep's model
     recipe) against the oracle's decompose -> evolve -> sum at the receivers
     (Steps 1-3): relative L2 <= 1e-10 in FP64, <= 1e-3 with the mixed
-    receiver sums; a second, larger request served beside it changes nothing."""
+    receiver sums; a second, larger request served beside it changes nothing.
+    merge: the served source makes one S beam per (q, p, direction) (as the
+    serving benchmark does); the oracle's separate SH and SV beams give the
+    same field."""
     import oracle as om
     m = fga()
-    say("served solve vs oracle", precision)
+    say("served solve vs oracle", precision, "merged" if merge else "")
     nodes = fi.sweep_model(1, nmed=32)
     mesh = fi.node_grid(32)
     med = m.Medium.grid(nodes, mesh, cs_ratio=1.0 / np.sqrt(3.0))
     rq = fi.sweep_request(3, nsteps=30)
     eps, nsteps, dt, stride = 1.0 / 32, 30, 2e-3, 3
-    src = m.point_source(eps, rq["x0"], rq["M"], nq=3, ndir=16, nshell=2)
+    src = m.point_source(eps, rq["x0"], rq["M"], nq=3, ndir=16, nshell=2, merge_s=merge)
     x = rq["receivers"][:10]
     prec = {"fp64": m.FGA_FP64, "mixed": m.FGA_FP32, "mixed32": m.FGA_FP32_ACC32}[precision]
-    other = m.point_source(eps, rq["x0"] + 0.05, rq["M"], nq=4, ndir=24, nshell=2)
+    other = m.point_source(eps, rq["x0"] + 0.05, rq["M"], nq=4, ndir=24, nshell=2, merge_s=merge)
     srv = m.Server(1 << 32, 2)
     try:
         r, seis, keep = m.make_request(med, None, None, x, 25.0, dt, nsteps, stride, precision=prec, source=src)
