@@ -48,8 +48,8 @@ void prof_clear()
 {
   for (auto &r : g_prof) {
     for (auto &p : r.ev) {
-      hipEventDestroy(p.first);
-      hipEventDestroy(p.second);
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
     }
     r.ev.clear();
   }
@@ -60,7 +60,7 @@ ProfScope::ProfScope(int kernel, hipStream_t s) : k(kernel), st(s)
 {
   if (g_prof_on && hipEventCreate(&a) == hipSuccess) {
     if (hipEventRecord(a, st) != hipSuccess) {
-      hipEventDestroy(a);
+      (void)hipEventDestroy(a);
       a = nullptr;
     }
   } else {
@@ -73,10 +73,14 @@ ProfScope::~ProfScope()
   if (!a) return;
   hipEvent_t b;
   if (hipEventCreate(&b) != hipSuccess) {
-    hipEventDestroy(a);
+    (void)hipEventDestroy(a);
     return;
   }
-  hipEventRecord(b, st);
+  if (hipEventRecord(b, st) != hipSuccess) {  // an unrecorded pair would time nothing
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return;
+  }
   g_prof[k].ev.emplace_back(a, b);
 }
 
@@ -335,8 +339,8 @@ fga_status fga_profile_read(int k, int64_t *launches, double *total_ms, int rese
   if (total_ms) *total_ms = tot;
   if (reset) {
     for (auto &p : g_prof[k].ev) {
-      hipEventDestroy(p.first);
-      hipEventDestroy(p.second);
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
     }
     g_prof[k].ev.clear();
   }
@@ -443,7 +447,7 @@ struct EvolveBufs {
   size_t cross_tmp_bytes = 0;
 };
 
-EvolveBufs evolve_layout(const EvolvePlan &p, const fga_receivers *r, int64_t cap, Arena &ar)
+static EvolveBufs evolve_layout(const EvolvePlan &p, const fga_receivers *r, int64_t cap, Arena &ar)
 {
   EvolveBufs b;
   b.ctr = ar.take<unsigned long long>(8);

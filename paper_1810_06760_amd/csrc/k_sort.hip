@@ -136,7 +136,9 @@ SortBufs sort_layout(int64_t n, Arena &ar)
   b.tmp = ar.take<double>(n + 1);
   b.alive = ar.take<int64_t>(1);
   b.sort_bytes = 0;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, b.sort_bytes, b.k1, b.k2, b.v1, b.v2, (int)(n > 0 ? n : 1), 0, 32);
+  // size query only (no device work): the bytes come back in sort_bytes
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b.sort_bytes, b.k1, b.k2, b.v1, b.v2, (int)(n > 0 ? n : 1), 0,
+                                           32);
   b.sort_tmp = ar.take<char>(b.sort_bytes + 1);
   return b;
 }
